@@ -1,0 +1,153 @@
+"""Seeded synthetic inputs and parameter sets.
+
+This module is the only code shared by the CPU oracle side (tests, the oracle
+baseline timing) and the HIP library side (tests, bench, smoke).  It holds no
+CKKS arithmetic: it chooses public parameters (ring degree, prime chains,
+digit count, scale) and draws seeded random data (slot vectors, plaintext
+matrices, integer residue arrays) that both sides then consume unchanged.
+
+Parameter shapes follow the workloads of the paper (CKKS primer in section 3.2,
+parameter table Table 8, ciphertext/key sizes Table 6) with the ring sizes of
+the benchmark configurations:
+
+* ``tiny``    N = 2^12, three 30-bit primes, one 60-bit special prime,
+               dnum = 3, scale 2^25.  (With a special prime barely above the
+               30-bit digits, the uncentred digit's mean term gives key-switching
+               noise of ~4e-3 in the slot whose root is nearest 1.)
+* ``vital``   N = 2^16, L = 24 (q0 of 60 bits, 23 primes of ~50 bits),
+               K = 8 special primes of 60 bits, dnum = 3, scale 2^50.
+* ``gesture`` N = 2^16, L = 30, K = 10, dnum = 3, scale 2^50.
+* ``mix15``   N = 2^15, L = 12, K = 4, dnum = 3, scale 2^50 (the paper's own
+               ring with the gesture pipeline's 12 limbs).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["CONFIGS", "params", "is_prime", "uniform_slots", "uniform_matrix",
+           "uniform_residues", "small_ints"]
+
+
+def is_prime(n: int) -> bool:
+    """Deterministic Miller-Rabin for n < 2^64 (bases 2..37)."""
+    if n < 2:
+        return False
+    small = (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)
+    for p in small:
+        if n % p == 0:
+            return n == p
+    d, r = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        r += 1
+    for a in small:
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(r - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def _primes_near(bits: int, two_n: int, count: int, taken: set[int],
+                 alternate: bool) -> list[int]:
+    """``count`` primes p = 1 (mod 2N) closest to 2^bits.
+
+    With ``alternate`` the search takes one prime below 2^bits, then one above,
+    and so on, so that the product of consecutive primes stays near 2^(2 bits)
+    and the scale drifts little after rescaling.  Without it every prime is
+    taken below 2^bits (so that it stays under 2^bits).
+    """
+    out: list[int] = []
+    centre = (1 << bits) // two_n * two_n + 1
+    down, up = centre, centre + two_n
+    side = 0
+    while len(out) < count:
+        if side == 0 or not alternate:
+            while not (is_prime(down) and down not in taken and down < (1 << bits)):
+                down -= two_n
+            out.append(down)
+            taken.add(down)
+            down -= two_n
+        else:
+            while not (is_prime(up) and up not in taken):
+                up += two_n
+            out.append(up)
+            taken.add(up)
+            up += two_n
+        side ^= 1
+    return out
+
+
+# name -> (log_n, q_layout, p_layout, dnum, scale)
+# q_layout/p_layout: list of (bits, count, alternate)
+CONFIGS: dict[str, dict] = {
+    "tiny": dict(log_n=12, q=[(30, 3, False)], p=[(60, 1, False)], dnum=3,
+                 scale=2.0 ** 25),
+    "vital": dict(log_n=16, q=[(60, 1, False), (50, 23, True)], p=[(60, 8, False)],
+                  dnum=3, scale=2.0 ** 50),
+    "gesture": dict(log_n=16, q=[(60, 1, False), (50, 29, True)], p=[(60, 10, False)],
+                    dnum=3, scale=2.0 ** 50),
+    "mix15": dict(log_n=15, q=[(60, 1, False), (50, 11, True)], p=[(60, 4, False)],
+                  dnum=3, scale=2.0 ** 50),
+}
+
+_cache: dict[str, dict] = {}
+
+
+def params(name: str) -> dict:
+    """Public parameter set: {'log_n', 'n', 'q': [...], 'p': [...], 'dnum', 'scale'}.
+
+    Every prime is = 1 (mod 2N) and below 2^61.  The q chain starts with q0.
+    """
+    if name in _cache:
+        return dict(_cache[name])
+    cfg = CONFIGS[name]
+    two_n = 2 << cfg["log_n"]
+    taken: set[int] = set()
+    q: list[int] = []
+    for bits, count, alt in cfg["q"]:
+        q += _primes_near(bits, two_n, count, taken, alt)
+    p: list[int] = []
+    for bits, count, alt in cfg["p"]:
+        p += _primes_near(bits, two_n, count, taken, alt)
+    out = dict(name=name, log_n=cfg["log_n"], n=1 << cfg["log_n"], q=q, p=p,
+               dnum=cfg["dnum"], scale=cfg["scale"])
+    _cache[name] = out
+    return dict(out)
+
+
+def uniform_slots(n_slots: int, seed: int, lo: float = -1.0, hi: float = 1.0,
+                  complex_: bool = False) -> np.ndarray:
+    """Slot vector drawn uniformly from [lo, hi) (real, or real+imag parts)."""
+    rng = np.random.default_rng(seed)
+    re = rng.uniform(lo, hi, n_slots)
+    if not complex_:
+        return re
+    return re + 1j * rng.uniform(lo, hi, n_slots)
+
+
+def uniform_matrix(rows: int, cols: int, seed: int, bound: float) -> np.ndarray:
+    """Real matrix with entries uniform in [-bound, bound)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-bound, bound, (rows, cols))
+
+
+def uniform_residues(moduli, n: int, seed: int, count: int = 1) -> np.ndarray:
+    """``count`` stacked arrays of shape [len(moduli)][n], row i uniform in [0, moduli[i])."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((count, len(moduli), n), dtype=np.uint64)
+    for c in range(count):
+        for i, m in enumerate(moduli):
+            out[c, i] = rng.integers(0, m, n, dtype=np.uint64)
+    return out
+
+
+def small_ints(n: int, seed: int, bound: int) -> np.ndarray:
+    """int64 array of n values uniform in [-bound, bound]."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(-bound, bound + 1, n, dtype=np.int64)
