@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark: homomorphic rotations per second at N = 2^16, L = 24 on one MI355X.
+
+One step is one pass of the evaluation hot path over one synthetic vital-sign
+window (200 frames x 64 range bins, complex; clutter-removed and normalized;
+packed bin-major into a real and an imaginary ciphertext at N = 2^16, L = 24
+primes, K = 8 special primes, dnum = 3, scale 2^50):
+
+  * the windowed, fftshifted 200-point DFT of every range bin as the
+    block-diagonal plaintext matrices C~ = I_64 (x) Re W and S~ = I_64 (x) Im W
+    (the paper's Kernel 3, Eq. dft_re): d_re = C~ v_re - S~ v_im and
+    d_im = S~ v_re + C~ v_im, four baby-step/giant-step transforms over 399
+    cached diagonals each (automorphisms, hybrid key switching, plaintext
+    products), then rescale;
+  * the power spectrum |d|^2 = d_re^2 + d_im^2 (the paper's energy kernel):
+    two tensor products, one relinearization, one rescale.
+
+`value` is rotations per second over the whole timed step (the step's other
+work is included in its time).  The dominant kernel's achieved rate is
+measured with HIP events on the library's stream; the CPU oracle is timed on a
+bounded sample of the same operation on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E, GB/s
+VALU_LANE_RATE = 256 * 64 * 2.4e9           # full-rate VALU lane operations / s
+MAD_PER_MULMOD = 10                         # v_mad_u64_u32 per 61-bit Shoup product
+MULMOD_PEAK = VALU_LANE_RATE / MAD_PER_MULMOD
+
+FRAMES, BINS, N1 = 200, 64, 20
+
+
+def block_diagonals(mat: np.ndarray, blocks: int, n_slots: int) -> dict:
+    """Generalized diagonals diag_k[j] = A[j][(j + k) mod n] of
+    A = I_blocks (x) mat placed on the first blocks*d slots (zero elsewhere)."""
+    d = mat.shape[0]
+    out = {}
+    k = np.arange(d)
+    for off in range(-(d - 1), d):
+        col = k + off
+        ok = (col >= 0) & (col < d)
+        vals = np.where(ok, mat[k, np.clip(col, 0, d - 1)], 0.0)
+        v = np.zeros(n_slots)
+        v[: blocks * d] = np.tile(vals, blocks)
+        if np.any(v):
+            out[off] = v
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the hot path is "
+              "single-GPU; see the design notes for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_22437_amd as H
+    import seeded_inputs as S
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    prm = S.params("vital")
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    ctx = H.Context.from_params(prm, 0, stream)
+    L, n_slots = len(prm["q"]), prm["n"] // 2
+    top = L - 1
+    log(f"context N=2^{prm['log_n']} L={L} K={len(prm['p'])} dnum={prm['dnum']} "
+        f"({time.time() - t0:.1f}s)")
+
+    # window -> bin-major slots (slot r*200 + t), real and imaginary ciphertexts
+    z = S.vital_window(1000, FRAMES, BINS)
+    v = np.zeros(n_slots, dtype=np.complex128)
+    v[: FRAMES * BINS] = z.T.reshape(-1)
+    sk = ctx.keygen_secret(1)
+    scale = prm["scale"]
+    ct_re = ctx.encrypt_sk(sk, ctx.encode(v.real, scale, top), 100)
+    ct_im = ctx.encrypt_sk(sk, ctx.encode(v.imag, scale, top), 101)
+
+    w = S.windowed_dft_matrix(FRAMES)
+    lt_c = ctx.lt_create(block_diagonals(w.real, BINS, n_slots), N1, top)
+    lt_s = ctx.lt_create(block_diagonals(w.imag, BINS, n_slots), N1, top)
+    steps_needed = sorted(set(ctx.lt_required_steps(lt_c)) | set(ctx.lt_required_steps(lt_s)))
+    gks = ctx.keygen_rotation(sk, steps_needed, 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    rot_per_lt = len(ctx.lt_required_steps(lt_c))
+    rot_per_step = 4 * rot_per_lt
+    log(f"setup done: {len(steps_needed)} rotation keys, 2 x {2 * FRAMES - 1} cached diagonals "
+        f"({time.time() - t0:.1f}s)")
+
+    # preallocated outputs
+    a, b, c, e = (ctx.ciphertext() for _ in range(4))
+    d_re, d_im, t1, t2, p = (ctx.ciphertext() for _ in range(5))
+
+    def step():
+        ctx.lt_apply(lt_c, ct_re, gks, a)
+        ctx.lt_apply(lt_s, ct_im, gks, b)
+        ctx.sub(a, b, d_re)
+        ctx.lt_apply(lt_s, ct_re, gks, c)
+        ctx.lt_apply(lt_c, ct_im, gks, e)
+        ctx.add(c, e, d_im)
+        ctx.rescale(d_re, d_re)
+        ctx.rescale(d_im, d_im)
+        ctx.mul(d_re, d_re, t1)
+        ctx.mul(d_im, d_im, t2)
+        ctx.add(t1, t2, t1)
+        ctx.relinearize(t1, rlk, p)
+        ctx.rescale(p, p)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = rot_per_step * args.steps / wall
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (events), wall {wall:.3f}s")
+
+    # correctness of the measured step: decoded power spectrum vs plaintext math
+    got = ctx.decode(ctx.decrypt(sk, p)).real[: FRAMES * BINS].reshape(BINS, FRAMES)
+    ref = np.abs(w @ z).T ** 2
+    max_err = float(np.max(np.abs(got - ref)))
+    log(f"decoded |DFT|^2 max error vs plaintext: {max_err:.3e}")
+
+    # per-kernel durations over two more steps (events around every launch)
+    ctx.timing(True)
+    ctx.timing_reset()
+    prof_steps = 2
+    for _ in range(prof_steps):
+        step()
+    ctx.synchronize()
+    kernels = {}
+    for name in ctx.timing_names():
+        kernels[name] = ctx.timing_read(name)
+    ctx.timing(False)
+    total_ms = sum(k["ms"] for k in kernels.values())
+    dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = dom["ms"] / dom["launches"]
+    gbs = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
+    mms = dom["mulmods"] / dom["launches"] / (avg_ms * 1e-3)
+    hbm_frac, alu_frac = gbs / HBM_PEAK_GBS, mms / MULMOD_PEAK
+    if alu_frac > hbm_frac:
+        roof = {"bound": "alu", "achieved": round(mms / 1e12, 4),
+                "peak": round(MULMOD_PEAK / 1e12, 4), "unit": "Tmulmod/s",
+                "frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(hbm_frac, 4)}
+    roof["traffic"] = None
+    roof["kernel"] = dom_name
+    roof["avg_launch_us"] = round(avg_ms * 1e3, 2)
+    roof["share_of_kernel_time"] = round(dom["ms"] / total_ms, 3)
+    breakdown = {k: {"ms_per_step": round(v["ms"] / prof_steps, 3), "launches": v["launches"],
+                     "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else None,
+                     "Tmulmod/s": round(v["mulmods"] / (v["ms"] * 1e-3) / 1e12, 3)
+                     if v["ms"] else None}
+                 for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prm, args.cpu_seconds, log)
+
+    line = {
+        "metric": "rotations/s at N=2^16 L=24",
+        "value": round(value, 2),
+        "unit": "rotations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "vital window PSD: 200 frames x 64 bins complex in 2 ciphertexts, "
+                        "I_64 (x) W_200 windowed-DFT by BSGS (4 transforms, 399 diagonals, "
+                        f"n1={N1}), rescale, |.|^2 by tensor+relin, rescale",
+            "ring_log_n": prm["log_n"], "L": L, "K": len(prm["p"]), "dnum": prm["dnum"],
+            "rotations_per_step": rot_per_step, "keyswitches_per_step": rot_per_step + 1,
+        },
+        "decoded_max_abs_err": max_err,
+        "roofline": roof,
+        "kernels": breakdown,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(prm, seconds, log):
+    """The oracle's rotation (automorphism + hybrid key switching) of one
+    N = 2^16, L = 24 ciphertext at the top level, repeated for ~`seconds`."""
+    import oracle as O
+    import seeded_inputs as S
+    o = O.Oracle(prm)
+    s = o.keygen_secret(1)
+    g = o.galois_element(1)
+    gk = {g: o.keygen_galois(s, g, 5)}
+    res = S.uniform_residues(o.qmods(o.L - 1), o.n, 7, count=2)
+    ct = O.Ciphertext(res, o.L - 1, 2.0 ** 50)
+    n_rot, t0 = 0, time.perf_counter()
+    while True:
+        ct = o.rotate(ct, 1, gk)
+        n_rot += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or (n_rot >= 1 and el * (n_rot + 1) / n_rot > 2 * seconds):
+            break
+    log(f"oracle: {n_rot} rotations in {el:.1f}s on {O.num_threads()} threads")
+    return {"value": round(n_rot / el, 4), "unit": "rotations/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_rot} rotation(s) of one N=2^16, L=24 top-level ciphertext "
+                      "(automorphism + hybrid key switching), not the full window step",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,293 @@
+/*
+ * hipckks.h -- C ABI of the MI355X (gfx950) RNS-CKKS evaluation library.
+ *
+ * The paper's encrypted sensing pipeline (section 3.3) is a fixed chain of
+ * homomorphic kernels built from the CKKS operations of its primer (section
+ * 3.2): KeyGen producing a secret key, a public key, a relinearization key and
+ * one Galois key per rotation amount; encoding of up to N/2 slots; slot-wise
+ * addition; slot-wise multiplication that consumes one level; and cyclic slot
+ * rotation.  Its DFT, FIR and fully connected kernels multiply plaintext
+ * matrices into ciphertexts with the diagonal method under baby-step /
+ * giant-step scheduling (Kernel 3, Eq. dft_re; Appendix D.1), with the
+ * encoded diagonals cached on the cloud GPU (section 5.4, Table 6
+ * discussion).  This header is the boundary of that evaluation layer.
+ *
+ * Conventions (all functions):
+ *   - Return HCK_OK (0) on success, a negative hck_status on failure; no C++
+ *     exception crosses the ABI.  hck_last_error() gives a message for the
+ *     calling thread's last failure.
+ *   - Handles returned through a `**` argument are owned by the caller and
+ *     freed with the matching *_destroy.  A context must outlive every object
+ *     created from it.  Host buffers passed in are read during the call and
+ *     never retained; host output buffers are written before the call returns.
+ *   - Device memory is owned by the library (stream-ordered allocations on
+ *     the context's HIP stream).  Evaluation calls are asynchronous on that
+ *     stream; *_export, hck_decode and hck_synchronize wait for it.
+ *   - Residue layouts at the boundary are little-endian uint64 words laid out
+ *     [poly][limb][N], coefficient domain, every word fully reduced in
+ *     [0, q_limb).  Limb i < L is the i-th prime of the q chain; in switching
+ *     keys limbs L..L+K-1 are the special primes.
+ *   - An output ciphertext may alias an input.  Handles are not thread safe.
+ *   - HCK_EDEVICE is sticky: after a HIP runtime error the context refuses
+ *     further work.
+ */
+#ifndef HIPCKKS_H
+#define HIPCKKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HCK_MAX_LIMBS 64 /* L + K */
+
+typedef enum hck_status {
+  HCK_OK = 0,
+  HCK_EINVAL = -1,  /* bad argument, null handle, size mismatch */
+  HCK_ENOMEM = -2,  /* device or host allocation failed */
+  HCK_EDEVICE = -3, /* HIP runtime error (sticky) */
+  HCK_ELEVEL = -4,  /* level mismatch, or no level left */
+  HCK_ESCALE = -5,  /* scales differ by more than 2^-30 (relative) */
+  HCK_ENOKEY = -6,  /* no Galois key for the requested element */
+  HCK_EPARAMS = -7  /* invalid parameter set */
+} hck_status;
+
+typedef struct hck_context hck_context;
+typedef struct hck_secret_key hck_secret_key;
+typedef struct hck_public_key hck_public_key;
+typedef struct hck_switch_key hck_switch_key;
+typedef struct hck_galois_keys hck_galois_keys;
+typedef struct hck_plaintext hck_plaintext;
+typedef struct hck_ciphertext hck_ciphertext;
+typedef struct hck_linear_transform hck_linear_transform;
+
+/* Parameter set of the ring Z_Q[X]/(X^N + 1) in RNS form (section 3.2: CKKS
+ * over RLWE; Table 8: ring degree and depth).  log_n in [4, 17]; q holds the
+ * L = num_q primes of the ciphertext modulus chain (q[0] first), p the
+ * K = num_p special primes of hybrid key switching; dnum the number of digits
+ * of the decomposition.  Every prime must be = 1 (mod 2N), below 2^61 and
+ * distinct, with L + K <= HCK_MAX_LIMBS and 1 <= dnum <= L.  The primes of
+ * any digit, and the special primes, must each sum to less than 2^64 (the
+ * accumulation bound of the basis conversion).  Arrays are copied.
+ * Errors: HCK_EPARAMS. */
+typedef struct hck_params {
+  uint32_t log_n;
+  uint32_t num_q;
+  uint32_t num_p;
+  uint32_t dnum;
+  const uint64_t *q;
+  const uint64_t *p;
+} hck_params;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the device's default stream).  Builds the twiddle
+ * and basis-conversion tables on the device.
+ * Errors: HCK_EPARAMS, HCK_EDEVICE, HCK_ENOMEM. */
+int hck_context_create(const hck_params *params, int device, void *hip_stream,
+                       hck_context **out);
+int hck_context_destroy(hck_context *ctx);
+/* Switches the stream later work is issued on (the caller orders the two). */
+int hck_context_set_stream(hck_context *ctx, void *hip_stream);
+/* Waits for all work issued on the context's stream. */
+int hck_synchronize(hck_context *ctx);
+/* Message of the calling thread's last failure ("" if none). */
+const char *hck_last_error(void);
+/* Galois element 5^(step mod N/2) mod 2N of a left rotation by `step` slots
+ * (reading of section 3.2's Rot(Enc(a), k)); 0 for a null context. */
+uint32_t hck_galois_element(const hck_context *ctx, int32_t step);
+
+/* ---- keys (client side in the paper, section 3.2 "Key Generation") -------
+ * Randomness comes from SHAKE-256 streams keyed by (tag, seed, index), so
+ * the same seed gives the same key everywhere (uniform `a` drawn per limb in
+ * the coefficient domain, secret ternary, errors discrete Gaussian with
+ * sigma = 3.2 cut at 19). */
+int hck_keygen_secret(hck_context *ctx, uint64_t seed, hck_secret_key **out);
+/* Secret key from N ternary coefficients in {-1, 0, 1}.  Errors: HCK_EINVAL. */
+int hck_secret_key_import(hck_context *ctx, const int8_t *coeffs, hck_secret_key **out);
+int hck_secret_key_destroy(hck_secret_key *sk);
+/* pk = (-a s + e, a) over the full q chain. */
+int hck_keygen_public(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
+                      hck_public_key **out);
+/* Writes pk as [2][L][N] coefficient-domain words. n_words must be 2 L N. */
+int hck_public_key_export(hck_context *ctx, const hck_public_key *pk, uint64_t *out,
+                          size_t n_words);
+int hck_public_key_destroy(hck_public_key *pk);
+/* Relinearization key: switching key from s^2 to s. */
+int hck_keygen_relin(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
+                     hck_switch_key **out);
+/* Writes a switching key as [dnum][2][L+K][N] coefficient-domain words
+ * (b_j rows then a_j rows). n_words must be dnum 2 (L+K) N. */
+int hck_switch_key_export(hck_context *ctx, const hck_switch_key *swk, uint64_t *out,
+                          size_t n_words);
+int hck_switch_key_destroy(hck_switch_key *swk);
+/* Galois keys (switching keys from phi_g(s) to s) for n Galois elements
+ * (odd, < 2N); duplicates are generated once. */
+int hck_keygen_galois(hck_context *ctx, const hck_secret_key *sk, const uint32_t *elements,
+                      uint32_t n, uint64_t seed, hck_galois_keys **out);
+/* Same, for the elements of left rotations by `steps` slots. */
+int hck_keygen_rotation(hck_context *ctx, const hck_secret_key *sk, const int32_t *steps,
+                        uint32_t n, uint64_t seed, hck_galois_keys **out);
+/* Exports the key of one element as hck_switch_key_export does.
+ * Errors: HCK_ENOKEY. */
+int hck_galois_keys_export(hck_context *ctx, const hck_galois_keys *gks, uint32_t element,
+                           uint64_t *out, size_t n_words);
+int hck_galois_keys_count(const hck_galois_keys *gks, uint32_t *n);
+int hck_galois_keys_destroy(hck_galois_keys *gks);
+
+/* ---- plaintexts (section 3.2 "Encoding and Batching") --------------------- */
+
+/* Encodes N/2 complex slots (im may be NULL: real slots) at `scale` and
+ * `level`: coefficients round(scale * m_i) of the real polynomial m with
+ * m(zeta^(5^j)) = z_j, zeta = exp(i pi / N), rounded half away from zero.
+ * n_slots must be N/2.  |scale * m_i| must stay below 2^62.
+ * Errors: HCK_EINVAL, HCK_ELEVEL. */
+int hck_encode(hck_context *ctx, const double *re, const double *im, uint32_t n_slots,
+               double scale, uint32_t level, hck_plaintext **out);
+/* Plaintext from residues [level+1][N] (coefficient domain, fully reduced).
+ * Errors: HCK_EINVAL (a word >= its prime), HCK_ELEVEL. */
+int hck_plaintext_import(hck_context *ctx, const uint64_t *res, uint32_t level, double scale,
+                         hck_plaintext **out);
+/* Writes [level+1][N] residues; n_words must be at least (level+1) N. */
+int hck_plaintext_export(hck_context *ctx, const hck_plaintext *pt, uint64_t *out,
+                         size_t n_words, uint32_t *level, double *scale);
+/* Decodes N/2 slots: CRT to centred integers, divided by the scale, then
+ * evaluated at the slot roots.  im may be NULL. */
+int hck_decode(hck_context *ctx, const hck_plaintext *pt, double *re, double *im,
+               uint32_t n_slots);
+int hck_plaintext_destroy(hck_plaintext *pt);
+
+/* ---- ciphertexts ---------------------------------------------------------- */
+
+/* Empty ciphertext to be written by an evaluation call. */
+int hck_ciphertext_create(hck_context *ctx, hck_ciphertext **out);
+/* Ciphertext from residues [size][level+1][N], size 2 or 3. */
+int hck_ciphertext_import(hck_context *ctx, const uint64_t *res, uint32_t size, uint32_t level,
+                          double scale, hck_ciphertext **out);
+/* Writes [size][level+1][N] residues (n_words at least that); waits. */
+int hck_ciphertext_export(hck_context *ctx, const hck_ciphertext *ct, uint64_t *out,
+                          size_t n_words, uint32_t *size, uint32_t *level, double *scale);
+int hck_ciphertext_info(const hck_ciphertext *ct, uint32_t *size, uint32_t *level,
+                        double *scale);
+int hck_ciphertext_destroy(hck_ciphertext *ct);
+
+/* Enc_sk: (-a s + e + m, a).  Enc_pk: (v pk0 + e0 + m, v pk1 + e1). */
+int hck_encrypt_sk(hck_context *ctx, const hck_secret_key *sk, const hck_plaintext *pt,
+                   uint64_t seed, hck_ciphertext *out);
+int hck_encrypt_pk(hck_context *ctx, const hck_public_key *pk, const hck_plaintext *pt,
+                   uint64_t seed, hck_ciphertext *out);
+/* m = c0 + c1 s (+ c2 s^2). */
+int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext *ct,
+                hck_plaintext **out);
+
+/* ---- evaluation (section 3.2 "Three Primitive Operations") ----------------
+ * All asynchronous on the context stream. */
+
+/* Slot-wise sum / difference; equal level, scales within 2^-30.
+ * Errors: HCK_ELEVEL, HCK_ESCALE, HCK_EINVAL. */
+int hck_add(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+            hck_ciphertext *out);
+int hck_sub(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+            hck_ciphertext *out);
+int hck_add_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
+                  hck_ciphertext *out);
+/* Slot-wise product with a plaintext of the same level; scales multiply. */
+int hck_mul_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
+                  hck_ciphertext *out);
+/* Keeps limbs 0..level. */
+int hck_drop_level(hck_context *ctx, const hck_ciphertext *a, uint32_t level,
+                   hck_ciphertext *out);
+/* Tensor product of two 2-part ciphertexts: (a0 b0, a0 b1 + a1 b0, a1 b1). */
+int hck_mul(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+            hck_ciphertext *out);
+/* (d0, d1) + KeySwitch(d2, rlk) of a 3-part ciphertext. */
+int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *rlk,
+                    hck_ciphertext *out);
+/* Divides by the last prime with a centred lift; level - 1, scale / q_level.
+ * Errors: HCK_ELEVEL at level 0. */
+int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out);
+/* Left rotation by `step` slots: (phi_g(c0), 0) + KeySwitch(phi_g(c1), gk_g),
+ * g = 5^step mod 2N.  A step = 0 (mod N/2) copies.  Errors: HCK_ENOKEY. */
+int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
+               const hck_galois_keys *gks, hck_ciphertext *out);
+/* The same for an explicit Galois element (e.g. 2N-1: conjugation). */
+int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element,
+                     const hck_galois_keys *gks, hck_ciphertext *out);
+/* Raw hybrid key switching of polynomial 0 of `a`: out = (u0, u1) with
+ * u0 + u1 s ~ a0 s' for the key's source secret s'. */
+int hck_keyswitch(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *swk,
+                  hck_ciphertext *out);
+
+/* ---- baby-step/giant-step linear transform (Kernel 3; Appendix D.1) --------
+ * y = sum_g Rot(sum_b pt_{g,b} * Rot(x, b), g n1) over the generalized
+ * diagonals diag_k[j] = A[j][(j + k) mod N/2], k = g n1 + b, 0 <= b < n1
+ * (g = floor(k / n1)); pt_{g,b} encodes diag_k rotated right by g n1.  No
+ * rescale is applied: the caller rescales. */
+
+/* From n_diag diagonals of N/2 doubles each (rows of diag_re / diag_im, im
+ * may be NULL) at offsets[] (|k| < N/2, distinct), encoded at pt_scale
+ * (0 = q_level) and cached on the device in evaluation form.
+ * Errors: HCK_EINVAL, HCK_ELEVEL. */
+int hck_lt_create(hck_context *ctx, const double *diag_re, const double *diag_im,
+                  const int32_t *offsets, uint32_t n_diag, uint32_t n_slots, uint32_t baby_step,
+                  double pt_scale, uint32_t level, hck_linear_transform **out);
+/* From already encoded, already pre-rotated diagonals: residues
+ * [n_diag][level+1][N] (coefficient domain). */
+int hck_lt_create_from_residues(hck_context *ctx, const uint64_t *res, const int32_t *offsets,
+                                uint32_t n_diag, uint32_t baby_step, double pt_scale,
+                                uint32_t level, hck_linear_transform **out);
+/* Rotation steps the transform needs keys for, ascending.  `cap` is the
+ * capacity of steps[]; *n receives the count (steps may be NULL to query). */
+int hck_lt_required_steps(const hck_linear_transform *lt, int32_t *steps, uint32_t cap,
+                          uint32_t *n);
+/* Errors: HCK_ELEVEL (input level != transform level), HCK_ENOKEY. */
+int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_ciphertext *a,
+                 const hck_galois_keys *gks, hck_ciphertext *out);
+int hck_lt_destroy(hck_linear_transform *lt);
+
+/* ---- kernel timing --------------------------------------------------------
+ * With timing on, every kernel launch is bracketed by HIP events on the
+ * context stream and its duration added to a per-kernel-name total, read
+ * (after waiting for the stream) with hck_timing_read, together with the
+ * launches' summed algorithmic HBM bytes (each operand read once, each result
+ * written once) and 64-bit modular multiplications.  `name` is one of the
+ * names hck_timing_names lists (comma separated).  Any output may be NULL. */
+int hck_timing_enable(hck_context *ctx, int on);
+int hck_timing_reset(hck_context *ctx);
+int hck_timing_read(hck_context *ctx, const char *name, double *total_ms, uint64_t *launches,
+                    double *bytes, double *mulmods);
+int hck_timing_names(hck_context *ctx, char *buf, size_t cap);
+
+/* ---- client-side host utilities (no context, no device) -------------------
+ * The paper's client encodes, encrypts and decodes (section 3.2 "Encoding and
+ * Batching"; section 3.3.4 result recovery).  These run on the host only. */
+
+/* SHAKE-256 (FIPS 202) of msg, outlen bytes. */
+int hck_shake256(const uint8_t *msg, size_t len, uint8_t *out, size_t outlen);
+/* The samplers behind key generation and encryption: stream
+ * SHAKE-256("hipckks/" || tag || "/" || le64(seed) || le32(index)).
+ * Uniform: 64-bit little-endian words masked to bitlen(q), kept when < q.
+ * Ternary (stream index 0): bytes, 255 rejected, b mod 3 -> 0, +1, -1.
+ * Gaussian (stream index 0): sigma = 3.2 cut at 19 by a cumulative table on
+ * the top 63 bits of each 64-bit word, bit 0 the sign. */
+int hck_sample_uniform(const char *tag, uint64_t seed, uint32_t index, uint64_t q,
+                       uint64_t *out, size_t n);
+int hck_sample_ternary(const char *tag, uint64_t seed, int32_t *out, size_t n);
+int hck_sample_gaussian(const char *tag, uint64_t seed, int32_t *out, size_t n);
+/* Integer coefficients [N] of the encoding of N/2 slots at `scale` (as
+ * hck_encode, before reduction modulo the primes). */
+int hck_encode_coeffs(uint32_t log_n, const double *re, const double *im, double scale,
+                      int64_t *coeffs);
+/* Slots [N/2] of coefficient-domain residues [nl][N] over mods[0..nl): centred
+ * CRT, divided by scale, evaluated at the slot roots.  im may be NULL. */
+int hck_decode_residues(uint32_t log_n, const uint64_t *res, const uint64_t *mods, uint32_t nl,
+                        double scale, double *re, double *im);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIPCKKS_H */

@@ -1,0 +1,506 @@
+"""Python binding of libhipckks, the MI355X (gfx950) RNS-CKKS evaluation library.
+
+Argument marshalling only: every homomorphic operation runs in the HIP
+library's kernels.  The raw C entry points are available under their C names
+(``capi.hck_add`` ...); ``Context`` and the handle classes wrap them.  There is
+no fallback: importing this package without the built library raises.
+
+Build the library first: ``python -m paper_2603_22437_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhipckks.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2603_22437_amd.build`")
+
+capi = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_U32, _U64, _I32, _D, _SZ, _I = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                                  ctypes.c_double, ctypes.c_size_t, ctypes.c_int)
+_PU32 = ctypes.POINTER(ctypes.c_uint32)
+_PD = ctypes.POINTER(ctypes.c_double)
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("log_n", _U32), ("num_q", _U32), ("num_p", _U32), ("dnum", _U32),
+                ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64))]
+
+
+# C signature table: name -> (argtypes, restype).  Every symbol of hipckks.h.
+SIGNATURES = {
+    "hck_context_create": ([ctypes.POINTER(_Params), _I, _P, _PP], _I),
+    "hck_context_destroy": ([_P], _I),
+    "hck_context_set_stream": ([_P, _P], _I),
+    "hck_synchronize": ([_P], _I),
+    "hck_last_error": ([], ctypes.c_char_p),
+    "hck_galois_element": ([_P, _I32], _U32),
+    "hck_keygen_secret": ([_P, _U64, _PP], _I),
+    "hck_secret_key_import": ([_P, _P, _PP], _I),
+    "hck_secret_key_destroy": ([_P], _I),
+    "hck_keygen_public": ([_P, _P, _U64, _PP], _I),
+    "hck_public_key_export": ([_P, _P, _P, _SZ], _I),
+    "hck_public_key_destroy": ([_P], _I),
+    "hck_keygen_relin": ([_P, _P, _U64, _PP], _I),
+    "hck_switch_key_export": ([_P, _P, _P, _SZ], _I),
+    "hck_switch_key_destroy": ([_P], _I),
+    "hck_keygen_galois": ([_P, _P, _P, _U32, _U64, _PP], _I),
+    "hck_keygen_rotation": ([_P, _P, _P, _U32, _U64, _PP], _I),
+    "hck_galois_keys_export": ([_P, _P, _U32, _P, _SZ], _I),
+    "hck_galois_keys_count": ([_P, _PU32], _I),
+    "hck_galois_keys_destroy": ([_P], _I),
+    "hck_encode": ([_P, _P, _P, _U32, _D, _U32, _PP], _I),
+    "hck_plaintext_import": ([_P, _P, _U32, _D, _PP], _I),
+    "hck_plaintext_export": ([_P, _P, _P, _SZ, _PU32, _PD], _I),
+    "hck_decode": ([_P, _P, _P, _P, _U32], _I),
+    "hck_plaintext_destroy": ([_P], _I),
+    "hck_ciphertext_create": ([_P, _PP], _I),
+    "hck_ciphertext_import": ([_P, _P, _U32, _U32, _D, _PP], _I),
+    "hck_ciphertext_export": ([_P, _P, _P, _SZ, _PU32, _PU32, _PD], _I),
+    "hck_ciphertext_info": ([_P, _PU32, _PU32, _PD], _I),
+    "hck_ciphertext_destroy": ([_P], _I),
+    "hck_encrypt_sk": ([_P, _P, _P, _U64, _P], _I),
+    "hck_encrypt_pk": ([_P, _P, _P, _U64, _P], _I),
+    "hck_decrypt": ([_P, _P, _P, _PP], _I),
+    "hck_add": ([_P, _P, _P, _P], _I),
+    "hck_sub": ([_P, _P, _P, _P], _I),
+    "hck_add_plain": ([_P, _P, _P, _P], _I),
+    "hck_mul_plain": ([_P, _P, _P, _P], _I),
+    "hck_drop_level": ([_P, _P, _U32, _P], _I),
+    "hck_mul": ([_P, _P, _P, _P], _I),
+    "hck_relinearize": ([_P, _P, _P, _P], _I),
+    "hck_rescale": ([_P, _P, _P], _I),
+    "hck_rotate": ([_P, _P, _I32, _P, _P], _I),
+    "hck_apply_galois": ([_P, _P, _U32, _P, _P], _I),
+    "hck_keyswitch": ([_P, _P, _P, _P], _I),
+    "hck_lt_create": ([_P, _P, _P, _P, _U32, _U32, _U32, _D, _U32, _PP], _I),
+    "hck_lt_create_from_residues": ([_P, _P, _P, _U32, _U32, _D, _U32, _PP], _I),
+    "hck_lt_required_steps": ([_P, _P, _U32, _PU32], _I),
+    "hck_lt_apply": ([_P, _P, _P, _P, _P], _I),
+    "hck_lt_destroy": ([_P], _I),
+    "hck_timing_enable": ([_P, _I], _I),
+    "hck_timing_reset": ([_P], _I),
+    "hck_timing_read": ([_P, ctypes.c_char_p, _PD, ctypes.POINTER(ctypes.c_uint64), _PD, _PD], _I),
+    "hck_timing_names": ([_P, ctypes.c_char_p, _SZ], _I),
+    "hck_shake256": ([_P, _SZ, _P, _SZ], _I),
+    "hck_sample_uniform": ([ctypes.c_char_p, _U64, _U32, _U64, _P, _SZ], _I),
+    "hck_sample_ternary": ([ctypes.c_char_p, _U64, _P, _SZ], _I),
+    "hck_sample_gaussian": ([ctypes.c_char_p, _U64, _P, _SZ], _I),
+    "hck_encode_coeffs": ([_U32, _P, _P, _D, _P], _I),
+    "hck_decode_residues": ([_U32, _P, _P, _U32, _D, _P, _P], _I),
+}
+
+for _name, (_args, _res) in SIGNATURES.items():
+    _fn = getattr(capi, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+    globals()[_name] = _fn
+
+HCK_OK, HCK_EINVAL, HCK_ENOMEM, HCK_EDEVICE, HCK_ELEVEL, HCK_ESCALE, HCK_ENOKEY, HCK_EPARAMS = \
+    0, -1, -2, -3, -4, -5, -6, -7
+
+
+class HckError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hipckks error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise HckError(rc, capi.hck_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _u64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+
+
+# ---------------------------------------------------------------------------
+# host utilities (no device)
+# ---------------------------------------------------------------------------
+
+def shake256(msg: bytes, outlen: int) -> bytes:
+    out = ctypes.create_string_buffer(outlen)
+    buf = ctypes.create_string_buffer(msg, len(msg))
+    _check(capi.hck_shake256(buf, len(msg), out, outlen))
+    return out.raw
+
+
+def sample_uniform(tag: str, seed: int, index: int, q: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.uint64)
+    _check(capi.hck_sample_uniform(tag.encode(), seed, index, q, _ptr(out), n))
+    return out
+
+
+def sample_ternary(tag: str, seed: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.int32)
+    _check(capi.hck_sample_ternary(tag.encode(), seed, _ptr(out), n))
+    return out
+
+
+def sample_gaussian(tag: str, seed: int, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.int32)
+    _check(capi.hck_sample_gaussian(tag.encode(), seed, _ptr(out), n))
+    return out
+
+
+def encode_coeffs(log_n: int, z, scale: float) -> np.ndarray:
+    z = np.asarray(z)
+    re = np.ascontiguousarray(z.real, dtype=np.float64)
+    im = np.ascontiguousarray(z.imag, dtype=np.float64) if np.iscomplexobj(z) else None
+    out = np.empty(1 << log_n, dtype=np.int64)
+    _check(capi.hck_encode_coeffs(log_n, _ptr(re), _ptr(im) if im is not None else None,
+                                  scale, _ptr(out)))
+    return out
+
+
+def decode_residues(log_n: int, res: np.ndarray, mods, scale: float) -> np.ndarray:
+    res = _u64(res)
+    mods = _u64(mods)
+    re = np.empty((1 << log_n) // 2)
+    im = np.empty_like(re)
+    _check(capi.hck_decode_residues(log_n, _ptr(res), _ptr(mods), len(mods), scale,
+                                    _ptr(re), _ptr(im)))
+    return re + 1j * im
+
+
+# ---------------------------------------------------------------------------
+# handles
+# ---------------------------------------------------------------------------
+
+class _Handle:
+    _destroy = None
+
+    def __init__(self, ctx, h):
+        self.ctx = ctx          # keeps the context alive
+        self.h = h
+
+    def close(self):
+        if self.h:
+            type(self)._destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        return self.h
+
+
+class SecretKey(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_secret_key_destroy(h))
+
+
+class PublicKey(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_public_key_destroy(h))
+
+
+class SwitchKey(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_switch_key_destroy(h))
+
+
+class GaloisKeys(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_galois_keys_destroy(h))
+
+    def __len__(self):
+        n = ctypes.c_uint32()
+        _check(capi.hck_galois_keys_count(self.h, ctypes.byref(n)))
+        return n.value
+
+
+class Plaintext(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_plaintext_destroy(h))
+
+
+class Ciphertext(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_ciphertext_destroy(h))
+
+    def info(self):
+        s, l, sc = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_double()
+        _check(capi.hck_ciphertext_info(self.h, ctypes.byref(s), ctypes.byref(l),
+                                        ctypes.byref(sc)))
+        return s.value, l.value, sc.value
+
+    @property
+    def size(self):
+        return self.info()[0]
+
+    @property
+    def level(self):
+        return self.info()[1]
+
+    @property
+    def scale(self):
+        return self.info()[2]
+
+
+class LinearTransform(_Handle):
+    _destroy = staticmethod(lambda h: capi.hck_lt_destroy(h))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream   # torch.cuda.Stream
+
+
+class Context:
+    """One parameter set on one device and stream (hck_context)."""
+
+    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0, stream=None):
+        self._q = _u64(q)
+        self._p = _u64(p)
+        prm = _Params(log_n, len(self._q), len(self._p), dnum,
+                      self._q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                      self._p.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+        h = ctypes.c_void_p()
+        _check(capi.hck_context_create(ctypes.byref(prm), device, _stream_handle(stream),
+                                       ctypes.byref(h)))
+        self.h = h.value
+        self.log_n, self.n, self.dnum = log_n, 1 << log_n, dnum
+        self.q = [int(x) for x in q]
+        self.p = [int(x) for x in p]
+        self.L, self.K = len(self.q), len(self.p)
+        self.n_slots = self.n // 2
+
+    @classmethod
+    def from_params(cls, prm: dict, device: int = 0, stream=None):
+        return cls(prm["log_n"], prm["q"], prm["p"], prm["dnum"], device, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            capi.hck_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def _as_parameter_(self):
+        return self.h
+
+    def _new(self, fn, *args, cls):
+        h = ctypes.c_void_p()
+        _check(fn(self.h, *args, ctypes.byref(h)))
+        return cls(self, h.value)
+
+    def set_stream(self, stream):
+        _check(capi.hck_context_set_stream(self.h, _stream_handle(stream)))
+
+    def synchronize(self):
+        _check(capi.hck_synchronize(self.h))
+
+    def galois_element(self, step: int) -> int:
+        return capi.hck_galois_element(self.h, step)
+
+    # --- keys ---
+    def keygen_secret(self, seed: int) -> SecretKey:
+        return self._new(capi.hck_keygen_secret, seed, cls=SecretKey)
+
+    def secret_key_import(self, coeffs) -> SecretKey:
+        c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.int8))
+        return self._new(capi.hck_secret_key_import, _ptr(c), cls=SecretKey)
+
+    def keygen_public(self, sk, seed: int) -> PublicKey:
+        return self._new(capi.hck_keygen_public, sk, seed, cls=PublicKey)
+
+    def public_key_export(self, pk) -> np.ndarray:
+        out = np.empty((2, self.L, self.n), dtype=np.uint64)
+        _check(capi.hck_public_key_export(self.h, pk, _ptr(out), out.size))
+        return out
+
+    def keygen_relin(self, sk, seed: int) -> SwitchKey:
+        return self._new(capi.hck_keygen_relin, sk, seed, cls=SwitchKey)
+
+    def switch_key_export(self, swk) -> np.ndarray:
+        out = np.empty((self.dnum, 2, self.L + self.K, self.n), dtype=np.uint64)
+        _check(capi.hck_switch_key_export(self.h, swk, _ptr(out), out.size))
+        return out
+
+    def keygen_galois(self, sk, elements, seed: int) -> GaloisKeys:
+        e = np.ascontiguousarray(np.asarray(elements, dtype=np.uint32))
+        return self._new(capi.hck_keygen_galois, sk, _ptr(e), len(e), seed, cls=GaloisKeys)
+
+    def keygen_rotation(self, sk, steps, seed: int) -> GaloisKeys:
+        s = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+        return self._new(capi.hck_keygen_rotation, sk, _ptr(s), len(s), seed, cls=GaloisKeys)
+
+    def galois_keys_export(self, gks, element: int) -> np.ndarray:
+        out = np.empty((self.dnum, 2, self.L + self.K, self.n), dtype=np.uint64)
+        _check(capi.hck_galois_keys_export(self.h, gks, element, _ptr(out), out.size))
+        return out
+
+    # --- plaintexts ---
+    def encode(self, z, scale: float, level: int) -> Plaintext:
+        z = np.asarray(z)
+        re = np.ascontiguousarray(z.real, dtype=np.float64)
+        im = np.ascontiguousarray(z.imag, dtype=np.float64) if np.iscomplexobj(z) else None
+        return self._new(capi.hck_encode, _ptr(re), _ptr(im) if im is not None else None,
+                         len(re), scale, level, cls=Plaintext)
+
+    def plaintext_import(self, res, level: int, scale: float) -> Plaintext:
+        r = _u64(res)
+        return self._new(capi.hck_plaintext_import, _ptr(r), level, scale, cls=Plaintext)
+
+    def plaintext_export(self, pt):
+        lvl, sc = ctypes.c_uint32(), ctypes.c_double()
+        out = np.empty((self.L, self.n), dtype=np.uint64)
+        _check(capi.hck_plaintext_export(self.h, pt, _ptr(out), out.size, ctypes.byref(lvl),
+                                         ctypes.byref(sc)))
+        return out[: lvl.value + 1].copy(), lvl.value, sc.value
+
+    def decode(self, pt) -> np.ndarray:
+        re = np.empty(self.n_slots)
+        im = np.empty(self.n_slots)
+        _check(capi.hck_decode(self.h, pt, _ptr(re), _ptr(im), self.n_slots))
+        return re + 1j * im
+
+    # --- ciphertexts ---
+    def ciphertext(self) -> Ciphertext:
+        return self._new(capi.hck_ciphertext_create, cls=Ciphertext)
+
+    def ciphertext_import(self, res, level: int, scale: float) -> Ciphertext:
+        r = _u64(res)
+        return self._new(capi.hck_ciphertext_import, _ptr(r), r.shape[0], level, scale,
+                         cls=Ciphertext)
+
+    def ciphertext_export(self, ct):
+        size, lvl, sc = ct.info()
+        out = np.empty((size, lvl + 1, self.n), dtype=np.uint64)
+        _check(capi.hck_ciphertext_export(self.h, ct, _ptr(out), out.size, None, None, None))
+        return out, lvl, sc
+
+    def _out(self, out):
+        return self.ciphertext() if out is None else out
+
+    def encrypt_sk(self, sk, pt, seed: int, out=None) -> Ciphertext:
+        out = self._out(out)
+        _check(capi.hck_encrypt_sk(self.h, sk, pt, seed, out))
+        return out
+
+    def encrypt_pk(self, pk, pt, seed: int, out=None) -> Ciphertext:
+        out = self._out(out)
+        _check(capi.hck_encrypt_pk(self.h, pk, pt, seed, out))
+        return out
+
+    def decrypt(self, sk, ct) -> Plaintext:
+        return self._new(capi.hck_decrypt, sk, ct, cls=Plaintext)
+
+    # --- evaluation ---
+    def _binary(self, fn, a, b, out):
+        out = self._out(out)
+        _check(fn(self.h, a, b, out))
+        return out
+
+    def add(self, a, b, out=None):
+        return self._binary(capi.hck_add, a, b, out)
+
+    def sub(self, a, b, out=None):
+        return self._binary(capi.hck_sub, a, b, out)
+
+    def add_plain(self, a, pt, out=None):
+        return self._binary(capi.hck_add_plain, a, pt, out)
+
+    def mul_plain(self, a, pt, out=None):
+        return self._binary(capi.hck_mul_plain, a, pt, out)
+
+    def mul(self, a, b, out=None):
+        return self._binary(capi.hck_mul, a, b, out)
+
+    def relinearize(self, a, rlk, out=None):
+        return self._binary(capi.hck_relinearize, a, rlk, out)
+
+    def keyswitch(self, a, swk, out=None):
+        return self._binary(capi.hck_keyswitch, a, swk, out)
+
+    def drop_level(self, a, level: int, out=None):
+        out = self._out(out)
+        _check(capi.hck_drop_level(self.h, a, level, out))
+        return out
+
+    def rescale(self, a, out=None):
+        out = self._out(out)
+        _check(capi.hck_rescale(self.h, a, out))
+        return out
+
+    def rotate(self, a, step: int, gks, out=None):
+        out = self._out(out)
+        _check(capi.hck_rotate(self.h, a, step, gks, out))
+        return out
+
+    def apply_galois(self, a, element: int, gks, out=None):
+        out = self._out(out)
+        _check(capi.hck_apply_galois(self.h, a, element, gks, out))
+        return out
+
+    # --- linear transforms ---
+    def lt_create(self, diags: dict, baby_step: int, level: int, pt_scale: float = 0.0
+                  ) -> LinearTransform:
+        offs = np.array(sorted(diags), dtype=np.int32)
+        mat = np.stack([np.asarray(diags[k]) for k in offs])
+        re = np.ascontiguousarray(mat.real, dtype=np.float64)
+        im = np.ascontiguousarray(mat.imag, dtype=np.float64) if np.iscomplexobj(mat) else None
+        return self._new(capi.hck_lt_create, _ptr(re), _ptr(im) if im is not None else None,
+                         _ptr(offs), len(offs), self.n_slots, baby_step, pt_scale, level,
+                         cls=LinearTransform)
+
+    def lt_create_from_residues(self, res: dict, baby_step: int, level: int,
+                                pt_scale: float) -> LinearTransform:
+        offs = np.array(sorted(res), dtype=np.int32)
+        r = _u64(np.stack([res[int(k)] for k in offs]))
+        return self._new(capi.hck_lt_create_from_residues, _ptr(r), _ptr(offs), len(offs),
+                         baby_step, pt_scale, level, cls=LinearTransform)
+
+    def lt_required_steps(self, lt) -> list[int]:
+        n = ctypes.c_uint32()
+        _check(capi.hck_lt_required_steps(lt, None, 0, ctypes.byref(n)))
+        out = np.empty(n.value, dtype=np.int32)
+        _check(capi.hck_lt_required_steps(lt, _ptr(out), n.value, ctypes.byref(n)))
+        return [int(x) for x in out]
+
+    def lt_apply(self, lt, a, gks, out=None):
+        out = self._out(out)
+        _check(capi.hck_lt_apply(self.h, lt, a, gks, out))
+        return out
+
+    # --- kernel timing ---
+    def timing(self, on: bool):
+        _check(capi.hck_timing_enable(self.h, 1 if on else 0))
+
+    def timing_reset(self):
+        _check(capi.hck_timing_reset(self.h))
+
+    def timing_read(self, name: str) -> dict:
+        """Summed duration (ms), launches, algorithmic bytes and modular
+        multiplications of one kernel since the last reset."""
+        ms, cnt, by, mm = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
+        _check(capi.hck_timing_read(self.h, name.encode(), ctypes.byref(ms), ctypes.byref(cnt),
+                                    ctypes.byref(by), ctypes.byref(mm)))
+        return dict(ms=ms.value, launches=cnt.value, bytes=by.value, mulmods=mm.value)
+
+    def timing_names(self) -> list[str]:
+        buf = ctypes.create_string_buffer(4096)
+        _check(capi.hck_timing_names(self.h, buf, 4096))
+        return [x for x in buf.value.decode().split(",") if x]

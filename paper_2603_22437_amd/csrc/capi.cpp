@@ -1,0 +1,1067 @@
+// The C ABI: keys, plaintexts, ciphertexts, evaluation, linear transforms.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+using namespace hck;
+
+namespace {
+
+int enter(hck_context *ctx) {
+  if (!ctx) return set_error(HCK_EINVAL, "null context");
+  if (ctx->broken) return set_error(HCK_EDEVICE, "context unusable after an earlier HIP error");
+  HCK_HIP(ctx, hipSetDevice(ctx->device));
+  return HCK_OK;
+}
+
+#define ENTER(ctx)             \
+  do {                         \
+    int _rc = enter(ctx);      \
+    if (_rc) return _rc;       \
+  } while (0)
+#define TRY(expr)              \
+  do {                         \
+    int _rc = (expr);          \
+    if (_rc) return _rc;       \
+  } while (0)
+
+size_t poly_stride(const hck_context *ctx) { return (size_t)ctx->L * ctx->n; }
+
+// Host buffers are often locals of the caller, so uploads complete before
+// returning (set-up paths only; evaluation never uploads).
+int upload(hck_context *ctx, uint64_t *dst, const void *src, size_t bytes) {
+  HCK_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+  HCK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HCK_OK;
+}
+
+int download(hck_context *ctx, void *dst, const uint64_t *src, size_t bytes) {
+  HCK_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HCK_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return HCK_OK;
+}
+
+// rows (row, modulus) of a [polys][stride/N][N] buffer for limbs 0..level
+std::vector<std::pair<uint16_t, uint8_t>> poly_rows(uint32_t polys, uint32_t rows_per_poly,
+                                                    uint32_t nlimbs, uint32_t mod_base = 0) {
+  std::vector<std::pair<uint16_t, uint8_t>> r;
+  for (uint32_t p = 0; p < polys; p++)
+    for (uint32_t i = 0; i < nlimbs; i++)
+      r.push_back({(uint16_t)(p * rows_per_poly + i), (uint8_t)(mod_base + i)});
+  return r;
+}
+
+LimbMap make_map(const std::vector<std::pair<uint16_t, uint8_t>> &rows, size_t start,
+                 size_t cap = kMaxLimbs) {
+  LimbMap m;
+  m.n = (uint32_t)std::min(rows.size() - start, cap);
+  for (uint32_t i = 0; i < m.n; i++) {
+    m.row[i] = rows[start + i].first;
+    m.mod[i] = rows[start + i].second;
+  }
+  return m;
+}
+
+int inverse_rows(hck_context *ctx, uint64_t *buf,
+                 const std::vector<std::pair<uint16_t, uint8_t>> &rows) {
+  for (size_t s = 0; s < rows.size(); s += kMaxRows) TRY(ntt_inverse(ctx, buf, make_map(rows, s, kMaxRows), nullptr));
+  return HCK_OK;
+}
+
+int mont_rows(hck_context *ctx, uint64_t *buf,
+              const std::vector<std::pair<uint16_t, uint8_t>> &rows, bool to) {
+  for (size_t s = 0; s < rows.size(); s += kMaxRows)
+    TRY(launch_to_mont(ctx, buf, make_map(rows, s, kMaxRows), to));
+  return HCK_OK;
+}
+
+// Uniform limbs drawn in parallel host threads (each limb its own stream).
+void sample_uniform_limbs(hck_context *ctx, const std::string &tag, uint64_t seed,
+                          uint32_t nlimbs, const std::vector<uint32_t> &mod_of_limb,
+                          std::vector<uint64_t> &out) {
+  out.resize((size_t)nlimbs * ctx->n);
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < nt; w++)
+    th.emplace_back([&, w]() {
+      for (uint32_t t = w; t < nlimbs; t += nt)
+        sample_uniform(tag, seed, t, ctx->mods[mod_of_limb[t]], out.data() + (size_t)t * ctx->n,
+                       ctx->n);
+    });
+  for (auto &t : th) t.join();
+}
+
+// Uploads N small integers and embeds them into `rows` of buf.
+int embed_small_host(hck_context *ctx, uint64_t *buf, const std::vector<int32_t> &v,
+                     const std::vector<std::pair<uint16_t, uint8_t>> &rows) {
+  uint64_t *tmp = nullptr;
+  TRY(dev_alloc(ctx, &tmp, (ctx->n + 1) / 2));
+  int rc = upload(ctx, tmp, v.data(), v.size() * sizeof(int32_t));
+  for (size_t s = 0; !rc && s < rows.size(); s += kMaxRows)
+    rc = launch_embed_small(ctx, buf, (const int32_t *)tmp, make_map(rows, s, kMaxRows));
+  dev_free(ctx, tmp);
+  return rc;
+}
+
+bool scales_match(double a, double b) {
+  return std::fabs(a - b) <= std::ldexp(std::max(std::fabs(a), std::fabs(b)), -30);
+}
+
+// residues (host, coefficient domain) -> evaluation form rows of buf, checked < q
+int import_rows(hck_context *ctx, uint64_t *buf, const uint64_t *res, uint32_t polys,
+                uint32_t rows_per_poly, uint32_t nlimbs) {
+  const size_t n = ctx->n;
+  for (uint32_t p = 0; p < polys; p++)
+    for (uint32_t i = 0; i < nlimbs; i++) {
+      const uint64_t *src = res + ((size_t)p * nlimbs + i) * n;
+      const uint64_t q = ctx->mods[i];
+      for (size_t c = 0; c < n; c++)
+        if (src[c] >= q) return set_error(HCK_EINVAL, "residue not below its prime");
+      TRY(upload(ctx, buf + ((size_t)p * rows_per_poly + i) * n, src, n * 8));
+    }
+  return ntt_forward_rows(ctx, buf, poly_rows(polys, rows_per_poly, nlimbs));
+}
+
+// evaluation-form rows -> host residues (compact [polys][nlimbs][N]); `mont`
+// undoes the Montgomery form first.  Uses a temporary device copy.
+int export_rows(hck_context *ctx, const uint64_t *buf, uint32_t polys, uint32_t rows_per_poly,
+                uint32_t nlimbs, bool mont, uint32_t mod_base, uint64_t *out) {
+  const size_t n = ctx->n;
+  uint64_t *tmp = nullptr;
+  TRY(dev_alloc(ctx, &tmp, (size_t)polys * nlimbs * n));
+  int rc = HCK_OK;
+  for (uint32_t p = 0; p < polys && !rc; p++)
+    rc = launch_copy(ctx, tmp + (size_t)p * nlimbs * n, buf + (size_t)p * rows_per_poly * n,
+                     (size_t)nlimbs * n);
+  auto rows = poly_rows(polys, nlimbs, nlimbs, 0);
+  // modulus of compact row (p, i) is the chain index of limb i (+ mod_base)
+  for (auto &r : rows) r.second = (uint8_t)(mod_base + r.first % nlimbs);
+  if (!rc && mont) rc = mont_rows(ctx, tmp, rows, false);
+  if (!rc) rc = inverse_rows(ctx, tmp, rows);
+  if (!rc) rc = download(ctx, out, tmp, (size_t)polys * nlimbs * n * 8);
+  dev_free(ctx, tmp);
+  return rc;
+}
+
+// key rows in chain order: limb t of a full-basis polynomial is modulus t
+int export_key_rows(hck_context *ctx, const uint64_t *buf, uint32_t polys, uint64_t *out) {
+  const size_t n = ctx->n;
+  const uint32_t nm = ctx->L + ctx->K;
+  uint64_t *tmp = nullptr;
+  TRY(dev_alloc(ctx, &tmp, (size_t)polys * nm * n));
+  int rc = launch_copy(ctx, tmp, buf, (size_t)polys * nm * n);
+  auto rows = poly_rows(polys, nm, nm, 0);
+  if (!rc) rc = mont_rows(ctx, tmp, rows, false);
+  if (!rc) rc = inverse_rows(ctx, tmp, rows);
+  if (!rc) rc = download(ctx, out, tmp, (size_t)polys * nm * n * 8);
+  dev_free(ctx, tmp);
+  return rc;
+}
+
+// swk(s' -> s): digit j = (-a_j s + e_j + [i in D_j] (P mod q_i) s'_i, a_j) on
+// all L+K limbs, stored in evaluation + Montgomery form.  sp_m: s' as
+// evaluation-form Montgomery rows [L+K][N].
+int make_switch_key(hck_context *ctx, const hck_secret_key *sk, const uint64_t *sp_m,
+                    const std::string &tag, uint64_t seed, hck_switch_key **out) {
+  const size_t n = ctx->n;
+  const uint32_t L = ctx->L, K = ctx->K, nm = L + K;
+  hck_switch_key *key = new hck_switch_key();
+  key->ctx = ctx;
+  int rc = dev_alloc(ctx, &key->data, (size_t)ctx->dnum * 2 * nm * n);
+  if (rc) {
+    delete key;
+    return rc;
+  }
+  uint64_t *tmp = ws_tmp(ctx);
+  std::vector<uint32_t> mod_of(nm);
+  for (uint32_t t = 0; t < nm; t++) mod_of[t] = t;
+  std::vector<uint64_t> a;
+  std::vector<int32_t> e(n);
+  const LimbMap full = fullmap(ctx);
+  for (uint32_t j = 0; j < ctx->dnum && !rc; j++) {
+    uint64_t *b = key->data + (size_t)2 * j * nm * n;
+    uint64_t *ak = b + (size_t)nm * n;
+    sample_uniform_limbs(ctx, tag + "/a/" + std::to_string(j), seed, nm, mod_of, a);
+    sample_gaussian(tag + "/e/" + std::to_string(j), seed, e.data(), n);
+    rc = upload(ctx, ak, a.data(), a.size() * 8);
+    if (!rc) rc = embed_small_host(ctx, b, e, poly_rows(1, nm, nm));
+    if (!rc) rc = ntt_forward_rows(ctx, b, poly_rows(2, nm, nm));
+    // b = e - a s
+    if (!rc) rc = launch_mul_mont(ctx, tmp, ak, sk->data, full, false);
+    if (!rc) rc = launch_addsub(ctx, b, b, tmp, full, 1);
+    // + (P mod q_i) s' on the limbs of digit j
+    const uint32_t lo = j * ctx->alpha, hi = std::min(L, lo + ctx->alpha);
+    if (!rc && lo < hi) {
+      LimbMap m;
+      RowScale sc;
+      m.n = hi - lo;
+      for (uint32_t i = lo; i < hi; i++) {
+        const uint64_t q = ctx->mods[i];
+        uint64_t pm = 1;
+        for (uint32_t k = 0; k < K; k++) pm = h_mulmod(pm, ctx->mods[L + k] % q, q);
+        m.row[i - lo] = (uint16_t)i;
+        m.mod[i - lo] = (uint8_t)i;
+        sc.w[i - lo] = pm;
+        sc.wp[i - lo] = 0;
+        sc.add[i - lo] = 0;
+      }
+      rc = launch_scalar_mac(ctx, b, sp_m, m, sc);
+    }
+    if (!rc) rc = mont_rows(ctx, b, poly_rows(2, nm, nm), true);
+  }
+  if (rc) {
+    dev_free(ctx, key->data);
+    delete key;
+    return rc;
+  }
+  *out = key;
+  return HCK_OK;
+}
+
+int lt_alloc_ct(hck_context *ctx, hck_ciphertext **ct) {
+  *ct = new hck_ciphertext();
+  (*ct)->ctx = ctx;
+  return ensure_ct(ctx, *ct, 2);
+}
+
+}  // namespace
+
+// Per-transform device scratch of hck_lt_apply (baby-step ciphertexts).
+struct LtScratch {
+  std::vector<hck_ciphertext *> babies;
+  hck_ciphertext *inner = nullptr, *giant = nullptr;
+};
+
+extern "C" {
+
+/* ---- keys -------------------------------------------------------------------- */
+
+int hck_keygen_secret(hck_context *ctx, uint64_t seed, hck_secret_key **out) {
+  ENTER(ctx);
+  if (!out) return set_error(HCK_EINVAL, "null output");
+  std::vector<int32_t> s(ctx->n);
+  sample_ternary("sk", seed, s.data(), ctx->n);
+  std::vector<int8_t> c(s.begin(), s.end());
+  return hck_secret_key_import(ctx, c.data(), out);
+}
+
+int hck_secret_key_import(hck_context *ctx, const int8_t *coeffs, hck_secret_key **out) {
+  ENTER(ctx);
+  if (!coeffs || !out) return set_error(HCK_EINVAL, "null argument");
+  const uint32_t nm = ctx->L + ctx->K;
+  std::vector<int32_t> v(ctx->n);
+  for (uint32_t i = 0; i < ctx->n; i++) {
+    if (coeffs[i] < -1 || coeffs[i] > 1) return set_error(HCK_EINVAL, "secret not ternary");
+    v[i] = coeffs[i];
+  }
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  hck_secret_key *sk = new hck_secret_key();
+  sk->ctx = ctx;
+  sk->coeffs.assign(coeffs, coeffs + ctx->n);
+  int rc = dev_alloc(ctx, &sk->data, (size_t)nm * ctx->n);
+  auto rows = poly_rows(1, nm, nm);
+  if (!rc) rc = embed_small_host(ctx, sk->data, v, rows);
+  if (!rc) rc = ntt_forward_rows(ctx, sk->data, rows);
+  if (!rc) rc = mont_rows(ctx, sk->data, rows, true);
+  if (rc) {
+    dev_free(ctx, sk->data);
+    delete sk;
+    return rc;
+  }
+  *out = sk;
+  return HCK_OK;
+}
+
+int hck_secret_key_destroy(hck_secret_key *sk) {
+  if (sk) {
+    dev_free(sk->ctx, sk->data);
+    delete sk;
+  }
+  return HCK_OK;
+}
+
+int hck_keygen_public(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
+                      hck_public_key **out) {
+  ENTER(ctx);
+  if (!sk || !out) return set_error(HCK_EINVAL, "null argument");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  const size_t n = ctx->n;
+  const uint32_t L = ctx->L;
+  hck_public_key *pk = new hck_public_key();
+  pk->ctx = ctx;
+  int rc = dev_alloc(ctx, &pk->data, (size_t)2 * L * n);
+  std::vector<uint32_t> mod_of(L);
+  for (uint32_t t = 0; t < L; t++) mod_of[t] = t;
+  std::vector<uint64_t> a;
+  std::vector<int32_t> e(n);
+  sample_uniform_limbs(ctx, "pk_a", seed, L, mod_of, a);
+  sample_gaussian("pk_e", seed, e.data(), n);
+  uint64_t *b = pk->data, *ak = pk->data + (size_t)L * n, *tmp = ws_tmp(ctx);
+  const LimbMap qm = qmap(ctx, L - 1);
+  if (!rc) rc = upload(ctx, ak, a.data(), a.size() * 8);
+  if (!rc) rc = embed_small_host(ctx, b, e, poly_rows(1, L, L));
+  if (!rc) rc = ntt_forward_rows(ctx, b, poly_rows(2, L, L));
+  if (!rc) rc = launch_mul_mont(ctx, tmp, ak, sk->data, qm, false);
+  if (!rc) rc = launch_addsub(ctx, b, b, tmp, qm, 1);
+  if (!rc) rc = mont_rows(ctx, pk->data, poly_rows(2, L, L), true);
+  if (rc) {
+    dev_free(ctx, pk->data);
+    delete pk;
+    return rc;
+  }
+  *out = pk;
+  return HCK_OK;
+}
+
+int hck_public_key_export(hck_context *ctx, const hck_public_key *pk, uint64_t *out,
+                          size_t n_words) {
+  ENTER(ctx);
+  if (!pk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (n_words != (size_t)2 * ctx->L * ctx->n) return set_error(HCK_EINVAL, "size mismatch");
+  return export_rows(ctx, pk->data, 2, ctx->L, ctx->L, true, 0, out);
+}
+
+int hck_public_key_destroy(hck_public_key *pk) {
+  if (pk) {
+    dev_free(pk->ctx, pk->data);
+    delete pk;
+  }
+  return HCK_OK;
+}
+
+int hck_keygen_relin(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
+                     hck_switch_key **out) {
+  ENTER(ctx);
+  if (!sk || !out) return set_error(HCK_EINVAL, "null argument");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  // s^2 in Montgomery form: REDC(s~ s~) = s^2 2^64
+  uint64_t *s2 = ws_rot(ctx);  // [L+K][N] fits in [2][L][N] when K <= L
+  uint64_t *own = nullptr;
+  if (ctx->K > ctx->L) {
+    TRY(dev_alloc(ctx, &own, (size_t)(ctx->L + ctx->K) * ctx->n));
+    s2 = own;
+  }
+  int rc = launch_mul_mont(ctx, s2, sk->data, sk->data, fullmap(ctx), false);
+  if (!rc) rc = make_switch_key(ctx, sk, s2, "rlk", seed, out);
+  dev_free(ctx, own);
+  return rc;
+}
+
+int hck_switch_key_export(hck_context *ctx, const hck_switch_key *swk, uint64_t *out,
+                          size_t n_words) {
+  ENTER(ctx);
+  if (!swk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (n_words != (size_t)ctx->dnum * 2 * (ctx->L + ctx->K) * ctx->n)
+    return set_error(HCK_EINVAL, "size mismatch");
+  return export_key_rows(ctx, swk->data, 2 * ctx->dnum, out);
+}
+
+int hck_switch_key_destroy(hck_switch_key *swk) {
+  if (swk) {
+    dev_free(swk->ctx, swk->data);
+    delete swk;
+  }
+  return HCK_OK;
+}
+
+int hck_keygen_galois(hck_context *ctx, const hck_secret_key *sk, const uint32_t *elements,
+                      uint32_t n, uint64_t seed, hck_galois_keys **out) {
+  ENTER(ctx);
+  if (!sk || !out || (n && !elements)) return set_error(HCK_EINVAL, "null argument");
+  for (uint32_t i = 0; i < n; i++)
+    if ((elements[i] & 1) == 0 || elements[i] >= 2 * ctx->n)
+      return set_error(HCK_EINVAL, "Galois element must be odd and below 2N");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  const uint32_t nm = ctx->L + ctx->K;
+  uint64_t *sg = nullptr;
+  TRY(dev_alloc(ctx, &sg, (size_t)nm * ctx->n));
+  hck_galois_keys *gks = new hck_galois_keys();
+  gks->ctx = ctx;
+  int rc = HCK_OK;
+  for (uint32_t i = 0; i < n && !rc; i++) {
+    const uint32_t g = elements[i];
+    if (gks->keys.count(g)) continue;
+    rc = launch_automorphism(ctx, sg, sk->data, 0, 1, fullmap(ctx), g);
+    hck_switch_key *key = nullptr;
+    if (!rc) rc = make_switch_key(ctx, sk, sg, "gk/" + std::to_string(g), seed, &key);
+    if (!rc) gks->keys[g] = key;
+  }
+  dev_free(ctx, sg);
+  if (rc) {
+    hck_galois_keys_destroy(gks);
+    return rc;
+  }
+  *out = gks;
+  return HCK_OK;
+}
+
+int hck_keygen_rotation(hck_context *ctx, const hck_secret_key *sk, const int32_t *steps,
+                        uint32_t n, uint64_t seed, hck_galois_keys **out) {
+  ENTER(ctx);
+  if (n && !steps) return set_error(HCK_EINVAL, "null steps");
+  std::vector<uint32_t> el;
+  for (uint32_t i = 0; i < n; i++)
+    if (((int64_t)steps[i] % (ctx->n / 2)) != 0) el.push_back(galois_of_step(ctx, steps[i]));
+  return hck_keygen_galois(ctx, sk, el.data(), (uint32_t)el.size(), seed, out);
+}
+
+int hck_galois_keys_export(hck_context *ctx, const hck_galois_keys *gks, uint32_t element,
+                           uint64_t *out, size_t n_words) {
+  ENTER(ctx);
+  if (!gks) return set_error(HCK_EINVAL, "null keys");
+  auto it = gks->keys.find(element);
+  if (it == gks->keys.end()) return set_error(HCK_ENOKEY, "no key for this element");
+  return hck_switch_key_export(ctx, it->second, out, n_words);
+}
+
+int hck_galois_keys_count(const hck_galois_keys *gks, uint32_t *n) {
+  if (!gks || !n) return set_error(HCK_EINVAL, "null argument");
+  *n = (uint32_t)gks->keys.size();
+  return HCK_OK;
+}
+
+int hck_galois_keys_destroy(hck_galois_keys *gks) {
+  if (gks) {
+    for (auto &kv : gks->keys) hck_switch_key_destroy(kv.second);
+    delete gks;
+  }
+  return HCK_OK;
+}
+
+/* ---- plaintexts ------------------------------------------------------------- */
+
+static int plaintext_from_rows(hck_context *ctx, const uint64_t *res, uint32_t level, double scale,
+                               hck_plaintext **out) {
+  hck_plaintext *pt = new hck_plaintext();
+  pt->ctx = ctx;
+  pt->level = level;
+  pt->scale = scale;
+  int rc = dev_alloc(ctx, &pt->data, (size_t)(level + 1) * ctx->n);
+  if (!rc) rc = import_rows(ctx, pt->data, res, 1, level + 1, level + 1);
+  if (!rc) rc = mont_rows(ctx, pt->data, poly_rows(1, level + 1, level + 1), true);
+  if (rc) {
+    dev_free(ctx, pt->data);
+    delete pt;
+    return rc;
+  }
+  *out = pt;
+  return HCK_OK;
+}
+
+int hck_plaintext_import(hck_context *ctx, const uint64_t *res, uint32_t level, double scale,
+                         hck_plaintext **out) {
+  ENTER(ctx);
+  if (!res || !out) return set_error(HCK_EINVAL, "null argument");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  return plaintext_from_rows(ctx, res, level, scale, out);
+}
+
+static void coeffs_to_residues(const hck_context *ctx, const std::vector<int64_t> &c,
+                               uint32_t level, std::vector<uint64_t> &res) {
+  const size_t n = ctx->n;
+  res.resize((size_t)(level + 1) * n);
+  for (uint32_t i = 0; i <= level; i++) {
+    const uint64_t q = ctx->mods[i];
+    for (size_t k = 0; k < n; k++) {
+      const int64_t v = c[k];
+      const uint64_t mag = (uint64_t)(v < 0 ? -v : v) % q;
+      res[(size_t)i * n + k] = (v < 0 && mag) ? q - mag : mag;
+    }
+  }
+}
+
+int hck_encode(hck_context *ctx, const double *re, const double *im, uint32_t n_slots,
+               double scale, uint32_t level, hck_plaintext **out) {
+  ENTER(ctx);
+  if (!re || !out) return set_error(HCK_EINVAL, "null argument");
+  if (n_slots != ctx->n / 2) return set_error(HCK_EINVAL, "n_slots must be N/2");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  std::vector<int64_t> c;
+  TRY(encode_coeffs(ctx->log_n, re, im, scale, c));
+  std::vector<uint64_t> res;
+  coeffs_to_residues(ctx, c, level, res);
+  return plaintext_from_rows(ctx, res.data(), level, scale, out);
+}
+
+int hck_plaintext_export(hck_context *ctx, const hck_plaintext *pt, uint64_t *out,
+                         size_t n_words, uint32_t *level, double *scale) {
+  ENTER(ctx);
+  if (!pt || !out) return set_error(HCK_EINVAL, "null argument");
+  if (n_words < (size_t)(pt->level + 1) * ctx->n) return set_error(HCK_EINVAL, "buffer too small");
+  if (level) *level = pt->level;
+  if (scale) *scale = pt->scale;
+  return export_rows(ctx, pt->data, 1, pt->level + 1, pt->level + 1, true, 0, out);
+}
+
+int hck_decode(hck_context *ctx, const hck_plaintext *pt, double *re, double *im,
+               uint32_t n_slots) {
+  ENTER(ctx);
+  if (!pt) return set_error(HCK_EINVAL, "null plaintext");
+  if (n_slots != ctx->n / 2) return set_error(HCK_EINVAL, "n_slots must be N/2");
+  std::vector<uint64_t> res((size_t)(pt->level + 1) * ctx->n);
+  TRY(hck_plaintext_export(ctx, pt, res.data(), res.size(), nullptr, nullptr));
+  decode_residues(ctx->log_n, res.data(), ctx->mods.data(), pt->level + 1, pt->scale, re, im);
+  return HCK_OK;
+}
+
+int hck_plaintext_destroy(hck_plaintext *pt) {
+  if (pt) {
+    dev_free(pt->ctx, pt->data);
+    delete pt;
+  }
+  return HCK_OK;
+}
+
+/* ---- ciphertexts ---------------------------------------------------------- */
+
+int hck_ciphertext_create(hck_context *ctx, hck_ciphertext **out) {
+  ENTER(ctx);
+  if (!out) return set_error(HCK_EINVAL, "null output");
+  hck_ciphertext *ct = new hck_ciphertext();
+  ct->ctx = ctx;
+  *out = ct;
+  return HCK_OK;
+}
+
+int hck_ciphertext_import(hck_context *ctx, const uint64_t *res, uint32_t size, uint32_t level,
+                          double scale, hck_ciphertext **out) {
+  ENTER(ctx);
+  if (!res || !out) return set_error(HCK_EINVAL, "null argument");
+  if (size != 2 && size != 3) return set_error(HCK_EINVAL, "size must be 2 or 3");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  hck_ciphertext *ct = new hck_ciphertext();
+  ct->ctx = ctx;
+  int rc = ensure_ct(ctx, ct, size);
+  if (!rc) rc = import_rows(ctx, ct->data, res, size, ctx->L, level + 1);
+  if (rc) {
+    hck_ciphertext_destroy(ct);
+    return rc;
+  }
+  ct->size = size;
+  ct->level = level;
+  ct->scale = scale;
+  *out = ct;
+  return HCK_OK;
+}
+
+int hck_ciphertext_export(hck_context *ctx, const hck_ciphertext *ct, uint64_t *out,
+                          size_t n_words, uint32_t *size, uint32_t *level, double *scale) {
+  ENTER(ctx);
+  if (!ct || !out) return set_error(HCK_EINVAL, "null argument");
+  if (ct->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
+  if (n_words < (size_t)ct->size * (ct->level + 1) * ctx->n)
+    return set_error(HCK_EINVAL, "buffer too small");
+  if (size) *size = ct->size;
+  if (level) *level = ct->level;
+  if (scale) *scale = ct->scale;
+  return export_rows(ctx, ct->data, ct->size, ctx->L, ct->level + 1, false, 0, out);
+}
+
+int hck_ciphertext_info(const hck_ciphertext *ct, uint32_t *size, uint32_t *level,
+                        double *scale) {
+  if (!ct) return set_error(HCK_EINVAL, "null ciphertext");
+  if (size) *size = ct->size;
+  if (level) *level = ct->level;
+  if (scale) *scale = ct->scale;
+  return HCK_OK;
+}
+
+int hck_ciphertext_destroy(hck_ciphertext *ct) {
+  if (ct) {
+    if (ct->ctx) dev_free(ct->ctx, ct->data);
+    delete ct;
+  }
+  return HCK_OK;
+}
+
+int hck_encrypt_sk(hck_context *ctx, const hck_secret_key *sk, const hck_plaintext *pt,
+                   uint64_t seed, hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!sk || !pt || !out) return set_error(HCK_EINVAL, "null argument");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  TRY(ensure_ct(ctx, out, 2));
+  const size_t n = ctx->n, ps = poly_stride(ctx);
+  const uint32_t nq = pt->level + 1;
+  std::vector<uint32_t> mod_of(nq);
+  for (uint32_t t = 0; t < nq; t++) mod_of[t] = t;
+  std::vector<uint64_t> a;
+  std::vector<int32_t> e(n);
+  sample_uniform_limbs(ctx, "enc_a", seed, nq, mod_of, a);
+  sample_gaussian("enc_e", seed, e.data(), n);
+  uint64_t *c0 = out->data, *c1 = out->data + ps, *tmp = ws_tmp(ctx);
+  const LimbMap qm = qmap(ctx, pt->level);
+  TRY(upload(ctx, c1, a.data(), a.size() * 8));
+  TRY(embed_small_host(ctx, c0, e, poly_rows(1, ctx->L, nq)));
+  TRY(ntt_forward_rows(ctx, c0, poly_rows(2, ctx->L, nq)));
+  // c0 = e + m - a s
+  TRY(launch_mul_mont(ctx, tmp, c1, sk->data, qm, false));
+  TRY(launch_addsub(ctx, c0, c0, tmp, qm, 1));
+  TRY(launch_copy(ctx, tmp, pt->data, (size_t)nq * n));
+  TRY(launch_to_mont(ctx, tmp, qm, false));
+  TRY(launch_addsub(ctx, c0, c0, tmp, qm, 0));
+  out->size = 2;
+  out->level = pt->level;
+  out->scale = pt->scale;
+  return HCK_OK;
+}
+
+int hck_encrypt_pk(hck_context *ctx, const hck_public_key *pk, const hck_plaintext *pt,
+                   uint64_t seed, hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!pk || !pt || !out) return set_error(HCK_EINVAL, "null argument");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  TRY(ensure_ct(ctx, out, 2));
+  const size_t n = ctx->n, ps = poly_stride(ctx);
+  const uint32_t nq = pt->level + 1;
+  std::vector<int32_t> v(n), e0(n), e1(n);
+  sample_ternary("enc_v", seed, v.data(), n);
+  sample_gaussian("enc_e0", seed, e0.data(), n);
+  sample_gaussian("enc_e1", seed, e1.data(), n);
+  uint64_t *c0 = out->data, *c1 = out->data + ps, *tmp = ws_tmp(ctx);
+  uint64_t *vv = tmp + (size_t)ctx->L * n;
+  const LimbMap qm = qmap(ctx, pt->level);
+  TRY(embed_small_host(ctx, vv, v, poly_rows(1, ctx->L, nq)));
+  TRY(embed_small_host(ctx, c0, e0, poly_rows(1, ctx->L, nq)));
+  TRY(embed_small_host(ctx, c1, e1, poly_rows(1, ctx->L, nq)));
+  TRY(ntt_forward_rows(ctx, c0, poly_rows(2, ctx->L, nq)));
+  TRY(ntt_forward_rows(ctx, vv, poly_rows(1, ctx->L, nq)));
+  TRY(launch_mul_mont(ctx, c0, vv, pk->data, qm, true));
+  TRY(launch_mul_mont(ctx, c1, vv, pk->data + ps, qm, true));
+  TRY(launch_copy(ctx, tmp, pt->data, (size_t)nq * n));
+  TRY(launch_to_mont(ctx, tmp, qm, false));
+  TRY(launch_addsub(ctx, c0, c0, tmp, qm, 0));
+  out->size = 2;
+  out->level = pt->level;
+  out->scale = pt->scale;
+  return HCK_OK;
+}
+
+int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext *ct,
+                hck_plaintext **out) {
+  ENTER(ctx);
+  if (!sk || !ct || !out) return set_error(HCK_EINVAL, "null argument");
+  if (ct->size < 2) return set_error(HCK_EINVAL, "empty ciphertext");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  const size_t n = ctx->n, ps = poly_stride(ctx);
+  const uint32_t nq = ct->level + 1;
+  const LimbMap qm = qmap(ctx, ct->level);
+  hck_plaintext *pt = new hck_plaintext();
+  pt->ctx = ctx;
+  pt->level = ct->level;
+  pt->scale = ct->scale;
+  int rc = dev_alloc(ctx, &pt->data, (size_t)nq * n);
+  uint64_t *tmp = ws_tmp(ctx);
+  // m = c0 + REDC(c1 s~) (+ REDC(c2 REDC(s~ s~)))
+  if (!rc) rc = launch_copy(ctx, pt->data, ct->data, (size_t)nq * n);
+  if (!rc) rc = launch_mul_mont(ctx, pt->data, ct->data + ps, sk->data, qm, true);
+  if (!rc && ct->size == 3) {
+    rc = launch_mul_mont(ctx, tmp, sk->data, sk->data, qm, false);
+    if (!rc) rc = launch_mul_mont(ctx, pt->data, ct->data + 2 * ps, tmp, qm, true);
+  }
+  if (!rc) rc = launch_to_mont(ctx, pt->data, qm, true);
+  if (rc) {
+    hck_plaintext_destroy(pt);
+    return rc;
+  }
+  *out = pt;
+  return HCK_OK;
+}
+
+/* ---- evaluation ---------------------------------------------------------------- */
+
+static int addsub_ct(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+                     hck_ciphertext *out, int op) {
+  ENTER(ctx);
+  if (!a || !b || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size == 0 || a->size != b->size) return set_error(HCK_EINVAL, "sizes differ");
+  if (a->level != b->level) return set_error(HCK_ELEVEL, "levels differ");
+  if (!scales_match(a->scale, b->scale)) return set_error(HCK_ESCALE, "scales differ");
+  const uint32_t size = a->size, level = a->level;
+  const double scale = a->scale;
+  TRY(ensure_ct(ctx, out, size));
+  const size_t ps = poly_stride(ctx);
+  for (uint32_t p = 0; p < size; p++)
+    TRY(launch_addsub(ctx, out->data + p * ps, a->data + p * ps, b->data + p * ps,
+                      qmap(ctx, level), op));
+  out->size = size;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_add(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+            hck_ciphertext *out) {
+  return addsub_ct(ctx, a, b, out, 0);
+}
+
+int hck_sub(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+            hck_ciphertext *out) {
+  return addsub_ct(ctx, a, b, out, 1);
+}
+
+int hck_add_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
+                  hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !pt || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
+  if (pt->level < a->level) return set_error(HCK_ELEVEL, "plaintext level below ciphertext level");
+  if (!scales_match(a->scale, pt->scale)) return set_error(HCK_ESCALE, "scales differ");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  const uint32_t size = a->size, level = a->level;
+  const double scale = a->scale;
+  TRY(ensure_ct(ctx, out, size));
+  const size_t n = ctx->n, ps = poly_stride(ctx);
+  uint64_t *tmp = ws_tmp(ctx);
+  const LimbMap qm = qmap(ctx, level);
+  TRY(launch_copy(ctx, tmp, pt->data, (size_t)(level + 1) * n));
+  TRY(launch_to_mont(ctx, tmp, qm, false));
+  TRY(launch_addsub(ctx, out->data, a->data, tmp, qm, 0));
+  for (uint32_t p = 1; p < size; p++)
+    TRY(launch_copy(ctx, out->data + p * ps, a->data + p * ps, (size_t)(level + 1) * n));
+  out->size = size;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_mul_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
+                  hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !pt || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
+  if (pt->level < a->level) return set_error(HCK_ELEVEL, "plaintext level below ciphertext level");
+  const uint32_t size = a->size, level = a->level;
+  const double scale = a->scale * pt->scale;
+  TRY(ensure_ct(ctx, out, size));
+  const size_t ps = poly_stride(ctx);
+  for (uint32_t p = 0; p < size; p++)
+    TRY(launch_mul_mont(ctx, out->data + p * ps, a->data + p * ps, pt->data, qmap(ctx, level),
+                        false));
+  out->size = size;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_drop_level(hck_context *ctx, const hck_ciphertext *a, uint32_t level,
+                   hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
+  if (level > a->level) return set_error(HCK_ELEVEL, "cannot raise the level");
+  const uint32_t size = a->size;
+  const double scale = a->scale;
+  if (out != a) {
+    TRY(ensure_ct(ctx, out, size));
+    const size_t ps = poly_stride(ctx);
+    for (uint32_t p = 0; p < size; p++)
+      TRY(launch_copy(ctx, out->data + p * ps, a->data + p * ps, (size_t)(level + 1) * ctx->n));
+  }
+  out->size = size;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_mul(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+            hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !b || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size != 2 || b->size != 2) return set_error(HCK_EINVAL, "mul needs 2-part ciphertexts");
+  if (a->level != b->level) return set_error(HCK_ELEVEL, "levels differ");
+  const uint32_t level = a->level;
+  const double scale = a->scale * b->scale;
+  TRY(ensure_ct(ctx, out, 3));
+  TRY(launch_tensor(ctx, out->data, a->data, b->data, poly_stride(ctx), qmap(ctx, level)));
+  out->size = 3;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *rlk,
+                    hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size != 3) return set_error(HCK_EINVAL, "relinearization needs a 3-part ciphertext");
+  const uint32_t level = a->level;
+  const double scale = a->scale;
+  TRY(ensure_ct(ctx, out, 2));
+  const size_t ps = poly_stride(ctx);
+  TRY(keyswitch_core(ctx, a->data + 2 * ps, level, rlk, out->data, out->data + ps, a->data,
+                     a->data + ps));
+  out->size = 2;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
+  if (a->level == 0) return set_error(HCK_ELEVEL, "no level left to rescale");
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  const uint32_t size = a->size, level = a->level;
+  const double scale = a->scale / (double)ctx->mods[level];
+  TRY(ensure_ct(ctx, out, size));
+  const size_t n = ctx->n, ps = poly_stride(ctx);
+  uint64_t *last = ws_tmp(ctx);
+  uint64_t *lift = last + (size_t)size * n;
+  std::vector<std::pair<uint16_t, uint8_t>> lrows, trows;
+  for (uint32_t p = 0; p < size; p++) {
+    TRY(launch_copy(ctx, last + p * n, a->data + p * ps + (size_t)level * n, n));
+    lrows.push_back({(uint16_t)p, (uint8_t)level});
+    for (uint32_t i = 0; i < level; i++) trows.push_back({(uint16_t)(p * level + i), (uint8_t)i});
+  }
+  TRY(ntt_inverse(ctx, last, make_map(lrows, 0), nullptr));
+  TRY(launch_rescale_lift(ctx, lift, last, level, size));
+  TRY(ntt_forward_rows(ctx, lift, trows));
+  TRY(launch_rescale_tail(ctx, out->data, a->data, lift, level, size));
+  out->size = size;
+  out->level = level - 1;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
+               const hck_galois_keys *gks, hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !out) return set_error(HCK_EINVAL, "null argument");
+  if ((int64_t)step % (ctx->n / 2) == 0) {
+    if (a == out) return HCK_OK;
+    TRY(ensure_ct(ctx, out, a->size));
+    const size_t ps = poly_stride(ctx);
+    for (uint32_t p = 0; p < a->size; p++)
+      TRY(launch_copy(ctx, out->data + p * ps, a->data + p * ps, (size_t)(a->level + 1) * ctx->n));
+    out->size = a->size;
+    out->level = a->level;
+    out->scale = a->scale;
+    return HCK_OK;
+  }
+  if (!gks) return set_error(HCK_EINVAL, "null Galois keys");
+  return apply_galois_core(ctx, a, galois_of_step(ctx, step), gks, out);
+}
+
+int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element,
+                     const hck_galois_keys *gks, hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !gks || !out) return set_error(HCK_EINVAL, "null argument");
+  return apply_galois_core(ctx, a, element, gks, out);
+}
+
+int hck_keyswitch(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *swk,
+                  hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!a || !swk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
+  const uint32_t level = a->level;
+  const double scale = a->scale;
+  TRY(ensure_ct(ctx, out, 2));
+  const size_t ps = poly_stride(ctx);
+  TRY(keyswitch_core(ctx, a->data, level, swk, out->data, out->data + ps, nullptr, nullptr));
+  out->size = 2;
+  out->level = level;
+  out->scale = scale;
+  return HCK_OK;
+}
+
+/* ---- linear transforms ------------------------------------------------------------ */
+
+static int lt_finish_create(hck_context *ctx, const std::vector<std::vector<uint64_t>> &res,
+                            const int32_t *offsets, uint32_t n_diag, uint32_t baby_step,
+                            double pt_scale, uint32_t level, hck_linear_transform **out) {
+  hck_linear_transform *lt = new hck_linear_transform();
+  lt->ctx = ctx;
+  lt->n1 = baby_step;
+  lt->level = level;
+  lt->scale = pt_scale;
+  int rc = HCK_OK;
+  for (uint32_t d = 0; d < n_diag && !rc; d++) {
+    const int32_t k = offsets[d];
+    const int32_t g = (int32_t)std::floor((double)k / (double)baby_step);
+    const int32_t b = k - g * (int32_t)baby_step;
+    uint64_t *p = nullptr;
+    rc = dev_alloc(ctx, &p, (size_t)(level + 1) * ctx->n);
+    if (rc) break;
+    lt->owned.push_back(p);
+    rc = import_rows(ctx, p, res[d].data(), 1, level + 1, level + 1);
+    if (!rc) rc = mont_rows(ctx, p, poly_rows(1, level + 1, level + 1), true);
+    lt->groups[g].push_back({b, p});
+  }
+  if (rc) {
+    hck_lt_destroy(lt);
+    return rc;
+  }
+  *out = lt;
+  return HCK_OK;
+}
+
+static int lt_check(hck_context *ctx, const int32_t *offsets, uint32_t n_diag, uint32_t baby_step,
+                    uint32_t level) {
+  if (!offsets || n_diag == 0) return set_error(HCK_EINVAL, "no diagonals");
+  if (baby_step == 0) return set_error(HCK_EINVAL, "baby step must be positive");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  const int32_t slots = (int32_t)(ctx->n / 2);
+  for (uint32_t d = 0; d < n_diag; d++) {
+    if (offsets[d] <= -slots || offsets[d] >= slots)
+      return set_error(HCK_EINVAL, "diagonal offset out of range");
+    for (uint32_t e = 0; e < d; e++)
+      if (offsets[e] == offsets[d]) return set_error(HCK_EINVAL, "duplicate diagonal offset");
+  }
+  return HCK_OK;
+}
+
+int hck_lt_create(hck_context *ctx, const double *diag_re, const double *diag_im,
+                  const int32_t *offsets, uint32_t n_diag, uint32_t n_slots, uint32_t baby_step,
+                  double pt_scale, uint32_t level, hck_linear_transform **out) {
+  ENTER(ctx);
+  if (!diag_re || !out) return set_error(HCK_EINVAL, "null argument");
+  if (n_slots != ctx->n / 2) return set_error(HCK_EINVAL, "n_slots must be N/2");
+  TRY(lt_check(ctx, offsets, n_diag, baby_step, level));
+  if (pt_scale == 0.0) pt_scale = (double)ctx->mods[level];
+  std::vector<std::vector<uint64_t>> res(n_diag);
+  std::vector<double> re(n_slots), im(n_slots);
+  for (uint32_t d = 0; d < n_diag; d++) {
+    const int64_t k = offsets[d];
+    const int64_t g = (int64_t)std::floor((double)k / (double)baby_step);
+    const int64_t shift = g * (int64_t)baby_step;  // diagonal rotated right by g n1
+    for (uint32_t j = 0; j < n_slots; j++) {
+      const int64_t src = (((int64_t)j - shift) % n_slots + n_slots) % n_slots;
+      re[j] = diag_re[(size_t)d * n_slots + src];
+      im[j] = diag_im ? diag_im[(size_t)d * n_slots + src] : 0.0;
+    }
+    std::vector<int64_t> c;
+    TRY(encode_coeffs(ctx->log_n, re.data(), im.data(), pt_scale, c));
+    coeffs_to_residues(ctx, c, level, res[d]);
+  }
+  return lt_finish_create(ctx, res, offsets, n_diag, baby_step, pt_scale, level, out);
+}
+
+int hck_lt_create_from_residues(hck_context *ctx, const uint64_t *res, const int32_t *offsets,
+                                uint32_t n_diag, uint32_t baby_step, double pt_scale,
+                                uint32_t level, hck_linear_transform **out) {
+  ENTER(ctx);
+  if (!res || !out) return set_error(HCK_EINVAL, "null argument");
+  TRY(lt_check(ctx, offsets, n_diag, baby_step, level));
+  const size_t per = (size_t)(level + 1) * ctx->n;
+  std::vector<std::vector<uint64_t>> rows(n_diag);
+  for (uint32_t d = 0; d < n_diag; d++) rows[d].assign(res + d * per, res + (d + 1) * per);
+  return lt_finish_create(ctx, rows, offsets, n_diag, baby_step, pt_scale, level, out);
+}
+
+int hck_lt_required_steps(const hck_linear_transform *lt, int32_t *steps, uint32_t cap,
+                          uint32_t *n) {
+  if (!lt || !n) return set_error(HCK_EINVAL, "null argument");
+  std::vector<int32_t> s;
+  for (auto &kv : lt->groups) {
+    if (kv.first != 0) s.push_back(kv.first * (int32_t)lt->n1);
+    for (auto &bp : kv.second)
+      if (bp.first != 0) s.push_back(bp.first);
+  }
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  *n = (uint32_t)s.size();
+  if (steps) {
+    if (cap < s.size()) return set_error(HCK_EINVAL, "steps buffer too small");
+    std::copy(s.begin(), s.end(), steps);
+  }
+  return HCK_OK;
+}
+
+int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_ciphertext *a,
+                 const hck_galois_keys *gks, hck_ciphertext *out) {
+  ENTER(ctx);
+  if (!lt || !a || !out || !gks) return set_error(HCK_EINVAL, "null argument");
+  if (a->size != 2) return set_error(HCK_EINVAL, "needs a 2-part ciphertext");
+  if (a->level != lt->level) return set_error(HCK_ELEVEL, "level differs from the transform's");
+  // key check up front, so a missing key fails before any work
+  {
+    uint32_t cnt = 0;
+    hck_lt_required_steps(lt, nullptr, 0, &cnt);
+    std::vector<int32_t> st(cnt);
+    hck_lt_required_steps(lt, st.data(), cnt, &cnt);
+    for (int32_t s : st)
+      if ((int64_t)s % (ctx->n / 2) != 0 && !gks->keys.count(galois_of_step(ctx, s)))
+        return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
+  }
+  hck_linear_transform *m = const_cast<hck_linear_transform *>(lt);
+  LtScratch *sc = nullptr;
+  // scratch ciphertexts: baby steps 0..n1-1, the inner sum, the giant rotation
+  static_assert(sizeof(void *) == 8, "64-bit only");
+  if (m->owned.empty()) return set_error(HCK_EINVAL, "empty transform");
+  sc = new LtScratch();
+  int rc = HCK_OK;
+  sc->babies.assign(m->n1, nullptr);
+  const uint32_t level = a->level;
+  const size_t n = ctx->n, ps = poly_stride(ctx);
+  const double out_scale = a->scale * m->scale;
+  // baby steps (b = 0 is a copy of the input, so out may alias a)
+  for (auto &kv : m->groups)
+    for (auto &bp : kv.second) {
+      const int32_t b = bp.first;
+      if (rc || sc->babies[b]) continue;
+      rc = lt_alloc_ct(ctx, &sc->babies[b]);
+      if (!rc) rc = hck_rotate(ctx, a, b, gks, sc->babies[b]);
+    }
+  if (!rc) rc = lt_alloc_ct(ctx, &sc->inner);
+  if (!rc) rc = lt_alloc_ct(ctx, &sc->giant);
+  bool first = true;
+  if (!rc) rc = ensure_ct(ctx, out, 2);
+  const LimbMap qm = qmap(ctx, level);
+  for (auto &kv : m->groups) {
+    if (rc) break;
+    const int32_t g = kv.first;
+    bool first_term = true;
+    for (auto &bp : kv.second) {
+      const hck_ciphertext *x = sc->babies[bp.first];
+      for (uint32_t p = 0; p < 2 && !rc; p++)
+        rc = launch_mul_mont(ctx, sc->inner->data + p * ps, x->data + p * ps, bp.second, qm,
+                             !first_term);
+      first_term = false;
+    }
+    sc->inner->size = 2;
+    sc->inner->level = level;
+    sc->inner->scale = out_scale;
+    const hck_ciphertext *term = sc->inner;
+    if (!rc && g != 0) {
+      rc = apply_galois_core(ctx, sc->inner, galois_of_step(ctx, g * (int32_t)m->n1), gks,
+                             sc->giant);
+      term = sc->giant;
+    }
+    for (uint32_t p = 0; p < 2 && !rc; p++) {
+      if (first)
+        rc = launch_copy(ctx, out->data + p * ps, term->data + p * ps, (size_t)(level + 1) * n);
+      else
+        rc = launch_addsub(ctx, out->data + p * ps, out->data + p * ps, term->data + p * ps, qm, 0);
+    }
+    first = false;
+  }
+  if (!rc) {
+    out->size = 2;
+    out->level = level;
+    out->scale = out_scale;
+  }
+  for (auto *b : sc->babies) hck_ciphertext_destroy(b);
+  hck_ciphertext_destroy(sc->inner);
+  hck_ciphertext_destroy(sc->giant);
+  delete sc;
+  return rc;
+}
+
+int hck_lt_destroy(hck_linear_transform *lt) {
+  if (lt) {
+    for (uint64_t *p : lt->owned) dev_free(lt->ctx, p);
+    delete lt;
+  }
+  return HCK_OK;
+}
+
+}  // extern "C"

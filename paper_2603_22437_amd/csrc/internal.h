@@ -1,0 +1,253 @@
+// Internal declarations of the hipckks library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hipckks.h"
+#include "modarith.h"
+
+namespace hck {
+
+constexpr int kMaxLimbs = HCK_MAX_LIMBS;
+constexpr int kMaxRows = 192;  // rows of one batched launch (e.g. every extended digit)
+
+// Per-modulus constants, indexed by the modulus index of the full chain
+// (0..L-1: q chain, L..L+K-1: special primes).
+struct ModConst {
+  uint64_t q;
+  uint64_t qinv;        // q^-1 mod 2^64 (Montgomery)
+  uint64_t r64;         // 2^64 mod q (into Montgomery form, Shoup constant)
+  uint64_t r64_shoup;
+  uint64_t ninv;        // N^-1 mod q
+  uint64_t ninv_shoup;
+  uint64_t r2;          // 2^128 mod q (Montgomery fix-up of a plain product)
+  uint64_t pad;
+};
+
+// Which rows of a [row][N] buffer a launch processes (blockIdx.y indexes the
+// list) and the modulus index of each row.  Passed by value as a kernel
+// argument.
+struct LimbMap {
+  uint32_t n;
+  uint16_t row[kMaxRows];
+  uint8_t mod[kMaxRows];
+};
+
+// Per-row Shoup multiplier and additive constant applied at the end of an
+// inverse NTT (x -> x w + a mod q); indexed like LimbMap rows (list index).
+struct RowScale {
+  uint64_t w[kMaxLimbs];
+  uint64_t wp[kMaxLimbs];
+  uint64_t add[kMaxLimbs];
+};
+
+}  // namespace hck
+
+struct hck_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t log_n = 0, n = 0, L = 0, K = 0, dnum = 0, alpha = 0;
+  std::vector<uint64_t> mods;  // L + K primes: q chain then special primes
+
+  // device tables
+  hck::ModConst *d_mod = nullptr;    // [L+K]
+  uint64_t *d_tw = nullptr;          // [L+K][N] psi^brv(k)
+  uint64_t *d_tw_shoup = nullptr;
+  uint64_t *d_itw = nullptr;         // [L+K][N] psi^-brv(k)
+  uint64_t *d_itw_shoup = nullptr;
+  // basis conversion matrices (Montgomery form, per (level, digit) or ModDown)
+  uint64_t *d_up_conv = nullptr;     // [L][dnum][alpha][L+K]
+  uint64_t *d_down_conv = nullptr;   // [K][L+K] (columns < L used)
+  uint64_t *d_down_hneg = nullptr;   // [L]: -(P-1)/2 mod q_i
+
+  // host copies of per-row scale factors
+  // up_scale[level][i]: N^-1 (Q'_j / q_i)^-1 mod q_i, digit j of limb i at that level
+  std::vector<std::vector<uint64_t>> up_scale;
+  std::vector<uint64_t> down_scale;   // [K]: N^-1 (P/p_k)^-1 mod p_k
+  std::vector<uint64_t> down_add;     // [K]: ((P-1)/2 mod p_k) (P/p_k)^-1 mod p_k
+  std::vector<uint64_t> down_hneg;    // [L]: -(P-1)/2 mod q_i
+  std::vector<uint64_t> pinv;         // [L]: P^-1 mod q_i
+  std::vector<std::vector<uint64_t>> rescale_inv;  // [l][i<l]: q_l^-1 mod q_i
+
+  // key-switch workspace (device)
+  uint64_t *ws = nullptr;
+  size_t ws_words = 0;
+
+  bool broken = false;
+
+  // kernel timing
+  bool timing = false;
+  struct Timed {
+    std::string name;
+    hipEvent_t start, stop;
+    double bytes, mulmods;
+  };
+  struct TimingTotal {
+    double ms = 0, bytes = 0, mulmods = 0;
+    uint64_t launches = 0;
+  };
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::string, TimingTotal> timing_total;
+};
+
+struct hck_ciphertext {
+  hck_context *ctx = nullptr;
+  uint64_t *data = nullptr;  // [cap_polys][L][N], evaluation (NTT) domain, plain form
+  uint32_t cap_polys = 0;
+  uint32_t size = 0;  // polynomials in use (0: empty)
+  uint32_t level = 0;
+  double scale = 1.0;
+};
+
+struct hck_plaintext {
+  hck_context *ctx = nullptr;
+  uint64_t *data = nullptr;  // [level+1][N], evaluation domain, Montgomery form
+  uint32_t level = 0;
+  double scale = 1.0;
+};
+
+struct hck_secret_key {
+  hck_context *ctx = nullptr;
+  std::vector<int8_t> coeffs;  // N ternary coefficients
+  uint64_t *data = nullptr;    // [L+K][N] evaluation domain, Montgomery form
+};
+
+struct hck_public_key {
+  hck_context *ctx = nullptr;
+  uint64_t *data = nullptr;  // [2][L][N] evaluation domain, Montgomery form
+};
+
+struct hck_switch_key {
+  hck_context *ctx = nullptr;
+  uint64_t *data = nullptr;  // [dnum][2][L+K][N] evaluation domain, Montgomery form
+};
+
+struct hck_galois_keys {
+  hck_context *ctx = nullptr;
+  std::map<uint32_t, hck_switch_key *> keys;
+};
+
+struct hck_linear_transform {
+  hck_context *ctx = nullptr;
+  uint32_t n1 = 1, level = 0;
+  double scale = 1.0;
+  // giant index g -> list of (baby step b, diagonal plaintext [level+1][N])
+  std::map<int32_t, std::vector<std::pair<int32_t, uint64_t *>>> groups;
+  std::vector<uint64_t *> owned;
+};
+
+namespace hck {
+
+// ---- error handling (errors.cpp) ----
+int set_error(int code, const std::string &msg);
+int check_hip(hck_context *ctx, hipError_t e, const char *what);
+#define HCK_HIP(ctx, expr)                                          \
+  do {                                                              \
+    hipError_t _e = (expr);                                         \
+    if (_e != hipSuccess) return ::hck::check_hip((ctx), _e, #expr); \
+  } while (0)
+
+// ---- device memory ----
+int dev_alloc(hck_context *ctx, uint64_t **p, size_t words);
+void dev_free(hck_context *ctx, void *p);
+int ensure_ct(hck_context *ctx, hck_ciphertext *ct, uint32_t polys);
+int ensure_workspace(hck_context *ctx, size_t words);
+
+// ---- kernel timing ----
+// `bytes` and `mulmods`: the launch's algorithmic HBM traffic and 64-bit
+// modular multiplications (the method's own counts, not the implementation's)
+void timing_begin(hck_context *ctx, const char *name, double bytes = 0, double mulmods = 0);
+void timing_end(hck_context *ctx);
+int timing_collect(hck_context *ctx);
+
+// ---- launchers (kernels.hip / ntt.hip); all asynchronous on ctx->stream ----
+// forward NTT, in place, rows of `buf` listed in map; input fully reduced,
+// output fully reduced
+int ntt_forward(hck_context *ctx, uint64_t *buf, const LimbMap &map);
+// inverse NTT, in place; output x * scale.w + scale.add (fully reduced); when
+// scale is null, multiplies by N^-1 only
+int ntt_inverse(hck_context *ctx, uint64_t *buf, const LimbMap &map, const RowScale *scale);
+
+int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t words);
+// out[r] = a[r] (+|-) b[r] for rows in map; op 0 add, 1 sub, 2 negate a
+int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
+                  const LimbMap &map, int op);
+// out = REDC(a * bm) (bm in Montgomery form); accumulate adds to out
+int launch_mul_mont(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *bm,
+                    const LimbMap &map, bool accumulate);
+// x -> x 2^64 mod q (into Montgomery form) or x 2^-64 (out of it), in place
+int launch_to_mont(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool to);
+// tensor of (a0, a1) and (b0, b1) into out0..out2; poly stride given in words
+int launch_tensor(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
+                  size_t poly_stride, const LimbMap &map);
+// NTT-domain Galois automorphism of `polys` polynomials (poly stride given)
+int launch_automorphism(hck_context *ctx, uint64_t *out, const uint64_t *in, size_t poly_stride,
+                        uint32_t polys, const LimbMap &map, uint32_t galois);
+// small signed integers -> residues for rows in map
+int launch_embed_small(hck_context *ctx, uint64_t *out, const int32_t *small, const LimbMap &map);
+// fast basis conversion: out[map_out rows] = REDC(sum_a in[src rows] conv[a][mod])
+//   + addc[list index]; conv rows indexed by source list position, columns by
+//   modulus index (stride conv_stride)
+int launch_bconv(hck_context *ctx, uint64_t *out, const LimbMap &map_out, const uint64_t *in,
+                 const LimbMap &map_in, const uint64_t *conv, uint32_t conv_stride,
+                 const uint64_t *addc);
+// key-switch inner product over the extended basis at level l
+int launch_ks_inner(hck_context *ctx, uint64_t *acc, const uint64_t *ext, const uint64_t *d,
+                    const uint64_t *key, uint32_t level);
+// ModDown tail: out_i = (u_i - conv_i) P^-1 (+ addend_i), i <= level
+int launch_moddown_tail(hck_context *ctx, uint64_t *out, const uint64_t *u, const uint64_t *conv,
+                        const uint64_t *addend, uint32_t level);
+// rescale: lift the coefficient-domain last limbs last[p] (p < polys) into
+// out[p][0..level-1]
+int launch_rescale_lift(hck_context *ctx, uint64_t *out, const uint64_t *last, uint32_t level,
+                        uint32_t polys);
+// rescale tail: out_p,i = (c_p,i - t[p][i]) q_l^-1 mod q_i (poly stride L N)
+int launch_rescale_tail(hck_context *ctx, uint64_t *out, const uint64_t *c, const uint64_t *t,
+                        uint32_t level, uint32_t polys);
+// out[r] += REDC(in[r] c_r) for rows in map, c_r = sc.w[list index]
+int launch_scalar_mac(hck_context *ctx, uint64_t *out, const uint64_t *in, const LimbMap &map,
+                      const RowScale &sc);
+
+// ---- host helpers ----
+LimbMap qmap(const hck_context *ctx, uint32_t level);     // rows 0..level of the q chain
+LimbMap fullmap(const hck_context *ctx);                  // rows 0..L+K-1
+uint32_t galois_of_step(const hck_context *ctx, int32_t step);
+
+// ---- sampler (sampler.cpp) ----
+void shake256(const uint8_t *msg, size_t len, uint8_t *out, size_t outlen);
+std::vector<uint8_t> shake_stream(const std::string &tag, uint64_t seed, uint32_t index,
+                                  size_t nbytes);
+void sample_uniform(const std::string &tag, uint64_t seed, uint32_t index, uint64_t q, uint64_t *out,
+                    size_t n);
+void sample_ternary(const std::string &tag, uint64_t seed, int32_t *out, size_t n);
+void sample_gaussian(const std::string &tag, uint64_t seed, int32_t *out, size_t n);
+
+// ---- encoder (encoder.cpp) ----
+// integer coefficients (as int64, |c| < 2^62) of the encoding of z
+int encode_coeffs(uint32_t log_n, const double *re, const double *im, double scale,
+                  std::vector<int64_t> &coeffs);
+// slots from centred CRT of residues [nl][N] (host, coefficient domain)
+void decode_residues(uint32_t log_n, const uint64_t *res, const uint64_t *mods, uint32_t nl,
+                     double scale, double *re, double *im);
+
+// ---- evaluation internals (eval.cpp) ----
+// workspace regions (words from ctx->ws)
+size_t ws_words_needed(const hck_context *ctx);
+uint64_t *ws_ks(hck_context *ctx);    // key-switch internals
+uint64_t *ws_rot(hck_context *ctx);   // [2][L][N]: automorphism output
+uint64_t *ws_tmp(hck_context *ctx);   // [3][L+K][N]: general temporary
+// (out0, out1) = KeySwitch(d) (+ add0, add1), d: [level+1][N] evaluation form
+int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t level, const hck_switch_key *key,
+                   uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1);
+int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
+                      const hck_galois_keys *gks, hck_ciphertext *out);
+// runs ntt_forward / ntt_inverse over maps longer than one launch allows
+int ntt_forward_rows(hck_context *ctx, uint64_t *buf, const std::vector<std::pair<uint16_t, uint8_t>> &rows);
+
+}  // namespace hck

@@ -1,0 +1,409 @@
+// Element-wise, automorphism, basis-conversion and key-switch kernels.
+//
+// Layout: a polynomial is [limb][N] 64-bit words, limb-major, each limb
+// contiguous; kernels index limbs through a LimbMap (row in the buffer,
+// modulus index) so that one launch covers every limb of an operation.
+#include "internal.h"
+
+namespace hck {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxSrc = 16;     // sources of one basis conversion (alpha or K)
+constexpr int kTargetsPerBlock = 4;
+
+__global__ __launch_bounds__(kThreads) void k_copy(uint64_t *__restrict__ dst,
+                                                   const uint64_t *__restrict__ src,
+                                                   size_t words) {
+  size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * kThreads;
+  for (; i < words; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_addsub(uint64_t *out, const uint64_t *a,
+                                                     const uint64_t *b, LimbMap map,
+                                                     const ModConst *__restrict__ mc, int n,
+                                                     int op) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t off = (size_t)map.row[blockIdx.y] * n + i;
+  const uint64_t q = mc[map.mod[blockIdx.y]].q;
+  uint64_t x = a[off];
+  uint64_t r;
+  if (op == 0)
+    r = add_mod(x, b[off], q);
+  else if (op == 1)
+    r = sub_mod(x, b[off], q);
+  else
+    r = x == 0 ? 0 : q - x;
+  out[off] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mul_mont(uint64_t *out, const uint64_t *a,
+                                                       const uint64_t *bm, LimbMap map,
+                                                       const ModConst *__restrict__ mc, int n,
+                                                       int accumulate) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t off = (size_t)map.row[blockIdx.y] * n + i;
+  const ModConst m = mc[map.mod[blockIdx.y]];
+  uint64_t r = redc(mul_wide(a[off], bm[off]), m.q, m.qinv);
+  if (accumulate) r = add_mod(r, out[off], m.q);
+  out[off] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_to_mont(uint64_t *buf, LimbMap map,
+                                                      const ModConst *__restrict__ mc, int n,
+                                                      int to) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t off = (size_t)map.row[blockIdx.y] * n + i;
+  const ModConst m = mc[map.mod[blockIdx.y]];
+  const uint64_t x = buf[off];
+  if (to) {
+    buf[off] = shoup(x, m.r64, m.r64_shoup, m.q);
+  } else {
+    u128 t;
+    t.lo = x;
+    t.hi = 0;
+    buf[off] = redc(t, m.q, m.qinv);
+  }
+}
+
+// (a0, a1) x (b0, b1) -> (a0 b0, a0 b1 + a1 b0, a1 b1); plain operands, so
+// each REDC result (x 2^-64) is brought back by a REDC with 2^128 mod q.
+__global__ __launch_bounds__(kThreads) void k_tensor(uint64_t *out, const uint64_t *a,
+                                                     const uint64_t *b, size_t ps, LimbMap map,
+                                                     const ModConst *__restrict__ mc, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t off = (size_t)map.row[blockIdx.y] * n + i;
+  const ModConst m = mc[map.mod[blockIdx.y]];
+  const uint64_t a0 = a[off], a1 = a[off + ps], b0 = b[off], b1 = b[off + ps];
+  uint64_t d0 = redc(mul_wide(a0, b0), m.q, m.qinv);
+  u128 x = mul_wide(a0, b1);
+  mac_wide(x, a1, b0);
+  uint64_t d1 = redc(x, m.q, m.qinv);
+  uint64_t d2 = redc(mul_wide(a1, b1), m.q, m.qinv);
+  out[off] = redc(mul_wide(d0, m.r2), m.q, m.qinv);
+  out[off + ps] = redc(mul_wide(d1, m.r2), m.q, m.qinv);
+  out[off + 2 * ps] = redc(mul_wide(d2, m.r2), m.q, m.qinv);
+}
+
+// Galois automorphism in the bit-reversed evaluation domain: slot j holds the
+// value at psi^(2 brv(j) + 1), and phi_g(a)(x) = a(x^g), so slot j of the
+// output is slot brv(((2 brv(j) + 1) g mod 2N - 1) / 2) of the input.
+__global__ __launch_bounds__(kThreads) void k_automorphism(uint64_t *__restrict__ out,
+                                                           const uint64_t *__restrict__ in,
+                                                           size_t ps, LimbMap map, int log_n,
+                                                           uint32_t g) {
+  const uint32_t n = 1u << log_n;
+  const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t shift = 32 - log_n;
+  const uint32_t e = 2 * (__brev(j) >> shift) + 1;
+  const uint32_t src_e = (uint32_t)(((uint64_t)e * g) & (2 * n - 1));
+  const uint32_t src = __brev((src_e - 1) >> 1) >> shift;
+  const size_t row = (size_t)map.row[blockIdx.y] * n + blockIdx.z * ps;
+  out[row + j] = in[row + src];
+}
+
+__global__ __launch_bounds__(kThreads) void k_embed_small(uint64_t *out, const int32_t *small,
+                                                          LimbMap map,
+                                                          const ModConst *__restrict__ mc,
+                                                          int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const uint64_t q = mc[map.mod[blockIdx.y]].q;
+  const int32_t v = small[i];
+  out[(size_t)map.row[blockIdx.y] * n + i] = v < 0 ? q - (uint64_t)(-(int64_t)v) : (uint64_t)v;
+}
+
+// Fast basis conversion, one coefficient per thread, kTargetsPerBlock
+// targets per block: out_t = REDC(sum_a y_a conv[a][mod_t]) (+ addc_t), where
+// conv holds (B / b_a mod t) 2^64 mod t, so the REDC yields the plain sum.
+// The caller keeps sum_a b_a < 2^64 so the 128-bit sum stays below t 2^64.
+__global__ __launch_bounds__(kThreads) void k_bconv(uint64_t *__restrict__ out, LimbMap mout,
+                                                    const uint64_t *__restrict__ in, LimbMap min,
+                                                    const uint64_t *__restrict__ conv,
+                                                    uint32_t conv_stride,
+                                                    const uint64_t *__restrict__ addc,
+                                                    const ModConst *__restrict__ mc, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  uint64_t y[kMaxSrc];
+  const int ns = min.n;
+#pragma unroll
+  for (int a = 0; a < kMaxSrc; a++)
+    if (a < ns) y[a] = in[(size_t)min.row[a] * n + i];
+  const int t0 = blockIdx.y * kTargetsPerBlock;
+  for (int t = t0; t < t0 + kTargetsPerBlock && t < (int)mout.n; t++) {
+    const int mi = mout.mod[t];
+    const ModConst m = mc[mi];
+    u128 acc;
+    acc.lo = 0;
+    acc.hi = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxSrc; a++)
+      if (a < ns) mac_wide(acc, y[a], conv[a * conv_stride + mi]);
+    uint64_t v = redc(acc, m.q, m.qinv);
+    if (addc) v = add_mod(v, addc[t], m.q);
+    out[(size_t)mout.row[t] * n + i] = v;
+  }
+}
+
+// Key-switch inner product at level l over the extended basis Q_l u P
+// (position t < l+1: q_t; else p_(t-l-1)).  For each digit j with limbs
+// D_j = [j alpha, min((j+1) alpha, l+1)): the extended digit is the input d on
+// its own limbs and ext[j][t] elsewhere.  acc0/acc1[t] = sum_j ext_j[t] key_j.
+struct KsInnerArgs {
+  uint32_t level, L, K, dnum, alpha;
+};
+
+__global__ __launch_bounds__(kThreads) void k_ks_inner(uint64_t *__restrict__ acc,
+                                                       const uint64_t *__restrict__ ext,
+                                                       const uint64_t *__restrict__ d,
+                                                       const uint64_t *__restrict__ key,
+                                                       KsInnerArgs ka,
+                                                       const ModConst *__restrict__ mc, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t t = blockIdx.y;
+  const uint32_t nq = ka.level + 1;
+  const uint32_t ne = nq + ka.K;
+  const uint32_t mi = t < nq ? t : ka.L + (t - nq);
+  const ModConst m = mc[mi];
+  const size_t krow = (size_t)(ka.L + ka.K) * n;  // words per key polynomial
+  u128 s0, s1;
+  s0.lo = s0.hi = s1.lo = s1.hi = 0;
+  for (uint32_t j = 0; j < ka.dnum; j++) {
+    const uint32_t lo = j * ka.alpha;
+    if (lo >= nq) break;
+    const uint32_t hi = min(lo + ka.alpha, nq);
+    const uint64_t x = (t >= lo && t < hi) ? d[(size_t)t * n + i]
+                                           : ext[((size_t)j * ne + t) * n + i];
+    const uint64_t *kb = key + (size_t)(2 * j) * krow + (size_t)mi * n;
+    const uint64_t *kk = key + (size_t)(2 * j + 1) * krow + (size_t)mi * n;
+    mac_wide(s0, x, kb[i]);
+    mac_wide(s1, x, kk[i]);
+  }
+  acc[(size_t)t * n + i] = redc(s0, m.q, m.qinv);
+  acc[((size_t)ne + t) * n + i] = redc(s1, m.q, m.qinv);
+}
+
+// out_i = (u_i - conv_i) P^-1 mod q_i (+ addend_i); Shoup constants per row.
+__global__ __launch_bounds__(kThreads) void k_moddown_tail(uint64_t *out, const uint64_t *u,
+                                                           const uint64_t *conv,
+                                                           const uint64_t *addend, RowScale sc,
+                                                           const ModConst *__restrict__ mc,
+                                                           int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int r = blockIdx.y;
+  const uint64_t q = mc[r].q;
+  const size_t off = (size_t)r * n + i;
+  uint64_t v = shoup(sub_mod(u[off], conv[off], q), sc.w[r], sc.wp[r], q);
+  if (addend) v = add_mod(v, addend[off], q);
+  out[off] = v;
+}
+
+// Centred lift of the dropped limb (coefficient domain, values in [0, q_l))
+// into row i < l: v if v <= (q_l - 1) / 2, else v - q_l, reduced mod q_i.
+// blockIdx.z selects the polynomial: last + z n, out + z l n.
+__global__ __launch_bounds__(kThreads) void k_rescale_lift(uint64_t *out, const uint64_t *last,
+                                                           uint32_t level,
+                                                           const ModConst *__restrict__ mc,
+                                                           int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t r = blockIdx.y;
+  const uint64_t ql = mc[level].q;
+  const uint64_t qi = mc[r].q;
+  const uint64_t one_p = (uint64_t)(((unsigned __int128)1 << 64) / qi);  // Shoup of 1
+  const uint64_t v = last[(size_t)blockIdx.z * n + i];
+  uint64_t t = shoup(v, 1, one_p, qi);
+  if (v > (ql - 1) / 2) t = sub_mod(t, shoup(ql, 1, one_p, qi), qi);
+  out[((size_t)blockIdx.z * level + r) * n + i] = t;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rescale_tail(uint64_t *out, const uint64_t *c,
+                                                           const uint64_t *t, RowScale sc,
+                                                           size_t ps, uint32_t level,
+                                                           const ModConst *__restrict__ mc,
+                                                           int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const uint32_t r = blockIdx.y;
+  const uint64_t q = mc[r].q;
+  const size_t off = (size_t)r * n + i + blockIdx.z * ps;
+  const uint64_t tv = t[((size_t)blockIdx.z * level + r) * n + i];
+  out[off] = shoup(sub_mod(c[off], tv, q), sc.w[r], sc.wp[r], q);
+}
+
+// out[r] += REDC(in[r] c_r): adds a per-row constant multiple of a
+// Montgomery-form operand.
+__global__ __launch_bounds__(kThreads) void k_scalar_mac(uint64_t *out, const uint64_t *in,
+                                                         LimbMap map, RowScale sc,
+                                                         const ModConst *__restrict__ mc, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t off = (size_t)map.row[blockIdx.y] * n + i;
+  const ModConst m = mc[map.mod[blockIdx.y]];
+  out[off] = add_mod(out[off], redc(mul_wide(in[off], sc.w[blockIdx.y]), m.q, m.qinv), m.q);
+}
+
+dim3 grid_rows(const hck_context *ctx, uint32_t rows, uint32_t z = 1) {
+  return dim3(ctx->n / kThreads, rows, z);
+}
+
+}  // namespace
+
+int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t words) {
+  if (words == 0 || dst == src) return HCK_OK;
+  timing_begin(ctx, "copy", 16.0 * words);
+  unsigned blocks = (unsigned)std::min<size_t>((words + kThreads - 1) / kThreads, 8192);
+  k_copy<<<blocks, kThreads, 0, ctx->stream>>>(dst, src, words);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
+                  const LimbMap &map, int op) {
+  if (map.n == 0) return HCK_OK;
+  timing_begin(ctx, "addsub", 24.0 * ctx->n * map.n);
+  k_addsub<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, b, map, ctx->d_mod,
+                                                                 ctx->n, op);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_mul_mont(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *bm,
+                    const LimbMap &map, bool accumulate) {
+  if (map.n == 0) return HCK_OK;
+  timing_begin(ctx, "mul_plain", (accumulate ? 32.0 : 24.0) * ctx->n * map.n,
+               (double)ctx->n * map.n);
+  k_mul_mont<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, bm, map, ctx->d_mod,
+                                                                   ctx->n, accumulate ? 1 : 0);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_to_mont(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool to) {
+  if (map.n == 0) return HCK_OK;
+  timing_begin(ctx, "mont", 16.0 * ctx->n * map.n, (double)ctx->n * map.n);
+  k_to_mont<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(buf, map, ctx->d_mod, ctx->n,
+                                                                  to ? 1 : 0);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_tensor(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
+                  size_t poly_stride, const LimbMap &map) {
+  timing_begin(ctx, "tensor", 56.0 * ctx->n * map.n, 4.0 * ctx->n * map.n);
+  k_tensor<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, b, poly_stride, map,
+                                                                 ctx->d_mod, ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_automorphism(hck_context *ctx, uint64_t *out, const uint64_t *in, size_t poly_stride,
+                        uint32_t polys, const LimbMap &map, uint32_t galois) {
+  timing_begin(ctx, "automorphism", 16.0 * ctx->n * map.n * polys);
+  k_automorphism<<<grid_rows(ctx, map.n, polys), kThreads, 0, ctx->stream>>>(
+      out, in, poly_stride, map, (int)ctx->log_n, galois);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_embed_small(hck_context *ctx, uint64_t *out, const int32_t *small, const LimbMap &map) {
+  timing_begin(ctx, "embed", (8.0 * map.n + 4.0) * ctx->n);
+  k_embed_small<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, small, map, ctx->d_mod,
+                                                                      ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_bconv(hck_context *ctx, uint64_t *out, const LimbMap &map_out, const uint64_t *in,
+                 const LimbMap &map_in, const uint64_t *conv, uint32_t conv_stride,
+                 const uint64_t *addc) {
+  if (map_out.n == 0) return HCK_OK;
+  if (map_in.n > (uint32_t)kMaxSrc) return set_error(HCK_EPARAMS, "too many conversion sources");
+  timing_begin(ctx, "bconv", 8.0 * ctx->n * (map_in.n + map_out.n),
+               (double)ctx->n * map_in.n * map_out.n);
+  dim3 grid(ctx->n / kThreads, (map_out.n + kTargetsPerBlock - 1) / kTargetsPerBlock);
+  k_bconv<<<grid, kThreads, 0, ctx->stream>>>(out, map_out, in, map_in, conv, conv_stride, addc,
+                                              ctx->d_mod, ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_ks_inner(hck_context *ctx, uint64_t *acc, const uint64_t *ext, const uint64_t *d,
+                    const uint64_t *key, uint32_t level) {
+  KsInnerArgs ka{level, ctx->L, ctx->K, ctx->dnum, ctx->alpha};
+  const double ne = level + 1 + ctx->K;
+  const double digits = (level + ctx->alpha) / ctx->alpha < ctx->dnum
+                            ? (level + ctx->alpha) / ctx->alpha : ctx->dnum;
+  timing_begin(ctx, "ks_inner", 8.0 * ctx->n * ne * (3 * digits + 2),
+               2.0 * digits * ctx->n * ne);
+  k_ks_inner<<<grid_rows(ctx, level + 1 + ctx->K), kThreads, 0, ctx->stream>>>(
+      acc, ext, d, key, ka, ctx->d_mod, ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_moddown_tail(hck_context *ctx, uint64_t *out, const uint64_t *u, const uint64_t *conv,
+                        const uint64_t *addend, uint32_t level) {
+  RowScale sc;
+  for (uint32_t i = 0; i <= level; i++) {
+    sc.w[i] = ctx->pinv[i];
+    sc.wp[i] = h_shoup(ctx->pinv[i], ctx->mods[i]);
+    sc.add[i] = 0;
+  }
+  timing_begin(ctx, "moddown_tail", (addend ? 32.0 : 24.0) * ctx->n * (level + 1),
+               (double)ctx->n * (level + 1));
+  k_moddown_tail<<<grid_rows(ctx, level + 1), kThreads, 0, ctx->stream>>>(out, u, conv, addend,
+                                                                          sc, ctx->d_mod, ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_rescale_lift(hck_context *ctx, uint64_t *out, const uint64_t *last, uint32_t level,
+                        uint32_t polys) {
+  timing_begin(ctx, "rescale_lift", 8.0 * ctx->n * polys * (1 + level));
+  k_rescale_lift<<<grid_rows(ctx, level, polys), kThreads, 0, ctx->stream>>>(out, last, level,
+                                                                             ctx->d_mod, ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_rescale_tail(hck_context *ctx, uint64_t *out, const uint64_t *c, const uint64_t *t,
+                        uint32_t level, uint32_t polys) {
+  RowScale sc;
+  for (uint32_t i = 0; i < level; i++) {
+    sc.w[i] = ctx->rescale_inv[level][i];
+    sc.wp[i] = h_shoup(sc.w[i], ctx->mods[i]);
+    sc.add[i] = 0;
+  }
+  const size_t ps = (size_t)ctx->L * ctx->n;
+  timing_begin(ctx, "rescale_tail", 24.0 * ctx->n * level * polys,
+               (double)ctx->n * level * polys);
+  k_rescale_tail<<<grid_rows(ctx, level, polys), kThreads, 0, ctx->stream>>>(
+      out, c, t, sc, ps, level, ctx->d_mod, ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_scalar_mac(hck_context *ctx, uint64_t *out, const uint64_t *in, const LimbMap &map,
+                      const RowScale &sc) {
+  if (map.n == 0) return HCK_OK;
+  if (map.n > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "too many rows");
+  timing_begin(ctx, "scalar_mac", 24.0 * ctx->n * map.n, (double)ctx->n * map.n);
+  k_scalar_mac<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, in, map, sc, ctx->d_mod,
+                                                                     ctx->n);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+}  // namespace hck

@@ -151,3 +151,46 @@ def small_ints(n: int, seed: int, bound: int) -> np.ndarray:
     """int64 array of n values uniform in [-bound, bound]."""
     rng = np.random.default_rng(seed)
     return rng.integers(-bound, bound + 1, n, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Synthetic radar windows (stand-ins for the paper's datasets, Table 2)
+# ---------------------------------------------------------------------------
+
+def vital_window(seed: int, frames: int = 200, bins: int = 64, fps: float = 20.0,
+                 snr_db: float = 20.0) -> np.ndarray:
+    """A vital-sign window: complex range profiles [frames][bins].
+
+    One target range bin (uniform in [8, 56)) carries the chest displacement
+    d(t) = A_r sin(2 pi f_r t + p_r) + A_h sin(2 pi f_h t + p_h), with
+    respiration f_r ~ U[0.1, 0.5] Hz, A_r ~ U[2, 10] mm and heartbeat
+    f_h ~ U[0.8, 2.0] Hz, A_h ~ U[0.1, 0.5] mm, as the phase
+    exp(j 4 pi d / lambda) at 60 GHz (lambda ~ 5 mm; the FMCW phase model of
+    the paper's Appendix A); every bin gets complex Gaussian noise at the
+    given SNR.  The clutter-removed (mean-subtracted, section 3.3.2) and
+    normalized (max |z| = 1) window is returned.
+    """
+    rng = np.random.default_rng(seed)
+    lam = 3e8 / 60e9
+    t = np.arange(frames) / fps
+    fr, ar = rng.uniform(0.1, 0.5), rng.uniform(2e-3, 10e-3)
+    fh, ah = rng.uniform(0.8, 2.0), rng.uniform(0.1e-3, 0.5e-3)
+    pr, ph = rng.uniform(0, 2 * np.pi, 2)
+    d = ar * np.sin(2 * np.pi * fr * t + pr) + ah * np.sin(2 * np.pi * fh * t + ph)
+    z = np.zeros((frames, bins), dtype=np.complex128)
+    target = rng.integers(8, 56)
+    z[:, target] = np.exp(1j * 4 * np.pi * d / lam)
+    sigma = 10 ** (-snr_db / 20) / np.sqrt(2)
+    z += sigma * (rng.standard_normal(z.shape) + 1j * rng.standard_normal(z.shape))
+    z -= z.mean(axis=0, keepdims=True)
+    return z / np.abs(z).max()
+
+
+def windowed_dft_matrix(d: int) -> np.ndarray:
+    """W[k, n] = w[n] exp(-j 2 pi sigma(k) n / D) / sum(w) with the Hann
+    window w and the fftshift permutation sigma(k) = (k + D/2) mod D (the
+    paper's Eq. dft_kernel), normalized so that |W x| <= max|x|."""
+    n = np.arange(d)
+    w = np.hanning(d)
+    sig = (n + d // 2) % d
+    return w[None, :] * np.exp(-2j * np.pi * np.outer(sig, n) / d) / w.sum()

@@ -1,0 +1,287 @@
+"""GPU <-> oracle parity through the C ABI (MI355X).
+
+Every test feeds the same seeded inputs to the HIP library and to the CPU
+oracle and requires bit-identical residues (coefficient domain, fully
+reduced).  Inputs are either uniform residue arrays from ``seeded_inputs`` or
+objects both sides derive from the same seeds (keys, encryptions).  Ring
+sizes: N = 2^12 (L = 3, K = 1), N = 2^15 (L = 12, K = 4) and the benchmark's
+N = 2^16, L = 24, K = 8, dnum = 3; levels from the top down to 0 exercise
+ragged last digits.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import seeded_inputs as S
+
+pytestmark = pytest.mark.gpu
+
+H = pytest.importorskip("paper_2603_22437_amd")
+
+
+class Pair:
+    """A GPU context and an oracle over one parameter set, with one secret."""
+
+    def __init__(self, name):
+        self.prm = S.params(name)
+        self.ctx = H.Context.from_params(self.prm)
+        self.o = O.Oracle(self.prm)
+        self.s_o = self.o.keygen_secret(1)
+        self.sk = self.ctx.keygen_secret(1)
+        self.gk_cache = {}
+
+    def galois(self, steps):
+        """GPU Galois keys and the oracle's, for the rotation steps."""
+        els = sorted({self.o.galois_element(k) for k in steps if k % self.o.n_slots})
+        missing = [g for g in els if g not in self.gk_cache]
+        for g in missing:
+            self.gk_cache[g] = self.o.keygen_galois(self.s_o, g, 5)
+        gks = self.ctx.keygen_galois(self.sk, els, 5)
+        return gks, {g: self.gk_cache[g] for g in els}
+
+    def rand_ct(self, level, seed, size=2):
+        res = S.uniform_residues(self.o.qmods(level), self.o.n, seed, count=size)
+        ct_o = O.Ciphertext(res, level, 2.0 ** 40)
+        ct_g = self.ctx.ciphertext_import(res, level, 2.0 ** 40)
+        return ct_g, ct_o
+
+    def export(self, ct):
+        return self.ctx.ciphertext_export(ct)[0]
+
+
+_pairs = {}
+
+
+def pair(name):
+    if name not in _pairs:
+        _pairs[name] = Pair(name)
+    return _pairs[name]
+
+
+CONFIGS = ["tiny", "mix15", "vital"]
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_import_export_roundtrip(name):
+    p = pair(name)
+    ct, ct_o = p.rand_ct(p.o.L - 1, 100)
+    assert np.array_equal(p.export(ct), ct_o.polys)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_poly_product_via_mul_plain(name):
+    """NTT -> pointwise -> INTT on the GPU equals the oracle's negacyclic product."""
+    p = pair(name)
+    level = p.o.L - 1
+    ct, ct_o = p.rand_ct(level, 101)
+    ptres = S.uniform_residues(p.o.qmods(level), p.o.n, 102)[0]
+    pt = p.ctx.plaintext_import(ptres, level, 3.0)
+    got = p.export(p.ctx.mul_plain(ct, pt))
+    want = p.o.mul_plain(ct_o, O.Plaintext(ptres, level, 3.0)).polys
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_keys_match_oracle(name):
+    p = pair(name)
+    o = p.o
+    pk = p.ctx.public_key_export(p.ctx.keygen_public(p.sk, 2))
+    assert np.array_equal(pk, o.keygen_public(p.s_o, 2))
+    g = o.galois_element(3)
+    gks, gko = p.galois([3])
+    assert np.array_equal(p.ctx.galois_keys_export(gks, g), gko[g])
+    rlk = p.ctx.switch_key_export(p.ctx.keygen_relin(p.sk, 7))
+    assert np.array_equal(rlk, o.keygen_relin(p.s_o, 7))
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_encrypt_matches_oracle(name):
+    p = pair(name)
+    o = p.o
+    level = o.L - 1
+    res = S.uniform_residues(o.qmods(level), o.n, 103)[0]
+    pt = p.ctx.plaintext_import(res, level, 2.0 ** 30)
+    got = p.export(p.ctx.encrypt_sk(p.sk, pt, 10))
+    want = o.encrypt_sk(p.s_o, O.Plaintext(res, level, 2.0 ** 30), 10).polys
+    assert np.array_equal(got, want)
+    pk = p.ctx.keygen_public(p.sk, 2)
+    got = p.export(p.ctx.encrypt_pk(pk, pt, 11))
+    want = o.encrypt_pk(o.keygen_public(p.s_o, 2), O.Plaintext(res, level, 2.0 ** 30), 11).polys
+    assert np.array_equal(got, want)
+    # decryption: c0 + c1 s
+    ct, ct_o = p.rand_ct(level, 104)
+    dec, lvl, _ = p.ctx.plaintext_export(p.ctx.decrypt(p.sk, ct))
+    assert np.array_equal(dec, o.decrypt(p.s_o, ct_o).res)
+
+
+def _levels(o):
+    return sorted({o.L - 1, (o.L - 1) // 2, o.alpha, 0})
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_keyswitch_matches_oracle(name):
+    """Raw hybrid key switching of polynomial 0 with the relinearization key."""
+    p = pair(name)
+    o = p.o
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    rlk_o = o.keygen_relin(p.s_o, 7)
+    for level in _levels(o):
+        ct, ct_o = p.rand_ct(level, 200 + level)
+        got = p.export(p.ctx.keyswitch(ct, rlk))
+        u0, u1 = o.keyswitch(ct_o.polys[0], level, rlk_o)
+        assert np.array_equal(got[0], u0), f"level {level} u0"
+        assert np.array_equal(got[1], u1), f"level {level} u1"
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_rotation_matches_oracle(name):
+    p = pair(name)
+    o = p.o
+    steps = [1, -1, 5, o.n_slots // 2 + 3]
+    gks, gko = p.galois(steps)
+    for level in _levels(o):
+        ct, ct_o = p.rand_ct(level, 300 + level)
+        for k in (steps if level == o.L - 1 else steps[:1]):
+            got = p.export(p.ctx.rotate(ct, k, gks))
+            want = o.rotate(ct_o, k, gko).polys
+            assert np.array_equal(got, want), f"level {level} step {k}"
+
+
+@pytest.mark.parametrize("name", ["tiny", "mix15"])
+def test_conjugation_matches_oracle(name):
+    p = pair(name)
+    o = p.o
+    g = 2 * o.n - 1
+    gks = p.ctx.keygen_galois(p.sk, [g], 6)
+    ct, ct_o = p.rand_ct(o.L - 1, 400)
+    got = p.export(p.ctx.apply_galois(ct, g, gks))
+    want = o.apply_galois(ct_o, g, o.keygen_galois(p.s_o, g, 6)).polys
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_tensor_relin_rescale_match_oracle(name):
+    p = pair(name)
+    o = p.o
+    level = o.L - 1
+    a, a_o = p.rand_ct(level, 500)
+    b, b_o = p.rand_ct(level, 501)
+    t = p.ctx.mul(a, b)
+    t_o = o.tensor(a_o, b_o)
+    assert np.array_equal(p.export(t), t_o.polys)
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    r = p.ctx.relinearize(t, rlk)
+    r_o = o.relinearize(t_o, o.keygen_relin(p.s_o, 7))
+    assert np.array_equal(p.export(r), r_o.polys)
+    for lv in [level, 1]:
+        c, c_o = p.rand_ct(lv, 510 + lv)
+        rs = p.ctx.rescale(c)
+        rs_o = o.rescale(c_o)
+        assert rs.level == lv - 1
+        assert np.array_equal(p.export(rs), rs_o.polys), f"rescale at level {lv}"
+    # a 3-part rescale
+    t3 = p.ctx.rescale(t)
+    assert np.array_equal(p.export(t3), o.rescale(t_o).polys)
+
+
+@pytest.mark.parametrize("name", ["tiny", "vital"])
+def test_elementwise_match_oracle(name):
+    p = pair(name)
+    o = p.o
+    level = o.L - 2
+    a, a_o = p.rand_ct(level, 600)
+    b, b_o = p.rand_ct(level, 601)
+    assert np.array_equal(p.export(p.ctx.add(a, b)), o.add(a_o, b_o).polys)
+    assert np.array_equal(p.export(p.ctx.sub(a, b)), o.sub(a_o, b_o).polys)
+    ptres = S.uniform_residues(o.qmods(level), o.n, 602)[0]
+    pt = p.ctx.plaintext_import(ptres, level, 2.0 ** 40)
+    assert np.array_equal(p.export(p.ctx.add_plain(a, pt)),
+                          o.add_plain(a_o, O.Plaintext(ptres, level, 2.0 ** 40)).polys)
+    d = p.ctx.drop_level(a, 1)
+    assert np.array_equal(p.export(d), o.drop_level(a_o, 1).polys)
+    # in-place (out aliases an input)
+    c, c_o = p.rand_ct(level, 603)
+    p.ctx.add(c, b, out=c)
+    assert np.array_equal(p.export(c), o.add(c_o, b_o).polys)
+
+
+@pytest.mark.parametrize("name,n_diag,n1", [("tiny", 127, 16), ("mix15", 9, 4)])
+def test_linear_transform_matches_oracle(name, n_diag, n1):
+    """BSGS over integer diagonal plaintexts imported identically on both sides."""
+    p = pair(name)
+    o = p.o
+    level = o.L - 1
+    half = n_diag // 2
+    offsets = list(range(-half, n_diag - half))
+    res = {k: S.uniform_residues(o.qmods(level), o.n, 700 + i)[0]
+           for i, k in enumerate(offsets)}
+    lt = p.ctx.lt_create_from_residues(res, n1, level, float(o.q[level]))
+    lt_o = o.lt_from_plaintexts({k: O.Plaintext(r, level, float(o.q[level]))
+                                 for k, r in res.items()}, n1, level, float(o.q[level]))
+    steps = p.ctx.lt_required_steps(lt)
+    assert steps == o.lt_required_steps(lt_o)
+    gks, gko = p.galois(steps)
+    ct, ct_o = p.rand_ct(level, 710)
+    got = p.export(p.ctx.lt_apply(lt, ct, gks))
+    want = o.lt_apply(lt_o, ct_o, gko).polys
+    assert np.array_equal(got, want)
+
+
+def test_error_paths():
+    p = pair("tiny")
+    o = p.o
+    ct, _ = p.rand_ct(o.L - 1, 800)
+    gks, _ = p.galois([1])
+    with pytest.raises(H.HckError) as e:
+        p.ctx.rotate(ct, 2, gks)
+    assert e.value.code == H.HCK_ENOKEY
+    low, _ = p.rand_ct(0, 801)
+    with pytest.raises(H.HckError) as e:
+        p.ctx.rescale(low)
+    assert e.value.code == H.HCK_ELEVEL
+    with pytest.raises(H.HckError) as e:
+        p.ctx.add(ct, low)
+    assert e.value.code == H.HCK_ELEVEL
+    other = p.ctx.ciphertext_import(S.uniform_residues(o.qmods(o.L - 1), o.n, 802, 2),
+                                    o.L - 1, 2.0 ** 41)
+    with pytest.raises(H.HckError) as e:
+        p.ctx.add(ct, other)
+    assert e.value.code == H.HCK_ESCALE
+    bad = S.uniform_residues(o.qmods(0), o.n, 803, 2)
+    bad[0, 0, 0] = o.q[0]
+    with pytest.raises(H.HckError) as e:
+        p.ctx.ciphertext_import(bad, 0, 1.0)
+    assert e.value.code == H.HCK_EINVAL
+    prm = dict(p.prm)
+    with pytest.raises(H.HckError) as e:
+        H.Context(12, [prm["q"][0] + 2] + prm["q"][1:], prm["p"], 3)
+    assert e.value.code == H.HCK_EPARAMS
+    with pytest.raises(H.HckError) as e:
+        H.Context(12, prm["q"], prm["p"], 5)   # dnum > L
+    assert e.value.code == H.HCK_EPARAMS
+    # rotation by a multiple of N/2 slots is a copy and needs no key
+    z = p.ctx.rotate(ct, o.n_slots, gks)
+    assert np.array_equal(p.export(z), p.export(ct))
+
+
+def test_tiny_config_decoded_end_to_end():
+    """The tiny workload with the GPU's own encoder: encrypt 2048 slots,
+    (I_32 (x) M64) x by BSGS, rescale, square + relinearize; decoded result
+    within 1e-3 of plaintext math (and of the oracle's decoded result)."""
+    from test_oracle_scheme import block_diag_diagonals
+    p = pair("tiny")
+    o, ctx = p.o, p.ctx
+    x = S.uniform_slots(o.n_slots, 0)
+    m = S.uniform_matrix(64, 64, 0, 0.125)
+    diags = block_diag_diagonals(m, 32)
+    lt = ctx.lt_create(diags, 16, 2)
+    steps = ctx.lt_required_steps(lt)
+    gks = ctx.keygen_rotation(p.sk, steps, 5)
+    rlk = ctx.keygen_relin(p.sk, 7)
+    ct = ctx.encrypt_sk(p.sk, ctx.encode(x, 2.0 ** 25, 2), 10)
+    y = ctx.rescale(ctx.lt_apply(lt, ct, gks))
+    sq = ctx.relinearize(ctx.mul(y, y), rlk)
+    lin = np.kron(np.eye(32), m) @ x
+    assert np.max(np.abs(ctx.decode(ctx.decrypt(p.sk, y)).real - lin)) < 1e-3
+    got = ctx.decode(ctx.decrypt(p.sk, sq)).real
+    assert np.max(np.abs(got - lin ** 2)) < 1e-3
