@@ -64,7 +64,7 @@ typedef struct hck_ciphertext hck_ciphertext;
 typedef struct hck_linear_transform hck_linear_transform;
 
 /* Parameter set of the ring Z_Q[X]/(X^N + 1) in RNS form (section 3.2: CKKS
- * over RLWE; Table 8: ring degree and depth).  log_n in [4, 17]; q holds the
+ * over RLWE; Table 8: ring degree and depth).  log_n in [11, 17]; q holds the
  * L = num_q primes of the ciphertext modulus chain (q[0] first), p the
  * K = num_p special primes of hybrid key switching; dnum the number of digits
  * of the decomposition.  Every prime must be = 1 (mod 2N), below 2^61 and

@@ -795,7 +795,7 @@ int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_
   const double scale = a->scale;
   TRY(ensure_ct(ctx, out, 2));
   const size_t ps = poly_stride(ctx);
-  TRY(keyswitch_core(ctx, a->data + 2 * ps, level, rlk, out->data, out->data + ps, a->data,
+  TRY(keyswitch_core(ctx, a->data + 2 * ps, 1, level, rlk, out->data, out->data + ps, a->data,
                      a->data + ps));
   out->size = 2;
   out->level = level;
@@ -866,7 +866,8 @@ int hck_keyswitch(hck_context *ctx, const hck_ciphertext *a, const hck_switch_ke
   const double scale = a->scale;
   TRY(ensure_ct(ctx, out, 2));
   const size_t ps = poly_stride(ctx);
-  TRY(keyswitch_core(ctx, a->data, level, swk, out->data, out->data + ps, nullptr, nullptr));
+  if (out == a) return set_error(HCK_EINVAL, "keyswitch output must not alias its input");
+  TRY(keyswitch_core(ctx, a->data, 1, level, swk, out->data, out->data + ps, nullptr, nullptr));
   out->size = 2;
   out->level = level;
   out->scale = scale;

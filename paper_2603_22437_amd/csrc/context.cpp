@@ -182,7 +182,7 @@ int timing_collect(hck_context *ctx) {
 
 static int validate(const hck_params *p) {
   if (!p || !p->q || (p->num_p && !p->p)) return set_error(HCK_EINVAL, "null parameters");
-  if (p->log_n < 10 || p->log_n > 17) return set_error(HCK_EPARAMS, "log_n must be in [10, 17]");
+  if (p->log_n < 11 || p->log_n > 17) return set_error(HCK_EPARAMS, "log_n must be in [11, 17]");
   if (p->num_q < 1 || p->num_p < 1) return set_error(HCK_EPARAMS, "need at least one q and one p");
   if (p->num_q + p->num_p > (uint32_t)kMaxLimbs)
     return set_error(HCK_EPARAMS, "L + K exceeds HCK_MAX_LIMBS");

@@ -173,6 +173,13 @@ int ntt_forward(hck_context *ctx, uint64_t *buf, const LimbMap &map);
 // inverse NTT, in place; output x * scale.w + scale.add (fully reduced); when
 // scale is null, multiplies by N^-1 only
 int ntt_inverse(hck_context *ctx, uint64_t *buf, const LimbMap &map, const RowScale *scale);
+// out-of-place variants: the first pass reads src, both passes write dst
+int ntt_forward_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map);
+int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                    const RowScale *scale);
+// one pass (strided or contiguous, forward or inverse) in place
+int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
+             const RowScale *scale);
 
 int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t words);
 // out[r] = a[r] (+|-) b[r] for rows in map; op 0 add, 1 sub, 2 negate a
@@ -191,18 +198,6 @@ int launch_automorphism(hck_context *ctx, uint64_t *out, const uint64_t *in, siz
                         uint32_t polys, const LimbMap &map, uint32_t galois);
 // small signed integers -> residues for rows in map
 int launch_embed_small(hck_context *ctx, uint64_t *out, const int32_t *small, const LimbMap &map);
-// fast basis conversion: out[map_out rows] = REDC(sum_a in[src rows] conv[a][mod])
-//   + addc[list index]; conv rows indexed by source list position, columns by
-//   modulus index (stride conv_stride)
-int launch_bconv(hck_context *ctx, uint64_t *out, const LimbMap &map_out, const uint64_t *in,
-                 const LimbMap &map_in, const uint64_t *conv, uint32_t conv_stride,
-                 const uint64_t *addc);
-// key-switch inner product over the extended basis at level l
-int launch_ks_inner(hck_context *ctx, uint64_t *acc, const uint64_t *ext, const uint64_t *d,
-                    const uint64_t *key, uint32_t level);
-// ModDown tail: out_i = (u_i - conv_i) P^-1 (+ addend_i), i <= level
-int launch_moddown_tail(hck_context *ctx, uint64_t *out, const uint64_t *u, const uint64_t *conv,
-                        const uint64_t *addend, uint32_t level);
 // rescale: lift the coefficient-domain last limbs last[p] (p < polys) into
 // out[p][0..level-1]
 int launch_rescale_lift(hck_context *ctx, uint64_t *out, const uint64_t *last, uint32_t level,
@@ -242,9 +237,12 @@ size_t ws_words_needed(const hck_context *ctx);
 uint64_t *ws_ks(hck_context *ctx);    // key-switch internals
 uint64_t *ws_rot(hck_context *ctx);   // [2][L][N]: automorphism output
 uint64_t *ws_tmp(hck_context *ctx);   // [3][L+K][N]: general temporary
-// (out0, out1) = KeySwitch(d) (+ add0, add1), d: [level+1][N] evaluation form
-int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t level, const hck_switch_key *key,
-                   uint64_t *out0, uint64_t *out1, const uint64_t *add0, const uint64_t *add1);
+// (out0, out1) = KeySwitch(phi_g(d)) + (phi_g(add0), phi_g(add1)); d and the
+// addends [level+1][N] in evaluation form; g = 1 for no automorphism.  out
+// rows must not overlap d; with g != 1 they must not overlap the addends.
+int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_t level,
+                   const hck_switch_key *key, uint64_t *out0, uint64_t *out1, const uint64_t *add0,
+                   const uint64_t *add1);
 int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *out);
 // runs ntt_forward / ntt_inverse over maps longer than one launch allows

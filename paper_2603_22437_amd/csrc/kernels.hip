@@ -10,8 +10,6 @@ namespace hck {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kMaxSrc = 16;     // sources of one basis conversion (alpha or K)
-constexpr int kTargetsPerBlock = 4;
 
 __global__ __launch_bounds__(kThreads) void k_copy(uint64_t *__restrict__ dst,
                                                    const uint64_t *__restrict__ src,
@@ -112,91 +110,6 @@ __global__ __launch_bounds__(kThreads) void k_embed_small(uint64_t *out, const i
   const uint64_t q = mc[map.mod[blockIdx.y]].q;
   const int32_t v = small[i];
   out[(size_t)map.row[blockIdx.y] * n + i] = v < 0 ? q - (uint64_t)(-(int64_t)v) : (uint64_t)v;
-}
-
-// Fast basis conversion, one coefficient per thread, kTargetsPerBlock
-// targets per block: out_t = REDC(sum_a y_a conv[a][mod_t]) (+ addc_t), where
-// conv holds (B / b_a mod t) 2^64 mod t, so the REDC yields the plain sum.
-// The caller keeps sum_a b_a < 2^64 so the 128-bit sum stays below t 2^64.
-__global__ __launch_bounds__(kThreads) void k_bconv(uint64_t *__restrict__ out, LimbMap mout,
-                                                    const uint64_t *__restrict__ in, LimbMap min,
-                                                    const uint64_t *__restrict__ conv,
-                                                    uint32_t conv_stride,
-                                                    const uint64_t *__restrict__ addc,
-                                                    const ModConst *__restrict__ mc, int n) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  uint64_t y[kMaxSrc];
-  const int ns = min.n;
-#pragma unroll
-  for (int a = 0; a < kMaxSrc; a++)
-    if (a < ns) y[a] = in[(size_t)min.row[a] * n + i];
-  const int t0 = blockIdx.y * kTargetsPerBlock;
-  for (int t = t0; t < t0 + kTargetsPerBlock && t < (int)mout.n; t++) {
-    const int mi = mout.mod[t];
-    const ModConst m = mc[mi];
-    u128 acc;
-    acc.lo = 0;
-    acc.hi = 0;
-#pragma unroll
-    for (int a = 0; a < kMaxSrc; a++)
-      if (a < ns) mac_wide(acc, y[a], conv[a * conv_stride + mi]);
-    uint64_t v = redc(acc, m.q, m.qinv);
-    if (addc) v = add_mod(v, addc[t], m.q);
-    out[(size_t)mout.row[t] * n + i] = v;
-  }
-}
-
-// Key-switch inner product at level l over the extended basis Q_l u P
-// (position t < l+1: q_t; else p_(t-l-1)).  For each digit j with limbs
-// D_j = [j alpha, min((j+1) alpha, l+1)): the extended digit is the input d on
-// its own limbs and ext[j][t] elsewhere.  acc0/acc1[t] = sum_j ext_j[t] key_j.
-struct KsInnerArgs {
-  uint32_t level, L, K, dnum, alpha;
-};
-
-__global__ __launch_bounds__(kThreads) void k_ks_inner(uint64_t *__restrict__ acc,
-                                                       const uint64_t *__restrict__ ext,
-                                                       const uint64_t *__restrict__ d,
-                                                       const uint64_t *__restrict__ key,
-                                                       KsInnerArgs ka,
-                                                       const ModConst *__restrict__ mc, int n) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  const uint32_t t = blockIdx.y;
-  const uint32_t nq = ka.level + 1;
-  const uint32_t ne = nq + ka.K;
-  const uint32_t mi = t < nq ? t : ka.L + (t - nq);
-  const ModConst m = mc[mi];
-  const size_t krow = (size_t)(ka.L + ka.K) * n;  // words per key polynomial
-  u128 s0, s1;
-  s0.lo = s0.hi = s1.lo = s1.hi = 0;
-  for (uint32_t j = 0; j < ka.dnum; j++) {
-    const uint32_t lo = j * ka.alpha;
-    if (lo >= nq) break;
-    const uint32_t hi = min(lo + ka.alpha, nq);
-    const uint64_t x = (t >= lo && t < hi) ? d[(size_t)t * n + i]
-                                           : ext[((size_t)j * ne + t) * n + i];
-    const uint64_t *kb = key + (size_t)(2 * j) * krow + (size_t)mi * n;
-    const uint64_t *kk = key + (size_t)(2 * j + 1) * krow + (size_t)mi * n;
-    mac_wide(s0, x, kb[i]);
-    mac_wide(s1, x, kk[i]);
-  }
-  acc[(size_t)t * n + i] = redc(s0, m.q, m.qinv);
-  acc[((size_t)ne + t) * n + i] = redc(s1, m.q, m.qinv);
-}
-
-// out_i = (u_i - conv_i) P^-1 mod q_i (+ addend_i); Shoup constants per row.
-__global__ __launch_bounds__(kThreads) void k_moddown_tail(uint64_t *out, const uint64_t *u,
-                                                           const uint64_t *conv,
-                                                           const uint64_t *addend, RowScale sc,
-                                                           const ModConst *__restrict__ mc,
-                                                           int n) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  const int r = blockIdx.y;
-  const uint64_t q = mc[r].q;
-  const size_t off = (size_t)r * n + i;
-  uint64_t v = shoup(sub_mod(u[off], conv[off], q), sc.w[r], sc.wp[r], q);
-  if (addend) v = add_mod(v, addend[off], q);
-  out[off] = v;
 }
 
 // Centred lift of the dropped limb (coefficient domain, values in [0, q_l))
@@ -314,53 +227,6 @@ int launch_embed_small(hck_context *ctx, uint64_t *out, const int32_t *small, co
   timing_begin(ctx, "embed", (8.0 * map.n + 4.0) * ctx->n);
   k_embed_small<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, small, map, ctx->d_mod,
                                                                       ctx->n);
-  timing_end(ctx);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
-}
-
-int launch_bconv(hck_context *ctx, uint64_t *out, const LimbMap &map_out, const uint64_t *in,
-                 const LimbMap &map_in, const uint64_t *conv, uint32_t conv_stride,
-                 const uint64_t *addc) {
-  if (map_out.n == 0) return HCK_OK;
-  if (map_in.n > (uint32_t)kMaxSrc) return set_error(HCK_EPARAMS, "too many conversion sources");
-  timing_begin(ctx, "bconv", 8.0 * ctx->n * (map_in.n + map_out.n),
-               (double)ctx->n * map_in.n * map_out.n);
-  dim3 grid(ctx->n / kThreads, (map_out.n + kTargetsPerBlock - 1) / kTargetsPerBlock);
-  k_bconv<<<grid, kThreads, 0, ctx->stream>>>(out, map_out, in, map_in, conv, conv_stride, addc,
-                                              ctx->d_mod, ctx->n);
-  timing_end(ctx);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
-}
-
-int launch_ks_inner(hck_context *ctx, uint64_t *acc, const uint64_t *ext, const uint64_t *d,
-                    const uint64_t *key, uint32_t level) {
-  KsInnerArgs ka{level, ctx->L, ctx->K, ctx->dnum, ctx->alpha};
-  const double ne = level + 1 + ctx->K;
-  const double digits = (level + ctx->alpha) / ctx->alpha < ctx->dnum
-                            ? (level + ctx->alpha) / ctx->alpha : ctx->dnum;
-  timing_begin(ctx, "ks_inner", 8.0 * ctx->n * ne * (3 * digits + 2),
-               2.0 * digits * ctx->n * ne);
-  k_ks_inner<<<grid_rows(ctx, level + 1 + ctx->K), kThreads, 0, ctx->stream>>>(
-      acc, ext, d, key, ka, ctx->d_mod, ctx->n);
-  timing_end(ctx);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
-}
-
-int launch_moddown_tail(hck_context *ctx, uint64_t *out, const uint64_t *u, const uint64_t *conv,
-                        const uint64_t *addend, uint32_t level) {
-  RowScale sc;
-  for (uint32_t i = 0; i <= level; i++) {
-    sc.w[i] = ctx->pinv[i];
-    sc.wp[i] = h_shoup(ctx->pinv[i], ctx->mods[i]);
-    sc.add[i] = 0;
-  }
-  timing_begin(ctx, "moddown_tail", (addend ? 32.0 : 24.0) * ctx->n * (level + 1),
-               (double)ctx->n * (level + 1));
-  k_moddown_tail<<<grid_rows(ctx, level + 1), kThreads, 0, ctx->stream>>>(out, u, conv, addend,
-                                                                          sc, ctx->d_mod, ctx->n);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;

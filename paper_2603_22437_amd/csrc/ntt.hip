@@ -1,238 +1,123 @@
-// Negacyclic NTT / inverse NTT over many limbs in one launch (gfx950).
-//
-// Forward transform: the merged Cooley-Tukey network whose stage m (m = 1, 2,
-// ..., N/2; half-width t = N / 2m) combines x[j], x[j+t] with the twiddle
-// psi^brv(m + j / 2t), psi a primitive 2N-th root of unity and brv the logN-bit
-// reversal.  Slot j of the output holds the polynomial's value at
-// psi^(2 brv(j) + 1) (bit-reversed evaluation order).  The inverse runs the
-// Gentleman-Sande network with psi^-brv in the reverse stage order and scales
-// by N^-1, optionally times a per-limb constant and plus a per-limb addend.
-//
-// A limb of N 64-bit words (512 KiB at N = 2^16) exceeds one CU's LDS, so
-// each transform is two passes over HBM, N = R1 x R2:
-//   * strided pass: stages m < R1 touch only elements R2 apart, so R1-point
-//     columns are independent; a workgroup loads a tile of C adjacent
-//     columns (C words contiguous per row), runs log2(R1) stages in LDS, and
-//     writes the tile back;
-//   * contiguous pass: stages m >= R1 stay inside blocks of R2 contiguous
-//     words; a workgroup runs log2(R2) stages on ROWS such blocks.
-// Butterflies are Harvey's lazy ones (values in [0, 4q) forward, [0, 2q)
-// inverse, q < 2^61) with Shoup twiddle products.
-#include "internal.h"
+// Negacyclic NTT / inverse NTT over many limbs in one launch: the two
+// passes of ntt_core.h, each a kernel over every listed limb.
+#include "ntt_core.h"
 
 namespace hck {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kTile = 4096;  // words per workgroup tile (32 KiB of LDS)
-
-__device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp,
-                                        uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  uint64_t a = x >= q2 ? x - q2 : x;       // [0, 2q)
-  uint64_t t = shoup_lazy(y, w, wp, q);    // [0, 2q)
-  x = a + t;                               // [0, 4q)
-  y = a - t + q2;                          // (0, 4q)
-}
-
-__device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp,
-                                        uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  uint64_t s = x + y;
-  s = s >= q2 ? s - q2 : s;                // [0, 2q)
-  y = shoup_lazy(x - y + q2, w, wp, q);    // [0, 2q)
-  x = s;
-}
-
-template <int LOG_R1, int LOG_R2>
-__global__ __launch_bounds__(kThreads) void k_fwd_strided(uint64_t *__restrict__ buf, LimbMap map,
+// One pass over the rows of `map`.  Reads from src (or dst when src is null)
+// and writes dst.  Forward strided: [0, 4q) in and out; forward contiguous:
+// [0, 4q) in, [0, q) out; inverse contiguous: [0, 2q) in and out; inverse
+// strided: [0, 2q) in, out = x N^-1 (or x sc.w + sc.add when use_scale) fully
+// reduced.
+template <int LOGR, int LOGN, bool STRIDED, bool INVERSE>
+__global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__ dst,
+                                                          const uint64_t *__restrict__ src,
+                                                          LimbMap map,
                                                           const ModConst *__restrict__ mc,
                                                           const uint64_t *__restrict__ tw,
-                                                          const uint64_t *__restrict__ tws) {
-  constexpr int R1 = 1 << LOG_R1, R2 = 1 << LOG_R2, N = R1 * R2;
-  constexpr int C = (kTile / R1) < R2 ? (kTile / R1) : R2;
-  constexpr int E = R1 * C;
-  __shared__ uint64_t lds[E];
-  const int mi = map.mod[blockIdx.y];
-  const uint64_t q = mc[mi].q;
-  uint64_t *p = buf + (size_t)map.row[blockIdx.y] * N + blockIdx.x * C;
-  const uint64_t *w_ = tw + (size_t)mi * N;
-  const uint64_t *wp_ = tws + (size_t)mi * N;
-  for (int e = threadIdx.x; e < E; e += kThreads) lds[e] = p[(e / C) * R2 + (e % C)];
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < LOG_R1; s++) {
-    const int t = R1 >> (s + 1);
-    for (int b = threadIdx.x; b < (R1 / 2) * C; b += kThreads) {
-      const int c = b % C, k = b / C;
-      const int grp = k / t;
-      const int j = grp * 2 * t + (k % t);
-      const int widx = (1 << s) + grp;
-      uint64_t x = lds[j * C + c], y = lds[(j + t) * C + c];
-      ct_bfly(x, y, w_[widx], wp_[widx], q);
-      lds[j * C + c] = x;
-      lds[(j + t) * C + c] = y;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < E; e += kThreads) p[(e / C) * R2 + (e % C)] = lds[e];
-}
-
-template <int LOG_R1, int LOG_R2>
-__global__ __launch_bounds__(kThreads) void k_fwd_contig(uint64_t *__restrict__ buf, LimbMap map,
-                                                         const ModConst *__restrict__ mc,
-                                                         const uint64_t *__restrict__ tw,
-                                                         const uint64_t *__restrict__ tws) {
-  constexpr int R1 = 1 << LOG_R1, R2 = 1 << LOG_R2, N = R1 * R2;
-  constexpr int ROWS = (kTile / R2) < R1 ? (kTile / R2) : R1;
-  constexpr int E = ROWS * R2;
-  __shared__ uint64_t lds[E];
-  const int mi = map.mod[blockIdx.y];
-  const uint64_t q = mc[mi].q;
-  const int r0 = blockIdx.x * ROWS;
-  uint64_t *p = buf + (size_t)map.row[blockIdx.y] * N + (size_t)r0 * R2;
-  const uint64_t *w_ = tw + (size_t)mi * N;
-  const uint64_t *wp_ = tws + (size_t)mi * N;
-  for (int e = threadIdx.x; e < E; e += kThreads) lds[e] = p[e];
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < LOG_R2; s++) {
-    const int t = R2 >> (s + 1);
-    for (int b = threadIdx.x; b < (R2 / 2) * ROWS; b += kThreads) {
-      const int k = b % (R2 / 2), rr = b / (R2 / 2);
-      const int grp = k / t;
-      const int j = rr * R2 + grp * 2 * t + (k % t);
-      const int widx = (1 << s) * (R1 + r0 + rr) + grp;
-      uint64_t x = lds[j], y = lds[j + t];
-      ct_bfly(x, y, w_[widx], wp_[widx], q);
-      lds[j] = x;
-      lds[j + t] = y;
-    }
-    __syncthreads();
-  }
-  const uint64_t q2 = 2 * q;
-  for (int e = threadIdx.x; e < E; e += kThreads) {
-    uint64_t v = lds[e];
-    v = v >= q2 ? v - q2 : v;
-    p[e] = v >= q ? v - q : v;
-  }
-}
-
-template <int LOG_R1, int LOG_R2>
-__global__ __launch_bounds__(kThreads) void k_inv_contig(uint64_t *__restrict__ buf, LimbMap map,
-                                                         const ModConst *__restrict__ mc,
-                                                         const uint64_t *__restrict__ itw,
-                                                         const uint64_t *__restrict__ itws) {
-  constexpr int R1 = 1 << LOG_R1, R2 = 1 << LOG_R2, N = R1 * R2;
-  constexpr int ROWS = (kTile / R2) < R1 ? (kTile / R2) : R1;
-  constexpr int E = ROWS * R2;
-  __shared__ uint64_t lds[E];
-  const int mi = map.mod[blockIdx.y];
-  const uint64_t q = mc[mi].q;
-  const int r0 = blockIdx.x * ROWS;
-  uint64_t *p = buf + (size_t)map.row[blockIdx.y] * N + (size_t)r0 * R2;
-  const uint64_t *w_ = itw + (size_t)mi * N;
-  const uint64_t *wp_ = itws + (size_t)mi * N;
-  for (int e = threadIdx.x; e < E; e += kThreads) lds[e] = p[e];
-  __syncthreads();
-#pragma unroll
-  for (int s = LOG_R2 - 1; s >= 0; s--) {
-    const int t = R2 >> (s + 1);
-    for (int b = threadIdx.x; b < (R2 / 2) * ROWS; b += kThreads) {
-      const int k = b % (R2 / 2), rr = b / (R2 / 2);
-      const int grp = k / t;
-      const int j = rr * R2 + grp * 2 * t + (k % t);
-      const int widx = (1 << s) * (R1 + r0 + rr) + grp;
-      uint64_t x = lds[j], y = lds[j + t];
-      gs_bfly(x, y, w_[widx], wp_[widx], q);
-      lds[j] = x;
-      lds[j + t] = y;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < E; e += kThreads) p[e] = lds[e];  // [0, 2q)
-}
-
-template <int LOG_R1, int LOG_R2>
-__global__ __launch_bounds__(kThreads) void k_inv_strided(uint64_t *__restrict__ buf, LimbMap map,
-                                                          const ModConst *__restrict__ mc,
-                                                          const uint64_t *__restrict__ itw,
-                                                          const uint64_t *__restrict__ itws,
+                                                          const uint64_t *__restrict__ tws,
                                                           RowScale sc, int use_scale) {
-  constexpr int R1 = 1 << LOG_R1, R2 = 1 << LOG_R2, N = R1 * R2;
-  constexpr int C = (kTile / R1) < R2 ? (kTile / R1) : R2;
-  constexpr int E = R1 * C;
-  __shared__ uint64_t lds[E];
+  using G = Pass<LOGR, LOGN, STRIDED>;
+  constexpr int P = G::P;
+  __shared__ uint64_t lds[G::LDS_WORDS];
   const int mi = map.mod[blockIdx.y];
   const uint64_t q = mc[mi].q;
-  uint64_t *p = buf + (size_t)map.row[blockIdx.y] * N + blockIdx.x * C;
-  const uint64_t *w_ = itw + (size_t)mi * N;
-  const uint64_t *wp_ = itws + (size_t)mi * N;
-  for (int e = threadIdx.x; e < E; e += kThreads) lds[e] = p[(e / C) * R2 + (e % C)];
-  __syncthreads();
+  const size_t roff = (size_t)map.row[blockIdx.y] * G::N;
+  uint64_t *out = dst + roff;
+  const uint64_t *in = (src ? src : dst) + roff;
+  const uint64_t *w = tw + (size_t)mi * G::N;
+  const uint64_t *wp = tws + (size_t)mi * G::N;
+  const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
+  const int g = blockIdx.x * G::TR + c;
+  uint64_t x[P];
+  if (!INVERSE) {
 #pragma unroll
-  for (int s = LOG_R1 - 1; s >= 0; s--) {
-    const int t = R1 >> (s + 1);
-    for (int b = threadIdx.x; b < (R1 / 2) * C; b += kThreads) {
-      const int c = b % C, k = b / C;
-      const int grp = k / t;
-      const int j = grp * 2 * t + (k % t);
-      const int widx = (1 << s) + grp;
-      uint64_t x = lds[j * C + c], y = lds[(j + t) * C + c];
-      gs_bfly(x, y, w_[widx], wp_[widx], q);
-      lds[j * C + c] = x;
-      lds[(j + t) * C + c] = y;
+    for (int i = 0; i < P; i++) x[i] = in[G::gaddr(g, G::ipoint(r, i))];
+    G::forward(lds, x, c, r, g, w, wp, q);
+    if (STRIDED) {
+#pragma unroll
+      for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    } else {
+#pragma unroll
+      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
+      G::to_interleaved(lds, x, c, r);
+#pragma unroll
+      for (int i = 0; i < P; i++) out[G::gaddr(g, G::ipoint(r, i))] = x[i];
     }
-    __syncthreads();
-  }
-  uint64_t sw, swp, sa;
-  if (use_scale) {
-    sw = sc.w[blockIdx.y];
-    swp = sc.wp[blockIdx.y];
-    sa = sc.add[blockIdx.y];
   } else {
-    sw = mc[mi].ninv;
-    swp = mc[mi].ninv_shoup;
-    sa = 0;
-  }
-  for (int e = threadIdx.x; e < E; e += kThreads) {
-    uint64_t v = shoup(lds[e], sw, swp, q);
-    p[(e / C) * R2 + (e % C)] = add_mod(v, sa, q);
+    if (STRIDED) {
+#pragma unroll
+      for (int v = 0; v < P; v++) x[v] = in[G::gaddr(g, G::bpoint(r, v))];
+    } else {
+#pragma unroll
+      for (int i = 0; i < P; i++) x[i] = in[G::gaddr(g, G::ipoint(r, i))];
+      G::to_blocked(lds, x, c, r);
+    }
+    G::inverse(lds, x, c, r, g, w, wp, q);
+    if (STRIDED) {
+      uint64_t sw, swp, sa;
+      if (use_scale) {
+        sw = sc.w[blockIdx.y];
+        swp = sc.wp[blockIdx.y];
+        sa = sc.add[blockIdx.y];
+      } else {
+        sw = mc[mi].ninv;
+        swp = mc[mi].ninv_shoup;
+        sa = 0;
+      }
+#pragma unroll
+      for (int i = 0; i < P; i++)
+        out[G::gaddr(g, G::ipoint(r, i))] = add_mod(shoup(x[i], sw, swp, q), sa, q);
+    } else {
+#pragma unroll
+      for (int i = 0; i < P; i++) out[G::gaddr(g, G::ipoint(r, i))] = x[i];
+    }
   }
 }
 
-template <int A, int B>
-int run_forward(hck_context *ctx, uint64_t *buf, const LimbMap &map) {
-  constexpr int R1 = 1 << A, R2 = 1 << B, N = R1 * R2;
-  constexpr int C = (kTile / R1) < R2 ? (kTile / R1) : R2;
-  constexpr int ROWS = (kTile / R2) < R1 ? (kTile / R2) : R1;
-  timing_begin(ctx, "ntt_fwd_strided", 16.0 * N * map.n, 0.5 * N * A * map.n);
-  k_fwd_strided<A, B><<<dim3(R2 / C, map.n), kThreads, 0, ctx->stream>>>(
-      buf, map, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+template <int LOGN, bool STRIDED, bool INVERSE>
+void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                 const RowScale *sc) {
+  constexpr int LOGR = STRIDED ? split_a(LOGN) : split_b(LOGN);
+  constexpr int N = 1 << LOGN;
+  using G = Pass<LOGR, LOGN, STRIDED>;
+  static const char *names[2][2] = {{"ntt_fwd_contig", "ntt_fwd_strided"},
+                                    {"ntt_inv_contig", "ntt_inv_strided"}};
+  const double mm = (0.5 * LOGR + (INVERSE && STRIDED ? 1 : 0)) * N * map.n;
+  RowScale dummy;
+  timing_begin(ctx, names[INVERSE][STRIDED], 16.0 * N * map.n, mm);
+  k_ntt_pass<LOGR, LOGN, STRIDED, INVERSE><<<dim3(G::BLOCKS, map.n), kNttThreads, 0, ctx->stream>>>(
+      dst, src, map, ctx->d_mod, INVERSE ? ctx->d_itw : ctx->d_tw,
+      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, sc ? *sc : dummy, sc ? 1 : 0);
   timing_end(ctx);
-  timing_begin(ctx, "ntt_fwd_contig", 16.0 * N * map.n, 0.5 * N * B * map.n);
-  k_fwd_contig<A, B><<<dim3(R1 / ROWS, map.n), kThreads, 0, ctx->stream>>>(
-      buf, map, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
-  timing_end(ctx);
+}
+
+template <int LOGN>
+int run_forward(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map) {
+  launch_pass<LOGN, true, false>(ctx, dst, src, map, nullptr);
+  launch_pass<LOGN, false, false>(ctx, dst, nullptr, map, nullptr);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
 }
 
-template <int A, int B>
-int run_inverse(hck_context *ctx, uint64_t *buf, const LimbMap &map, const RowScale *sc) {
-  constexpr int R1 = 1 << A, R2 = 1 << B, N = R1 * R2;
-  constexpr int C = (kTile / R1) < R2 ? (kTile / R1) : R2;
-  constexpr int ROWS = (kTile / R2) < R1 ? (kTile / R2) : R1;
-  timing_begin(ctx, "ntt_inv_contig", 16.0 * N * map.n, 0.5 * N * B * map.n);
-  k_inv_contig<A, B><<<dim3(R1 / ROWS, map.n), kThreads, 0, ctx->stream>>>(
-      buf, map, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup);
-  timing_end(ctx);
-  RowScale dummy;
-  timing_begin(ctx, "ntt_inv_strided", 16.0 * N * map.n, (0.5 * A + 1) * N * map.n);
-  k_inv_strided<A, B><<<dim3(R2 / C, map.n), kThreads, 0, ctx->stream>>>(
-      buf, map, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup, sc ? *sc : dummy, sc ? 1 : 0);
-  timing_end(ctx);
+template <int LOGN>
+int run_inverse(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                const RowScale *sc) {
+  launch_pass<LOGN, false, true>(ctx, dst, src, map, nullptr);
+  launch_pass<LOGN, true, true>(ctx, dst, nullptr, map, sc);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+template <int LOGN>
+int run_one(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
+            const RowScale *sc) {
+  if (!inverse && strided) launch_pass<LOGN, true, false>(ctx, buf, nullptr, map, nullptr);
+  if (!inverse && !strided) launch_pass<LOGN, false, false>(ctx, buf, nullptr, map, nullptr);
+  if (inverse && !strided) launch_pass<LOGN, false, true>(ctx, buf, nullptr, map, nullptr);
+  if (inverse && strided) launch_pass<LOGN, true, true>(ctx, buf, nullptr, map, sc);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
 }
@@ -240,32 +125,55 @@ int run_inverse(hck_context *ctx, uint64_t *buf, const LimbMap &map, const RowSc
 }  // namespace
 
 int ntt_forward(hck_context *ctx, uint64_t *buf, const LimbMap &map) {
+  return ntt_forward_oop(ctx, buf, nullptr, map);
+}
+
+int ntt_forward_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map) {
   if (map.n == 0) return HCK_OK;
   switch (ctx->log_n) {
-    case 10: return run_forward<5, 5>(ctx, buf, map);
-    case 11: return run_forward<6, 5>(ctx, buf, map);
-    case 12: return run_forward<6, 6>(ctx, buf, map);
-    case 13: return run_forward<7, 6>(ctx, buf, map);
-    case 14: return run_forward<7, 7>(ctx, buf, map);
-    case 15: return run_forward<8, 7>(ctx, buf, map);
-    case 16: return run_forward<8, 8>(ctx, buf, map);
-    case 17: return run_forward<9, 8>(ctx, buf, map);
+    case 11: return run_forward<11>(ctx, dst, src, map);
+    case 12: return run_forward<12>(ctx, dst, src, map);
+    case 13: return run_forward<13>(ctx, dst, src, map);
+    case 14: return run_forward<14>(ctx, dst, src, map);
+    case 15: return run_forward<15>(ctx, dst, src, map);
+    case 16: return run_forward<16>(ctx, dst, src, map);
+    case 17: return run_forward<17>(ctx, dst, src, map);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }
 
 int ntt_inverse(hck_context *ctx, uint64_t *buf, const LimbMap &map, const RowScale *sc) {
+  return ntt_inverse_oop(ctx, buf, nullptr, map, sc);
+}
+
+int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                    const RowScale *sc) {
   if (map.n == 0) return HCK_OK;
   if (sc && map.n > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "too many scaled rows");
   switch (ctx->log_n) {
-    case 10: return run_inverse<5, 5>(ctx, buf, map, sc);
-    case 11: return run_inverse<6, 5>(ctx, buf, map, sc);
-    case 12: return run_inverse<6, 6>(ctx, buf, map, sc);
-    case 13: return run_inverse<7, 6>(ctx, buf, map, sc);
-    case 14: return run_inverse<7, 7>(ctx, buf, map, sc);
-    case 15: return run_inverse<8, 7>(ctx, buf, map, sc);
-    case 16: return run_inverse<8, 8>(ctx, buf, map, sc);
-    case 17: return run_inverse<9, 8>(ctx, buf, map, sc);
+    case 11: return run_inverse<11>(ctx, dst, src, map, sc);
+    case 12: return run_inverse<12>(ctx, dst, src, map, sc);
+    case 13: return run_inverse<13>(ctx, dst, src, map, sc);
+    case 14: return run_inverse<14>(ctx, dst, src, map, sc);
+    case 15: return run_inverse<15>(ctx, dst, src, map, sc);
+    case 16: return run_inverse<16>(ctx, dst, src, map, sc);
+    case 17: return run_inverse<17>(ctx, dst, src, map, sc);
+    default: return set_error(HCK_EPARAMS, "unsupported ring degree");
+  }
+}
+
+int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
+             const RowScale *sc) {
+  if (map.n == 0) return HCK_OK;
+  if (sc && map.n > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "too many scaled rows");
+  switch (ctx->log_n) {
+    case 11: return run_one<11>(ctx, buf, map, inverse, strided, sc);
+    case 12: return run_one<12>(ctx, buf, map, inverse, strided, sc);
+    case 13: return run_one<13>(ctx, buf, map, inverse, strided, sc);
+    case 14: return run_one<14>(ctx, buf, map, inverse, strided, sc);
+    case 15: return run_one<15>(ctx, buf, map, inverse, strided, sc);
+    case 16: return run_one<16>(ctx, buf, map, inverse, strided, sc);
+    case 17: return run_one<17>(ctx, buf, map, inverse, strided, sc);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }
