@@ -9,8 +9,10 @@ primes, K = 8 special primes, dnum = 3, scale 2^50):
   * the windowed, fftshifted 200-point DFT of every range bin as the
     block-diagonal plaintext matrices C~ = I_64 (x) Re W and S~ = I_64 (x) Im W
     (the paper's Kernel 3, Eq. dft_re): d_re = C~ v_re - S~ v_im and
-    d_im = S~ v_re + C~ v_im, four baby-step/giant-step transforms over 399
-    cached diagonals each (automorphisms, hybrid key switching, plaintext
+    d_im = S~ v_re + C~ v_im by baby-step/giant-step over 2 x 399 cached
+    diagonals, with the baby rotations of v_re and v_im shared by both
+    outputs and the inner sums of each output combined before its giant
+    rotations (automorphisms, batched hybrid key switching, plaintext
     products), then rescale;
   * the power spectrum |d|^2 = d_re^2 + d_im^2 (the paper's energy kernel):
     two tensor products, one relinearization, one rescale.
@@ -67,6 +69,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hoist", action="store_true",
+                    help="plain (not hoisted) baby-step rotations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the hot path is "
@@ -105,22 +109,18 @@ def main():
     steps_needed = sorted(set(ctx.lt_required_steps(lt_c)) | set(ctx.lt_required_steps(lt_s)))
     gks = ctx.keygen_rotation(sk, steps_needed, 5)
     rlk = ctx.keygen_relin(sk, 7)
-    rot_per_lt = len(ctx.lt_required_steps(lt_c))
-    rot_per_step = 4 * rot_per_lt
     log(f"setup done: {len(steps_needed)} rotation keys, 2 x {2 * FRAMES - 1} cached diagonals "
         f"({time.time() - t0:.1f}s)")
 
     # preallocated outputs
-    a, b, c, e = (ctx.ciphertext() for _ in range(4))
     d_re, d_im, t1, t2, p = (ctx.ciphertext() for _ in range(5))
+    terms = [(lt_c, 0, 0, 1), (lt_s, 1, 0, -1), (lt_s, 0, 1, 1), (lt_c, 1, 1, 1)]
+    babies = sum(1 for b in ctx.lt_required_steps(lt_c) if 0 < b < N1)
+    giants = len(ctx.lt_required_steps(lt_c)) - babies
+    rot_per_step = 2 * babies + 2 * giants
 
     def step():
-        ctx.lt_apply(lt_c, ct_re, gks, a)
-        ctx.lt_apply(lt_s, ct_im, gks, b)
-        ctx.sub(a, b, d_re)
-        ctx.lt_apply(lt_s, ct_re, gks, c)
-        ctx.lt_apply(lt_c, ct_im, gks, e)
-        ctx.add(c, e, d_im)
+        ctx.lt_eval([ct_re, ct_im], terms, gks, outputs=[d_re, d_im], hoist=not args.no_hoist)
         ctx.rescale(d_re, d_re)
         ctx.rescale(d_im, d_im)
         ctx.mul(d_re, d_re, t1)
@@ -135,14 +135,15 @@ def main():
     log(f"warmup done ({time.time() - t0:.1f}s)")
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for k in range(args.steps):
         step()
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    step_ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
+    ms_per_step = float(evs[0].elapsed_time(evs[-1])) / args.steps
     value = rot_per_step * args.steps / wall
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (events), wall {wall:.3f}s")
 
@@ -151,6 +152,41 @@ def main():
     ref = np.abs(w @ z).T ** 2
     max_err = float(np.max(np.abs(got - ref)))
     log(f"decoded |DFT|^2 max error vs plaintext: {max_err:.3e}")
+
+    # rotation-only throughput: R1 dependent chain, R2 16 ciphertexts with one
+    # key (batched key switching), R3 16 ciphertexts with 16 distinct keys
+    pool = [ctx.ciphertext() for _ in range(16)]
+    for c in pool:
+        ctx.add(ct_re, ct_im, c)
+    chain_a, chain_b = ctx.ciphertext(), ctx.ciphertext()
+    ctx.add(ct_re, ct_im, chain_a)
+    distinct = [k for k in steps_needed if k > 0][:16]
+
+    def timed(fn, count):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return count / (time.perf_counter() - t)
+
+    def r1():
+        x, y = chain_a, chain_b
+        for _ in range(32):
+            ctx.rotate(x, 1, gks, y)
+            x, y = y, x
+
+    def r2():
+        ctx.rotate_many(pool, 1, gks, pool)
+
+    def r3():
+        for c, k in zip(pool, distinct):
+            ctx.rotate(c, k, gks, c)
+
+    rotation_modes = {"R1_chain_rot_per_s": round(timed(r1, 32), 1),
+                      "R2_16ct_one_key_rot_per_s": round(timed(r2, 16), 1),
+                      "R3_16ct_16_keys_rot_per_s": round(timed(r3, len(distinct)), 1)}
+    log(f"rotation modes: {rotation_modes}")
 
     # per-kernel durations over two more steps (events around every launch)
     ctx.timing(True)
@@ -205,12 +241,18 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "vital window PSD: 200 frames x 64 bins complex in 2 ciphertexts, "
-                        "I_64 (x) W_200 windowed-DFT by BSGS (4 transforms, 399 diagonals, "
-                        f"n1={N1}), rescale, |.|^2 by tensor+relin, rescale",
+                        "complex I_64 (x) W_200 windowed DFT by BSGS (2 x 399 cached "
+                        f"diagonals, n1={N1}, shared baby steps), rescale, |.|^2 by "
+                        "tensor+relin, rescale",
             "ring_log_n": prm["log_n"], "L": L, "K": len(prm["p"]), "dnum": prm["dnum"],
             "rotations_per_step": rot_per_step, "keyswitches_per_step": rot_per_step + 1,
+            "hoisted_baby_steps": not args.no_hoist,
         },
         "decoded_max_abs_err": max_err,
+        "window_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                              "p99": round(float(np.percentile(step_ms, 99)), 3),
+                              "windows_per_s": round(args.steps / wall, 2)},
+        "rotation_modes": rotation_modes,
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,

@@ -213,6 +213,19 @@ int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out);
  * g = 5^step mod 2N.  A step = 0 (mod N/2) copies.  Errors: HCK_ENOKEY. */
 int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
                const hck_galois_keys *gks, hck_ciphertext *out);
+/* Rotations of n ciphertexts (one level) by the same step: the key switches
+ * run in batches that stream the Galois key once per batch.  out[i] may alias
+ * a[i]; outputs must be distinct.  Errors as hck_rotate, HCK_ELEVEL. */
+int hck_rotate_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, int32_t step,
+                    const hck_galois_keys *gks, hck_ciphertext *const *out);
+/* Hoisted rotations of one ciphertext by n steps: c1 is extended to Q u P
+ * once (ModUp) and every step applies its automorphism to the extended
+ * digits before the key inner product and ModDown.  These are valid
+ * rotations whose residues differ from hck_rotate's (the automorphism does
+ * not commute bit-exactly with the basis conversion).  Outputs must be
+ * distinct; one may alias a.  Errors: HCK_ENOKEY, HCK_EINVAL. */
+int hck_rotate_hoisted(hck_context *ctx, const hck_ciphertext *a, const int32_t *steps,
+                       uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out);
 /* The same for an explicit Galois element (e.g. 2N-1: conjugation). */
 int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element,
                      const hck_galois_keys *gks, hck_ciphertext *out);
@@ -246,6 +259,23 @@ int hck_lt_required_steps(const hck_linear_transform *lt, int32_t *steps, uint32
 /* Errors: HCK_ELEVEL (input level != transform level), HCK_ENOKEY. */
 int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_ciphertext *a,
                  const hck_galois_keys *gks, hck_ciphertext *out);
+/* Sums of transforms over shared inputs, e.g. the complex DFT of Eq. dft_re
+ * (d_re = C v_re - S v_im, d_im = S v_re + C v_im):
+ *   out[o] = sum_{t : term_out[t] = o} term_sign[t] lts[t](in[term_in[t]]).
+ * Every baby rotation Rot(in[i], b) is computed once and the inner sums of
+ * all outputs are combined before the giant rotations (Rot(A) + Rot(B) =
+ * Rot(A + B)); rotations by one step are key-switched in batches.  All
+ * inputs share one level and all transforms that level and one baby step;
+ * term_sign may be NULL (all +1) and holds +1 or -1.  Outputs may alias
+ * inputs.  flags: HCK_LT_HOIST_BABY computes each input's baby rotations as
+ * hoisted rotations (hck_rotate_hoisted).  Errors: HCK_EINVAL, HCK_ELEVEL,
+ * HCK_ESCALE (terms of one output with different scales), HCK_ENOKEY. */
+#define HCK_LT_HOIST_BABY 1u
+int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in,
+                const hck_linear_transform *const *lts, const uint32_t *term_in,
+                const uint32_t *term_out, const int32_t *term_sign, uint32_t n_terms,
+                const hck_galois_keys *gks, hck_ciphertext *const *out, uint32_t n_out,
+                uint32_t flags);
 int hck_lt_destroy(hck_linear_transform *lt);
 
 /* ---- kernel timing --------------------------------------------------------

@@ -24,7 +24,7 @@ silent is listed in the design document (readings A1-A23):
 * secret ternary, errors discrete Gaussian sigma = 3.2 cut at 19 (A7, A8),
   all randomness from SHAKE-256 streams (A9);
 * hybrid key switching with dnum contiguous digits, fast basis conversion
-  without correction and ModDown without rounding (A6, A14, A15);
+  without correction and ModDown with rounding (A6, A14, A15);
 * Rot(ct, k) = automorphism X -> X^(5^k) then key switching (A12, A13);
 * rescale by the last prime with a centred lift (A16); exact scale tracking
   (A17); BSGS with generalized diagonals and pre-rotated plaintexts (A18).
@@ -71,6 +71,8 @@ def _load():
         "ock_bconv": ([P, P, I, P, P, I, I], None),
         "ock_moddown": ([P, P, P, I, P, I, I], None),
         "ock_keyswitch": ([P, I, P, P, I, P, I, I, I, P, P], None),
+        "ock_modup": ([P, I, P, I, P, I, I, I, P], I),
+        "ock_keyswitch_ext": ([P, I, I, P, P, I, P, I, I, P, P], None),
         "ock_rescale": ([P, P, P, I, I], None),
         "ock_num_threads": ([], ctypes.c_int),
     }
@@ -544,6 +546,48 @@ class Oracle:
                               self.dnum, self.log_n, _ptr(out0), _ptr(out1))
         return out0, out1
 
+    def modup(self, d: np.ndarray, level: int) -> np.ndarray:
+        """Extended digits [digits][level+1+K][N] of d (coefficient form)."""
+        ne = level + 1 + self.K
+        ext = np.empty((self.dnum, ne, self.n), dtype=np.uint64)
+        q, p = _u64(self.q), _u64(self.p)
+        digits = _load().ock_modup(_ptr(_u64(d)), level, _ptr(q), self.L, _ptr(p), self.K,
+                                   self.dnum, self.log_n, _ptr(ext))
+        return np.ascontiguousarray(ext[:digits])
+
+    def keyswitch_ext(self, ext: np.ndarray, level: int, swk: np.ndarray):
+        out0 = np.empty((level + 1, self.n), dtype=np.uint64)
+        out1 = np.empty_like(out0)
+        q, p = _u64(self.q), _u64(self.p)
+        ext = _u64(ext)
+        _load().ock_keyswitch_ext(_ptr(ext), ext.shape[0], level, _ptr(_u64(swk)), _ptr(q),
+                                  self.L, _ptr(p), self.K, self.log_n, _ptr(out0), _ptr(out1))
+        return out0, out1
+
+    def rotate_hoisted(self, c: Ciphertext, steps: list, gks: dict) -> list:
+        """Rotations of one ciphertext by several steps sharing one ModUp
+        (reading A13): the extended digits of c1 are computed once; for each
+        step the automorphism X -> X^g is applied to every extended limb
+        before the key inner product and ModDown, and phi_g(c0) is added.
+        Valid key switches, with residues that differ from rotate()."""
+        ext = self.modup(c.polys[1], c.level)
+        ne_mods = self.qmods(c.level) + self.p
+        mods = self.qmods(c.level)
+        out = []
+        for k in steps:
+            if k % self.n_slots == 0:
+                out.append(Ciphertext(c.polys.copy(), c.level, c.scale))
+                continue
+            g = self.galois_element(k)
+            if g not in gks:
+                raise KeyError(f"no Galois key for element {g}")
+            ext_g = np.stack([automorphism(e, g, self.log_n, ne_mods) for e in ext])
+            u0, u1 = self.keyswitch_ext(ext_g, c.level, gks[g])
+            c0 = automorphism(c.polys[0], g, self.log_n, mods)
+            out.append(Ciphertext(np.stack([poly_add(c0, u0, self.log_n, mods), u1]),
+                                  c.level, c.scale))
+        return out
+
     def relinearize(self, c: Ciphertext, rlk: np.ndarray) -> Ciphertext:
         mods = self.qmods(c.level)
         u0, u1 = self.keyswitch(c.polys[2], c.level, rlk)
@@ -611,6 +655,50 @@ class Oracle:
                 if b != 0:
                     steps.add(b)
         return sorted(steps)
+
+    def lt_eval(self, inputs: list, terms: list, gks: dict, n_out: int,
+                hoist: bool = False) -> list:
+        """Sums of transforms over shared inputs (the complex DFT of Eq. dft_re
+        is C v_re - S v_im and S v_re + C v_im): terms are (transform, input
+        index, output index, sign).  For every output and giant index g the
+        inner sum runs over the terms' baby-step products, and is rotated once
+        by g n1: out_o = sum_g Rot(sum_t sign_t sum_b pt_{t,g,b} Rot(x_t, b), g n1).
+        With hoist the baby rotations of an input are hoisted rotations."""
+        n1 = terms[0][0].n1
+        need = {}
+        for lt, i, _o, _s in terms:
+            for items in lt.groups.values():
+                for b, _ in items:
+                    need.setdefault(i, set()).add(b)
+        babies = {}
+        for i, bs in need.items():
+            bs = sorted(bs)
+            if hoist:
+                rotated = self.rotate_hoisted(inputs[i], [b for b in bs if b != 0], gks)
+                it = iter(rotated)
+                for b in bs:
+                    babies[(i, b)] = inputs[i] if b == 0 else next(it)
+            else:
+                for b in bs:
+                    babies[(i, b)] = inputs[i] if b == 0 else self.rotate(inputs[i], b, gks)
+        giants = sorted({g for lt, _i, _o, _s in terms for g in lt.groups})
+        out = [None] * n_out
+        for g in giants:
+            inner = [None] * n_out
+            for lt, i, o, sign in terms:
+                for b, pt in lt.groups.get(g, []):
+                    term = self.mul_plain(babies[(i, b)], pt)
+                    if inner[o] is None:
+                        inner[o] = term if sign > 0 else self.sub(
+                            Ciphertext(np.zeros_like(term.polys), term.level, term.scale), term)
+                    else:
+                        inner[o] = self.add(inner[o], term) if sign > 0 else self.sub(inner[o], term)
+            for o in range(n_out):
+                if inner[o] is None:
+                    continue
+                r = inner[o] if g == 0 else self.rotate(inner[o], g * n1, gks)
+                out[o] = r if out[o] is None else self.add(out[o], r)
+        return out
 
     def lt_apply(self, lt: LinearTransform, c: Ciphertext, gks: dict) -> Ciphertext:
         """y = sum_g Rot(sum_b pt_{g,b} * Rot(c, b), g n1); no rescale."""

@@ -284,18 +284,15 @@ void ock_moddown(const u64 *u, u64 *out, const u64 *q, uint32_t nq, const u64 *p
   free(up);
 }
 
-/* Hybrid key switching of d (coefficient form, limbs 0..level of the q chain)
- * with switching key swk laid out [dnum][2][L+K][N] (rows 0..L-1 for the q
- * chain, rows L..L+K-1 for the special primes), coefficient form.
- *
- * Digits are the contiguous blocks D_j = [j*alpha, (j+1)*alpha) of the q
- * chain, alpha = ceil(L/dnum), cut to the limbs present at this level.  Each
- * digit is extended to Q_level u P by fast basis conversion (its own limbs are
- * kept), multiplied with (b_j, a_j) and summed; the two sums are brought back
- * to Q_level by ModDown.  Outputs (out0, out1) have level+1 limbs. */
-void ock_keyswitch(const u64 *d, uint32_t level, const u64 *swk, const u64 *q, uint32_t L,
-                   const u64 *p, uint32_t K, uint32_t dnum, uint32_t log_n, u64 *out0,
-                   u64 *out1) {
+/* ModUp of d (coefficient form, limbs 0..level of the q chain) for hybrid
+ * key switching: digits are the contiguous blocks D_j = [j*alpha,
+ * (j+1)*alpha) of the q chain, alpha = ceil(L/dnum), cut to the limbs present
+ * at this level; each present digit is extended by fast basis conversion to
+ * every limb of Q_level u P (its own limbs are kept).  ext is laid out
+ * [digit][level+1+K][N] (q limbs first, then the special primes); returns the
+ * number of digits present. */
+uint32_t ock_modup(const u64 *d, uint32_t level, const u64 *q, uint32_t L, const u64 *p,
+                   uint32_t K, uint32_t dnum, uint32_t log_n, u64 *ext) {
   u64 n = (u64)1 << log_n;
   uint32_t nq = level + 1;
   uint32_t ne = nq + K;
@@ -303,28 +300,53 @@ void ock_keyswitch(const u64 *d, uint32_t level, const u64 *swk, const u64 *q, u
   u64 *mods = (u64 *)malloc(ne * sizeof(u64));
   for (uint32_t t = 0; t < nq; t++) mods[t] = q[t];
   for (uint32_t k = 0; k < K; k++) mods[nq + k] = p[k];
-  u64 *acc0 = (u64 *)calloc((size_t)ne * n, sizeof(u64));
-  u64 *acc1 = (u64 *)calloc((size_t)ne * n, sizeof(u64));
+  uint32_t digits = 0;
   for (uint32_t j = 0; j < dnum; j++) {
     uint32_t lo = j * alpha;
     uint32_t hi = (j + 1) * alpha < nq ? (j + 1) * alpha : nq;
     if (lo >= hi) continue;
+    digits++;
 #pragma omp parallel for schedule(dynamic)
     for (uint32_t t = 0; t < ne; t++) {
-      u64 *ext = (u64 *)malloc(n * sizeof(u64));
-      u64 *prod = (u64 *)malloc(n * sizeof(u64));
+      u64 *row = ext + ((u64)j * ne + t) * n;
       if (t >= lo && t < hi)
-        memcpy(ext, d + (u64)t * n, n * sizeof(u64));
+        memcpy(row, d + (u64)t * n, n * sizeof(u64));
       else
-        bconv_one(d + (u64)lo * n, q + lo, hi - lo, mods[t], ext, n);
+        bconv_one(d + (u64)lo * n, q + lo, hi - lo, mods[t], row, n);
+    }
+  }
+  free(mods);
+  return digits;
+}
+
+/* Second half of hybrid key switching: given the extended digits (as
+ * ock_modup lays them out), u_{0,1} = sum_j ext_j * (b_j, a_j) over
+ * Q_level u P with the switching key swk [dnum][2][L+K][N] (rows 0..L-1 for
+ * the q chain, L..L+K-1 for the special primes), then ModDown of both sums to
+ * Q_level.  Outputs (out0, out1) have level+1 limbs. */
+void ock_keyswitch_ext(const u64 *ext, uint32_t digits, uint32_t level, const u64 *swk,
+                       const u64 *q, uint32_t L, const u64 *p, uint32_t K, uint32_t log_n,
+                       u64 *out0, u64 *out1) {
+  u64 n = (u64)1 << log_n;
+  uint32_t nq = level + 1;
+  uint32_t ne = nq + K;
+  u64 *mods = (u64 *)malloc(ne * sizeof(u64));
+  for (uint32_t t = 0; t < nq; t++) mods[t] = q[t];
+  for (uint32_t k = 0; k < K; k++) mods[nq + k] = p[k];
+  u64 *acc0 = (u64 *)calloc((size_t)ne * n, sizeof(u64));
+  u64 *acc1 = (u64 *)calloc((size_t)ne * n, sizeof(u64));
+  for (uint32_t j = 0; j < digits; j++) {
+#pragma omp parallel for schedule(dynamic)
+    for (uint32_t t = 0; t < ne; t++) {
+      u64 *prod = (u64 *)malloc(n * sizeof(u64));
+      const u64 *row = ext + ((u64)j * ne + t) * n;
       uint32_t key_row = t < nq ? t : L + (t - nq);
       const u64 *kb = swk + (((u64)j * 2 + 0) * (L + K) + key_row) * n;
       const u64 *ka = swk + (((u64)j * 2 + 1) * (L + K) + key_row) * n;
-      ock_poly_mul(ext, kb, prod, log_n, &mods[t], 1);
+      ock_poly_mul(row, kb, prod, log_n, &mods[t], 1);
       for (u64 c = 0; c < n; c++) acc0[t * n + c] = addmod(acc0[t * n + c], prod[c], mods[t]);
-      ock_poly_mul(ext, ka, prod, log_n, &mods[t], 1);
+      ock_poly_mul(row, ka, prod, log_n, &mods[t], 1);
       for (u64 c = 0; c < n; c++) acc1[t * n + c] = addmod(acc1[t * n + c], prod[c], mods[t]);
-      free(ext);
       free(prod);
     }
   }
@@ -333,6 +355,18 @@ void ock_keyswitch(const u64 *d, uint32_t level, const u64 *swk, const u64 *q, u
   free(acc0);
   free(acc1);
   free(mods);
+}
+
+/* Hybrid key switching of d: ModUp, then inner product and ModDown. */
+void ock_keyswitch(const u64 *d, uint32_t level, const u64 *swk, const u64 *q, uint32_t L,
+                   const u64 *p, uint32_t K, uint32_t dnum, uint32_t log_n, u64 *out0,
+                   u64 *out1) {
+  u64 n = (u64)1 << log_n;
+  uint32_t ne = level + 1 + K;
+  u64 *ext = (u64 *)malloc((size_t)dnum * ne * n * sizeof(u64));
+  uint32_t digits = ock_modup(d, level, q, L, p, K, dnum, log_n, ext);
+  ock_keyswitch_ext(ext, digits, level, swk, q, L, p, K, log_n, out0, out1);
+  free(ext);
 }
 
 /* Rescale one polynomial of nq = level+1 limbs by the last prime ql:

@@ -5,7 +5,7 @@ library's kernels.  The raw C entry points are available under their C names
 (``capi.hck_add`` ...); ``Context`` and the handle classes wrap them.  There is
 no fallback: importing this package without the built library raises.
 
-Build the library first: ``python -m paper_2603_22437_amd.build``.
+Build the library first: ``python paper_2603_22437_amd/build.py``.
 """
 from __future__ import annotations
 
@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhipckks.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2603_22437_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2603_22437_amd/build.py`")
 
 capi = ctypes.CDLL(LIB_PATH)
 
@@ -80,6 +80,9 @@ SIGNATURES = {
     "hck_rescale": ([_P, _P, _P], _I),
     "hck_rotate": ([_P, _P, _I32, _P, _P], _I),
     "hck_apply_galois": ([_P, _P, _U32, _P, _P], _I),
+    "hck_rotate_many": ([_P, _P, _U32, _I32, _P, _P], _I),
+    "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
+    "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_keyswitch": ([_P, _P, _P, _P], _I),
     "hck_lt_create": ([_P, _P, _P, _P, _U32, _U32, _U32, _D, _U32, _PP], _I),
     "hck_lt_create_from_residues": ([_P, _P, _P, _U32, _U32, _D, _U32, _PP], _I),
@@ -450,6 +453,13 @@ class Context:
         _check(capi.hck_rotate(self.h, a, step, gks, out))
         return out
 
+    def rotate_many(self, cts, step: int, gks, outs=None):
+        outs = [self.ciphertext() for _ in cts] if outs is None else outs
+        a = (ctypes.c_void_p * len(cts))(*[c.h for c in cts])
+        o = (ctypes.c_void_p * len(outs))(*[c.h for c in outs])
+        _check(capi.hck_rotate_many(self.h, a, len(cts), step, gks, o))
+        return outs
+
     def apply_galois(self, a, element: int, gks, out=None):
         out = self._out(out)
         _check(capi.hck_apply_galois(self.h, a, element, gks, out))
@@ -484,6 +494,30 @@ class Context:
         out = self._out(out)
         _check(capi.hck_lt_apply(self.h, lt, a, gks, out))
         return out
+
+    def rotate_hoisted(self, a, steps, gks, outs=None):
+        outs = [self.ciphertext() for _ in steps] if outs is None else outs
+        s = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+        o = (ctypes.c_void_p * len(outs))(*[c.h for c in outs])
+        _check(capi.hck_rotate_hoisted(self.h, a, _ptr(s), len(s), gks, o))
+        return outs
+
+    def lt_eval(self, inputs, terms, gks, outputs=None, n_out=None, hoist=False):
+        """terms: list of (transform, input index, output index, sign +-1);
+        returns the outputs out[o] = sum sign * lt(inputs[i]); with hoist the
+        baby rotations of each input share one ModUp."""
+        if outputs is None:
+            n_out = n_out if n_out is not None else 1 + max(t[2] for t in terms)
+            outputs = [self.ciphertext() for _ in range(n_out)]
+        ins = (ctypes.c_void_p * len(inputs))(*[c.h for c in inputs])
+        lts = (ctypes.c_void_p * len(terms))(*[t[0].h for t in terms])
+        ti = np.array([t[1] for t in terms], dtype=np.uint32)
+        to = np.array([t[2] for t in terms], dtype=np.uint32)
+        ts = np.array([t[3] for t in terms], dtype=np.int32)
+        outs = (ctypes.c_void_p * len(outputs))(*[c.h for c in outputs])
+        _check(capi.hck_lt_eval(self.h, ins, len(inputs), lts, _ptr(ti), _ptr(to), _ptr(ts),
+                                len(terms), gks, outs, len(outputs), 1 if hoist else 0))
+        return outputs
 
     # --- kernel timing ---
     def timing(self, on: bool):

@@ -1,7 +1,9 @@
 """Builds the HIP library libhipckks.so in-tree for gfx950 with hipcc.
 
 Every source under csrc/ is compiled to an object (in parallel) and linked
-into paper_2603_22437_amd/libhipckks.so.  Run: python -m paper_2603_22437_amd.build
+into paper_2603_22437_amd/libhipckks.so.  Run it as a script,
+`python paper_2603_22437_amd/build.py` (importing it through the package would
+first load the library it is about to rebuild).
 """
 import concurrent.futures
 import os

@@ -194,7 +194,7 @@ int make_switch_key(hck_context *ctx, const hck_secret_key *sk, const uint64_t *
     if (!rc) rc = embed_small_host(ctx, b, e, poly_rows(1, nm, nm));
     if (!rc) rc = ntt_forward_rows(ctx, b, poly_rows(2, nm, nm));
     // b = e - a s
-    if (!rc) rc = launch_mul_mont(ctx, tmp, ak, sk->data, full, false);
+    if (!rc) rc = launch_mul_mont(ctx, tmp, ak, sk->data, full, 0);
     if (!rc) rc = launch_addsub(ctx, b, b, tmp, full, 1);
     // + (P mod q_i) s' on the limbs of digit j
     const uint32_t lo = j * ctx->alpha, hi = std::min(L, lo + ctx->alpha);
@@ -232,12 +232,6 @@ int lt_alloc_ct(hck_context *ctx, hck_ciphertext **ct) {
 }
 
 }  // namespace
-
-// Per-transform device scratch of hck_lt_apply (baby-step ciphertexts).
-struct LtScratch {
-  std::vector<hck_ciphertext *> babies;
-  hck_ciphertext *inner = nullptr, *giant = nullptr;
-};
 
 extern "C" {
 
@@ -308,7 +302,7 @@ int hck_keygen_public(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
   if (!rc) rc = upload(ctx, ak, a.data(), a.size() * 8);
   if (!rc) rc = embed_small_host(ctx, b, e, poly_rows(1, L, L));
   if (!rc) rc = ntt_forward_rows(ctx, b, poly_rows(2, L, L));
-  if (!rc) rc = launch_mul_mont(ctx, tmp, ak, sk->data, qm, false);
+  if (!rc) rc = launch_mul_mont(ctx, tmp, ak, sk->data, qm, 0);
   if (!rc) rc = launch_addsub(ctx, b, b, tmp, qm, 1);
   if (!rc) rc = mont_rows(ctx, pk->data, poly_rows(2, L, L), true);
   if (rc) {
@@ -348,7 +342,7 @@ int hck_keygen_relin(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
     TRY(dev_alloc(ctx, &own, (size_t)(ctx->L + ctx->K) * ctx->n));
     s2 = own;
   }
-  int rc = launch_mul_mont(ctx, s2, sk->data, sk->data, fullmap(ctx), false);
+  int rc = launch_mul_mont(ctx, s2, sk->data, sk->data, fullmap(ctx), 0);
   if (!rc) rc = make_switch_key(ctx, sk, s2, "rlk", seed, out);
   dev_free(ctx, own);
   return rc;
@@ -601,7 +595,7 @@ int hck_encrypt_sk(hck_context *ctx, const hck_secret_key *sk, const hck_plainte
   TRY(embed_small_host(ctx, c0, e, poly_rows(1, ctx->L, nq)));
   TRY(ntt_forward_rows(ctx, c0, poly_rows(2, ctx->L, nq)));
   // c0 = e + m - a s
-  TRY(launch_mul_mont(ctx, tmp, c1, sk->data, qm, false));
+  TRY(launch_mul_mont(ctx, tmp, c1, sk->data, qm, 0));
   TRY(launch_addsub(ctx, c0, c0, tmp, qm, 1));
   TRY(launch_copy(ctx, tmp, pt->data, (size_t)nq * n));
   TRY(launch_to_mont(ctx, tmp, qm, false));
@@ -632,8 +626,8 @@ int hck_encrypt_pk(hck_context *ctx, const hck_public_key *pk, const hck_plainte
   TRY(embed_small_host(ctx, c1, e1, poly_rows(1, ctx->L, nq)));
   TRY(ntt_forward_rows(ctx, c0, poly_rows(2, ctx->L, nq)));
   TRY(ntt_forward_rows(ctx, vv, poly_rows(1, ctx->L, nq)));
-  TRY(launch_mul_mont(ctx, c0, vv, pk->data, qm, true));
-  TRY(launch_mul_mont(ctx, c1, vv, pk->data + ps, qm, true));
+  TRY(launch_mul_mont(ctx, c0, vv, pk->data, qm, 1));
+  TRY(launch_mul_mont(ctx, c1, vv, pk->data + ps, qm, 1));
   TRY(launch_copy(ctx, tmp, pt->data, (size_t)nq * n));
   TRY(launch_to_mont(ctx, tmp, qm, false));
   TRY(launch_addsub(ctx, c0, c0, tmp, qm, 0));
@@ -660,10 +654,10 @@ int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext
   uint64_t *tmp = ws_tmp(ctx);
   // m = c0 + REDC(c1 s~) (+ REDC(c2 REDC(s~ s~)))
   if (!rc) rc = launch_copy(ctx, pt->data, ct->data, (size_t)nq * n);
-  if (!rc) rc = launch_mul_mont(ctx, pt->data, ct->data + ps, sk->data, qm, true);
+  if (!rc) rc = launch_mul_mont(ctx, pt->data, ct->data + ps, sk->data, qm, 1);
   if (!rc && ct->size == 3) {
-    rc = launch_mul_mont(ctx, tmp, sk->data, sk->data, qm, false);
-    if (!rc) rc = launch_mul_mont(ctx, pt->data, ct->data + 2 * ps, tmp, qm, true);
+    rc = launch_mul_mont(ctx, tmp, sk->data, sk->data, qm, 0);
+    if (!rc) rc = launch_mul_mont(ctx, pt->data, ct->data + 2 * ps, tmp, qm, 1);
   }
   if (!rc) rc = launch_to_mont(ctx, pt->data, qm, true);
   if (rc) {
@@ -743,7 +737,7 @@ int hck_mul_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext
   const size_t ps = poly_stride(ctx);
   for (uint32_t p = 0; p < size; p++)
     TRY(launch_mul_mont(ctx, out->data + p * ps, a->data + p * ps, pt->data, qmap(ctx, level),
-                        false));
+                        0));
   out->size = size;
   out->level = level;
   out->scale = scale;
@@ -977,84 +971,273 @@ int hck_lt_required_steps(const hck_linear_transform *lt, int32_t *steps, uint32
   return HCK_OK;
 }
 
-int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_ciphertext *a,
-                 const hck_galois_keys *gks, hck_ciphertext *out) {
-  ENTER(ctx);
-  if (!lt || !a || !out || !gks) return set_error(HCK_EINVAL, "null argument");
-  if (a->size != 2) return set_error(HCK_EINVAL, "needs a 2-part ciphertext");
-  if (a->level != lt->level) return set_error(HCK_ELEVEL, "level differs from the transform's");
-  // key check up front, so a missing key fails before any work
-  {
-    uint32_t cnt = 0;
-    hck_lt_required_steps(lt, nullptr, 0, &cnt);
-    std::vector<int32_t> st(cnt);
-    hck_lt_required_steps(lt, st.data(), cnt, &cnt);
-    for (int32_t s : st)
-      if ((int64_t)s % (ctx->n / 2) != 0 && !gks->keys.count(galois_of_step(ctx, s)))
-        return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
+// Pooled scratch ciphertexts of the linear-transform evaluator.
+static hck_ciphertext *pool_get(hck_context *ctx) {
+  if (!ctx->ct_pool.empty()) {
+    hck_ciphertext *ct = ctx->ct_pool.back();
+    ctx->ct_pool.pop_back();
+    return ct;
   }
-  hck_linear_transform *m = const_cast<hck_linear_transform *>(lt);
-  LtScratch *sc = nullptr;
-  // scratch ciphertexts: baby steps 0..n1-1, the inner sum, the giant rotation
-  static_assert(sizeof(void *) == 8, "64-bit only");
-  if (m->owned.empty()) return set_error(HCK_EINVAL, "empty transform");
-  sc = new LtScratch();
-  int rc = HCK_OK;
-  sc->babies.assign(m->n1, nullptr);
+  hck_ciphertext *ct = new hck_ciphertext();
+  ct->ctx = ctx;
+  return ct;
+}
+
+static void pool_put(hck_context *ctx, hck_ciphertext *ct) {
+  if (ct) ctx->ct_pool.push_back(ct);
+}
+
+int hck_rotate_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, int32_t step,
+                    const hck_galois_keys *gks, hck_ciphertext *const *out) {
+  ENTER(ctx);
+  if ((n && (!a || !out)) || !gks) return set_error(HCK_EINVAL, "null argument");
+  for (uint32_t i = 0; i < n; i++)
+    if (!a[i] || !out[i]) return set_error(HCK_EINVAL, "null ciphertext");
+  if ((int64_t)step % (ctx->n / 2) == 0) {
+    for (uint32_t i = 0; i < n; i++) TRY(hck_rotate(ctx, a[i], step, gks, out[i]));
+    return HCK_OK;
+  }
+  return apply_galois_many(ctx, a, n, galois_of_step(ctx, step), gks, out);
+}
+
+int hck_rotate_hoisted(hck_context *ctx, const hck_ciphertext *a, const int32_t *steps,
+                       uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
+  ENTER(ctx);
+  if (!a || !gks || (n && (!steps || !out))) return set_error(HCK_EINVAL, "null argument");
+  if (a->size != 2) return set_error(HCK_EINVAL, "rotation needs a 2-part ciphertext");
+  std::vector<uint32_t> gal;
+  std::vector<const hck_switch_key *> keys;
+  std::vector<hck_ciphertext *> dst;
+  const int64_t slots = ctx->n / 2;
+  bool alias = false;
+  for (uint32_t i = 0; i < n; i++) {
+    if (!out[i]) return set_error(HCK_EINVAL, "null output");
+    for (uint32_t k = 0; k < i; k++)
+      if (out[k] == out[i]) return set_error(HCK_EINVAL, "outputs must be distinct");
+    alias = alias || out[i] == a;
+    if ((int64_t)steps[i] % slots == 0) continue;
+    const uint32_t g = galois_of_step(ctx, steps[i]);
+    auto it = gks->keys.find(g);
+    if (it == gks->keys.end())
+      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(steps[i]));
+    gal.push_back(g);
+    keys.push_back(it->second);
+    dst.push_back(out[i]);
+  }
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
   const uint32_t level = a->level;
-  const size_t n = ctx->n, ps = poly_stride(ctx);
-  const double out_scale = a->scale * m->scale;
-  // baby steps (b = 0 is a copy of the input, so out may alias a)
-  for (auto &kv : m->groups)
-    for (auto &bp : kv.second) {
-      const int32_t b = bp.first;
-      if (rc || sc->babies[b]) continue;
-      rc = lt_alloc_ct(ctx, &sc->babies[b]);
-      if (!rc) rc = hck_rotate(ctx, a, b, gks, sc->babies[b]);
+  const double scale = a->scale;
+  const size_t ps = poly_stride(ctx), words = (size_t)(level + 1) * ctx->n;
+  const uint64_t *c0 = a->data, *c1 = a->data + ps;
+  if (alias) {  // read the input from a copy so that its handle can be written
+    uint64_t *copy = ws_rot(ctx);
+    TRY(launch_copy(ctx, copy, a->data, words));
+    TRY(launch_copy(ctx, copy + ps, a->data + ps, words));
+    c0 = copy;
+    c1 = copy + ps;
+  }
+  std::vector<uint64_t *> o0, o1;
+  for (hck_ciphertext *y : dst) {
+    TRY(ensure_ct(ctx, y, 2));
+    o0.push_back(y->data);
+    o1.push_back(y->data + ps);
+  }
+  TRY(keyswitch_hoisted(ctx, c0, c1, level, gal.data(), keys.data(), (uint32_t)gal.size(),
+                        o0.data(), o1.data()));
+  for (uint32_t i = 0; i < n; i++) {
+    if ((int64_t)steps[i] % slots == 0 && out[i] != a) {
+      TRY(ensure_ct(ctx, out[i], 2));
+      TRY(launch_copy(ctx, out[i]->data, c0, words));
+      TRY(launch_copy(ctx, out[i]->data + ps, c1, words));
     }
-  if (!rc) rc = lt_alloc_ct(ctx, &sc->inner);
-  if (!rc) rc = lt_alloc_ct(ctx, &sc->giant);
-  bool first = true;
-  if (!rc) rc = ensure_ct(ctx, out, 2);
+    out[i]->size = 2;
+    out[i]->level = level;
+    out[i]->scale = scale;
+  }
+  return HCK_OK;
+}
+
+// Baby-step/giant-step evaluation of sums of transforms:
+//   out[o] = sum over terms t with term_out[t] = o of sign_t lt_t(in[term_in[t]]).
+// Baby rotations Rot(in, b) are computed once per (input, b) and key-switched
+// in batches over the inputs; for every giant index g the inner sums of all
+// outputs are formed first (Rot(A) + Rot(B) = Rot(A + B)) and then rotated
+// by g n1 together, one key stream per batch.
+int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in,
+                const hck_linear_transform *const *lts, const uint32_t *term_in,
+                const uint32_t *term_out, const int32_t *term_sign, uint32_t n_terms,
+                const hck_galois_keys *gks, hck_ciphertext *const *out, uint32_t n_out,
+                uint32_t flags) {
+  ENTER(ctx);
+  if (!in || !lts || !term_in || !term_out || !out || !gks || n_in == 0 || n_terms == 0 ||
+      n_out == 0)
+    return set_error(HCK_EINVAL, "null or empty argument");
+  const uint32_t level = in[0]->level;
+  uint32_t n1 = 0;
+  for (uint32_t i = 0; i < n_in; i++) {
+    if (!in[i] || in[i]->size != 2) return set_error(HCK_EINVAL, "inputs must be 2-part ciphertexts");
+    if (in[i]->level != level) return set_error(HCK_ELEVEL, "inputs at different levels");
+  }
+  for (uint32_t o = 0; o < n_out; o++)
+    if (!out[o]) return set_error(HCK_EINVAL, "null output");
+  std::vector<double> out_scale(n_out, 0.0);
+  for (uint32_t t = 0; t < n_terms; t++) {
+    const hck_linear_transform *lt = lts[t];
+    if (!lt || term_in[t] >= n_in || term_out[t] >= n_out)
+      return set_error(HCK_EINVAL, "bad term");
+    if (term_sign && term_sign[t] != 1 && term_sign[t] != -1)
+      return set_error(HCK_EINVAL, "term signs must be +1 or -1");
+    if (lt->level != level) return set_error(HCK_ELEVEL, "transform level differs from input level");
+    if (n1 == 0) n1 = lt->n1;
+    if (lt->n1 != n1) return set_error(HCK_EINVAL, "transforms must share the baby step");
+    const double sc = in[term_in[t]]->scale * lt->scale;
+    double &os = out_scale[term_out[t]];
+    if (os == 0.0) os = sc;
+    else if (!scales_match(os, sc)) return set_error(HCK_ESCALE, "terms of one output differ in scale");
+  }
+  for (uint32_t o = 0; o < n_out; o++)
+    if (out_scale[o] == 0.0) return set_error(HCK_EINVAL, "an output has no term");
+  // keys needed, checked before any work
+  std::map<int32_t, std::vector<uint32_t>> baby_inputs;  // b -> inputs
+  std::map<int32_t, std::vector<uint32_t>> giant_outputs; // g -> outputs
+  for (uint32_t t = 0; t < n_terms; t++)
+    for (auto &kv : lts[t]->groups) {
+      auto &go = giant_outputs[kv.first];
+      if (std::find(go.begin(), go.end(), term_out[t]) == go.end()) go.push_back(term_out[t]);
+      for (auto &bp : kv.second) {
+        auto &bi = baby_inputs[bp.first];
+        if (std::find(bi.begin(), bi.end(), term_in[t]) == bi.end()) bi.push_back(term_in[t]);
+      }
+    }
+  const int64_t slots = ctx->n / 2;
+  auto need = [&](int64_t step) -> int {
+    if (step % slots == 0) return HCK_OK;
+    if (!gks->keys.count(galois_of_step(ctx, (int32_t)step)))
+      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(step));
+    return HCK_OK;
+  };
+  for (auto &kv : baby_inputs) TRY(need(kv.first));
+  for (auto &kv : giant_outputs) TRY(need((int64_t)kv.first * n1));
+
+  const size_t n = ctx->n, ps = poly_stride(ctx);
   const LimbMap qm = qmap(ctx, level);
-  for (auto &kv : m->groups) {
+  std::vector<hck_ciphertext *> scratch;
+  auto get = [&]() {
+    hck_ciphertext *c = pool_get(ctx);
+    scratch.push_back(c);
+    return c;
+  };
+  int rc = HCK_OK;
+  // baby steps: baby[(input, b)]; b = 0 is the input itself
+  std::map<std::pair<uint32_t, int32_t>, const hck_ciphertext *> baby;
+  if (flags & HCK_LT_HOIST_BABY) {
+    std::map<uint32_t, std::vector<int32_t>> per_input;
+    for (auto &kv : baby_inputs)
+      for (uint32_t i : kv.second) {
+        if (kv.first == 0) baby[{i, 0}] = in[i];
+        else per_input[i].push_back(kv.first);
+      }
+    for (auto &kv : per_input) {
+      std::vector<hck_ciphertext *> dst;
+      for (int32_t b : kv.second) {
+        hck_ciphertext *c = get();
+        dst.push_back(c);
+        baby[{kv.first, b}] = c;
+      }
+      if (rc == HCK_OK)
+        rc = hck_rotate_hoisted(ctx, in[kv.first], kv.second.data(), (uint32_t)kv.second.size(),
+                                gks, dst.data());
+    }
+  } else {
+    for (auto &kv : baby_inputs) {
+      const int32_t b = kv.first;
+      if (b == 0) {
+        for (uint32_t i : kv.second) baby[{i, 0}] = in[i];
+        continue;
+      }
+      std::vector<const hck_ciphertext *> src;
+      std::vector<hck_ciphertext *> dst;
+      for (uint32_t i : kv.second) {
+        hck_ciphertext *c = get();
+        src.push_back(in[i]);
+        dst.push_back(c);
+        baby[{i, b}] = c;
+      }
+      if (rc == HCK_OK)
+        rc = hck_rotate_many(ctx, src.data(), (uint32_t)src.size(), b, gks, dst.data());
+    }
+  }
+  // accumulators (outputs may alias inputs, so results land in scratch first)
+  std::vector<hck_ciphertext *> acc(n_out), inner(n_out), giant(n_out);
+  std::vector<bool> started(n_out, false);
+  for (uint32_t o = 0; o < n_out; o++) {
+    acc[o] = get();
+    inner[o] = get();
+    giant[o] = get();
+    if (!rc) rc = ensure_ct(ctx, acc[o], 2);
+    if (!rc) rc = ensure_ct(ctx, inner[o], 2);
+  }
+  for (auto &kv : giant_outputs) {
     if (rc) break;
     const int32_t g = kv.first;
-    bool first_term = true;
-    for (auto &bp : kv.second) {
-      const hck_ciphertext *x = sc->babies[bp.first];
-      for (uint32_t p = 0; p < 2 && !rc; p++)
-        rc = launch_mul_mont(ctx, sc->inner->data + p * ps, x->data + p * ps, bp.second, qm,
-                             !first_term);
-      first_term = false;
+    std::vector<bool> touched(n_out, false);
+    for (uint32_t t = 0; t < n_terms && !rc; t++) {
+      auto it = lts[t]->groups.find(g);
+      if (it == lts[t]->groups.end()) continue;
+      const uint32_t o = term_out[t];
+      const bool neg = term_sign && term_sign[t] < 0;
+      for (auto &bp : it->second) {
+        const hck_ciphertext *x = baby[{term_in[t], bp.first}];
+        const int mode = touched[o] ? (neg ? 2 : 1) : (neg ? 3 : 0);
+        for (uint32_t p = 0; p < 2 && !rc; p++)
+          rc = launch_mul_mont(ctx, inner[o]->data + p * ps, x->data + p * ps, bp.second, qm, mode);
+        touched[o] = true;
+      }
     }
-    sc->inner->size = 2;
-    sc->inner->level = level;
-    sc->inner->scale = out_scale;
-    const hck_ciphertext *term = sc->inner;
-    if (!rc && g != 0) {
-      rc = apply_galois_core(ctx, sc->inner, galois_of_step(ctx, g * (int32_t)m->n1), gks,
-                             sc->giant);
-      term = sc->giant;
+    std::vector<const hck_ciphertext *> src;
+    std::vector<hck_ciphertext *> dst;
+    for (uint32_t o : kv.second) {
+      inner[o]->size = 2;
+      inner[o]->level = level;
+      inner[o]->scale = out_scale[o];
+      src.push_back(inner[o]);
+      dst.push_back(giant[o]);
     }
-    for (uint32_t p = 0; p < 2 && !rc; p++) {
-      if (first)
-        rc = launch_copy(ctx, out->data + p * ps, term->data + p * ps, (size_t)(level + 1) * n);
-      else
-        rc = launch_addsub(ctx, out->data + p * ps, out->data + p * ps, term->data + p * ps, qm, 0);
+    if (!rc && g != 0)
+      rc = apply_galois_many(ctx, src.data(), (uint32_t)src.size(),
+                             galois_of_step(ctx, g * (int32_t)n1), gks, dst.data());
+    for (uint32_t o : kv.second) {
+      if (rc) break;
+      const hck_ciphertext *term = g != 0 ? giant[o] : inner[o];
+      for (uint32_t p = 0; p < 2 && !rc; p++) {
+        if (!started[o])
+          rc = launch_copy(ctx, acc[o]->data + p * ps, term->data + p * ps, (size_t)(level + 1) * n);
+        else
+          rc = launch_addsub(ctx, acc[o]->data + p * ps, acc[o]->data + p * ps, term->data + p * ps,
+                             qm, 0);
+      }
+      started[o] = true;
     }
-    first = false;
   }
-  if (!rc) {
-    out->size = 2;
-    out->level = level;
-    out->scale = out_scale;
+  for (uint32_t o = 0; o < n_out && !rc; o++) {
+    rc = ensure_ct(ctx, out[o], 2);
+    for (uint32_t p = 0; p < 2 && !rc; p++)
+      rc = launch_copy(ctx, out[o]->data + p * ps, acc[o]->data + p * ps, (size_t)(level + 1) * n);
+    if (!rc) {
+      out[o]->size = 2;
+      out[o]->level = level;
+      out[o]->scale = out_scale[o];
+    }
   }
-  for (auto *b : sc->babies) hck_ciphertext_destroy(b);
-  hck_ciphertext_destroy(sc->inner);
-  hck_ciphertext_destroy(sc->giant);
-  delete sc;
+  for (hck_ciphertext *s : scratch) pool_put(ctx, s);
   return rc;
+}
+
+int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_ciphertext *a,
+                 const hck_galois_keys *gks, hck_ciphertext *out) {
+  const uint32_t zero = 0;
+  const int32_t one = 1;
+  return hck_lt_eval(ctx, &a, 1, &lt, &zero, &zero, &one, 1, gks, &out, 1, 0);
 }
 
 int hck_lt_destroy(hck_linear_transform *lt) {

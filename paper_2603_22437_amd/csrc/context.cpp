@@ -360,6 +360,11 @@ void destroy_context(hck_context *ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx, ctx->ws);
+  for (hck_ciphertext *ct : ctx->ct_pool) {
+    dev_free(ctx, ct->data);
+    delete ct;
+  }
+  ctx->ct_pool.clear();
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (void *p : {(void *)ctx->d_mod, (void *)ctx->d_tw, (void *)ctx->d_tw_shoup,

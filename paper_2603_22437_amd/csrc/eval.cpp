@@ -8,20 +8,27 @@
 
 namespace hck {
 
+size_t ws_ks_rows(const hck_context *ctx) {
+  const size_t L = ctx->L, LK = ctx->L + ctx->K;
+  return L + ctx->dnum * LK + 2 * LK + 2 * L;
+}
+
+// [kMaxBatch key-switch slots][kMaxBatch x L rows: automorphism sources]
+// [3 (L+K) rows: general temporary]
 size_t ws_words_needed(const hck_context *ctx) {
   const size_t n = ctx->n, L = ctx->L, LK = ctx->L + ctx->K;
-  const size_t ks = L + ctx->dnum * LK + 2 * LK + 2 * L;
-  return n * (ks + 2 * L + 3 * LK);
+  return n * (kMaxBatch * ws_ks_rows(ctx) + kMaxBatch * L + 3 * LK);
 }
 
 uint64_t *ws_ks(hck_context *ctx) { return ctx->ws; }
 
 uint64_t *ws_rot(hck_context *ctx) {
-  const size_t n = ctx->n, L = ctx->L, LK = ctx->L + ctx->K;
-  return ctx->ws + n * (L + ctx->dnum * LK + 2 * LK + 2 * L);
+  return ctx->ws + (size_t)ctx->n * kMaxBatch * ws_ks_rows(ctx);
 }
 
-uint64_t *ws_tmp(hck_context *ctx) { return ws_rot(ctx) + (size_t)ctx->n * 2 * ctx->L; }
+uint64_t *ws_tmp(hck_context *ctx) {
+  return ws_rot(ctx) + (size_t)ctx->n * kMaxBatch * ctx->L;
+}
 
 int ntt_forward_rows(hck_context *ctx, uint64_t *buf,
                      const std::vector<std::pair<uint16_t, uint8_t>> &rows) {
@@ -38,34 +45,63 @@ int ntt_forward_rows(hck_context *ctx, uint64_t *buf,
   return HCK_OK;
 }
 
-int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
-                      const hck_galois_keys *gks, hck_ciphertext *out) {
+int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
+                      const hck_galois_keys *gks, hck_ciphertext *const *out) {
   auto it = gks->keys.find(g);
   if (it == gks->keys.end())
     return set_error(HCK_ENOKEY, "no Galois key for element " + std::to_string(g));
-  if (a->size != 2) return set_error(HCK_EINVAL, "rotation needs a 2-part ciphertext");
+  if (n == 0) return HCK_OK;
+  const uint32_t level = a[0]->level;
+  for (uint32_t i = 0; i < n; i++) {
+    if (a[i]->size != 2) return set_error(HCK_EINVAL, "rotation needs a 2-part ciphertext");
+    if (a[i]->level != level) return set_error(HCK_ELEVEL, "batched rotations need one level");
+    for (uint32_t k = 0; k < i; k++)
+      if (out[k] == out[i]) return set_error(HCK_EINVAL, "batched outputs must be distinct");
+  }
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
   if (rc) return rc;
-  rc = ensure_ct(ctx, out, 2);
-  if (rc) return rc;
   const size_t ps = (size_t)ctx->L * ctx->n;
-  const uint32_t level = a->level;
-  const double scale = a->scale;
-  // (phi_g(c0), 0) + KeySwitch(phi_g(c1)); the automorphism is applied while
-  // reading c1 and c0, so c0 must not be overwritten while it is gathered
-  const uint64_t *c0 = a->data;
-  if (out == a) {
-    uint64_t *copy = ws_rot(ctx);
-    if ((rc = launch_copy(ctx, copy, a->data, (size_t)(level + 1) * ctx->n))) return rc;
-    c0 = copy;
+  for (uint32_t s = 0; s < n; s += kMaxBatch) {
+    KsBatch kb;
+    kb.n = std::min<uint32_t>(kMaxBatch, n - s);
+    std::vector<double> scales(kb.n);
+    for (uint32_t b = 0; b < kb.n; b++) {
+      const hck_ciphertext *x = a[s + b];
+      hck_ciphertext *y = out[s + b];
+      scales[b] = x->scale;
+      // (phi_g(c0), 0) + KeySwitch(phi_g(c1)).  c1 is only read by the
+      // launches before the final one, but c0 is gathered through phi_g by the
+      // final launch while it writes the outputs: an output that aliases this
+      // input gets a copy of c0 to read instead
+      bool alias = false;
+      for (uint32_t k = 0; k < kb.n; k++) alias = alias || out[s + k] == x;
+      if ((rc = ensure_ct(ctx, y, 2))) return rc;
+      const uint64_t *c0 = x->data, *c1 = x->data + ps;
+      if (alias) {
+        uint64_t *copy = ws_rot(ctx) + (size_t)b * ps;
+        if ((rc = launch_copy(ctx, copy, x->data, (size_t)(level + 1) * ctx->n))) return rc;
+        c0 = copy;
+      }
+      kb.galois[b] = g;
+      kb.d[b] = c1;
+      kb.out0[b] = y->data;
+      kb.out1[b] = y->data + ps;
+      kb.add0[b] = c0;
+      kb.add1[b] = nullptr;
+    }
+    if ((rc = keyswitch_batch(ctx, kb, level, it->second))) return rc;
+    for (uint32_t b = 0; b < kb.n; b++) {
+      out[s + b]->size = 2;
+      out[s + b]->level = level;
+      out[s + b]->scale = scales[b];
+    }
   }
-  rc = keyswitch_core(ctx, a->data + ps, g, level, it->second, out->data, out->data + ps, c0,
-                      nullptr);
-  if (rc) return rc;
-  out->size = 2;
-  out->level = level;
-  out->scale = scale;
   return HCK_OK;
+}
+
+int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
+                      const hck_galois_keys *gks, hck_ciphertext *out) {
+  return apply_galois_many(ctx, &a, 1, g, gks, &out);
 }
 
 }  // namespace hck

@@ -15,6 +15,7 @@ namespace hck {
 
 constexpr int kMaxLimbs = HCK_MAX_LIMBS;
 constexpr int kMaxRows = 192;  // rows of one batched launch (e.g. every extended digit)
+constexpr int kMaxBatch = 4;   // ciphertexts key-switched together with one key
 
 // Per-modulus constants, indexed by the modulus index of the full chain
 // (0..L-1: q chain, L..L+K-1: special primes).
@@ -77,6 +78,8 @@ struct hck_context {
   // key-switch workspace (device)
   uint64_t *ws = nullptr;
   size_t ws_words = 0;
+  // scratch ciphertexts reused by linear transforms
+  std::vector<struct hck_ciphertext *> ct_pool;
 
   bool broken = false;
 
@@ -177,17 +180,20 @@ int ntt_inverse(hck_context *ctx, uint64_t *buf, const LimbMap &map, const RowSc
 int ntt_forward_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map);
 int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
                     const RowScale *scale);
-// one pass (strided or contiguous, forward or inverse) in place
+// one pass (strided or contiguous, forward or inverse) in place; an inverse
+// strided pass with `scale` uses entry (row list index mod period) (period 0:
+// the list index itself)
 int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
-             const RowScale *scale);
+             const RowScale *scale, int period = 0);
 
 int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t words);
 // out[r] = a[r] (+|-) b[r] for rows in map; op 0 add, 1 sub, 2 negate a
 int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
                   const LimbMap &map, int op);
-// out = REDC(a * bm) (bm in Montgomery form); accumulate adds to out
+// out = [+-] REDC(a * bm) [+ out] (bm in Montgomery form): mode 0 set,
+// 1 add to out, 2 subtract from out, 3 set negated
 int launch_mul_mont(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *bm,
-                    const LimbMap &map, bool accumulate);
+                    const LimbMap &map, int mode);
 // x -> x 2^64 mod q (into Montgomery form) or x 2^-64 (out of it), in place
 int launch_to_mont(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool to);
 // tensor of (a0, a1) and (b0, b1) into out0..out2; poly stride given in words
@@ -237,12 +243,39 @@ size_t ws_words_needed(const hck_context *ctx);
 uint64_t *ws_ks(hck_context *ctx);    // key-switch internals
 uint64_t *ws_rot(hck_context *ctx);   // [2][L][N]: automorphism output
 uint64_t *ws_tmp(hck_context *ctx);   // [3][L+K][N]: general temporary
-// (out0, out1) = KeySwitch(phi_g(d)) + (phi_g(add0), phi_g(add1)); d and the
-// addends [level+1][N] in evaluation form; g = 1 for no automorphism.  out
-// rows must not overlap d; with g != 1 they must not overlap the addends.
+// Up to kMaxBatch key switches with one key, at one level, in one sequence
+// of launches (the key is streamed once per batch):
+// (out0[b], out1[b]) = KeySwitch(phi_g(d[b])) + (phi_g(add0[b]), phi_g(add1[b])).
+// d and the addends are [level+1][N] in evaluation form; g = 1 for no
+// automorphism; null addends are skipped.  out rows must not overlap d; with
+// g != 1 they must not overlap the addends.
+struct KsBatch {
+  uint32_t n;
+  uint32_t galois[kMaxBatch];
+  const uint64_t *d[kMaxBatch];
+  uint64_t *out0[kMaxBatch];
+  uint64_t *out1[kMaxBatch];
+  const uint64_t *add0[kMaxBatch];
+  const uint64_t *add1[kMaxBatch];
+};
+int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level,
+                    const hck_switch_key *key);
+// Hoisted rotations of one ciphertext (c0, c1) by n Galois elements: ModUp of
+// c1 once, then per element the automorphism of the extended digits, the key
+// inner product and ModDown (batched over the elements), plus phi_g(c0).
+// out0/out1 rows must not overlap c0 or c1.
+int keyswitch_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_t level,
+                      const uint32_t *galois, const hck_switch_key *const *keys, uint32_t n,
+                      uint64_t *const *out0, uint64_t *const *out1);
+// single key switch (batch of one)
 int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_t level,
                    const hck_switch_key *key, uint64_t *out0, uint64_t *out1, const uint64_t *add0,
                    const uint64_t *add1);
+// rotations of n ciphertexts (same level) by one Galois element, key-switched
+// in batches; out[i] may alias a[i]
+int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
+                      const hck_galois_keys *gks, hck_ciphertext *const *out);
+size_t ws_ks_rows(const hck_context *ctx);   // rows of one batch slot of ws_ks
 int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *out);
 // runs ntt_forward / ntt_inverse over maps longer than one launch allows

@@ -37,15 +37,19 @@ __global__ __launch_bounds__(kThreads) void k_addsub(uint64_t *out, const uint64
   out[off] = r;
 }
 
+// out = [+-] REDC(a * bm) [+ out]: mode 0 set, 1 add to out, 2 subtract from
+// out, 3 set negated (bm in Montgomery form, so REDC gives a * b mod q)
 __global__ __launch_bounds__(kThreads) void k_mul_mont(uint64_t *out, const uint64_t *a,
                                                        const uint64_t *bm, LimbMap map,
                                                        const ModConst *__restrict__ mc, int n,
-                                                       int accumulate) {
+                                                       int mode) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   const size_t off = (size_t)map.row[blockIdx.y] * n + i;
   const ModConst m = mc[map.mod[blockIdx.y]];
   uint64_t r = redc(mul_wide(a[off], bm[off]), m.q, m.qinv);
-  if (accumulate) r = add_mod(r, out[off], m.q);
+  if (mode == 1) r = add_mod(out[off], r, m.q);
+  else if (mode == 2) r = sub_mod(out[off], r, m.q);
+  else if (mode == 3) r = r == 0 ? 0 : m.q - r;
   out[off] = r;
 }
 
@@ -182,12 +186,12 @@ int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint
 }
 
 int launch_mul_mont(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *bm,
-                    const LimbMap &map, bool accumulate) {
+                    const LimbMap &map, int mode) {
   if (map.n == 0) return HCK_OK;
-  timing_begin(ctx, "mul_plain", (accumulate ? 32.0 : 24.0) * ctx->n * map.n,
+  timing_begin(ctx, "mul_plain", ((mode == 1 || mode == 2) ? 32.0 : 24.0) * ctx->n * map.n,
                (double)ctx->n * map.n);
   k_mul_mont<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, bm, map, ctx->d_mod,
-                                                                   ctx->n, accumulate ? 1 : 0);
+                                                                   ctx->n, mode);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;

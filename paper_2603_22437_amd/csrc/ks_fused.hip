@@ -1,5 +1,6 @@
 // Hybrid key switching with the basis conversions, the key inner product and
-// the ModDown tail fused into the NTT passes (ntt_core.h).
+// the ModDown tail fused into the NTT passes (ntt_core.h), for a batch of up
+// to kMaxBatch inputs that share one switching key.
 //
 // KeySwitch(d) at level l with a switching key swk(s' -> s); d is read through
 // the NTT-domain automorphism X -> X^g (g = 1: no automorphism), so a
@@ -11,13 +12,18 @@
 //       forward strided pass -> ext[j][t]
 //   K4  per extended limb t: forward contiguous pass of every digit's ext
 //       (or phi_g(d) itself on the digit's own limbs), then
-//       acc_{0,1}[t] = sum_j d~_j[t] swk_j[t] (keys in Montgomery form)
+//       acc_{0,1}[t] = sum_j d~_j[t] swk_j[t] (keys in Montgomery form); the
+//       workgroup loops over the batch, so each key tile is fetched from HBM
+//       once per batch and re-read from cache
 //   K5  inverse passes of acc's P limbs, times N^-1 (P/p_k)^-1, plus
 //       ((P-1)/2) (P/p_k)^-1 (the rounding term of ModDown)
 //   K6  ModDown conversion P -> q_i (minus (P-1)/2) at load time, then the
 //       forward strided pass -> conv
 //   K7  forward contiguous pass of conv, then
 //       out_i = (acc_i - conv_i) P^-1 (+ phi_g(addend)_i)
+//
+// Workspace: batch slot b occupies rows [b R, (b+1) R) of ws_ks (R rows of N
+// words): y [L] | ext [dnum][L+K] | acc [2][L+K] | conv [2][L].
 #include "ntt_core.h"
 
 namespace hck {
@@ -26,26 +32,33 @@ namespace {
 
 struct KsGeom {
   uint32_t level, nq, ne, L, K, dnum, alpha, nm;
+  uint32_t slot_rows;                       // rows per batch slot
+  uint32_t off_ext, off_acc, off_conv;      // row offsets inside a slot
 };
 
 struct ModUpRows {
   uint32_t n;
-  uint16_t row[kMaxRows];
+  uint16_t row[kMaxRows];     // output row (workspace row)
+  uint16_t src[kMaxRows];     // workspace row of the digit's first source limb
   uint8_t mod[kMaxRows];
   uint8_t digit[kMaxRows];
 };
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
-    uint64_t *__restrict__ y, const uint64_t *__restrict__ d, uint32_t galois,
+    uint64_t *__restrict__ ws, KsBatch kb, KsGeom kg,
     const ModConst *__restrict__ mc, const uint64_t *__restrict__ itw,
     const uint64_t *__restrict__ itws) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
   const int li = blockIdx.y;  // limb i (modulus i)
+  const uint32_t b = blockIdx.z;
   const uint64_t q = mc[li].q;
   const size_t roff = (size_t)li * G::N;
+  const uint64_t *d = kb.d[b];
+  const uint32_t galois = kb.galois[b];
+  uint64_t *y = ws + (size_t)b * kg.slot_rows * G::N;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   uint64_t x[P];
@@ -60,19 +73,18 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
-    uint64_t *__restrict__ ext, const uint64_t *__restrict__ y, ModUpRows rows,
-    const uint64_t *__restrict__ conv, KsGeom kg, const ModConst *__restrict__ mc,
-    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
+    uint64_t *__restrict__ ws, ModUpRows rows, const uint64_t *__restrict__ conv, KsGeom kg,
+    const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
+    const uint64_t *__restrict__ tws) {
   using G = Pass<split_a(LOGN), LOGN, true>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
   const int mi = rows.mod[blockIdx.y];
   const int j = rows.digit[blockIdx.y];
-  const uint32_t lo = j * kg.alpha;
-  const uint32_t na = min(kg.alpha, kg.nq - lo);
+  const uint32_t na = min(kg.alpha, kg.nq - j * kg.alpha);
   const ModConst m = mc[mi];
   const uint64_t *cv = conv + (size_t)j * kg.alpha * kg.nm + mi;
-  const uint64_t *src = y + (size_t)lo * G::N;
+  const uint64_t *src = ws + (size_t)rows.src[blockIdx.y] * G::N;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   uint64_t x[P];
@@ -81,20 +93,20 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     const size_t pos = G::gaddr(g, G::ipoint(r, i));
     u128 acc;
     acc.lo = acc.hi = 0;
-    for (uint32_t a = 0; a < na; a++) mac_wide(acc, src[(size_t)a * G::N + pos], cv[(size_t)a * kg.nm]);
+    for (uint32_t a = 0; a < na; a++)
+      mac_wide(acc, src[(size_t)a * G::N + pos], cv[(size_t)a * kg.nm]);
     x[i] = redc(acc, m.q, m.qinv);
   }
   G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
-  uint64_t *out = ext + (size_t)rows.row[blockIdx.y] * G::N;
+  uint64_t *out = ws + (size_t)rows.row[blockIdx.y] * G::N;
 #pragma unroll
   for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
 }
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
-    uint64_t *__restrict__ acc, const uint64_t *__restrict__ ext, const uint64_t *__restrict__ d,
-    uint32_t galois, const uint64_t *__restrict__ key, KsGeom kg,
-    const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
+    uint64_t *__restrict__ ws, KsBatch kb, const uint64_t *__restrict__ key,
+    KsGeom kg, const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
     const uint64_t *__restrict__ tws) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
@@ -105,59 +117,64 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   const size_t krow = (size_t)kg.nm * G::N;
-  uint64_t a0[P], a1[P], x[P];
+  for (uint32_t b = 0; b < kb.n; b++) {
+    uint64_t *slot = ws + (size_t)b * kg.slot_rows * G::N;
+    const uint64_t *d = kb.d[b];
+    const uint32_t galois = kb.galois[b];
+    uint64_t a0[P], a1[P], x[P];
 #pragma unroll
-  for (int i = 0; i < P; i++) a0[i] = a1[i] = 0;
-  for (uint32_t j = 0; j < kg.dnum; j++) {
-    const uint32_t lo = j * kg.alpha;
-    if (lo >= kg.nq) break;
-    const uint32_t hi = min(lo + kg.alpha, kg.nq);
-    if (t >= lo && t < hi) {
+    for (int i = 0; i < P; i++) a0[i] = a1[i] = 0;
+    for (uint32_t j = 0; j < kg.dnum; j++) {
+      const uint32_t lo = j * kg.alpha;
+      if (lo >= kg.nq) break;
+      const uint32_t hi = min(lo + kg.alpha, kg.nq);
+      if (t >= lo && t < hi) {
 #pragma unroll
-      for (int i = 0; i < P; i++)
-        x[i] = d[(size_t)t * G::N +
-                 galois_src((uint32_t)G::gaddr(g, G::ipoint(r, i)), galois, LOGN)];
-    } else {
-      const uint64_t *e = ext + ((size_t)j * kg.ne + t) * G::N;
+        for (int i = 0; i < P; i++)
+          x[i] = d[(size_t)t * G::N +
+                   galois_src((uint32_t)G::gaddr(g, G::ipoint(r, i)), galois, LOGN)];
+      } else {
+        const uint64_t *e = slot + ((size_t)kg.off_ext + j * kg.ne + t) * G::N;
 #pragma unroll
-      for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
-      G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+        for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
+        G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
 #pragma unroll
-      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], m.q);
-      G::to_interleaved(lds, x, c, r);
+        for (int v = 0; v < P; v++) x[v] = reduce4(x[v], m.q);
+        G::to_interleaved(lds, x, c, r);
+      }
+      const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * G::N;
+      const uint64_t *kap = kbp + krow;
+#pragma unroll
+      for (int i = 0; i < P; i++) {
+        const size_t pos = G::gaddr(g, G::ipoint(r, i));
+        a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kbp[pos]), m.q, m.qinv), m.q);
+        a1[i] = add_mod(a1[i], redc(mul_wide(x[i], kap[pos]), m.q, m.qinv), m.q);
+      }
     }
-    const uint64_t *kb = key + 2 * j * krow + (size_t)mi * G::N;
-    const uint64_t *ka = kb + krow;
+    uint64_t *o0 = slot + ((size_t)kg.off_acc + t) * G::N;
+    uint64_t *o1 = slot + ((size_t)kg.off_acc + kg.ne + t) * G::N;
 #pragma unroll
     for (int i = 0; i < P; i++) {
       const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kb[pos]), m.q, m.qinv), m.q);
-      a1[i] = add_mod(a1[i], redc(mul_wide(x[i], ka[pos]), m.q, m.qinv), m.q);
+      o0[pos] = a0[i];
+      o1[pos] = a1[i];
     }
-  }
-  uint64_t *o0 = acc + (size_t)t * G::N;
-  uint64_t *o1 = acc + ((size_t)kg.ne + t) * G::N;
-#pragma unroll
-  for (int i = 0; i < P; i++) {
-    const size_t pos = G::gaddr(g, G::ipoint(r, i));
-    o0[pos] = a0[i];
-    o1[pos] = a1[i];
   }
 }
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
-    uint64_t *__restrict__ conv_out, const uint64_t *__restrict__ acc,
-    const uint64_t *__restrict__ down_conv, const uint64_t *__restrict__ hneg, KsGeom kg,
-    const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
-    const uint64_t *__restrict__ tws) {
+    uint64_t *__restrict__ ws, const uint64_t *__restrict__ down_conv,
+    const uint64_t *__restrict__ hneg, KsGeom kg, const ModConst *__restrict__ mc,
+    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
   using G = Pass<split_a(LOGN), LOGN, true>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
   const uint32_t p = blockIdx.y / kg.nq, li = blockIdx.y % kg.nq;
+  uint64_t *slot = ws + (size_t)blockIdx.z * kg.slot_rows * G::N;
   const ModConst m = mc[li];
   const uint64_t h = hneg[li];
-  const uint64_t *src = acc + ((size_t)p * kg.ne + kg.nq) * G::N;
+  const uint64_t *src = slot + ((size_t)kg.off_acc + p * kg.ne + kg.nq) * G::N;
   const uint64_t *cv = down_conv + li;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
@@ -167,29 +184,31 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
     const size_t pos = G::gaddr(g, G::ipoint(r, i));
     u128 s;
     s.lo = s.hi = 0;
-    for (uint32_t k = 0; k < kg.K; k++) mac_wide(s, src[(size_t)k * G::N + pos], cv[(size_t)k * kg.nm]);
+    for (uint32_t k = 0; k < kg.K; k++)
+      mac_wide(s, src[(size_t)k * G::N + pos], cv[(size_t)k * kg.nm]);
     x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
   }
   G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
-  uint64_t *out = conv_out + ((size_t)p * kg.L + li) * G::N;
+  uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
 #pragma unroll
   for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
 }
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
-    uint64_t *__restrict__ out0, uint64_t *__restrict__ out1, const uint64_t *__restrict__ conv_in,
-    const uint64_t *__restrict__ acc, const uint64_t *add0, const uint64_t *add1,
-    uint32_t galois, RowScale pinv, KsGeom kg, const ModConst *__restrict__ mc,
-    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
+    uint64_t *__restrict__ ws, KsBatch kb, RowScale pinv, KsGeom kg,
+    const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
+    const uint64_t *__restrict__ tws) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
   const uint32_t p = blockIdx.y / kg.nq, li = blockIdx.y % kg.nq;
+  const uint32_t b = blockIdx.z;
+  const uint64_t *slot = ws + (size_t)b * kg.slot_rows * G::N;
   const uint64_t q = mc[li].q;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
-  const uint64_t *cin = conv_in + ((size_t)p * kg.L + li) * G::N;
+  const uint64_t *cin = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
   uint64_t x[P];
 #pragma unroll
   for (int i = 0; i < P; i++) x[i] = cin[G::gaddr(g, G::ipoint(r, i))];
@@ -197,9 +216,10 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
 #pragma unroll
   for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
   G::to_interleaved(lds, x, c, r);
-  const uint64_t *u = acc + ((size_t)p * kg.ne + li) * G::N;
-  const uint64_t *add = p == 0 ? add0 : add1;
-  uint64_t *out = (p == 0 ? out0 : out1) + (size_t)li * G::N;
+  const uint64_t *u = slot + ((size_t)kg.off_acc + p * kg.ne + li) * G::N;
+  const uint64_t *add = p == 0 ? kb.add0[b] : kb.add1[b];
+  const uint32_t galois = kb.galois[b];
+  uint64_t *out = (p == 0 ? kb.out0[b] : kb.out1[b]) + (size_t)li * G::N;
   const uint64_t w = pinv.w[li], wp = pinv.wp[li];
 #pragma unroll
   for (int i = 0; i < P; i++) {
@@ -210,28 +230,69 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
   }
 }
 
+// inner product of hoisted rotations: for extended limb t,
+// acc_{0,1}[t] = sum_j phi_g(d~_j)[t] swk_j[t], with d~_j fully transformed in
+// slot 0's ext rows (own limbs: phi_g(c1)) and the result in slot b's acc rows
 template <int LOGN>
-int ks_run(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_t level,
-           const hck_switch_key *key, uint64_t *out0, uint64_t *out1, const uint64_t *add0,
-           const uint64_t *add1) {
+__global__ __launch_bounds__(256) void k_ks_inner_gather(
+    uint64_t *__restrict__ ws, const uint64_t *__restrict__ c1, uint32_t galois, uint32_t b,
+    const uint64_t *__restrict__ key, KsGeom kg, const ModConst *__restrict__ mc) {
+  constexpr int N = 1 << LOGN;
+  const uint32_t pos = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t t = blockIdx.y;
+  const uint32_t mi = t < kg.nq ? t : kg.L + (t - kg.nq);
+  const ModConst m = mc[mi];
+  const uint32_t src = galois_src(pos, galois, LOGN);
+  const size_t krow = (size_t)kg.nm * N;
+  u128 s0, s1;
+  s0.lo = s0.hi = s1.lo = s1.hi = 0;
+  for (uint32_t j = 0; j < kg.dnum; j++) {
+    const uint32_t lo = j * kg.alpha;
+    if (lo >= kg.nq) break;
+    const uint32_t hi = min(lo + kg.alpha, kg.nq);
+    const uint64_t x = (t >= lo && t < hi)
+                           ? c1[(size_t)t * N + src]
+                           : ws[((size_t)kg.off_ext + j * kg.ne + t) * N + src];
+    const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * N;
+    mac_wide(s0, x, kbp[pos]);
+    mac_wide(s1, x, kbp[krow + pos]);
+  }
+  uint64_t *slot = ws + (size_t)b * kg.slot_rows * N;
+  slot[((size_t)kg.off_acc + t) * N + pos] = redc(s0, m.q, m.qinv);
+  slot[((size_t)kg.off_acc + kg.ne + t) * N + pos] = redc(s1, m.q, m.qinv);
+}
+
+KsGeom make_geom(const hck_context *ctx, uint32_t level) {
+  KsGeom kg;
+  kg.level = level;
+  kg.nq = level + 1;
+  kg.ne = level + 1 + ctx->K;
+  kg.L = ctx->L;
+  kg.K = ctx->K;
+  kg.dnum = ctx->dnum;
+  kg.alpha = ctx->alpha;
+  kg.nm = ctx->L + ctx->K;
+  kg.slot_rows = (uint32_t)ws_ks_rows(ctx);
+  kg.off_ext = ctx->L;
+  kg.off_acc = ctx->L + ctx->dnum * kg.nm;
+  kg.off_conv = kg.off_acc + 2 * kg.nm;
+  return kg;
+}
+
+// K1-K3 for batch slots 0..nb-1 (ModUp into each slot's ext rows)
+template <int LOGN>
+int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
   constexpr int A = split_a(LOGN), B = split_b(LOGN);
   constexpr double N = (double)(1 << LOGN);
   using GA = Pass<A, LOGN, true>;
   using GB = Pass<B, LOGN, false>;
-  const size_t n = ctx->n;
-  const uint32_t L = ctx->L, K = ctx->K, nm = L + K, alpha = ctx->alpha;
-  const uint32_t nq = level + 1, ne = nq + K;
-  const KsGeom kg{level, nq, ne, L, K, ctx->dnum, alpha, nm};
-  uint64_t *y = ws_ks(ctx);
-  uint64_t *ext = y + (size_t)L * n;
-  uint64_t *acc = ext + (size_t)ctx->dnum * nm * n;
-  uint64_t *conv = acc + (size_t)2 * nm * n;
+  const uint32_t L = kg.L, nm = kg.nm, alpha = kg.alpha, nq = kg.nq, ne = kg.ne, nb = kb.n;
+  const uint32_t level = kg.level;
+  uint64_t *ws = ws_ks(ctx);
   int rc;
-
-  // K1, K2: coefficient form of phi_g(d) times N^-1 (Q_j / q_i)^-1
-  timing_begin(ctx, "ks_intt_gather", 16.0 * N * nq, 0.5 * N * B * nq);
-  k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nq), kNttThreads, 0, ctx->stream>>>(
-      y, d, galois, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup);
+  timing_begin(ctx, "ks_intt_gather", 16.0 * N * nq * nb, 0.5 * N * B * nq * nb);
+  k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nq, nb), kNttThreads, 0, ctx->stream>>>(
+      ws, kb, kg, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup);
   timing_end(ctx);
   RowScale sc;
   for (uint32_t i = 0; i < nq; i++) {
@@ -239,98 +300,240 @@ int ks_run(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_t level,
     sc.wp[i] = h_shoup(sc.w[i], ctx->mods[i]);
     sc.add[i] = 0;
   }
-  if ((rc = ntt_pass(ctx, y, qmap(ctx, level), true, true, &sc))) return rc;
-
-  // K3: ModUp conversion + forward strided pass of every extended limb
-  std::vector<std::pair<uint32_t, uint32_t>> ext_rows;  // (digit, t)
-  for (uint32_t j = 0; j < ctx->dnum; j++) {
-    const uint32_t lo = j * alpha;
-    if (lo >= nq) break;
-    const uint32_t hi = std::min(lo + alpha, nq);
-    for (uint32_t t = 0; t < ne; t++)
-      if (t < lo || t >= hi) ext_rows.push_back({j, t});
+  {
+    LimbMap m;
+    m.n = nq * nb;
+    for (uint32_t b = 0; b < nb; b++)
+      for (uint32_t i = 0; i < nq; i++) {
+        m.row[b * nq + i] = (uint16_t)(b * kg.slot_rows + i);
+        m.mod[b * nq + i] = (uint8_t)i;
+      }
+    if ((rc = ntt_pass(ctx, ws, m, true, true, &sc, (int)nq))) return rc;
   }
-  const uint64_t *up_conv = ctx->d_up_conv + (size_t)level * ctx->dnum * alpha * nm;
+  struct Row {
+    uint16_t row, src;
+    uint8_t mod, digit;
+    uint32_t na;
+  };
+  std::vector<Row> ext_rows;
+  for (uint32_t b = 0; b < nb; b++)
+    for (uint32_t j = 0; j < kg.dnum; j++) {
+      const uint32_t lo = j * alpha;
+      if (lo >= nq) break;
+      const uint32_t hi = std::min(lo + alpha, nq);
+      for (uint32_t t = 0; t < ne; t++) {
+        if (t >= lo && t < hi) continue;
+        Row rw;
+        rw.row = (uint16_t)(b * kg.slot_rows + kg.off_ext + j * ne + t);
+        rw.src = (uint16_t)(b * kg.slot_rows + lo);
+        rw.mod = (uint8_t)(t < nq ? t : L + (t - nq));
+        rw.digit = (uint8_t)j;
+        rw.na = hi - lo;
+        ext_rows.push_back(rw);
+      }
+    }
+  const uint64_t *up_conv = ctx->d_up_conv + (size_t)level * kg.dnum * alpha * nm;
   for (size_t s = 0; s < ext_rows.size(); s += kMaxRows) {
     ModUpRows mr;
     mr.n = (uint32_t)std::min(ext_rows.size() - s, (size_t)kMaxRows);
     double srcs = 0;
     for (uint32_t k = 0; k < mr.n; k++) {
-      const uint32_t j = ext_rows[s + k].first, t = ext_rows[s + k].second;
-      mr.row[k] = (uint16_t)(j * ne + t);
-      mr.mod[k] = (uint8_t)(t < nq ? t : L + (t - nq));
-      mr.digit[k] = (uint8_t)j;
-      srcs += std::min(alpha, nq - j * alpha);
+      const Row &rw = ext_rows[s + k];
+      mr.row[k] = rw.row;
+      mr.src[k] = rw.src;
+      mr.mod[k] = rw.mod;
+      mr.digit[k] = rw.digit;
+      srcs += rw.na;
     }
     timing_begin(ctx, "ks_modup_strided", 8.0 * N * (srcs + mr.n), N * (srcs + 0.5 * A * mr.n));
     k_modup_strided<LOGN><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
-        ext, y, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+        ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
     timing_end(ctx);
   }
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
 
-  // K4: forward contiguous pass of the extended digits + key inner product
-  const double digits = (double)((nq + alpha - 1) / alpha);
-  const double ext_limbs = (double)ext_rows.size();
-  timing_begin(ctx, "ks_contig_inner", 8.0 * N * (ext_limbs + nq + 2 * digits * ne + 2 * ne),
-               N * (0.5 * B * ext_limbs + 2 * digits * ne));
-  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne), kNttThreads, 0, ctx->stream>>>(
-      acc, ext, d, galois, key->data, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+// K5-K7 for batch slots 0..nb-1 (ModDown of each slot's acc rows)
+template <int LOGN>
+int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
+  constexpr int A = split_a(LOGN), B = split_b(LOGN);
+  constexpr double N = (double)(1 << LOGN);
+  using GA = Pass<A, LOGN, true>;
+  using GB = Pass<B, LOGN, false>;
+  const uint32_t L = kg.L, K = kg.K, nq = kg.nq, ne = kg.ne, nb = kb.n;
+  uint64_t *ws = ws_ks(ctx);
+  int rc;
+  {
+    LimbMap mp;
+    RowScale sp;
+    mp.n = 2 * K * nb;
+    for (uint32_t b = 0; b < nb; b++)
+      for (uint32_t p = 0; p < 2; p++)
+        for (uint32_t k = 0; k < K; k++) {
+          const uint32_t r = (b * 2 + p) * K + k;
+          mp.row[r] = (uint16_t)(b * kg.slot_rows + kg.off_acc + p * ne + nq + k);
+          mp.mod[r] = (uint8_t)(L + k);
+        }
+    for (uint32_t p = 0; p < 2; p++)
+      for (uint32_t k = 0; k < K; k++) {
+        sp.w[p * K + k] = ctx->down_scale[k];
+        sp.wp[p * K + k] = h_shoup(ctx->down_scale[k], ctx->mods[L + k]);
+        sp.add[p * K + k] = ctx->down_add[k];
+      }
+    if ((rc = ntt_pass(ctx, ws, mp, true, false, nullptr))) return rc;
+    if ((rc = ntt_pass(ctx, ws, mp, true, true, &sp, (int)(2 * K)))) return rc;
+  }
+  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K + 1) * 2 * nq * nb,
+               N * (K + 0.5 * A) * 2 * nq * nb);
+  k_moddown_strided<LOGN><<<dim3(GA::BLOCKS, 2 * nq, nb), kNttThreads, 0, ctx->stream>>>(
+      ws, ctx->d_down_conv, ctx->d_down_hneg, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
-
-  // K5: inverse transform of the P limbs of both accumulators (+ ModDown scale)
-  LimbMap mp;
-  RowScale sp;
-  mp.n = 2 * K;
-  for (uint32_t p = 0; p < 2; p++)
-    for (uint32_t k = 0; k < K; k++) {
-      const uint32_t r = p * K + k;
-      mp.row[r] = (uint16_t)(p * ne + nq + k);
-      mp.mod[r] = (uint8_t)(L + k);
-      sp.w[r] = ctx->down_scale[k];
-      sp.wp[r] = h_shoup(sp.w[r], ctx->mods[L + k]);
-      sp.add[r] = ctx->down_add[k];
-    }
-  if ((rc = ntt_pass(ctx, acc, mp, true, false, nullptr))) return rc;
-  if ((rc = ntt_pass(ctx, acc, mp, true, true, &sp))) return rc;
-
-  // K6: ModDown conversion + forward strided pass
-  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K + 1) * 2 * nq, N * (K + 0.5 * A) * 2 * nq);
-  k_moddown_strided<LOGN><<<dim3(GA::BLOCKS, 2 * nq), kNttThreads, 0, ctx->stream>>>(
-      conv, acc, ctx->d_down_conv, ctx->d_down_hneg, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
-  timing_end(ctx);
-
-  // K7: forward contiguous pass + (acc - conv) P^-1 + addend
   RowScale pinv;
   for (uint32_t i = 0; i < nq; i++) {
     pinv.w[i] = ctx->pinv[i];
     pinv.wp[i] = h_shoup(ctx->pinv[i], ctx->mods[i]);
     pinv.add[i] = 0;
   }
-  const double adds = (add0 ? nq : 0) + (add1 ? nq : 0);
-  timing_begin(ctx, "ks_moddown_tail", 8.0 * N * (3.0 * 2 * nq + adds), N * (0.5 * B + 1) * 2 * nq);
-  k_moddown_contig_tail<LOGN><<<dim3(GB::BLOCKS, 2 * nq), kNttThreads, 0, ctx->stream>>>(
-      out0, out1, conv, acc, add0, add1, galois, pinv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  double adds = 0;
+  for (uint32_t b = 0; b < nb; b++) adds += (kb.add0[b] ? nq : 0) + (kb.add1[b] ? nq : 0);
+  timing_begin(ctx, "ks_moddown_tail", 8.0 * N * (3.0 * 2 * nq * nb + adds),
+               N * (0.5 * B + 1) * 2 * nq * nb);
+  k_moddown_contig_tail<LOGN><<<dim3(GB::BLOCKS, 2 * nq, nb), kNttThreads, 0, ctx->stream>>>(
+      ws, kb, pinv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+template <int LOGN>
+int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level, const hck_switch_key *key) {
+  constexpr int B = split_b(LOGN);
+  constexpr double N = (double)(1 << LOGN);
+  using GB = Pass<B, LOGN, false>;
+  const KsGeom kg = make_geom(ctx, level);
+  const uint32_t nq = kg.nq, ne = kg.ne, nb = kb.n, alpha = kg.alpha;
+  int rc;
+  if ((rc = ks_modup<LOGN>(ctx, kb, kg))) return rc;
+  const double digits = (double)((nq + alpha - 1) / alpha);
+  const double ext_limbs = nb * (digits * ne - nq);
+  timing_begin(ctx, "ks_contig_inner",
+               8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne),
+               N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
+  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne), kNttThreads, 0, ctx->stream>>>(
+      ws_ks(ctx), kb, key->data, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  timing_end(ctx);
+  return ks_moddown<LOGN>(ctx, kb, kg);
+}
+
+template <int LOGN>
+int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_t level,
+               const uint32_t *galois, const hck_switch_key *const *keys, uint32_t n,
+               uint64_t *const *out0, uint64_t *const *out1) {
+  constexpr double N = (double)(1 << LOGN);
+  const KsGeom kg = make_geom(ctx, level);
+  const uint32_t nq = kg.nq, ne = kg.ne, alpha = kg.alpha;
+  int rc;
+  KsBatch up;
+  up.n = 1;
+  up.galois[0] = 1;
+  up.d[0] = c1;
+  if ((rc = ks_modup<LOGN>(ctx, up, kg))) return rc;
+  // finish the forward transform of slot 0's extended digits in place
+  std::vector<std::pair<uint16_t, uint8_t>> rows;
+  for (uint32_t j = 0; j < kg.dnum; j++) {
+    const uint32_t lo = j * alpha;
+    if (lo >= nq) break;
+    const uint32_t hi = std::min(lo + alpha, nq);
+    for (uint32_t t = 0; t < ne; t++)
+      if (t < lo || t >= hi)
+        rows.push_back({(uint16_t)(kg.off_ext + j * ne + t),
+                        (uint8_t)(t < nq ? t : kg.L + (t - nq))});
+  }
+  for (size_t s = 0; s < rows.size(); s += kMaxRows) {
+    LimbMap m;
+    m.n = (uint32_t)std::min(rows.size() - s, (size_t)kMaxRows);
+    for (uint32_t r = 0; r < m.n; r++) {
+      m.row[r] = rows[s + r].first;
+      m.mod[r] = rows[s + r].second;
+    }
+    if ((rc = ntt_pass(ctx, ws_ks(ctx), m, false, false, nullptr))) return rc;
+  }
+  const double digits = (double)((nq + alpha - 1) / alpha);
+  for (uint32_t s = 0; s < n; s += kMaxBatch) {
+    KsBatch kb;
+    kb.n = std::min<uint32_t>(kMaxBatch, n - s);
+    for (uint32_t b = 0; b < kb.n; b++) {
+      kb.galois[b] = galois[s + b];
+      kb.d[b] = c1;
+      kb.out0[b] = out0[s + b];
+      kb.out1[b] = out1[s + b];
+      kb.add0[b] = c0;
+      kb.add1[b] = nullptr;
+      timing_begin(ctx, "ks_inner_gather", 8.0 * N * ne * (3 * digits + 2), 2 * digits * N * ne);
+      k_ks_inner_gather<LOGN><<<dim3((1 << LOGN) / 256, ne), 256, 0, ctx->stream>>>(
+          ws_ks(ctx), c1, galois[s + b], b, keys[s + b]->data, kg, ctx->d_mod);
+      timing_end(ctx);
+    }
+    if ((rc = ks_moddown<LOGN>(ctx, kb, kg))) return rc;
+  }
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
 }
 
 }  // namespace
 
+int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level,
+                    const hck_switch_key *key) {
+  if (kb.n == 0) return HCK_OK;
+  if (kb.n > (uint32_t)kMaxBatch) return set_error(HCK_EINVAL, "batch too large");
+  int rc = ensure_workspace(ctx, ws_words_needed(ctx));
+  if (rc) return rc;
+  if (level + 1 > (uint32_t)kMaxLimbs || (level + 1) * kb.n > (uint32_t)kMaxRows ||
+      2 * ctx->K * kb.n > (uint32_t)kMaxRows)
+    return set_error(HCK_EINVAL, "level too high for one batched launch");
+  switch (ctx->log_n) {
+    case 11: return ks_run<11>(ctx, kb, level, key);
+    case 12: return ks_run<12>(ctx, kb, level, key);
+    case 13: return ks_run<13>(ctx, kb, level, key);
+    case 14: return ks_run<14>(ctx, kb, level, key);
+    case 15: return ks_run<15>(ctx, kb, level, key);
+    case 16: return ks_run<16>(ctx, kb, level, key);
+    case 17: return ks_run<17>(ctx, kb, level, key);
+    default: return set_error(HCK_EPARAMS, "unsupported ring degree");
+  }
+}
+
 int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_t level,
                    const hck_switch_key *key, uint64_t *out0, uint64_t *out1, const uint64_t *add0,
                    const uint64_t *add1) {
+  KsBatch kb;
+  kb.n = 1;
+  kb.galois[0] = galois;
+  kb.d[0] = d;
+  kb.out0[0] = out0;
+  kb.out1[0] = out1;
+  kb.add0[0] = add0;
+  kb.add1[0] = add1;
+  return keyswitch_batch(ctx, kb, level, key);
+}
+
+int keyswitch_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_t level,
+                      const uint32_t *galois, const hck_switch_key *const *keys, uint32_t n,
+                      uint64_t *const *out0, uint64_t *const *out1) {
+  if (n == 0) return HCK_OK;
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
   if (rc) return rc;
-  if (level + 1 > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "level too high");
+  if (level + 1 > (uint32_t)kMaxLimbs || 2 * ctx->K * kMaxBatch > (uint32_t)kMaxRows)
+    return set_error(HCK_EINVAL, "level too high for one batched launch");
   switch (ctx->log_n) {
-    case 11: return ks_run<11>(ctx, d, galois, level, key, out0, out1, add0, add1);
-    case 12: return ks_run<12>(ctx, d, galois, level, key, out0, out1, add0, add1);
-    case 13: return ks_run<13>(ctx, d, galois, level, key, out0, out1, add0, add1);
-    case 14: return ks_run<14>(ctx, d, galois, level, key, out0, out1, add0, add1);
-    case 15: return ks_run<15>(ctx, d, galois, level, key, out0, out1, add0, add1);
-    case 16: return ks_run<16>(ctx, d, galois, level, key, out0, out1, add0, add1);
-    case 17: return ks_run<17>(ctx, d, galois, level, key, out0, out1, add0, add1);
+    case 11: return ks_hoisted<11>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    case 12: return ks_hoisted<12>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    case 13: return ks_hoisted<13>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    case 14: return ks_hoisted<14>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    case 15: return ks_hoisted<15>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    case 16: return ks_hoisted<16>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    case 17: return ks_hoisted<17>(ctx, c0, c1, level, galois, keys, n, out0, out1);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }

@@ -9,8 +9,8 @@ namespace {
 // One pass over the rows of `map`.  Reads from src (or dst when src is null)
 // and writes dst.  Forward strided: [0, 4q) in and out; forward contiguous:
 // [0, 4q) in, [0, q) out; inverse contiguous: [0, 2q) in and out; inverse
-// strided: [0, 2q) in, out = x N^-1 (or x sc.w + sc.add when use_scale) fully
-// reduced.
+// strided: [0, 2q) in, out = x N^-1 fully reduced, or with scale_period > 0
+// x sc.w[k] + sc.add[k], k = (row list index) mod scale_period.
 template <int LOGR, int LOGN, bool STRIDED, bool INVERSE>
 __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__ dst,
                                                           const uint64_t *__restrict__ src,
@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
                                                           const ModConst *__restrict__ mc,
                                                           const uint64_t *__restrict__ tw,
                                                           const uint64_t *__restrict__ tws,
-                                                          RowScale sc, int use_scale) {
+                                                          RowScale sc, int scale_period) {
   using G = Pass<LOGR, LOGN, STRIDED>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
@@ -58,10 +58,11 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
     G::inverse(lds, x, c, r, g, w, wp, q);
     if (STRIDED) {
       uint64_t sw, swp, sa;
-      if (use_scale) {
-        sw = sc.w[blockIdx.y];
-        swp = sc.wp[blockIdx.y];
-        sa = sc.add[blockIdx.y];
+      if (scale_period) {
+        const int k = blockIdx.y % scale_period;
+        sw = sc.w[k];
+        swp = sc.wp[k];
+        sa = sc.add[k];
       } else {
         sw = mc[mi].ninv;
         swp = mc[mi].ninv_shoup;
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
 
 template <int LOGN, bool STRIDED, bool INVERSE>
 void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
-                 const RowScale *sc) {
+                 const RowScale *sc, int period = 0) {
   constexpr int LOGR = STRIDED ? split_a(LOGN) : split_b(LOGN);
   constexpr int N = 1 << LOGN;
   using G = Pass<LOGR, LOGN, STRIDED>;
@@ -90,7 +91,8 @@ void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const Lim
   timing_begin(ctx, names[INVERSE][STRIDED], 16.0 * N * map.n, mm);
   k_ntt_pass<LOGR, LOGN, STRIDED, INVERSE><<<dim3(G::BLOCKS, map.n), kNttThreads, 0, ctx->stream>>>(
       dst, src, map, ctx->d_mod, INVERSE ? ctx->d_itw : ctx->d_tw,
-      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, sc ? *sc : dummy, sc ? 1 : 0);
+      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, sc ? *sc : dummy,
+      sc ? (period ? period : (int)map.n) : 0);
   timing_end(ctx);
 }
 
@@ -113,11 +115,11 @@ int run_inverse(hck_context *ctx, uint64_t *dst, const uint64_t *src, const Limb
 
 template <int LOGN>
 int run_one(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
-            const RowScale *sc) {
+            const RowScale *sc, int period) {
   if (!inverse && strided) launch_pass<LOGN, true, false>(ctx, buf, nullptr, map, nullptr);
   if (!inverse && !strided) launch_pass<LOGN, false, false>(ctx, buf, nullptr, map, nullptr);
   if (inverse && !strided) launch_pass<LOGN, false, true>(ctx, buf, nullptr, map, nullptr);
-  if (inverse && strided) launch_pass<LOGN, true, true>(ctx, buf, nullptr, map, sc);
+  if (inverse && strided) launch_pass<LOGN, true, true>(ctx, buf, nullptr, map, sc, period);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
 }
@@ -163,17 +165,18 @@ int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const 
 }
 
 int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
-             const RowScale *sc) {
+             const RowScale *sc, int period) {
   if (map.n == 0) return HCK_OK;
-  if (sc && map.n > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "too many scaled rows");
+  const int per = period ? period : (int)map.n;
+  if (sc && per > kMaxLimbs) return set_error(HCK_EINVAL, "too many scaled rows");
   switch (ctx->log_n) {
-    case 11: return run_one<11>(ctx, buf, map, inverse, strided, sc);
-    case 12: return run_one<12>(ctx, buf, map, inverse, strided, sc);
-    case 13: return run_one<13>(ctx, buf, map, inverse, strided, sc);
-    case 14: return run_one<14>(ctx, buf, map, inverse, strided, sc);
-    case 15: return run_one<15>(ctx, buf, map, inverse, strided, sc);
-    case 16: return run_one<16>(ctx, buf, map, inverse, strided, sc);
-    case 17: return run_one<17>(ctx, buf, map, inverse, strided, sc);
+    case 11: return run_one<11>(ctx, buf, map, inverse, strided, sc, period);
+    case 12: return run_one<12>(ctx, buf, map, inverse, strided, sc, period);
+    case 13: return run_one<13>(ctx, buf, map, inverse, strided, sc, period);
+    case 14: return run_one<14>(ctx, buf, map, inverse, strided, sc, period);
+    case 15: return run_one<15>(ctx, buf, map, inverse, strided, sc, period);
+    case 16: return run_one<16>(ctx, buf, map, inverse, strided, sc, period);
+    case 17: return run_one<17>(ctx, buf, map, inverse, strided, sc, period);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }

@@ -227,6 +227,80 @@ def test_linear_transform_matches_oracle(name, n_diag, n1):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("name", ["tiny", "vital"])
+def test_rotate_many_matches_single_rotations(name):
+    """Batched key switching (one key stream for several ciphertexts) gives the
+    oracle's residues for every member, including an output aliasing its input
+    and batches larger than one launch."""
+    p = pair(name)
+    o = p.o
+    gks, gko = p.galois([3])
+    level = o.L - 1 if name == "tiny" else o.L // 2
+    cts = [p.rand_ct(level, 1000 + i) for i in range(6)]
+    outs = [p.ctx.ciphertext() for _ in range(5)] + [cts[5][0]]   # last one in place
+    p.ctx.rotate_many([c for c, _ in cts], 3, gks, outs)
+    for (c, c_o), out in zip(cts, outs):
+        assert np.array_equal(p.export(out), o.rotate(c_o, 3, gko).polys)
+
+
+@pytest.mark.parametrize("name,d,n1", [("tiny", 16, 4), ("mix15", 6, 3)])
+def test_lt_eval_complex_dft_matches_oracle(name, d, n1):
+    """The complex DFT form d_re = C v_re - S v_im, d_im = S v_re + C v_im with
+    shared baby steps and combined giant rotations."""
+    p = pair(name)
+    o = p.o
+    level = o.L - 1
+    offs = list(range(-(d - 1), d))
+    mats = {}
+    for m, seed in (("C", 1100), ("S", 1200)):
+        res = {k: S.uniform_residues(o.qmods(level), o.n, seed + i)[0] for i, k in enumerate(offs)}
+        qs = float(o.q[level])
+        mats[m] = (p.ctx.lt_create_from_residues(res, n1, level, qs),
+                   o.lt_from_plaintexts({k: O.Plaintext(r, level, qs) for k, r in res.items()},
+                                        n1, level, qs))
+    steps = sorted(set(p.ctx.lt_required_steps(mats["C"][0])))
+    gks, gko = p.galois(steps)
+    v_re, v_re_o = p.rand_ct(level, 1300)
+    v_im, v_im_o = p.rand_ct(level, 1301)
+    terms = [("C", 0, 0, 1), ("S", 1, 0, -1), ("S", 0, 1, 1), ("C", 1, 1, 1)]
+    got = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks)
+    want = o.lt_eval([v_re_o, v_im_o], [(mats[m][1], i, j, s) for m, i, j, s in terms], gko, 2)
+    for g, w in zip(got, want):
+        assert np.array_equal(p.export(g), w.polys)
+    # hoisted baby steps
+    goth = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks,
+                         hoist=True)
+    wanth = o.lt_eval([v_re_o, v_im_o], [(mats[m][1], i, j, s) for m, i, j, s in terms], gko, 2,
+                      hoist=True)
+    for g_, w in zip(goth, wanth):
+        assert np.array_equal(p.export(g_), w.polys)
+    # outputs aliasing inputs
+    got2 = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks,
+                         outputs=[v_im, v_re])
+    assert np.array_equal(p.export(got2[0]), want[0].polys)
+    assert np.array_equal(p.export(got2[1]), want[1].polys)
+
+
+@pytest.mark.parametrize("name", ["tiny", "mix15", "vital"])
+def test_hoisted_rotations_match_oracle(name):
+    p = pair(name)
+    o = p.o
+    steps = [1, 5, -1, o.n_slots // 2 + 3, 0]
+    gks, gko = p.galois(steps)
+    for level in sorted({o.L - 1, o.alpha - 1, 0}):
+        ct, ct_o = p.rand_ct(level, 1400 + level)
+        got = p.ctx.rotate_hoisted(ct, steps, gks)
+        want = o.rotate_hoisted(ct_o, steps, gko)
+        for k, g_, w in zip(steps, got, want):
+            assert np.array_equal(p.export(g_), w.polys), f"level {level} step {k}"
+    # an output aliasing the input
+    ct, ct_o = p.rand_ct(o.L - 1, 1450)
+    outs = p.ctx.rotate_hoisted(ct, [5, 1], gks, outs=[p.ctx.ciphertext(), ct])
+    want = o.rotate_hoisted(ct_o, [5, 1], gko)
+    assert np.array_equal(p.export(outs[0]), want[0].polys)
+    assert np.array_equal(p.export(outs[1]), want[1].polys)
+
+
 def test_error_paths():
     p = pair("tiny")
     o = p.o

@@ -214,3 +214,52 @@ def test_bsgs_equals_naive_diagonal_method(tiny):
     naive = o.decode(o.decrypt(s, o.rescale(naive))).real
     assert np.max(np.abs(bsgs - naive)) < 1e-3
     assert np.max(np.abs(bsgs - np.kron(np.eye(o.n_slots // 8), m) @ x)) < 1e-3
+
+
+def test_lt_eval_complex_dft_decodes(tiny):
+    """Sums of transforms with shared baby steps and combined giant rotations
+    (the complex DFT form of Eq. dft_re) decode to the plaintext result."""
+    o, s = tiny
+    d, n1, level = 8, 4, 2
+    c = S.uniform_matrix(d, d, 1, 0.2)
+    sm = S.uniform_matrix(d, d, 2, 0.2)
+    lc = o.lt_create(block_diag_diagonals(c, o.n_slots // d), n1, level)
+    ls = o.lt_create(block_diag_diagonals(sm, o.n_slots // d), n1, level)
+    steps = set(o.lt_required_steps(lc)) | set(o.lt_required_steps(ls))
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5) for k in steps}
+    xr, xi = S.uniform_slots(o.n_slots, 3), S.uniform_slots(o.n_slots, 4)
+    cr = o.encrypt_sk(s, o.encode(xr, 2.0 ** 25, level), 10)
+    ci = o.encrypt_sk(s, o.encode(xi, 2.0 ** 25, level), 11)
+    out = o.lt_eval([cr, ci], [(lc, 0, 0, 1), (ls, 1, 0, -1), (ls, 0, 1, 1), (lc, 1, 1, 1)],
+                    gks, 2)
+    eye = np.eye(o.n_slots // d)
+    re = np.kron(eye, c) @ xr - np.kron(eye, sm) @ xi
+    im = np.kron(eye, sm) @ xr + np.kron(eye, c) @ xi
+    assert np.max(np.abs(o.decode(o.decrypt(s, o.rescale(out[0]))).real - re)) < 1e-3
+    assert np.max(np.abs(o.decode(o.decrypt(s, o.rescale(out[1]))).real - im)) < 1e-3
+
+
+def test_hoisted_rotations_decode_and_differ(tiny, tiny_ct):
+    """Hoisted rotations (one ModUp for several steps) decode to the rolled
+    slots like plain rotations, with different but valid residues."""
+    o, s = tiny
+    z, ct = tiny_ct
+    steps = [1, 2, 7, -5]
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5) for k in steps}
+    outs = o.rotate_hoisted(ct, steps, gks)
+    for k, r in zip(steps, outs):
+        assert np.max(np.abs(o.decode(o.decrypt(s, r)).real - np.roll(z, -k))) < 1e-3
+    plain = o.rotate(ct, 1, gks)
+    assert not np.array_equal(plain.polys, outs[0].polys)
+
+
+def test_keyswitch_split_equals_whole(tiny):
+    """ModUp followed by the extended-basis inner product and ModDown is the
+    key switch (same residues)."""
+    o, s = tiny
+    rlk = o.keygen_relin(s, 7)
+    for level in (2, 0):
+        d = S.uniform_residues(o.qmods(level), o.n, 31)[0]
+        u0, u1 = o.keyswitch(d, level, rlk)
+        v0, v1 = o.keyswitch_ext(o.modup(d, level), level, rlk)
+        assert np.array_equal(u0, v0) and np.array_equal(u1, v1)
