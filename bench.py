@@ -71,6 +71,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hoist", action="store_true",
                     help="plain (not hoisted) baby-step rotations")
+    ap.add_argument("--quick", action="store_true",
+                    help="timed steps only (for profiler runs): no oracle baseline, "
+                         "rotation modes or per-kernel event pass")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a plain copy of known "
+                         "size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the hot path is "
@@ -129,6 +135,13 @@ def main():
         ctx.relinearize(t1, rlk, p)
         ctx.rescale(p, p)
 
+    if args.calib_copy_mb:
+        src = torch.empty(args.calib_copy_mb << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mb} MiB done")
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -152,6 +165,12 @@ def main():
     ref = np.abs(w @ z).T ** 2
     max_err = float(np.max(np.abs(got - ref)))
     log(f"decoded |DFT|^2 max error vs plaintext: {max_err:.3e}")
+
+    if args.quick:
+        print(json.dumps({"metric": "rotations/s at N=2^16 L=24", "value": round(value, 2),
+                          "unit": "rotations/s", "ms_per_step": round(ms_per_step, 3),
+                          "quick": True, "decoded_max_abs_err": max_err}), flush=True)
+        return
 
     # rotation-only throughput: R1 dependent chain, R2 16 ciphertexts with one
     # key (batched key switching), R3 16 ciphertexts with 16 distinct keys

@@ -1168,55 +1168,114 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
     }
   }
   // accumulators (outputs may alias inputs, so results land in scratch first)
-  std::vector<hck_ciphertext *> acc(n_out), inner(n_out), giant(n_out);
+  if (n_in > (uint32_t)kLtIn || n_out > (uint32_t)kLtOut)
+    rc = rc ? rc : set_error(HCK_EINVAL, "at most 4 inputs and 4 outputs per evaluation");
+  std::vector<hck_ciphertext *> acc(n_out), giant(n_out);
   std::vector<bool> started(n_out, false);
   for (uint32_t o = 0; o < n_out; o++) {
     acc[o] = get();
-    inner[o] = get();
     giant[o] = get();
     if (!rc) rc = ensure_ct(ctx, acc[o], 2);
-    if (!rc) rc = ensure_ct(ctx, inner[o], 2);
   }
-  for (auto &kv : giant_outputs) {
-    if (rc) break;
-    const int32_t g = kv.first;
-    std::vector<bool> touched(n_out, false);
-    for (uint32_t t = 0; t < n_terms && !rc; t++) {
-      auto it = lts[t]->groups.find(g);
-      if (it == lts[t]->groups.end()) continue;
-      const uint32_t o = term_out[t];
-      const bool neg = term_sign && term_sign[t] < 0;
-      for (auto &bp : it->second) {
-        const hck_ciphertext *x = baby[{term_in[t], bp.first}];
-        const int mode = touched[o] ? (neg ? 2 : 1) : (neg ? 3 : 0);
-        for (uint32_t p = 0; p < 2 && !rc; p++)
-          rc = launch_mul_mont(ctx, inner[o]->data + p * ps, x->data + p * ps, bp.second, qm, mode);
-        touched[o] = true;
-      }
+  // distinct transforms, in order of first use, processed two per pass
+  std::vector<const hck_linear_transform *> uniq;
+  std::vector<uint32_t> term_lt(n_terms);
+  for (uint32_t t = 0; t < n_terms; t++) {
+    auto it = std::find(uniq.begin(), uniq.end(), lts[t]);
+    term_lt[t] = (uint32_t)(it - uniq.begin());
+    if (it == uniq.end()) uniq.push_back(lts[t]);
+  }
+  std::vector<int32_t> giants;
+  for (auto &kv : giant_outputs) giants.push_back(kv.first);
+  const uint32_t chunk = (n_in <= 2 && n_out <= 2) ? 4 : 2;
+  std::vector<std::vector<hck_ciphertext *>> inner(chunk, std::vector<hck_ciphertext *>(n_out));
+  for (uint32_t gi = 0; gi < chunk; gi++)
+    for (uint32_t o = 0; o < n_out; o++) {
+      inner[gi][o] = get();
+      if (!rc) rc = ensure_ct(ctx, inner[gi][o], 2);
     }
-    std::vector<const hck_ciphertext *> src;
-    std::vector<hck_ciphertext *> dst;
-    for (uint32_t o : kv.second) {
-      inner[o]->size = 2;
-      inner[o]->level = level;
-      inner[o]->scale = out_scale[o];
-      src.push_back(inner[o]);
-      dst.push_back(giant[o]);
-    }
-    if (!rc && g != 0)
-      rc = apply_galois_many(ctx, src.data(), (uint32_t)src.size(),
-                             galois_of_step(ctx, g * (int32_t)n1), gks, dst.data());
-    for (uint32_t o : kv.second) {
-      if (rc) break;
-      const hck_ciphertext *term = g != 0 ? giant[o] : inner[o];
-      for (uint32_t p = 0; p < 2 && !rc; p++) {
-        if (!started[o])
-          rc = launch_copy(ctx, acc[o]->data + p * ps, term->data + p * ps, (size_t)(level + 1) * n);
-        else
-          rc = launch_addsub(ctx, acc[o]->data + p * ps, acc[o]->data + p * ps, term->data + p * ps,
-                             qm, 0);
+  for (size_t g0 = 0; g0 < giants.size() && !rc; g0 += chunk) {
+    const uint32_t ng = (uint32_t)std::min<size_t>(chunk, giants.size() - g0);
+    // which (group, output) sums exist
+    std::vector<std::vector<bool>> live(ng, std::vector<bool>(n_out, false));
+    for (uint32_t gi = 0; gi < ng; gi++)
+      for (uint32_t o : giant_outputs[giants[g0 + gi]]) live[gi][o] = true;
+    bool first_pass = true;
+    for (size_t l0 = 0; l0 < uniq.size() && !rc; l0 += kLtLts)
+      for (uint32_t b0 = 0; b0 < n1 && !rc; b0 += kLtN1) {
+        LtInnerArgs la;
+        std::memset(&la, 0, sizeof(la));
+        la.n1 = std::min<uint32_t>(kLtN1, n1 - b0);
+        la.ng = ng;
+        la.n_in = n_in;
+        la.n_out = n_out;
+        la.ps = ps;
+        la.accumulate = first_pass ? 0 : 1;
+        for (uint32_t gi = 0; gi < ng; gi++) {
+          for (uint32_t l = 0; l < (uint32_t)kLtLts && l0 + l < uniq.size(); l++) {
+            auto it = uniq[l0 + l]->groups.find(giants[g0 + gi]);
+            if (it == uniq[l0 + l]->groups.end()) continue;
+            for (auto &bp : it->second)
+              if ((uint32_t)bp.first >= b0 && (uint32_t)bp.first < b0 + la.n1)
+                la.pt[gi][l][bp.first - b0] = bp.second;
+          }
+          for (uint32_t o = 0; o < n_out; o++)
+            if (live[gi][o]) la.inner[gi][o] = inner[gi][o]->data;
+        }
+        for (uint32_t i = 0; i < n_in; i++)
+          for (uint32_t b = 0; b < la.n1; b++) {
+            auto it = baby.find({i, (int32_t)(b0 + b)});
+            if (it != baby.end()) la.baby[i][b] = it->second->data;
+          }
+        std::vector<uint32_t> per_out(n_out, 0);
+        for (uint32_t t = 0; t < n_terms; t++) {
+          if (term_lt[t] < l0 || term_lt[t] >= l0 + kLtLts) continue;
+          if (la.n_terms == (uint32_t)kLtTerms) {
+            rc = set_error(HCK_EINVAL, "too many terms per transform pair");
+            break;
+          }
+          la.term_lt[la.n_terms] = (uint8_t)(term_lt[t] - l0);
+          la.term_in[la.n_terms] = (uint8_t)term_in[t];
+          la.term_out[la.n_terms] = (uint8_t)term_out[t];
+          la.term_neg[la.n_terms] = (term_sign && term_sign[t] < 0) ? 1 : 0;
+          la.n_terms++;
+          per_out[term_out[t]]++;
+        }
+        la.max_terms = std::max<uint32_t>(1, *std::max_element(per_out.begin(), per_out.end()));
+        if (!rc) rc = launch_lt_inner(ctx, la, level);
+        first_pass = false;
       }
-      started[o] = true;
+    // giant rotations of the group sums, batched over the outputs
+    for (uint32_t gi = 0; gi < ng && !rc; gi++) {
+      const int32_t g = giants[g0 + gi];
+      std::vector<const hck_ciphertext *> src;
+      std::vector<hck_ciphertext *> dst;
+      std::vector<uint32_t> outs;
+      for (uint32_t o = 0; o < n_out; o++) {
+        if (!live[gi][o]) continue;
+        inner[gi][o]->size = 2;
+        inner[gi][o]->level = level;
+        inner[gi][o]->scale = out_scale[o];
+        src.push_back(inner[gi][o]);
+        dst.push_back(giant[o]);
+        outs.push_back(o);
+      }
+      if (g != 0)
+        rc = apply_galois_many(ctx, src.data(), (uint32_t)src.size(),
+                               galois_of_step(ctx, g * (int32_t)n1), gks, dst.data());
+      for (size_t k = 0; k < outs.size() && !rc; k++) {
+        const uint32_t o = outs[k];
+        const hck_ciphertext *term = g != 0 ? dst[k] : src[k];
+        for (uint32_t p = 0; p < 2 && !rc; p++) {
+          if (!started[o])
+            rc = launch_copy(ctx, acc[o]->data + p * ps, term->data + p * ps,
+                             (size_t)(level + 1) * n);
+          else
+            rc = launch_addsub(ctx, acc[o]->data + p * ps, acc[o]->data + p * ps,
+                               term->data + p * ps, qm, 0);
+        }
+        started[o] = true;
+      }
     }
   }
   for (uint32_t o = 0; o < n_out && !rc; o++) {

@@ -99,6 +99,24 @@ struct hck_context {
   std::map<std::string, TimingTotal> timing_total;
 };
 
+namespace hck {
+// one launch of the fused linear-transform inner sums (lt_kernels.hip)
+constexpr int kLtG = 4;      // giant groups
+constexpr int kLtLts = 2;    // distinct transforms
+constexpr int kLtIn = 4;     // inputs
+constexpr int kLtOut = 4;    // outputs
+constexpr int kLtN1 = 32;    // baby steps
+constexpr int kLtTerms = 8;  // (transform, input, output, sign) terms
+struct LtInnerArgs {
+  uint32_t n1, ng, n_in, n_out, n_terms, max_terms, accumulate;
+  size_t ps;                                   // polynomial stride of the ciphertexts
+  const uint64_t *pt[kLtG][kLtLts][kLtN1];     // diagonal (group, transform, baby) or null
+  const uint64_t *baby[kLtIn][kLtN1];          // baby rotation (input, b) or null
+  uint64_t *inner[kLtG][kLtOut];               // inner sum (group, output) or null
+  uint8_t term_lt[kLtTerms], term_in[kLtTerms], term_out[kLtTerms], term_neg[kLtTerms];
+};
+}  // namespace hck
+
 struct hck_ciphertext {
   hck_context *ctx = nullptr;
   uint64_t *data = nullptr;  // [cap_polys][L][N], evaluation (NTT) domain, plain form
@@ -271,6 +289,8 @@ int keyswitch_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, 
 int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_t level,
                    const hck_switch_key *key, uint64_t *out0, uint64_t *out1, const uint64_t *add0,
                    const uint64_t *add1);
+// fused inner sums of the linear-transform evaluator over limbs 0..level
+int launch_lt_inner(hck_context *ctx, const LtInnerArgs &a, uint32_t level);
 // rotations of n ciphertexts (same level) by one Galois element, key-switched
 // in batches; out[i] may alias a[i]
 int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
