@@ -231,7 +231,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(hbm_frac, 4)}
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom_name)
     roof["kernel"] = dom_name
     roof["avg_launch_us"] = round(avg_ms * 1e3, 2)
     roof["share_of_kernel_time"] = round(dom["ms"] / total_ms, 3)
@@ -277,6 +277,39 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_vital_window.md")
+KERNEL_SOURCE = {"lt_inner": "lt_kernels.hip", "ks_contig_inner": "ks_fused.hip",
+                 "ks_moddown_strided": "ks_fused.hip", "ks_modup_strided": "ks_fused.hip",
+                 "ks_moddown_tail": "ks_fused.hip", "ks_inner_gather": "ks_fused.hip",
+                 "ks_intt_gather": "ks_fused.hip"}
+
+
+def source_hash(fname):
+    """sha256 prefix over a kernel's source file and the library headers."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2603_22437_amd", "csrc")
+    h = hashlib.sha256()
+    for f in [fname] + sorted(x for x in os.listdir(csrc) if x.endswith(".h")):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (counts scaled by a plain copy of known size), or None when the
+    kernel is not listed or its source changed after the counters were taken."""
+    if kernel not in KERNEL_SOURCE or not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 6 and cells[0] == kernel:
+            if cells[5] != source_hash(KERNEL_SOURCE[kernel]):
+                return None
+            return int(cells[4])
+    return None
 
 
 def cpu_baseline(prm, seconds, log):
