@@ -199,8 +199,7 @@ def main():
         ctx.rotate_many(pool, 1, gks, pool)
 
     def r3():
-        for c, k in zip(pool, distinct):
-            ctx.rotate(c, k, gks, c)
+        ctx.rotate_steps(pool[:len(distinct)], distinct, gks, pool[:len(distinct)])
 
     rotation_modes = {"R1_chain_rot_per_s": round(timed(r1, 32), 1),
                       "R2_16ct_one_key_rot_per_s": round(timed(r2, 16), 1),

@@ -215,9 +215,17 @@ int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
                const hck_galois_keys *gks, hck_ciphertext *out);
 /* Rotations of n ciphertexts (one level) by the same step: the key switches
  * run in batches that stream the Galois key once per batch.  out[i] may alias
- * a[i]; outputs must be distinct.  Errors as hck_rotate, HCK_ELEVEL. */
+ * a[i] but no other input; outputs must be distinct.  Errors as hck_rotate,
+ * HCK_ELEVEL, HCK_EINVAL. */
 int hck_rotate_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, int32_t step,
                     const hck_galois_keys *gks, hck_ciphertext *const *out);
+/* Rotations of n ciphertexts (one level), a[i] by steps[i] (section 3.2
+ * rotation, one Galois key per step): the key switches run together in
+ * batches, each member with its own key.  Residues equal hck_rotate's for
+ * every member.  out[i] may alias a[i] but no other input; outputs must be
+ * distinct.  Errors as hck_rotate_many. */
+int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int32_t *steps,
+                     uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out);
 /* Hoisted rotations of one ciphertext by n steps: c1 is extended to Q u P
  * once (ModUp) and every step applies its automorphism to the extended
  * digits before the key inner product and ModDown.  These are valid

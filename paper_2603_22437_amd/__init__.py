@@ -81,6 +81,7 @@ SIGNATURES = {
     "hck_rotate": ([_P, _P, _I32, _P, _P], _I),
     "hck_apply_galois": ([_P, _P, _U32, _P, _P], _I),
     "hck_rotate_many": ([_P, _P, _U32, _I32, _P, _P], _I),
+    "hck_rotate_steps": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_keyswitch": ([_P, _P, _P, _P], _I),
@@ -458,6 +459,17 @@ class Context:
         a = (ctypes.c_void_p * len(cts))(*[c.h for c in cts])
         o = (ctypes.c_void_p * len(outs))(*[c.h for c in outs])
         _check(capi.hck_rotate_many(self.h, a, len(cts), step, gks, o))
+        return outs
+
+    def rotate_steps(self, cts, steps, gks, outs=None):
+        """a[i] rotated by steps[i], key-switched together in batches."""
+        if len(steps) != len(cts):
+            raise ValueError("one step per ciphertext")
+        outs = [self.ciphertext() for _ in cts] if outs is None else outs
+        a = (ctypes.c_void_p * len(cts))(*[c.h for c in cts])
+        o = (ctypes.c_void_p * len(outs))(*[c.h for c in outs])
+        st = (ctypes.c_int32 * len(steps))(*steps)
+        _check(capi.hck_rotate_steps(self.h, a, st, len(cts), gks, o))
         return outs
 
     def apply_galois(self, a, element: int, gks, out=None):

@@ -987,6 +987,31 @@ static void pool_put(hck_context *ctx, hck_ciphertext *ct) {
   if (ct) ctx->ct_pool.push_back(ct);
 }
 
+int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int32_t *steps,
+                     uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
+  ENTER(ctx);
+  if ((n && (!a || !out || !steps)) || !gks) return set_error(HCK_EINVAL, "null argument");
+  std::vector<const hck_ciphertext *> src;
+  std::vector<hck_ciphertext *> dst;
+  std::vector<uint32_t> gal;
+  for (uint32_t i = 0; i < n; i++) {
+    if (!a[i] || !out[i]) return set_error(HCK_EINVAL, "null ciphertext");
+    for (uint32_t k = 0; k < n; k++)
+      if ((k < i && out[k] == out[i]) || (k != i && out[k] == a[i]))
+        return set_error(HCK_EINVAL, "outputs must be distinct and alias only their own input");
+  }
+  for (uint32_t i = 0; i < n; i++) {
+    if ((int64_t)steps[i] % (ctx->n / 2) == 0) {
+      TRY(hck_rotate(ctx, a[i], steps[i], gks, out[i]));
+      continue;
+    }
+    src.push_back(a[i]);
+    dst.push_back(out[i]);
+    gal.push_back(galois_of_step(ctx, steps[i]));
+  }
+  return apply_galois_multi(ctx, src.data(), gal.data(), (uint32_t)src.size(), gks, dst.data());
+}
+
 int hck_rotate_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, int32_t step,
                     const hck_galois_keys *gks, hck_ciphertext *const *out) {
   ENTER(ctx);
@@ -1167,16 +1192,8 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
         rc = hck_rotate_many(ctx, src.data(), (uint32_t)src.size(), b, gks, dst.data());
     }
   }
-  // accumulators (outputs may alias inputs, so results land in scratch first)
   if (n_in > (uint32_t)kLtIn || n_out > (uint32_t)kLtOut)
     rc = rc ? rc : set_error(HCK_EINVAL, "at most 4 inputs and 4 outputs per evaluation");
-  std::vector<hck_ciphertext *> acc(n_out), giant(n_out);
-  std::vector<bool> started(n_out, false);
-  for (uint32_t o = 0; o < n_out; o++) {
-    acc[o] = get();
-    giant[o] = get();
-    if (!rc) rc = ensure_ct(ctx, acc[o], 2);
-  }
   // distinct transforms, in order of first use, processed two per pass
   std::vector<const hck_linear_transform *> uniq;
   std::vector<uint32_t> term_lt(n_terms);
@@ -1187,19 +1204,18 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
   }
   std::vector<int32_t> giants;
   for (auto &kv : giant_outputs) giants.push_back(kv.first);
-  const uint32_t chunk = (n_in <= 2 && n_out <= 2) ? 4 : 2;
-  std::vector<std::vector<hck_ciphertext *>> inner(chunk, std::vector<hck_ciphertext *>(n_out));
-  for (uint32_t gi = 0; gi < chunk; gi++)
-    for (uint32_t o = 0; o < n_out; o++) {
+  // inner[gi][o]: the inner sum of giant group gi for output o (null when the
+  // output has no term in that group)
+  std::vector<std::vector<hck_ciphertext *>> inner(giants.size(),
+                                                   std::vector<hck_ciphertext *>(n_out, nullptr));
+  for (size_t gi = 0; gi < giants.size(); gi++)
+    for (uint32_t o : giant_outputs[giants[gi]]) {
       inner[gi][o] = get();
       if (!rc) rc = ensure_ct(ctx, inner[gi][o], 2);
     }
+  const uint32_t chunk = (n_in <= 2 && n_out <= 2) ? 4 : 2;
   for (size_t g0 = 0; g0 < giants.size() && !rc; g0 += chunk) {
     const uint32_t ng = (uint32_t)std::min<size_t>(chunk, giants.size() - g0);
-    // which (group, output) sums exist
-    std::vector<std::vector<bool>> live(ng, std::vector<bool>(n_out, false));
-    for (uint32_t gi = 0; gi < ng; gi++)
-      for (uint32_t o : giant_outputs[giants[g0 + gi]]) live[gi][o] = true;
     bool first_pass = true;
     for (size_t l0 = 0; l0 < uniq.size() && !rc; l0 += kLtLts)
       for (uint32_t b0 = 0; b0 < n1 && !rc; b0 += kLtN1) {
@@ -1220,7 +1236,7 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
                 la.pt[gi][l][bp.first - b0] = bp.second;
           }
           for (uint32_t o = 0; o < n_out; o++)
-            if (live[gi][o]) la.inner[gi][o] = inner[gi][o]->data;
+            if (inner[g0 + gi][o]) la.inner[gi][o] = inner[g0 + gi][o]->data;
         }
         for (uint32_t i = 0; i < n_in; i++)
           for (uint32_t b = 0; b < la.n1; b++) {
@@ -1245,43 +1261,40 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
         if (!rc) rc = launch_lt_inner(ctx, la, level);
         first_pass = false;
       }
-    // giant rotations of the group sums, batched over the outputs
-    for (uint32_t gi = 0; gi < ng && !rc; gi++) {
-      const int32_t g = giants[g0 + gi];
-      std::vector<const hck_ciphertext *> src;
-      std::vector<hck_ciphertext *> dst;
-      std::vector<uint32_t> outs;
-      for (uint32_t o = 0; o < n_out; o++) {
-        if (!live[gi][o]) continue;
-        inner[gi][o]->size = 2;
-        inner[gi][o]->level = level;
-        inner[gi][o]->scale = out_scale[o];
-        src.push_back(inner[gi][o]);
-        dst.push_back(giant[o]);
-        outs.push_back(o);
-      }
-      if (g != 0)
-        rc = apply_galois_many(ctx, src.data(), (uint32_t)src.size(),
-                               galois_of_step(ctx, g * (int32_t)n1), gks, dst.data());
-      for (size_t k = 0; k < outs.size() && !rc; k++) {
-        const uint32_t o = outs[k];
-        const hck_ciphertext *term = g != 0 ? dst[k] : src[k];
-        for (uint32_t p = 0; p < 2 && !rc; p++) {
-          if (!started[o])
-            rc = launch_copy(ctx, acc[o]->data + p * ps, term->data + p * ps,
-                             (size_t)(level + 1) * n);
-          else
-            rc = launch_addsub(ctx, acc[o]->data + p * ps, acc[o]->data + p * ps,
-                               term->data + p * ps, qm, 0);
-        }
-        started[o] = true;
-      }
-    }
   }
+  // giant rotations of every group sum, key-switched together in batches;
+  // then each output is the sum of its rotated group sums (the inputs are no
+  // longer read, so outputs may alias them)
+  std::vector<const hck_ciphertext *> src;
+  std::vector<hck_ciphertext *> dst;
+  std::vector<uint32_t> gal;
+  std::vector<std::vector<const hck_ciphertext *>> parts(n_out);
+  for (size_t gi = 0; gi < giants.size() && !rc; gi++)
+    for (uint32_t o = 0; o < n_out; o++) {
+      hck_ciphertext *u = inner[gi][o];
+      if (!u) continue;
+      u->size = 2;
+      u->level = level;
+      u->scale = out_scale[o];
+      if (giants[gi] == 0) {
+        parts[o].push_back(u);
+        continue;
+      }
+      hck_ciphertext *r = get();
+      src.push_back(u);
+      dst.push_back(r);
+      gal.push_back(galois_of_step(ctx, giants[gi] * (int32_t)n1));
+      parts[o].push_back(r);
+    }
+  if (!rc) rc = apply_galois_multi(ctx, src.data(), gal.data(), (uint32_t)src.size(), gks, dst.data());
   for (uint32_t o = 0; o < n_out && !rc; o++) {
     rc = ensure_ct(ctx, out[o], 2);
-    for (uint32_t p = 0; p < 2 && !rc; p++)
-      rc = launch_copy(ctx, out[o]->data + p * ps, acc[o]->data + p * ps, (size_t)(level + 1) * n);
+    std::vector<const uint64_t *> polys;
+    for (uint32_t p = 0; p < 2 && !rc; p++) {
+      polys.clear();
+      for (const hck_ciphertext *c : parts[o]) polys.push_back(c->data + p * ps);
+      rc = launch_sum_many(ctx, out[o]->data + p * ps, polys.data(), (uint32_t)polys.size(), qm);
+    }
     if (!rc) {
       out[o]->size = 2;
       out[o]->level = level;

@@ -13,7 +13,7 @@ size_t ws_ks_rows(const hck_context *ctx) {
   return L + ctx->dnum * LK + 2 * LK + 2 * L;
 }
 
-// [kMaxBatch key-switch slots][kMaxBatch x L rows: automorphism sources]
+// [kMaxBatch key-switch slots][kMaxBatch x L rows: copies of aliased inputs]
 // [3 (L+K) rows: general temporary]
 size_t ws_words_needed(const hck_context *ctx) {
   const size_t n = ctx->n, L = ctx->L, LK = ctx->L + ctx->K;
@@ -45,25 +45,31 @@ int ntt_forward_rows(hck_context *ctx, uint64_t *buf,
   return HCK_OK;
 }
 
-int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
-                      const hck_galois_keys *gks, hck_ciphertext *const *out) {
-  auto it = gks->keys.find(g);
-  if (it == gks->keys.end())
-    return set_error(HCK_ENOKEY, "no Galois key for element " + std::to_string(g));
+int apply_galois_multi(hck_context *ctx, const hck_ciphertext *const *a, const uint32_t *g,
+                       uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
   if (n == 0) return HCK_OK;
+  std::vector<const hck_switch_key *> keys(n);
   const uint32_t level = a[0]->level;
   for (uint32_t i = 0; i < n; i++) {
+    auto it = gks->keys.find(g[i]);
+    if (it == gks->keys.end())
+      return set_error(HCK_ENOKEY, "no Galois key for element " + std::to_string(g[i]));
+    keys[i] = it->second;
     if (a[i]->size != 2) return set_error(HCK_EINVAL, "rotation needs a 2-part ciphertext");
     if (a[i]->level != level) return set_error(HCK_ELEVEL, "batched rotations need one level");
-    for (uint32_t k = 0; k < i; k++)
-      if (out[k] == out[i]) return set_error(HCK_EINVAL, "batched outputs must be distinct");
+    for (uint32_t k = 0; k < n; k++) {
+      if (k < i && out[k] == out[i]) return set_error(HCK_EINVAL, "batched outputs must be distinct");
+      if (k != i && out[k] == a[i])
+        return set_error(HCK_EINVAL, "a batched output may alias only its own input");
+    }
   }
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
   if (rc) return rc;
   const size_t ps = (size_t)ctx->L * ctx->n;
-  for (uint32_t s = 0; s < n; s += kMaxBatch) {
+  const uint32_t limit = ks_batch_limit(ctx, level);
+  for (uint32_t s = 0; s < n; s += limit) {
     KsBatch kb;
-    kb.n = std::min<uint32_t>(kMaxBatch, n - s);
+    kb.n = std::min<uint32_t>(limit, n - s);
     std::vector<double> scales(kb.n);
     for (uint32_t b = 0; b < kb.n; b++) {
       const hck_ciphertext *x = a[s + b];
@@ -73,23 +79,22 @@ int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t
       // launches before the final one, but c0 is gathered through phi_g by the
       // final launch while it writes the outputs: an output that aliases this
       // input gets a copy of c0 to read instead
-      bool alias = false;
-      for (uint32_t k = 0; k < kb.n; k++) alias = alias || out[s + k] == x;
       if ((rc = ensure_ct(ctx, y, 2))) return rc;
       const uint64_t *c0 = x->data, *c1 = x->data + ps;
-      if (alias) {
+      if (y == x) {
         uint64_t *copy = ws_rot(ctx) + (size_t)b * ps;
         if ((rc = launch_copy(ctx, copy, x->data, (size_t)(level + 1) * ctx->n))) return rc;
         c0 = copy;
       }
-      kb.galois[b] = g;
+      kb.key[b] = keys[s + b]->data;
+      kb.galois[b] = g[s + b];
       kb.d[b] = c1;
       kb.out0[b] = y->data;
       kb.out1[b] = y->data + ps;
       kb.add0[b] = c0;
       kb.add1[b] = nullptr;
     }
-    if ((rc = keyswitch_batch(ctx, kb, level, it->second))) return rc;
+    if ((rc = keyswitch_batch(ctx, kb, level))) return rc;
     for (uint32_t b = 0; b < kb.n; b++) {
       out[s + b]->size = 2;
       out[s + b]->level = level;
@@ -97,6 +102,12 @@ int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t
     }
   }
   return HCK_OK;
+}
+
+int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
+                      const hck_galois_keys *gks, hck_ciphertext *const *out) {
+  std::vector<uint32_t> gs(n, g);
+  return apply_galois_multi(ctx, a, gs.data(), n, gks, out);
 }
 
 int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,

@@ -14,8 +14,8 @@
 namespace hck {
 
 constexpr int kMaxLimbs = HCK_MAX_LIMBS;
-constexpr int kMaxRows = 192;  // rows of one batched launch (e.g. every extended digit)
-constexpr int kMaxBatch = 4;   // ciphertexts key-switched together with one key
+constexpr int kMaxRows = 256;  // rows of one batched launch (e.g. every extended digit)
+constexpr int kMaxBatch = 8;   // key switches run together in one sequence of launches
 
 // Per-modulus constants, indexed by the modulus index of the full chain
 // (0..L-1: q chain, L..L+K-1: special primes).
@@ -206,6 +206,10 @@ int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, 
 
 int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t words);
 // out[r] = a[r] (+|-) b[r] for rows in map; op 0 add, 1 sub, 2 negate a
+// out = sum of in[0..n_in) mod q over the rows of map (out may be one of the inputs)
+constexpr int kSumInputs = 32;
+int launch_sum_many(hck_context *ctx, uint64_t *out, const uint64_t *const *in, uint32_t n_in,
+                    const LimbMap &map);
 int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
                   const LimbMap &map, int op);
 // out = [+-] REDC(a * bm) [+ out] (bm in Montgomery form): mode 0 set,
@@ -259,16 +263,18 @@ void decode_residues(uint32_t log_n, const uint64_t *res, const uint64_t *mods, 
 // workspace regions (words from ctx->ws)
 size_t ws_words_needed(const hck_context *ctx);
 uint64_t *ws_ks(hck_context *ctx);    // key-switch internals
-uint64_t *ws_rot(hck_context *ctx);   // [2][L][N]: automorphism output
+uint64_t *ws_rot(hck_context *ctx);   // [kMaxBatch][L][N]: copies of aliased inputs
 uint64_t *ws_tmp(hck_context *ctx);   // [3][L+K][N]: general temporary
-// Up to kMaxBatch key switches with one key, at one level, in one sequence
-// of launches (the key is streamed once per batch):
+// Up to kMaxBatch key switches at one level in one sequence of launches,
+// slot b with its own switching key key[b] ([dnum][2][L+K][N], Montgomery
+// form; slots that share a key read it through the cache):
 // (out0[b], out1[b]) = KeySwitch(phi_g(d[b])) + (phi_g(add0[b]), phi_g(add1[b])).
 // d and the addends are [level+1][N] in evaluation form; g = 1 for no
 // automorphism; null addends are skipped.  out rows must not overlap d; with
 // g != 1 they must not overlap the addends.
 struct KsBatch {
   uint32_t n;
+  const uint64_t *key[kMaxBatch];
   uint32_t galois[kMaxBatch];
   const uint64_t *d[kMaxBatch];
   uint64_t *out0[kMaxBatch];
@@ -276,8 +282,9 @@ struct KsBatch {
   const uint64_t *add0[kMaxBatch];
   const uint64_t *add1[kMaxBatch];
 };
-int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level,
-                    const hck_switch_key *key);
+int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level);
+// largest batch keyswitch_batch accepts at this level (row limits of one launch)
+uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level);
 // Hoisted rotations of one ciphertext (c0, c1) by n Galois elements: ModUp of
 // c1 once, then per element the automorphism of the extended digits, the key
 // inner product and ModDown (batched over the elements), plus phi_g(c0).
@@ -291,8 +298,12 @@ int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_
                    const uint64_t *add1);
 // fused inner sums of the linear-transform evaluator over limbs 0..level
 int launch_lt_inner(hck_context *ctx, const LtInnerArgs &a, uint32_t level);
-// rotations of n ciphertexts (same level) by one Galois element, key-switched
-// in batches; out[i] may alias a[i]
+// automorphisms a[i] -> phi_{g[i]}(a[i]) of n ciphertexts (same level), each
+// key-switched with its Galois key, in batches of kMaxBatch; outputs are
+// distinct and out[i] may alias a[i] (no other input)
+int apply_galois_multi(hck_context *ctx, const hck_ciphertext *const *a, const uint32_t *g,
+                       uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out);
+// the same with one Galois element for all
 int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *const *out);
 size_t ws_ks_rows(const hck_context *ctx);   // rows of one batch slot of ws_ks

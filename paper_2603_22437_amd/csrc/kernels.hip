@@ -37,6 +37,22 @@ __global__ __launch_bounds__(kThreads) void k_addsub(uint64_t *out, const uint64
   out[off] = r;
 }
 
+// out = sum of n inputs mod q, row by row (rows of `map`)
+struct SumArgs {
+  const uint64_t *in[kSumInputs];
+  uint32_t n;
+};
+
+__global__ __launch_bounds__(kThreads) void k_sum_many(uint64_t *out, SumArgs sa, LimbMap map,
+                                                       const ModConst *__restrict__ mc, int n) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const size_t off = (size_t)map.row[blockIdx.y] * n + i;
+  const uint64_t q = mc[map.mod[blockIdx.y]].q;
+  uint64_t acc = sa.in[0][off];
+  for (uint32_t k = 1; k < sa.n; k++) acc = add_mod(acc, sa.in[k][off], q);
+  out[off] = acc;
+}
+
 // out = [+-] REDC(a * bm) [+ out]: mode 0 set, 1 add to out, 2 subtract from
 // out, 3 set negated (bm in Montgomery form, so REDC gives a * b mod q)
 __global__ __launch_bounds__(kThreads) void k_mul_mont(uint64_t *out, const uint64_t *a,
@@ -182,6 +198,25 @@ int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint
                                                                  ctx->n, op);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
+int launch_sum_many(hck_context *ctx, uint64_t *out, const uint64_t *const *in, uint32_t n_in,
+                    const LimbMap &map) {
+  if (n_in == 0) return set_error(HCK_EINVAL, "empty sum");
+  if (map.n == 0) return HCK_OK;
+  // chunks of kSumInputs; later chunks add to the partial sum in `out`
+  for (uint32_t s = 0; s < n_in;) {
+    SumArgs sa;
+    sa.n = 0;
+    if (s > 0) sa.in[sa.n++] = out;
+    while (s < n_in && sa.n < (uint32_t)kSumInputs) sa.in[sa.n++] = in[s++];
+    timing_begin(ctx, "sum_many", 8.0 * ctx->n * map.n * (sa.n + 1));
+    k_sum_many<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, sa, map, ctx->d_mod,
+                                                                      ctx->n);
+    timing_end(ctx);
+    HCK_HIP(ctx, hipGetLastError());
+  }
   return HCK_OK;
 }
 

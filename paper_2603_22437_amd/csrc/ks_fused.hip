@@ -12,9 +12,8 @@
 //       forward strided pass -> ext[j][t]
 //   K4  per extended limb t: forward contiguous pass of every digit's ext
 //       (or phi_g(d) itself on the digit's own limbs), then
-//       acc_{0,1}[t] = sum_j d~_j[t] swk_j[t] (keys in Montgomery form); the
-//       workgroup loops over the batch, so each key tile is fetched from HBM
-//       once per batch and re-read from cache
+//       acc_{0,1}[t] = sum_j d~_j[t] swk_j[t] (keys in Montgomery form); slots
+//       that share a key re-read its tiles from cache
 //   K5  inverse passes of acc's P limbs, times N^-1 (P/p_k)^-1, plus
 //       ((P-1)/2) (P/p_k)^-1 (the rounding term of ModDown)
 //   K6  ModDown conversion P -> q_i (minus (P-1)/2) at load time, then the
@@ -24,6 +23,8 @@
 //
 // Workspace: batch slot b occupies rows [b R, (b+1) R) of ws_ks (R rows of N
 // words): y [L] | ext [dnum][L+K] | acc [2][L+K] | conv [2][L].
+#include <algorithm>
+
 #include "ntt_core.h"
 
 namespace hck {
@@ -105,60 +106,59 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
-    uint64_t *__restrict__ ws, KsBatch kb, const uint64_t *__restrict__ key,
-    KsGeom kg, const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
-    const uint64_t *__restrict__ tws) {
+    uint64_t *__restrict__ ws, KsBatch kb, KsGeom kg, const ModConst *__restrict__ mc,
+    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
   const uint32_t t = blockIdx.y;
+  const uint32_t b = blockIdx.z;
   const uint32_t mi = t < kg.nq ? t : kg.L + (t - kg.nq);
   const ModConst m = mc[mi];
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   const size_t krow = (size_t)kg.nm * G::N;
-  for (uint32_t b = 0; b < kb.n; b++) {
-    uint64_t *slot = ws + (size_t)b * kg.slot_rows * G::N;
-    const uint64_t *d = kb.d[b];
-    const uint32_t galois = kb.galois[b];
-    uint64_t a0[P], a1[P], x[P];
+  uint64_t *slot = ws + (size_t)b * kg.slot_rows * G::N;
+  const uint64_t *d = kb.d[b];
+  const uint64_t *key = kb.key[b];
+  const uint32_t galois = kb.galois[b];
+  uint64_t a0[P], a1[P], x[P];
 #pragma unroll
-    for (int i = 0; i < P; i++) a0[i] = a1[i] = 0;
-    for (uint32_t j = 0; j < kg.dnum; j++) {
-      const uint32_t lo = j * kg.alpha;
-      if (lo >= kg.nq) break;
-      const uint32_t hi = min(lo + kg.alpha, kg.nq);
-      if (t >= lo && t < hi) {
+  for (int i = 0; i < P; i++) a0[i] = a1[i] = 0;
+  for (uint32_t j = 0; j < kg.dnum; j++) {
+    const uint32_t lo = j * kg.alpha;
+    if (lo >= kg.nq) break;
+    const uint32_t hi = min(lo + kg.alpha, kg.nq);
+    if (t >= lo && t < hi) {
 #pragma unroll
-        for (int i = 0; i < P; i++)
-          x[i] = d[(size_t)t * G::N +
-                   galois_src((uint32_t)G::gaddr(g, G::ipoint(r, i)), galois, LOGN)];
-      } else {
-        const uint64_t *e = slot + ((size_t)kg.off_ext + j * kg.ne + t) * G::N;
+      for (int i = 0; i < P; i++)
+        x[i] = d[(size_t)t * G::N +
+                 galois_src((uint32_t)G::gaddr(g, G::ipoint(r, i)), galois, LOGN)];
+    } else {
+      const uint64_t *e = slot + ((size_t)kg.off_ext + j * kg.ne + t) * G::N;
 #pragma unroll
-        for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
-        G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+      for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
+      G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
 #pragma unroll
-        for (int v = 0; v < P; v++) x[v] = reduce4(x[v], m.q);
-        G::to_interleaved(lds, x, c, r);
-      }
-      const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * G::N;
-      const uint64_t *kap = kbp + krow;
-#pragma unroll
-      for (int i = 0; i < P; i++) {
-        const size_t pos = G::gaddr(g, G::ipoint(r, i));
-        a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kbp[pos]), m.q, m.qinv), m.q);
-        a1[i] = add_mod(a1[i], redc(mul_wide(x[i], kap[pos]), m.q, m.qinv), m.q);
-      }
+      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], m.q);
+      G::to_interleaved(lds, x, c, r);
     }
-    uint64_t *o0 = slot + ((size_t)kg.off_acc + t) * G::N;
-    uint64_t *o1 = slot + ((size_t)kg.off_acc + kg.ne + t) * G::N;
+    const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * G::N;
+    const uint64_t *kap = kbp + krow;
 #pragma unroll
     for (int i = 0; i < P; i++) {
       const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      o0[pos] = a0[i];
-      o1[pos] = a1[i];
+      a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kbp[pos]), m.q, m.qinv), m.q);
+      a1[i] = add_mod(a1[i], redc(mul_wide(x[i], kap[pos]), m.q, m.qinv), m.q);
     }
+  }
+  uint64_t *o0 = slot + ((size_t)kg.off_acc + t) * G::N;
+  uint64_t *o1 = slot + ((size_t)kg.off_acc + kg.ne + t) * G::N;
+#pragma unroll
+  for (int i = 0; i < P; i++) {
+    const size_t pos = G::gaddr(g, G::ipoint(r, i));
+    o0[pos] = a0[i];
+    o1[pos] = a1[i];
   }
 }
 
@@ -407,7 +407,7 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
 }
 
 template <int LOGN>
-int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level, const hck_switch_key *key) {
+int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level) {
   constexpr int B = split_b(LOGN);
   constexpr double N = (double)(1 << LOGN);
   using GB = Pass<B, LOGN, false>;
@@ -417,11 +417,17 @@ int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level, const hck_switch
   if ((rc = ks_modup<LOGN>(ctx, kb, kg))) return rc;
   const double digits = (double)((nq + alpha - 1) / alpha);
   const double ext_limbs = nb * (digits * ne - nq);
+  double keys = 0;  // distinct keys in the batch
+  for (uint32_t b = 0; b < nb; b++) {
+    bool seen = false;
+    for (uint32_t k = 0; k < b; k++) seen = seen || kb.key[k] == kb.key[b];
+    keys += seen ? 0 : 1;
+  }
   timing_begin(ctx, "ks_contig_inner",
-               8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne),
+               8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * keys),
                N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
-  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne), kNttThreads, 0, ctx->stream>>>(
-      ws_ks(ctx), kb, key->data, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne, nb), kNttThreads, 0, ctx->stream>>>(
+      ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
   return ks_moddown<LOGN>(ctx, kb, kg);
 }
@@ -460,10 +466,12 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
     if ((rc = ntt_pass(ctx, ws_ks(ctx), m, false, false, nullptr))) return rc;
   }
   const double digits = (double)((nq + alpha - 1) / alpha);
-  for (uint32_t s = 0; s < n; s += kMaxBatch) {
+  const uint32_t limit = ks_batch_limit(ctx, level);
+  for (uint32_t s = 0; s < n; s += limit) {
     KsBatch kb;
-    kb.n = std::min<uint32_t>(kMaxBatch, n - s);
+    kb.n = std::min<uint32_t>(limit, n - s);
     for (uint32_t b = 0; b < kb.n; b++) {
+      kb.key[b] = keys[s + b]->data;
       kb.galois[b] = galois[s + b];
       kb.d[b] = c1;
       kb.out0[b] = out0[s + b];
@@ -483,8 +491,12 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
 
 }  // namespace
 
-int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level,
-                    const hck_switch_key *key) {
+uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level) {
+  const uint32_t by_rows = (uint32_t)kMaxRows / std::max<uint32_t>(level + 1, 2 * ctx->K);
+  return std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)kMaxBatch, by_rows));
+}
+
+int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level) {
   if (kb.n == 0) return HCK_OK;
   if (kb.n > (uint32_t)kMaxBatch) return set_error(HCK_EINVAL, "batch too large");
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
@@ -493,13 +505,13 @@ int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level,
       2 * ctx->K * kb.n > (uint32_t)kMaxRows)
     return set_error(HCK_EINVAL, "level too high for one batched launch");
   switch (ctx->log_n) {
-    case 11: return ks_run<11>(ctx, kb, level, key);
-    case 12: return ks_run<12>(ctx, kb, level, key);
-    case 13: return ks_run<13>(ctx, kb, level, key);
-    case 14: return ks_run<14>(ctx, kb, level, key);
-    case 15: return ks_run<15>(ctx, kb, level, key);
-    case 16: return ks_run<16>(ctx, kb, level, key);
-    case 17: return ks_run<17>(ctx, kb, level, key);
+    case 11: return ks_run<11>(ctx, kb, level);
+    case 12: return ks_run<12>(ctx, kb, level);
+    case 13: return ks_run<13>(ctx, kb, level);
+    case 14: return ks_run<14>(ctx, kb, level);
+    case 15: return ks_run<15>(ctx, kb, level);
+    case 16: return ks_run<16>(ctx, kb, level);
+    case 17: return ks_run<17>(ctx, kb, level);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }
@@ -509,13 +521,14 @@ int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_
                    const uint64_t *add1) {
   KsBatch kb;
   kb.n = 1;
+  kb.key[0] = key->data;
   kb.galois[0] = galois;
   kb.d[0] = d;
   kb.out0[0] = out0;
   kb.out1[0] = out1;
   kb.add0[0] = add0;
   kb.add1[0] = add1;
-  return keyswitch_batch(ctx, kb, level, key);
+  return keyswitch_batch(ctx, kb, level);
 }
 
 int keyswitch_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_t level,
@@ -524,7 +537,7 @@ int keyswitch_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, 
   if (n == 0) return HCK_OK;
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
   if (rc) return rc;
-  if (level + 1 > (uint32_t)kMaxLimbs || 2 * ctx->K * kMaxBatch > (uint32_t)kMaxRows)
+  if (level + 1 > (uint32_t)kMaxLimbs || 2 * ctx->K > (uint32_t)kMaxRows)
     return set_error(HCK_EINVAL, "level too high for one batched launch");
   switch (ctx->log_n) {
     case 11: return ks_hoisted<11>(ctx, c0, c1, level, galois, keys, n, out0, out1);

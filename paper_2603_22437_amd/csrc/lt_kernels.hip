@@ -8,9 +8,9 @@
 // in evaluation + Montgomery form).  A thread owns one coefficient of one
 // limb and walks the baby steps once: it loads every input's baby rotation
 // once per pass, each cached diagonal exactly once, and keeps the sums of G
-// giant groups x O outputs x 2 polynomials in 128-bit registers, reducing
-// them with one Montgomery REDC per flush.  A negative sign is folded into
-// the ciphertext operand (q - x).
+// giant groups x O outputs x 2 polynomials in 128-bit registers, reduced by
+// one Montgomery REDC at the end (and at flushes, see below).  A negative
+// sign is folded into the ciphertext operand (q - x).
 #include "internal.h"
 
 namespace hck {
@@ -26,11 +26,11 @@ __global__ __launch_bounds__(256) void k_lt_inner(LtInnerArgs a, const ModConst 
   const size_t off = (size_t)limb * n + i;
   // products of values below q accumulate safely while their count stays
   // below 2^64 / q (the REDC input bound); each baby step adds up to
-  // max_terms products to one sum
+  // max_terms products to one sum.  A flush reduces a sum to r in [0, q) and
+  // restarts it from r 2^64 mod q, which REDC maps back to r.
   const uint64_t per_flush = ~0ull / m.q - 1;
   const uint32_t flush_b = (uint32_t)max<uint64_t>(1, per_flush / a.max_terms);
   u128 acc[G][O][2];
-  uint64_t red[G][O][2];
 #pragma unroll
   for (int g = 0; g < G; g++)
 #pragma unroll
@@ -38,9 +38,8 @@ __global__ __launch_bounds__(256) void k_lt_inner(LtInnerArgs a, const ModConst 
 #pragma unroll
       for (int p = 0; p < 2; p++) {
         acc[g][o][p].lo = acc[g][o][p].hi = 0;
-        red[g][o][p] = 0;
         if (a.accumulate && g < (int)a.ng && o < (int)a.n_out && a.inner[g][o])
-          red[g][o][p] = a.inner[g][o][off + p * a.ps];
+          acc[g][o][p].lo = shoup(a.inner[g][o][off + p * a.ps], m.r64, m.r64_shoup, m.q);
       }
   uint32_t since = 0;
   for (uint32_t b = 0; b < a.n1; b++) {
@@ -80,7 +79,7 @@ __global__ __launch_bounds__(256) void k_lt_inner(LtInnerArgs a, const ModConst 
         }
       }
     }
-    if (++since == flush_b || b + 1 == a.n1) {
+    if (++since == flush_b && b + 1 < a.n1) {
       since = 0;
 #pragma unroll
       for (int g = 0; g < G; g++)
@@ -88,8 +87,8 @@ __global__ __launch_bounds__(256) void k_lt_inner(LtInnerArgs a, const ModConst 
         for (int o = 0; o < O; o++)
 #pragma unroll
           for (int p = 0; p < 2; p++) {
-            red[g][o][p] = add_mod(red[g][o][p], redc(acc[g][o][p], m.q, m.qinv), m.q);
-            acc[g][o][p].lo = acc[g][o][p].hi = 0;
+            acc[g][o][p].lo = shoup(redc(acc[g][o][p], m.q, m.qinv), m.r64, m.r64_shoup, m.q);
+            acc[g][o][p].hi = 0;
           }
     }
   }
@@ -98,8 +97,8 @@ __global__ __launch_bounds__(256) void k_lt_inner(LtInnerArgs a, const ModConst 
 #pragma unroll
     for (int o = 0; o < O; o++)
       if (g < (int)a.ng && o < (int)a.n_out && a.inner[g][o]) {
-        a.inner[g][o][off] = red[g][o][0];
-        a.inner[g][o][off + a.ps] = red[g][o][1];
+        a.inner[g][o][off] = redc(acc[g][o][0], m.q, m.qinv);
+        a.inner[g][o][off + a.ps] = redc(acc[g][o][1], m.q, m.qinv);
       }
 }
 

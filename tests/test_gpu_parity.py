@@ -231,16 +231,33 @@ def test_linear_transform_matches_oracle(name, n_diag, n1):
 def test_rotate_many_matches_single_rotations(name):
     """Batched key switching (one key stream for several ciphertexts) gives the
     oracle's residues for every member, including an output aliasing its input
-    and batches larger than one launch."""
+    and more members than one batch holds."""
     p = pair(name)
     o = p.o
     gks, gko = p.galois([3])
     level = o.L - 1 if name == "tiny" else o.L // 2
-    cts = [p.rand_ct(level, 1000 + i) for i in range(6)]
-    outs = [p.ctx.ciphertext() for _ in range(5)] + [cts[5][0]]   # last one in place
+    cts = [p.rand_ct(level, 1000 + i) for i in range(10)]
+    outs = [p.ctx.ciphertext() for _ in range(9)] + [cts[9][0]]   # last one in place
     p.ctx.rotate_many([c for c, _ in cts], 3, gks, outs)
     for (c, c_o), out in zip(cts, outs):
         assert np.array_equal(p.export(out), o.rotate(c_o, 3, gko).polys)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_rotate_steps_matches_single_rotations(name):
+    """Rotations by different steps switched together (each batch member with
+    its own key) give the oracle's residues, including a zero step (a copy), an
+    in-place member and more members than one batch holds."""
+    p = pair(name)
+    o = p.o
+    steps = [1, 3, 0, 5, 1, -2, 3, 5, 1, 7] if name != "vital" else [1, 3, 0, 1, 3, 1, 3, 1, 3, 1]
+    gks, gko = p.galois(steps)
+    level = o.L - 1 if name != "mix15" else o.L // 2
+    cts = [p.rand_ct(level, 1100 + i) for i in range(len(steps))]
+    outs = [p.ctx.ciphertext() for _ in range(len(steps) - 1)] + [cts[-1][0]]
+    p.ctx.rotate_steps([c for c, _ in cts], steps, gks, outs)
+    for (c, c_o), k, out in zip(cts, steps, outs):
+        assert np.array_equal(p.export(out), o.rotate(c_o, k, gko).polys), k
 
 
 @pytest.mark.parametrize("name,d,n1", [("tiny", 16, 4), ("mix15", 6, 3)])
