@@ -73,6 +73,7 @@ def _load():
         "ock_keyswitch": ([P, I, P, P, I, P, I, I, I, P, P], None),
         "ock_modup": ([P, I, P, I, P, I, I, I, P], I),
         "ock_keyswitch_ext": ([P, I, I, P, P, I, P, I, I, P, P], None),
+        "ock_ks_inner": ([P, I, I, P, P, I, P, I, I, P, P], None),
         "ock_rescale": ([P, P, P, I, I], None),
         "ock_num_threads": ([], ctypes.c_int),
     }
@@ -564,6 +565,22 @@ class Oracle:
                                   self.L, _ptr(p), self.K, self.log_n, _ptr(out0), _ptr(out1))
         return out0, out1
 
+    def ks_inner(self, ext: np.ndarray, level: int, swk: np.ndarray):
+        """Key inner product of extended digits in Q_level u P, without
+        ModDown: (acc0, acc1), each [level+1+K][N] (q limbs, then P limbs)."""
+        ne = level + 1 + self.K
+        acc0 = np.empty((ne, self.n), dtype=np.uint64)
+        acc1 = np.empty_like(acc0)
+        q, p = _u64(self.q), _u64(self.p)
+        ext = _u64(ext)
+        _load().ock_ks_inner(_ptr(ext), ext.shape[0], level, _ptr(_u64(swk)), _ptr(q), self.L,
+                             _ptr(p), self.K, self.log_n, _ptr(acc0), _ptr(acc1))
+        return acc0, acc1
+
+    def moddown(self, acc: np.ndarray, level: int) -> np.ndarray:
+        """ModDown (with rounding, A15) of a [level+1+K][N] polynomial to Q_level."""
+        return moddown(acc, self.qmods(level), self.p, self.log_n)
+
     def rotate_hoisted(self, c: Ciphertext, steps: list, gks: dict) -> list:
         """Rotations of one ciphertext by several steps sharing one ModUp
         (reading A13): the extended digits of c1 are computed once; for each
@@ -657,13 +674,15 @@ class Oracle:
         return sorted(steps)
 
     def lt_eval(self, inputs: list, terms: list, gks: dict, n_out: int,
-                hoist: bool = False) -> list:
+                hoist: bool = False, hoist_giant: bool = False) -> list:
         """Sums of transforms over shared inputs (the complex DFT of Eq. dft_re
         is C v_re - S v_im and S v_re + C v_im): terms are (transform, input
         index, output index, sign).  For every output and giant index g the
         inner sum runs over the terms' baby-step products, and is rotated once
         by g n1: out_o = sum_g Rot(sum_t sign_t sum_b pt_{t,g,b} Rot(x_t, b), g n1).
-        With hoist the baby rotations of an input are hoisted rotations."""
+        With hoist the baby rotations of an input are hoisted rotations.  With
+        hoist_giant an output's giant rotations share one ModDown: their key
+        inner products are summed in Q u P and reduced once (giant_sum)."""
         n1 = terms[0][0].n1
         need = {}
         for lt, i, _o, _s in terms:
@@ -682,7 +701,7 @@ class Oracle:
                 for b in bs:
                     babies[(i, b)] = inputs[i] if b == 0 else self.rotate(inputs[i], b, gks)
         giants = sorted({g for lt, _i, _o, _s in terms for g in lt.groups})
-        out = [None] * n_out
+        parts = [[] for _ in range(n_out)]   # (g, inner sum) per output
         for g in giants:
             inner = [None] * n_out
             for lt, i, o, sign in terms:
@@ -694,11 +713,51 @@ class Oracle:
                     else:
                         inner[o] = self.add(inner[o], term) if sign > 0 else self.sub(inner[o], term)
             for o in range(n_out):
-                if inner[o] is None:
-                    continue
-                r = inner[o] if g == 0 else self.rotate(inner[o], g * n1, gks)
-                out[o] = r if out[o] is None else self.add(out[o], r)
+                if inner[o] is not None:
+                    parts[o].append((g * n1, inner[o]))
+        out = []
+        for o in range(n_out):
+            if hoist_giant:
+                out.append(self.giant_sum(parts[o], gks))
+                continue
+            acc = None
+            for step, u in parts[o]:
+                r = u if step == 0 else self.rotate(u, step, gks)
+                acc = r if acc is None else self.add(acc, r)
+            out.append(acc)
         return out
+
+    def giant_sum(self, parts: list, gks: dict) -> Ciphertext:
+        """sum_k Rot(u_k, step_k) with one ModDown for all the key switches
+        (the giant-step half of double hoisting): for each rotated part the
+        automorphism phi_g is applied to u_k, phi_g(c1) is extended (ModUp)
+        and multiplied by gk_g in Q u P; the products of all parts are added
+        in Q u P and ModDown runs once per polynomial; the phi_g(c0) (and the
+        unrotated parts) are added in Q.  Valid rotations whose residues
+        differ from a sum of rotate() results."""
+        level, scale = parts[0][1].level, parts[0][1].scale
+        mods = self.qmods(level)
+        ne_mods = mods + self.p
+        c0 = np.zeros((level + 1, self.n), dtype=np.uint64)
+        c1 = np.zeros_like(c0)
+        pq0 = pq1 = None
+        for step, u in parts:
+            if step % self.n_slots == 0:
+                c0 = poly_add(c0, u.polys[0], self.log_n, mods)
+                c1 = poly_add(c1, u.polys[1], self.log_n, mods)
+                continue
+            g = self.galois_element(step)
+            if g not in gks:
+                raise KeyError(f"no Galois key for element {g}")
+            c0 = poly_add(c0, automorphism(u.polys[0], g, self.log_n, mods), self.log_n, mods)
+            ext = self.modup(automorphism(u.polys[1], g, self.log_n, mods), level)
+            a0, a1 = self.ks_inner(ext, level, gks[g])
+            pq0 = a0 if pq0 is None else poly_add(pq0, a0, self.log_n, ne_mods)
+            pq1 = a1 if pq1 is None else poly_add(pq1, a1, self.log_n, ne_mods)
+        if pq0 is not None:
+            c0 = poly_add(c0, self.moddown(pq0, level), self.log_n, mods)
+            c1 = poly_add(c1, self.moddown(pq1, level), self.log_n, mods)
+        return Ciphertext(np.stack([c0, c1]), level, scale)
 
     def lt_apply(self, lt: LinearTransform, c: Ciphertext, gks: dict) -> Ciphertext:
         """y = sum_g Rot(sum_b pt_{g,b} * Rot(c, b), g n1); no rescale."""

@@ -324,17 +324,20 @@ uint32_t ock_modup(const u64 *d, uint32_t level, const u64 *q, uint32_t L, const
  * Q_level u P with the switching key swk [dnum][2][L+K][N] (rows 0..L-1 for
  * the q chain, L..L+K-1 for the special primes), then ModDown of both sums to
  * Q_level.  Outputs (out0, out1) have level+1 limbs. */
-void ock_keyswitch_ext(const u64 *ext, uint32_t digits, uint32_t level, const u64 *swk,
-                       const u64 *q, uint32_t L, const u64 *p, uint32_t K, uint32_t log_n,
-                       u64 *out0, u64 *out1) {
+/* Key inner product in Q_level u P: acc_{0,1}[t] = sum_j ext_j[t] * swk_j[t]
+ * (negacyclic products per limb; keys [dnum][2][L+K][N], b first), without
+ * ModDown.  acc0/acc1 are [level+1+K][N]. */
+void ock_ks_inner(const u64 *ext, uint32_t digits, uint32_t level, const u64 *swk,
+                  const u64 *q, uint32_t L, const u64 *p, uint32_t K, uint32_t log_n,
+                  u64 *acc0, u64 *acc1) {
   u64 n = (u64)1 << log_n;
   uint32_t nq = level + 1;
   uint32_t ne = nq + K;
   u64 *mods = (u64 *)malloc(ne * sizeof(u64));
   for (uint32_t t = 0; t < nq; t++) mods[t] = q[t];
   for (uint32_t k = 0; k < K; k++) mods[nq + k] = p[k];
-  u64 *acc0 = (u64 *)calloc((size_t)ne * n, sizeof(u64));
-  u64 *acc1 = (u64 *)calloc((size_t)ne * n, sizeof(u64));
+  memset(acc0, 0, (size_t)ne * n * sizeof(u64));
+  memset(acc1, 0, (size_t)ne * n * sizeof(u64));
   for (uint32_t j = 0; j < digits; j++) {
 #pragma omp parallel for schedule(dynamic)
     for (uint32_t t = 0; t < ne; t++) {
@@ -350,11 +353,23 @@ void ock_keyswitch_ext(const u64 *ext, uint32_t digits, uint32_t level, const u6
       free(prod);
     }
   }
-  ock_moddown(acc0, out0, q, nq, p, K, log_n);
-  ock_moddown(acc1, out1, q, nq, p, K, log_n);
+  free(mods);
+}
+
+/* Inner product of the extended digits with the key, then ModDown of both
+ * accumulators to Q_level. */
+void ock_keyswitch_ext(const u64 *ext, uint32_t digits, uint32_t level, const u64 *swk,
+                       const u64 *q, uint32_t L, const u64 *p, uint32_t K, uint32_t log_n,
+                       u64 *out0, u64 *out1) {
+  u64 n = (u64)1 << log_n;
+  uint32_t ne = level + 1 + K;
+  u64 *acc0 = (u64 *)malloc((size_t)ne * n * sizeof(u64));
+  u64 *acc1 = (u64 *)malloc((size_t)ne * n * sizeof(u64));
+  ock_ks_inner(ext, digits, level, swk, q, L, p, K, log_n, acc0, acc1);
+  ock_moddown(acc0, out0, q, level + 1, p, K, log_n);
+  ock_moddown(acc1, out1, q, level + 1, p, K, log_n);
   free(acc0);
   free(acc1);
-  free(mods);
 }
 
 /* Hybrid key switching of d: ModUp, then inner product and ModDown. */

@@ -263,3 +263,72 @@ def test_keyswitch_split_equals_whole(tiny):
         u0, u1 = o.keyswitch(d, level, rlk)
         v0, v1 = o.keyswitch_ext(o.modup(d, level), level, rlk)
         assert np.array_equal(u0, v0) and np.array_equal(u1, v1)
+
+
+def test_inner_product_then_moddown_is_keyswitch_ext(tiny):
+    """The extended-basis inner product followed by ModDown of each
+    accumulator gives the key switch's residues."""
+    o, s = tiny
+    rlk = o.keygen_relin(s, 7)
+    level = 2
+    ext = o.modup(S.uniform_residues(o.qmods(level), o.n, 32)[0], level)
+    a0, a1 = o.ks_inner(ext, level, rlk)
+    assert a0.shape == (level + 1 + o.K, o.n)
+    u0, u1 = o.keyswitch_ext(ext, level, rlk)
+    assert np.array_equal(o.moddown(a0, level), u0)
+    assert np.array_equal(o.moddown(a1, level), u1)
+
+
+def test_giant_sum_of_one_rotation_is_the_rotation(tiny, tiny_ct):
+    """With a single rotated part the shared ModDown is that rotation's own
+    ModDown: same residues as rotate(), also next to an unrotated part."""
+    o, s = tiny
+    z, ct = tiny_ct
+    g = o.galois_element(5)
+    gks = {g: o.keygen_galois(s, g, 5)}
+    assert np.array_equal(o.giant_sum([(5, ct)], gks).polys, o.rotate(ct, 5, gks).polys)
+    other = o.encrypt_sk(s, o.encode(S.uniform_slots(o.n_slots, 9), 2.0 ** 25, 2), 12)
+    want = o.add(other, o.rotate(ct, 5, gks))
+    assert np.array_equal(o.giant_sum([(0, other), (5, ct)], gks).polys, want.polys)
+
+
+def test_giant_sum_decodes_and_differs(tiny):
+    """Several rotations sharing one ModDown decode to the sum of the rolled
+    slots (within the noise of one key switch per part) and differ in their
+    residues from the sum of separate rotations."""
+    o, s = tiny
+    steps = [0, 1, 6, -11, 300]
+    zs = [S.uniform_slots(o.n_slots, 40 + i) for i in range(len(steps))]
+    cts = [o.encrypt_sk(s, o.encode(z, 2.0 ** 25, 2), 20 + i) for i, z in enumerate(zs)]
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5)
+           for k in steps if k}
+    got = o.giant_sum(list(zip(steps, cts)), gks)
+    want = sum(np.roll(z, -k) for z, k in zip(zs, steps))
+    assert np.max(np.abs(o.decode(o.decrypt(s, got)).real - want)) < 1e-3
+    plain = cts[0]
+    for k, c in zip(steps[1:], cts[1:]):
+        plain = o.add(plain, o.rotate(c, k, gks))
+    assert not np.array_equal(plain.polys, got.polys)
+
+
+def test_lt_eval_with_shared_giant_moddown_decodes(tiny):
+    """The complex DFT of Eq. dft_re with hoisted baby steps and one ModDown
+    per output for the giant steps decodes to the plaintext result."""
+    o, s = tiny
+    d, n1, level = 8, 4, 2
+    c = S.uniform_matrix(d, d, 1, 0.2)
+    sm = S.uniform_matrix(d, d, 2, 0.2)
+    lc = o.lt_create(block_diag_diagonals(c, o.n_slots // d), n1, level)
+    ls = o.lt_create(block_diag_diagonals(sm, o.n_slots // d), n1, level)
+    steps = set(o.lt_required_steps(lc)) | set(o.lt_required_steps(ls))
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5) for k in steps}
+    xr, xi = S.uniform_slots(o.n_slots, 3), S.uniform_slots(o.n_slots, 4)
+    cr = o.encrypt_sk(s, o.encode(xr, 2.0 ** 25, level), 10)
+    ci = o.encrypt_sk(s, o.encode(xi, 2.0 ** 25, level), 11)
+    out = o.lt_eval([cr, ci], [(lc, 0, 0, 1), (ls, 1, 0, -1), (ls, 0, 1, 1), (lc, 1, 1, 1)],
+                    gks, 2, hoist=True, hoist_giant=True)
+    eye = np.eye(o.n_slots // d)
+    re = np.kron(eye, c) @ xr - np.kron(eye, sm) @ xi
+    im = np.kron(eye, sm) @ xr + np.kron(eye, c) @ xi
+    assert np.max(np.abs(o.decode(o.decrypt(s, o.rescale(out[0]))).real - re)) < 1e-3
+    assert np.max(np.abs(o.decode(o.decrypt(s, o.rescale(out[1]))).real - im)) < 1e-3
