@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hoist", action="store_true",
                     help="plain (not hoisted) baby-step rotations")
+    ap.add_argument("--no-hoist-giant", action="store_true",
+                    help="one ModDown per giant rotation instead of one per output")
     ap.add_argument("--quick", action="store_true",
                     help="timed steps only (for profiler runs): no oracle baseline, "
                          "rotation modes or per-kernel event pass")
@@ -126,7 +128,8 @@ def main():
     rot_per_step = 2 * babies + 2 * giants
 
     def step():
-        ctx.lt_eval([ct_re, ct_im], terms, gks, outputs=[d_re, d_im], hoist=not args.no_hoist)
+        ctx.lt_eval([ct_re, ct_im], terms, gks, outputs=[d_re, d_im], hoist=not args.no_hoist,
+                    hoist_giant=not args.no_hoist_giant)
         ctx.rescale(d_re, d_re)
         ctx.rescale(d_im, d_im)
         ctx.mul(d_re, d_re, t1)
@@ -265,6 +268,7 @@ def main():
             "ring_log_n": prm["log_n"], "L": L, "K": len(prm["p"]), "dnum": prm["dnum"],
             "rotations_per_step": rot_per_step, "keyswitches_per_step": rot_per_step + 1,
             "hoisted_baby_steps": not args.no_hoist,
+            "shared_giant_moddown": not args.no_hoist_giant,
         },
         "decoded_max_abs_err": max_err,
         "window_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),

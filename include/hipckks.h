@@ -272,13 +272,21 @@ int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_cip
  *   out[o] = sum_{t : term_out[t] = o} term_sign[t] lts[t](in[term_in[t]]).
  * Every baby rotation Rot(in[i], b) is computed once and the inner sums of
  * all outputs are combined before the giant rotations (Rot(A) + Rot(B) =
- * Rot(A + B)); rotations by one step are key-switched in batches.  All
- * inputs share one level and all transforms that level and one baby step;
- * term_sign may be NULL (all +1) and holds +1 or -1.  Outputs may alias
- * inputs.  flags: HCK_LT_HOIST_BABY computes each input's baby rotations as
- * hoisted rotations (hck_rotate_hoisted).  Errors: HCK_EINVAL, HCK_ELEVEL,
- * HCK_ESCALE (terms of one output with different scales), HCK_ENOKEY. */
+ * Rot(A + B)); all giant rotations are key-switched together in batches.
+ * All inputs share one level and all transforms that level and one baby
+ * step; term_sign may be NULL (all +1) and holds +1 or -1; at most 4 inputs
+ * and 4 outputs.  Outputs may alias inputs.  flags:
+ *   HCK_LT_HOIST_BABY   each input's baby rotations are hoisted rotations
+ *                       (hck_rotate_hoisted);
+ *   HCK_LT_HOIST_GIANT  an output's giant rotations share one ModDown: their
+ *                       key products are summed in Q u P and reduced once,
+ *                       and the phi_g(c0) are summed in Q (valid rotations
+ *                       with less rounding noise and different residues
+ *                       than separate ones).
+ * Errors: HCK_EINVAL, HCK_ELEVEL, HCK_ESCALE (terms of one output with
+ * different scales), HCK_ENOKEY. */
 #define HCK_LT_HOIST_BABY 1u
+#define HCK_LT_HOIST_GIANT 2u
 int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in,
                 const hck_linear_transform *const *lts, const uint32_t *term_in,
                 const uint32_t *term_out, const int32_t *term_sign, uint32_t n_terms,

@@ -514,10 +514,12 @@ class Context:
         _check(capi.hck_rotate_hoisted(self.h, a, _ptr(s), len(s), gks, o))
         return outs
 
-    def lt_eval(self, inputs, terms, gks, outputs=None, n_out=None, hoist=False):
+    def lt_eval(self, inputs, terms, gks, outputs=None, n_out=None, hoist=False,
+                hoist_giant=False):
         """terms: list of (transform, input index, output index, sign +-1);
         returns the outputs out[o] = sum sign * lt(inputs[i]); with hoist the
-        baby rotations of each input share one ModUp."""
+        baby rotations of each input share one ModUp, with hoist_giant the
+        giant rotations of each output share one ModDown."""
         if outputs is None:
             n_out = n_out if n_out is not None else 1 + max(t[2] for t in terms)
             outputs = [self.ciphertext() for _ in range(n_out)]
@@ -528,7 +530,8 @@ class Context:
         ts = np.array([t[3] for t in terms], dtype=np.int32)
         outs = (ctypes.c_void_p * len(outputs))(*[c.h for c in outputs])
         _check(capi.hck_lt_eval(self.h, ins, len(inputs), lts, _ptr(ti), _ptr(to), _ptr(ts),
-                                len(terms), gks, outs, len(outputs), 1 if hoist else 0))
+                                len(terms), gks, outs, len(outputs),
+                                (1 if hoist else 0) | (2 if hoist_giant else 0)))
         return outputs
 
     # --- kernel timing ---

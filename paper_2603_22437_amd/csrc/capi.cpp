@@ -1262,13 +1262,14 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
         first_pass = false;
       }
   }
-  // giant rotations of every group sum, key-switched together in batches;
-  // then each output is the sum of its rotated group sums (the inputs are no
-  // longer read, so outputs may alias them)
-  std::vector<const hck_ciphertext *> src;
-  std::vector<hck_ciphertext *> dst;
-  std::vector<uint32_t> gal;
-  std::vector<std::vector<const hck_ciphertext *>> parts(n_out);
+  // every output is the sum over its groups g of Rot(inner_g, g n1); the
+  // inputs are no longer read, so outputs may alias them
+  struct Part {
+    uint32_t o;
+    uint32_t galois;  // 1: unrotated group
+    hck_ciphertext *u;
+  };
+  std::vector<Part> parts;
   for (size_t gi = 0; gi < giants.size() && !rc; gi++)
     for (uint32_t o = 0; o < n_out; o++) {
       hck_ciphertext *u = inner[gi][o];
@@ -1276,30 +1277,112 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
       u->size = 2;
       u->level = level;
       u->scale = out_scale[o];
-      if (giants[gi] == 0) {
-        parts[o].push_back(u);
+      parts.push_back({o, giants[gi] == 0 ? 1u : galois_of_step(ctx, giants[gi] * (int32_t)n1), u});
+    }
+  const size_t words = (size_t)(level + 1) * n;
+  if (!rc && (flags & HCK_LT_HOIST_GIANT)) {
+    // shared ModDown: the rotated groups' key products are summed in Q u P
+    // per output (ws_pq), the phi_g(c0) and the unrotated group in Q
+    const uint32_t limit = ks_batch_limit(ctx, level);
+    std::vector<bool> written(n_out, false);
+    std::vector<Part> rot;
+    for (const Part &pt : parts)
+      if (pt.galois != 1) rot.push_back(pt);
+    if (!rc) rc = ensure_workspace(ctx, ws_words_needed(ctx));
+    const size_t pq_stride = (size_t)2 * (ctx->L + ctx->K) * n;
+    for (size_t s0 = 0; s0 < rot.size() && !rc; s0 += limit) {
+      KsBatch kb;
+      kb.n = (uint32_t)std::min<size_t>(limit, rot.size() - s0);
+      std::vector<uint64_t *> pq(kb.n);
+      bool first[kMaxBatch];
+      for (uint32_t b = 0; b < kb.n; b++) {
+        const Part &pt = rot[s0 + b];
+        auto it = gks->keys.find(pt.galois);
+        kb.key[b] = it->second->data;
+        kb.galois[b] = pt.galois;
+        kb.d[b] = pt.u->data + ps;
+        kb.out0[b] = kb.out1[b] = nullptr;
+        kb.add0[b] = kb.add1[b] = nullptr;
+        pq[b] = ws_pq(ctx) + pt.o * pq_stride;
+        first[b] = !written[pt.o];
+      }
+      rc = keyswitch_pq(ctx, kb, level, pq.data(), first);
+      for (uint32_t b = 0; b < kb.n; b++) written[rot[s0 + b].o] = true;
+    }
+    std::vector<hck_ciphertext *> c0sum(n_out, nullptr);
+    KsBatch md;
+    md.n = 0;
+    std::vector<const uint64_t *> md_pq;
+    for (uint32_t o = 0; o < n_out && !rc; o++) {
+      rc = ensure_ct(ctx, out[o], 2);
+      std::vector<const uint64_t *> c0s;
+      std::vector<uint32_t> gs;
+      const hck_ciphertext *plain = nullptr;
+      for (const Part &pt : parts) {
+        if (pt.o != o) continue;
+        c0s.push_back(pt.u->data);
+        gs.push_back(pt.galois);
+        if (pt.galois == 1) plain = pt.u;
+      }
+      if (!written[o]) {  // no rotated group: the unrotated one is the output
+        for (uint32_t p = 0; p < 2 && !rc && plain; p++)
+          rc = launch_copy(ctx, out[o]->data + p * ps, plain->data + p * ps, words);
+        continue;
+      }
+      c0sum[o] = get();
+      if (!rc) rc = ensure_ct(ctx, c0sum[o], 2);
+      if (!rc) rc = launch_gather_sum(ctx, c0sum[o]->data, c0s.data(), gs.data(),
+                                      (uint32_t)c0s.size(), qm);
+      const uint32_t b = md.n++;
+      md.key[b] = nullptr;
+      md.galois[b] = 1;
+      md.d[b] = nullptr;
+      md.out0[b] = out[o]->data;
+      md.out1[b] = out[o]->data + ps;
+      md.add0[b] = c0sum[o]->data;
+      md.add1[b] = plain ? plain->data + ps : nullptr;
+      md_pq.push_back(ws_pq(ctx) + o * pq_stride);
+      if (md.n == limit && !rc) {
+        rc = moddown_pq(ctx, md, level, md_pq.data());
+        md.n = 0;
+        md_pq.clear();
+      }
+    }
+    if (!rc && md.n) rc = moddown_pq(ctx, md, level, md_pq.data());
+  } else if (!rc) {
+    // separate rotations, key-switched together in batches, then one sum per
+    // output
+    std::vector<const hck_ciphertext *> src;
+    std::vector<hck_ciphertext *> dst;
+    std::vector<uint32_t> gal;
+    std::vector<std::vector<const hck_ciphertext *>> terms_of(n_out);
+    for (const Part &pt : parts) {
+      if (pt.galois == 1) {
+        terms_of[pt.o].push_back(pt.u);
         continue;
       }
       hck_ciphertext *r = get();
-      src.push_back(u);
+      src.push_back(pt.u);
       dst.push_back(r);
-      gal.push_back(galois_of_step(ctx, giants[gi] * (int32_t)n1));
-      parts[o].push_back(r);
+      gal.push_back(pt.galois);
+      terms_of[pt.o].push_back(r);
     }
-  if (!rc) rc = apply_galois_multi(ctx, src.data(), gal.data(), (uint32_t)src.size(), gks, dst.data());
+    rc = apply_galois_multi(ctx, src.data(), gal.data(), (uint32_t)src.size(), gks, dst.data());
+    for (uint32_t o = 0; o < n_out && !rc; o++) {
+      rc = ensure_ct(ctx, out[o], 2);
+      std::vector<const uint64_t *> polys;
+      for (uint32_t p = 0; p < 2 && !rc; p++) {
+        polys.clear();
+        for (const hck_ciphertext *c : terms_of[o]) polys.push_back(c->data + p * ps);
+        rc = launch_sum_many(ctx, out[o]->data + p * ps, polys.data(), (uint32_t)polys.size(),
+                             qm);
+      }
+    }
+  }
   for (uint32_t o = 0; o < n_out && !rc; o++) {
-    rc = ensure_ct(ctx, out[o], 2);
-    std::vector<const uint64_t *> polys;
-    for (uint32_t p = 0; p < 2 && !rc; p++) {
-      polys.clear();
-      for (const hck_ciphertext *c : parts[o]) polys.push_back(c->data + p * ps);
-      rc = launch_sum_many(ctx, out[o]->data + p * ps, polys.data(), (uint32_t)polys.size(), qm);
-    }
-    if (!rc) {
-      out[o]->size = 2;
-      out[o]->level = level;
-      out[o]->scale = out_scale[o];
-    }
+    out[o]->size = 2;
+    out[o]->level = level;
+    out[o]->scale = out_scale[o];
   }
   for (hck_ciphertext *s : scratch) pool_put(ctx, s);
   return rc;

@@ -14,10 +14,10 @@ size_t ws_ks_rows(const hck_context *ctx) {
 }
 
 // [kMaxBatch key-switch slots][kMaxBatch x L rows: copies of aliased inputs]
-// [3 (L+K) rows: general temporary]
+// [3 (L+K) rows: general temporary][kLtOut x 2 (L+K) rows: extended-basis sums]
 size_t ws_words_needed(const hck_context *ctx) {
   const size_t n = ctx->n, L = ctx->L, LK = ctx->L + ctx->K;
-  return n * (kMaxBatch * ws_ks_rows(ctx) + kMaxBatch * L + 3 * LK);
+  return n * (kMaxBatch * ws_ks_rows(ctx) + kMaxBatch * L + 3 * LK + kLtOut * 2 * LK);
 }
 
 uint64_t *ws_ks(hck_context *ctx) { return ctx->ws; }
@@ -28,6 +28,10 @@ uint64_t *ws_rot(hck_context *ctx) {
 
 uint64_t *ws_tmp(hck_context *ctx) {
   return ws_rot(ctx) + (size_t)ctx->n * kMaxBatch * ctx->L;
+}
+
+uint64_t *ws_pq(hck_context *ctx) {
+  return ws_tmp(ctx) + (size_t)ctx->n * 3 * (ctx->L + ctx->K);
 }
 
 int ntt_forward_rows(hck_context *ctx, uint64_t *buf,

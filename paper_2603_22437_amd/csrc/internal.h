@@ -210,6 +210,11 @@ int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t wor
 constexpr int kSumInputs = 32;
 int launch_sum_many(hck_context *ctx, uint64_t *out, const uint64_t *const *in, uint32_t n_in,
                     const LimbMap &map);
+// out = sum of phi_{galois[k]}(in[k]) (evaluation-domain automorphisms;
+// galois 1 = identity); out must not overlap an input read through an
+// automorphism
+int launch_gather_sum(hck_context *ctx, uint64_t *out, const uint64_t *const *in,
+                      const uint32_t *galois, uint32_t n_in, const LimbMap &map);
 int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
                   const LimbMap &map, int op);
 // out = [+-] REDC(a * bm) [+ out] (bm in Montgomery form): mode 0 set,
@@ -265,6 +270,7 @@ size_t ws_words_needed(const hck_context *ctx);
 uint64_t *ws_ks(hck_context *ctx);    // key-switch internals
 uint64_t *ws_rot(hck_context *ctx);   // [kMaxBatch][L][N]: copies of aliased inputs
 uint64_t *ws_tmp(hck_context *ctx);   // [3][L+K][N]: general temporary
+uint64_t *ws_pq(hck_context *ctx);    // [kLtOut][2][L+K][N]: extended-basis sums
 // Up to kMaxBatch key switches at one level in one sequence of launches,
 // slot b with its own switching key key[b] ([dnum][2][L+K][N], Montgomery
 // form; slots that share a key read it through the cache):
@@ -285,6 +291,17 @@ struct KsBatch {
 int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level);
 // largest batch keyswitch_batch accepts at this level (row limits of one launch)
 uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level);
+// K1-K4 of keyswitch_batch without ModDown: slot b's key products
+// (acc0, acc1) in Q_level u P are added into pq[b] ([2][level+1+K][N],
+// evaluation form), or stored there when first[b]; slots may share a pq
+// buffer.  out/add fields of the batch are unused.
+int keyswitch_pq(hck_context *ctx, const KsBatch &batch, uint32_t level, uint64_t *const *pq,
+                 const bool *first);
+// ModDown of n extended-basis pairs pq[b] ([2][level+1+K][N]) to Q_level:
+// (out0[b], out1[b]) = ModDown(pq[b]) + (add0[b], add1[b]) (galois fields of
+// the batch apply to the addends as in keyswitch_batch; d and key unused)
+int moddown_pq(hck_context *ctx, const KsBatch &batch, uint32_t level,
+               const uint64_t *const *pq);
 // Hoisted rotations of one ciphertext (c0, c1) by n Galois elements: ModUp of
 // c1 once, then per element the automorphism of the extended digits, the key
 // inner product and ModDown (batched over the elements), plus phi_g(c0).

@@ -53,6 +53,33 @@ __global__ __launch_bounds__(kThreads) void k_sum_many(uint64_t *out, SumArgs sa
   out[off] = acc;
 }
 
+// out = sum of phi_{g_k}(in_k) mod q (NTT-domain automorphism gathers; g = 1
+// reads in place), row by row
+struct GatherSumArgs {
+  const uint64_t *in[kSumInputs];
+  uint32_t galois[kSumInputs];
+  uint32_t n;
+};
+
+__global__ __launch_bounds__(kThreads) void k_gather_sum(uint64_t *out, GatherSumArgs ga,
+                                                         LimbMap map,
+                                                         const ModConst *__restrict__ mc,
+                                                         int log_n) {
+  const uint32_t n = 1u << log_n;
+  const uint32_t j = blockIdx.x * kThreads + threadIdx.x;
+  const size_t row = (size_t)map.row[blockIdx.y] * n;
+  const uint64_t q = mc[map.mod[blockIdx.y]].q;
+  const uint32_t shift = 32 - log_n;
+  const uint32_t e = 2 * (__brev(j) >> shift) + 1;
+  uint64_t acc = 0;
+  for (uint32_t k = 0; k < ga.n; k++) {
+    const uint32_t src_e = (uint32_t)(((uint64_t)e * ga.galois[k]) & (2 * n - 1));
+    const uint32_t src = __brev((src_e - 1) >> 1) >> shift;
+    acc = add_mod(acc, ga.in[k][row + src], q);
+  }
+  out[row + j] = acc;
+}
+
 // out = [+-] REDC(a * bm) [+ out]: mode 0 set, 1 add to out, 2 subtract from
 // out, 3 set negated (bm in Montgomery form, so REDC gives a * b mod q)
 __global__ __launch_bounds__(kThreads) void k_mul_mont(uint64_t *out, const uint64_t *a,
@@ -214,6 +241,32 @@ int launch_sum_many(hck_context *ctx, uint64_t *out, const uint64_t *const *in, 
     timing_begin(ctx, "sum_many", 8.0 * ctx->n * map.n * (sa.n + 1));
     k_sum_many<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, sa, map, ctx->d_mod,
                                                                       ctx->n);
+    timing_end(ctx);
+    HCK_HIP(ctx, hipGetLastError());
+  }
+  return HCK_OK;
+}
+
+int launch_gather_sum(hck_context *ctx, uint64_t *out, const uint64_t *const *in,
+                      const uint32_t *galois, uint32_t n_in, const LimbMap &map) {
+  if (n_in == 0) return set_error(HCK_EINVAL, "empty sum");
+  if (map.n == 0) return HCK_OK;
+  // chunks of kSumInputs; later chunks add to the partial sum in `out`
+  for (uint32_t s = 0; s < n_in;) {
+    GatherSumArgs ga;
+    ga.n = 0;
+    if (s > 0) {
+      ga.in[0] = out;
+      ga.galois[0] = 1;
+      ga.n = 1;
+    }
+    while (s < n_in && ga.n < (uint32_t)kSumInputs) {
+      ga.in[ga.n] = in[s];
+      ga.galois[ga.n++] = galois[s++];
+    }
+    timing_begin(ctx, "gather_sum", 8.0 * ctx->n * map.n * (ga.n + 1));
+    k_gather_sum<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, ga, map, ctx->d_mod,
+                                                                        (int)ctx->log_n);
     timing_end(ctx);
     HCK_HIP(ctx, hipGetLastError());
   }

@@ -489,6 +489,59 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
   return HCK_OK;
 }
 
+// K1-K4, then each slot's accumulators added into its extended-basis sum
+template <int LOGN>
+int ks_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *const *pq,
+          const bool *first) {
+  constexpr int B = split_b(LOGN);
+  constexpr double N = (double)(1 << LOGN);
+  using GB = Pass<B, LOGN, false>;
+  const KsGeom kg = make_geom(ctx, level);
+  const uint32_t nq = kg.nq, ne = kg.ne, nb = kb.n, alpha = kg.alpha;
+  int rc;
+  if ((rc = ks_modup<LOGN>(ctx, kb, kg))) return rc;
+  const double digits = (double)((nq + alpha - 1) / alpha);
+  const double ext_limbs = nb * (digits * ne - nq);
+  timing_begin(ctx, "ks_contig_inner",
+               8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * nb),
+               N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
+  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne, nb), kNttThreads, 0, ctx->stream>>>(
+      ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  LimbMap rows;
+  rows.n = 2 * ne;
+  for (uint32_t r = 0; r < 2 * ne; r++) {
+    const uint32_t t = r % ne;
+    rows.row[r] = (uint16_t)r;
+    rows.mod[r] = (uint8_t)(t < nq ? t : kg.L + (t - nq));
+  }
+  std::vector<bool> done(nb, false);
+  for (uint32_t b = 0; b < nb; b++) {
+    if (done[b]) continue;
+    std::vector<const uint64_t *> in;
+    if (!first[b]) in.push_back(pq[b]);
+    for (uint32_t k = b; k < nb; k++)
+      if (pq[k] == pq[b]) {
+        done[k] = true;
+        in.push_back(ws_ks(ctx) + ((size_t)k * kg.slot_rows + kg.off_acc) * (size_t)N);
+      }
+    if ((rc = launch_sum_many(ctx, pq[b], in.data(), (uint32_t)in.size(), rows))) return rc;
+  }
+  return HCK_OK;
+}
+
+template <int LOGN>
+int md_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, const uint64_t *const *pq) {
+  const KsGeom kg = make_geom(ctx, level);
+  int rc;
+  for (uint32_t b = 0; b < kb.n; b++)
+    if ((rc = launch_copy(ctx, ws_ks(ctx) + ((size_t)b * kg.slot_rows + kg.off_acc) * ctx->n,
+                          pq[b], (size_t)2 * kg.ne * ctx->n)))
+      return rc;
+  return ks_moddown<LOGN>(ctx, kb, kg);
+}
+
 }  // namespace
 
 uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level) {
@@ -547,6 +600,45 @@ int keyswitch_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, 
     case 15: return ks_hoisted<15>(ctx, c0, c1, level, galois, keys, n, out0, out1);
     case 16: return ks_hoisted<16>(ctx, c0, c1, level, galois, keys, n, out0, out1);
     case 17: return ks_hoisted<17>(ctx, c0, c1, level, galois, keys, n, out0, out1);
+    default: return set_error(HCK_EPARAMS, "unsupported ring degree");
+  }
+}
+
+}  // namespace hck
+
+namespace hck {
+
+int keyswitch_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *const *pq,
+                 const bool *first) {
+  if (kb.n == 0) return HCK_OK;
+  if (kb.n > ks_batch_limit(ctx, level)) return set_error(HCK_EINVAL, "batch too large");
+  int rc = ensure_workspace(ctx, ws_words_needed(ctx));
+  if (rc) return rc;
+  switch (ctx->log_n) {
+    case 11: return ks_pq<11>(ctx, kb, level, pq, first);
+    case 12: return ks_pq<12>(ctx, kb, level, pq, first);
+    case 13: return ks_pq<13>(ctx, kb, level, pq, first);
+    case 14: return ks_pq<14>(ctx, kb, level, pq, first);
+    case 15: return ks_pq<15>(ctx, kb, level, pq, first);
+    case 16: return ks_pq<16>(ctx, kb, level, pq, first);
+    case 17: return ks_pq<17>(ctx, kb, level, pq, first);
+    default: return set_error(HCK_EPARAMS, "unsupported ring degree");
+  }
+}
+
+int moddown_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, const uint64_t *const *pq) {
+  if (kb.n == 0) return HCK_OK;
+  if (kb.n > ks_batch_limit(ctx, level)) return set_error(HCK_EINVAL, "batch too large");
+  int rc = ensure_workspace(ctx, ws_words_needed(ctx));
+  if (rc) return rc;
+  switch (ctx->log_n) {
+    case 11: return md_pq<11>(ctx, kb, level, pq);
+    case 12: return md_pq<12>(ctx, kb, level, pq);
+    case 13: return md_pq<13>(ctx, kb, level, pq);
+    case 14: return md_pq<14>(ctx, kb, level, pq);
+    case 15: return md_pq<15>(ctx, kb, level, pq);
+    case 16: return md_pq<16>(ctx, kb, level, pq);
+    case 17: return md_pq<17>(ctx, kb, level, pq);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }

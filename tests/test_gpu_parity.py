@@ -291,6 +291,24 @@ def test_lt_eval_complex_dft_matches_oracle(name, d, n1):
                       hoist=True)
     for g_, w in zip(goth, wanth):
         assert np.array_equal(p.export(g_), w.polys)
+    # giant rotations sharing one ModDown per output, with and without
+    # hoisted baby steps
+    for hb in (False, True):
+        gotg = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks,
+                             hoist=hb, hoist_giant=True)
+        wantg = o.lt_eval([v_re_o, v_im_o], [(mats[m][1], i, j, s) for m, i, j, s in terms],
+                          gko, 2, hoist=hb, hoist_giant=True)
+        for g_, w in zip(gotg, wantg):
+            assert np.array_equal(p.export(g_), w.polys), f"hoist={hb}"
+    # outputs aliasing inputs
+    gota = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks,
+                         outputs=[v_re, v_im], hoist=True, hoist_giant=True)
+    want_hh = o.lt_eval([v_re_o, v_im_o], [(mats[m][1], i, j, s) for m, i, j, s in terms], gko,
+                        2, hoist=True, hoist_giant=True)
+    assert np.array_equal(p.export(gota[0]), want_hh[0].polys)
+    assert np.array_equal(p.export(gota[1]), want_hh[1].polys)
+    v_re = p.ctx.ciphertext_import(v_re_o.polys, level, v_re_o.scale)
+    v_im = p.ctx.ciphertext_import(v_im_o.polys, level, v_im_o.scale)
     # outputs aliasing inputs
     got2 = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks,
                          outputs=[v_im, v_re])
