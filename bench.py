@@ -76,6 +76,10 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="timed steps only (for profiler runs): no oracle baseline, "
                          "rotation modes or per-kernel event pass")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the vital-sign pipeline latency measurement")
+    ap.add_argument("--pipeline-windows", type=int, default=8,
+                    help="timed windows of the vital-sign pipeline")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy of known "
                          "size, to scale hardware byte counters)")
@@ -243,6 +247,10 @@ def main():
                      if v["ms"] else None}
                  for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"])}
 
+    vital = None
+    if not args.no_pipeline:
+        vital = vital_pipeline_latency(ctx, prm, sk, rlk, args.pipeline_windows, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prm, args.cpu_seconds, log)
@@ -275,6 +283,7 @@ def main():
                               "p99": round(float(np.percentile(step_ms, 99)), 3),
                               "windows_per_s": round(args.steps / wall, 2)},
         "rotation_modes": rotation_modes,
+        "vital_pipeline": vital,
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,
@@ -313,6 +322,48 @@ def measured_traffic(kernel):
                 return None
             return int(cells[4])
     return None
+
+
+def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
+    """Latency of the encrypted vital-sign pipeline (K1 -> K2 -> K4 -> K5 ->
+    K7 -> K3 -> K1 -> K2 on one 200 x 64 window at N = 2^16, L = 24), per
+    window with HIP events, after one warm-up window."""
+    import torch
+    import seeded_inputs as S
+    from paper_2603_22437_amd import vital as HV
+    cfg = S.vital_pipeline_config()
+    top = len(prm["q"]) - 1
+    plan = HV.encode_plan(ctx, cfg, top)
+    gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
+    z = S.vital_window(1003, cfg["frames"], cfg["bins"])
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: z.size] = z.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 200)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 201)
+    outs = [ctx.ciphertext() for _ in range(6)]
+    stream = torch.cuda.current_stream()
+    ctx.vital_eval(plan, re, im, gks, rlk, outs)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(windows + 1)]
+    evs[0].record(stream)
+    t0 = time.perf_counter()
+    for k in range(windows):
+        ctx.vital_eval(plan, re, im, gks, rlk, outs)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(windows)])
+    got = [float(ctx.decode(ctx.decrypt(sk, c))[0].real) for c in outs]
+    # the energy-weighted bin estimate must land on the synthetic target bin
+    target = int(np.argmax(np.abs(z).sum(axis=0)))
+    res = {"windows": windows, "p50_ms": round(float(np.percentile(ms, 50)), 3),
+           "p99_ms": round(float(np.percentile(ms, 99)), 3),
+           "windows_per_s": round(windows / wall, 2), "taylor_order": cfg["taylor_order"],
+           "rotation_keys": len(gks), "target_bin_true": target,
+           "target_bin_est": round(got[0] / got[1], 4),
+           "resp_bpm_est": round(got[2] / got[3], 3), "hr_bpm_est": round(got[4] / got[5], 3)}
+    log(f"vital pipeline: {res}")
+    return res
 
 
 def cpu_baseline(prm, seconds, log):

@@ -294,6 +294,51 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
                 uint32_t flags);
 int hck_lt_destroy(hck_linear_transform *lt);
 
+/* ---- vital-sign pipeline -------------------------------------------------
+ * The paper's encrypted vital-sign pipeline (section 3.3.3, example
+ * pipelines: K1 -> K2 -> K4 -> K5 -> K7 -> K3 -> K1 -> K2) on one window of
+ * F frames x R range bins, packed frame-major (slot t R + r) into a real
+ * and an imaginary ciphertext at level l0 (the batched packing of section
+ * 3.3.1).  Stages (level reached):
+ *   K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p by rotations R, 2R, ...
+ *   K2  w = E^2 (l0-2); num_bin = sum_r w_r bin_index_r,
+ *       den_bin = sum_r w_r bin_mask_r (rotations 1 .. R/2; l0-3)
+ *   K4  m = p^2 (l0-2); I = sum_r m Re, Q = sum_r m Im per frame (l0-3)
+ *   K5  (If, Qf) per band = FIR transform (I, Q) (BSGS, hck_lt_eval; l0-4)
+ *   K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
+ *       (l0-5); taylor_order 3: dphi = y x^2 - y^3 third (l0-7); 1: dphi = y
+ *   K3  dphi copied into lanes_resp (respiration) or the first power of two
+ *       >= lanes_resp + lanes_hr lanes (heart rate) by rotations -1, -2, ...;
+ *       X = sum_t dft weights x dphi (rotations R, 2R, ...); bands added
+ *   K1  P = Re X^2 + Im X^2;  K2  S = P^2;  num_b = sum_k S_k freq_b,
+ *       den_b = sum_k S_k mask_b (rotations 1 .. lanes/2; output level:
+ *       dft level - 4).
+ * Outputs (value in slot 0): out[0] num_bin, out[1] den_bin, out[2]
+ * num_resp, out[3] den_resp, out[4] num_hr, out[5] den_hr; the client's
+ * scalar divisions (section 3.3.4) give the target bin and the two rates.
+ * The operands are public plaintexts and transforms owned by the caller,
+ * encoded at least at the level where they are applied (above); scales
+ * follow from the operands' scales (q_level keeps a ciphertext's scale).
+ * Errors: HCK_EINVAL (bad layout or missing operand), HCK_ELEVEL (input
+ * level too low for the depth, operand level too low), HCK_ENOKEY. */
+typedef struct {
+  uint32_t frames, bins;         /* F; R a power of two, pow2ceil(F) R <= N/2 */
+  uint32_t taylor_order;         /* 1 or 3 */
+  uint32_t lanes_resp, lanes_hr; /* DFT bins per band; pow2ceil(sum) <= R */
+  const hck_plaintext *bin_index, *bin_mask;                    /* l0-2 */
+  const hck_linear_transform *fir_resp, *fir_hr;                /* l0-3 */
+  const hck_plaintext *third;                                   /* l0-5 (order 3) */
+  const hck_plaintext *dft_re_resp, *dft_im_resp, *dft_re_hr, *dft_im_hr; /* l0-7 / l0-5 */
+  const hck_plaintext *freq_resp, *mask_resp, *freq_hr, *mask_hr;         /* dft level - 3 */
+} hck_vital_plan;
+/* Rotation steps the pipeline needs Galois keys for (ascending; `cap` is the
+ * capacity of steps[], *n receives the count; steps may be NULL). */
+int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan, int32_t *steps,
+                             uint32_t cap, uint32_t *n);
+int hck_vital_eval(hck_context *ctx, const hck_vital_plan *plan, const hck_ciphertext *re,
+                   const hck_ciphertext *im, const hck_galois_keys *gks,
+                   const hck_switch_key *rlk, hck_ciphertext *const *out);
+
 /* ---- kernel timing --------------------------------------------------------
  * With timing on, every kernel launch is bracketed by HIP events on the
  * context stream and its duration added to a per-kernel-name total, read

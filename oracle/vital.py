@@ -1,0 +1,297 @@
+"""The paper's encrypted vital-sign pipeline (section 3.3.3, example
+pipelines: K1 -> K2 -> K4 -> K5 -> K7 -> K3 -> K1 -> K2; depth budget of
+Table 1) composed from the oracle's ciphertext operations.
+
+TEST INFRASTRUCTURE ONLY: this module is the reference the GPU pipeline is
+checked against.  Nothing in the product path imports it.
+
+Slot layout (frame-major, the batched packing of section 3.3.1): frame t and
+range bin r sit in slot t R + r, F frames x R bins, zero elsewhere; T2 is the
+power of two >= F with T2 R <= N/2.  The stages and the level each ends at
+(input level l0):
+
+  K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p[t, r] by rotations R, 2R, ...
+  K2  w = E^2 (l0-2); num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2
+      (index and mask plaintexts, rotations 1 .. R/2; l0-3)
+  K4  m = p^2 (l0-2); I[t] = sum_r m Re, Q[t] = sum_r m Im (l0-3), left in
+      slot t R
+  K5  per band b: If_b = T_b I, Qf_b = T_b Q with the zero-padded Toeplitz
+      matrix of the band's taps, T_b[t][t+k] = h_b[k] (BSGS over offsets
+      k R with hoisted baby steps and one ModDown per output; l0-4)
+  K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
+      (t-1 by a rotation of -R; l0-5); third order: dphi = y x^2 - y^3 / 3
+      (l0-7), first order: dphi = y
+  K3  band b's DFT bins k occupy lanes c (slot t R + c; respiration first,
+      then heart rate): dphi is copied into the lanes by rotations -1, -2,
+      ..., multiplied by g w[t] cos(2 pi k t / F) / sum w and by
+      -g w[t] sin(...) / sum w (g: the folded DFT gain), and summed over t
+      by rotations R, 2R, ...; the
+      bands' results are added (disjoint lanes)
+  K1  P = Re X^2 + Im X^2
+  K2  S = P^2; per band num_b = sum_k f_k S_k, den_b = sum_k S_k with f_k
+      the bin frequency in beats per minute (rotations 1 .. C/2)
+
+Outputs (value in slot 0): num_r, den_r (target bin r^ = num_r / den_r) and
+num_b, den_b per band (rate in BPM = num_b / den_b), the client's scalar
+divisions of section 3.3.4.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import Ciphertext, Oracle, Plaintext
+
+OUTPUTS = ("num_bin", "den_bin", "num_resp", "den_resp", "num_hr", "den_hr")
+
+
+def _pow2_at_least(x: int) -> int:
+    p = 1
+    while p < x:
+        p *= 2
+    return p
+
+
+@dataclass
+class Layout:
+    frames: int
+    bins: int
+    t2: int          # frames rounded up to a power of two
+    n_slots: int
+    lanes: dict      # band -> first lane, count
+    c_resp: int      # lanes the respiration dphi is copied into
+    c_all: int       # lanes of both bands (power of two)
+
+
+def layout(cfg: dict, n_slots: int) -> Layout:
+    f, r = cfg["frames"], cfg["bins"]
+    t2 = _pow2_at_least(f)
+    if r & (r - 1) or t2 * r > n_slots:
+        raise ValueError("bins must be a power of two and T2 R <= N/2")
+    nr, nh = len(cfg["k_resp"]), len(cfg["k_hr"])
+    c_all = _pow2_at_least(nr + nh)
+    if c_all > r:
+        raise ValueError("more DFT lanes than range bins")
+    return Layout(f, r, t2, n_slots, {"resp": (0, nr), "hr": (nr, nh)},
+                  _pow2_at_least(nr), c_all)
+
+
+def operand_vectors(cfg: dict, n_slots: int) -> dict:
+    """Real slot vectors of every public plaintext operand, and the FIR
+    transforms' generalized diagonals (offset -> vector)."""
+    lay = layout(cfg, n_slots)
+    f, r = lay.frames, lay.bins
+    v = {}
+    idx = np.zeros(n_slots)
+    idx[:r] = np.arange(r) / f ** 2
+    v["bin_index"] = idx
+    msk = np.zeros(n_slots)
+    msk[:r] = 1.0 / f ** 2
+    v["bin_mask"] = msk
+    for band in ("resp", "hr"):
+        h = np.asarray(cfg[f"taps_{band}"])
+        half = (len(h) - 1) // 2
+        diags = {}
+        for k in range(-half, half + 1):
+            d = np.zeros(n_slots)
+            for t in range(f):
+                if 0 <= t + k < f:
+                    d[t * r] = h[k + half]
+            if np.any(d):
+                diags[(k * r) % n_slots] = d
+        v[f"fir_{band}"] = diags
+    v["third"] = np.full(n_slots, 1.0 / 3.0)
+    w = np.asarray(cfg["window"])
+    ws = w.sum() / cfg["dft_gain"]
+    t = np.arange(f)
+    for band in ("resp", "hr"):
+        c0, nb = lay.lanes[band]
+        re = np.zeros(n_slots)
+        im = np.zeros(n_slots)
+        fr = np.zeros(n_slots)
+        mk = np.zeros(n_slots)
+        for i, k in enumerate(cfg[f"k_{band}"]):
+            c = c0 + i
+            re[t * r + c] = w * np.cos(2 * np.pi * k * t / f) / ws
+            im[t * r + c] = -w * np.sin(2 * np.pi * k * t / f) / ws
+            fr[c] = 60.0 * k * cfg["fps"] / f
+            mk[c] = 1.0
+        v[f"dft_re_{band}"] = re
+        v[f"dft_im_{band}"] = im
+        v[f"freq_{band}"] = fr
+        v[f"mask_{band}"] = mk
+    return v
+
+
+def levels(cfg: dict, level0: int) -> dict:
+    """Level of each operand for inputs at level0."""
+    phi = level0 - (7 if cfg["taylor_order"] == 3 else 5)
+    return {"bin_index": level0 - 2, "bin_mask": level0 - 2, "fir": level0 - 3,
+            "third": level0 - 5, "dft": phi, "freq": phi - 3, "out": phi - 4}
+
+
+def fir_baby_step(cfg: dict) -> int:
+    """Baby step of the FIR transforms: about sqrt(taps) frames of R slots."""
+    taps = len(cfg["taps_resp"])
+    return cfg["bins"] * max(1, int(round(np.sqrt(taps))))
+
+
+def encode_operands(o: Oracle, cfg: dict, level0: int, vecs: dict | None = None) -> dict:
+    """Plaintexts (at q_level scale) and FIR transforms for inputs at level0."""
+    vecs = operand_vectors(cfg, o.n_slots) if vecs is None else vecs
+    lv = levels(cfg, level0)
+    enc = lambda name, lvl: o.encode(vecs[name], float(o.q[lvl]), lvl)
+    ops = {"bin_index": enc("bin_index", lv["bin_index"]),
+           "bin_mask": enc("bin_mask", lv["bin_mask"]),
+           "third": enc("third", lv["third"])}
+    n1 = fir_baby_step(cfg)
+    for band in ("resp", "hr"):
+        ops[f"fir_{band}"] = o.lt_create(vecs[f"fir_{band}"], n1, lv["fir"])
+        for part in ("dft_re", "dft_im"):
+            ops[f"{part}_{band}"] = enc(f"{part}_{band}", lv["dft"])
+        for part in ("freq", "mask"):
+            ops[f"{part}_{band}"] = enc(f"{part}_{band}", lv["freq"])
+    return ops
+
+
+def required_steps(o: Oracle, cfg: dict, ops: dict) -> list:
+    lay = layout(cfg, o.n_slots)
+    r = lay.bins
+    steps = {r * (1 << i) for i in range(lay.t2.bit_length() - 1)}
+    steps |= {1 << i for i in range(r.bit_length() - 1)}
+    steps.add(-r)
+    steps |= {-(1 << i) for i in range(lay.c_all.bit_length() - 1)}
+    for band in ("resp", "hr"):
+        steps |= set(o.lt_required_steps(ops[f"fir_{band}"]))
+    return sorted(steps)
+
+
+def _square_sum(o: Oracle, a: Ciphertext, b: Ciphertext, rlk) -> Ciphertext:
+    """a^2 + b^2, relinearized and rescaled."""
+    return o.rescale(o.relinearize(o.add(o.tensor(a, a), o.tensor(b, b)), rlk))
+
+
+def _mul(o: Oracle, a: Ciphertext, b: Ciphertext, rlk) -> Ciphertext:
+    return o.rescale(o.relinearize(o.tensor(a, b), rlk))
+
+
+def _rotsum(o: Oracle, c: Ciphertext, step: int, count: int, gks) -> Ciphertext:
+    """c + Rot(c, step) + ... over `count` (a power of two) shifts, by doubling."""
+    s = step
+    while s < step * count:
+        c = o.add(c, o.rotate(c, s, gks))
+        s *= 2
+    return c
+
+
+def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gks: dict,
+             rlk) -> dict:
+    lay = layout(cfg, o.n_slots)
+    r, t2 = lay.bins, lay.t2
+    out = {}
+    # K1: energy per bin
+    p = _square_sum(o, re, im, rlk)
+    e = _rotsum(o, p, r, t2, gks)
+    # K2: soft power attention over bins (gamma = 2)
+    w = _mul(o, e, e, rlk)
+    out["num_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_index"])), 1, r, gks)
+    out["den_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_mask"])), 1, r, gks)
+    # K4: soft I/Q (P_phi = 2)
+    m = _mul(o, p, p, rlk)
+    re2, im2 = o.drop_level(re, m.level), o.drop_level(im, m.level)
+    i_t = _rotsum(o, _mul(o, m, re2, rlk), 1, r, gks)
+    q_t = _rotsum(o, _mul(o, m, im2, rlk), 1, r, gks)
+    # K5: FIR into the two bands
+    terms = [(ops["fir_resp"], 0, 0, 1), (ops["fir_resp"], 1, 1, 1),
+             (ops["fir_hr"], 0, 2, 1), (ops["fir_hr"], 1, 3, 1)]
+    filt = [o.rescale(c) for c in o.lt_eval([i_t, q_t], terms, gks, 4, hoist=True,
+                                                hoist_giant=True)]
+    # K7 and K3 per band
+    x_re = x_im = None
+    for band, (fi, fq) in (("resp", (filt[0], filt[1])), ("hr", (filt[2], filt[3]))):
+        fi1, fq1 = o.rotate(fi, -r, gks), o.rotate(fq, -r, gks)
+        y = o.rescale(o.relinearize(o.sub(o.tensor(fq, fi1), o.tensor(fi, fq1)), rlk))
+        if cfg["taylor_order"] == 3:
+            x = o.rescale(o.relinearize(o.add(o.tensor(fi, fi1), o.tensor(fq, fq1)), rlk))
+            x2 = _mul(o, x, x, rlk)
+            a = _mul(o, o.drop_level(y, x2.level), x2, rlk)
+            y2 = _mul(o, y, y, rlk)
+            yc = o.rescale(o.mul_plain(y, ops["third"]))
+            dphi = o.sub(a, _mul(o, yc, y2, rlk))
+        else:
+            dphi = y
+        c = lay.c_resp if band == "resp" else lay.c_all
+        rep = dphi
+        s = 1
+        while s < c:
+            rep = o.add(rep, o.rotate(rep, -s, gks))
+            s *= 2
+        xr = _rotsum(o, o.rescale(o.mul_plain(rep, ops[f"dft_re_{band}"])), r, t2, gks)
+        xi = _rotsum(o, o.rescale(o.mul_plain(rep, ops[f"dft_im_{band}"])), r, t2, gks)
+        x_re = xr if x_re is None else o.add(x_re, xr)
+        x_im = xi if x_im is None else o.add(x_im, xi)
+    # K1 on the spectrum, K2: sharpening and weighted frequency average
+    pw = _square_sum(o, x_re, x_im, rlk)
+    sh = _mul(o, pw, pw, rlk)
+    for band in ("resp", "hr"):
+        out[f"num_{band}"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops[f"freq_{band}"])), 1,
+                                     lay.c_all, gks)
+        out[f"den_{band}"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops[f"mask_{band}"])), 1,
+                                     lay.c_all, gks)
+    return out
+
+
+def plain(cfg: dict, z: np.ndarray) -> dict:
+    """The same circuit on plaintext numbers (z: [frames][bins] complex): the
+    'mmFHE on plaintext' comparison of section 5.1."""
+    f, r = cfg["frames"], cfg["bins"]
+    re, im = z.real, z.imag
+    p = re ** 2 + im ** 2
+    e = p.sum(axis=0)
+    w = e ** 2
+    out = {"num_bin": float(np.sum(np.arange(r) * w) / f ** 2),
+           "den_bin": float(np.sum(w) / f ** 2)}
+    m = p ** 2
+    i_t = (m * re).sum(axis=1)
+    q_t = (m * im).sum(axis=1)
+    win = np.asarray(cfg["window"])
+    t = np.arange(f)
+    spec = {}
+    for band in ("resp", "hr"):
+        h = np.asarray(cfg[f"taps_{band}"])
+        half = (len(h) - 1) // 2
+
+        def fir(x):
+            y = np.zeros(f)
+            for k in range(-half, half + 1):
+                lo, hi = max(0, -k), min(f, f - k)
+                y[lo:hi] += h[k + half] * x[lo + k:hi + k]
+            return y
+
+        fi, fq = fir(i_t), fir(q_t)
+        fi1 = np.concatenate([[0.0], fi[:-1]])
+        fq1 = np.concatenate([[0.0], fq[:-1]])
+        y = fq * fi1 - fi * fq1
+        if cfg["taylor_order"] == 3:
+            x = fi * fi1 + fq * fq1
+            dphi = y * x ** 2 - y ** 3 / 3
+        else:
+            dphi = y
+        ks = np.asarray(cfg[f"k_{band}"])
+        ws = win.sum() / cfg["dft_gain"]
+        xr = np.array([np.sum(win * np.cos(2 * np.pi * k * t / f) * dphi) for k in ks]) / ws
+        xi = np.array([-np.sum(win * np.sin(2 * np.pi * k * t / f) * dphi) for k in ks]) / ws
+        s = (xr ** 2 + xi ** 2) ** 2
+        fk = 60.0 * ks * cfg["fps"] / f
+        out[f"num_{band}"] = float(np.sum(fk * s))
+        out[f"den_{band}"] = float(np.sum(s))
+    return out
+
+
+def encrypt_window(o: Oracle, s, z: np.ndarray, level: int, scale: float, seed: int):
+    """Re and Im of a [frames][bins] window packed frame-major (slot t R + r)."""
+    v = np.zeros(o.n_slots, dtype=np.complex128)
+    v[: z.size] = z.reshape(-1)
+    return (o.encrypt_sk(s, o.encode(v.real, scale, level), seed),
+            o.encrypt_sk(s, o.encode(v.imag, scale, level), seed + 1))

@@ -82,6 +82,8 @@ SIGNATURES = {
     "hck_apply_galois": ([_P, _P, _U32, _P, _P], _I),
     "hck_rotate_many": ([_P, _P, _U32, _I32, _P, _P], _I),
     "hck_rotate_steps": ([_P, _P, _P, _U32, _P, _P], _I),
+    "hck_vital_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
+    "hck_vital_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_keyswitch": ([_P, _P, _P, _P], _I),
@@ -257,6 +259,32 @@ class Ciphertext(_Handle):
 
 class LinearTransform(_Handle):
     _destroy = staticmethod(lambda h: capi.hck_lt_destroy(h))
+
+
+class VitalPlan(ctypes.Structure):
+    """hck_vital_plan: layout of one vital-sign window and its public operands."""
+    _fields_ = [("frames", ctypes.c_uint32), ("bins", ctypes.c_uint32),
+                ("taylor_order", ctypes.c_uint32), ("lanes_resp", ctypes.c_uint32),
+                ("lanes_hr", ctypes.c_uint32)] + [
+        (name, ctypes.c_void_p) for name in (
+            "bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
+            "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq_resp", "mask_resp", "freq_hr",
+            "mask_hr")]
+
+    OPERANDS = ("bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
+                "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq_resp", "mask_resp", "freq_hr",
+                "mask_hr")
+
+    @classmethod
+    def build(cls, frames, bins, taylor_order, lanes_resp, lanes_hr, operands: dict):
+        """operands: name -> Plaintext / LinearTransform handle (kept alive by
+        the plan object)."""
+        plan = cls(frames, bins, taylor_order, lanes_resp, lanes_hr)
+        plan._keep = dict(operands)
+        for name in cls.OPERANDS:
+            h = operands.get(name)
+            setattr(plan, name, h.h if h is not None else None)
+        return plan
 
 
 def _stream_handle(stream):
@@ -532,6 +560,23 @@ class Context:
         _check(capi.hck_lt_eval(self.h, ins, len(inputs), lts, _ptr(ti), _ptr(to), _ptr(ts),
                                 len(terms), gks, outs, len(outputs),
                                 (1 if hoist else 0) | (2 if hoist_giant else 0)))
+        return outputs
+
+    # --- vital-sign pipeline ---
+    def vital_required_steps(self, plan: VitalPlan) -> list:
+        n = ctypes.c_uint32()
+        _check(capi.hck_vital_required_steps(self.h, ctypes.addressof(plan), None, 0,
+                                             ctypes.byref(n)))
+        buf = (ctypes.c_int32 * max(1, n.value))()
+        _check(capi.hck_vital_required_steps(self.h, ctypes.addressof(plan), buf, n.value,
+                                             ctypes.byref(n)))
+        return list(buf[: n.value])
+
+    def vital_eval(self, plan: VitalPlan, re, im, gks, rlk, outputs=None):
+        """The six outputs num_bin, den_bin, num_resp, den_resp, num_hr, den_hr."""
+        outputs = [self.ciphertext() for _ in range(6)] if outputs is None else outputs
+        outs = (ctypes.c_void_p * 6)(*[c.h for c in outputs])
+        _check(capi.hck_vital_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs))
         return outputs
 
     # --- kernel timing ---

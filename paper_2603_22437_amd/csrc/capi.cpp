@@ -971,21 +971,6 @@ int hck_lt_required_steps(const hck_linear_transform *lt, int32_t *steps, uint32
   return HCK_OK;
 }
 
-// Pooled scratch ciphertexts of the linear-transform evaluator.
-static hck_ciphertext *pool_get(hck_context *ctx) {
-  if (!ctx->ct_pool.empty()) {
-    hck_ciphertext *ct = ctx->ct_pool.back();
-    ctx->ct_pool.pop_back();
-    return ct;
-  }
-  hck_ciphertext *ct = new hck_ciphertext();
-  ct->ctx = ctx;
-  return ct;
-}
-
-static void pool_put(hck_context *ctx, hck_ciphertext *ct) {
-  if (ct) ctx->ct_pool.push_back(ct);
-}
 
 int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int32_t *steps,
                      uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {

@@ -119,4 +119,21 @@ int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
   return apply_galois_many(ctx, &a, 1, g, gks, &out);
 }
 
+// Pooled scratch ciphertexts of the host-side evaluators (returned empty or
+// with their last contents; the context frees them).
+hck_ciphertext *pool_get(hck_context *ctx) {
+  if (!ctx->ct_pool.empty()) {
+    hck_ciphertext *ct = ctx->ct_pool.back();
+    ctx->ct_pool.pop_back();
+    return ct;
+  }
+  hck_ciphertext *ct = new hck_ciphertext();
+  ct->ctx = ctx;
+  return ct;
+}
+
+void pool_put(hck_context *ctx, hck_ciphertext *ct) {
+  if (ct) ctx->ct_pool.push_back(ct);
+}
+
 }  // namespace hck

@@ -324,6 +324,9 @@ int apply_galois_multi(hck_context *ctx, const hck_ciphertext *const *a, const u
 int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *const *out);
 size_t ws_ks_rows(const hck_context *ctx);   // rows of one batch slot of ws_ks
+// scratch ciphertexts owned by the context
+hck_ciphertext *pool_get(hck_context *ctx);
+void pool_put(hck_context *ctx, hck_ciphertext *ct);
 int apply_galois_core(hck_context *ctx, const hck_ciphertext *a, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *out);
 // runs ntt_forward / ntt_inverse over maps longer than one launch allows

@@ -1,0 +1,89 @@
+"""Public operands of the vital-sign pipeline (hck_vital_eval): the slot
+vectors of the masks, index and frequency weights, the FIR transforms'
+diagonals and the DFT weights for a window of F frames x R bins packed
+frame-major (slot t R + r), encoded with this library's encoder.
+
+This is plaintext setup (the pipeline's public weights, section 3.3.3);
+every homomorphic step runs in the library.
+"""
+import numpy as np
+
+
+def _next_pow2(x: int) -> int:
+    return 1 << max(0, (int(x) - 1).bit_length())
+
+
+def plan_levels(taylor_order: int, level0: int) -> dict:
+    """Level at which each operand is applied, for inputs at level0."""
+    dft = level0 - (7 if taylor_order == 3 else 5)
+    return dict(bins=level0 - 2, fir=level0 - 3, third=level0 - 5, dft=dft, freq=dft - 3)
+
+
+def operand_vectors(cfg: dict, n_slots: int) -> dict:
+    """name -> real slot vector (FIR transforms: offset -> diagonal vector)."""
+    F, R = cfg["frames"], cfg["bins"]
+    if _next_pow2(F) * R > n_slots:
+        raise ValueError("window does not fit the slots")
+    frames = np.arange(F)
+    out = {}
+    zero = lambda: np.zeros(n_slots)
+    out["bin_index"], out["bin_mask"] = zero(), zero()
+    out["bin_index"][:R] = np.arange(R, dtype=np.float64) / (F * F)
+    out["bin_mask"][:R] = 1.0 / (F * F)
+    for band in ("resp", "hr"):
+        taps = np.asarray(cfg["taps_" + band], dtype=np.float64)
+        h = len(taps) // 2
+        diags = {}
+        for k in range(-h, h + 1):
+            rows = frames[(frames + k >= 0) & (frames + k < F)]
+            if rows.size == 0:
+                continue
+            d = zero()
+            d[rows * R] = taps[k + h]
+            diags[(k * R) % n_slots] = d
+        out["fir_" + band] = diags
+    out["third"] = np.full(n_slots, 1.0 / 3.0)
+    win = np.asarray(cfg["window"], dtype=np.float64)
+    norm = cfg["dft_gain"] / win.sum()
+    lane0 = {"resp": 0, "hr": len(cfg["k_resp"])}
+    for band in ("resp", "hr"):
+        vr, vi, fq, mk = zero(), zero(), zero(), zero()
+        for lane, k in enumerate(cfg["k_" + band], start=lane0[band]):
+            ang = 2.0 * np.pi * k * frames / F
+            vr[frames * R + lane] = norm * win * np.cos(ang)
+            vi[frames * R + lane] = -norm * win * np.sin(ang)
+            fq[lane] = 60.0 * k * cfg["fps"] / F
+            mk[lane] = 1.0
+        out["dft_re_" + band], out["dft_im_" + band] = vr, vi
+        out["freq_" + band], out["mask_" + band] = fq, mk
+    return out
+
+
+def fir_baby_step(cfg: dict) -> int:
+    """Baby step of the FIR transforms (offsets are multiples of R): about
+    sqrt(taps) frames."""
+    return cfg["bins"] * max(1, int(round(np.sqrt(len(cfg["taps_resp"])))))
+
+
+def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
+    """A VitalPlan with every operand encoded by the library at the level it
+    is applied, at scale q_level (a product then keeps the ciphertext scale)."""
+    from . import VitalPlan
+    vec = operand_vectors(cfg, ctx.n // 2) if vectors is None else vectors
+    lv = plan_levels(cfg["taylor_order"], level0)
+    q = ctx.q
+
+    def pt(name, level):
+        return ctx.encode(vec[name], float(q[level]), level)
+
+    ops = {"bin_index": pt("bin_index", lv["bins"]), "bin_mask": pt("bin_mask", lv["bins"]),
+           "third": pt("third", lv["third"])}
+    n1 = fir_baby_step(cfg)
+    for band in ("resp", "hr"):
+        ops["fir_" + band] = ctx.lt_create(vec["fir_" + band], n1, lv["fir"])
+        for name in ("dft_re_", "dft_im_"):
+            ops[name + band] = pt(name + band, lv["dft"])
+        for name in ("freq_", "mask_"):
+            ops[name + band] = pt(name + band, lv["freq"])
+    return VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"], len(cfg["k_resp"]),
+                           len(cfg["k_hr"]), ops)

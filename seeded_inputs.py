@@ -25,6 +25,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["CONFIGS", "params", "is_prime", "uniform_slots", "uniform_matrix",
+           "vital_window", "windowed_dft_matrix", "fir_bandpass", "vital_pipeline_config",
            "uniform_residues", "small_ints"]
 
 
@@ -194,3 +195,45 @@ def windowed_dft_matrix(d: int) -> np.ndarray:
     w = np.hanning(d)
     sig = (n + d // 2) % d
     return w[None, :] * np.exp(-2j * np.pi * np.outer(sig, n) / d) / w.sum()
+
+
+# ---- public constants of the vital-sign pipeline (plaintext DSP design) ----
+
+def fir_bandpass(taps: int, lo_hz: float, hi_hz: float, fs: float) -> np.ndarray:
+    """Zero-phase band-pass FIR taps h[k], k = -(taps-1)/2 .. (taps-1)/2: the
+    difference of two windowed-sinc low-passes (Hamming window), scaled to
+    unit gain at the band centre (the paper's K5 filters its soft I/Q into the
+    respiration and heart-rate bands)."""
+    if taps % 2 == 0:
+        raise ValueError("odd tap count")
+    k = np.arange(taps) - (taps - 1) // 2
+
+    def lowpass(fc):
+        return 2 * fc / fs * np.sinc(2 * fc / fs * k)
+
+    h = (lowpass(hi_hz) - lowpass(lo_hz)) * np.hamming(taps)
+    fc = 0.5 * (lo_hz + hi_hz)
+    gain = abs(np.sum(h * np.exp(-2j * np.pi * fc / fs * k)))
+    return h / gain
+
+
+def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
+                          taps: int = 41, taylor_order: int = 3, fir_gain: float = 5.0,
+                          dft_gain: float = 10.0) -> dict:
+    """The vital-sign pipeline's public parameters (section 3.3.3 example
+    pipeline): respiration 0.1-0.6 Hz and heart rate 0.8-2.5 Hz bands, the
+    FIR taps of each band (times fir_gain), the Hann window of the phase DFT
+    (its weights are w[t] dft_gain / sum w) and the DFT bins k (frequency
+    k fps / frames) inside each band.  The two gains are normalization
+    constants folded into public weights (as section 3.3.3 folds s^gamma / F
+    into W^(1)) so that the cubic Taylor term and the spectra stay near 1 on
+    unit-normalized windows."""
+    res = fps / frames
+    bands = {"resp": (0.1, 0.6), "hr": (0.8, 2.5)}
+    cfg = dict(frames=frames, bins=bins, fps=fps, taylor_order=taylor_order,
+               window=np.hanning(frames), dft_gain=dft_gain)
+    for name, (lo, hi) in bands.items():
+        cfg[f"taps_{name}"] = fir_gain * fir_bandpass(taps, lo, hi, fps)
+        cfg[f"k_{name}"] = list(range(int(np.ceil(lo / res - 1e-9)),
+                                      int(np.floor(hi / res + 1e-9)) + 1))
+    return cfg

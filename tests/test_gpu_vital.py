@@ -1,0 +1,106 @@
+"""The vital-sign pipeline on the GPU (hck_vital_eval).
+
+* N = 2^15, L = 12 (the third-order circuit's 11 levels): residues of all six
+  outputs bit-exact against the oracle's pipeline, both sides fed the same
+  integer operands (encoded once by the oracle) and the same encrypted
+  window.
+* N = 2^16, L = 24 (the benchmark ring), with the library's own encoder:
+  decoded outputs against the circuit on plaintext numbers.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2603_22437_amd as H
+import seeded_inputs as S
+from oracle import vital as OV
+from paper_2603_22437_amd import vital as HV
+
+pytestmark = pytest.mark.gpu
+
+
+def _import_plan(ctx, o, cfg, ops):
+    """GPU plan holding the oracle's encoded operands."""
+    handles = {}
+    for name, v in ops.items():
+        if isinstance(v, O.LinearTransform):
+            res = {g * v.n1 + b: pt.res for g, items in v.groups.items() for b, pt in items}
+            handles[name] = ctx.lt_create_from_residues(res, v.n1, v.level, v.scale)
+        else:
+            handles[name] = ctx.plaintext_import(v.res, v.level, v.scale)
+    return H.VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"],
+                             len(cfg["k_resp"]), len(cfg["k_hr"]), handles)
+
+
+@pytest.mark.parametrize("order", [3, 1])
+def test_vital_pipeline_matches_oracle(order):
+    prm = S.params("mix15")
+    o = O.Oracle(prm)
+    ctx = H.Context.from_params(prm)
+    s_o = o.keygen_secret(1)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config(taylor_order=order)
+    z = S.vital_window(1001, cfg["frames"], cfg["bins"])
+    l0 = o.L - 1
+    ops = OV.encode_operands(o, cfg, l0)
+    plan = _import_plan(ctx, o, cfg, ops)
+    steps = OV.required_steps(o, cfg, ops)
+    assert ctx.vital_required_steps(plan) == steps
+    gko = {o.galois_element(k): o.keygen_galois(s_o, o.galois_element(k), 5) for k in steps}
+    rlk_o = o.keygen_relin(s_o, 7)
+    gks = ctx.keygen_rotation(sk, steps, 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    re_o, im_o = OV.encrypt_window(o, s_o, z, l0, prm["scale"], 100)
+    re = ctx.ciphertext_import(re_o.polys, l0, re_o.scale)
+    im = ctx.ciphertext_import(im_o.polys, l0, im_o.scale)
+    got = ctx.vital_eval(plan, re, im, gks, rlk)
+    want = OV.evaluate(o, cfg, ops, re_o, im_o, gko, rlk_o)
+    for name, g in zip(OV.OUTPUTS, got):
+        res, lvl, sc = ctx.ciphertext_export(g)
+        assert lvl == want[name].level, name
+        assert sc == want[name].scale, name
+        assert np.array_equal(res, want[name].polys), name
+
+
+def test_vital_pipeline_decodes_at_benchmark_ring():
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1002, cfg["frames"], cfg["bins"])
+    l0 = len(prm["q"]) - 1
+    plan = HV.encode_plan(ctx, cfg, l0)
+    gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: z.size] = z.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 101)
+    got = ctx.vital_eval(plan, re, im, gks, rlk)
+    want = OV.plain(cfg, z)
+    for name, g in zip(OV.OUTPUTS, got):
+        val = ctx.decode(ctx.decrypt(sk, g))[0].real
+        assert abs(val - want[name]) < 1e-3, (name, val, want[name])
+    # the client's divisions (section 3.3.4)
+    num, den = (ctx.decode(ctx.decrypt(sk, got[i]))[0].real for i in (0, 1))
+    assert abs(num / den - want["num_bin"] / want["den_bin"]) < 1e-3
+
+
+def test_vital_plan_errors():
+    prm = S.params("mix15")
+    ctx = H.Context.from_params(prm)
+    cfg = S.vital_pipeline_config()
+    plan = HV.encode_plan(ctx, cfg, len(prm["q"]) - 1)
+    bad = H.VitalPlan.build(cfg["frames"], 48, 3, 6, 18, plan._keep)   # bins not 2^k
+    with pytest.raises(H.HckError):
+        ctx.vital_required_steps(bad)
+    sk = ctx.keygen_secret(1)
+    rlk = ctx.keygen_relin(sk, 7)
+    gks = ctx.keygen_rotation(sk, [1], 5)
+    low = ctx.encrypt_sk(sk, ctx.encode(np.zeros(ctx.n_slots), prm["scale"], 5), 3)
+    with pytest.raises(H.HckError):   # level 5 < depth 11
+        ctx.vital_eval(plan, low, low, gks, rlk)
+    top = ctx.encrypt_sk(sk, ctx.encode(np.zeros(ctx.n_slots), prm["scale"],
+                                        len(prm["q"]) - 1), 4)
+    with pytest.raises(H.HckError):   # keys missing
+        ctx.vital_eval(plan, top, top, gks, rlk)

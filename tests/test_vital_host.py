@@ -1,0 +1,67 @@
+"""Host-side checks of the vital-sign pipeline (no GPU): the library's
+operand builder against the oracle's, the oracle pipeline against the same
+circuit on plaintext numbers, and the C ABI's plan checks."""
+import numpy as np
+import pytest
+
+import oracle as O
+import seeded_inputs as S
+from oracle import vital as OV
+from paper_2603_22437_amd import vital as HV
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_operand_vectors_match_oracle(order):
+    cfg = S.vital_pipeline_config(taylor_order=order)
+    n_slots = 1 << 14
+    a = HV.operand_vectors(cfg, n_slots)
+    b = OV.operand_vectors(cfg, n_slots)
+    assert set(a) == set(b)
+    for k in a:
+        if isinstance(a[k], dict):
+            assert set(a[k]) == set(b[k]), k
+            for off in a[k]:
+                np.testing.assert_allclose(a[k][off], b[k][off], rtol=0, atol=1e-15)
+        else:
+            np.testing.assert_allclose(a[k], b[k], rtol=0, atol=1e-15, err_msg=k)
+    assert HV.fir_baby_step(cfg) == OV.fir_baby_step(cfg)
+    lv = OV.levels(cfg, 23)
+    hl = HV.plan_levels(order, 23)
+    assert (hl["bins"], hl["fir"], hl["third"], hl["dft"], hl["freq"]) == (
+        lv["bin_index"], lv["fir"], lv["third"], lv["dft"], lv["freq"])
+
+
+def test_plain_circuit_is_the_dsp_it_approximates():
+    """The plaintext mirror: the bin estimate lands on the synthetic target
+    bin, and with a small phase step the cubic Taylor term is arctan(y/x) x^3
+    to third order (its defining property)."""
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1000, cfg["frames"], cfg["bins"])
+    out = OV.plain(cfg, z)
+    target = int(np.argmax(np.abs(z).sum(axis=0)))
+    assert abs(out["num_bin"] / out["den_bin"] - target) < 1.0
+    y, x = 1e-2, 1.0
+    assert abs((y * x ** 2 - y ** 3 / 3) - np.arctan2(y, x) * x ** 3) < 1e-9
+
+
+@pytest.mark.slow
+def test_oracle_pipeline_decodes_to_plain_circuit():
+    """The oracle pipeline at N = 2^15 (L = 12: the 11 levels of the third
+    order circuit) decodes to the plaintext circuit's numbers."""
+    prm = S.params("mix15")
+    o = O.Oracle(prm)
+    s = o.keygen_secret(1)
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1000, cfg["frames"], cfg["bins"])
+    l0 = o.L - 1
+    ops = OV.encode_operands(o, cfg, l0)
+    steps = OV.required_steps(o, cfg, ops)
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5) for k in steps}
+    rlk = o.keygen_relin(s, 7)
+    re, im = OV.encrypt_window(o, s, z, l0, prm["scale"], 100)
+    out = OV.evaluate(o, cfg, ops, re, im, gks, rlk)
+    want = OV.plain(cfg, z)
+    for k in OV.OUTPUTS:
+        assert out[k].level == (l0 - 3 if k.endswith("bin") else 0)
+        got = o.decode(o.decrypt(s, out[k]))[0].real
+        assert abs(got - want[k]) < 1e-6 * max(1.0, abs(want[k])), k
