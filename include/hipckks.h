@@ -274,8 +274,9 @@ int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_cip
  * all outputs are combined before the giant rotations (Rot(A) + Rot(B) =
  * Rot(A + B)); all giant rotations are key-switched together in batches.
  * All inputs share one level and all transforms that level and one baby
- * step; term_sign may be NULL (all +1) and holds +1 or -1; at most 4 inputs
- * and 4 outputs.  Outputs may alias inputs.  flags:
+ * step; term_sign may be NULL (all +1) and holds +1 or -1; at most 4 inputs,
+ * 4 outputs and 64 giant groups, and no (transform, input, output) twice.
+ * Outputs may alias inputs.  flags:
  *   HCK_LT_HOIST_BABY   each input's baby rotations are hoisted rotations
  *                       (hck_rotate_hoisted);
  *   HCK_LT_HOIST_GIANT  an output's giant rotations share one ModDown: their

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <deque>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -878,18 +879,34 @@ static int lt_finish_create(hck_context *ctx, const std::vector<std::vector<uint
   lt->n1 = baby_step;
   lt->level = level;
   lt->scale = pt_scale;
-  int rc = HCK_OK;
+  std::vector<int32_t> gs(n_diag), bs(n_diag);
+  for (uint32_t d = 0; d < n_diag; d++) {
+    gs[d] = (int32_t)std::floor((double)offsets[d] / (double)baby_step);
+    bs[d] = offsets[d] - gs[d] * (int32_t)baby_step;
+  }
+  lt->giants = gs;
+  lt->babies = bs;
+  for (auto *v : {&lt->giants, &lt->babies}) {
+    std::sort(v->begin(), v->end());
+    v->erase(std::unique(v->begin(), v->end()), v->end());
+  }
+  const size_t per = (size_t)(level + 1) * ctx->n;
+  const size_t cells = lt->giants.size() * lt->babies.size();
+  int rc = dev_alloc(ctx, &lt->grid, cells * per);
+  if (!rc) {
+    lt->owned.push_back(lt->grid);
+    const hipError_t e = hipMemsetAsync(lt->grid, 0, cells * per * sizeof(uint64_t), ctx->stream);
+    if (e != hipSuccess) rc = check_hip(ctx, e, "hipMemsetAsync");
+  }
   for (uint32_t d = 0; d < n_diag && !rc; d++) {
-    const int32_t k = offsets[d];
-    const int32_t g = (int32_t)std::floor((double)k / (double)baby_step);
-    const int32_t b = k - g * (int32_t)baby_step;
-    uint64_t *p = nullptr;
-    rc = dev_alloc(ctx, &p, (size_t)(level + 1) * ctx->n);
-    if (rc) break;
-    lt->owned.push_back(p);
+    const size_t gi = std::lower_bound(lt->giants.begin(), lt->giants.end(), gs[d]) -
+                      lt->giants.begin();
+    const size_t bi = std::lower_bound(lt->babies.begin(), lt->babies.end(), bs[d]) -
+                      lt->babies.begin();
+    uint64_t *p = lt->grid + (gi * lt->babies.size() + bi) * per;
     rc = import_rows(ctx, p, res[d].data(), 1, level + 1, level + 1);
     if (!rc) rc = mont_rows(ctx, p, poly_rows(1, level + 1, level + 1), true);
-    lt->groups[g].push_back({b, p});
+    lt->groups[gs[d]].push_back({bs[d], p});
   }
   if (rc) {
     hck_lt_destroy(lt);
@@ -1179,7 +1196,7 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
   }
   if (n_in > (uint32_t)kLtIn || n_out > (uint32_t)kLtOut)
     rc = rc ? rc : set_error(HCK_EINVAL, "at most 4 inputs and 4 outputs per evaluation");
-  // distinct transforms, in order of first use, processed two per pass
+  // distinct transforms, in order of first use, processed two per launch
   std::vector<const hck_linear_transform *> uniq;
   std::vector<uint32_t> term_lt(n_terms);
   for (uint32_t t = 0; t < n_terms; t++) {
@@ -1187,66 +1204,83 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
     term_lt[t] = (uint32_t)(it - uniq.begin());
     if (it == uniq.end()) uniq.push_back(lts[t]);
   }
-  std::vector<int32_t> giants;
+  std::vector<int32_t> giants, babies;
   for (auto &kv : giant_outputs) giants.push_back(kv.first);
-  // inner[gi][o]: the inner sum of giant group gi for output o (null when the
-  // output has no term in that group)
-  std::vector<std::vector<hck_ciphertext *>> inner(giants.size(),
-                                                   std::vector<hck_ciphertext *>(n_out, nullptr));
-  for (size_t gi = 0; gi < giants.size(); gi++)
-    for (uint32_t o : giant_outputs[giants[gi]]) {
-      inner[gi][o] = get();
-      if (!rc) rc = ensure_ct(ctx, inner[gi][o], 2);
-    }
-  const uint32_t chunk = (n_in <= 2 && n_out <= 2) ? 4 : 2;
-  for (size_t g0 = 0; g0 < giants.size() && !rc; g0 += chunk) {
-    const uint32_t ng = (uint32_t)std::min<size_t>(chunk, giants.size() - g0);
-    bool first_pass = true;
-    for (size_t l0 = 0; l0 < uniq.size() && !rc; l0 += kLtLts)
-      for (uint32_t b0 = 0; b0 < n1 && !rc; b0 += kLtN1) {
-        LtInnerArgs la;
-        std::memset(&la, 0, sizeof(la));
-        la.n1 = std::min<uint32_t>(kLtN1, n1 - b0);
-        la.ng = ng;
-        la.n_in = n_in;
-        la.n_out = n_out;
-        la.ps = ps;
-        la.accumulate = first_pass ? 0 : 1;
-        for (uint32_t gi = 0; gi < ng; gi++) {
-          for (uint32_t l = 0; l < (uint32_t)kLtLts && l0 + l < uniq.size(); l++) {
-            auto it = uniq[l0 + l]->groups.find(giants[g0 + gi]);
-            if (it == uniq[l0 + l]->groups.end()) continue;
-            for (auto &bp : it->second)
-              if ((uint32_t)bp.first >= b0 && (uint32_t)bp.first < b0 + la.n1)
-                la.pt[gi][l][bp.first - b0] = bp.second;
-          }
-          for (uint32_t o = 0; o < n_out; o++)
-            if (inner[g0 + gi][o]) la.inner[gi][o] = inner[g0 + gi][o]->data;
+  for (auto &kv : baby_inputs) babies.push_back(kv.first);
+  if (giants.size() > (size_t)kLtMaxG)
+    rc = rc ? rc : set_error(HCK_EINVAL, "more than 64 giant groups in one evaluation");
+  const uint32_t ng = (uint32_t)giants.size();
+  if (!rc) rc = ensure_lt_scratch(ctx, (size_t)ng * n_out * 2 * ps);
+  if (!rc) rc = ensure_zero_rows(ctx);
+  uint64_t *sums = ctx->lt_scratch;
+  // inner sums of every (giant group, output), babies in chunks that fit LDS
+  const uint32_t bchunk = std::min<uint32_t>((uint32_t)kLtB, 64 / n_in);
+  bool first = true;
+  for (size_t l0 = 0; l0 < uniq.size() && !rc; l0 += kLtLts)
+    for (size_t b0 = 0; b0 < babies.size() && !rc; b0 += bchunk) {
+      LtSumArgs la;
+      std::memset(&la, 0, sizeof(la));
+      la.nb = (uint32_t)std::min<size_t>(bchunk, babies.size() - b0);
+      la.ng = ng;
+      la.n_in = n_in;
+      la.n_out = n_out;
+      la.ps = ps;
+      la.accumulate = first ? 0 : 1;
+      la.sums = sums;
+      la.zero = ctx->zero_rows;
+      for (uint32_t l = 0; l < (uint32_t)kLtLts && l0 + l < uniq.size(); l++) {
+        const hck_linear_transform *lt = uniq[l0 + l];
+        la.grid[l] = lt->grid;
+        la.grid_nb[l] = (uint32_t)lt->babies.size();
+        la.grid_rows[l] = lt->level + 1;
+        for (uint32_t g = 0; g < ng; g++) {
+          auto git = std::lower_bound(lt->giants.begin(), lt->giants.end(), giants[g]);
+          const bool has_g = git != lt->giants.end() && *git == giants[g];
+          la.gmap[l][g] = has_g ? (int32_t)(git - lt->giants.begin()) : -1;
+          auto grp = lt->groups.find(giants[g]);
+          for (uint32_t b = 0; b < la.nb && has_g && grp != lt->groups.end(); b++)
+            for (auto &bp : grp->second)
+              if (bp.first == babies[b0 + b]) la.present[l][g] |= 1u << b;
         }
-        for (uint32_t i = 0; i < n_in; i++)
-          for (uint32_t b = 0; b < la.n1; b++) {
-            auto it = baby.find({i, (int32_t)(b0 + b)});
-            if (it != baby.end()) la.baby[i][b] = it->second->data;
-          }
-        std::vector<uint32_t> per_out(n_out, 0);
-        for (uint32_t t = 0; t < n_terms; t++) {
-          if (term_lt[t] < l0 || term_lt[t] >= l0 + kLtLts) continue;
-          if (la.n_terms == (uint32_t)kLtTerms) {
-            rc = set_error(HCK_EINVAL, "too many terms per transform pair");
-            break;
-          }
-          la.term_lt[la.n_terms] = (uint8_t)(term_lt[t] - l0);
-          la.term_in[la.n_terms] = (uint8_t)term_in[t];
-          la.term_out[la.n_terms] = (uint8_t)term_out[t];
-          la.term_neg[la.n_terms] = (term_sign && term_sign[t] < 0) ? 1 : 0;
-          la.n_terms++;
-          per_out[term_out[t]]++;
+        for (uint32_t b = 0; b < la.nb; b++) {
+          auto bit = std::lower_bound(lt->babies.begin(), lt->babies.end(), babies[b0 + b]);
+          la.bmap[l][b] = (bit != lt->babies.end() && *bit == babies[b0 + b])
+                              ? (int32_t)(bit - lt->babies.begin())
+                              : -1;
         }
-        la.max_terms = std::max<uint32_t>(1, *std::max_element(per_out.begin(), per_out.end()));
-        if (!rc) rc = launch_lt_inner(ctx, la, level);
-        first_pass = false;
       }
-  }
+      for (uint32_t i = 0; i < n_in; i++)
+        for (uint32_t b = 0; b < la.nb; b++) {
+          auto it = baby.find({i, babies[b0 + b]});
+          if (it != baby.end()) la.baby[i][b] = it->second->data;
+        }
+      std::vector<uint32_t> per_out(n_out, 0);
+      for (uint32_t t = 0; t < n_terms; t++) {
+        if (term_lt[t] < l0 || term_lt[t] >= l0 + kLtLts) continue;
+        int8_t &c = la.coef[term_lt[t] - l0][term_in[t]][term_out[t]];
+        if (c != 0) {
+          rc = set_error(HCK_EINVAL, "repeated (transform, input, output) term");
+          break;
+        }
+        c = (term_sign && term_sign[t] < 0) ? -1 : 1;
+        per_out[term_out[t]]++;
+      }
+      la.max_terms = std::max<uint32_t>(1, *std::max_element(per_out.begin(), per_out.end()));
+      if (!rc) rc = launch_lt_sums(ctx, la, level);
+      first = false;
+    }
+  // the (group, output) sums that have terms, as ciphertexts over the scratch
+  std::deque<hck_ciphertext> views;
+  std::vector<std::vector<hck_ciphertext *>> inner(ng, std::vector<hck_ciphertext *>(n_out, nullptr));
+  for (uint32_t gi = 0; gi < ng; gi++)
+    for (uint32_t o : giant_outputs[giants[gi]]) {
+      views.emplace_back();
+      hck_ciphertext &v = views.back();
+      v.ctx = ctx;
+      v.data = sums + ((size_t)gi * n_out + o) * 2 * ps;
+      v.cap_polys = 2;
+      inner[gi][o] = &v;
+    }
   // every output is the sum over its groups g of Rot(inner_g, g n1); the
   // inputs are no longer read, so outputs may alias them
   struct Part {

@@ -108,6 +108,26 @@ int ensure_workspace(hck_context *ctx, size_t words) {
   return HCK_OK;
 }
 
+int ensure_lt_scratch(hck_context *ctx, size_t words) {
+  if (ctx->lt_scratch_words >= words) return HCK_OK;
+  dev_free(ctx, ctx->lt_scratch);
+  ctx->lt_scratch = nullptr;
+  ctx->lt_scratch_words = 0;
+  int rc = dev_alloc(ctx, &ctx->lt_scratch, words);
+  if (rc) return rc;
+  ctx->lt_scratch_words = words;
+  return HCK_OK;
+}
+
+int ensure_zero_rows(hck_context *ctx) {
+  if (ctx->zero_rows) return HCK_OK;
+  const size_t words = (size_t)ctx->L * ctx->n;
+  int rc = dev_alloc(ctx, &ctx->zero_rows, words);
+  if (rc) return rc;
+  HCK_HIP(ctx, hipMemsetAsync(ctx->zero_rows, 0, words * sizeof(uint64_t), ctx->stream));
+  return HCK_OK;
+}
+
 LimbMap qmap(const hck_context *ctx, uint32_t level) {
   LimbMap m;
   m.n = level + 1;
@@ -360,6 +380,8 @@ void destroy_context(hck_context *ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx, ctx->ws);
+  dev_free(ctx, ctx->lt_scratch);
+  dev_free(ctx, ctx->zero_rows);
   for (hck_ciphertext *ct : ctx->ct_pool) {
     dev_free(ctx, ct->data);
     delete ct;

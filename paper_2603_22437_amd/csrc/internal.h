@@ -78,6 +78,9 @@ struct hck_context {
   // key-switch workspace (device)
   uint64_t *ws = nullptr;
   size_t ws_words = 0;
+  uint64_t *lt_scratch = nullptr;   // inner sums of the linear-transform evaluator
+  size_t lt_scratch_words = 0;
+  uint64_t *zero_rows = nullptr;    // [L][N] zeros (absent diagonals of the BSGS grid)
   // scratch ciphertexts reused by linear transforms
   std::vector<struct hck_ciphertext *> ct_pool;
 
@@ -100,20 +103,27 @@ struct hck_context {
 };
 
 namespace hck {
-// one launch of the fused linear-transform inner sums (lt_kernels.hip)
-constexpr int kLtG = 4;      // giant groups
-constexpr int kLtLts = 2;    // distinct transforms
+// one launch of the linear-transform inner sums (lt_kernels.hip)
+constexpr int kLtLts = 2;    // distinct transforms per launch
 constexpr int kLtIn = 4;     // inputs
 constexpr int kLtOut = 4;    // outputs
-constexpr int kLtN1 = 32;    // baby steps
-constexpr int kLtTerms = 8;  // (transform, input, output, sign) terms
-struct LtInnerArgs {
-  uint32_t n1, ng, n_in, n_out, n_terms, max_terms, accumulate;
-  size_t ps;                                   // polynomial stride of the ciphertexts
-  const uint64_t *pt[kLtG][kLtLts][kLtN1];     // diagonal (group, transform, baby) or null
-  const uint64_t *baby[kLtIn][kLtN1];          // baby rotation (input, b) or null
-  uint64_t *inner[kLtG][kLtOut];               // inner sum (group, output) or null
-  uint8_t term_lt[kLtTerms], term_in[kLtTerms], term_out[kLtTerms], term_neg[kLtTerms];
+constexpr int kLtB = 32;     // baby steps per launch
+constexpr int kLtMaxG = 64;  // giant groups per evaluation
+constexpr int kLtCoeffs = 64;  // coefficients per workgroup (one per lane)
+struct LtSumArgs {
+  uint32_t nb, ng, n_in, n_out, n_terms, max_terms, accumulate;
+  size_t ps;                                 // polynomial stride of baby ciphertexts / sums
+  const uint64_t *baby[kLtIn][kLtB];         // baby rotation (input, chunk baby) or null
+  const uint64_t *grid[kLtLts];              // transform's diagonal grid [giant][baby][limb][N]
+  uint32_t grid_nb[kLtLts];                  // babies of the transform's grid
+  uint32_t grid_rows[kLtLts];                // limbs per diagonal (transform level + 1)
+  int32_t gmap[kLtLts][kLtMaxG];             // evaluation giant -> transform giant, -1: none
+  int32_t bmap[kLtLts][kLtB];                // chunk baby -> transform baby, -1: none
+  uint32_t present[kLtLts][kLtMaxG];         // bit b: diagonal (giant, chunk baby b) exists
+  uint64_t *sums;                            // [ng][n_out] ciphertexts of 2 polys (stride ps)
+  const uint64_t *zero;                      // [L][N] zeros, read for absent diagonals
+  // sign of the term (transform, input -> output), 0: no such term
+  int8_t coef[kLtLts][kLtIn][kLtOut];
 };
 }  // namespace hck
 
@@ -160,6 +170,10 @@ struct hck_linear_transform {
   double scale = 1.0;
   // giant index g -> list of (baby step b, diagonal plaintext [level+1][N])
   std::map<int32_t, std::vector<std::pair<int32_t, uint64_t *>>> groups;
+  // the diagonals as one grid [giants][babies][level+1][N] (rows of absent
+  // diagonals are zero); giants and babies ascending
+  std::vector<int32_t> giants, babies;
+  uint64_t *grid = nullptr;
   std::vector<uint64_t *> owned;
 };
 
@@ -179,6 +193,8 @@ int dev_alloc(hck_context *ctx, uint64_t **p, size_t words);
 void dev_free(hck_context *ctx, void *p);
 int ensure_ct(hck_context *ctx, hck_ciphertext *ct, uint32_t polys);
 int ensure_workspace(hck_context *ctx, size_t words);
+int ensure_lt_scratch(hck_context *ctx, size_t words);
+int ensure_zero_rows(hck_context *ctx);
 
 // ---- kernel timing ----
 // `bytes` and `mulmods`: the launch's algorithmic HBM traffic and 64-bit
@@ -314,7 +330,8 @@ int keyswitch_core(hck_context *ctx, const uint64_t *d, uint32_t galois, uint32_
                    const hck_switch_key *key, uint64_t *out0, uint64_t *out1, const uint64_t *add0,
                    const uint64_t *add1);
 // fused inner sums of the linear-transform evaluator over limbs 0..level
-int launch_lt_inner(hck_context *ctx, const LtInnerArgs &a, uint32_t level);
+// inner sums of the linear-transform evaluator over limbs 0..level
+int launch_lt_sums(hck_context *ctx, const LtSumArgs &a, uint32_t level);
 // automorphisms a[i] -> phi_{g[i]}(a[i]) of n ciphertexts (same level), each
 // key-switched with its Galois key, in batches of kMaxBatch; outputs are
 // distinct and out[i] may alias a[i] (no other input)

@@ -1,135 +1,184 @@
 // Inner sums of the baby-step/giant-step linear transform (Kernel 3's
-// diagonal method) in one pass over memory.
+// diagonal method), all giant groups in one pass over the diagonals.
 //
-// For giant index g and output o the inner sum is
-//   inner[g][o] = sum over terms t of o, baby steps b:
-//                 sign_t pt_{lt_t, g, b} * Rot(x_{in_t}, b)
+// For giant group g and output o the inner sum is
+//   sums[g][o] = sum over terms t of o, baby steps b:
+//                sign_t pt_{lt_t, g, b} * Rot(x_{in_t}, b)
 // (pt_{lt, g, b} is the transform's diagonal g n1 + b, pre-rotated and cached
-// in evaluation + Montgomery form).  A thread owns one coefficient of one
-// limb and walks the baby steps once: it loads every input's baby rotation
-// once per pass, each cached diagonal exactly once, and keeps the sums of G
-// giant groups x O outputs x 2 polynomials in 128-bit registers, reduced by
-// one Montgomery REDC at the end (and at flushes, see below).  A negative
-// sign is folded into the ciphertext operand (q - x).
+// in evaluation + Montgomery form, in the transform's [giant][baby] grid).
+//
+// A workgroup owns kLtCoeffs consecutive coefficients of one limb.  It first
+// stages the baby rotations of its coefficients (every input, every baby step
+// of the launch, both polynomials) in LDS, read from HBM once for all giant
+// groups; then each of its 4 waves takes giant groups w, w + 4, ... (GW at a
+// time, round robin), one coefficient per lane, and streams those groups'
+// diagonals once,
+// keeping GW x O x 2 sums in 128-bit registers that are reduced by one
+// Montgomery REDC at the end (and at flushes, see below).  The terms enter as
+// a sign per (transform, input, output); a negative one multiplies by the
+// negated diagonal (q - w).
 #include "internal.h"
 
 namespace hck {
 
 namespace {
 
-template <int G, int O, int I>
-__global__ __launch_bounds__(256) void k_lt_inner(LtInnerArgs a, const ModConst *__restrict__ mc,
-                                                  int n) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+template <int GW, int O, int I>
+__global__ __launch_bounds__(256, 4) void k_lt_sums(LtSumArgs a, const ModConst *__restrict__ mc,
+                                                 int n) {
+  constexpr int C = kLtCoeffs;
+  extern __shared__ uint64_t xs[];  // [in][b][poly][C]
   const int limb = blockIdx.y;
+  const size_t base = (size_t)limb * n + (size_t)blockIdx.x * C;
+  const int nb = (int)a.nb;
+  const int total = (int)a.n_in * nb * 2 * C;
+  for (int idx = threadIdx.x; idx < total; idx += 256) {
+    const int c = idx % C;
+    const int r = idx / C;
+    const int p = r & 1, b = (r >> 1) % nb, in = (r >> 1) / nb;
+    const uint64_t *src = a.baby[in][b];
+    xs[idx] = src ? src[base + p * a.ps + c] : 0;
+  }
+  __syncthreads();
+  // the wave index is uniform across the wave: readfirstlane lets the
+  // compiler keep the giant tables, branches and diagonal addresses scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const ModConst m = mc[limb];
-  const size_t off = (size_t)limb * n + i;
+  const size_t off = base + lane;
   // products of values below q accumulate safely while their count stays
   // below 2^64 / q (the REDC input bound); each baby step adds up to
   // max_terms products to one sum.  A flush reduces a sum to r in [0, q) and
   // restarts it from r 2^64 mod q, which REDC maps back to r.
   const uint64_t per_flush = ~0ull / m.q - 1;
-  const uint32_t flush_b = (uint32_t)max<uint64_t>(1, per_flush / a.max_terms);
-  u128 acc[G][O][2];
+  const int flush_b = (int)max<uint64_t>(1, per_flush / a.max_terms);
+  // wave w takes giant groups w, w + 4, w + 8, ... (GW at a time), so the
+  // four waves of a workgroup stay within one group of each other
+  for (int g0 = wave; g0 < (int)a.ng; g0 += 4 * GW) {
+    u128 acc[GW][O][2];
 #pragma unroll
-  for (int g = 0; g < G; g++)
+    for (int gi = 0; gi < GW; gi++)
 #pragma unroll
-    for (int o = 0; o < O; o++)
+      for (int o = 0; o < O; o++)
 #pragma unroll
-      for (int p = 0; p < 2; p++) {
-        acc[g][o][p].lo = acc[g][o][p].hi = 0;
-        if (a.accumulate && g < (int)a.ng && o < (int)a.n_out && a.inner[g][o])
-          acc[g][o][p].lo = shoup(a.inner[g][o][off + p * a.ps], m.r64, m.r64_shoup, m.q);
-      }
-  uint32_t since = 0;
-  for (uint32_t b = 0; b < a.n1; b++) {
-    uint64_t x[I][2];
+        for (int p = 0; p < 2; p++) {
+          acc[gi][o][p].lo = acc[gi][o][p].hi = 0;
+          if (a.accumulate && g0 + 4 * gi < (int)a.ng && o < (int)a.n_out)
+            acc[gi][o][p].lo =
+                shoup(a.sums[((size_t)(g0 + 4 * gi) * a.n_out + o) * 2 * a.ps + p * a.ps + off],
+                      m.r64, m.r64_shoup, m.q);
+        }
+    // an absent diagonal reads a row of zeros, so every step issues all its
+    // loads without branches before any product; addresses are wave-uniform
+    // bases (scalar) plus the lane
+    int since = 0;
+    for (int b = 0; b < nb; b++) {
+      uint64_t x[I][2];
 #pragma unroll
-    for (int in = 0; in < I; in++) {
-      x[in][0] = x[in][1] = 0;
-      if (in < (int)a.n_in && a.baby[in][b]) {
-        x[in][0] = a.baby[in][b][off];
-        x[in][1] = a.baby[in][b][off + a.ps];
-      }
-    }
+      for (int in = 0; in < I; in++)
 #pragma unroll
-    for (int g = 0; g < G; g++) {
-      if (g >= (int)a.ng) break;
+        for (int p = 0; p < 2; p++)
+          x[in][p] = in < (int)a.n_in ? xs[((in * nb + b) * 2 + p) * C + lane] : 0;
+      uint64_t w[GW][kLtLts];
 #pragma unroll
       for (int l = 0; l < kLtLts; l++) {
-        const uint64_t *pp = a.pt[g][l][b];
-        if (!pp) continue;
-        const uint64_t w = pp[off];
 #pragma unroll
-        for (int t = 0; t < kLtTerms; t++) {
-          if (t >= (int)a.n_terms || a.term_lt[t] != l) continue;
-          const int in = a.term_in[t], o = a.term_out[t];
-#pragma unroll
-          for (int ii = 0; ii < I; ii++) {
-            if (ii != in) continue;
-#pragma unroll
-            for (int oo = 0; oo < O; oo++) {
-              if (oo != o) continue;
-              const uint64_t x0 = a.term_neg[t] ? m.q - x[ii][0] : x[ii][0];
-              const uint64_t x1 = a.term_neg[t] ? m.q - x[ii][1] : x[ii][1];
-              mac_wide(acc[g][oo][0], w, x0);
-              mac_wide(acc[g][oo][1], w, x1);
-            }
-          }
+        for (int gi = 0; gi < GW; gi++) {
+          const int g = g0 + 4 * gi;
+          const bool on = g < (int)a.ng && ((a.present[l][g] >> b) & 1u);
+          const uint64_t *row =
+              on ? a.grid[l] +
+                       (size_t)(a.gmap[l][g] * (int)a.grid_nb[l] + a.bmap[l][b]) * a.grid_rows[l] * n +
+                       base
+                 : a.zero + base;
+          w[gi][l] = row[lane];
         }
       }
-    }
-    if (++since == flush_b && b + 1 < a.n1) {
-      since = 0;
+      // a negative term multiplies by q - w (a transform's terms share w)
 #pragma unroll
-      for (int g = 0; g < G; g++)
+      for (int l = 0; l < kLtLts; l++) {
+        bool neg = false;
 #pragma unroll
-        for (int o = 0; o < O; o++)
+        for (int ii = 0; ii < I; ii++)
 #pragma unroll
-          for (int p = 0; p < 2; p++) {
-            acc[g][o][p].lo = shoup(redc(acc[g][o][p], m.q, m.qinv), m.r64, m.r64_shoup, m.q);
-            acc[g][o][p].hi = 0;
-          }
-    }
-  }
+          for (int oo = 0; oo < O; oo++) neg = neg || a.coef[l][ii][oo] < 0;
 #pragma unroll
-  for (int g = 0; g < G; g++)
+        for (int gi = 0; gi < GW; gi++) {
+          const uint64_t wn = neg ? m.q - w[gi][l] : 0;
 #pragma unroll
-    for (int o = 0; o < O; o++)
-      if (g < (int)a.ng && o < (int)a.n_out && a.inner[g][o]) {
-        a.inner[g][o][off] = redc(acc[g][o][0], m.q, m.qinv);
-        a.inner[g][o][off + a.ps] = redc(acc[g][o][1], m.q, m.qinv);
+          for (int ii = 0; ii < I; ii++)
+#pragma unroll
+            for (int oo = 0; oo < O; oo++) {
+              const int c = a.coef[l][ii][oo];
+              if (c == 0) continue;
+              const uint64_t ws = c < 0 ? wn : w[gi][l];
+              mac_wide(acc[gi][oo][0], ws, x[ii][0]);
+              mac_wide(acc[gi][oo][1], ws, x[ii][1]);
+            }
+        }
       }
+      if (++since == flush_b && b + 1 < nb) {
+        since = 0;
+#pragma unroll
+        for (int gi = 0; gi < GW; gi++)
+#pragma unroll
+          for (int o = 0; o < O; o++)
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+              acc[gi][o][p].lo =
+                  shoup(redc(acc[gi][o][p], m.q, m.qinv), m.r64, m.r64_shoup, m.q);
+              acc[gi][o][p].hi = 0;
+            }
+      }
+    }
+#pragma unroll
+    for (int gi = 0; gi < GW; gi++)
+#pragma unroll
+      for (int o = 0; o < O; o++)
+        if (g0 + 4 * gi < (int)a.ng && o < (int)a.n_out) {
+          uint64_t *dst = a.sums + ((size_t)(g0 + 4 * gi) * a.n_out + o) * 2 * a.ps + off;
+          dst[0] = redc(acc[gi][o][0], m.q, m.qinv);
+          dst[a.ps] = redc(acc[gi][o][1], m.q, m.qinv);
+        }
+  }
+}
+
+template <int GW, int O, int I>
+void launch(hck_context *ctx, const LtSumArgs &a, uint32_t nq) {
+  const size_t lds = (size_t)a.n_in * a.nb * 2 * kLtCoeffs * sizeof(uint64_t);
+  k_lt_sums<GW, O, I><<<dim3(ctx->n / kLtCoeffs, nq), 256, lds, ctx->stream>>>(a, ctx->d_mod,
+                                                                               ctx->n);
 }
 
 }  // namespace
 
-int launch_lt_inner(hck_context *ctx, const LtInnerArgs &a, uint32_t level) {
+int launch_lt_sums(hck_context *ctx, const LtSumArgs &a, uint32_t level) {
   const uint32_t nq = level + 1;
-  double loads = 0, macs = 0;
+  if (a.nb == 0 || a.nb > (uint32_t)kLtB || a.ng > (uint32_t)kLtMaxG || a.n_in == 0 ||
+      a.n_in > (uint32_t)kLtIn || a.n_out == 0 || a.n_out > (uint32_t)kLtOut ||
+      (size_t)a.n_in * a.nb * 2 * kLtCoeffs * sizeof(uint64_t) > 65536)
+    return set_error(HCK_EINVAL, "linear-transform launch shape not supported");
+  double diags = 0, macs = 0;
   for (uint32_t g = 0; g < a.ng; g++)
     for (int l = 0; l < kLtLts; l++)
-      for (uint32_t b = 0; b < a.n1; b++)
-        if (a.pt[g][l][b]) {
-          loads += 1;
-          for (uint32_t t = 0; t < a.n_terms; t++) macs += (a.term_lt[t] == l) ? 2 : 0;
+      for (uint32_t b = 0; b < a.nb; b++)
+        if ((a.present[l][g] >> b) & 1u) {
+          diags += 1;
+          for (int i = 0; i < kLtIn; i++)
+            for (int o = 0; o < kLtOut; o++) macs += a.coef[l][i][o] ? 2.0 : 0.0;
         }
   double babies = 0;
   for (uint32_t in = 0; in < a.n_in; in++)
-    for (uint32_t b = 0; b < a.n1; b++) babies += a.baby[in][b] ? 2 : 0;
+    for (uint32_t b = 0; b < a.nb; b++) babies += a.baby[in][b] ? 2 : 0;
   const double words = (double)ctx->n * nq;
   timing_begin(ctx, "lt_inner",
-               8.0 * words * (loads + babies + 2.0 * a.ng * a.n_out * (a.accumulate ? 2 : 1)),
-               words * (macs + 2.0 * a.ng * a.n_out));
-  dim3 grid(ctx->n / 256, nq);
-  if (a.n_in <= 1 && a.n_out <= 1)
-    k_lt_inner<4, 1, 1><<<grid, 256, 0, ctx->stream>>>(a, ctx->d_mod, ctx->n);
-  else if (a.n_in <= 2 && a.n_out <= 2 && a.ng <= 4)
-    k_lt_inner<4, 2, 2><<<grid, 256, 0, ctx->stream>>>(a, ctx->d_mod, ctx->n);
-  else if (a.n_in <= kLtIn && a.n_out <= kLtOut && a.ng <= 2)
-    k_lt_inner<2, kLtOut, kLtIn><<<grid, 256, 0, ctx->stream>>>(a, ctx->d_mod, ctx->n);
+               8.0 * words * (diags + babies + 2.0 * a.ng * a.n_out * (a.accumulate ? 2 : 1)),
+               words * macs);
+  if (a.n_out <= 1 && a.n_in <= 2)
+    launch<8, 1, 2>(ctx, a, nq);
+  else if (a.n_out <= 2 && a.n_in <= 2)
+    launch<5, 2, 2>(ctx, a, nq);
   else
-    return set_error(HCK_EINVAL, "linear-transform launch shape not supported");
+    launch<2, kLtOut, kLtIn>(ctx, a, nq);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;

@@ -394,3 +394,43 @@ def test_tiny_config_decoded_end_to_end():
     assert np.max(np.abs(ctx.decode(ctx.decrypt(p.sk, y)).real - lin)) < 1e-3
     got = ctx.decode(ctx.decrypt(p.sk, sq)).real
     assert np.max(np.abs(got - lin ** 2)) < 1e-3
+
+
+@pytest.mark.parametrize("name", ["edge11", "edge17"])
+def test_edge_rings_match_oracle(name):
+    """The smallest (N = 2^11) and largest (N = 2^17) supported rings: NTT
+    product, key switching at the top level and level 0 (ragged digits with
+    dnum = 2 and 3), rotation, tensor + relinearize + rescale, all bit-exact."""
+    p = pair(name)
+    o = p.o
+    top = o.L - 1
+    # negacyclic product through the evaluation domain
+    a = S.uniform_residues(o.qmods(top), o.n, 5)[0]
+    b = S.uniform_residues(o.qmods(top), o.n, 6)[0]
+    ct = p.ctx.ciphertext_import(np.stack([a, a]), top, 1.0)
+    pt = p.ctx.plaintext_import(b, top, 1.0)
+    got = p.export(p.ctx.mul_plain(ct, pt))
+    assert np.array_equal(got[0], O.poly_mul(a, b, o.log_n, o.qmods(top)))
+    gks, gko = p.galois([1, -3])
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    rlk_o = o.keygen_relin(p.s_o, 7)
+    for level in sorted({top, 0}):
+        c, c_o = p.rand_ct(level, 1500 + level)
+        for k in (1, -3):
+            assert np.array_equal(p.export(p.ctx.rotate(c, k, gks)),
+                                  o.rotate(c_o, k, gko).polys), (level, k)
+        if level > 0:
+            d, d_o = p.rand_ct(level, 1600 + level)
+            got = p.export(p.ctx.rescale(p.ctx.relinearize(p.ctx.mul(c, d), rlk)))
+            want = o.rescale(o.relinearize(o.tensor(c_o, d_o), rlk_o)).polys
+            assert np.array_equal(got, want), level
+
+
+def test_empty_batches():
+    """Batched calls with no members do nothing and succeed."""
+    p = pair("tiny")
+    gks, _ = p.galois([1])
+    assert p.ctx.rotate_many([], 1, gks, []) == []
+    assert p.ctx.rotate_steps([], [], gks, []) == []
+    c, _ = p.rand_ct(p.o.L - 1, 1700)
+    assert p.ctx.rotate_hoisted(c, [], gks) == []
