@@ -247,9 +247,10 @@ def main():
                      if v["ms"] else None}
                  for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"])}
 
-    vital = None
+    vital = gesture = None
     if not args.no_pipeline:
         vital = vital_pipeline_latency(ctx, prm, sk, rlk, args.pipeline_windows, log)
+        gesture = gesture_pipeline_latency(ctx, prm, sk, rlk, args.pipeline_windows, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -284,6 +285,7 @@ def main():
                               "windows_per_s": round(args.steps / wall, 2)},
         "rotation_modes": rotation_modes,
         "vital_pipeline": vital,
+        "gesture_pipeline": gesture,
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,
@@ -363,6 +365,47 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "target_bin_est": round(got[0] / got[1], 4),
            "resp_bpm_est": round(got[2] / got[3], 3), "hr_bpm_est": round(got[4] / got[5], 3)}
     log(f"vital pipeline: {res}")
+    return res
+
+
+def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
+    """Latency of the encrypted gesture pipeline (Doppler DFT, power, notch,
+    gamma = 4 attention, frame sum, FC1 -> x^2 -> FC2 -> x^2 -> FC3) on one
+    30 frames x 32 range x 32 chirps window at N = 2^16, L = 24, per window
+    with HIP events, after one warm-up window."""
+    import torch
+    import seeded_inputs as S
+    from paper_2603_22437_amd import gesture as HG
+    cfg = S.gesture_pipeline_config(frames=30)
+    top = len(prm["q"]) - 1
+    plan = HG.encode_plan(ctx, cfg, top, prm["scale"])
+    gks = ctx.keygen_rotation(sk, ctx.gesture_required_steps(plan), 5)
+    x = S.gesture_window(2003, cfg["frames"])
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: x.size] = x.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 300)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 301)
+    out = ctx.ciphertext()
+    stream = torch.cuda.current_stream()
+    ctx.gesture_eval(plan, re, im, gks, rlk, out)
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(windows + 1)]
+    evs[0].record(stream)
+    t0 = time.perf_counter()
+    for k in range(windows):
+        ctx.gesture_eval(plan, re, im, gks, rlk, out)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(windows)])
+    classes = cfg["weights"][2].shape[0]
+    logits = ctx.decode(ctx.decrypt(sk, out))[:classes].real
+    res = {"windows": windows, "p50_ms": round(float(np.percentile(ms, 50)), 3),
+           "p99_ms": round(float(np.percentile(ms, 99)), 3),
+           "windows_per_s": round(windows / wall, 2), "rotation_keys": len(gks),
+           "frames": cfg["frames"], "classes": classes,
+           "predicted_class": int(np.argmax(logits))}
+    log(f"gesture pipeline: {res}")
     return res
 
 

@@ -340,6 +340,38 @@ int hck_vital_eval(hck_context *ctx, const hck_vital_plan *plan, const hck_ciphe
                    const hck_ciphertext *im, const hck_galois_keys *gks,
                    const hck_switch_key *rlk, hck_ciphertext *const *out);
 
+/* ---- gesture-classification pipeline --------------------------------------
+ * The paper's encrypted gesture pipeline (section 3.3.3, example pipelines:
+ * K3 -> K1 -> K2 + K6 per frame, frame accumulation, FC1 -> x^2 -> FC2 ->
+ * x^2 -> FC3; depth 11, Table 1) on F range-processed frames of R range bins
+ * x D chirps packed (t R + r) D + c into a real and an imaginary ciphertext
+ * at level l0, with pow2ceil(F) R D = N/2.  Stages (level reached):
+ *   K3  Doppler DFT of every D-chirp block by hck_lt_eval with the windowed
+ *       fftshifted DFT's real and imaginary block-diagonal transforms dft_c,
+ *       dft_s (hoisted baby steps, shared giant ModDown; l0-1)
+ *   K1  P = d_re^2 + d_im^2 (l0-2);  K6  P notch (l0-3)
+ *   K2  w = P^4 by two squarings (gamma = 4; l0-5); feature = P w (l0-6);
+ *       frames summed by rotations R D, 2 R D, ...
+ *   FC1 fc1 over the cyclic feature vector (H1 diagonals), blocks of H1
+ *       slots summed by rotations H1, 2 H1, ..., R D / 2; + bias1; squared
+ *   FC2 fc2 (rectangular diagonals) + bias2; squared;  FC3 fc3 + bias3.
+ * The output holds the logits in slots 0 .. classes-1 at level l0-11.
+ * Transforms and plaintexts are owned by the caller and encoded at least at
+ * the level where they are applied (dft l0, notch l0-2, fc1 l0-6, fc2 l0-8,
+ * fc3 l0-10; bias_i at the level after its product, at the scale reached
+ * there).  Errors: HCK_EINVAL, HCK_ELEVEL, HCK_ESCALE, HCK_ENOKEY. */
+typedef struct {
+  uint32_t frames, bins, chirps; /* F, R, D */
+  uint32_t hidden1;              /* FC1 outputs H1; R D / H1 a power of two */
+  const hck_linear_transform *dft_c, *dft_s, *fc1, *fc2, *fc3;
+  const hck_plaintext *notch, *bias1, *bias2, *bias3;
+} hck_gesture_plan;
+int hck_gesture_required_steps(const hck_context *ctx, const hck_gesture_plan *plan,
+                               int32_t *steps, uint32_t cap, uint32_t *n);
+int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *plan, const hck_ciphertext *re,
+                     const hck_ciphertext *im, const hck_galois_keys *gks,
+                     const hck_switch_key *rlk, hck_ciphertext *out);
+
 /* ---- kernel timing --------------------------------------------------------
  * With timing on, every kernel launch is bracketed by HIP events on the
  * context stream and its duration added to a per-kernel-name total, read

@@ -84,6 +84,8 @@ SIGNATURES = {
     "hck_rotate_steps": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_vital_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
     "hck_vital_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
+    "hck_gesture_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
+    "hck_gesture_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_keyswitch": ([_P, _P, _P, _P], _I),
@@ -280,6 +282,23 @@ class VitalPlan(ctypes.Structure):
         """operands: name -> Plaintext / LinearTransform handle (kept alive by
         the plan object)."""
         plan = cls(frames, bins, taylor_order, lanes_resp, lanes_hr)
+        plan._keep = dict(operands)
+        for name in cls.OPERANDS:
+            h = operands.get(name)
+            setattr(plan, name, h.h if h is not None else None)
+        return plan
+
+
+class GesturePlan(ctypes.Structure):
+    """hck_gesture_plan: layout of one gesture window and its public operands."""
+    OPERANDS = ("dft_c", "dft_s", "fc1", "fc2", "fc3", "notch", "bias1", "bias2", "bias3")
+    _fields_ = [("frames", ctypes.c_uint32), ("bins", ctypes.c_uint32),
+                ("chirps", ctypes.c_uint32), ("hidden1", ctypes.c_uint32)] + [
+        (name, ctypes.c_void_p) for name in OPERANDS]
+
+    @classmethod
+    def build(cls, frames, bins, chirps, hidden1, operands: dict):
+        plan = cls(frames, bins, chirps, hidden1)
         plan._keep = dict(operands)
         for name in cls.OPERANDS:
             h = operands.get(name)
@@ -578,6 +597,22 @@ class Context:
         outs = (ctypes.c_void_p * 6)(*[c.h for c in outputs])
         _check(capi.hck_vital_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs))
         return outputs
+
+    # --- gesture-classification pipeline ---
+    def gesture_required_steps(self, plan: GesturePlan) -> list:
+        n = ctypes.c_uint32()
+        _check(capi.hck_gesture_required_steps(self.h, ctypes.addressof(plan), None, 0,
+                                               ctypes.byref(n)))
+        buf = (ctypes.c_int32 * max(1, n.value))()
+        _check(capi.hck_gesture_required_steps(self.h, ctypes.addressof(plan), buf, n.value,
+                                               ctypes.byref(n)))
+        return list(buf[: n.value])
+
+    def gesture_eval(self, plan: GesturePlan, re, im, gks, rlk, out=None):
+        """The logits ciphertext (slots 0 .. classes-1)."""
+        out = self._out(out)
+        _check(capi.hck_gesture_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, out))
+        return out
 
     # --- kernel timing ---
     def timing(self, on: bool):

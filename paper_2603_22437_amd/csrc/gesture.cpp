@@ -1,0 +1,166 @@
+// The paper's gesture-classification pipeline (section 3.3.3 example
+// pipelines: K3 -> K1 -> K2 + K6, frame accumulation, FC1 -> x^2 -> FC2 ->
+// x^2 -> FC3) composed from the library's evaluation calls.
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+using namespace hck;
+
+namespace {
+
+#define TRY(expr)         \
+  do {                    \
+    int _rc = (expr);     \
+    if (_rc) return _rc;  \
+  } while (0)
+
+uint32_t pow2_at_least(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+
+struct Scratch {
+  hck_context *ctx;
+  std::vector<hck_ciphertext *> held;
+  explicit Scratch(hck_context *c) : ctx(c) {}
+  ~Scratch() {
+    for (hck_ciphertext *c : held) pool_put(ctx, c);
+  }
+  hck_ciphertext *get() {
+    hck_ciphertext *c = pool_get(ctx);
+    held.push_back(c);
+    return c;
+  }
+};
+
+int check_plan(const hck_context *ctx, const hck_gesture_plan *p) {
+  if (!p) return set_error(HCK_EINVAL, "null plan");
+  if (!p->dft_c || !p->dft_s || !p->fc1 || !p->fc2 || !p->fc3 || !p->notch || !p->bias1 ||
+      !p->bias2 || !p->bias3)
+    return set_error(HCK_EINVAL, "missing plan operand");
+  if (p->frames == 0 || p->bins == 0 || p->chirps == 0 || p->hidden1 == 0)
+    return set_error(HCK_EINVAL, "empty layout");
+  const uint64_t rd = (uint64_t)p->bins * p->chirps;
+  if (pow2_at_least(p->frames) * rd != ctx->n / 2)
+    return set_error(HCK_EINVAL, "pow2(frames) x bins x chirps must equal N/2");
+  if (rd % p->hidden1 || ((rd / p->hidden1) & (rd / p->hidden1 - 1)))
+    return set_error(HCK_EINVAL, "bins x chirps / hidden1 must be a power of two");
+  return HCK_OK;
+}
+
+std::vector<int32_t> plan_steps(const hck_gesture_plan *p) {
+  std::vector<int32_t> s;
+  const uint32_t rd = p->bins * p->chirps, t2 = pow2_at_least(p->frames);
+  for (uint32_t k = rd; k < rd * t2; k *= 2) s.push_back((int32_t)k);
+  for (uint32_t k = p->hidden1; k < rd; k *= 2) s.push_back((int32_t)k);
+  for (const hck_linear_transform *lt : {p->dft_c, p->dft_s, p->fc1, p->fc2, p->fc3})
+    for (auto &kv : lt->groups) {
+      if (kv.first != 0) s.push_back(kv.first * (int32_t)lt->n1);
+      for (auto &bp : kv.second)
+        if (bp.first != 0) s.push_back(bp.first);
+    }
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  return s;
+}
+
+int rotsum(hck_context *ctx, hck_ciphertext *c, uint32_t step, uint32_t count,
+           const hck_galois_keys *gks, Scratch &sc) {
+  hck_ciphertext *t = sc.get();
+  for (uint64_t s = step; s < (uint64_t)step * count; s *= 2) {
+    TRY(hck_rotate(ctx, c, (int32_t)s, gks, t));
+    TRY(hck_add(ctx, c, t, c));
+  }
+  return HCK_OK;
+}
+
+int mul_rs(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
+           const hck_switch_key *rlk, hck_ciphertext *out, Scratch &sc) {
+  hck_ciphertext *t = sc.get();
+  TRY(hck_mul(ctx, a, b, t));
+  TRY(hck_relinearize(ctx, t, rlk, out));
+  return hck_rescale(ctx, out, out);
+}
+
+// out = rescale(fc(x)) + bias
+int dense(hck_context *ctx, const hck_linear_transform *fc, const hck_plaintext *bias,
+          const hck_ciphertext *x, const hck_galois_keys *gks, hck_ciphertext *out,
+          uint32_t sum_from, uint32_t sum_count, Scratch &sc) {
+  const uint32_t zero = 0;
+  TRY(hck_lt_eval(ctx, &x, 1, &fc, &zero, &zero, nullptr, 1, gks, &out, 1,
+                  HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
+  TRY(hck_rescale(ctx, out, out));
+  if (sum_count > 1) TRY(rotsum(ctx, out, sum_from, sum_count, gks, sc));
+  return hck_add_plain(ctx, out, bias, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hck_gesture_required_steps(const hck_context *ctx, const hck_gesture_plan *plan,
+                               int32_t *steps, uint32_t cap, uint32_t *n) {
+  if (!ctx || !n) return set_error(HCK_EINVAL, "null argument");
+  TRY(check_plan(ctx, plan));
+  const std::vector<int32_t> s = plan_steps(plan);
+  *n = (uint32_t)s.size();
+  if (steps) {
+    if (cap < s.size()) return set_error(HCK_EINVAL, "steps buffer too small");
+    std::copy(s.begin(), s.end(), steps);
+  }
+  return HCK_OK;
+}
+
+int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *p, const hck_ciphertext *re,
+                     const hck_ciphertext *im, const hck_galois_keys *gks,
+                     const hck_switch_key *rlk, hck_ciphertext *out) {
+  if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  TRY(check_plan(ctx, p));
+  if (re->level != im->level || re->level < 11)
+    return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
+  for (int32_t s : plan_steps(p))
+    if (!gks->keys.count(galois_of_step(ctx, s)))
+      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
+  Scratch sc(ctx);
+  const uint32_t rd = p->bins * p->chirps, t2 = pow2_at_least(p->frames);
+  // K3: Doppler DFT (complex, Eq. dft_re form)
+  hck_ciphertext *d[2] = {sc.get(), sc.get()};
+  {
+    const hck_ciphertext *ins[2] = {re, im};
+    const hck_linear_transform *lts[4] = {p->dft_c, p->dft_s, p->dft_s, p->dft_c};
+    const uint32_t tin[4] = {0, 1, 0, 1}, tout[4] = {0, 0, 1, 1};
+    const int32_t sign[4] = {1, -1, 1, 1};
+    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, sign, 4, gks, d, 2,
+                    HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
+    TRY(hck_rescale(ctx, d[0], d[0]));
+    TRY(hck_rescale(ctx, d[1], d[1]));
+  }
+  // K1: power, K6: notch
+  hck_ciphertext *pw = sc.get(), *t = sc.get(), *u = sc.get();
+  TRY(hck_mul(ctx, d[0], d[0], t));
+  TRY(hck_mul(ctx, d[1], d[1], u));
+  TRY(hck_add(ctx, t, u, t));
+  TRY(hck_relinearize(ctx, t, rlk, pw));
+  TRY(hck_rescale(ctx, pw, pw));
+  TRY(hck_mul_plain(ctx, pw, p->notch, pw));
+  TRY(hck_rescale(ctx, pw, pw));
+  // K2: gamma = 4, feature = P w, then the frame sum
+  hck_ciphertext *p2 = sc.get(), *p4 = sc.get(), *pl = sc.get(), *feat = sc.get();
+  TRY(mul_rs(ctx, pw, pw, rlk, p2, sc));
+  TRY(mul_rs(ctx, p2, p2, rlk, p4, sc));
+  TRY(hck_drop_level(ctx, pw, p4->level, pl));
+  TRY(mul_rs(ctx, pl, p4, rlk, feat, sc));
+  TRY(rotsum(ctx, feat, rd, t2, gks, sc));
+  // FC network with square activations
+  hck_ciphertext *y = sc.get(), *h = sc.get();
+  TRY(dense(ctx, p->fc1, p->bias1, feat, gks, y, p->hidden1, rd / p->hidden1, sc));
+  TRY(mul_rs(ctx, y, y, rlk, h, sc));
+  TRY(dense(ctx, p->fc2, p->bias2, h, gks, y, 0, 1, sc));
+  TRY(mul_rs(ctx, y, y, rlk, h, sc));
+  return dense(ctx, p->fc3, p->bias3, h, gks, out, 0, 1, sc);
+}
+
+}  // extern "C"

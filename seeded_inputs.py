@@ -242,3 +242,56 @@ def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
         cfg[f"k_{name}"] = list(range(int(np.ceil(lo / res - 1e-9)),
                                       int(np.floor(hi / res + 1e-9)) + 1))
     return cfg
+
+
+# ---- synthetic gesture window and the gesture pipeline's public constants ----
+
+def gesture_window(seed: int, frames: int = 30, bins: int = 32, chirps: int = 32,
+                   fps: float = 10.0, snr_db: float = 20.0) -> np.ndarray:
+    """Range-processed FMCW frames [frames][range bins][chirps] (complex) of
+    1-3 point scatterers on random constant-acceleration trajectories (range
+    and radial velocity; the range and Doppler spectra of Appendix A), plus
+    complex Gaussian noise at snr_db, normalized to max |x| = 1."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 4))
+    t = np.arange(frames) / fps
+    c = np.arange(chirps)
+    x = np.zeros((frames, bins, chirps), dtype=np.complex128)
+    for _ in range(k):
+        r0 = rng.uniform(4, bins - 4)
+        v0 = rng.uniform(-0.4, 0.4)           # Doppler cycles per chirp
+        acc = rng.uniform(-0.3, 0.3)
+        amp = rng.uniform(0.5, 1.0)
+        phi = rng.uniform(0, 2 * np.pi)
+        for f in range(frames):
+            r = r0 + 3.0 * np.sin(2 * np.pi * 0.3 * t[f] + phi)
+            fd = np.clip(v0 + acc * t[f], -0.45, 0.45)
+            prof = np.sinc(np.arange(bins) - r)           # range-FFT peak shape
+            x[f] += amp * prof[:, None] * np.exp(1j * (2 * np.pi * fd * c + phi))[None, :]
+    p_sig = np.mean(np.abs(x) ** 2)
+    sigma = np.sqrt(p_sig / 10 ** (snr_db / 10) / 2)
+    x += sigma * (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
+    return x / np.abs(x).max()
+
+
+def gesture_pipeline_config(frames: int = 30, bins: int = 32, chirps: int = 32,
+                            hidden=(64, 32), classes: int = 5, seed: int = 77,
+                            feature_gain: float = 4.0) -> dict:
+    """The gesture pipeline's public parameters (section 3.3.3 example
+    pipeline): the Hann window of the Doppler DFT over the chirps (fftshifted,
+    normalized by its sum), the notch (the zero-Doppler bin after fftshift,
+    reading of Eq. notch_mask for even D), and random public weights of the
+    FC network chirps*bins -> hidden[0] -> hidden[1] -> classes (trained
+    weights are not available); feature_gain is folded into W1 (the paper
+    folds its normalization into W^(1))."""
+    rng = np.random.default_rng(seed)
+    dims = [bins * chirps, hidden[0], hidden[1], classes]
+    ws, bs = [], []
+    for i in range(3):
+        w = rng.standard_normal((dims[i + 1], dims[i])) / np.sqrt(dims[i])
+        if i == 0:
+            w = w * feature_gain
+        ws.append(w)
+        bs.append(rng.uniform(-0.1, 0.1, dims[i + 1]))
+    return dict(frames=frames, bins=bins, chirps=chirps, window=np.hanning(chirps),
+                notch=[chirps // 2], weights=ws, biases=bs)

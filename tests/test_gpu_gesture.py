@@ -1,0 +1,96 @@
+"""The gesture-classification pipeline on the GPU (hck_gesture_eval).
+
+* N = 2^15, L = 12 (the 11 levels of the circuit), 14 frames: the logits'
+  residues bit-exact against the oracle's pipeline, both sides fed the same
+  integer operands (encoded once by the oracle) and the same encrypted window.
+* N = 2^16, L = 24, 30 frames, the library's own encoder: decoded logits
+  against the circuit on plaintext numbers.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2603_22437_amd as H
+import seeded_inputs as S
+from oracle import gesture as OG
+from paper_2603_22437_amd import gesture as HG
+
+pytestmark = pytest.mark.gpu
+
+
+def _import_plan(ctx, cfg, ops):
+    handles = {}
+    for name, v in ops.items():
+        if isinstance(v, O.LinearTransform):
+            res = {g * v.n1 + b: pt.res for g, items in v.groups.items() for b, pt in items}
+            handles[name] = ctx.lt_create_from_residues(res, v.n1, v.level, v.scale)
+        else:
+            handles[name] = ctx.plaintext_import(v.res, v.level, v.scale)
+    return H.GesturePlan.build(cfg["frames"], cfg["bins"], cfg["chirps"],
+                               cfg["weights"][0].shape[0], handles)
+
+
+def test_gesture_pipeline_matches_oracle():
+    prm = S.params("mix15")
+    o = O.Oracle(prm)
+    ctx = H.Context.from_params(prm)
+    s_o = o.keygen_secret(1)
+    sk = ctx.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=14)
+    x = S.gesture_window(2001, cfg["frames"])
+    l0 = o.L - 1
+    ops = OG.encode_operands(o, cfg, l0, prm["scale"])
+    plan = _import_plan(ctx, cfg, ops)
+    steps = OG.required_steps(o, cfg, ops)
+    assert ctx.gesture_required_steps(plan) == steps
+    gko = {o.galois_element(k): o.keygen_galois(s_o, o.galois_element(k), 5) for k in steps}
+    rlk_o = o.keygen_relin(s_o, 7)
+    gks = ctx.keygen_rotation(sk, steps, 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    re_o, im_o = OG.encrypt_window(o, s_o, x, l0, prm["scale"], 100)
+    re = ctx.ciphertext_import(re_o.polys, l0, re_o.scale)
+    im = ctx.ciphertext_import(im_o.polys, l0, im_o.scale)
+    got = ctx.gesture_eval(plan, re, im, gks, rlk)
+    want = OG.evaluate(o, cfg, ops, re_o, im_o, gko, rlk_o)
+    res, lvl, sc = ctx.ciphertext_export(got)
+    assert lvl == want.level == l0 - OG.DEPTH
+    assert sc == want.scale
+    assert np.array_equal(res, want.polys)
+
+
+def test_gesture_pipeline_decodes_at_benchmark_ring():
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=30)
+    x = S.gesture_window(2002, cfg["frames"])
+    l0 = len(prm["q"]) - 1
+    plan = HG.encode_plan(ctx, cfg, l0, prm["scale"])
+    gks = ctx.keygen_rotation(sk, ctx.gesture_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: x.size] = x.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 101)
+    out = ctx.gesture_eval(plan, re, im, gks, rlk)
+    classes = cfg["weights"][2].shape[0]
+    got = ctx.decode(ctx.decrypt(sk, out))[:classes].real
+    want = OG.plain(cfg, x)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3)
+    assert int(np.argmax(got)) == int(np.argmax(want))
+
+
+def test_gesture_plan_errors():
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    cfg = S.gesture_pipeline_config(frames=30)
+    plan = HG.encode_plan(ctx, cfg, len(prm["q"]) - 1, prm["scale"])
+    bad = H.GesturePlan.build(16, cfg["bins"], cfg["chirps"], 64, plan._keep)  # 16 x 1024 != N/2
+    with pytest.raises(H.HckError):
+        ctx.gesture_required_steps(bad)
+    sk = ctx.keygen_secret(1)
+    rlk = ctx.keygen_relin(sk, 7)
+    gks = ctx.keygen_rotation(sk, [1], 5)
+    low = ctx.encrypt_sk(sk, ctx.encode(np.zeros(ctx.n_slots), prm["scale"], 8), 3)
+    with pytest.raises(H.HckError):   # level 8 < depth 11
+        ctx.gesture_eval(plan, low, low, gks, rlk)
