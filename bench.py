@@ -212,6 +212,7 @@ def main():
                       "R2_16ct_one_key_rot_per_s": round(timed(r2, 16), 1),
                       "R3_16ct_16_keys_rot_per_s": round(timed(r3, len(distinct)), 1)}
     log(f"rotation modes: {rotation_modes}")
+    ceilings = rotation_ceilings(ctx, prm, rotation_modes, log)
 
     # per-kernel durations over two more steps (events around every launch)
     ctx.timing(True)
@@ -284,6 +285,7 @@ def main():
                               "p99": round(float(np.percentile(step_ms, 99)), 3),
                               "windows_per_s": round(args.steps / wall, 2)},
         "rotation_modes": rotation_modes,
+        "rotation_ceilings": ceilings,
         "vital_pipeline": vital,
         "gesture_pipeline": gesture,
         "roofline": roof,
@@ -324,6 +326,36 @@ def measured_traffic(kernel):
                 return None
             return int(cells[4])
     return None
+
+
+def rotation_ceilings(ctx, prm, modes, log):
+    """The two ceilings of one rotation at the top level (N = 2^16, L = 24,
+    K = 8, dnum = 3): HBM (ciphertext in + key + ciphertext out at 8 TB/s) and
+    the vector-ALU integer rate (modular products per rotation over the
+    device's measured Shoup-product rate), with the achieved fraction of each
+    for the rotation modes without key reuse (R3) and with it (R2)."""
+    n, L, K, dnum = prm["n"], len(prm["q"]), len(prm["p"]), prm["dnum"]
+    alpha = -(-L // dnum)
+    digits = -(-L // alpha)
+    ext = digits * (L + K) - L
+    ntts = L + ext + 2 * K + 2 * L                   # INTT d, NTT ext, INTT P, NTT conv
+    mulmods = (ntts * (n // 2) * (n.bit_length() - 1)          # butterflies
+               + digits * alpha * (L + K - alpha) * n + L * n   # ModUp BConv + digit scale
+               + 2 * K * L * n + 2 * K * n                      # ModDown BConv + scale
+               + 2 * digits * (L + K) * n                       # key inner product
+               + 2 * L * n)                                     # P^-1
+    bytes_ = 8 * n * (2 * L + digits * 2 * (L + K) + 2 * L)
+    rate = ctx.measure_mulmod_rate() * 1e12
+    hbm = HBM_PEAK_GBS * 1e9 / bytes_
+    valu = rate / mulmods
+    out = {"bytes_per_rotation": bytes_, "mulmods_per_rotation": mulmods,
+           "measured_shoup_mulmod_T_per_s": round(rate / 1e12, 3),
+           "hbm_ceiling_rot_per_s": round(hbm, 1), "valu_ceiling_rot_per_s": round(valu, 1),
+           "R3_frac_of_hbm": round(modes["R3_16ct_16_keys_rot_per_s"] / hbm, 4),
+           "R3_frac_of_valu": round(modes["R3_16ct_16_keys_rot_per_s"] / valu, 4),
+           "R2_frac_of_valu": round(modes["R2_16ct_one_key_rot_per_s"] / valu, 4)}
+    log(f"rotation ceilings: {out}")
+    return out
 
 
 def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):

@@ -372,6 +372,15 @@ int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *plan, const hck_c
                      const hck_ciphertext *im, const hck_galois_keys *gks,
                      const hck_switch_key *rlk, hck_ciphertext *out);
 
+/* ---- device calibration ---------------------------------------------------
+ * Rate of 64-bit Shoup modular products (a w mod q for a fixed w, the product
+ * of every NTT butterfly) that this device sustains on its vector ALUs, in
+ * 10^12 per second, from one timed compute-only launch (about 2^30 products
+ * in dependent chains, 8 per thread) on the context's stream.  A measured
+ * integer ceiling for the evaluation kernels, reported beside the HBM
+ * bandwidth.  Errors: HCK_EINVAL, HCK_EDEVICE. */
+int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s);
+
 /* ---- kernel timing --------------------------------------------------------
  * With timing on, every kernel launch is bracketed by HIP events on the
  * context stream and its duration added to a per-kernel-name total, read

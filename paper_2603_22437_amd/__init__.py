@@ -86,6 +86,7 @@ SIGNATURES = {
     "hck_vital_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "hck_gesture_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
     "hck_gesture_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
+    "hck_measure_mulmod_rate": ([_P, _PD], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_keyswitch": ([_P, _P, _P, _P], _I),
@@ -613,6 +614,12 @@ class Context:
         out = self._out(out)
         _check(capi.hck_gesture_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, out))
         return out
+
+    def measure_mulmod_rate(self) -> float:
+        """Sustained 64-bit Shoup modular products per second on this device (T/s)."""
+        r = ctypes.c_double()
+        _check(capi.hck_measure_mulmod_rate(self.h, ctypes.byref(r)))
+        return r.value
 
     # --- kernel timing ---
     def timing(self, on: bool):

@@ -989,6 +989,12 @@ int hck_lt_required_steps(const hck_linear_transform *lt, int32_t *steps, uint32
 }
 
 
+int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s) {
+  ENTER(ctx);
+  if (!tera_per_s) return set_error(HCK_EINVAL, "null argument");
+  return measure_mulmod_rate(ctx, tera_per_s);
+}
+
 int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int32_t *steps,
                      uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
   ENTER(ctx);

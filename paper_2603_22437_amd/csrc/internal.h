@@ -231,6 +231,8 @@ int launch_sum_many(hck_context *ctx, uint64_t *out, const uint64_t *const *in, 
 // automorphism
 int launch_gather_sum(hck_context *ctx, uint64_t *out, const uint64_t *const *in,
                       const uint32_t *galois, uint32_t n_in, const LimbMap &map);
+// measured rate of Shoup modular products on this device (T per second)
+int measure_mulmod_rate(hck_context *ctx, double *tera_per_s);
 int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
                   const LimbMap &map, int op);
 // out = [+-] REDC(a * bm) [+ out] (bm in Montgomery form): mode 0 set,

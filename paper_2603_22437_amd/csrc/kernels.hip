@@ -80,6 +80,25 @@ __global__ __launch_bounds__(kThreads) void k_gather_sum(uint64_t *out, GatherSu
   out[row + j] = acc;
 }
 
+// Calibration: chains of dependent Shoup products a <- a w mod q (the
+// modular product of every NTT butterfly), 8 independent chains per thread,
+// results folded into one word per thread so nothing is optimized away.
+__global__ __launch_bounds__(kThreads) void k_mulmod_rate(uint64_t *out, uint64_t q, uint64_t w,
+                                                          uint64_t wp, int iters) {
+  const uint64_t tid = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+  uint64_t x[8];
+#pragma unroll
+  for (int k = 0; k < 8; k++) x[k] = (tid * 8 + k) % q;
+  for (int i = 0; i < iters; i++) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) x[k] = reduce2(shoup_lazy(x[k], w, wp, q), q);
+  }
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) s ^= x[k];
+  out[tid] = s;
+}
+
 // out = [+-] REDC(a * bm) [+ out]: mode 0 set, 1 add to out, 2 subtract from
 // out, 3 set negated (bm in Montgomery form, so REDC gives a * b mod q)
 __global__ __launch_bounds__(kThreads) void k_mul_mont(uint64_t *out, const uint64_t *a,
@@ -270,6 +289,37 @@ int launch_gather_sum(hck_context *ctx, uint64_t *out, const uint64_t *const *in
     timing_end(ctx);
     HCK_HIP(ctx, hipGetLastError());
   }
+  return HCK_OK;
+}
+
+int measure_mulmod_rate(hck_context *ctx, double *tera_per_s) {
+  const unsigned blocks = 256 * 16;
+  const int iters = 1024;
+  uint64_t *buf = nullptr;
+  int rc = dev_alloc(ctx, &buf, (size_t)blocks * kThreads);
+  if (rc) return rc;
+  const uint64_t q = ctx->mods[0];
+  const uint64_t w = h_powmod(3, 12345, q), wp = h_shoup(w, q);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    k_mulmod_rate<<<blocks, kThreads, 0, ctx->stream>>>(buf, q, w, wp, iters);  // warm-up
+    e = hipEventRecord(e0, ctx->stream);
+  }
+  if (e == hipSuccess) {
+    k_mulmod_rate<<<blocks, kThreads, 0, ctx->stream>>>(buf, q, w, wp, iters);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  dev_free(ctx, buf);
+  if (e != hipSuccess) return check_hip(ctx, e, "mulmod rate");
+  *tera_per_s = (double)blocks * kThreads * iters * 8 / (ms * 1e-3) / 1e12;
   return HCK_OK;
 }
 
