@@ -206,6 +206,12 @@ int hck_mul(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
 /* (d0, d1) + KeySwitch(d2, rlk) of a 3-part ciphertext. */
 int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *rlk,
                     hck_ciphertext *out);
+/* Relinearizations of n 3-part ciphertexts of one level, key-switched
+ * together in batches (the key is streamed once per batch); residues equal
+ * hck_relinearize's for every member.  out[i] may alias a[i] but no other
+ * input; outputs must be distinct.  Errors: HCK_EINVAL, HCK_ELEVEL. */
+int hck_relinearize_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n,
+                         const hck_switch_key *rlk, hck_ciphertext *const *out);
 /* Divides by the last prime with a centred lift; level - 1, scale / q_level.
  * Errors: HCK_ELEVEL at level 0. */
 int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out);
@@ -336,9 +342,19 @@ typedef struct {
  * capacity of steps[], *n receives the count; steps may be NULL). */
 int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan, int32_t *steps,
                              uint32_t cap, uint32_t *n);
+/* One window; out[0..5] must not alias re or im. */
 int hck_vital_eval(hck_context *ctx, const hck_vital_plan *plan, const hck_ciphertext *re,
                    const hck_ciphertext *im, const hck_galois_keys *gks,
                    const hck_switch_key *rlk, hck_ciphertext *const *out);
+/* n windows with one plan, evaluated together: every stage advances all
+ * windows, so their rotate-and-sum chains and relinearizations share batched
+ * key switches (a throughput mode; each window's residues equal
+ * hck_vital_eval's).  Window k reads re[k], im[k] and writes out[6k .. 6k+5];
+ * outputs must not alias inputs. */
+int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *plan,
+                        const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                        uint32_t n, const hck_galois_keys *gks, const hck_switch_key *rlk,
+                        hck_ciphertext *const *out);
 
 /* ---- gesture-classification pipeline --------------------------------------
  * The paper's encrypted gesture pipeline (section 3.3.3, example pipelines:

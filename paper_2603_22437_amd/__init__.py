@@ -82,8 +82,10 @@ SIGNATURES = {
     "hck_apply_galois": ([_P, _P, _U32, _P, _P], _I),
     "hck_rotate_many": ([_P, _P, _U32, _I32, _P, _P], _I),
     "hck_rotate_steps": ([_P, _P, _P, _U32, _P, _P], _I),
+    "hck_relinearize_many": ([_P, _P, _U32, _P, _P], _I),
     "hck_vital_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
     "hck_vital_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
+    "hck_vital_eval_many": ([_P, _P, _P, _P, _U32, _P, _P, _P], _I),
     "hck_gesture_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
     "hck_gesture_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "hck_measure_mulmod_rate": ([_P, _PD], _I),
@@ -509,6 +511,15 @@ class Context:
         _check(capi.hck_rotate_many(self.h, a, len(cts), step, gks, o))
         return outs
 
+    def relinearize_many(self, cts, rlk, outs=None):
+        """Relinearizations of several 3-part ciphertexts of one level,
+        key-switched together in batches."""
+        outs = [self.ciphertext() for _ in cts] if outs is None else outs
+        a = (ctypes.c_void_p * len(cts))(*[c.h for c in cts])
+        o = (ctypes.c_void_p * len(outs))(*[c.h for c in outs])
+        _check(capi.hck_relinearize_many(self.h, a, len(cts), rlk, o))
+        return outs
+
     def rotate_steps(self, cts, steps, gks, outs=None):
         """a[i] rotated by steps[i], key-switched together in batches."""
         if len(steps) != len(cts):
@@ -598,6 +609,19 @@ class Context:
         outs = (ctypes.c_void_p * 6)(*[c.h for c in outputs])
         _check(capi.hck_vital_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs))
         return outputs
+
+    def vital_eval_many(self, plan: VitalPlan, res, ims, gks, rlk, outputs=None):
+        """Several windows together; returns one list of 6 outputs per window."""
+        n = len(res)
+        if len(ims) != n:
+            raise ValueError("one imaginary ciphertext per window")
+        outputs = ([self.ciphertext() for _ in range(6 * n)] if outputs is None
+                   else [c for w in outputs for c in w])
+        a = (ctypes.c_void_p * n)(*[c.h for c in res])
+        b = (ctypes.c_void_p * n)(*[c.h for c in ims])
+        o = (ctypes.c_void_p * (6 * n))(*[c.h for c in outputs])
+        _check(capi.hck_vital_eval_many(self.h, ctypes.addressof(plan), a, b, n, gks, rlk, o))
+        return [outputs[6 * k: 6 * k + 6] for k in range(n)]
 
     # --- gesture-classification pipeline ---
     def gesture_required_steps(self, plan: GesturePlan) -> list:

@@ -798,6 +798,51 @@ int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_
   return HCK_OK;
 }
 
+int hck_relinearize_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n,
+                         const hck_switch_key *rlk, hck_ciphertext *const *out) {
+  ENTER(ctx);
+  if ((n && (!a || !out)) || !rlk) return set_error(HCK_EINVAL, "null argument");
+  if (n == 0) return HCK_OK;
+  for (uint32_t i = 0; i < n; i++) {
+    if (!a[i] || !out[i]) return set_error(HCK_EINVAL, "null ciphertext");
+    if (a[i]->size != 3) return set_error(HCK_EINVAL, "relinearization needs a 3-part ciphertext");
+    if (a[i]->level != a[0]->level) return set_error(HCK_ELEVEL, "batched inputs need one level");
+    for (uint32_t k = 0; k < n; k++)
+      if ((k < i && out[k] == out[i]) || (k != i && out[k] == a[i]))
+        return set_error(HCK_EINVAL, "outputs must be distinct and alias only their own input");
+  }
+  const uint32_t level = a[0]->level;
+  const size_t ps = poly_stride(ctx);
+  const uint32_t limit = ks_batch_limit(ctx, level);
+  for (uint32_t s0 = 0; s0 < n; s0 += limit) {
+    KsBatch kb;
+    kb.n = std::min<uint32_t>(limit, n - s0);
+    std::vector<double> scales(kb.n);
+    for (uint32_t b = 0; b < kb.n; b++) {
+      const hck_ciphertext *x = a[s0 + b];
+      hck_ciphertext *y = out[s0 + b];
+      scales[b] = x->scale;
+      TRY(ensure_ct(ctx, y, 2));
+      // (d0, d1) + KeySwitch(d2): d2 is read before the final launch writes
+      // the outputs, and the addends are read at the positions written
+      kb.key[b] = rlk->data;
+      kb.galois[b] = 1;
+      kb.d[b] = x->data + 2 * ps;
+      kb.out0[b] = y->data;
+      kb.out1[b] = y->data + ps;
+      kb.add0[b] = x->data;
+      kb.add1[b] = x->data + ps;
+    }
+    TRY(keyswitch_batch(ctx, kb, level));
+    for (uint32_t b = 0; b < kb.n; b++) {
+      out[s0 + b]->size = 2;
+      out[s0 + b]->level = level;
+      out[s0 + b]->scale = scales[b];
+    }
+  }
+  return HCK_OK;
+}
+
 int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out) {
   ENTER(ctx);
   if (!a || !out) return set_error(HCK_EINVAL, "null argument");

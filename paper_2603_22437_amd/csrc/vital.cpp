@@ -111,6 +111,14 @@ int mul2_rs(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
   return hck_rescale(ctx, out, out);
 }
 
+// outs[i] = relin(ts[i]) rescaled, the relinearizations key-switched together
+int relin_rs(hck_context *ctx, std::vector<hck_ciphertext *> ts, const hck_switch_key *rlk,
+             std::vector<hck_ciphertext *> outs) {
+  TRY(hck_relinearize_many(ctx, ts.data(), (uint32_t)ts.size(), rlk, outs.data()));
+  for (hck_ciphertext *o : outs) TRY(hck_rescale(ctx, o, o));
+  return HCK_OK;
+}
+
 // out = (a pt) rescaled
 int mulpt_rs(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
              hck_ciphertext *out) {
@@ -135,16 +143,23 @@ int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
   return HCK_OK;
 }
 
-int hck_vital_eval(hck_context *ctx, const hck_vital_plan *p, const hck_ciphertext *re,
-                   const hck_ciphertext *im, const hck_galois_keys *gks,
-                   const hck_switch_key *rlk, hck_ciphertext *const *out) {
-  if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+}  // extern "C"
+
+// The pipeline over n windows at once: every stage advances all windows, so
+// their rotate-and-sum chains and relinearizations share key-switch batches.
+static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
+                              const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                              uint32_t n, const hck_galois_keys *gks, const hck_switch_key *rlk,
+                              hck_ciphertext *const *out) {
   TRY(check_plan(ctx, p));
-  for (int i = 0; i < 6; i++)
-    if (!out[i]) return set_error(HCK_EINVAL, "null output");
   const uint32_t depth = p->taylor_order == 3 ? 11 : 9;
-  if (re->level != im->level || re->level < depth)
-    return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
+  for (uint32_t k = 0; k < n; k++) {
+    if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
+    if (re[k]->level != re[0]->level || im[k]->level != re[0]->level || re[0]->level < depth)
+      return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
+    for (int i = 0; i < 6; i++)
+      if (!out[6 * k + i]) return set_error(HCK_EINVAL, "null output");
+  }
   for (int32_t s : plan_steps(p))
     if (!gks->keys.count(galois_of_step(ctx, s)))
       return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
@@ -153,83 +168,192 @@ int hck_vital_eval(hck_context *ctx, const hck_vital_plan *p, const hck_cipherte
   const uint32_t t2 = pow2_at_least(p->frames);
   const uint32_t c_resp = pow2_at_least(p->lanes_resp);
   const uint32_t c_all = pow2_at_least(p->lanes_resp + p->lanes_hr);
+  auto fresh = [&](uint32_t count) {
+    std::vector<hck_ciphertext *> v(count);
+    for (auto &c : v) c = sc.get();
+    return v;
+  };
+  auto O = [&](uint32_t k, int i) { return out[6 * k + i]; };
 
-  // K1: p = Re^2 + Im^2, E = sum over frames
-  hck_ciphertext *pw = sc.get(), *e = sc.get();
-  TRY(mul2_rs(ctx, re, re, im, im, 0, rlk, pw, sc));
-  TRY(hck_drop_level(ctx, pw, pw->level, e));  // a copy
-  TRY(rotsum(ctx, {e}, r, t2, gks, sc));
+  // K1: p = Re^2 + Im^2 (one batched relinearization), E = sum over frames
+  std::vector<hck_ciphertext *> pw = fresh(n), e = fresh(n), t = fresh(n), u = fresh(n);
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(hck_mul(ctx, re[k], re[k], t[k]));
+    TRY(hck_mul(ctx, im[k], im[k], u[k]));
+    TRY(hck_add(ctx, t[k], u[k], t[k]));
+  }
+  TRY(relin_rs(ctx, t, rlk, pw));
+  for (uint32_t k = 0; k < n; k++) TRY(hck_drop_level(ctx, pw[k], pw[k]->level, e[k]));
+  TRY(rotsum(ctx, e, r, t2, gks, sc));
   // K2 over bins (gamma = 2) and K4 (P_phi = 2) share their squarings' level
-  hck_ciphertext *w = sc.get(), *m = sc.get();
-  TRY(mul_rs(ctx, e, e, rlk, w, sc));
-  TRY(mul_rs(ctx, pw, pw, rlk, m, sc));
-  TRY(mulpt_rs(ctx, w, p->bin_index, out[0]));
-  TRY(mulpt_rs(ctx, w, p->bin_mask, out[1]));
-  hck_ciphertext *re2 = sc.get(), *im2 = sc.get(), *it = sc.get(), *qt = sc.get();
-  TRY(hck_drop_level(ctx, re, m->level, re2));
-  TRY(hck_drop_level(ctx, im, m->level, im2));
-  TRY(mul_rs(ctx, m, re2, rlk, it, sc));
-  TRY(mul_rs(ctx, m, im2, rlk, qt, sc));
-  TRY(rotsum(ctx, {out[0], out[1], it, qt}, 1, (uint32_t)r, gks, sc));
-  // K5: both bands' FIR of I and Q in one BSGS evaluation
-  hck_ciphertext *f[4] = {sc.get(), sc.get(), sc.get(), sc.get()};
+  std::vector<hck_ciphertext *> w = fresh(n), m = fresh(n), ts, outs;
+  for (uint32_t k = 0; k < n; k++) {
+    hck_ciphertext *tw = sc.get(), *tm = sc.get();
+    TRY(hck_mul(ctx, e[k], e[k], tw));
+    TRY(hck_mul(ctx, pw[k], pw[k], tm));
+    ts.insert(ts.end(), {tw, tm});
+    outs.insert(outs.end(), {w[k], m[k]});
+  }
+  TRY(relin_rs(ctx, ts, rlk, outs));
+  std::vector<hck_ciphertext *> it = fresh(n), qt = fresh(n);
+  ts.clear();
+  outs.clear();
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(mulpt_rs(ctx, w[k], p->bin_index, O(k, 0)));
+    TRY(mulpt_rs(ctx, w[k], p->bin_mask, O(k, 1)));
+    hck_ciphertext *re2 = sc.get(), *im2 = sc.get(), *ti = sc.get(), *tq = sc.get();
+    TRY(hck_drop_level(ctx, re[k], m[k]->level, re2));
+    TRY(hck_drop_level(ctx, im[k], m[k]->level, im2));
+    TRY(hck_mul(ctx, m[k], re2, ti));
+    TRY(hck_mul(ctx, m[k], im2, tq));
+    ts.insert(ts.end(), {ti, tq});
+    outs.insert(outs.end(), {it[k], qt[k]});
+  }
+  TRY(relin_rs(ctx, ts, rlk, outs));
   {
-    const hck_ciphertext *ins[2] = {it, qt};
+    std::vector<hck_ciphertext *> chain;
+    for (uint32_t k = 0; k < n; k++) chain.insert(chain.end(), {O(k, 0), O(k, 1), it[k], qt[k]});
+    TRY(rotsum(ctx, chain, 1, (uint32_t)r, gks, sc));
+  }
+  // K5: both bands' FIR of I and Q, one BSGS evaluation per window
+  std::vector<hck_ciphertext *> f = fresh(4 * n);
+  for (uint32_t k = 0; k < n; k++) {
+    const hck_ciphertext *ins[2] = {it[k], qt[k]};
     const hck_linear_transform *lts[4] = {p->fir_resp, p->fir_resp, p->fir_hr, p->fir_hr};
     const uint32_t tin[4] = {0, 1, 0, 1}, tout[4] = {0, 1, 2, 3};
-    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, nullptr, 4, gks, f, 4,
+    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, nullptr, 4, gks, &f[4 * k], 4,
                     HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
-    for (int i = 0; i < 4; i++) TRY(hck_rescale(ctx, f[i], f[i]));
+    for (int i = 0; i < 4; i++) TRY(hck_rescale(ctx, f[4 * k + i], f[4 * k + i]));
   }
-  // K7: the previous frame by a rotation of -R (all four in one batch)
-  hck_ciphertext *f1[4] = {sc.get(), sc.get(), sc.get(), sc.get()};
-  TRY(hck_rotate_many(ctx, f, 4, -r, gks, f1));
-  hck_ciphertext *dphi[2] = {sc.get(), sc.get()};
-  for (int b = 0; b < 2; b++) {
-    hck_ciphertext *fi = f[2 * b], *fq = f[2 * b + 1], *fi1 = f1[2 * b], *fq1 = f1[2 * b + 1];
-    hck_ciphertext *y = sc.get();
-    TRY(mul2_rs(ctx, fq, fi1, fi, fq1, 1, rlk, y, sc));
-    if (p->taylor_order == 1) {
-      TRY(hck_drop_level(ctx, y, y->level, dphi[b]));
-      continue;
+  // K7: the previous frame by a rotation of -R; both bands of every window
+  // advance together, one batched relinearization per product level
+  std::vector<hck_ciphertext *> f1 = fresh(4 * n);
+  TRY(hck_rotate_many(ctx, f.data(), 4 * n, -r, gks, f1.data()));
+  std::vector<hck_ciphertext *> dphi = fresh(2 * n), y = fresh(2 * n), x = fresh(2 * n);
+  ts.clear();
+  outs.clear();
+  for (uint32_t j = 0; j < 2 * n; j++) {
+    hck_ciphertext *fi = f[2 * j], *fq = f[2 * j + 1], *fi1 = f1[2 * j], *fq1 = f1[2 * j + 1];
+    hck_ciphertext *t1 = sc.get(), *t2 = sc.get();
+    TRY(hck_mul(ctx, fq, fi1, t1));
+    TRY(hck_mul(ctx, fi, fq1, t2));
+    TRY(hck_sub(ctx, t1, t2, t1));
+    ts.push_back(t1);
+    outs.push_back(y[j]);
+    if (p->taylor_order == 3) {
+      hck_ciphertext *u1 = sc.get(), *u2 = sc.get();
+      TRY(hck_mul(ctx, fi, fi1, u1));
+      TRY(hck_mul(ctx, fq, fq1, u2));
+      TRY(hck_add(ctx, u1, u2, u1));
+      ts.push_back(u1);
+      outs.push_back(x[j]);
     }
-    hck_ciphertext *x = sc.get(), *x2 = sc.get(), *y6 = sc.get(), *a = sc.get();
-    hck_ciphertext *y2 = sc.get(), *yc = sc.get(), *bb = sc.get();
-    TRY(mul2_rs(ctx, fi, fi1, fq, fq1, 0, rlk, x, sc));
-    TRY(mul_rs(ctx, x, x, rlk, x2, sc));
-    TRY(hck_drop_level(ctx, y, x2->level, y6));
-    TRY(mul_rs(ctx, y6, x2, rlk, a, sc));
-    TRY(mul_rs(ctx, y, y, rlk, y2, sc));
-    TRY(mulpt_rs(ctx, y, p->third, yc));
-    TRY(mul_rs(ctx, yc, y2, rlk, bb, sc));
-    TRY(hck_sub(ctx, a, bb, dphi[b]));
   }
-  // K3: copy dphi into the band's lanes, weight, sum over frames
+  TRY(relin_rs(ctx, ts, rlk, outs));
+  if (p->taylor_order == 1) {
+    for (uint32_t j = 0; j < 2 * n; j++) TRY(hck_drop_level(ctx, y[j], y[j]->level, dphi[j]));
+  } else {
+    // x^2 and y^2 (one batch), then y x^2 and (y / 3) y^2 (one batch)
+    std::vector<hck_ciphertext *> x2 = fresh(2 * n), y2 = fresh(2 * n);
+    ts.clear();
+    outs.clear();
+    for (uint32_t j = 0; j < 2 * n; j++) {
+      hck_ciphertext *t1 = sc.get(), *t2 = sc.get();
+      TRY(hck_mul(ctx, x[j], x[j], t1));
+      TRY(hck_mul(ctx, y[j], y[j], t2));
+      ts.insert(ts.end(), {t1, t2});
+      outs.insert(outs.end(), {x2[j], y2[j]});
+    }
+    TRY(relin_rs(ctx, ts, rlk, outs));
+    std::vector<hck_ciphertext *> av = fresh(2 * n), bv = fresh(2 * n);
+    ts.clear();
+    outs.clear();
+    for (uint32_t j = 0; j < 2 * n; j++) {
+      hck_ciphertext *y6 = sc.get(), *yc = sc.get(), *t1 = sc.get(), *t2 = sc.get();
+      TRY(hck_drop_level(ctx, y[j], x2[j]->level, y6));
+      TRY(mulpt_rs(ctx, y[j], p->third, yc));
+      TRY(hck_mul(ctx, y6, x2[j], t1));
+      TRY(hck_mul(ctx, yc, y2[j], t2));
+      ts.insert(ts.end(), {t1, t2});
+      outs.insert(outs.end(), {av[j], bv[j]});
+    }
+    TRY(relin_rs(ctx, ts, rlk, outs));
+    for (uint32_t j = 0; j < 2 * n; j++) TRY(hck_sub(ctx, av[j], bv[j], dphi[j]));
+  }
+  // K3: copy each dphi into its band's lanes (dphi[2k]: respiration,
+  // dphi[2k + 1]: heart rate), weight, sum over frames
   for (uint32_t s = 1; s < c_all; s *= 2) {
-    const uint32_t nb = s < c_resp ? 2 : 1;   // respiration needs fewer lanes
-    hck_ciphertext *src[2] = {dphi[1], dphi[0]};
-    hck_ciphertext *tmp[2] = {sc.get(), sc.get()};
-    TRY(hck_rotate_many(ctx, src, nb, -(int32_t)s, gks, tmp));
-    for (uint32_t i = 0; i < nb; i++) TRY(hck_add(ctx, src[i], tmp[i], src[i]));
+    std::vector<hck_ciphertext *> src;
+    for (uint32_t k = 0; k < n; k++) {
+      src.push_back(dphi[2 * k + 1]);
+      if (s < c_resp) src.push_back(dphi[2 * k]);
+    }
+    std::vector<hck_ciphertext *> tmp = fresh((uint32_t)src.size());
+    TRY(hck_rotate_many(ctx, src.data(), (uint32_t)src.size(), -(int32_t)s, gks, tmp.data()));
+    for (size_t i = 0; i < src.size(); i++) TRY(hck_add(ctx, src[i], tmp[i], src[i]));
   }
-  hck_ciphertext *xs[4] = {sc.get(), sc.get(), sc.get(), sc.get()};
-  TRY(mulpt_rs(ctx, dphi[0], p->dft_re_resp, xs[0]));
-  TRY(mulpt_rs(ctx, dphi[0], p->dft_im_resp, xs[1]));
-  TRY(mulpt_rs(ctx, dphi[1], p->dft_re_hr, xs[2]));
-  TRY(mulpt_rs(ctx, dphi[1], p->dft_im_hr, xs[3]));
-  TRY(rotsum(ctx, {xs[0], xs[1], xs[2], xs[3]}, r, t2, gks, sc));
-  TRY(hck_add(ctx, xs[0], xs[2], xs[0]));
-  TRY(hck_add(ctx, xs[1], xs[3], xs[1]));
+  std::vector<hck_ciphertext *> xs = fresh(4 * n);
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(mulpt_rs(ctx, dphi[2 * k], p->dft_re_resp, xs[4 * k]));
+    TRY(mulpt_rs(ctx, dphi[2 * k], p->dft_im_resp, xs[4 * k + 1]));
+    TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_re_hr, xs[4 * k + 2]));
+    TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_im_hr, xs[4 * k + 3]));
+  }
+  TRY(rotsum(ctx, xs, r, t2, gks, sc));
   // K1 on the spectrum, K2: sharpening and weighted frequency averages
-  hck_ciphertext *pspec = sc.get(), *sh = sc.get();
-  TRY(mul2_rs(ctx, xs[0], xs[0], xs[1], xs[1], 0, rlk, pspec, sc));
-  TRY(mul_rs(ctx, pspec, pspec, rlk, sh, sc));
-  TRY(mulpt_rs(ctx, sh, p->freq_resp, out[2]));
-  TRY(mulpt_rs(ctx, sh, p->mask_resp, out[3]));
-  TRY(mulpt_rs(ctx, sh, p->freq_hr, out[4]));
-  TRY(mulpt_rs(ctx, sh, p->mask_hr, out[5]));
-  TRY(rotsum(ctx, {out[2], out[3], out[4], out[5]}, 1, c_all, gks, sc));
-  return HCK_OK;
+  std::vector<hck_ciphertext *> pspec = fresh(n), sh = fresh(n);
+  ts.clear();
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(hck_add(ctx, xs[4 * k], xs[4 * k + 2], xs[4 * k]));
+    TRY(hck_add(ctx, xs[4 * k + 1], xs[4 * k + 3], xs[4 * k + 1]));
+    hck_ciphertext *t1 = sc.get(), *t2 = sc.get();
+    TRY(hck_mul(ctx, xs[4 * k], xs[4 * k], t1));
+    TRY(hck_mul(ctx, xs[4 * k + 1], xs[4 * k + 1], t2));
+    TRY(hck_add(ctx, t1, t2, t1));
+    ts.push_back(t1);
+  }
+  TRY(relin_rs(ctx, ts, rlk, pspec));
+  ts.clear();
+  for (uint32_t k = 0; k < n; k++) {
+    hck_ciphertext *t1 = sc.get();
+    TRY(hck_mul(ctx, pspec[k], pspec[k], t1));
+    ts.push_back(t1);
+  }
+  TRY(relin_rs(ctx, ts, rlk, sh));
+  std::vector<hck_ciphertext *> chain;
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(mulpt_rs(ctx, sh[k], p->freq_resp, O(k, 2)));
+    TRY(mulpt_rs(ctx, sh[k], p->mask_resp, O(k, 3)));
+    TRY(mulpt_rs(ctx, sh[k], p->freq_hr, O(k, 4)));
+    TRY(mulpt_rs(ctx, sh[k], p->mask_hr, O(k, 5)));
+    chain.insert(chain.end(), {O(k, 2), O(k, 3), O(k, 4), O(k, 5)});
+  }
+  return rotsum(ctx, chain, 1, c_all, gks, sc);
+}
+
+extern "C" {
+
+int hck_vital_eval(hck_context *ctx, const hck_vital_plan *p, const hck_ciphertext *re,
+                   const hck_ciphertext *im, const hck_galois_keys *gks,
+                   const hck_switch_key *rlk, hck_ciphertext *const *out) {
+  if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  for (int i = 0; i < 6; i++)
+    if (out[i] == re || out[i] == im) return set_error(HCK_EINVAL, "outputs must not alias inputs");
+  return vital_eval_windows(ctx, p, &re, &im, 1, gks, rlk, out);
+}
+
+int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
+                        const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                        uint32_t n, const hck_galois_keys *gks, const hck_switch_key *rlk,
+                        hck_ciphertext *const *out) {
+  if (!ctx || !gks || !rlk || (n && (!re || !im || !out)))
+    return set_error(HCK_EINVAL, "null argument");
+  if (n == 0) return HCK_OK;
+  for (uint32_t i = 0; i < 6 * n; i++)
+    for (uint32_t k = 0; k < n; k++)
+      if (out[i] == re[k] || out[i] == im[k])
+        return set_error(HCK_EINVAL, "outputs must not alias inputs");
+  return vital_eval_windows(ctx, p, re, im, n, gks, rlk, out);
 }
 
 }  // extern "C"

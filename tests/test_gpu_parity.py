@@ -434,3 +434,20 @@ def test_empty_batches():
     assert p.ctx.rotate_steps([], [], gks, []) == []
     c, _ = p.rand_ct(p.o.L - 1, 1700)
     assert p.ctx.rotate_hoisted(c, [], gks) == []
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_relinearize_many_matches_oracle(name):
+    """Relinearizations switched together in batches (one relinearization key
+    stream) give the oracle's residues for every member, including an
+    in-place member and more members than one batch holds."""
+    p = pair(name)
+    o = p.o
+    level = o.L - 1 if name == "tiny" else o.L // 2
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    rlk_o = o.keygen_relin(p.s_o, 7)
+    cts = [p.rand_ct(level, 1800 + i, size=3) for i in range(10 if name != "vital" else 9)]
+    outs = [p.ctx.ciphertext() for _ in range(len(cts) - 1)] + [cts[-1][0]]
+    p.ctx.relinearize_many([c for c, _ in cts], rlk, outs)
+    for (c, c_o), out in zip(cts, outs):
+        assert np.array_equal(p.export(out), o.relinearize(c_o, rlk_o).polys)

@@ -104,3 +104,29 @@ def test_vital_plan_errors():
                                         len(prm["q"]) - 1), 4)
     with pytest.raises(H.HckError):   # keys missing
         ctx.vital_eval(plan, top, top, gks, rlk)
+
+
+def test_vital_windows_together_match_single_windows():
+    """Several windows evaluated together (shared key-switch batches) give
+    each window's residues of the single-window evaluation, which the test
+    above pins to the oracle."""
+    prm = S.params("mix15")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config()
+    l0 = len(prm["q"]) - 1
+    plan = HV.encode_plan(ctx, cfg, l0)
+    gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    res, ims = [], []
+    for k in range(3):
+        z = S.vital_window(1010 + k, cfg["frames"], cfg["bins"])
+        v = np.zeros(ctx.n_slots, dtype=np.complex128)
+        v[: z.size] = z.reshape(-1)
+        res.append(ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 400 + k))
+        ims.append(ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 500 + k))
+    together = ctx.vital_eval_many(plan, res, ims, gks, rlk)
+    for k in range(3):
+        alone = ctx.vital_eval(plan, res[k], ims[k], gks, rlk)
+        for a, b in zip(alone, together[k]):
+            assert np.array_equal(ctx.ciphertext_export(a)[0], ctx.ciphertext_export(b)[0]), k
