@@ -314,15 +314,18 @@ int hck_lt_destroy(hck_linear_transform *lt);
  *   K5  (If, Qf) per band = FIR transform (I, Q) (BSGS, hck_lt_eval; l0-4)
  *   K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
  *       (l0-5); taylor_order 3: dphi = y x^2 - y^3 third (l0-7); 1: dphi = y
- *   K3  dphi copied into lanes_resp (respiration) or the first power of two
- *       >= lanes_resp + lanes_hr lanes (heart rate) by rotations -1, -2, ...;
- *       X = sum_t dft weights x dphi (rotations R, 2R, ...); bands added
- *   K1  P = Re X^2 + Im X^2;  K2  S = P^2;  num_b = sum_k S_k freq_b,
- *       den_b = sum_k S_k mask_b (rotations 1 .. lanes/2; output level:
- *       dft level - 4).
- * Outputs (value in slot 0): out[0] num_bin, out[1] den_bin, out[2]
- * num_resp, out[3] den_resp, out[4] num_hr, out[5] den_hr; the client's
- * scalar divisions (section 3.3.4) give the target bin and the two rates.
+ *   K3  the two bands' DFT bins sit in two groups of G lanes per frame (G the
+ *       first power of two >= lanes_resp and lanes_hr): respiration from
+ *       lane 0, heart rate from lane G.  Each band's dphi is copied into its
+ *       lanes by rotations -1, -2, ...; the bands' weighted products are
+ *       added and summed over frames at once (rotations R, 2R, ...): X
+ *   K1  P = Re X^2 + Im X^2;  K2  S = P^2;  num = sum S freq, den = sum S
+ *       mask over each lane group (rotations 1 .. G/2; output level: dft
+ *       level - 4).
+ * Outputs: out[0] num_bin, out[1] den_bin (value in slot 0), out[2]
+ * num_rates, out[3] den_rates (respiration in slot 0, heart rate in slot
+ * G); the client's scalar divisions (section 3.3.4) give the target bin and
+ * the two rates in beats per minute.
  * The operands are public plaintexts and transforms owned by the caller,
  * encoded at least at the level where they are applied (above); scales
  * follow from the operands' scales (q_level keeps a ciphertext's scale).
@@ -331,25 +334,25 @@ int hck_lt_destroy(hck_linear_transform *lt);
 typedef struct {
   uint32_t frames, bins;         /* F; R a power of two, pow2ceil(F) R <= N/2 */
   uint32_t taylor_order;         /* 1 or 3 */
-  uint32_t lanes_resp, lanes_hr; /* DFT bins per band; pow2ceil(sum) <= R */
+  uint32_t lanes_resp, lanes_hr; /* DFT bins per band; 2 pow2ceil(max) <= R */
   const hck_plaintext *bin_index, *bin_mask;                    /* l0-2 */
   const hck_linear_transform *fir_resp, *fir_hr;                /* l0-3 */
   const hck_plaintext *third;                                   /* l0-5 (order 3) */
   const hck_plaintext *dft_re_resp, *dft_im_resp, *dft_re_hr, *dft_im_hr; /* l0-7 / l0-5 */
-  const hck_plaintext *freq_resp, *mask_resp, *freq_hr, *mask_hr;         /* dft level - 3 */
+  const hck_plaintext *freq, *mask;                             /* dft level - 3 */
 } hck_vital_plan;
 /* Rotation steps the pipeline needs Galois keys for (ascending; `cap` is the
  * capacity of steps[], *n receives the count; steps may be NULL). */
 int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan, int32_t *steps,
                              uint32_t cap, uint32_t *n);
-/* One window; out[0..5] must not alias re or im. */
+/* One window; out[0..3] must not alias re or im. */
 int hck_vital_eval(hck_context *ctx, const hck_vital_plan *plan, const hck_ciphertext *re,
                    const hck_ciphertext *im, const hck_galois_keys *gks,
                    const hck_switch_key *rlk, hck_ciphertext *const *out);
 /* n windows with one plan, evaluated together: every stage advances all
  * windows, so their rotate-and-sum chains and relinearizations share batched
  * key switches (a throughput mode; each window's residues equal
- * hck_vital_eval's).  Window k reads re[k], im[k] and writes out[6k .. 6k+5];
+ * hck_vital_eval's).  Window k reads re[k], im[k] and writes out[4k .. 4k+3];
  * outputs must not alias inputs. */
 int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *plan,
                         const hck_ciphertext *const *re, const hck_ciphertext *const *im,

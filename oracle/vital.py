@@ -21,19 +21,21 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
   K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
       (t-1 by a rotation of -R; l0-5); third order: dphi = y x^2 - y^3 / 3
       (l0-7), first order: dphi = y
-  K3  band b's DFT bins k occupy lanes c (slot t R + c; respiration first,
-      then heart rate): dphi is copied into the lanes by rotations -1, -2,
-      ..., multiplied by g w[t] cos(2 pi k t / F) / sum w and by
-      -g w[t] sin(...) / sum w (g: the folded DFT gain), and summed over t
-      by rotations R, 2R, ...; the
-      bands' results are added (disjoint lanes)
+  K3  the bands' DFT bins sit in two lane groups of G lanes (G the power of
+      two >= both bin counts; slot t R + c): respiration in lanes 0 .. G-1,
+      heart rate in lanes G .. 2G-1.  Each band's dphi is copied into its
+      lanes by rotations -1, -2, ..., multiplied by g w[t] cos(2 pi k t / F)
+      / sum w and by -g w[t] sin(...) / sum w (g: the folded DFT gain); the
+      two bands' products are added (disjoint lanes) and summed over t by
+      rotations R, 2R, ... (one chain for the real, one for the imaginary
+      part)
   K1  P = Re X^2 + Im X^2
-  K2  S = P^2; per band num_b = sum_k f_k S_k, den_b = sum_k S_k with f_k
-      the bin frequency in beats per minute (rotations 1 .. C/2)
+  K2  S = P^2; num = sum_c f_c S_c, den = sum_c S_c over each lane group
+      (f_c the bin frequency in beats per minute; rotations 1 .. G/2)
 
-Outputs (value in slot 0): num_r, den_r (target bin r^ = num_r / den_r) and
-num_b, den_b per band (rate in BPM = num_b / den_b), the client's scalar
-divisions of section 3.3.4.
+Outputs: num_bin, den_bin (value in slot 0; the target bin r^ = num / den),
+num_rates, den_rates (respiration in slot 0, heart rate in slot G; rate in
+BPM = num / den): the client's scalar divisions of section 3.3.4.
 """
 from __future__ import annotations
 
@@ -43,7 +45,7 @@ import numpy as np
 
 from . import Ciphertext, Oracle, Plaintext
 
-OUTPUTS = ("num_bin", "den_bin", "num_resp", "den_resp", "num_hr", "den_hr")
+OUTPUTS = ("num_bin", "den_bin", "num_rates", "den_rates")
 
 
 def _pow2_at_least(x: int) -> int:
@@ -59,9 +61,9 @@ class Layout:
     bins: int
     t2: int          # frames rounded up to a power of two
     n_slots: int
+    group: int       # lanes per band group (power of two)
     lanes: dict      # band -> first lane, count
-    c_resp: int      # lanes the respiration dphi is copied into
-    c_all: int       # lanes of both bands (power of two)
+    copies: dict     # band -> lanes its dphi is copied into (power of two)
 
 
 def layout(cfg: dict, n_slots: int) -> Layout:
@@ -70,11 +72,11 @@ def layout(cfg: dict, n_slots: int) -> Layout:
     if r & (r - 1) or t2 * r > n_slots:
         raise ValueError("bins must be a power of two and T2 R <= N/2")
     nr, nh = len(cfg["k_resp"]), len(cfg["k_hr"])
-    c_all = _pow2_at_least(nr + nh)
-    if c_all > r:
-        raise ValueError("more DFT lanes than range bins")
-    return Layout(f, r, t2, n_slots, {"resp": (0, nr), "hr": (nr, nh)},
-                  _pow2_at_least(nr), c_all)
+    g = _pow2_at_least(max(nr, nh))
+    if 2 * g > r:
+        raise ValueError("two lane groups do not fit the range bins")
+    return Layout(f, r, t2, n_slots, g, {"resp": (0, nr), "hr": (g, nh)},
+                  {"resp": _pow2_at_least(nr), "hr": _pow2_at_least(g + nh)})
 
 
 def operand_vectors(cfg: dict, n_slots: int) -> dict:
@@ -105,12 +107,12 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
     w = np.asarray(cfg["window"])
     ws = w.sum() / cfg["dft_gain"]
     t = np.arange(f)
+    fr = np.zeros(n_slots)
+    mk = np.zeros(n_slots)
     for band in ("resp", "hr"):
         c0, nb = lay.lanes[band]
         re = np.zeros(n_slots)
         im = np.zeros(n_slots)
-        fr = np.zeros(n_slots)
-        mk = np.zeros(n_slots)
         for i, k in enumerate(cfg[f"k_{band}"]):
             c = c0 + i
             re[t * r + c] = w * np.cos(2 * np.pi * k * t / f) / ws
@@ -119,8 +121,8 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
             mk[c] = 1.0
         v[f"dft_re_{band}"] = re
         v[f"dft_im_{band}"] = im
-        v[f"freq_{band}"] = fr
-        v[f"mask_{band}"] = mk
+    v["freq"] = fr
+    v["mask"] = mk
     return v
 
 
@@ -150,8 +152,8 @@ def encode_operands(o: Oracle, cfg: dict, level0: int, vecs: dict | None = None)
         ops[f"fir_{band}"] = o.lt_create(vecs[f"fir_{band}"], n1, lv["fir"])
         for part in ("dft_re", "dft_im"):
             ops[f"{part}_{band}"] = enc(f"{part}_{band}", lv["dft"])
-        for part in ("freq", "mask"):
-            ops[f"{part}_{band}"] = enc(f"{part}_{band}", lv["freq"])
+    for part in ("freq", "mask"):
+        ops[part] = enc(part, lv["freq"])
     return ops
 
 
@@ -161,7 +163,7 @@ def required_steps(o: Oracle, cfg: dict, ops: dict) -> list:
     steps = {r * (1 << i) for i in range(lay.t2.bit_length() - 1)}
     steps |= {1 << i for i in range(r.bit_length() - 1)}
     steps.add(-r)
-    steps |= {-(1 << i) for i in range(lay.c_all.bit_length() - 1)}
+    steps |= {-(1 << i) for i in range(lay.copies["hr"].bit_length() - 1)}
     for band in ("resp", "hr"):
         steps |= set(o.lt_required_steps(ops[f"fir_{band}"]))
     return sorted(steps)
@@ -207,7 +209,8 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
              (ops["fir_hr"], 0, 2, 1), (ops["fir_hr"], 1, 3, 1)]
     filt = [o.rescale(c) for c in o.lt_eval([i_t, q_t], terms, gks, 4, hoist=True,
                                                 hoist_giant=True)]
-    # K7 and K3 per band
+    # K7 and K3 per band; the bands' DFT products are added before the sum
+    # over frames
     x_re = x_im = None
     for band, (fi, fq) in (("resp", (filt[0], filt[1])), ("hr", (filt[2], filt[3]))):
         fi1, fq1 = o.rotate(fi, -r, gks), o.rotate(fq, -r, gks)
@@ -221,24 +224,22 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
             dphi = o.sub(a, _mul(o, yc, y2, rlk))
         else:
             dphi = y
-        c = lay.c_resp if band == "resp" else lay.c_all
         rep = dphi
         s = 1
-        while s < c:
+        while s < lay.copies[band]:
             rep = o.add(rep, o.rotate(rep, -s, gks))
             s *= 2
-        xr = _rotsum(o, o.rescale(o.mul_plain(rep, ops[f"dft_re_{band}"])), r, t2, gks)
-        xi = _rotsum(o, o.rescale(o.mul_plain(rep, ops[f"dft_im_{band}"])), r, t2, gks)
+        xr = o.rescale(o.mul_plain(rep, ops[f"dft_re_{band}"]))
+        xi = o.rescale(o.mul_plain(rep, ops[f"dft_im_{band}"]))
         x_re = xr if x_re is None else o.add(x_re, xr)
         x_im = xi if x_im is None else o.add(x_im, xi)
-    # K1 on the spectrum, K2: sharpening and weighted frequency average
+    x_re = _rotsum(o, x_re, r, t2, gks)
+    x_im = _rotsum(o, x_im, r, t2, gks)
+    # K1 on the spectrum, K2: sharpening and weighted frequency averages
     pw = _square_sum(o, x_re, x_im, rlk)
     sh = _mul(o, pw, pw, rlk)
-    for band in ("resp", "hr"):
-        out[f"num_{band}"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops[f"freq_{band}"])), 1,
-                                     lay.c_all, gks)
-        out[f"den_{band}"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops[f"mask_{band}"])), 1,
-                                     lay.c_all, gks)
+    out["num_rates"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops["freq"])), 1, lay.group, gks)
+    out["den_rates"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops["mask"])), 1, lay.group, gks)
     return out
 
 
@@ -287,6 +288,16 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
         out[f"num_{band}"] = float(np.sum(fk * s))
         out[f"den_{band}"] = float(np.sum(s))
     return out
+
+
+def plain_slots(cfg: dict, z: np.ndarray, n_slots: int) -> dict:
+    """plain() arranged as the outputs' decoded slots: output name -> {slot:
+    value}."""
+    lay = layout(cfg, n_slots)
+    v = plain(cfg, z)
+    return {"num_bin": {0: v["num_bin"]}, "den_bin": {0: v["den_bin"]},
+            "num_rates": {0: v["num_resp"], lay.group: v["num_hr"]},
+            "den_rates": {0: v["den_resp"], lay.group: v["den_hr"]}}
 
 
 def encrypt_window(o: Oracle, s, z: np.ndarray, level: int, scale: float, seed: int):

@@ -273,12 +273,11 @@ class VitalPlan(ctypes.Structure):
                 ("lanes_hr", ctypes.c_uint32)] + [
         (name, ctypes.c_void_p) for name in (
             "bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
-            "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq_resp", "mask_resp", "freq_hr",
-            "mask_hr")]
+            "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")]
 
     OPERANDS = ("bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
-                "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq_resp", "mask_resp", "freq_hr",
-                "mask_hr")
+                "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")
+    OUTPUTS = ("num_bin", "den_bin", "num_rates", "den_rates")
 
     @classmethod
     def build(cls, frames, bins, taylor_order, lanes_resp, lanes_hr, operands: dict):
@@ -604,24 +603,26 @@ class Context:
         return list(buf[: n.value])
 
     def vital_eval(self, plan: VitalPlan, re, im, gks, rlk, outputs=None):
-        """The six outputs num_bin, den_bin, num_resp, den_resp, num_hr, den_hr."""
-        outputs = [self.ciphertext() for _ in range(6)] if outputs is None else outputs
-        outs = (ctypes.c_void_p * 6)(*[c.h for c in outputs])
+        """The four outputs num_bin, den_bin (slot 0) and num_rates,
+        den_rates (respiration in slot 0, heart rate in slot
+        vital.lane_group(...))."""
+        outputs = [self.ciphertext() for _ in range(4)] if outputs is None else outputs
+        outs = (ctypes.c_void_p * 4)(*[c.h for c in outputs])
         _check(capi.hck_vital_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs))
         return outputs
 
     def vital_eval_many(self, plan: VitalPlan, res, ims, gks, rlk, outputs=None):
-        """Several windows together; returns one list of 6 outputs per window."""
+        """Several windows together; returns one list of 4 outputs per window."""
         n = len(res)
         if len(ims) != n:
             raise ValueError("one imaginary ciphertext per window")
-        outputs = ([self.ciphertext() for _ in range(6 * n)] if outputs is None
+        outputs = ([self.ciphertext() for _ in range(4 * n)] if outputs is None
                    else [c for w in outputs for c in w])
         a = (ctypes.c_void_p * n)(*[c.h for c in res])
         b = (ctypes.c_void_p * n)(*[c.h for c in ims])
-        o = (ctypes.c_void_p * (6 * n))(*[c.h for c in outputs])
+        o = (ctypes.c_void_p * (4 * n))(*[c.h for c in outputs])
         _check(capi.hck_vital_eval_many(self.h, ctypes.addressof(plan), a, b, n, gks, rlk, o))
-        return [outputs[6 * k: 6 * k + 6] for k in range(n)]
+        return [outputs[4 * k: 4 * k + 4] for k in range(n)]
 
     # --- gesture-classification pipeline ---
     def gesture_required_steps(self, plan: GesturePlan) -> list:

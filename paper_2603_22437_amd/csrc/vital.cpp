@@ -1,7 +1,7 @@
 // The paper's vital-sign pipeline (section 3.3.3 example pipelines:
 // K1 -> K2 -> K4 -> K5 -> K7 -> K3 -> K1 -> K2) composed from the library's
 // evaluation calls.  Every rotate-and-sum chain advances all its independent
-// members (num/den, I/Q, real/imaginary parts of both bands) by one step per
+// members (num/den, I/Q, real/imaginary parts) by one step per
 // batched key switch (hck_rotate_many), so one window issues as few key-switch
 // launch sequences as its dependency depth allows.
 #include <algorithm>
@@ -23,6 +23,18 @@ uint32_t pow2_at_least(uint32_t x) {
   uint32_t p = 1;
   while (p < x) p *= 2;
   return p;
+}
+
+// The DFT bins of the two bands sit in two lane groups of `group` lanes of
+// every frame's R slots: respiration from lane 0, heart rate from lane group.
+// Each band's phase is copied into the first copies_* lanes.
+struct Lanes {
+  uint32_t group, copies_resp, copies_hr;
+};
+
+Lanes lanes_of(const hck_vital_plan *p) {
+  const uint32_t g = pow2_at_least(std::max(p->lanes_resp, p->lanes_hr));
+  return {g, pow2_at_least(p->lanes_resp), pow2_at_least(g + p->lanes_hr)};
 }
 
 // Scratch ciphertexts returned to the context's pool on scope exit.
@@ -48,12 +60,12 @@ int check_plan(const hck_context *ctx, const hck_vital_plan *p) {
     return set_error(HCK_EINVAL, "frames x bins do not fit the slots");
   if (p->taylor_order != 1 && p->taylor_order != 3)
     return set_error(HCK_EINVAL, "Taylor order must be 1 or 3");
-  if (p->lanes_resp == 0 || p->lanes_hr == 0 ||
-      pow2_at_least(p->lanes_resp + p->lanes_hr) > p->bins)
-    return set_error(HCK_EINVAL, "DFT lanes do not fit the range bins");
+  if (p->lanes_resp == 0 || p->lanes_hr == 0 || p->lanes_resp > p->bins ||
+      p->lanes_hr > p->bins || 2 * lanes_of(p).group > p->bins)
+    return set_error(HCK_EINVAL, "the two DFT lane groups do not fit the range bins");
   if (!p->bin_index || !p->bin_mask || !p->fir_resp || !p->fir_hr || !p->dft_re_resp ||
-      !p->dft_im_resp || !p->dft_re_hr || !p->dft_im_hr || !p->freq_resp || !p->mask_resp ||
-      !p->freq_hr || !p->mask_hr || (p->taylor_order == 3 && !p->third))
+      !p->dft_im_resp || !p->dft_re_hr || !p->dft_im_hr || !p->freq || !p->mask ||
+      (p->taylor_order == 3 && !p->third))
     return set_error(HCK_EINVAL, "missing plan operand");
   return HCK_OK;
 }
@@ -61,11 +73,10 @@ int check_plan(const hck_context *ctx, const hck_vital_plan *p) {
 std::vector<int32_t> plan_steps(const hck_vital_plan *p) {
   std::vector<int32_t> s;
   const uint32_t r = p->bins, t2 = pow2_at_least(p->frames);
-  const uint32_t c_all = pow2_at_least(p->lanes_resp + p->lanes_hr);
   for (uint32_t k = r; k < r * t2; k *= 2) s.push_back((int32_t)k);
   for (uint32_t k = 1; k < r; k *= 2) s.push_back((int32_t)k);
   s.push_back(-(int32_t)r);
-  for (uint32_t k = 1; k < c_all; k *= 2) s.push_back(-(int32_t)k);
+  for (uint32_t k = 1; k < lanes_of(p).copies_hr; k *= 2) s.push_back(-(int32_t)k);
   for (const hck_linear_transform *lt : {p->fir_resp, p->fir_hr})
     for (auto &kv : lt->groups) {
       if (kv.first != 0) s.push_back(kv.first * (int32_t)lt->n1);
@@ -157,8 +168,8 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
     if (re[k]->level != re[0]->level || im[k]->level != re[0]->level || re[0]->level < depth)
       return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
-    for (int i = 0; i < 6; i++)
-      if (!out[6 * k + i]) return set_error(HCK_EINVAL, "null output");
+    for (int i = 0; i < 4; i++)
+      if (!out[4 * k + i]) return set_error(HCK_EINVAL, "null output");
   }
   for (int32_t s : plan_steps(p))
     if (!gks->keys.count(galois_of_step(ctx, s)))
@@ -166,14 +177,13 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   Scratch sc(ctx);
   const int32_t r = (int32_t)p->bins;
   const uint32_t t2 = pow2_at_least(p->frames);
-  const uint32_t c_resp = pow2_at_least(p->lanes_resp);
-  const uint32_t c_all = pow2_at_least(p->lanes_resp + p->lanes_hr);
+  const Lanes lanes = lanes_of(p);
   auto fresh = [&](uint32_t count) {
     std::vector<hck_ciphertext *> v(count);
     for (auto &c : v) c = sc.get();
     return v;
   };
-  auto O = [&](uint32_t k, int i) { return out[6 * k + i]; };
+  auto O = [&](uint32_t k, int i) { return out[4 * k + i]; };
 
   // K1: p = Re^2 + Im^2 (one batched relinearization), E = sum over frames
   std::vector<hck_ciphertext *> pw = fresh(n), e = fresh(n), t = fresh(n), u = fresh(n);
@@ -281,36 +291,39 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     for (uint32_t j = 0; j < 2 * n; j++) TRY(hck_sub(ctx, av[j], bv[j], dphi[j]));
   }
   // K3: copy each dphi into its band's lanes (dphi[2k]: respiration,
-  // dphi[2k + 1]: heart rate), weight, sum over frames
-  for (uint32_t s = 1; s < c_all; s *= 2) {
+  // dphi[2k + 1]: heart rate), weight; the bands' products are added (disjoint
+  // lanes) so that one sum over frames serves both
+  for (uint32_t s = 1; s < lanes.copies_hr; s *= 2) {
     std::vector<hck_ciphertext *> src;
     for (uint32_t k = 0; k < n; k++) {
       src.push_back(dphi[2 * k + 1]);
-      if (s < c_resp) src.push_back(dphi[2 * k]);
+      if (s < lanes.copies_resp) src.push_back(dphi[2 * k]);
     }
     std::vector<hck_ciphertext *> tmp = fresh((uint32_t)src.size());
     TRY(hck_rotate_many(ctx, src.data(), (uint32_t)src.size(), -(int32_t)s, gks, tmp.data()));
     for (size_t i = 0; i < src.size(); i++) TRY(hck_add(ctx, src[i], tmp[i], src[i]));
   }
-  std::vector<hck_ciphertext *> xs = fresh(4 * n);
+  std::vector<hck_ciphertext *> xs = fresh(2 * n);
   for (uint32_t k = 0; k < n; k++) {
-    TRY(mulpt_rs(ctx, dphi[2 * k], p->dft_re_resp, xs[4 * k]));
-    TRY(mulpt_rs(ctx, dphi[2 * k], p->dft_im_resp, xs[4 * k + 1]));
-    TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_re_hr, xs[4 * k + 2]));
-    TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_im_hr, xs[4 * k + 3]));
+    hck_ciphertext *hr_re = sc.get(), *hr_im = sc.get();
+    TRY(mulpt_rs(ctx, dphi[2 * k], p->dft_re_resp, xs[2 * k]));
+    TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_re_hr, hr_re));
+    TRY(hck_add(ctx, xs[2 * k], hr_re, xs[2 * k]));
+    TRY(mulpt_rs(ctx, dphi[2 * k], p->dft_im_resp, xs[2 * k + 1]));
+    TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_im_hr, hr_im));
+    TRY(hck_add(ctx, xs[2 * k + 1], hr_im, xs[2 * k + 1]));
   }
   TRY(rotsum(ctx, xs, r, t2, gks, sc));
-  // K1 on the spectrum, K2: sharpening and weighted frequency averages
+  // K1 on the spectrum, K2: sharpening and the weighted frequency averages of
+  // both lane groups (respiration in slot 0, heart rate in slot `group`)
   std::vector<hck_ciphertext *> pspec = fresh(n), sh = fresh(n);
   ts.clear();
   for (uint32_t k = 0; k < n; k++) {
-    TRY(hck_add(ctx, xs[4 * k], xs[4 * k + 2], xs[4 * k]));
-    TRY(hck_add(ctx, xs[4 * k + 1], xs[4 * k + 3], xs[4 * k + 1]));
-    hck_ciphertext *t1 = sc.get(), *t2 = sc.get();
-    TRY(hck_mul(ctx, xs[4 * k], xs[4 * k], t1));
-    TRY(hck_mul(ctx, xs[4 * k + 1], xs[4 * k + 1], t2));
-    TRY(hck_add(ctx, t1, t2, t1));
-    ts.push_back(t1);
+    hck_ciphertext *sq_re = sc.get(), *sq_im = sc.get();
+    TRY(hck_mul(ctx, xs[2 * k], xs[2 * k], sq_re));
+    TRY(hck_mul(ctx, xs[2 * k + 1], xs[2 * k + 1], sq_im));
+    TRY(hck_add(ctx, sq_re, sq_im, sq_re));
+    ts.push_back(sq_re);
   }
   TRY(relin_rs(ctx, ts, rlk, pspec));
   ts.clear();
@@ -322,13 +335,11 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   TRY(relin_rs(ctx, ts, rlk, sh));
   std::vector<hck_ciphertext *> chain;
   for (uint32_t k = 0; k < n; k++) {
-    TRY(mulpt_rs(ctx, sh[k], p->freq_resp, O(k, 2)));
-    TRY(mulpt_rs(ctx, sh[k], p->mask_resp, O(k, 3)));
-    TRY(mulpt_rs(ctx, sh[k], p->freq_hr, O(k, 4)));
-    TRY(mulpt_rs(ctx, sh[k], p->mask_hr, O(k, 5)));
-    chain.insert(chain.end(), {O(k, 2), O(k, 3), O(k, 4), O(k, 5)});
+    TRY(mulpt_rs(ctx, sh[k], p->freq, O(k, 2)));
+    TRY(mulpt_rs(ctx, sh[k], p->mask, O(k, 3)));
+    chain.insert(chain.end(), {O(k, 2), O(k, 3)});
   }
-  return rotsum(ctx, chain, 1, c_all, gks, sc);
+  return rotsum(ctx, chain, 1, lanes.group, gks, sc);
 }
 
 extern "C" {
@@ -337,7 +348,7 @@ int hck_vital_eval(hck_context *ctx, const hck_vital_plan *p, const hck_cipherte
                    const hck_ciphertext *im, const hck_galois_keys *gks,
                    const hck_switch_key *rlk, hck_ciphertext *const *out) {
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
-  for (int i = 0; i < 6; i++)
+  for (int i = 0; i < 4; i++)
     if (out[i] == re || out[i] == im) return set_error(HCK_EINVAL, "outputs must not alias inputs");
   return vital_eval_windows(ctx, p, &re, &im, 1, gks, rlk, out);
 }
@@ -349,7 +360,7 @@ int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
   if (!ctx || !gks || !rlk || (n && (!re || !im || !out)))
     return set_error(HCK_EINVAL, "null argument");
   if (n == 0) return HCK_OK;
-  for (uint32_t i = 0; i < 6 * n; i++)
+  for (uint32_t i = 0; i < 4 * n; i++)
     for (uint32_t k = 0; k < n; k++)
       if (out[i] == re[k] || out[i] == im[k])
         return set_error(HCK_EINVAL, "outputs must not alias inputs");

@@ -24,6 +24,8 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
     F, R = cfg["frames"], cfg["bins"]
     if _next_pow2(F) * R > n_slots:
         raise ValueError("window does not fit the slots")
+    if 2 * lane_group(cfg) > R:
+        raise ValueError("the two DFT lane groups do not fit the range bins")
     frames = np.arange(F)
     out = {}
     zero = lambda: np.zeros(n_slots)
@@ -45,18 +47,25 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
     out["third"] = np.full(n_slots, 1.0 / 3.0)
     win = np.asarray(cfg["window"], dtype=np.float64)
     norm = cfg["dft_gain"] / win.sum()
-    lane0 = {"resp": 0, "hr": len(cfg["k_resp"])}
+    group = lane_group(cfg)
+    lane0 = {"resp": 0, "hr": group}
+    out["freq"], out["mask"] = zero(), zero()
     for band in ("resp", "hr"):
-        vr, vi, fq, mk = zero(), zero(), zero(), zero()
+        vr, vi = zero(), zero()
         for lane, k in enumerate(cfg["k_" + band], start=lane0[band]):
             ang = 2.0 * np.pi * k * frames / F
             vr[frames * R + lane] = norm * win * np.cos(ang)
             vi[frames * R + lane] = -norm * win * np.sin(ang)
-            fq[lane] = 60.0 * k * cfg["fps"] / F
-            mk[lane] = 1.0
+            out["freq"][lane] = 60.0 * k * cfg["fps"] / F
+            out["mask"][lane] = 1.0
         out["dft_re_" + band], out["dft_im_" + band] = vr, vi
-        out["freq_" + band], out["mask_" + band] = fq, mk
     return out
+
+
+def lane_group(cfg: dict) -> int:
+    """Lanes per band group: respiration's DFT bins from lane 0, heart rate's
+    from this lane, of every frame's R slots (the rates' output slots)."""
+    return _next_pow2(max(len(cfg["k_resp"]), len(cfg["k_hr"])))
 
 
 def fir_baby_step(cfg: dict) -> int:
@@ -83,7 +92,7 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
         ops["fir_" + band] = ctx.lt_create(vec["fir_" + band], n1, lv["fir"])
         for name in ("dft_re_", "dft_im_"):
             ops[name + band] = pt(name + band, lv["dft"])
-        for name in ("freq_", "mask_"):
-            ops[name + band] = pt(name + band, lv["freq"])
+    for name in ("freq", "mask"):
+        ops[name] = pt(name, lv["freq"])
     return VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"], len(cfg["k_resp"]),
                            len(cfg["k_hr"]), ops)

@@ -451,3 +451,79 @@ def test_relinearize_many_matches_oracle(name):
     p.ctx.relinearize_many([c for c, _ in cts], rlk, outs)
     for (c, c_o), out in zip(cts, outs):
         assert np.array_equal(p.export(out), o.relinearize(c_o, rlk_o).polys)
+
+
+@pytest.mark.slow
+def test_lt_eval_full_size_bench_shape():
+    """The benchmark's linear-transform launch at full size (N = 2^16, L = 24,
+    n1 = 20, complex four-term evaluation over shared inputs, hoisted baby
+    steps and one ModDown per output): 2 x 61 diagonals over 4 giant groups
+    instead of 2 x 399 (which the oracle would take many minutes to multiply),
+    same kernels and launch shapes, bit-exact."""
+    p = pair("vital")
+    o = p.o
+    level = o.L - 1
+    offs = list(range(-30, 31))
+    mats = {}
+    qs = float(o.q[level])
+    for m, seed in (("C", 2100), ("S", 2200)):
+        res = {k: S.uniform_residues(o.qmods(level), o.n, seed + i)[0] for i, k in enumerate(offs)}
+        mats[m] = (p.ctx.lt_create_from_residues(res, 20, level, qs),
+                   o.lt_from_plaintexts({k: O.Plaintext(r, level, qs) for k, r in res.items()},
+                                        20, level, qs))
+    steps = sorted(set(p.ctx.lt_required_steps(mats["C"][0])))
+    gks, gko = p.galois(steps)
+    v_re, v_re_o = p.rand_ct(level, 2300)
+    v_im, v_im_o = p.rand_ct(level, 2301)
+    terms = [("C", 0, 0, 1), ("S", 1, 0, -1), ("S", 0, 1, 1), ("C", 1, 1, 1)]
+    got = p.ctx.lt_eval([v_re, v_im], [(mats[m][0], i, j, s) for m, i, j, s in terms], gks,
+                        hoist=True, hoist_giant=True)
+    want = o.lt_eval([v_re_o, v_im_o], [(mats[m][1], i, j, s) for m, i, j, s in terms], gko, 2,
+                     hoist=True, hoist_giant=True)
+    for g_, w in zip(got, want):
+        assert np.array_equal(p.export(g_), w.polys)
+
+
+def test_bench_step_decodes_at_full_size():
+    """The benchmark step itself (2 x 399 cached diagonals of the windowed
+    200-point DFT, n1 = 20, then |.|^2) decodes to |W z|^2 of the synthetic
+    window within 1e-3 (a property that holds at any size)."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    frames, bins, n1 = 200, 64, 20
+    z = S.vital_window(1000, frames, bins)
+    n_slots = ctx.n_slots
+    v = np.zeros(n_slots, dtype=np.complex128)
+    v[: frames * bins] = z.T.reshape(-1)
+    top = len(prm["q"]) - 1
+    ct_re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 100)
+    ct_im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 101)
+    w = S.windowed_dft_matrix(frames)
+
+    def block_diagonals(mat):
+        out = {}
+        k = np.arange(frames)
+        for off in range(-(frames - 1), frames):
+            col = k + off
+            ok = (col >= 0) & (col < frames)
+            vals = np.where(ok, mat[k, np.clip(col, 0, frames - 1)], 0.0)
+            vec = np.zeros(n_slots)
+            vec[: bins * frames] = np.tile(vals, bins)
+            if np.any(vec):
+                out[off] = vec
+        return out
+
+    lt_c = ctx.lt_create(block_diagonals(w.real), n1, top)
+    lt_s = ctx.lt_create(block_diagonals(w.imag), n1, top)
+    steps = sorted(set(ctx.lt_required_steps(lt_c)) | set(ctx.lt_required_steps(lt_s)))
+    gks = ctx.keygen_rotation(sk, steps, 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    d_re, d_im = ctx.lt_eval([ct_re, ct_im], [(lt_c, 0, 0, 1), (lt_s, 1, 0, -1),
+                                              (lt_s, 0, 1, 1), (lt_c, 1, 1, 1)], gks,
+                             hoist=True, hoist_giant=True)
+    d_re, d_im = ctx.rescale(d_re), ctx.rescale(d_im)
+    pw = ctx.rescale(ctx.relinearize(ctx.add(ctx.mul(d_re, d_re), ctx.mul(d_im, d_im)), rlk))
+    got = ctx.decode(ctx.decrypt(sk, pw)).real[: frames * bins].reshape(bins, frames)
+    ref = np.abs(w @ z).T ** 2
+    assert np.max(np.abs(got - ref)) < 1e-3

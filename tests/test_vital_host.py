@@ -31,6 +31,42 @@ def test_operand_vectors_match_oracle(order):
         lv["bin_index"], lv["fir"], lv["third"], lv["dft"], lv["freq"])
 
 
+def test_band_lane_groups():
+    """Respiration's DFT bins from lane 0 and heart rate's from lane G (the
+    power of two >= both counts), inside the R range bins; both builders agree
+    and reject a layout whose two groups overflow the bins."""
+    cfg = S.vital_pipeline_config()
+    lay = OV.layout(cfg, 1 << 15)
+    assert lay.group == HV.lane_group(cfg) == 32
+    assert lay.lanes == {"resp": (0, 6), "hr": (32, 18)}
+    v = OV.operand_vectors(cfg, 1 << 15)
+    lanes = np.flatnonzero(v["mask"])
+    assert list(lanes) == list(range(6)) + list(range(32, 50))
+    for band, (c0, nb) in lay.lanes.items():
+        # every frame's weights stay inside the band's lanes
+        nz = np.flatnonzero(v[f"dft_re_{band}"]) % cfg["bins"]
+        assert nz.min() >= c0 and nz.max() < c0 + nb
+    small = dict(cfg, bins=32)
+    with pytest.raises(ValueError):
+        OV.layout(small, 1 << 15)
+    with pytest.raises(ValueError):
+        HV.operand_vectors(small, 1 << 15)
+
+
+def test_plain_slots_are_the_band_sums():
+    """plain_slots places each band's sums where the lane-group sums leave
+    them: slot 0 for respiration, slot G for heart rate."""
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1000, cfg["frames"], cfg["bins"])
+    p = OV.plain(cfg, z)
+    ps = OV.plain_slots(cfg, z, 1 << 15)
+    assert ps["num_rates"] == {0: p["num_resp"], 32: p["num_hr"]}
+    assert ps["den_rates"] == {0: p["den_resp"], 32: p["den_hr"]}
+    # the rates fall inside their bands (beats / breaths per minute)
+    assert 6 <= p["num_resp"] / p["den_resp"] <= 36
+    assert 48 <= p["num_hr"] / p["den_hr"] <= 150
+
+
 def test_plain_circuit_is_the_dsp_it_approximates():
     """The plaintext mirror: the bin estimate lands on the synthetic target
     bin, and with a small phase step the cubic Taylor term is arctan(y/x) x^3
@@ -60,8 +96,9 @@ def test_oracle_pipeline_decodes_to_plain_circuit():
     rlk = o.keygen_relin(s, 7)
     re, im = OV.encrypt_window(o, s, z, l0, prm["scale"], 100)
     out = OV.evaluate(o, cfg, ops, re, im, gks, rlk)
-    want = OV.plain(cfg, z)
+    want = OV.plain_slots(cfg, z, o.n_slots)
     for k in OV.OUTPUTS:
         assert out[k].level == (l0 - 3 if k.endswith("bin") else 0)
-        got = o.decode(o.decrypt(s, out[k]))[0].real
-        assert abs(got - want[k]) < 1e-6 * max(1.0, abs(want[k])), k
+        dec = o.decode(o.decrypt(s, out[k])).real
+        for slot, v in want[k].items():
+            assert abs(dec[slot] - v) < 1e-6 * max(1.0, abs(v)), (k, slot)
