@@ -78,7 +78,7 @@ def main():
                          "rotation modes or per-kernel event pass")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the vital-sign pipeline latency measurement")
-    ap.add_argument("--pipeline-windows", type=int, default=8,
+    ap.add_argument("--pipeline-windows", type=int, default=100,
                     help="timed windows of the vital-sign pipeline")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy of known "
@@ -406,6 +406,10 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     torch.cuda.synchronize()
     batched_wps = batch * reps / (time.perf_counter() - t0)
     del outs_b, res_b, ims_b
+    noise = kernel_noise(ctx, prm, sk, top, ctx.VITAL_TAPS + plan.OUTPUTS,
+                         lambda re_, im_: _flat(ctx.vital_eval_taps(plan, re_, im_, gks, rlk)),
+                         lambda zz: HV.plain_stages(cfg, zz, ctx.n_slots),
+                         [S.vital_window(1000 + i, cfg["frames"], cfg["bins"]) for i in range(3)])
     got = [ctx.decode(ctx.decrypt(sk, c)).real for c in outs]
     g = HV.lane_group(cfg)
     # the energy-weighted bin estimate must land on the synthetic target bin
@@ -418,7 +422,8 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "rotation_keys": len(gks), "target_bin_true": target,
            "target_bin_est": round(float(got[0][0] / got[1][0]), 4),
            "resp_bpm_est": round(float(got[2][0] / got[3][0]), 3),
-           "hr_bpm_est": round(float(got[2][g] / got[3][g]), 3)}
+           "hr_bpm_est": round(float(got[2][g] / got[3][g]), 3),
+           "kernel_noise": noise}
     log(f"vital pipeline: {res}")
     return res
 
@@ -455,13 +460,50 @@ def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(windows)])
     classes = cfg["weights"][2].shape[0]
     logits = ctx.decode(ctx.decrypt(sk, out))[:classes].real
+    noise = kernel_noise(ctx, prm, sk, top, ctx.GESTURE_TAPS + ("FC3 logits",),
+                         lambda re_, im_: _flat(ctx.gesture_eval_taps(plan, re_, im_, gks, rlk)),
+                         lambda xx: HG.plain_stages(cfg, xx, ctx.n_slots),
+                         [S.gesture_window(2000 + i, cfg["frames"]) for i in range(3)])
     res = {"windows": windows, "p50_ms": round(float(np.percentile(ms, 50)), 3),
            "p99_ms": round(float(np.percentile(ms, 99)), 3),
            "windows_per_s": round(windows / wall, 2), "rotation_keys": len(gks),
            "frames": cfg["frames"], "classes": classes,
-           "predicted_class": int(np.argmax(logits))}
+           "predicted_class": int(np.argmax(logits)), "kernel_noise": noise}
     log(f"gesture pipeline: {res}")
     return res
+
+
+def _flat(result):
+    """(outputs, taps) of a *_eval_taps call as one list: taps, then outputs."""
+    outs, taps = result
+    return list(taps) + (list(outs) if isinstance(outs, (list, tuple)) else [outs])
+
+
+def kernel_noise(ctx, prm, sk, top, names, run, plain, windows):
+    """Per-kernel encryption noise, the method of section 5.2 (Table 3): the
+    MSE and max |error| between each decoded intermediate of the encrypted
+    pipeline and the same value from plaintext execution, cumulative after
+    the preceding kernels, over the given windows; depth = levels consumed."""
+    sq = [0.0] * len(names)
+    cnt = [0] * len(names)
+    mx = [0.0] * len(names)
+    depth = [0] * len(names)
+    for k, z in enumerate(windows):
+        v = np.zeros(ctx.n_slots, dtype=np.complex128)
+        v[: z.size] = np.asarray(z).reshape(-1)
+        re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 900 + 2 * k)
+        im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 901 + 2 * k)
+        cts = run(re, im)
+        for i, (c, (slots, want)) in enumerate(zip(cts, plain(z))):
+            got = ctx.decode(ctx.decrypt(sk, c)).real[slots]
+            err = got - want
+            sq[i] += float(np.sum(err ** 2))
+            cnt[i] += len(slots)
+            mx[i] = max(mx[i], float(np.max(np.abs(err))))
+            depth[i] = top - c.level
+    return [{"stage": n, "mse": float(f"{sq[i] / cnt[i]:.3e}"),
+             "max_abs_err": float(f"{mx[i]:.3e}"), "depth": depth[i]}
+            for i, n in enumerate(names)]
 
 
 def cpu_baseline(prm, seconds, log):

@@ -349,6 +349,23 @@ int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
 int hck_vital_eval(hck_context *ctx, const hck_vital_plan *plan, const hck_ciphertext *re,
                    const hck_ciphertext *im, const hck_galois_keys *gks,
                    const hck_switch_key *rlk, hck_ciphertext *const *out);
+/* hck_vital_eval that also copies each kernel's intermediate result into
+ * taps[i] (caller-owned; a null entry skips that copy), for the per-kernel
+ * encryption-noise measurement of section 5.2 (Table 3: encrypted against
+ * plaintext execution, cumulative after the preceding kernels):
+ *   0 K1 p (slot t R + r)          1 K1 energy E (slot r)
+ *   2 K2 w = E^2 (slot r)          3, 4 K4 I, Q (slot t R)
+ *   5..8 K5 If, Qf of respiration, If, Qf of heart rate (slot t R)
+ *   9, 10 K7 dphi of respiration, heart rate (slot t R)
+ *   11, 12 K3 Re X, Im X (lane c of frame 0)
+ *   13 K1 P = Re X^2 + Im X^2     14 K2 S = P^2 (lane c).
+ * out[] receives hck_vital_eval's results, bit-identical to it.  Taps must
+ * not alias re or im. */
+#define HCK_VITAL_TAPS 15
+int hck_vital_eval_taps(hck_context *ctx, const hck_vital_plan *plan, const hck_ciphertext *re,
+                        const hck_ciphertext *im, const hck_galois_keys *gks,
+                        const hck_switch_key *rlk, hck_ciphertext *const *out,
+                        hck_ciphertext *const *taps);
 /* n windows with one plan, evaluated together: every stage advances all
  * windows, so their rotate-and-sum chains and relinearizations share batched
  * key switches (a throughput mode; each window's residues equal
@@ -390,6 +407,19 @@ int hck_gesture_required_steps(const hck_context *ctx, const hck_gesture_plan *p
 int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *plan, const hck_ciphertext *re,
                      const hck_ciphertext *im, const hck_galois_keys *gks,
                      const hck_switch_key *rlk, hck_ciphertext *out);
+/* hck_gesture_eval that also copies each stage's result into taps[i]
+ * (caller-owned; null entries skipped), for the per-kernel encryption-noise
+ * measurement of section 5.2 (Table 3):
+ *   0, 1 K3 d_re, d_im (slot (t R + r) D + c)   2 K1 P   3 K6 P notch
+ *   4 K2 w = P^4   5 feature P w summed over frames (slot r D + c)
+ *   6 FC1 + bias1 (slots 0 .. H1-1)   7 FC2 + bias2 (slots 0 .. H2-1).
+ * out receives hck_gesture_eval's logits, bit-identical to it.  Taps must
+ * not alias re or im. */
+#define HCK_GESTURE_TAPS 8
+int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *plan,
+                          const hck_ciphertext *re, const hck_ciphertext *im,
+                          const hck_galois_keys *gks, const hck_switch_key *rlk,
+                          hck_ciphertext *out, hck_ciphertext *const *taps);
 
 /* ---- device calibration ---------------------------------------------------
  * Rate of 64-bit Shoup modular products (a w mod q for a fixed w, the product

@@ -88,6 +88,8 @@ SIGNATURES = {
     "hck_vital_eval_many": ([_P, _P, _P, _P, _U32, _P, _P, _P], _I),
     "hck_gesture_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
     "hck_gesture_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
+    "hck_vital_eval_taps": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "hck_gesture_eval_taps": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
     "hck_measure_mulmod_rate": ([_P, _PD], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
@@ -611,6 +613,21 @@ class Context:
         _check(capi.hck_vital_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs))
         return outputs
 
+    VITAL_TAPS = ("K1 p", "K1 energy", "K2 attention", "K4 I", "K4 Q", "K5 If resp",
+                  "K5 Qf resp", "K5 If hr", "K5 Qf hr", "K7 dphi resp", "K7 dphi hr",
+                  "K3 Re X", "K3 Im X", "K1 spectrum power", "K2 sharpened")
+
+    def vital_eval_taps(self, plan: VitalPlan, re, im, gks, rlk):
+        """(outputs, taps): hck_vital_eval's four outputs and the kernels'
+        intermediate ciphertexts, in the order of VITAL_TAPS."""
+        outputs = [self.ciphertext() for _ in range(4)]
+        taps = [self.ciphertext() for _ in self.VITAL_TAPS]
+        outs = (ctypes.c_void_p * 4)(*[c.h for c in outputs])
+        tp = (ctypes.c_void_p * len(taps))(*[c.h for c in taps])
+        _check(capi.hck_vital_eval_taps(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs,
+                                        tp))
+        return outputs, taps
+
     def vital_eval_many(self, plan: VitalPlan, res, ims, gks, rlk, outputs=None):
         """Several windows together; returns one list of 4 outputs per window."""
         n = len(res)
@@ -639,6 +656,19 @@ class Context:
         out = self._out(out)
         _check(capi.hck_gesture_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, out))
         return out
+
+    GESTURE_TAPS = ("K3 d_re", "K3 d_im", "K1 power", "K6 notch", "K2 P^4", "K2 feature",
+                    "FC1", "FC2")
+
+    def gesture_eval_taps(self, plan: GesturePlan, re, im, gks, rlk):
+        """(logits, taps): hck_gesture_eval's output and the stages'
+        intermediate ciphertexts, in the order of GESTURE_TAPS."""
+        out = self.ciphertext()
+        taps = [self.ciphertext() for _ in self.GESTURE_TAPS]
+        tp = (ctypes.c_void_p * len(taps))(*[c.h for c in taps])
+        _check(capi.hck_gesture_eval_taps(self.h, ctypes.addressof(plan), re, im, gks, rlk,
+                                          out, tp))
+        return out, taps
 
     def measure_mulmod_rate(self) -> float:
         """Sustained 64-bit Shoup modular products per second on this device (T/s)."""

@@ -117,7 +117,22 @@ int hck_gesture_required_steps(const hck_context *ctx, const hck_gesture_plan *p
 int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *p, const hck_ciphertext *re,
                      const hck_ciphertext *im, const hck_galois_keys *gks,
                      const hck_switch_key *rlk, hck_ciphertext *out) {
+  return hck_gesture_eval_taps(ctx, p, re, im, gks, rlk, out, nullptr);
+}
+
+int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *p, const hck_ciphertext *re,
+                          const hck_ciphertext *im, const hck_galois_keys *gks,
+                          const hck_switch_key *rlk, hck_ciphertext *out,
+                          hck_ciphertext *const *taps) {
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (taps)
+    for (int i = 0; i < HCK_GESTURE_TAPS; i++)
+      if (taps[i] && (taps[i] == re || taps[i] == im))
+        return set_error(HCK_EINVAL, "taps must not alias inputs");
+  auto tap = [&](int i, const hck_ciphertext *c) {
+    hck_ciphertext *t = taps ? taps[i] : nullptr;
+    return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
+  };
   TRY(check_plan(ctx, p));
   if (re->level != im->level || re->level < 11)
     return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
@@ -138,6 +153,8 @@ int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *p, const hck_ciph
     TRY(hck_rescale(ctx, d[0], d[0]));
     TRY(hck_rescale(ctx, d[1], d[1]));
   }
+  TRY(tap(0, d[0]));
+  TRY(tap(1, d[1]));
   // K1: power, K6: notch
   hck_ciphertext *pw = sc.get(), *t = sc.get(), *u = sc.get();
   TRY(hck_mul(ctx, d[0], d[0], t));
@@ -145,20 +162,26 @@ int hck_gesture_eval(hck_context *ctx, const hck_gesture_plan *p, const hck_ciph
   TRY(hck_add(ctx, t, u, t));
   TRY(hck_relinearize(ctx, t, rlk, pw));
   TRY(hck_rescale(ctx, pw, pw));
+  TRY(tap(2, pw));
   TRY(hck_mul_plain(ctx, pw, p->notch, pw));
   TRY(hck_rescale(ctx, pw, pw));
+  TRY(tap(3, pw));
   // K2: gamma = 4, feature = P w, then the frame sum
   hck_ciphertext *p2 = sc.get(), *p4 = sc.get(), *pl = sc.get(), *feat = sc.get();
   TRY(mul_rs(ctx, pw, pw, rlk, p2, sc));
   TRY(mul_rs(ctx, p2, p2, rlk, p4, sc));
+  TRY(tap(4, p4));
   TRY(hck_drop_level(ctx, pw, p4->level, pl));
   TRY(mul_rs(ctx, pl, p4, rlk, feat, sc));
   TRY(rotsum(ctx, feat, rd, t2, gks, sc));
+  TRY(tap(5, feat));
   // FC network with square activations
   hck_ciphertext *y = sc.get(), *h = sc.get();
   TRY(dense(ctx, p->fc1, p->bias1, feat, gks, y, p->hidden1, rd / p->hidden1, sc));
+  TRY(tap(6, y));
   TRY(mul_rs(ctx, y, y, rlk, h, sc));
   TRY(dense(ctx, p->fc2, p->bias2, h, gks, y, 0, 1, sc));
+  TRY(tap(7, y));
   TRY(mul_rs(ctx, y, y, rlk, h, sc));
   return dense(ctx, p->fc3, p->bias3, h, gks, out, 0, 1, sc);
 }

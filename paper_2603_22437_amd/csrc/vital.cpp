@@ -158,10 +158,12 @@ int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
 
 // The pipeline over n windows at once: every stage advances all windows, so
 // their rotate-and-sum chains and relinearizations share key-switch batches.
+// taps (optional, HCK_VITAL_TAPS per window, entries may be null) receive
+// copies of the kernels' intermediate results.
 static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
                               const hck_ciphertext *const *re, const hck_ciphertext *const *im,
                               uint32_t n, const hck_galois_keys *gks, const hck_switch_key *rlk,
-                              hck_ciphertext *const *out) {
+                              hck_ciphertext *const *out, hck_ciphertext *const *taps) {
   TRY(check_plan(ctx, p));
   const uint32_t depth = p->taylor_order == 3 ? 11 : 9;
   for (uint32_t k = 0; k < n; k++) {
@@ -184,6 +186,10 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     return v;
   };
   auto O = [&](uint32_t k, int i) { return out[4 * k + i]; };
+  auto tap = [&](uint32_t k, int i, const hck_ciphertext *c) {
+    hck_ciphertext *t = taps ? taps[HCK_VITAL_TAPS * k + i] : nullptr;
+    return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
+  };
 
   // K1: p = Re^2 + Im^2 (one batched relinearization), E = sum over frames
   std::vector<hck_ciphertext *> pw = fresh(n), e = fresh(n), t = fresh(n), u = fresh(n);
@@ -195,6 +201,10 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   TRY(relin_rs(ctx, t, rlk, pw));
   for (uint32_t k = 0; k < n; k++) TRY(hck_drop_level(ctx, pw[k], pw[k]->level, e[k]));
   TRY(rotsum(ctx, e, r, t2, gks, sc));
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(tap(k, 0, pw[k]));
+    TRY(tap(k, 1, e[k]));
+  }
   // K2 over bins (gamma = 2) and K4 (P_phi = 2) share their squarings' level
   std::vector<hck_ciphertext *> w = fresh(n), m = fresh(n), ts, outs;
   for (uint32_t k = 0; k < n; k++) {
@@ -205,6 +215,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     outs.insert(outs.end(), {w[k], m[k]});
   }
   TRY(relin_rs(ctx, ts, rlk, outs));
+  for (uint32_t k = 0; k < n; k++) TRY(tap(k, 2, w[k]));
   std::vector<hck_ciphertext *> it = fresh(n), qt = fresh(n);
   ts.clear();
   outs.clear();
@@ -225,6 +236,10 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     for (uint32_t k = 0; k < n; k++) chain.insert(chain.end(), {O(k, 0), O(k, 1), it[k], qt[k]});
     TRY(rotsum(ctx, chain, 1, (uint32_t)r, gks, sc));
   }
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(tap(k, 3, it[k]));
+    TRY(tap(k, 4, qt[k]));
+  }
   // K5: both bands' FIR of I and Q, one BSGS evaluation per window
   std::vector<hck_ciphertext *> f = fresh(4 * n);
   for (uint32_t k = 0; k < n; k++) {
@@ -233,7 +248,10 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     const uint32_t tin[4] = {0, 1, 0, 1}, tout[4] = {0, 1, 2, 3};
     TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, nullptr, 4, gks, &f[4 * k], 4,
                     HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
-    for (int i = 0; i < 4; i++) TRY(hck_rescale(ctx, f[4 * k + i], f[4 * k + i]));
+    for (int i = 0; i < 4; i++) {
+      TRY(hck_rescale(ctx, f[4 * k + i], f[4 * k + i]));
+      TRY(tap(k, 5 + i, f[4 * k + i]));
+    }
   }
   // K7: the previous frame by a rotation of -R; both bands of every window
   // advance together, one batched relinearization per product level
@@ -290,6 +308,10 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(relin_rs(ctx, ts, rlk, outs));
     for (uint32_t j = 0; j < 2 * n; j++) TRY(hck_sub(ctx, av[j], bv[j], dphi[j]));
   }
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(tap(k, 9, dphi[2 * k]));
+    TRY(tap(k, 10, dphi[2 * k + 1]));
+  }
   // K3: copy each dphi into its band's lanes (dphi[2k]: respiration,
   // dphi[2k + 1]: heart rate), weight; the bands' products are added (disjoint
   // lanes) so that one sum over frames serves both
@@ -314,6 +336,10 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(hck_add(ctx, xs[2 * k + 1], hr_im, xs[2 * k + 1]));
   }
   TRY(rotsum(ctx, xs, r, t2, gks, sc));
+  for (uint32_t k = 0; k < n; k++) {
+    TRY(tap(k, 11, xs[2 * k]));
+    TRY(tap(k, 12, xs[2 * k + 1]));
+  }
   // K1 on the spectrum, K2: sharpening and the weighted frequency averages of
   // both lane groups (respiration in slot 0, heart rate in slot `group`)
   std::vector<hck_ciphertext *> pspec = fresh(n), sh = fresh(n);
@@ -326,6 +352,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     ts.push_back(sq_re);
   }
   TRY(relin_rs(ctx, ts, rlk, pspec));
+  for (uint32_t k = 0; k < n; k++) TRY(tap(k, 13, pspec[k]));
   ts.clear();
   for (uint32_t k = 0; k < n; k++) {
     hck_ciphertext *t1 = sc.get();
@@ -333,6 +360,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     ts.push_back(t1);
   }
   TRY(relin_rs(ctx, ts, rlk, sh));
+  for (uint32_t k = 0; k < n; k++) TRY(tap(k, 14, sh[k]));
   std::vector<hck_ciphertext *> chain;
   for (uint32_t k = 0; k < n; k++) {
     TRY(mulpt_rs(ctx, sh[k], p->freq, O(k, 2)));
@@ -342,15 +370,32 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   return rotsum(ctx, chain, 1, lanes.group, gks, sc);
 }
 
+// outputs and taps must not alias an input
+static int check_aliases(const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                         uint32_t n, hck_ciphertext *const *out, uint32_t n_out) {
+  for (uint32_t i = 0; i < n_out; i++)
+    for (uint32_t k = 0; k < n; k++)
+      if (out[i] && (out[i] == re[k] || out[i] == im[k]))
+        return set_error(HCK_EINVAL, "outputs must not alias inputs");
+  return HCK_OK;
+}
+
 extern "C" {
 
 int hck_vital_eval(hck_context *ctx, const hck_vital_plan *p, const hck_ciphertext *re,
                    const hck_ciphertext *im, const hck_galois_keys *gks,
                    const hck_switch_key *rlk, hck_ciphertext *const *out) {
+  return hck_vital_eval_taps(ctx, p, re, im, gks, rlk, out, nullptr);
+}
+
+int hck_vital_eval_taps(hck_context *ctx, const hck_vital_plan *p, const hck_ciphertext *re,
+                        const hck_ciphertext *im, const hck_galois_keys *gks,
+                        const hck_switch_key *rlk, hck_ciphertext *const *out,
+                        hck_ciphertext *const *taps) {
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
-  for (int i = 0; i < 4; i++)
-    if (out[i] == re || out[i] == im) return set_error(HCK_EINVAL, "outputs must not alias inputs");
-  return vital_eval_windows(ctx, p, &re, &im, 1, gks, rlk, out);
+  TRY(check_aliases(&re, &im, 1, out, 4));
+  if (taps) TRY(check_aliases(&re, &im, 1, taps, HCK_VITAL_TAPS));
+  return vital_eval_windows(ctx, p, &re, &im, 1, gks, rlk, out, taps);
 }
 
 int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
@@ -360,11 +405,8 @@ int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
   if (!ctx || !gks || !rlk || (n && (!re || !im || !out)))
     return set_error(HCK_EINVAL, "null argument");
   if (n == 0) return HCK_OK;
-  for (uint32_t i = 0; i < 4 * n; i++)
-    for (uint32_t k = 0; k < n; k++)
-      if (out[i] == re[k] || out[i] == im[k])
-        return set_error(HCK_EINVAL, "outputs must not alias inputs");
-  return vital_eval_windows(ctx, p, re, im, n, gks, rlk, out);
+  TRY(check_aliases(re, im, n, out, 4 * n));
+  return vital_eval_windows(ctx, p, re, im, n, gks, rlk, out, nullptr);
 }
 
 }  // extern "C"

@@ -105,3 +105,31 @@ def encode_plan(ctx, cfg: dict, level0: int, scale0: float, vectors: dict | None
         ops[f"bias{idx}"] = ctx.encode(vec[f"bias{idx}"], s, lvl)
     return GesturePlan.build(cfg["frames"], cfg["bins"], cfg["chirps"],
                              np.asarray(cfg["weights"][0]).shape[0], ops)
+
+
+def plain_stages(cfg: dict, x: np.ndarray, n_slots: int) -> list:
+    """Plaintext execution of the pipeline, the reference of the per-kernel
+    encryption noise (section 5.2, Table 3).  For each tap of
+    hck_gesture_eval_taps, then the logits: (slot indices, values) where the
+    encrypted result holds them."""
+    F, R, D = cfg["frames"], cfg["bins"], cfg["chirps"]
+    if (1 << max(0, (F - 1).bit_length())) * R * D != n_slots:
+        raise ValueError("pow2(frames) x bins x chirps must equal the slot count")
+    dft = _shifted_dft(D, cfg["window"])
+    spec = np.einsum("kn,frn->frk", dft, np.asarray(x))
+    slots = np.arange(F * R * D)
+    power = np.abs(spec) ** 2
+    mask = np.ones(D)
+    mask[list(cfg["notch"])] = 0.0
+    notched = power * mask
+    p4 = notched ** 4
+    feat = (notched * p4).sum(axis=0).reshape(-1)
+    w1, w2, w3 = (np.asarray(w, dtype=np.float64) for w in cfg["weights"])
+    b1, b2, b3 = (np.asarray(b, dtype=np.float64) for b in cfg["biases"])
+    y1 = w1 @ feat + b1
+    y2 = w2 @ y1 ** 2 + b2
+    y3 = w3 @ y2 ** 2 + b3
+    return [(slots, spec.real.reshape(-1)), (slots, spec.imag.reshape(-1)),
+            (slots, power.reshape(-1)), (slots, notched.reshape(-1)), (slots, p4.reshape(-1)),
+            (np.arange(R * D), feat), (np.arange(len(y1)), y1), (np.arange(len(y2)), y2),
+            (np.arange(len(y3)), y3)]

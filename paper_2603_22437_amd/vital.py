@@ -96,3 +96,68 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
         ops[name] = pt(name, lv["freq"])
     return VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"], len(cfg["k_resp"]),
                            len(cfg["k_hr"]), ops)
+
+
+def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
+    """Plaintext execution of the pipeline, the reference of the per-kernel
+    encryption noise (section 5.2, Table 3).  For each tap of
+    hck_vital_eval_taps, then each of the four outputs: (slot indices,
+    values) where the encrypted result holds them."""
+    F, R = cfg["frames"], cfg["bins"]
+    if _next_pow2(F) * R > n_slots or 2 * lane_group(cfg) > R:
+        raise ValueError("window does not fit the slots")
+    G = lane_group(cfg)
+    re, im = np.asarray(z).real, np.asarray(z).imag
+    t = np.arange(F)
+    frame0 = t * R
+    p = re ** 2 + im ** 2
+    e = p.sum(axis=0)
+    w = e ** 2
+    m = p ** 2
+    i_t, q_t = (m * re).sum(axis=1), (m * im).sum(axis=1)
+    out = [(np.arange(F * R), p.reshape(-1)), (np.arange(R), e), (np.arange(R), w),
+           (frame0, i_t), (frame0, q_t)]
+
+    def fir(x, taps):
+        h = len(taps) // 2
+        y = np.zeros(F)
+        for k in range(-h, h + 1):
+            ok = (t + k >= 0) & (t + k < F)
+            y[ok] += taps[k + h] * x[t[ok] + k]
+        return y
+
+    filt = {}
+    for band in ("resp", "hr"):
+        taps = np.asarray(cfg["taps_" + band], dtype=np.float64)
+        filt[band] = (fir(i_t, taps), fir(q_t, taps))
+        out += [(frame0, filt[band][0]), (frame0, filt[band][1])]
+    win = np.asarray(cfg["window"], dtype=np.float64)
+    norm = cfg["dft_gain"] / win.sum()
+    lanes, xr, xi, fq = [], [], [], []
+    dphis = []
+    for band, lane0 in (("resp", 0), ("hr", G)):
+        fi, fq_ = filt[band]
+        fi1, fq1 = np.roll(fi, 1), np.roll(fq_, 1)
+        fi1[0] = fq1[0] = 0.0
+        y = fq_ * fi1 - fi * fq1
+        x = fi * fi1 + fq_ * fq1
+        dphi = y * x ** 2 - y ** 3 / 3.0 if cfg["taylor_order"] == 3 else y
+        dphis.append((frame0, dphi))
+        for j, k in enumerate(cfg["k_" + band]):
+            ang = 2.0 * np.pi * k * t / F
+            lanes.append(lane0 + j)
+            xr.append(norm * np.sum(win * np.cos(ang) * dphi))
+            xi.append(-norm * np.sum(win * np.sin(ang) * dphi))
+            fq.append(60.0 * k * cfg["fps"] / F)
+    out += dphis
+    lanes, xr, xi, fq = (np.asarray(v) for v in (lanes, xr, xi, fq))
+    pw = xr ** 2 + xi ** 2
+    sh = pw ** 2
+    out += [(lanes, xr), (lanes, xi), (lanes, pw), (lanes, sh)]
+    n_resp = len(cfg["k_resp"])
+    two = np.array([0, G])
+    out += [(np.array([0]), np.array([np.sum(np.arange(R) * w) / F ** 2])),
+            (np.array([0]), np.array([np.sum(w) / F ** 2])),
+            (two, np.array([np.sum(fq[:n_resp] * sh[:n_resp]), np.sum(fq[n_resp:] * sh[n_resp:])])),
+            (two, np.array([np.sum(sh[:n_resp]), np.sum(sh[n_resp:])]))]
+    return out

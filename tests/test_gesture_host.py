@@ -68,3 +68,20 @@ def test_oracle_pipeline_decodes_to_plain_circuit():
     classes = cfg["weights"][2].shape[0]
     got = o.decode(o.decrypt(s, out))[:classes].real
     np.testing.assert_allclose(got, OG.plain(cfg, x), rtol=0, atol=1e-6)
+
+
+def test_library_plain_stages_end_in_the_oracle_logits():
+    """The library's plaintext execution (the reference of the per-kernel
+    noise table) ends in the oracle's plaintext logits and places every
+    stage where the packing puts it."""
+    cfg = S.gesture_pipeline_config(frames=30)
+    x = S.gesture_window(2005, cfg["frames"])
+    st = HG.plain_stages(cfg, x, 1 << 15)
+    assert len(st) == 8 + 1
+    np.testing.assert_allclose(st[-1][1], OG.plain(cfg, x), rtol=1e-12, atol=1e-12)
+    # K3's bins of frame t, range r sit at slot (t R + r) D + k
+    t, r, k = 7, 5, 3
+    slots, d_re = st[0]
+    spec = np.fft.fftshift(np.fft.fft(np.asarray(cfg["window"]) * x[t, r]))
+    idx = int(np.flatnonzero(slots == (t * cfg["bins"] + r) * cfg["chirps"] + k)[0])
+    assert abs(d_re[idx] - spec[k].real / np.sum(cfg["window"])) < 1e-12

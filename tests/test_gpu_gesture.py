@@ -94,3 +94,32 @@ def test_gesture_plan_errors():
     low = ctx.encrypt_sk(sk, ctx.encode(np.zeros(ctx.n_slots), prm["scale"], 8), 3)
     with pytest.raises(H.HckError):   # level 8 < depth 11
         ctx.gesture_eval(plan, low, low, gks, rlk)
+
+
+def test_gesture_taps_follow_plaintext_execution():
+    """hck_gesture_eval_taps: the logits are bit-identical to
+    hck_gesture_eval's, and every stage's decoded intermediate stays within
+    the paper's per-kernel encryption-noise bound (MSE < 1e-5, section 5.2)
+    of plaintext execution, at the depth the circuit assigns it."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=30)
+    x = S.gesture_window(2004, cfg["frames"])
+    l0 = len(prm["q"]) - 1
+    plan = HG.encode_plan(ctx, cfg, l0, prm["scale"])
+    gks = ctx.keygen_rotation(sk, ctx.gesture_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: x.size] = x.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 101)
+    out, taps = ctx.gesture_eval_taps(plan, re, im, gks, rlk)
+    ref = ctx.gesture_eval(plan, re, im, gks, rlk)
+    assert np.array_equal(ctx.ciphertext_export(out)[0], ctx.ciphertext_export(ref)[0])
+    depths = [1, 1, 2, 3, 5, 6, 7, 9, 11]
+    for name, c, (slots, want), d in zip(ctx.GESTURE_TAPS + ("FC3",), taps + [out],
+                                         HG.plain_stages(cfg, x, ctx.n_slots), depths):
+        assert l0 - c.level == d, name
+        err = ctx.decode(ctx.decrypt(sk, c)).real[slots] - want
+        assert np.mean(err ** 2) < 1e-5 and np.max(np.abs(err)) < 1e-3, name

@@ -134,3 +134,34 @@ def test_vital_windows_together_match_single_windows():
         alone = ctx.vital_eval(plan, res[k], ims[k], gks, rlk)
         for a, b in zip(alone, together[k]):
             assert np.array_equal(ctx.ciphertext_export(a)[0], ctx.ciphertext_export(b)[0]), k
+
+
+def test_vital_taps_follow_plaintext_execution():
+    """hck_vital_eval_taps: outputs bit-identical to hck_vital_eval's, and
+    every kernel's decoded intermediate within the paper's per-kernel
+    encryption-noise bound (MSE < 1e-5, section 5.2) of plaintext execution,
+    at the depth the circuit assigns it."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1004, cfg["frames"], cfg["bins"])
+    l0 = len(prm["q"]) - 1
+    plan = HV.encode_plan(ctx, cfg, l0)
+    gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: z.size] = z.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 101)
+    outs, taps = ctx.vital_eval_taps(plan, re, im, gks, rlk)
+    ref = ctx.vital_eval(plan, re, im, gks, rlk)
+    for a, b in zip(outs, ref):
+        assert np.array_equal(ctx.ciphertext_export(a)[0], ctx.ciphertext_export(b)[0])
+    depths = [1, 1, 2, 3, 3, 4, 4, 4, 4, 7, 7, 8, 8, 9, 10, 3, 3, 11, 11]
+    names = ctx.VITAL_TAPS + plan.OUTPUTS
+    for name, c, (slots, want), d in zip(names, taps + outs,
+                                         HV.plain_stages(cfg, z, ctx.n_slots), depths):
+        assert l0 - c.level == d, name
+        err = ctx.decode(ctx.decrypt(sk, c)).real[slots] - want
+        assert np.mean(err ** 2) < 1e-5 and np.max(np.abs(err)) < 1e-3, name

@@ -102,3 +102,18 @@ def test_oracle_pipeline_decodes_to_plain_circuit():
         dec = o.decode(o.decrypt(s, out[k])).real
         for slot, v in want[k].items():
             assert abs(dec[slot] - v) < 1e-6 * max(1.0, abs(v)), (k, slot)
+
+
+def test_library_plain_stages_end_in_the_oracle_outputs():
+    """The library's plaintext execution (the reference of the per-kernel
+    noise table) ends in the oracle's plaintext circuit's numbers, slot for
+    slot, and has one entry per tap and output."""
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1001, cfg["frames"], cfg["bins"])
+    st = HV.plain_stages(cfg, z, 1 << 15)
+    assert len(st) == 15 + 4
+    want = OV.plain_slots(cfg, z, 1 << 15)
+    for (slots, vals), name in zip(st[-4:], OV.OUTPUTS):
+        assert sorted(int(s) for s in slots) == sorted(want[name])
+        for s, v in zip(slots, vals):
+            assert abs(v - want[name][int(s)]) <= 1e-12 * max(1.0, abs(v)), name
