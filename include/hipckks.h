@@ -137,6 +137,16 @@ int hck_galois_keys_export(hck_context *ctx, const hck_galois_keys *gks, uint32_
                            uint64_t *out, size_t n_words);
 int hck_galois_keys_count(const hck_galois_keys *gks, uint32_t *n);
 int hck_galois_keys_destroy(hck_galois_keys *gks);
+/* Imports a switching key from the words hck_switch_key_export writes (the
+ * form a client uploads its evaluation keys in; every residue below its
+ * prime, else HCK_EINVAL).  The caller owns the result. */
+int hck_switch_key_import(hck_context *ctx, const uint64_t *words, size_t n_words,
+                          hck_switch_key **out);
+/* An empty Galois key set, filled by hck_galois_keys_insert, which takes
+ * ownership of swk as the key of `element` (odd, < 2N; a key already there is
+ * destroyed). */
+int hck_galois_keys_create(hck_context *ctx, hck_galois_keys **out);
+int hck_galois_keys_insert(hck_galois_keys *gks, uint32_t element, hck_switch_key *swk);
 
 /* ---- plaintexts (section 3.2 "Encoding and Batching") --------------------- */
 
@@ -467,6 +477,79 @@ int hck_encode_coeffs(uint32_t log_n, const double *re, const double *im, double
  * CRT, divided by scale, evaluated at the slot roots.  im may be NULL. */
 int hck_decode_residues(uint32_t log_n, const uint64_t *res, const uint64_t *mods, uint32_t nl,
                         double scale, double *re, double *im);
+
+/* ---- serving runtime ---------------------------------------------------------
+ * Encrypted windows from many tenants (edge clients) evaluated with continuous
+ * batching: the streaming deployment that section 7 names as future work,
+ * with the cloud side of section 3.3 serving several clients at once.
+ *
+ * A server owns one context: after hck_server_create, the caller uses the
+ * context only through the server until hck_server_destroy.  One worker
+ * thread admits requests in arrival order while the HBM budget allows.  A
+ * tenant's evaluation keys are loaded from the caller's host memory when it
+ * has none resident.  To make room, idle tenants are evicted, least recently
+ * used first; a tenant with admitted work is never evicted.  The worker
+ * launches admitted windows, up to max_batch of one pipeline per batch,
+ * whenever fewer than two batches are queued on the device.  So requests
+ * that arrive while others run join the next batch, and windows of different
+ * tenants share key-switch launches, each with its own keys.  Every result
+ * equals, bit for bit, the plain call's (hck_vital_eval / hck_gesture_eval)
+ * on the same window and keys. */
+#define HCK_SERVE_VITAL 1u
+#define HCK_SERVE_GESTURE 2u
+typedef struct hck_server hck_server;
+typedef struct {
+  uint64_t hbm_budget;   /* bytes for resident tenant keys + admitted windows'
+                            input and output ciphertexts */
+  uint32_t max_batch;    /* windows per batch, 1..64 */
+  uint32_t max_inflight; /* windows admitted and not yet completed, 1..256
+                            (also the number of pinned staging slots) */
+} hck_server_config;
+typedef struct {
+  uint64_t request;      /* the caller's id */
+  int32_t status;        /* HCK_OK or the error code of the failure */
+  uint32_t tenant;
+  uint32_t n_out;        /* 4 (vital) or 1 (gesture) */
+  uint32_t batch;        /* windows in the batch the request ran in */
+  uint32_t out_level[4];
+  double out_scale[4];
+  double t_submit, t_admit, t_launch, t_done; /* seconds, host steady clock */
+} hck_server_result;
+typedef struct {
+  uint64_t budget, resident_bytes; /* resident_bytes: keys + admitted windows */
+  uint64_t tenants, submitted, completed, failed, pending;
+  uint64_t batches, windows, key_loads, evictions, key_bytes_loaded;
+} hck_server_stats;
+int hck_server_create(hck_context *ctx, const hck_server_config *cfg, hck_server **out);
+/* Registers tenant `tenant` running pipeline `kind` with `plan` (an
+ * hck_vital_plan or hck_gesture_plan, caller-owned, may be shared by tenants)
+ * and its keys in host memory as hck_switch_key_export writes them: the
+ * Galois key of each of n_steps rotation steps (gk_words[i] for steps[i]) and
+ * the relinearization key.  The host words are read whenever the keys are
+ * loaded: they stay valid and unchanged until the server is destroyed (pinned
+ * memory makes the loads asynchronous).  Errors: HCK_ENOKEY when a step the
+ * pipeline needs has no key; HCK_EINVAL for a tenant id already registered. */
+int hck_server_add_tenant(hck_server *srv, uint32_t tenant, uint32_t kind, const void *plan,
+                          const int32_t *steps, const uint64_t *const *gk_words, uint32_t n_steps,
+                          const uint64_t *rlk_words);
+/* Queues one window of a registered tenant: re and im in interchange form
+ * ([2][level+1][N] each, as hck_ciphertext_export writes; copied, so the
+ * buffers may be reused on return).  When the request completes, its outputs
+ * are written to out_words one after another, each [2][out_level[i]+1][N]
+ * (vital: num_bin, den_bin, num_rates, den_rates; gesture: the logits);
+ * out_capacity (words) must cover them, else the request fails with
+ * HCK_EINVAL.  out_words stays valid until the request's result is polled. */
+int hck_server_submit(hck_server *srv, uint64_t request, uint32_t tenant, const uint64_t *re_words,
+                      const uint64_t *im_words, uint32_t level, double scale, uint64_t *out_words,
+                      size_t out_capacity);
+/* Returns up to cap completed requests in completion order, waiting up to
+ * timeout_ms for the first (returning early once nothing is outstanding). */
+int hck_server_poll(hck_server *srv, uint32_t timeout_ms, hck_server_result *results, uint32_t cap,
+                    uint32_t *n);
+int hck_server_stats_get(hck_server *srv, hck_server_stats *out);
+/* Completes every queued request, frees the tenants' device keys and the
+ * staging memory, and hands the context back to the caller. */
+int hck_server_destroy(hck_server *srv);
 
 #ifdef __cplusplus
 }

@@ -109,6 +109,15 @@ SIGNATURES = {
     "hck_sample_gaussian": ([ctypes.c_char_p, _U64, _P, _SZ], _I),
     "hck_encode_coeffs": ([_U32, _P, _P, _D, _P], _I),
     "hck_decode_residues": ([_U32, _P, _P, _U32, _D, _P, _P], _I),
+    "hck_switch_key_import": ([_P, _P, _SZ, _PP], _I),
+    "hck_galois_keys_create": ([_P, _PP], _I),
+    "hck_galois_keys_insert": ([_P, _U32, _P], _I),
+    "hck_server_create": ([_P, _P, _PP], _I),
+    "hck_server_add_tenant": ([_P, _U32, _U32, _P, _P, _P, _U32, _P], _I),
+    "hck_server_submit": ([_P, _U64, _U32, _P, _P, _U32, _D, _P, _SZ], _I),
+    "hck_server_poll": ([_P, _U32, _P, _U32, _PU32], _I),
+    "hck_server_stats_get": ([_P, _P], _I),
+    "hck_server_destroy": ([_P], _I),
 }
 
 for _name, (_args, _res) in SIGNATURES.items():
@@ -393,6 +402,19 @@ class Context:
         out = np.empty((self.dnum, 2, self.L + self.K, self.n), dtype=np.uint64)
         _check(capi.hck_switch_key_export(self.h, swk, _ptr(out), out.size))
         return out
+
+    def switch_key_import(self, words) -> SwitchKey:
+        w = _u64(words).reshape(-1)
+        return self._new(capi.hck_switch_key_import, _ptr(w), w.size, cls=SwitchKey)
+
+    def galois_keys_from_words(self, keys: dict) -> GaloisKeys:
+        """A Galois key set from exported words: {element: words}."""
+        gks = self._new(capi.hck_galois_keys_create, cls=GaloisKeys)
+        for g, words in keys.items():
+            swk = self.switch_key_import(words)
+            _check(capi.hck_galois_keys_insert(gks.h, int(g), swk.h))
+            swk.h = None    # owned by the set now
+        return gks
 
     def keygen_galois(self, sk, elements, seed: int) -> GaloisKeys:
         e = np.ascontiguousarray(np.asarray(elements, dtype=np.uint32))
@@ -695,3 +717,101 @@ class Context:
         buf = ctypes.create_string_buffer(4096)
         _check(capi.hck_timing_names(self.h, buf, 4096))
         return [x for x in buf.value.decode().split(",") if x]
+
+
+# --- serving runtime -----------------------------------------------------
+
+SERVE_VITAL, SERVE_GESTURE = 1, 2
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", _U64), ("max_batch", _U32), ("max_inflight", _U32)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("request", _U64), ("status", _I32), ("tenant", _U32), ("n_out", _U32),
+                ("batch", _U32), ("out_level", _U32 * 4), ("out_scale", _D * 4),
+                ("t_submit", _D), ("t_admit", _D), ("t_launch", _D), ("t_done", _D)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, _U64) for name in (
+        "budget", "resident_bytes", "tenants", "submitted", "completed", "failed", "pending",
+        "batches", "windows", "key_loads", "evictions", "key_bytes_loaded")]
+
+
+class Server:
+    """hck_server: continuous batching of encrypted windows from many tenants.
+    While it exists, the context belongs to its worker thread: use only the
+    server's methods until close()."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_batch: int = 8,
+                 max_inflight: int = 16):
+        self.ctx = ctx
+        cfg = ServerConfig(hbm_budget, max_batch, max_inflight)
+        h = ctypes.c_void_p()
+        _check(capi.hck_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h.value
+        self._keep = {}         # tenants' plans and key words
+        self._out = {}          # request -> output buffer
+
+    def add_tenant(self, tenant: int, kind: int, plan, steps, gk_words, rlk_words):
+        """gk_words[i]: exported words of the key of steps[i] (kept alive, and
+        read again whenever the tenant's keys are loaded)."""
+        st = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+        gk = [w if isinstance(w, np.ndarray) else np.asarray(w) for w in gk_words]
+        for w in gk + [rlk_words]:
+            if w.dtype != np.uint64 or not w.flags["C_CONTIGUOUS"]:
+                raise ValueError("key words must be C-contiguous uint64 arrays")
+        ptrs = (ctypes.c_void_p * max(1, len(gk)))(*[w.ctypes.data for w in gk])
+        _check(capi.hck_server_add_tenant(self.h, tenant, kind, ctypes.addressof(plan),
+                                          _ptr(st), ptrs, len(gk), rlk_words.ctypes.data))
+        self._keep[tenant] = (kind, plan, st, gk, rlk_words, ptrs)
+
+    def submit(self, request: int, tenant: int, re_words, im_words, level: int, scale: float):
+        re = _u64(re_words)
+        im = _u64(im_words)
+        n_out = 1 if self._keep.get(tenant, (SERVE_VITAL,))[0] == SERVE_GESTURE else 4
+        out = np.empty(n_out * 2 * self.ctx.L * self.ctx.n, dtype=np.uint64)
+        self._out[request] = out
+        _check(capi.hck_server_submit(self.h, request, tenant, _ptr(re), _ptr(im), level, scale,
+                                      _ptr(out), out.size))
+
+    def poll(self, timeout_ms: int = 0, cap: int = 64) -> list:
+        """Completed requests: dicts with the result record and 'outputs', the
+        output ciphertexts' words ([2][level+1][N] each)."""
+        buf = (ServerResult * cap)()
+        n = ctypes.c_uint32()
+        _check(capi.hck_server_poll(self.h, timeout_ms, buf, cap, ctypes.byref(n)))
+        done = []
+        for r in buf[: n.value]:
+            words = self._out.pop(r.request)
+            outs, off = [], 0
+            if r.status == 0:
+                for i in range(r.n_out):
+                    size = 2 * (r.out_level[i] + 1) * self.ctx.n
+                    outs.append(words[off: off + size].reshape(2, r.out_level[i] + 1,
+                                                               self.ctx.n).copy())
+                    off += size
+            done.append({"request": r.request, "status": r.status, "tenant": r.tenant,
+                         "batch": r.batch, "levels": list(r.out_level[: r.n_out]),
+                         "scales": list(r.out_scale[: r.n_out]), "t_submit": r.t_submit,
+                         "t_admit": r.t_admit, "t_launch": r.t_launch, "t_done": r.t_done,
+                         "outputs": outs})
+        return done
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(capi.hck_server_stats_get(self.h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.h:
+            capi.hck_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

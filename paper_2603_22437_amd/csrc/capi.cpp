@@ -234,6 +234,91 @@ int lt_alloc_ct(hck_context *ctx, hck_ciphertext **ct) {
 
 }  // namespace
 
+namespace hck {
+
+int key_rows_to_internal(hck_context *ctx, uint64_t *buf) {
+  const uint32_t nm = ctx->L + ctx->K;
+  const auto rows = poly_rows(2 * ctx->dnum, nm, nm, 0);
+  TRY(ntt_forward_rows(ctx, buf, rows));
+  return mont_rows(ctx, buf, rows, true);
+}
+
+int ct_from_host_async(hck_context *ctx, hck_ciphertext *ct, const uint64_t *host,
+                       uint32_t polys, uint32_t level, double scale) {
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  TRY(ensure_ct(ctx, ct, polys));
+  const size_t n = ctx->n, rows = level + 1;
+  for (uint32_t p = 0; p < polys; p++)
+    HCK_HIP(ctx, hipMemcpyAsync(ct->data + (size_t)p * ctx->L * n, host + p * rows * n,
+                                rows * n * 8, hipMemcpyHostToDevice, ctx->stream));
+  TRY(ntt_forward_rows(ctx, ct->data, poly_rows(polys, ctx->L, level + 1)));
+  ct->size = polys;
+  ct->level = level;
+  ct->scale = scale;
+  return HCK_OK;
+}
+
+int ct_to_host_async(hck_context *ctx, const hck_ciphertext *ct, uint64_t *host) {
+  const size_t n = ctx->n, rows = ct->level + 1, words = (size_t)ct->size * rows * n;
+  uint64_t *tmp = nullptr;
+  TRY(dev_alloc(ctx, &tmp, words));
+  int rc = HCK_OK;
+  for (uint32_t p = 0; p < ct->size && !rc; p++)
+    rc = launch_copy(ctx, tmp + p * rows * n, ct->data + (size_t)p * ctx->L * n, rows * n);
+  if (!rc) rc = inverse_rows(ctx, tmp, poly_rows(ct->size, ct->level + 1, ct->level + 1));
+  if (!rc) {
+    hipError_t e = hipMemcpyAsync(host, tmp, words * 8, hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) rc = check_hip(ctx, e, "device-to-host copy");
+  }
+  dev_free(ctx, tmp);
+  return rc;
+}
+
+int relinearize_keys(hck_context *ctx, const hck_ciphertext *const *a,
+                     const hck_switch_key *const *rlk, uint32_t n, hck_ciphertext *const *out) {
+  if (n == 0) return HCK_OK;
+  for (uint32_t i = 0; i < n; i++) {
+    if (!a[i] || !out[i] || !rlk[i]) return set_error(HCK_EINVAL, "null ciphertext or key");
+    if (a[i]->size != 3) return set_error(HCK_EINVAL, "relinearization needs a 3-part ciphertext");
+    if (a[i]->level != a[0]->level) return set_error(HCK_ELEVEL, "batched inputs need one level");
+    for (uint32_t k = 0; k < n; k++)
+      if ((k < i && out[k] == out[i]) || (k != i && out[k] == a[i]))
+        return set_error(HCK_EINVAL, "outputs must be distinct and alias only their own input");
+  }
+  const uint32_t level = a[0]->level;
+  const size_t ps = poly_stride(ctx);
+  const uint32_t limit = ks_batch_limit(ctx, level);
+  for (uint32_t s0 = 0; s0 < n; s0 += limit) {
+    KsBatch kb;
+    kb.n = std::min<uint32_t>(limit, n - s0);
+    std::vector<double> scales(kb.n);
+    for (uint32_t b = 0; b < kb.n; b++) {
+      const hck_ciphertext *x = a[s0 + b];
+      hck_ciphertext *y = out[s0 + b];
+      scales[b] = x->scale;
+      TRY(ensure_ct(ctx, y, 2));
+      // (d0, d1) + KeySwitch(d2): d2 is read before the final launch writes
+      // the outputs, and the addends are read at the positions written
+      kb.key[b] = rlk[s0 + b]->data;
+      kb.galois[b] = 1;
+      kb.d[b] = x->data + 2 * ps;
+      kb.out0[b] = y->data;
+      kb.out1[b] = y->data + ps;
+      kb.add0[b] = x->data;
+      kb.add1[b] = x->data + ps;
+    }
+    TRY(keyswitch_batch(ctx, kb, level));
+    for (uint32_t b = 0; b < kb.n; b++) {
+      out[s0 + b]->size = 2;
+      out[s0 + b]->level = level;
+      out[s0 + b]->scale = scales[b];
+    }
+  }
+  return HCK_OK;
+}
+
+}  // namespace hck
+
 extern "C" {
 
 /* ---- keys -------------------------------------------------------------------- */
@@ -363,6 +448,50 @@ int hck_switch_key_destroy(hck_switch_key *swk) {
     dev_free(swk->ctx, swk->data);
     delete swk;
   }
+  return HCK_OK;
+}
+
+int hck_switch_key_import(hck_context *ctx, const uint64_t *words, size_t n_words,
+                          hck_switch_key **out) {
+  ENTER(ctx);
+  if (!words || !out) return set_error(HCK_EINVAL, "null argument");
+  const uint32_t nm = ctx->L + ctx->K;
+  const size_t total = (size_t)ctx->dnum * 2 * nm * ctx->n;
+  if (n_words != total) return set_error(HCK_EINVAL, "size mismatch");
+  for (size_t r = 0; r < (size_t)ctx->dnum * 2 * nm; r++) {
+    const uint64_t q = ctx->mods[r % nm];
+    for (size_t c = 0; c < ctx->n; c++)
+      if (words[r * ctx->n + c] >= q) return set_error(HCK_EINVAL, "residue not below its prime");
+  }
+  hck_switch_key *key = new hck_switch_key();
+  key->ctx = ctx;
+  int rc = dev_alloc(ctx, &key->data, total);
+  if (!rc) rc = upload(ctx, key->data, words, total * 8);
+  if (!rc) rc = key_rows_to_internal(ctx, key->data);
+  if (rc) {
+    hck_switch_key_destroy(key);
+    return rc;
+  }
+  *out = key;
+  return HCK_OK;
+}
+
+int hck_galois_keys_create(hck_context *ctx, hck_galois_keys **out) {
+  if (!ctx || !out) return set_error(HCK_EINVAL, "null argument");
+  hck_galois_keys *gks = new hck_galois_keys();
+  gks->ctx = ctx;
+  *out = gks;
+  return HCK_OK;
+}
+
+int hck_galois_keys_insert(hck_galois_keys *gks, uint32_t element, hck_switch_key *swk) {
+  if (!gks || !swk) return set_error(HCK_EINVAL, "null argument");
+  if ((element & 1) == 0 || element >= 2 * gks->ctx->n)
+    return set_error(HCK_EINVAL, "Galois element must be odd and below 2N");
+  if (swk->ctx != gks->ctx) return set_error(HCK_EINVAL, "key of another context");
+  auto it = gks->keys.find(element);
+  if (it != gks->keys.end()) hck_switch_key_destroy(it->second);
+  gks->keys[element] = swk;
   return HCK_OK;
 }
 
@@ -802,45 +931,8 @@ int hck_relinearize_many(hck_context *ctx, const hck_ciphertext *const *a, uint3
                          const hck_switch_key *rlk, hck_ciphertext *const *out) {
   ENTER(ctx);
   if ((n && (!a || !out)) || !rlk) return set_error(HCK_EINVAL, "null argument");
-  if (n == 0) return HCK_OK;
-  for (uint32_t i = 0; i < n; i++) {
-    if (!a[i] || !out[i]) return set_error(HCK_EINVAL, "null ciphertext");
-    if (a[i]->size != 3) return set_error(HCK_EINVAL, "relinearization needs a 3-part ciphertext");
-    if (a[i]->level != a[0]->level) return set_error(HCK_ELEVEL, "batched inputs need one level");
-    for (uint32_t k = 0; k < n; k++)
-      if ((k < i && out[k] == out[i]) || (k != i && out[k] == a[i]))
-        return set_error(HCK_EINVAL, "outputs must be distinct and alias only their own input");
-  }
-  const uint32_t level = a[0]->level;
-  const size_t ps = poly_stride(ctx);
-  const uint32_t limit = ks_batch_limit(ctx, level);
-  for (uint32_t s0 = 0; s0 < n; s0 += limit) {
-    KsBatch kb;
-    kb.n = std::min<uint32_t>(limit, n - s0);
-    std::vector<double> scales(kb.n);
-    for (uint32_t b = 0; b < kb.n; b++) {
-      const hck_ciphertext *x = a[s0 + b];
-      hck_ciphertext *y = out[s0 + b];
-      scales[b] = x->scale;
-      TRY(ensure_ct(ctx, y, 2));
-      // (d0, d1) + KeySwitch(d2): d2 is read before the final launch writes
-      // the outputs, and the addends are read at the positions written
-      kb.key[b] = rlk->data;
-      kb.galois[b] = 1;
-      kb.d[b] = x->data + 2 * ps;
-      kb.out0[b] = y->data;
-      kb.out1[b] = y->data + ps;
-      kb.add0[b] = x->data;
-      kb.add1[b] = x->data + ps;
-    }
-    TRY(keyswitch_batch(ctx, kb, level));
-    for (uint32_t b = 0; b < kb.n; b++) {
-      out[s0 + b]->size = 2;
-      out[s0 + b]->level = level;
-      out[s0 + b]->scale = scales[b];
-    }
-  }
-  return HCK_OK;
+  std::vector<const hck_switch_key *> keys(n, rlk);
+  return relinearize_keys(ctx, a, keys.data(), n, out);
 }
 
 int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out) {

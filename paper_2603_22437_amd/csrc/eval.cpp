@@ -51,14 +51,22 @@ int ntt_forward_rows(hck_context *ctx, uint64_t *buf,
 
 int apply_galois_multi(hck_context *ctx, const hck_ciphertext *const *a, const uint32_t *g,
                        uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
-  if (n == 0) return HCK_OK;
   std::vector<const hck_switch_key *> keys(n);
-  const uint32_t level = a[0]->level;
   for (uint32_t i = 0; i < n; i++) {
     auto it = gks->keys.find(g[i]);
     if (it == gks->keys.end())
       return set_error(HCK_ENOKEY, "no Galois key for element " + std::to_string(g[i]));
     keys[i] = it->second;
+  }
+  return apply_galois_keys(ctx, a, g, keys.data(), n, out);
+}
+
+int apply_galois_keys(hck_context *ctx, const hck_ciphertext *const *a, const uint32_t *g,
+                      const hck_switch_key *const *keys, uint32_t n,
+                      hck_ciphertext *const *out) {
+  if (n == 0) return HCK_OK;
+  const uint32_t level = a[0]->level;
+  for (uint32_t i = 0; i < n; i++) {
     if (a[i]->size != 2) return set_error(HCK_EINVAL, "rotation needs a 2-part ciphertext");
     if (a[i]->level != level) return set_error(HCK_ELEVEL, "batched rotations need one level");
     for (uint32_t k = 0; k < n; k++) {

@@ -339,6 +339,33 @@ int launch_lt_sums(hck_context *ctx, const LtSumArgs &a, uint32_t level);
 // distinct and out[i] may alias a[i] (no other input)
 int apply_galois_multi(hck_context *ctx, const hck_ciphertext *const *a, const uint32_t *g,
                        uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out);
+// the same with the switch keys given, one per ciphertext (they may differ in
+// owner: batches across tenants)
+int apply_galois_keys(hck_context *ctx, const hck_ciphertext *const *a, const uint32_t *g,
+                      const hck_switch_key *const *keys, uint32_t n,
+                      hck_ciphertext *const *out);
+// relinearizations of n 3-part ciphertexts (one level), each with its own
+// key, key-switched together; outputs distinct, out[i] may alias a[i]
+int relinearize_keys(hck_context *ctx, const hck_ciphertext *const *a,
+                     const hck_switch_key *const *rlk, uint32_t n, hck_ciphertext *const *out);
+// switch-key rows in interchange form ([2 dnum][L+K][N] coefficient domain)
+// -> evaluation + Montgomery form, in place, on the context stream
+int key_rows_to_internal(hck_context *ctx, uint64_t *buf);
+// interchange-form ciphertext words in host memory ([polys][level+1][N]) ->
+// ct, stream-ordered with no synchronization (host memory pinned for a truly
+// asynchronous copy; it must stay valid until the stream reaches the copy)
+int ct_from_host_async(hck_context *ctx, hck_ciphertext *ct, const uint64_t *host,
+                       uint32_t polys, uint32_t level, double scale);
+// ct -> interchange form in host memory (as hck_ciphertext_export writes it),
+// stream-ordered with no synchronization
+int ct_to_host_async(hck_context *ctx, const hck_ciphertext *ct, uint64_t *host);
+// the vital-sign pipeline (hck_vital_eval) over n windows evaluated
+// together, window k with its own keys gks[k], rlk[k] (windows of different
+// tenants share key-switch batches); out: 4 per window, not aliasing inputs
+int vital_eval_batch(hck_context *ctx, const hck_vital_plan *p, const hck_ciphertext *const *re,
+                     const hck_ciphertext *const *im, uint32_t n,
+                     const hck_galois_keys *const *gks, const hck_switch_key *const *rlk,
+                     hck_ciphertext *const *out);
 // the same with one Galois element for all
 int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *const *out);

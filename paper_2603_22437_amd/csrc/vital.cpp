@@ -2,7 +2,7 @@
 // K1 -> K2 -> K4 -> K5 -> K7 -> K3 -> K1 -> K2) composed from the library's
 // evaluation calls.  Every rotate-and-sum chain advances all its independent
 // members (num/den, I/Q, real/imaginary parts) by one step per
-// batched key switch (hck_rotate_many), so one window issues as few key-switch
+// batched key switch, so one window issues as few key-switch
 // launch sequences as its dependency depth allows.
 #include <algorithm>
 #include <vector>
@@ -88,44 +88,60 @@ std::vector<int32_t> plan_steps(const hck_vital_plan *p) {
   return s;
 }
 
+// Window k of a batch rotates with gks[k] and relinearizes with rlk[k] (the
+// windows may belong to different tenants).  A batch's members are listed
+// with the window each belongs to.
+struct WindowKeys {
+  const hck_galois_keys *const *gks;
+  const hck_switch_key *const *rlk;
+};
+
+// member i belongs to window i / per
+std::vector<uint32_t> owners(size_t members, uint32_t per) {
+  std::vector<uint32_t> w(members);
+  for (size_t i = 0; i < members; i++) w[i] = (uint32_t)(i / per);
+  return w;
+}
+
+// dst[i] = Rot(src[i], step), every member with its window's key, key-switched
+// together
+int rotate_members(hck_context *ctx, const std::vector<hck_ciphertext *> &src,
+                   const std::vector<uint32_t> &win, int32_t step, const WindowKeys &wk,
+                   const std::vector<hck_ciphertext *> &dst) {
+  const uint32_t g = galois_of_step(ctx, step);
+  std::vector<uint32_t> gs(src.size(), g);
+  std::vector<const hck_switch_key *> keys(src.size());
+  for (size_t i = 0; i < src.size(); i++) {
+    auto it = wk.gks[win[i]]->keys.find(g);
+    if (it == wk.gks[win[i]]->keys.end())
+      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(step));
+    keys[i] = it->second;
+  }
+  return apply_galois_keys(ctx, src.data(), gs.data(), keys.data(), (uint32_t)src.size(),
+                           dst.data());
+}
+
 // c_i <- c_i + Rot(c_i, step) + ... over `count` (a power of two) shifts, for
 // every member at once
-int rotsum(hck_context *ctx, std::vector<hck_ciphertext *> cs, int32_t step, uint32_t count,
-           const hck_galois_keys *gks, Scratch &sc) {
+int rotsum(hck_context *ctx, const std::vector<hck_ciphertext *> &cs,
+           const std::vector<uint32_t> &win, int32_t step, uint32_t count, const WindowKeys &wk,
+           Scratch &sc) {
   std::vector<hck_ciphertext *> tmp;
   for (size_t i = 0; i < cs.size(); i++) tmp.push_back(sc.get());
   for (uint64_t s = (uint64_t)step; s < (uint64_t)step * count; s *= 2) {
-    TRY(hck_rotate_many(ctx, cs.data(), (uint32_t)cs.size(), (int32_t)s, gks, tmp.data()));
+    TRY(rotate_members(ctx, cs, win, (int32_t)s, wk, tmp));
     for (size_t i = 0; i < cs.size(); i++) TRY(hck_add(ctx, cs[i], tmp[i], cs[i]));
   }
   return HCK_OK;
 }
 
-// out = relin(a b) rescaled
-int mul_rs(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
-           const hck_switch_key *rlk, hck_ciphertext *out, Scratch &sc) {
-  hck_ciphertext *t = sc.get();
-  TRY(hck_mul(ctx, a, b, t));
-  TRY(hck_relinearize(ctx, t, rlk, out));
-  return hck_rescale(ctx, out, out);
-}
-
-// out = relin(a b + c d) (op 0) or relin(a b - c d) (op 1), rescaled
-int mul2_rs(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
-            const hck_ciphertext *c, const hck_ciphertext *d, int op, const hck_switch_key *rlk,
-            hck_ciphertext *out, Scratch &sc) {
-  hck_ciphertext *t = sc.get(), *u = sc.get();
-  TRY(hck_mul(ctx, a, b, t));
-  TRY(hck_mul(ctx, c, d, u));
-  TRY(op ? hck_sub(ctx, t, u, t) : hck_add(ctx, t, u, t));
-  TRY(hck_relinearize(ctx, t, rlk, out));
-  return hck_rescale(ctx, out, out);
-}
-
 // outs[i] = relin(ts[i]) rescaled, the relinearizations key-switched together
-int relin_rs(hck_context *ctx, std::vector<hck_ciphertext *> ts, const hck_switch_key *rlk,
-             std::vector<hck_ciphertext *> outs) {
-  TRY(hck_relinearize_many(ctx, ts.data(), (uint32_t)ts.size(), rlk, outs.data()));
+int relin_rs(hck_context *ctx, const std::vector<hck_ciphertext *> &ts,
+             const std::vector<uint32_t> &win, const WindowKeys &wk,
+             const std::vector<hck_ciphertext *> &outs) {
+  std::vector<const hck_switch_key *> keys(ts.size());
+  for (size_t i = 0; i < ts.size(); i++) keys[i] = wk.rlk[win[i]];
+  TRY(relinearize_keys(ctx, ts.data(), keys.data(), (uint32_t)ts.size(), outs.data()));
   for (hck_ciphertext *o : outs) TRY(hck_rescale(ctx, o, o));
   return HCK_OK;
 }
@@ -162,21 +178,25 @@ int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
 // copies of the kernels' intermediate results.
 static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
                               const hck_ciphertext *const *re, const hck_ciphertext *const *im,
-                              uint32_t n, const hck_galois_keys *gks, const hck_switch_key *rlk,
-                              hck_ciphertext *const *out, hck_ciphertext *const *taps) {
+                              uint32_t n, const WindowKeys &wk, hck_ciphertext *const *out,
+                              hck_ciphertext *const *taps) {
   TRY(check_plan(ctx, p));
   const uint32_t depth = p->taylor_order == 3 ? 11 : 9;
   for (uint32_t k = 0; k < n; k++) {
     if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
+    if (!wk.gks[k] || !wk.rlk[k]) return set_error(HCK_EINVAL, "null key");
     if (re[k]->level != re[0]->level || im[k]->level != re[0]->level || re[0]->level < depth)
       return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
     for (int i = 0; i < 4; i++)
       if (!out[4 * k + i]) return set_error(HCK_EINVAL, "null output");
   }
   for (int32_t s : plan_steps(p))
-    if (!gks->keys.count(galois_of_step(ctx, s)))
-      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
+    for (uint32_t k = 0; k < n; k++)
+      if (!wk.gks[k]->keys.count(galois_of_step(ctx, s)))
+        return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
   Scratch sc(ctx);
+  const std::vector<uint32_t> one = owners(n, 1), two = owners(2 * n, 2),
+                              four = owners(4 * n, 4);
   const int32_t r = (int32_t)p->bins;
   const uint32_t t2 = pow2_at_least(p->frames);
   const Lanes lanes = lanes_of(p);
@@ -198,9 +218,9 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(hck_mul(ctx, im[k], im[k], u[k]));
     TRY(hck_add(ctx, t[k], u[k], t[k]));
   }
-  TRY(relin_rs(ctx, t, rlk, pw));
+  TRY(relin_rs(ctx, t, one, wk, pw));
   for (uint32_t k = 0; k < n; k++) TRY(hck_drop_level(ctx, pw[k], pw[k]->level, e[k]));
-  TRY(rotsum(ctx, e, r, t2, gks, sc));
+  TRY(rotsum(ctx, e, one, r, t2, wk, sc));
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 0, pw[k]));
     TRY(tap(k, 1, e[k]));
@@ -214,7 +234,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     ts.insert(ts.end(), {tw, tm});
     outs.insert(outs.end(), {w[k], m[k]});
   }
-  TRY(relin_rs(ctx, ts, rlk, outs));
+  TRY(relin_rs(ctx, ts, two, wk, outs));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 2, w[k]));
   std::vector<hck_ciphertext *> it = fresh(n), qt = fresh(n);
   ts.clear();
@@ -230,11 +250,11 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     ts.insert(ts.end(), {ti, tq});
     outs.insert(outs.end(), {it[k], qt[k]});
   }
-  TRY(relin_rs(ctx, ts, rlk, outs));
+  TRY(relin_rs(ctx, ts, two, wk, outs));
   {
     std::vector<hck_ciphertext *> chain;
     for (uint32_t k = 0; k < n; k++) chain.insert(chain.end(), {O(k, 0), O(k, 1), it[k], qt[k]});
-    TRY(rotsum(ctx, chain, 1, (uint32_t)r, gks, sc));
+    TRY(rotsum(ctx, chain, four, 1, (uint32_t)r, wk, sc));
   }
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 3, it[k]));
@@ -246,7 +266,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     const hck_ciphertext *ins[2] = {it[k], qt[k]};
     const hck_linear_transform *lts[4] = {p->fir_resp, p->fir_resp, p->fir_hr, p->fir_hr};
     const uint32_t tin[4] = {0, 1, 0, 1}, tout[4] = {0, 1, 2, 3};
-    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, nullptr, 4, gks, &f[4 * k], 4,
+    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, nullptr, 4, wk.gks[k], &f[4 * k], 4,
                     HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
     for (int i = 0; i < 4; i++) {
       TRY(hck_rescale(ctx, f[4 * k + i], f[4 * k + i]));
@@ -256,7 +276,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   // K7: the previous frame by a rotation of -R; both bands of every window
   // advance together, one batched relinearization per product level
   std::vector<hck_ciphertext *> f1 = fresh(4 * n);
-  TRY(hck_rotate_many(ctx, f.data(), 4 * n, -r, gks, f1.data()));
+  TRY(rotate_members(ctx, f, four, -r, wk, f1));
   std::vector<hck_ciphertext *> dphi = fresh(2 * n), y = fresh(2 * n), x = fresh(2 * n);
   ts.clear();
   outs.clear();
@@ -277,7 +297,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
       outs.push_back(x[j]);
     }
   }
-  TRY(relin_rs(ctx, ts, rlk, outs));
+  TRY(relin_rs(ctx, ts, owners(ts.size(), (uint32_t)(ts.size() / n)), wk, outs));
   if (p->taylor_order == 1) {
     for (uint32_t j = 0; j < 2 * n; j++) TRY(hck_drop_level(ctx, y[j], y[j]->level, dphi[j]));
   } else {
@@ -292,7 +312,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
       ts.insert(ts.end(), {t1, t2});
       outs.insert(outs.end(), {x2[j], y2[j]});
     }
-    TRY(relin_rs(ctx, ts, rlk, outs));
+    TRY(relin_rs(ctx, ts, owners(ts.size(), (uint32_t)(ts.size() / n)), wk, outs));
     std::vector<hck_ciphertext *> av = fresh(2 * n), bv = fresh(2 * n);
     ts.clear();
     outs.clear();
@@ -305,7 +325,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
       ts.insert(ts.end(), {t1, t2});
       outs.insert(outs.end(), {av[j], bv[j]});
     }
-    TRY(relin_rs(ctx, ts, rlk, outs));
+    TRY(relin_rs(ctx, ts, owners(ts.size(), (uint32_t)(ts.size() / n)), wk, outs));
     for (uint32_t j = 0; j < 2 * n; j++) TRY(hck_sub(ctx, av[j], bv[j], dphi[j]));
   }
   for (uint32_t k = 0; k < n; k++) {
@@ -317,12 +337,17 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   // lanes) so that one sum over frames serves both
   for (uint32_t s = 1; s < lanes.copies_hr; s *= 2) {
     std::vector<hck_ciphertext *> src;
+    std::vector<uint32_t> win;
     for (uint32_t k = 0; k < n; k++) {
       src.push_back(dphi[2 * k + 1]);
-      if (s < lanes.copies_resp) src.push_back(dphi[2 * k]);
+      win.push_back(k);
+      if (s < lanes.copies_resp) {
+        src.push_back(dphi[2 * k]);
+        win.push_back(k);
+      }
     }
     std::vector<hck_ciphertext *> tmp = fresh((uint32_t)src.size());
-    TRY(hck_rotate_many(ctx, src.data(), (uint32_t)src.size(), -(int32_t)s, gks, tmp.data()));
+    TRY(rotate_members(ctx, src, win, -(int32_t)s, wk, tmp));
     for (size_t i = 0; i < src.size(); i++) TRY(hck_add(ctx, src[i], tmp[i], src[i]));
   }
   std::vector<hck_ciphertext *> xs = fresh(2 * n);
@@ -335,7 +360,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(mulpt_rs(ctx, dphi[2 * k + 1], p->dft_im_hr, hr_im));
     TRY(hck_add(ctx, xs[2 * k + 1], hr_im, xs[2 * k + 1]));
   }
-  TRY(rotsum(ctx, xs, r, t2, gks, sc));
+  TRY(rotsum(ctx, xs, two, r, t2, wk, sc));
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 11, xs[2 * k]));
     TRY(tap(k, 12, xs[2 * k + 1]));
@@ -351,7 +376,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(hck_add(ctx, sq_re, sq_im, sq_re));
     ts.push_back(sq_re);
   }
-  TRY(relin_rs(ctx, ts, rlk, pspec));
+  TRY(relin_rs(ctx, ts, one, wk, pspec));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 13, pspec[k]));
   ts.clear();
   for (uint32_t k = 0; k < n; k++) {
@@ -359,7 +384,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(hck_mul(ctx, pspec[k], pspec[k], t1));
     ts.push_back(t1);
   }
-  TRY(relin_rs(ctx, ts, rlk, sh));
+  TRY(relin_rs(ctx, ts, one, wk, sh));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 14, sh[k]));
   std::vector<hck_ciphertext *> chain;
   for (uint32_t k = 0; k < n; k++) {
@@ -367,8 +392,20 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(mulpt_rs(ctx, sh[k], p->mask, O(k, 3)));
     chain.insert(chain.end(), {O(k, 2), O(k, 3)});
   }
-  return rotsum(ctx, chain, 1, lanes.group, gks, sc);
+  return rotsum(ctx, chain, two, 1, lanes.group, wk, sc);
 }
+
+namespace hck {
+
+int vital_eval_batch(hck_context *ctx, const hck_vital_plan *p, const hck_ciphertext *const *re,
+                     const hck_ciphertext *const *im, uint32_t n,
+                     const hck_galois_keys *const *gks, const hck_switch_key *const *rlk,
+                     hck_ciphertext *const *out) {
+  if (n == 0) return HCK_OK;
+  return vital_eval_windows(ctx, p, re, im, n, WindowKeys{gks, rlk}, out, nullptr);
+}
+
+}  // namespace hck
 
 // outputs and taps must not alias an input
 static int check_aliases(const hck_ciphertext *const *re, const hck_ciphertext *const *im,
@@ -395,7 +432,7 @@ int hck_vital_eval_taps(hck_context *ctx, const hck_vital_plan *p, const hck_cip
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
   TRY(check_aliases(&re, &im, 1, out, 4));
   if (taps) TRY(check_aliases(&re, &im, 1, taps, HCK_VITAL_TAPS));
-  return vital_eval_windows(ctx, p, &re, &im, 1, gks, rlk, out, taps);
+  return vital_eval_windows(ctx, p, &re, &im, 1, WindowKeys{&gks, &rlk}, out, taps);
 }
 
 int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
@@ -406,7 +443,9 @@ int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
     return set_error(HCK_EINVAL, "null argument");
   if (n == 0) return HCK_OK;
   TRY(check_aliases(re, im, n, out, 4 * n));
-  return vital_eval_windows(ctx, p, re, im, n, gks, rlk, out, nullptr);
+  std::vector<const hck_galois_keys *> g(n, gks);
+  std::vector<const hck_switch_key *> rl(n, rlk);
+  return vital_eval_windows(ctx, p, re, im, n, WindowKeys{g.data(), rl.data()}, out, nullptr);
 }
 
 }  // extern "C"
