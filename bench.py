@@ -80,6 +80,10 @@ def main():
                     help="skip the vital-sign pipeline latency measurement")
     ap.add_argument("--pipeline-windows", type=int, default=100,
                     help="timed windows of the vital-sign pipeline")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving measurement (256 tenants, Poisson arrivals)")
+    ap.add_argument("--serving-seconds", type=float, default=20.0,
+                    help="duration of the synthetic serving traffic")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy of known "
                          "size, to scale hardware byte counters)")
@@ -253,6 +257,10 @@ def main():
         vital = vital_pipeline_latency(ctx, prm, sk, rlk, args.pipeline_windows, log)
         gesture = gesture_pipeline_latency(ctx, prm, sk, rlk, args.pipeline_windows, log)
 
+    serving = None
+    if not args.no_serving and not args.quick:
+        serving = serving_benchmark(args.serving_seconds, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(prm, args.cpu_seconds, log)
@@ -288,6 +296,7 @@ def main():
         "rotation_ceilings": ceilings,
         "vital_pipeline": vital,
         "gesture_pipeline": gesture,
+        "serving": serving,
         "roofline": roof,
         "kernels": breakdown,
         "cpu_baseline": cpu,
@@ -471,6 +480,212 @@ def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "predicted_class": int(np.argmax(logits)), "kernel_noise": noise}
     log(f"gesture pipeline: {res}")
     return res
+
+
+def _pinned_u64(a):
+    """A copy of a uint64 array in pinned host memory (asynchronous uploads)."""
+    import torch
+    t = torch.empty(a.size, dtype=torch.int64, pin_memory=True)
+    out = t.numpy().view(np.uint64).reshape(a.shape)
+    out[...] = a
+    return out, t
+
+
+def serving_benchmark(seconds, log, tenants=256, key_sets=4, budget_gb=200.0, max_batch=8,
+                      max_inflight=32, seed=7):
+    """The serving runtime (hck_server) on synthetic traffic, at N = 2^15,
+    L = 12, where one tenant's evaluation keys take 0.5-2 GB.
+
+    1. Batched against sequential: 64 mixed windows (40 vital, 24 gesture) of
+       64 tenants as plain per-window calls, one after another, and then
+       submitted to the server at once (keys resident after a warm-up pass).
+    2. Serving: Poisson arrivals from `tenants` tenants (70 % vital, 30 %
+       gesture) for `seconds`, at 80 % of the batched throughput, under an HBM
+       budget of `budget_gb` for resident keys and admitted windows.  Latency is
+       submit-to-result per request.  Synthetic tenants draw their keys from
+       `key_sets` distinct secret keys (host-memory bound); each tenant still
+       holds its own device copy."""
+    import torch
+    import paper_2603_22437_amd as H
+    import seeded_inputs as S
+    from paper_2603_22437_amd import gesture as HG
+    from paper_2603_22437_amd import vital as HV
+    prm = S.params("mix15")
+    ctx = H.Context.from_params(prm)
+    l0 = len(prm["q"]) - 1
+    vcfg = S.vital_pipeline_config()
+    gcfg = S.gesture_pipeline_config(frames=14)
+    plans = {H.SERVE_VITAL: HV.encode_plan(ctx, vcfg, l0),
+             H.SERVE_GESTURE: HG.encode_plan(ctx, gcfg, l0, prm["scale"])}
+    steps = {H.SERVE_VITAL: ctx.vital_required_steps(plans[H.SERVE_VITAL]),
+             H.SERVE_GESTURE: ctx.gesture_required_steps(plans[H.SERVE_GESTURE])}
+    union = sorted(set(steps[H.SERVE_VITAL]) | set(steps[H.SERVE_GESTURE]))
+    t0 = time.perf_counter()
+    sets, keep = [], []
+    for k in range(key_sets):
+        sk = ctx.keygen_secret(900 + k)
+        gks = ctx.keygen_rotation(sk, union, 910 + k)
+        rlk = ctx.keygen_relin(sk, 920 + k)
+        words = {}
+        for st in union:
+            w, t = _pinned_u64(ctx.galois_keys_export(gks, ctx.galois_element(st)))
+            words[st] = w
+            keep.append(t)
+        rw, t = _pinned_u64(ctx.switch_key_export(rlk))
+        keep.append(t)
+        wins = {}
+        for kind in (H.SERVE_VITAL, H.SERVE_GESTURE):
+            wins[kind] = []
+            for j in range(2):
+                sd = 3000 + 10 * k + j
+                z = (S.vital_window(sd, vcfg["frames"], vcfg["bins"]) if kind == H.SERVE_VITAL
+                     else S.gesture_window(sd, gcfg["frames"]))
+                v = np.zeros(ctx.n_slots, dtype=np.complex128)
+                v[: z.size] = z.reshape(-1)
+                re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 2 * sd)
+                im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 2 * sd + 1)
+                wins[kind].append((re, im, ctx.ciphertext_export(re)[0],
+                                   ctx.ciphertext_export(im)[0]))
+        sets.append(dict(gks=gks, rlk=rlk, words=words, rlk_words=rw, wins=wins))
+    kind_of = lambda t: H.SERVE_VITAL if t % 10 < 7 else H.SERVE_GESTURE
+    log(f"serving set-up: {key_sets} key sets, {len(union)} rotation keys each, "
+        f"{time.perf_counter() - t0:.1f} s")
+
+    # 1. 64 mixed windows: sequential plain calls
+    burst = [t for t in range(tenants) if kind_of(t) == H.SERVE_VITAL][:40] + \
+            [t for t in range(tenants) if kind_of(t) == H.SERVE_GESTURE][:24]
+    def window_of(t, j=0):
+        return sets[t % key_sets]["wins"][kind_of(t)][j % 2]
+    def sequential(transfers):
+        """64 plain calls one after another (keys resident); with transfers,
+        each window is also uploaded from and its outputs downloaded to host
+        memory, as a caller without the server would."""
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for t in burst:
+            ks = sets[t % key_sets]
+            re, im, rw, iw = window_of(t)
+            if transfers:
+                re = ctx.ciphertext_import(rw, l0, prm["scale"])
+                im = ctx.ciphertext_import(iw, l0, prm["scale"])
+            if kind_of(t) == H.SERVE_VITAL:
+                outs = ctx.vital_eval(plans[H.SERVE_VITAL], re, im, ks["gks"], ks["rlk"])
+            else:
+                outs = [ctx.gesture_eval(plans[H.SERVE_GESTURE], re, im, ks["gks"], ks["rlk"])]
+            if transfers:
+                for c in outs:
+                    ctx.ciphertext_export(c)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ts
+
+    sequential(False)
+    seq_s = sequential(False)
+    seq_io_s = sequential(True)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(budget_gb * 2 ** 30, free - 24 * 2 ** 30))
+    srv = H.Server(ctx, budget, max_batch, max_inflight)
+    try:
+        for t in range(tenants):
+            ks = sets[t % key_sets]
+            kind = kind_of(t)
+            srv.add_tenant(t, kind, plans[kind], steps[kind],
+                           [ks["words"][st] for st in steps[kind]], ks["rlk_words"])
+
+        def run_burst(first_id):
+            ts = time.perf_counter()
+            for i, t in enumerate(burst):
+                _, _, rw, iw = window_of(t)
+                srv.submit(first_id + i, t, rw, iw, l0, prm["scale"])
+            got = []
+            while len(got) < len(burst):
+                got += srv.poll(timeout_ms=60000)
+            return time.perf_counter() - ts, got
+
+        run_burst(0)                       # loads the 64 tenants' keys
+        run_burst(500)                     # grows the scratch pool to full batches
+        burst_s, got = run_burst(1000)     # keys resident
+        assert all(r["status"] == 0 for r in got)
+        batched_wps = len(burst) / burst_s
+        batches = [r["batch"] for r in got]
+        log(f"64 mixed windows: sequential {len(burst) / seq_s:.1f} windows/s, "
+            f"served {batched_wps:.1f} windows/s")
+
+        # 2. Poisson arrivals
+        rng = np.random.default_rng(seed)
+        rate = 0.8 * batched_wps
+        gaps = rng.exponential(1.0 / rate, size=int(rate * seconds * 1.5) + 16)
+        arrivals = np.cumsum(gaps)
+        arrivals = arrivals[arrivals < seconds]
+        who = rng.integers(0, tenants, size=len(arrivals))
+        st0 = srv.stats()
+        results, lag = [], 0.0
+        base = time.perf_counter()
+        nxt = 0
+        next_log = base + 5.0
+        while nxt < len(arrivals) or len(results) < len(arrivals):
+            now = time.perf_counter() - base
+            while nxt < len(arrivals) and arrivals[nxt] <= now:
+                t = int(who[nxt])
+                _, _, rw, iw = window_of(t, nxt)
+                srv.submit(10000 + nxt, t, rw, iw, l0, prm["scale"])
+                lag = max(lag, time.perf_counter() - base - arrivals[nxt])
+                nxt += 1
+            wait = 0 if nxt >= len(arrivals) else max(0.0, arrivals[nxt] - now)
+            results += srv.poll(timeout_ms=int(min(wait, 0.05) * 1000) if nxt < len(arrivals)
+                                else 1000)
+            if time.perf_counter() > next_log:
+                log(f"serving: {nxt} submitted, {len(results)} done")
+                next_log += 5.0
+        wall = time.perf_counter() - base
+        st1 = srv.stats()
+    finally:
+        srv.close()
+    ok = [r for r in results if r["status"] == 0]
+    lat = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in ok])
+    vl = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in ok
+                   if kind_of(r["tenant"]) == H.SERVE_VITAL])
+    gl = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in ok
+                   if kind_of(r["tenant"]) == H.SERVE_GESTURE])
+    warm = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in ok if not r["key_load"]])
+    cold = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in ok if r["key_load"]])
+    pct = lambda a, q: round(float(np.percentile(a, q)), 2) if len(a) else None
+    out = {
+        "ring": "N=2^15, L=12, K=4, dnum=3",
+        "tenants": tenants, "mix": "70% vital / 30% gesture",
+        "key_gb_per_tenant": {"vital": round((len(steps[H.SERVE_VITAL]) + 1) *
+                                             sets[0]["rlk_words"].nbytes / 2 ** 30, 3),
+                              "gesture": round((len(steps[H.SERVE_GESTURE]) + 1) *
+                                               sets[0]["rlk_words"].nbytes / 2 ** 30, 3)},
+        "hbm_budget_gb": round(budget / 2 ** 30, 1),
+        "max_batch": max_batch, "max_inflight": max_inflight,
+        "batched_vs_sequential": {
+            "windows": len(burst), "sequential_plain_windows_per_s": round(len(burst) / seq_s, 2),
+            "sequential_plain_with_transfers_windows_per_s": round(len(burst) / seq_io_s, 2),
+            "served_batched_windows_per_s": round(batched_wps, 2),
+            "speedup_vs_plain": round(batched_wps * seq_s / len(burst), 3),
+            "speedup_vs_plain_with_transfers": round(batched_wps * seq_io_s / len(burst), 3),
+            "mean_batch": round(float(np.mean(batches)), 2)},
+        "poisson": {
+            "seconds": seconds, "offered_windows_per_s": round(rate, 2),
+            "submitted": int(len(arrivals)), "completed": len(ok),
+            "failed": len(results) - len(ok),
+            "windows_per_s": round(len(ok) / wall, 2),
+            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+            "vital_p50_ms": pct(vl, 50), "vital_p99_ms": pct(vl, 99),
+            "gesture_p50_ms": pct(gl, 50), "gesture_p99_ms": pct(gl, 99),
+            "warm_requests": int(len(warm)), "warm_p50_ms": pct(warm, 50),
+            "warm_p99_ms": pct(warm, 99),
+            "cold_requests": int(len(cold)), "cold_p50_ms": pct(cold, 50),
+            "cold_p99_ms": pct(cold, 99),
+            "mean_batch": round(float(np.mean([r["batch"] for r in ok])), 2) if ok else None,
+            "key_loads": st1["key_loads"] - st0["key_loads"],
+            "evictions": st1["evictions"] - st0["evictions"],
+            "key_gb_loaded": round((st1["key_bytes_loaded"] - st0["key_bytes_loaded"]) / 2 ** 30,
+                                   1),
+            "max_submit_lag_ms": round(float(lag) * 1e3, 2)},
+    }
+    log(f"serving: {out}")
+    return out
 
 
 def _flat(result):

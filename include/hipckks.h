@@ -487,9 +487,12 @@ int hck_decode_residues(uint32_t log_n, const uint64_t *res, const uint64_t *mod
  * context only through the server until hck_server_destroy.  One worker
  * thread admits requests in arrival order while the HBM budget allows.  A
  * tenant's evaluation keys are loaded from the caller's host memory when it
- * has none resident.  To make room, idle tenants are evicted, least recently
- * used first; a tenant with admitted work is never evicted.  The worker
- * launches admitted windows, up to max_batch of one pipeline per batch,
+ * has none resident, two tenants' transfers at a time, on a copy stream that
+ * overlaps the evaluation.  To make room, idle tenants are evicted, least
+ * recently used first; a tenant with admitted work is never evicted.  A
+ * request waiting for its tenant's keys (or for budget) does not hold back
+ * later requests of resident tenants.  The worker launches admitted windows
+ * whose keys have arrived, up to max_batch of one pipeline per batch,
  * whenever fewer than two batches are queued on the device.  So requests
  * that arrive while others run join the next batch, and windows of different
  * tenants share key-switch launches, each with its own keys.  Every result
@@ -511,6 +514,7 @@ typedef struct {
   uint32_t tenant;
   uint32_t n_out;        /* 4 (vital) or 1 (gesture) */
   uint32_t batch;        /* windows in the batch the request ran in */
+  uint32_t key_load;     /* 1 if admitting it loaded its tenant's keys */
   uint32_t out_level[4];
   double out_scale[4];
   double t_submit, t_admit, t_launch, t_done; /* seconds, host steady clock */

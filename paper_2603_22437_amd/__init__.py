@@ -730,7 +730,8 @@ class ServerConfig(ctypes.Structure):
 
 class ServerResult(ctypes.Structure):
     _fields_ = [("request", _U64), ("status", _I32), ("tenant", _U32), ("n_out", _U32),
-                ("batch", _U32), ("out_level", _U32 * 4), ("out_scale", _D * 4),
+                ("batch", _U32), ("key_load", _U32), ("out_level", _U32 * 4),
+                ("out_scale", _D * 4),
                 ("t_submit", _D), ("t_admit", _D), ("t_launch", _D), ("t_done", _D)]
 
 
@@ -794,7 +795,8 @@ class Server:
                                                                self.ctx.n).copy())
                     off += size
             done.append({"request": r.request, "status": r.status, "tenant": r.tenant,
-                         "batch": r.batch, "levels": list(r.out_level[: r.n_out]),
+                         "batch": r.batch, "key_load": bool(r.key_load),
+                         "levels": list(r.out_level[: r.n_out]),
                          "scales": list(r.out_scale[: r.n_out]), "t_submit": r.t_submit,
                          "t_admit": r.t_admit, "t_launch": r.t_launch, "t_done": r.t_done,
                          "outputs": outs})

@@ -8,15 +8,20 @@
 //    evaluation keys are loaded from host memory when it has none resident
 //    (least recently used idle tenants are evicted to make room, never one
 //    with admitted work), on a copy stream of their own so that the transfer
-//    overlaps the evaluation already queued;
-//  * launches admitted windows as soon as fewer than two batches are queued on
-//    the device, up to max_batch windows of one pipeline per batch (windows of
-//    different tenants share key-switch batches, each with its own keys), so
-//    that requests arriving while others run join the next batch;
+//    overlaps the evaluation already queued.  At most kMaxUploads tenants'
+//    keys are in transfer at once; requests of resident tenants are admitted
+//    past those waiting for an upload slot;
+//  * launches admitted windows whose keys have arrived as soon as fewer than
+//    two batches are queued on the device, up to max_batch windows of one
+//    pipeline per batch (windows of different tenants share key-switch
+//    batches, each with its own keys), so that requests arriving while others
+//    run join the next batch and a key transfer never stalls the evaluation
+//    of resident tenants;
 //  * completes batches as their events fire, copying the results to the
 //    caller's buffers and releasing their footprint.
 // All device work is stream-ordered on the context stream; the host never
 // waits for the device except on teardown.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -81,6 +86,9 @@ struct Batch {
 
 uint32_t outputs_of(uint32_t kind) { return kind == HCK_SERVE_VITAL ? 4 : 1; }
 
+// tenants whose keys may be in transfer at once
+constexpr size_t kMaxUploads = 2;
+
 }  // namespace
 
 struct hck_server {
@@ -107,6 +115,7 @@ struct hck_server {
   std::map<uint32_t, Tenant> tenants;
   std::deque<Request *> pending, admitted;
   std::deque<Batch> inflight;
+  std::vector<uint32_t> uploading;  // tenants whose key transfer may be running
   std::thread worker;
   int fatal = HCK_OK;
 };
@@ -177,6 +186,12 @@ int convert_keys(hck_server *s, Tenant &t) {
   if (rc) return rc;
   t.converted = true;
   return HCK_OK;
+}
+
+// true once a tenant's key transfer has completed (or its keys are in use)
+bool keys_arrived(Tenant &t) {
+  if (t.converted || !t.copied) return true;
+  return hipEventQuery(t.copied) != hipErrorNotReady;
 }
 
 uint64_t window_bytes(const hck_context *ctx, uint32_t kind) {
@@ -300,21 +315,33 @@ bool complete(hck_server *s, bool block) {
 }
 
 // admits pending requests in arrival order while the budget and the in-flight
-// limit allow; true if any was admitted
+// limit allow; a request whose tenant's keys must be loaded waits for an
+// upload slot without holding back later requests of resident tenants.  True
+// if any was admitted.
 bool admit(hck_server *s) {
   bool any = false;
   const size_t cap = s->cfg.max_inflight;
   size_t flying = s->admitted.size();
   for (auto &b : s->inflight) flying += b.reqs.size();
-  while (!s->pending.empty() && flying < cap) {
-    Request *r = s->pending.front();
+  s->uploading.erase(std::remove_if(s->uploading.begin(), s->uploading.end(),
+                                    [&](uint32_t t) { return keys_arrived(s->tenants[t]); }),
+                     s->uploading.end());
+  for (auto pit = s->pending.begin(); pit != s->pending.end() && flying < cap;) {
+    Request *r = *pit;
     auto it = s->tenants.find(r->tenant);
+    if (!s->res.resident(r->tenant) && s->uploading.size() >= kMaxUploads) {
+      ++pit;
+      continue;
+    }
     const uint64_t extra = window_bytes(s->ctx, it->second.kind);
     std::vector<uint32_t> evict;
     bool load = false;
     const Residency::Decision d = s->res.admit(r->tenant, extra, evict, load);
-    if (d == Residency::kWait) break;
-    s->pending.pop_front();
+    if (d == Residency::kWait) {
+      ++pit;
+      continue;
+    }
+    pit = s->pending.erase(pit);
     r->res.t_admit = now_s();
     if (d == Residency::kReject) {
       finish(s, r, HCK_ENOMEM);
@@ -334,6 +361,8 @@ bool admit(hck_server *s) {
         s->res.evict(tenant);
         continue;
       }
+      s->uploading.push_back(r->tenant);
+      r->res.key_load = 1;
       std::lock_guard<std::mutex> g(s->mu);
       s->stats.key_loads++;
       s->stats.key_bytes_loaded += it->second.key_bytes;
@@ -350,13 +379,16 @@ bool admit(hck_server *s) {
 // launches one batch of admitted windows (the oldest request's pipeline)
 bool launch_next(hck_server *s) {
   if (s->admitted.empty() || s->inflight.size() >= 2) return false;
-  Request *first = s->admitted.front();
+  // the oldest admitted request whose keys have arrived sets the pipeline
+  auto ready = [&](Request *r) { return keys_arrived(s->tenants[r->tenant]); };
+  auto fit = std::find_if(s->admitted.begin(), s->admitted.end(), ready);
+  if (fit == s->admitted.end()) return false;
+  Request *first = *fit;
   const Tenant &t0 = s->tenants[first->tenant];
   std::vector<Request *> reqs;
-  for (auto it = s->admitted.begin();
-       it != s->admitted.end() && reqs.size() < s->cfg.max_batch;) {
+  for (auto it = fit; it != s->admitted.end() && reqs.size() < s->cfg.max_batch;) {
     const Tenant &t = s->tenants[(*it)->tenant];
-    if (t.kind == t0.kind && t.plan == t0.plan && (*it)->level == first->level) {
+    if (t.kind == t0.kind && t.plan == t0.plan && (*it)->level == first->level && ready(*it)) {
       reqs.push_back(*it);
       it = s->admitted.erase(it);
     } else {
@@ -425,7 +457,8 @@ void worker_main(hck_server *s) {
                             [&] { return !s->incoming.empty() || !s->new_tenants.empty(); });
       } else {
         std::unique_lock<std::mutex> g(s->mu);
-        s->cv_work.wait_for(g, std::chrono::microseconds(s->inflight.empty() ? 2000 : 200),
+        const bool busy = !s->inflight.empty() || !s->admitted.empty() || !s->pending.empty();
+        s->cv_work.wait_for(g, std::chrono::microseconds(busy ? 200 : 2000),
                             [&] {
                               return !s->incoming.empty() || !s->new_tenants.empty() || s->stop;
                             });
@@ -530,12 +563,18 @@ int hck_server_submit(hck_server *s, uint64_t request, uint32_t tenant, const ui
   r->in.resize(2 * half);
   std::memcpy(r->in.data(), re_words, half * 8);
   std::memcpy(r->in.data() + half, im_words, half * 8);
-  for (size_t w = 0; w < 2 * half; w++) {
-    const size_t row = (w % half) / ctx->n;  // [poly][limb] row of one input
-    if (r->in[w] >= ctx->mods[row % (level + 1)]) {
-      delete r;
-      return set_error(HCK_EINVAL, "residue not below its prime");
-    }
+  // every row [ct][poly][limb] below its limb's prime
+  bool ok = true;
+  for (size_t row = 0; row < 4 * (size_t)(level + 1); row++) {
+    const uint64_t q = ctx->mods[row % (level + 1)];
+    const uint64_t *v = r->in.data() + row * ctx->n;
+    uint64_t bad = 0;
+    for (size_t c = 0; c < ctx->n; c++) bad |= (uint64_t)(v[c] >= q);
+    ok = ok && !bad;
+  }
+  if (!ok) {
+    delete r;
+    return set_error(HCK_EINVAL, "residue not below its prime");
   }
   r->res.request = request;
   r->res.tenant = tenant;

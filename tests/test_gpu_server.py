@@ -164,7 +164,9 @@ def test_budget_forces_evictions_and_results_stay_exact(world):
         reqs.append((rid, t, rw, iw))
     done, st = _serve(w, reqs, budget=budget, max_batch=4, max_inflight=4)
     assert st["failed"] == 0 and st["completed"] == len(reqs)
-    assert st["evictions"] >= 3 and st["key_loads"] >= 4
+    # only one tenant's keys fit at a time: every tenant is loaded, and each
+    # switch to another tenant evicts the previous one
+    assert st["key_loads"] >= 3 and st["evictions"] >= 2
     assert st["resident_bytes"] <= budget
     for rid, (t, re, im) in wins.items():
         want = _direct(w, t, re, im)

@@ -30,4 +30,5 @@ def test_server_symbols_exported():
         assert hasattr(H.capi, name)
     # the result record's layout matches the C struct (8-byte aligned doubles)
     assert H.ServerResult.t_submit.offset % 8 == 0
-    assert H.ctypes.sizeof(H.ServerResult) == 8 + 4 * 4 + 16 + 32 + 32
+    assert H.ServerResult.out_scale.offset == 48
+    assert H.ctypes.sizeof(H.ServerResult) == 48 + 32 + 32
