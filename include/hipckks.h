@@ -92,6 +92,18 @@ int hck_context_create(const hck_params *params, int device, void *hip_stream,
 int hck_context_destroy(hck_context *ctx);
 /* Switches the stream later work is issued on (the caller orders the two). */
 int hck_context_set_stream(hck_context *ctx, void *hip_stream);
+/* Routes the context's device buffers (ciphertexts, keys, plaintexts,
+ * transforms, workspaces) through the caller's allocator, e.g. torch's
+ * caching allocator: alloc(bytes, stream, user) returns device memory usable
+ * in the order of `stream` (the context stream), or NULL (HCK_ENOMEM);
+ * free(ptr, stream, user) returns it, stream-ordered after every use queued
+ * on that stream.  Both NULL restores the default (hipMallocAsync /
+ * hipFreeAsync on the context stream).  Allowed only while the context holds
+ * no buffer of the current allocator (set it right after creation), else
+ * HCK_EINVAL.  Constant tables made at creation and a server's resident
+ * tenant keys use their own allocations. */
+int hck_set_allocator(hck_context *ctx, void *(*alloc)(size_t bytes, void *stream, void *user),
+                      void (*free)(void *ptr, void *stream, void *user), void *user);
 /* Waits for all work issued on the context's stream. */
 int hck_synchronize(hck_context *ctx);
 /* Message of the calling thread's last failure ("" if none). */

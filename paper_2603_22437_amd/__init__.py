@@ -20,6 +20,16 @@ LIB_PATH = os.path.join(_HERE, "libhipckks.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python paper_2603_22437_amd/build.py`")
 
+# torch ships its own HIP runtime.  Loading torch first makes the library bind
+# to that same runtime, so that one runtime serves both in the process: torch
+# then sees the GPU, and torch's streams and allocator are usable here.
+# Loaded the other way round, a second HIP runtime would come up beside the
+# library's, and torch would find no GPU.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 capi = ctypes.CDLL(LIB_PATH)
 
 _P = ctypes.c_void_p
@@ -28,6 +38,11 @@ _U32, _U64, _I32, _D, _SZ, _I = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int3
                                   ctypes.c_double, ctypes.c_size_t, ctypes.c_int)
 _PU32 = ctypes.POINTER(ctypes.c_uint32)
 _PD = ctypes.POINTER(ctypes.c_double)
+
+
+# allocator hook types of hck_set_allocator
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class _Params(ctypes.Structure):
@@ -40,6 +55,7 @@ SIGNATURES = {
     "hck_context_create": ([ctypes.POINTER(_Params), _I, _P, _PP], _I),
     "hck_context_destroy": ([_P], _I),
     "hck_context_set_stream": ([_P, _P], _I),
+    "hck_set_allocator": ([_P, ALLOC_FN, FREE_FN, _P], _I),
     "hck_synchronize": ([_P], _I),
     "hck_last_error": ([], ctypes.c_char_p),
     "hck_galois_element": ([_P, _I32], _U32),
@@ -345,6 +361,8 @@ class Context:
         self.p = [int(x) for x in p]
         self.L, self.K = len(self.q), len(self.p)
         self.n_slots = self.n // 2
+        self.device = device
+        self._alloc_hooks = None
 
     @classmethod
     def from_params(cls, prm: dict, device: int = 0, stream=None):
@@ -372,6 +390,30 @@ class Context:
 
     def set_stream(self, stream):
         _check(capi.hck_context_set_stream(self.h, _stream_handle(stream)))
+
+    def use_torch_allocator(self):
+        """Routes the context's device buffers through torch's caching
+        allocator (hck_set_allocator), on the context's stream.  Call it right
+        after creation; close() the context before torch shuts down."""
+        import torch
+        dev = self.device
+
+        def alloc(size, stream, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(size, dev, stream or 0)
+            except Exception:       # out of memory: the library reports HCK_ENOMEM
+                return None
+
+        def free(ptr, stream, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        hooks = (ALLOC_FN(alloc), FREE_FN(free))
+        _check(capi.hck_set_allocator(self.h, hooks[0], hooks[1], None))
+        self._alloc_hooks = hooks   # the C side calls them until close()
+
+    def use_default_allocator(self):
+        _check(capi.hck_set_allocator(self.h, ALLOC_FN(), FREE_FN(), None))
+        self._alloc_hooks = None
 
     def synchronize(self):
         _check(capi.hck_synchronize(self.h))

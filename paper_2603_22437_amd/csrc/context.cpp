@@ -69,17 +69,29 @@ int check_hip(hck_context *ctx, hipError_t e, const char *what) {
 int dev_alloc(hck_context *ctx, uint64_t **p, size_t words) {
   *p = nullptr;
   if (words == 0) return HCK_OK;
-  hipError_t e = hipMallocAsync((void **)p, words * sizeof(uint64_t), ctx->stream);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return set_error(HCK_ENOMEM, "device allocation of " + std::to_string(words * 8) + " bytes failed");
+  const size_t bytes = words * sizeof(uint64_t);
+  if (ctx->alloc_fn) {
+    *p = (uint64_t *)ctx->alloc_fn(bytes, (void *)ctx->stream, ctx->alloc_user);
+    if (!*p)
+      return set_error(HCK_ENOMEM, "the allocator hook returned no memory for " +
+                                       std::to_string(bytes) + " bytes");
+  } else {
+    hipError_t e = hipMallocAsync((void **)p, bytes, ctx->stream);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+      return set_error(HCK_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
   }
+  ctx->live_allocs++;
   return HCK_OK;
 }
 
 void dev_free(hck_context *ctx, void *p) {
-  if (p) (void)hipFreeAsync(p, ctx->stream);
+  if (!p) return;
+  if (ctx->free_fn) ctx->free_fn(p, (void *)ctx->stream, ctx->alloc_user);
+  else (void)hipFreeAsync(p, ctx->stream);
+  ctx->live_allocs--;
 }
 
 int ensure_ct(hck_context *ctx, hck_ciphertext *ct, uint32_t polys) {
@@ -416,6 +428,20 @@ int hck_context_create(const hck_params *params, int device, void *hip_stream,
 
 int hck_context_destroy(hck_context *ctx) {
   hck::destroy_context(ctx);
+  return HCK_OK;
+}
+
+int hck_set_allocator(hck_context *ctx, void *(*alloc)(size_t, void *, void *),
+                      void (*free_fn)(void *, void *, void *), void *user) {
+  if (!ctx) return hck::set_error(HCK_EINVAL, "null context");
+  if (!alloc != !free_fn)
+    return hck::set_error(HCK_EINVAL, "give both allocator functions or neither");
+  if (ctx->live_allocs)
+    return hck::set_error(HCK_EINVAL, "the context still holds device buffers of the current "
+                                      "allocator");
+  ctx->alloc_fn = alloc;
+  ctx->free_fn = free_fn;
+  ctx->alloc_user = alloc ? user : nullptr;
   return HCK_OK;
 }
 

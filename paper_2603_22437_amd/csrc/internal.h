@@ -83,6 +83,13 @@ struct hck_context {
   uint64_t *zero_rows = nullptr;    // [L][N] zeros (absent diagonals of the BSGS grid)
   // scratch ciphertexts reused by linear transforms
   std::vector<struct hck_ciphertext *> ct_pool;
+  // device allocator: the caller's hook (hck_set_allocator) or, when unset,
+  // stream-ordered hipMallocAsync / hipFreeAsync; live_allocs counts the
+  // buffers dev_alloc handed out and dev_free has not yet returned
+  void *(*alloc_fn)(size_t, void *, void *) = nullptr;
+  void (*free_fn)(void *, void *, void *) = nullptr;
+  void *alloc_user = nullptr;
+  uint64_t live_allocs = 0;
 
   bool broken = false;
 

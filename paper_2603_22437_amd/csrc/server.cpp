@@ -124,10 +124,19 @@ namespace {
 
 // releases a tenant's device keys, stream-ordered after every use (uses are
 // on the context stream, which also waits for the upload when it never did)
+void free_key(hck_server *s, hck_switch_key *k) {
+  if (!k) return;
+  if (k->data) (void)hipFreeAsync(k->data, s->ctx->stream);
+  delete k;
+}
+
 void drop_keys(hck_server *s, Tenant &t) {
   if (t.copied && !t.converted) (void)hipStreamWaitEvent(s->ctx->stream, t.copied, 0);
-  if (t.gks) hck_galois_keys_destroy(t.gks);
-  if (t.rlk) hck_switch_key_destroy(t.rlk);
+  if (t.gks) {
+    for (auto &kv : t.gks->keys) free_key(s, kv.second);
+    delete t.gks;
+  }
+  free_key(s, t.rlk);
   if (t.copied) (void)hipEventDestroy(t.copied);
   t.gks = nullptr;
   t.rlk = nullptr;
@@ -136,6 +145,8 @@ void drop_keys(hck_server *s, Tenant &t) {
 }
 
 // device copies of a tenant's keys, allocated and filled on the copy stream
+// (their own stream-ordered allocations, whatever allocator the context uses;
+// free_key releases them)
 int load_keys(hck_server *s, Tenant &t) {
   hck_context *ctx = s->ctx;
   const size_t words = (size_t)ctx->dnum * 2 * (ctx->L + ctx->K) * ctx->n;
@@ -152,7 +163,9 @@ int load_keys(hck_server *s, Tenant &t) {
     *out = k;
     return e == hipSuccess ? HCK_OK : check_hip(ctx, e, "key upload");
   };
-  int rc = hck_galois_keys_create(ctx, &t.gks);
+  t.gks = new hck_galois_keys();
+  t.gks->ctx = ctx;
+  int rc = HCK_OK;
   for (size_t i = 0; !rc && i < t.steps.size(); i++) {
     hck_switch_key *k = nullptr;
     rc = one(t.gk_host[i], &k);

@@ -527,3 +527,39 @@ def test_bench_step_decodes_at_full_size():
     got = ctx.decode(ctx.decrypt(sk, pw)).real[: frames * bins].reshape(bins, frames)
     ref = np.abs(w @ z).T ** 2
     assert np.max(np.abs(got - ref)) < 1e-3
+
+
+def test_torch_allocator_hook():
+    """hck_set_allocator with torch's caching allocator: the context's buffers
+    come from torch (its counter rises while they live and falls after
+    close), results equal the default allocator's bit for bit, and the hook
+    cannot be swapped while buffers of the current allocator are alive."""
+    import torch
+    prm = S.params("tiny")
+    z = np.random.default_rng(3).uniform(-1, 1, 1 << (prm["log_n"] - 1))
+
+    def run(ctx):
+        sk = ctx.keygen_secret(1)
+        gks = ctx.keygen_rotation(sk, [1, 5], 2)
+        rlk = ctx.keygen_relin(sk, 3)
+        ct = ctx.encrypt_sk(sk, ctx.encode(z, prm["scale"], len(prm["q"]) - 1), 4)
+        r = ctx.rotate(ctx.relinearize(ctx.mul(ct, ct), rlk), 5, gks)
+        return ctx.ciphertext_export(r)[0]
+
+    ref_ctx = H.Context.from_params(prm)
+    ref = run(ref_ctx)
+    ref_ctx.close()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    ctx = H.Context.from_params(prm)
+    ctx.use_torch_allocator()
+    sk = ctx.keygen_secret(9)
+    assert torch.cuda.memory_allocated() > before
+    with pytest.raises(H.HckError):   # buffers of the hook are alive
+        ctx.use_default_allocator()
+    del sk
+    got = run(ctx)
+    assert np.array_equal(got, ref)
+    ctx.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
