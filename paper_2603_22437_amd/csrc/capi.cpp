@@ -288,9 +288,9 @@ int relinearize_keys(hck_context *ctx, const hck_ciphertext *const *a,
   const uint32_t level = a[0]->level;
   const size_t ps = poly_stride(ctx);
   const uint32_t limit = ks_batch_limit(ctx, level);
-  for (uint32_t s0 = 0; s0 < n; s0 += limit) {
+  for (uint32_t s0 = 0; s0 < n; s0 += even_batch(n - s0, limit)) {
     KsBatch kb;
-    kb.n = std::min<uint32_t>(limit, n - s0);
+    kb.n = even_batch(n - s0, limit);
     std::vector<double> scales(kb.n);
     for (uint32_t b = 0; b < kb.n; b++) {
       const hck_ciphertext *x = a[s0 + b];
@@ -1452,9 +1452,9 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
       if (pt.galois != 1) rot.push_back(pt);
     if (!rc) rc = ensure_workspace(ctx, ws_words_needed(ctx));
     const size_t pq_stride = (size_t)2 * (ctx->L + ctx->K) * n;
-    for (size_t s0 = 0; s0 < rot.size() && !rc; s0 += limit) {
+    for (size_t s0 = 0; s0 < rot.size() && !rc; s0 += even_batch(rot.size() - s0, limit)) {
       KsBatch kb;
-      kb.n = (uint32_t)std::min<size_t>(limit, rot.size() - s0);
+      kb.n = even_batch(rot.size() - s0, limit);
       std::vector<uint64_t *> pq(kb.n);
       bool first[kMaxBatch];
       for (uint32_t b = 0; b < kb.n; b++) {

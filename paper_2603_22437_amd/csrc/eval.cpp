@@ -13,21 +13,28 @@ size_t ws_ks_rows(const hck_context *ctx) {
   return L + ctx->dnum * LK + 2 * LK + 2 * L;
 }
 
-// [kMaxBatch key-switch slots][kMaxBatch x L rows: copies of aliased inputs]
+uint32_t ks_slots(const hck_context *ctx) {
+  const size_t rows = ws_ks_rows(ctx);
+  const size_t by_size = std::max<size_t>(8, 8192 / rows);
+  const size_t by_index = 65535 / rows;
+  return (uint32_t)std::max<size_t>(1, std::min<size_t>({(size_t)kMaxBatch, by_size, by_index}));
+}
+
+// [ks_slots key-switch slots][ks_slots x L rows: copies of aliased inputs]
 // [3 (L+K) rows: general temporary][kLtOut x 2 (L+K) rows: extended-basis sums]
 size_t ws_words_needed(const hck_context *ctx) {
-  const size_t n = ctx->n, L = ctx->L, LK = ctx->L + ctx->K;
-  return n * (kMaxBatch * ws_ks_rows(ctx) + kMaxBatch * L + 3 * LK + kLtOut * 2 * LK);
+  const size_t n = ctx->n, L = ctx->L, LK = ctx->L + ctx->K, S = ks_slots(ctx);
+  return n * (S * ws_ks_rows(ctx) + S * L + 3 * LK + kLtOut * 2 * LK);
 }
 
 uint64_t *ws_ks(hck_context *ctx) { return ctx->ws; }
 
 uint64_t *ws_rot(hck_context *ctx) {
-  return ctx->ws + (size_t)ctx->n * kMaxBatch * ws_ks_rows(ctx);
+  return ctx->ws + (size_t)ctx->n * ks_slots(ctx) * ws_ks_rows(ctx);
 }
 
 uint64_t *ws_tmp(hck_context *ctx) {
-  return ws_rot(ctx) + (size_t)ctx->n * kMaxBatch * ctx->L;
+  return ws_rot(ctx) + (size_t)ctx->n * ks_slots(ctx) * ctx->L;
 }
 
 uint64_t *ws_pq(hck_context *ctx) {
@@ -79,9 +86,9 @@ int apply_galois_keys(hck_context *ctx, const hck_ciphertext *const *a, const ui
   if (rc) return rc;
   const size_t ps = (size_t)ctx->L * ctx->n;
   const uint32_t limit = ks_batch_limit(ctx, level);
-  for (uint32_t s = 0; s < n; s += limit) {
+  for (uint32_t s = 0; s < n; s += even_batch(n - s, limit)) {
     KsBatch kb;
-    kb.n = std::min<uint32_t>(limit, n - s);
+    kb.n = even_batch(n - s, limit);
     std::vector<double> scales(kb.n);
     for (uint32_t b = 0; b < kb.n; b++) {
       const hck_ciphertext *x = a[s + b];

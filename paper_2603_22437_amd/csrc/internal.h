@@ -15,7 +15,7 @@ namespace hck {
 
 constexpr int kMaxLimbs = HCK_MAX_LIMBS;
 constexpr int kMaxRows = 256;  // rows of one batched launch (e.g. every extended digit)
-constexpr int kMaxBatch = 8;   // key switches run together in one sequence of launches
+constexpr int kMaxBatch = 32;  // key switches run together in one sequence of launches
 
 // Per-modulus constants, indexed by the modulus index of the full chain
 // (0..L-1: q chain, L..L+K-1: special primes).
@@ -316,6 +316,12 @@ struct KsBatch {
 int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level);
 // largest batch keyswitch_batch accepts at this level (row limits of one launch)
 uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level);
+// size of the next batch when `left` key switches remain and one launch takes
+// at most `limit`: the batches of what remains are made as even as possible
+inline uint32_t even_batch(size_t left, uint32_t limit) {
+  const size_t batches = (left + limit - 1) / limit;
+  return (uint32_t)((left + batches - 1) / batches);
+}
 // K1-K4 of keyswitch_batch without ModDown: slot b's key products
 // (acc0, acc1) in Q_level u P are added into pq[b] ([2][level+1+K][N],
 // evaluation form), or stored there when first[b]; slots may share a pq
@@ -377,6 +383,10 @@ int vital_eval_batch(hck_context *ctx, const hck_vital_plan *p, const hck_cipher
 int apply_galois_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, uint32_t g,
                       const hck_galois_keys *gks, hck_ciphertext *const *out);
 size_t ws_ks_rows(const hck_context *ctx);   // rows of one batch slot of ws_ks
+// key-switch slots of the workspace: up to kMaxBatch while the slots' rows
+// stay addressable by 16-bit row indices and within 8192 rows (8 slots at
+// least, as many as one launch can take)
+uint32_t ks_slots(const hck_context *ctx);
 // scratch ciphertexts owned by the context
 hck_ciphertext *pool_get(hck_context *ctx);
 void pool_put(hck_context *ctx, hck_ciphertext *ct);

@@ -1,6 +1,6 @@
 // Hybrid key switching with the basis conversions, the key inner product and
 // the ModDown tail fused into the NTT passes (ntt_core.h), for a batch of up
-// to kMaxBatch inputs that share one switching key.
+// to ks_slots inputs, each with its own switching key.
 //
 // KeySwitch(d) at level l with a switching key swk(s' -> s); d is read through
 // the NTT-domain automorphism X -> X^g (g = 1: no automorphism), so a
@@ -30,6 +30,12 @@
 namespace hck {
 
 namespace {
+
+struct KsGeom;
+// the largest kernel argument list (ModDown tail: batch table, row scales,
+// geometry, pointers) stays within the 4 KiB a kernel can take
+static_assert(sizeof(KsBatch) + sizeof(RowScale) + 128 + 64 <= 4096,
+              "kernel arguments beyond 4 KiB");
 
 struct KsGeom {
   uint32_t level, nq, ne, L, K, dnum, alpha, nm;
@@ -467,9 +473,9 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
   }
   const double digits = (double)((nq + alpha - 1) / alpha);
   const uint32_t limit = ks_batch_limit(ctx, level);
-  for (uint32_t s = 0; s < n; s += limit) {
+  for (uint32_t s = 0; s < n; s += even_batch(n - s, limit)) {
     KsBatch kb;
-    kb.n = std::min<uint32_t>(limit, n - s);
+    kb.n = even_batch(n - s, limit);
     for (uint32_t b = 0; b < kb.n; b++) {
       kb.key[b] = keys[s + b]->data;
       kb.galois[b] = galois[s + b];
@@ -544,14 +550,18 @@ int md_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, const uint64_t *c
 
 }  // namespace
 
+// Batches grow where each slot is small (low levels), so that a launch still
+// fills the chip; at high levels 8 slots of 24 limbs already do, and larger
+// batches measured slower there (more data between the passes of a batch).
 uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level) {
   const uint32_t by_rows = (uint32_t)kMaxRows / std::max<uint32_t>(level + 1, 2 * ctx->K);
-  return std::max<uint32_t>(1, std::min<uint32_t>((uint32_t)kMaxBatch, by_rows));
+  const uint32_t by_work = std::max<uint32_t>(1, 192 / (level + 1));
+  return std::max<uint32_t>(1, std::min({ks_slots(ctx), by_rows, by_work}));
 }
 
 int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level) {
   if (kb.n == 0) return HCK_OK;
-  if (kb.n > (uint32_t)kMaxBatch) return set_error(HCK_EINVAL, "batch too large");
+  if (kb.n > ks_slots(ctx)) return set_error(HCK_EINVAL, "batch too large");
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
   if (rc) return rc;
   if (level + 1 > (uint32_t)kMaxLimbs || (level + 1) * kb.n > (uint32_t)kMaxRows ||
