@@ -74,12 +74,14 @@ def main():
     ap.add_argument("--no-hoist-giant", action="store_true",
                     help="one ModDown per giant rotation instead of one per output")
     ap.add_argument("--quick", action="store_true",
-                    help="timed steps only (for profiler runs): no oracle baseline, "
-                         "rotation modes or per-kernel event pass")
+                    help="timed steps only (for profiler runs): no autotuning, oracle "
+                         "baseline, rotation modes or per-kernel event pass")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the vital-sign pipeline latency measurement")
     ap.add_argument("--pipeline-windows", type=int, default=100,
                     help="timed windows of the vital-sign pipeline")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in key-switch batch rule (no autotuning)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement (256 tenants, Poisson arrivals)")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
@@ -109,6 +111,15 @@ def main():
     top = L - 1
     log(f"context N=2^{prm['log_n']} L={L} K={len(prm['p'])} dnum={prm['dnum']} "
         f"({time.time() - t0:.1f}s)")
+    tuning = None
+    if not args.no_autotune and not args.quick:
+        t0 = time.time()
+        tuned = ctx.autotune_keyswitch()
+        tuning = {"keyswitches_per_launch": [tuned[l][0] for l in range(L)],
+                  "us_per_keyswitch": [round(tuned[l][1], 1) for l in range(L)],
+                  "seconds": round(time.time() - t0, 1)}
+        log(f"key-switch schedule tuned in {tuning['seconds']} s: "
+            f"{tuning['keyswitches_per_launch']}")
 
     # window -> bin-major slots (slot r*200 + t), real and imaginary ciphertexts
     z = S.vital_window(1000, FRAMES, BINS)
@@ -192,13 +203,17 @@ def main():
     ctx.add(ct_re, ct_im, chain_a)
     distinct = [k for k in steps_needed if k > 0][:16]
 
-    def timed(fn, count):
+    def timed(fn, count, trials=3):
+        """rate of the best of `trials` timed calls, after one warm-up call"""
         fn()
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        fn()
-        torch.cuda.synchronize()
-        return count / (time.perf_counter() - t)
+        best = float("inf")
+        for _ in range(trials):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return count / best
 
     def r1():
         x, y = chain_a, chain_b
@@ -287,7 +302,9 @@ def main():
             "rotations_per_step": rot_per_step, "keyswitches_per_step": rot_per_step + 1,
             "hoisted_baby_steps": not args.no_hoist,
             "shared_giant_moddown": not args.no_hoist_giant,
+            "keyswitch_schedule": "autotuned" if tuning else "built-in rule",
         },
+        "autotune": tuning,
         "decoded_max_abs_err": max_err,
         "window_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                               "p99": round(float(np.percentile(step_ms, 99)), 3),
@@ -578,6 +595,7 @@ def serving_benchmark(seconds, log, tenants=256, key_sets=4, budget_gb=200.0, ma
         torch.cuda.synchronize()
         return time.perf_counter() - ts
 
+    tuned = ctx.autotune_keyswitch()       # both paths run the tuned schedule
     sequential(False)
     seq_s = sequential(False)
     seq_io_s = sequential(True)
@@ -658,6 +676,7 @@ def serving_benchmark(seconds, log, tenants=256, key_sets=4, budget_gb=200.0, ma
                                                sets[0]["rlk_words"].nbytes / 2 ** 30, 3)},
         "hbm_budget_gb": round(budget / 2 ** 30, 1),
         "max_batch": max_batch, "max_inflight": max_inflight,
+        "keyswitches_per_launch": [tuned[l][0] for l in sorted(tuned)],
         "batched_vs_sequential": {
             "windows": len(burst), "sequential_plain_windows_per_s": round(len(burst) / seq_s, 2),
             "sequential_plain_with_transfers_windows_per_s": round(len(burst) / seq_io_s, 2),

@@ -450,6 +450,21 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *plan,
  * in dependent chains, 8 per thread) on the context's stream.  A measured
  * integer ceiling for the evaluation kernels, reported beside the HBM
  * bandwidth.  Errors: HCK_EINVAL, HCK_EDEVICE. */
+/* Autotuner of the key-switch schedule (the batching of section 3.3's
+ * rotations on this chip): for each of n_levels levels it times key
+ * switches of `count` zero ciphertexts at that level with a zero key.  Each
+ * candidate number of key switches per launch sequence (1 .. 32, within the
+ * launch row limits) is tried, and the context keeps the fastest per key
+ * switch.  The built-in rule stays unless a candidate beats it by 2 %.
+ * caps[i] and us_per_switch[i] (either may be NULL) receive the choice and
+ * its time.  Synchronizes the stream; results of later calls do not depend
+ * on the schedule (tested bit for bit).  Errors: HCK_ELEVEL, HCK_EINVAL. */
+int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_levels,
+                           uint32_t count, uint32_t *caps, double *us_per_switch);
+/* Sets the key switches per launch sequence at `level` (a saved tuning; 0
+ * restores the built-in rule), and reads the size in force. */
+int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap);
+int hck_keyswitch_batch_limit(const hck_context *ctx, uint32_t level, uint32_t *cap);
 int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s);
 
 /* ---- kernel timing --------------------------------------------------------

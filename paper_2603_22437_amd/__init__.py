@@ -126,6 +126,9 @@ SIGNATURES = {
     "hck_encode_coeffs": ([_U32, _P, _P, _D, _P], _I),
     "hck_decode_residues": ([_U32, _P, _P, _U32, _D, _P, _P], _I),
     "hck_switch_key_import": ([_P, _P, _SZ, _PP], _I),
+    "hck_autotune_keyswitch": ([_P, _P, _U32, _U32, _P, _P], _I),
+    "hck_set_keyswitch_cap": ([_P, _U32, _U32], _I),
+    "hck_keyswitch_batch_limit": ([_P, _U32, _PU32], _I),
     "hck_galois_keys_create": ([_P, _PP], _I),
     "hck_galois_keys_insert": ([_P, _U32, _P], _I),
     "hck_server_create": ([_P, _P, _PP], _I),
@@ -733,6 +736,26 @@ class Context:
         _check(capi.hck_gesture_eval_taps(self.h, ctypes.addressof(plan), re, im, gks, rlk,
                                           out, tp))
         return out, taps
+
+    def autotune_keyswitch(self, levels=None, count: int = 32) -> dict:
+        """Times key-switch batch sizes at each level (all by default) and
+        keeps the fastest; returns {level: (batch size, microseconds per key
+        switch)}."""
+        lv = np.ascontiguousarray(np.asarray(range(self.L) if levels is None else levels,
+                                             dtype=np.uint32))
+        caps = np.zeros(len(lv), dtype=np.uint32)
+        us = np.zeros(len(lv), dtype=np.float64)
+        _check(capi.hck_autotune_keyswitch(self.h, _ptr(lv), len(lv), count, _ptr(caps),
+                                           _ptr(us)))
+        return {int(l): (int(c), float(u)) for l, c, u in zip(lv, caps, us)}
+
+    def set_keyswitch_cap(self, level: int, cap: int):
+        _check(capi.hck_set_keyswitch_cap(self.h, level, cap))
+
+    def keyswitch_batch_limit(self, level: int) -> int:
+        c = ctypes.c_uint32()
+        _check(capi.hck_keyswitch_batch_limit(self.h, level, ctypes.byref(c)))
+        return c.value
 
     def measure_mulmod_rate(self) -> float:
         """Sustained 64-bit Shoup modular products per second on this device (T/s)."""

@@ -1,0 +1,132 @@
+// Autotuner of the key-switch schedule: how many key switches one launch
+// sequence takes at each level.  Small batches leave the chip idle at low
+// levels (each slot has few limbs); large ones stream more data between the
+// passes of a batch at high levels.  The best size depends on the ring, the
+// level and the chip, so it is measured: for each level, batches of zero
+// ciphertexts are key-switched with a zero key (the work does not depend on
+// the values) in launch sequences of each candidate size, timed with HIP
+// events, and the fastest per key switch is kept.
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+using namespace hck;
+
+namespace {
+
+#define TRY(expr)         \
+  do {                    \
+    int _rc = (expr);     \
+    if (_rc) return _rc;  \
+  } while (0)
+
+// microseconds per key switch of `count` rotations at `level` with the
+// current cap (median of `reps` timed calls after one warm-up call)
+int time_batch(hck_context *ctx, const std::vector<hck_ciphertext *> &in,
+               const std::vector<hck_ciphertext *> &out, const hck_switch_key *key, uint32_t reps,
+               hipEvent_t e0, hipEvent_t e1, double *us) {
+  const uint32_t n = (uint32_t)in.size();
+  const uint32_t g = galois_of_step(ctx, 1);
+  std::vector<uint32_t> gs(n, g);
+  std::vector<const hck_switch_key *> keys(n, key);
+  std::vector<double> t;
+  for (uint32_t r = 0; r <= reps; r++) {
+    HCK_HIP(ctx, hipEventRecord(e0, ctx->stream));
+    TRY(apply_galois_keys(ctx, in.data(), gs.data(), keys.data(), n, out.data()));
+    HCK_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    HCK_HIP(ctx, hipEventSynchronize(e1));
+    float ms = 0;
+    HCK_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+    if (r) t.push_back(1e3 * ms / n);
+  }
+  std::sort(t.begin(), t.end());
+  *us = t[t.size() / 2];
+  return HCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_levels,
+                           uint32_t count, uint32_t *caps, double *us_per_switch) {
+  if (!ctx || (n_levels && !levels)) return set_error(HCK_EINVAL, "null argument");
+  if (count == 0 || count > 256) return set_error(HCK_EINVAL, "count must be 1..256");
+  for (uint32_t i = 0; i < n_levels; i++)
+    if (levels[i] >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  HCK_HIP(ctx, hipSetDevice(ctx->device));
+  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+  // a zero switching key and zero ciphertexts
+  const size_t kwords = (size_t)ctx->dnum * 2 * (ctx->L + ctx->K) * ctx->n;
+  hck_switch_key key;
+  key.ctx = ctx;
+  TRY(dev_alloc(ctx, &key.data, kwords));
+  std::vector<hck_ciphertext *> in, out;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = HCK_OK;
+  for (uint32_t i = 0; i < count && !rc; i++) {
+    in.push_back(pool_get(ctx));
+    out.push_back(pool_get(ctx));
+    rc = ensure_ct(ctx, in.back(), 2);
+    if (!rc) rc = ensure_ct(ctx, out.back(), 2);
+    if (!rc && hipMemsetAsync(in.back()->data, 0, (size_t)2 * ctx->L * ctx->n * 8, ctx->stream) !=
+                   hipSuccess)
+      rc = check_hip(ctx, hipGetLastError(), "autotune set-up");
+    in.back()->size = 2;
+    in.back()->scale = 1.0;
+  }
+  if (!rc && hipMemsetAsync(key.data, 0, kwords * 8, ctx->stream) != hipSuccess)
+    rc = check_hip(ctx, hipGetLastError(), "autotune set-up");
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = check_hip(ctx, hipGetLastError(), "autotune events");
+  static const uint32_t kCand[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+  for (uint32_t li = 0; li < n_levels && !rc; li++) {
+    const uint32_t level = levels[li];
+    for (hck_ciphertext *c : in) c->level = level;
+    const uint32_t fit = ks_batch_fit(ctx, level);
+    const uint8_t saved = ctx->ks_cap[level];
+    // the built-in rule first: a candidate must beat it by 2 % to replace it
+    ctx->ks_cap[level] = 0;
+    const uint32_t rule = ks_batch_limit(ctx, level);
+    double best_us = 0;
+    rc = time_batch(ctx, in, out, &key, 3, e0, e1, &best_us);
+    uint32_t best = rule;
+    for (uint32_t c : kCand) {
+      if (rc || c > fit || c == rule) continue;
+      ctx->ks_cap[level] = (uint8_t)c;
+      double us = 0;
+      rc = time_batch(ctx, in, out, &key, 3, e0, e1, &us);
+      if (!rc && us < 0.98 * best_us) {
+        best_us = us;
+        best = c;
+      }
+    }
+    ctx->ks_cap[level] = rc ? saved : (uint8_t)best;
+    if (caps) caps[li] = best;
+    if (us_per_switch) us_per_switch[li] = best_us;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (hck_ciphertext *c : in) pool_put(ctx, c);
+  for (hck_ciphertext *c : out) pool_put(ctx, c);
+  dev_free(ctx, key.data);
+  return rc;
+}
+
+int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap) {
+  if (!ctx) return set_error(HCK_EINVAL, "null context");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  if (cap > (uint32_t)kMaxBatch) return set_error(HCK_EINVAL, "cap beyond the batch limit");
+  ctx->ks_cap[level] = (uint8_t)cap;
+  return HCK_OK;
+}
+
+int hck_keyswitch_batch_limit(const hck_context *ctx, uint32_t level, uint32_t *cap) {
+  if (!ctx || !cap) return set_error(HCK_EINVAL, "null argument");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  *cap = ks_batch_limit(ctx, level);
+  return HCK_OK;
+}
+
+}  // extern "C"

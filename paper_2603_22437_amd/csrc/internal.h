@@ -86,6 +86,9 @@ struct hck_context {
   // device allocator: the caller's hook (hck_set_allocator) or, when unset,
   // stream-ordered hipMallocAsync / hipFreeAsync; live_allocs counts the
   // buffers dev_alloc handed out and dev_free has not yet returned
+  // key switches per launch sequence at each level, chosen by the autotuner
+  // (hck_autotune_keyswitch) or set by the caller; 0: the built-in rule
+  uint8_t ks_cap[HCK_MAX_LIMBS] = {};
   void *(*alloc_fn)(size_t, void *, void *) = nullptr;
   void (*free_fn)(void *, void *, void *) = nullptr;
   void *alloc_user = nullptr;
@@ -316,6 +319,8 @@ struct KsBatch {
 int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level);
 // largest batch keyswitch_batch accepts at this level (row limits of one launch)
 uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level);
+// the largest batch one launch sequence can take at this level (row limits)
+uint32_t ks_batch_fit(const hck_context *ctx, uint32_t level);
 // size of the next batch when `left` key switches remain and one launch takes
 // at most `limit`: the batches of what remains are made as even as possible
 inline uint32_t even_batch(size_t left, uint32_t limit) {

@@ -553,10 +553,16 @@ int md_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, const uint64_t *c
 // Batches grow where each slot is small (low levels), so that a launch still
 // fills the chip; at high levels 8 slots of 24 limbs already do, and larger
 // batches measured slower there (more data between the passes of a batch).
-uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level) {
+uint32_t ks_batch_fit(const hck_context *ctx, uint32_t level) {
   const uint32_t by_rows = (uint32_t)kMaxRows / std::max<uint32_t>(level + 1, 2 * ctx->K);
-  const uint32_t by_work = std::max<uint32_t>(1, 192 / (level + 1));
-  return std::max<uint32_t>(1, std::min({ks_slots(ctx), by_rows, by_work}));
+  return std::max<uint32_t>(1, std::min(ks_slots(ctx), by_rows));
+}
+
+uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level) {
+  const uint32_t fit = ks_batch_fit(ctx, level);
+  if (level < (uint32_t)HCK_MAX_LIMBS && ctx->ks_cap[level])
+    return std::min<uint32_t>(fit, ctx->ks_cap[level]);
+  return std::min<uint32_t>(fit, std::max<uint32_t>(1, 192 / (level + 1)));
 }
 
 int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level) {

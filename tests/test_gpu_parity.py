@@ -563,3 +563,34 @@ def test_torch_allocator_hook():
     ctx.close()
     torch.cuda.synchronize()
     assert torch.cuda.memory_allocated() == before
+
+
+def test_autotune_keyswitch_keeps_results_exact():
+    """The key-switch autotuner picks a batch size per level within the launch
+    limits, and batched rotations give the same residues under the built-in
+    rule, the tuned sizes and one key switch per launch."""
+    prm = S.params("mix15")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    gks = ctx.keygen_rotation(sk, [3], 2)
+    top = len(prm["q"]) - 1
+    cts = [ctx.encrypt_sk(sk, ctx.encode(np.random.default_rng(k).uniform(-1, 1, ctx.n_slots),
+                                         prm["scale"], 5), 10 + k) for k in range(19)]
+
+    def rotated():
+        return [ctx.ciphertext_export(c)[0] for c in ctx.rotate_many(cts, 3, gks)]
+
+    ref = rotated()
+    rule = {l: ctx.keyswitch_batch_limit(l) for l in (0, 5, top)}
+    tuned = ctx.autotune_keyswitch([0, 5, top], count=16)
+    for l, (cap, us) in tuned.items():
+        assert 1 <= cap <= 32 and us > 0
+        assert ctx.keyswitch_batch_limit(l) == cap
+    assert all(np.array_equal(a, b) for a, b in zip(ref, rotated()))
+    ctx.set_keyswitch_cap(5, 1)
+    assert ctx.keyswitch_batch_limit(5) == 1
+    assert all(np.array_equal(a, b) for a, b in zip(ref, rotated()))
+    ctx.set_keyswitch_cap(5, 0)
+    assert ctx.keyswitch_batch_limit(5) == rule[5]
+    with pytest.raises(H.HckError):
+        ctx.set_keyswitch_cap(top + 1, 4)
