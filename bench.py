@@ -393,7 +393,12 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     from paper_2603_22437_amd import vital as HV
     cfg = S.vital_pipeline_config()
     top = len(prm["q"]) - 1
-    plan = HV.encode_plan(ctx, cfg, top)
+    # the circuit needs its depth in levels, plus one of headroom for the rate
+    # numerators (fourth powers of the spectrum reach 1e6 on strong windows,
+    # beyond q0 / scale at level 0): the plan is encoded for inputs at that
+    # level and the top-level inputs are dropped to it
+    base = (11 if cfg["taylor_order"] == 3 else 9) + 1
+    plan = HV.encode_plan(ctx, cfg, base)
     gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
     z = S.vital_window(1003, cfg["frames"], cfg["bins"])
     v = np.zeros(ctx.n_slots, dtype=np.complex128)
@@ -432,23 +437,29 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     torch.cuda.synchronize()
     batched_wps = batch * reps / (time.perf_counter() - t0)
     del outs_b, res_b, ims_b
-    noise = kernel_noise(ctx, prm, sk, top, ctx.VITAL_TAPS + plan.OUTPUTS,
+    noise = kernel_noise(ctx, prm, sk, top, base, ctx.VITAL_TAPS + plan.OUTPUTS,
                          lambda re_, im_: _flat(ctx.vital_eval_taps(plan, re_, im_, gks, rlk)),
                          lambda zz: HV.plain_stages(cfg, zz, ctx.n_slots),
                          [S.vital_window(1000 + i, cfg["frames"], cfg["bins"]) for i in range(3)])
     got = [ctx.decode(ctx.decrypt(sk, c)).real for c in outs]
     g = HV.lane_group(cfg)
+    plain_out = HV.plain_stages(cfg, z, ctx.n_slots)
     # the energy-weighted bin estimate must land on the synthetic target bin
     target = int(np.argmax(np.abs(z).sum(axis=0)))
     res = {"windows": windows, "p50_ms": round(float(np.percentile(ms, 50)), 3),
            "p99_ms": round(float(np.percentile(ms, 99)), 3),
            "windows_per_s": round(windows / wall, 2),
            "batched_8_windows_per_s": round(batched_wps, 2),
-           "taylor_order": cfg["taylor_order"],
+           "taylor_order": cfg["taylor_order"], "input_level": top, "plan_level": base,
            "rotation_keys": len(gks), "target_bin_true": target,
            "target_bin_est": round(float(got[0][0] / got[1][0]), 4),
            "resp_bpm_est": round(float(got[2][0] / got[3][0]), 3),
            "hr_bpm_est": round(float(got[2][g] / got[3][g]), 3),
+           # the same circuit on plaintext numbers; a weak band (tiny
+           # numerator and denominator) makes its rate ill-conditioned
+           "resp_bpm_plain": round(float(plain_out[-2][1][0] / plain_out[-1][1][0]), 3),
+           "hr_bpm_plain": round(float(plain_out[-2][1][1] / plain_out[-1][1][1]), 3),
+           "resp_band_den": float(f"{plain_out[-1][1][0]:.3e}"),
            "kernel_noise": noise}
     log(f"vital pipeline: {res}")
     return res
@@ -464,7 +475,8 @@ def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     from paper_2603_22437_amd import gesture as HG
     cfg = S.gesture_pipeline_config(frames=30)
     top = len(prm["q"]) - 1
-    plan = HG.encode_plan(ctx, cfg, top, prm["scale"])
+    base = HG.DEPTH            # plan for inputs at the circuit's depth
+    plan = HG.encode_plan(ctx, cfg, base, prm["scale"])
     gks = ctx.keygen_rotation(sk, ctx.gesture_required_steps(plan), 5)
     x = S.gesture_window(2003, cfg["frames"])
     v = np.zeros(ctx.n_slots, dtype=np.complex128)
@@ -486,13 +498,14 @@ def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(windows)])
     classes = cfg["weights"][2].shape[0]
     logits = ctx.decode(ctx.decrypt(sk, out))[:classes].real
-    noise = kernel_noise(ctx, prm, sk, top, ctx.GESTURE_TAPS + ("FC3 logits",),
+    noise = kernel_noise(ctx, prm, sk, top, base, ctx.GESTURE_TAPS + ("FC3 logits",),
                          lambda re_, im_: _flat(ctx.gesture_eval_taps(plan, re_, im_, gks, rlk)),
                          lambda xx: HG.plain_stages(cfg, xx, ctx.n_slots),
                          [S.gesture_window(2000 + i, cfg["frames"]) for i in range(3)])
     res = {"windows": windows, "p50_ms": round(float(np.percentile(ms, 50)), 3),
            "p99_ms": round(float(np.percentile(ms, 99)), 3),
            "windows_per_s": round(windows / wall, 2), "rotation_keys": len(gks),
+           "input_level": top, "plan_level": base,
            "frames": cfg["frames"], "classes": classes,
            "predicted_class": int(np.argmax(logits)), "kernel_noise": noise}
     log(f"gesture pipeline: {res}")
@@ -713,11 +726,12 @@ def _flat(result):
     return list(taps) + (list(outs) if isinstance(outs, (list, tuple)) else [outs])
 
 
-def kernel_noise(ctx, prm, sk, top, names, run, plain, windows):
+def kernel_noise(ctx, prm, sk, top, base, names, run, plain, windows):
     """Per-kernel encryption noise, the method of section 5.2 (Table 3): the
     MSE and max |error| between each decoded intermediate of the encrypted
     pipeline and the same value from plaintext execution, cumulative after
-    the preceding kernels, over the given windows; depth = levels consumed."""
+    the preceding kernels, over the given windows (encrypted at level `top`,
+    evaluated from the plan's level `base`); depth = levels consumed."""
     sq = [0.0] * len(names)
     cnt = [0] * len(names)
     mx = [0.0] * len(names)
@@ -734,7 +748,7 @@ def kernel_noise(ctx, prm, sk, top, names, run, plain, windows):
             sq[i] += float(np.sum(err ** 2))
             cnt[i] += len(slots)
             mx[i] = max(mx[i], float(np.max(np.abs(err))))
-            depth[i] = top - c.level
+            depth[i] = base - c.level
     return [{"stage": n, "mse": float(f"{sq[i] / cnt[i]:.3e}"),
              "max_abs_err": float(f"{mx[i]:.3e}"), "depth": depth[i]}
             for i, n in enumerate(names)]

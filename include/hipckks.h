@@ -349,8 +349,11 @@ int hck_lt_destroy(hck_linear_transform *lt);
  * G); the client's scalar divisions (section 3.3.4) give the target bin and
  * the two rates in beats per minute.
  * The operands are public plaintexts and transforms owned by the caller,
- * encoded at least at the level where they are applied (above); scales
- * follow from the operands' scales (q_level keeps a ciphertext's scale).
+ * encoded for inputs at a base level l0 (bin_index at l0-2, the others as
+ * above, at scale q_level so that a product keeps the ciphertext's scale).
+ * Inputs may come at any level >= l0: the pipeline drops them to l0 first
+ * (the circuit consumes only its depth), so a plan encoded at l0 = depth runs
+ * on depth + 1 primes whatever level the client encrypted at.
  * Errors: HCK_EINVAL (bad layout or missing operand), HCK_ELEVEL (input
  * level too low for the depth, operand level too low), HCK_ENOKEY. */
 typedef struct {
@@ -414,10 +417,11 @@ int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *plan,
  *       slots summed by rotations H1, 2 H1, ..., R D / 2; + bias1; squared
  *   FC2 fc2 (rectangular diagonals) + bias2; squared;  FC3 fc3 + bias3.
  * The output holds the logits in slots 0 .. classes-1 at level l0-11.
- * Transforms and plaintexts are owned by the caller and encoded at least at
- * the level where they are applied (dft l0, notch l0-2, fc1 l0-6, fc2 l0-8,
- * fc3 l0-10; bias_i at the level after its product, at the scale reached
- * there).  Errors: HCK_EINVAL, HCK_ELEVEL, HCK_ESCALE, HCK_ENOKEY. */
+ * Transforms and plaintexts are owned by the caller and encoded for inputs
+ * at a base level l0 (dft l0, notch l0-2, fc1 l0-6, fc2 l0-8, fc3 l0-10;
+ * bias_i at the level after its product, at the scale reached there).
+ * Inputs at a level above l0 are dropped to l0 first.
+ * Errors: HCK_EINVAL, HCK_ELEVEL, HCK_ESCALE, HCK_ENOKEY. */
 typedef struct {
   uint32_t frames, bins, chirps; /* F, R, D */
   uint32_t hidden1;              /* FC1 outputs H1; R D / H1 a power of two */

@@ -134,12 +134,23 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *p, const hck
     return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
   };
   TRY(check_plan(ctx, p));
-  if (re->level != im->level || re->level < 11)
-    return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
+  // the plan's operands are encoded for inputs at the level of its Doppler
+  // DFT; inputs above it are dropped to it
+  const uint32_t l0 = p->dft_c->level;
+  if (l0 < 11) return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
+  if (re->level != im->level || re->level < l0)
+    return set_error(HCK_ELEVEL, "inputs must share a level of at least the plan's level");
   for (int32_t s : plan_steps(p))
     if (!gks->keys.count(galois_of_step(ctx, s)))
       return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
   Scratch sc(ctx);
+  if (re->level > l0) {
+    hck_ciphertext *a = sc.get(), *b = sc.get();
+    TRY(hck_drop_level(ctx, re, l0, a));
+    TRY(hck_drop_level(ctx, im, l0, b));
+    re = a;
+    im = b;
+  }
   const uint32_t rd = p->bins * p->chirps, t2 = pow2_at_least(p->frames);
   // K3: Doppler DFT (complex, Eq. dft_re form)
   hck_ciphertext *d[2] = {sc.get(), sc.get()};

@@ -182,11 +182,17 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
                               hck_ciphertext *const *taps) {
   TRY(check_plan(ctx, p));
   const uint32_t depth = p->taylor_order == 3 ? 11 : 9;
+  // the plan's operands are encoded for inputs at level l0 (bin_index at
+  // l0 - 2); inputs above it are dropped to it, since the circuit uses only
+  // its first depth + 1 primes anyway
+  const uint32_t l0 = p->bin_index->level + 2;
+  if (l0 < depth || l0 >= ctx->L)
+    return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
   for (uint32_t k = 0; k < n; k++) {
     if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
     if (!wk.gks[k] || !wk.rlk[k]) return set_error(HCK_EINVAL, "null key");
-    if (re[k]->level != re[0]->level || im[k]->level != re[0]->level || re[0]->level < depth)
-      return set_error(HCK_ELEVEL, "inputs must share a level of at least the pipeline depth");
+    if (re[k]->level != re[0]->level || im[k]->level != re[0]->level || re[0]->level < l0)
+      return set_error(HCK_ELEVEL, "inputs must share a level of at least the plan's level");
     for (int i = 0; i < 4; i++)
       if (!out[4 * k + i]) return set_error(HCK_EINVAL, "null output");
   }
@@ -205,6 +211,17 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     for (auto &c : v) c = sc.get();
     return v;
   };
+  std::vector<const hck_ciphertext *> in_re(re, re + n), in_im(im, im + n);
+  if (re[0]->level > l0)
+    for (uint32_t k = 0; k < n; k++) {
+      hck_ciphertext *a = sc.get(), *b = sc.get();
+      TRY(hck_drop_level(ctx, re[k], l0, a));
+      TRY(hck_drop_level(ctx, im[k], l0, b));
+      in_re[k] = a;
+      in_im[k] = b;
+    }
+  re = in_re.data();
+  im = in_im.data();
   auto O = [&](uint32_t k, int i) { return out[4 * k + i]; };
   auto tap = [&](uint32_t k, int i, const hck_ciphertext *c) {
     hck_ciphertext *t = taps ? taps[HCK_VITAL_TAPS * k + i] : nullptr;

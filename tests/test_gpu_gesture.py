@@ -123,3 +123,30 @@ def test_gesture_taps_follow_plaintext_execution():
         assert l0 - c.level == d, name
         err = ctx.decode(ctx.decrypt(sk, c)).real[slots] - want
         assert np.mean(err ** 2) < 1e-5 and np.max(np.abs(err)) < 1e-3, name
+
+
+def test_gesture_inputs_above_the_plan_level_are_dropped():
+    """A plan for inputs at the circuit's depth (level 11 of 24): top-level
+    inputs give exactly the logits of inputs the caller dropped, and the
+    plaintext circuit's logits when decoded."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=30)
+    x = S.gesture_window(2006, cfg["frames"])
+    top = len(prm["q"]) - 1
+    plan = HG.encode_plan(ctx, cfg, HG.DEPTH, prm["scale"])
+    gks = ctx.keygen_rotation(sk, ctx.gesture_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: x.size] = x.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 101)
+    out = ctx.gesture_eval(plan, re, im, gks, rlk)
+    ref = ctx.gesture_eval(plan, ctx.drop_level(re, HG.DEPTH), ctx.drop_level(im, HG.DEPTH),
+                           gks, rlk)
+    assert np.array_equal(ctx.ciphertext_export(out)[0], ctx.ciphertext_export(ref)[0])
+    assert out.level == 0
+    classes = cfg["weights"][2].shape[0]
+    got = ctx.decode(ctx.decrypt(sk, out))[:classes].real
+    np.testing.assert_allclose(got, OG.plain(cfg, x), rtol=0, atol=1e-3)

@@ -165,3 +165,45 @@ def test_vital_taps_follow_plaintext_execution():
         assert l0 - c.level == d, name
         err = ctx.decode(ctx.decrypt(sk, c)).real[slots] - want
         assert np.mean(err ** 2) < 1e-5 and np.max(np.abs(err)) < 1e-3, name
+
+
+def test_vital_inputs_above_the_plan_level_are_dropped():
+    """A plan encoded for inputs at level 12 of 24 (the depth, 11, plus one
+    level of headroom: the rate numerators, fourth powers of the spectrum,
+    reach 1e6 on strong windows, beyond what q0 holds at scale 2^50):
+    top-level inputs are dropped to it, giving exactly the residues of inputs
+    the caller dropped, and the decoded outputs of the plaintext circuit."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config()
+    top = len(prm["q"]) - 1
+    plan = HV.encode_plan(ctx, cfg, 12)
+    gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    z = S.vital_window(1005, cfg["frames"], cfg["bins"])
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: z.size] = z.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 101)
+    got = ctx.vital_eval(plan, re, im, gks, rlk)
+    ref = ctx.vital_eval(plan, ctx.drop_level(re, 12), ctx.drop_level(im, 12), gks, rlk)
+    for a, b in zip(got, ref):
+        assert np.array_equal(ctx.ciphertext_export(a)[0], ctx.ciphertext_export(b)[0])
+    assert [c.level for c in got] == [9, 9, 1, 1]
+    want = OV.plain_slots(cfg, z, ctx.n_slots)
+    dec = {name: ctx.decode(ctx.decrypt(sk, g)).real for name, g in zip(OV.OUTPUTS, got)}
+    # the bin outputs within 1e-3; the rate numerators and denominators reach
+    # 1e6 on this strong window, so they are checked relatively, and the
+    # client's quantity, the rate in beats per minute, within 1e-3
+    for name in ("num_bin", "den_bin"):
+        assert abs(dec[name][0] - want[name][0]) < 1e-3, name
+    for name in ("num_rates", "den_rates"):
+        for slot, val in want[name].items():
+            assert abs(dec[name][slot] - val) <= 1e-6 * max(1.0, abs(val)), (name, slot)
+    for slot in want["num_rates"]:
+        bpm = dec["num_rates"][slot] / dec["den_rates"][slot]
+        assert abs(bpm - want["num_rates"][slot] / want["den_rates"][slot]) < 1e-3, slot
+    low = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], 11), 102)
+    with pytest.raises(H.HckError):   # below the plan's level
+        ctx.vital_eval(plan, low, low, gks, rlk)
