@@ -232,6 +232,7 @@ def main():
                       "R3_16ct_16_keys_rot_per_s": round(timed(r3, len(distinct)), 1)}
     log(f"rotation modes: {rotation_modes}")
     ceilings = rotation_ceilings(ctx, prm, rotation_modes, log)
+    tiny = tiny_end_to_end(log)
 
     # per-kernel durations over two more steps (events around every launch)
     ctx.timing(True)
@@ -311,6 +312,7 @@ def main():
                               "windows_per_s": round(args.steps / wall, 2)},
         "rotation_modes": rotation_modes,
         "rotation_ceilings": ceilings,
+        "tiny_end_to_end": tiny,
         "vital_pipeline": vital,
         "gesture_pipeline": gesture,
         "serving": serving,
@@ -352,6 +354,52 @@ def measured_traffic(kernel):
                 return None
             return int(cells[4])
     return None
+
+
+def tiny_end_to_end(log, reps=50):
+    """Latency of the tiny configuration (N = 2^12, L = 3) end to end on the
+    GPU: (I_32 (x) M64) x by BSGS (127 diagonals, n1 = 16), rescale, square
+    with relinearization, decrypted at scale ~2^50; median over `reps`
+    runs."""
+    import torch
+    import paper_2603_22437_amd as H
+    import seeded_inputs as S
+    tp = S.params("tiny")
+    ctx = H.Context.from_params(tp)
+    sk = ctx.keygen_secret(1)
+    level = len(tp["q"]) - 1
+    n_slots = ctx.n_slots
+    mat = S.uniform_matrix(64, 64, 0, 1 / 8)
+    j = np.arange(n_slots)
+    diags = {}
+    for k in range(-63, 64):
+        i = j % 64
+        ok = (i + k >= 0) & (i + k < 64)
+        diags[k % n_slots] = np.where(ok, mat[i, np.clip(i + k, 0, 63)], 0.0)
+    lt = ctx.lt_create(diags, 16, level)
+    gks = ctx.keygen_rotation(sk, ctx.lt_required_steps(lt), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    x = S.uniform_slots(n_slots, 0)
+    ct = ctx.encrypt_sk(sk, ctx.encode(x, tp["scale"], level), 3)
+
+    def once():     # decrypted at scale ~2^50 on 2 limbs, with no final rescale
+        y = ctx.rescale(ctx.lt_apply(lt, ct, gks))
+        return ctx.relinearize(ctx.mul(y, y), rlk)
+
+    out = once()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        out = once()
+        ctx.synchronize()
+        ms.append((time.perf_counter() - t) * 1e3)
+    err = float(np.max(np.abs(ctx.decode(ctx.decrypt(sk, out)).real -
+                              (np.kron(np.eye(n_slots // 64), mat) @ x) ** 2)))
+    res = {"p50_ms": round(float(np.median(ms)), 3), "reps": reps,
+           "decoded_max_abs_err": float(f"{err:.3e}")}
+    log(f"tiny end to end: {res}")
+    return res
 
 
 def rotation_ceilings(ctx, prm, modes, log):
@@ -755,8 +803,11 @@ def kernel_noise(ctx, prm, sk, top, base, names, run, plain, windows):
 
 
 def cpu_baseline(prm, seconds, log):
-    """The oracle's rotation (automorphism + hybrid key switching) of one
-    N = 2^16, L = 24 ciphertext at the top level, repeated for ~`seconds`."""
+    """The oracle on the host: the rotation (automorphism + hybrid key
+    switching) of one N = 2^16, L = 24 ciphertext at the top level, repeated
+    for ~`seconds` on all threads and for 2 rotations on one thread; and the
+    tiny configuration end to end (BSGS linear transform, rescale, square
+    with relinearization) at N = 2^12."""
     import oracle as O
     import seeded_inputs as S
     o = O.Oracle(prm)
@@ -765,18 +816,60 @@ def cpu_baseline(prm, seconds, log):
     gk = {g: o.keygen_galois(s, g, 5)}
     res = S.uniform_residues(o.qmods(o.L - 1), o.n, 7, count=2)
     ct = O.Ciphertext(res, o.L - 1, 2.0 ** 50)
-    n_rot, t0 = 0, time.perf_counter()
-    while True:
-        ct = o.rotate(ct, 1, gk)
-        n_rot += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or (n_rot >= 1 and el * (n_rot + 1) / n_rot > 2 * seconds):
-            break
-    log(f"oracle: {n_rot} rotations in {el:.1f}s on {O.num_threads()} threads")
-    return {"value": round(n_rot / el, 4), "unit": "rotations/s", "cores": O.num_threads(),
+
+    def rotations(budget, most):
+        nonlocal ct
+        n_rot, t0 = 0, time.perf_counter()
+        while n_rot < most:
+            ct = o.rotate(ct, 1, gk)
+            n_rot += 1
+            el = time.perf_counter() - t0
+            if el >= budget or el * (n_rot + 1) / n_rot > 2 * budget:
+                break
+        return n_rot, el
+
+    threads = O.num_threads()
+    n_rot, el = rotations(seconds, 10 ** 6)
+    log(f"oracle: {n_rot} rotations in {el:.1f}s on {threads} threads")
+    O.set_num_threads(1)
+    try:
+        n1, el1 = rotations(seconds, 2)
+    finally:
+        O.set_num_threads(threads)
+    log(f"oracle: {n1} rotations in {el1:.1f}s on 1 thread")
+    # the tiny configuration end to end
+    tp = S.params("tiny")
+    ot = O.Oracle(tp)
+    st = ot.keygen_secret(1)
+    level = ot.L - 1
+    x = S.uniform_slots(ot.n_slots, 0)
+    mat = S.uniform_matrix(64, 64, 0, 1 / 8)
+    diags = {}
+    for k in range(-63, 64):
+        d = np.zeros(ot.n_slots)
+        for j in range(ot.n_slots):
+            i = j % 64
+            if 0 <= i + k < 64:
+                d[j] = mat[i, i + k]
+        diags[k % ot.n_slots] = d
+    lt = ot.lt_create(diags, 16, level)
+    gks = {ot.galois_element(k): ot.keygen_galois(st, ot.galois_element(k), 5)
+           for k in ot.lt_required_steps(lt)}
+    rlk = ot.keygen_relin(st, 7)
+    ctt = ot.encrypt_sk(st, ot.encode(x, tp["scale"], level), 3)
+    t0 = time.perf_counter()
+    y = ot.rescale(ot.lt_apply(lt, ctt, gks))
+    y = ot.relinearize(ot.tensor(y, y), rlk)
+    tiny_s = time.perf_counter() - t0
+    log(f"oracle: tiny configuration end to end in {tiny_s:.2f}s")
+    return {"value": round(n_rot / el, 4), "unit": "rotations/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{n_rot} rotation(s) of one N=2^16, L=24 top-level ciphertext "
                       "(automorphism + hybrid key switching), not the full window step",
+            "single_thread_rotations_per_s": round(n1 / el1, 4),
+            "tiny_end_to_end_s": round(tiny_s, 3),
+            "tiny_sample": "N=2^12, L=3: (I_32 (x) M64) x by BSGS (127 diagonals, n1=16), "
+                           "rescale, square + relinearize",
             "cpu": _cpu_model()}
 
 

@@ -76,6 +76,7 @@ def _load():
         "ock_ks_inner": ([P, I, I, P, P, I, P, I, I, P, P], None),
         "ock_rescale": ([P, P, P, I, I], None),
         "ock_num_threads": ([], ctypes.c_int),
+        "ock_set_num_threads": ([ctypes.c_int], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -96,6 +97,11 @@ def _u64(x) -> np.ndarray:
 
 def num_threads() -> int:
     return _load().ock_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's limb loops from now on."""
+    _load().ock_set_num_threads(n)
 
 
 # ---------------------------------------------------------------------------

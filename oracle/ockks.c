@@ -409,6 +409,9 @@ void ock_rescale(const u64 *c, u64 *out, const u64 *q, uint32_t level, uint32_t 
 #ifdef _OPENMP
 #include <omp.h>
 int ock_num_threads(void) { return omp_get_max_threads(); }
+/* threads of the limb loops from now on (timing at one thread and at all) */
+void ock_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 #else
 int ock_num_threads(void) { return 1; }
+void ock_set_num_threads(int n) { (void)n; }
 #endif
