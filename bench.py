@@ -485,7 +485,7 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     torch.cuda.synchronize()
     batched_wps = batch * reps / (time.perf_counter() - t0)
     del outs_b, res_b, ims_b
-    noise = kernel_noise(ctx, prm, sk, top, base, ctx.VITAL_TAPS + plan.OUTPUTS,
+    noise = kernel_noise(ctx, prm, sk, top, base, VITAL_DEPTHS, ctx.VITAL_TAPS + plan.OUTPUTS,
                          lambda re_, im_: _flat(ctx.vital_eval_taps(plan, re_, im_, gks, rlk)),
                          lambda zz: HV.plain_stages(cfg, zz, ctx.n_slots),
                          [S.vital_window(1000 + i, cfg["frames"], cfg["bins"]) for i in range(3)])
@@ -546,7 +546,8 @@ def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     ms = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(windows)])
     classes = cfg["weights"][2].shape[0]
     logits = ctx.decode(ctx.decrypt(sk, out))[:classes].real
-    noise = kernel_noise(ctx, prm, sk, top, base, ctx.GESTURE_TAPS + ("FC3 logits",),
+    noise = kernel_noise(ctx, prm, sk, top, base, GESTURE_DEPTHS,
+                         ctx.GESTURE_TAPS + ("FC3 logits",),
                          lambda re_, im_: _flat(ctx.gesture_eval_taps(plan, re_, im_, gks, rlk)),
                          lambda xx: HG.plain_stages(cfg, xx, ctx.n_slots),
                          [S.gesture_window(2000 + i, cfg["frames"]) for i in range(3)])
@@ -774,16 +775,22 @@ def _flat(result):
     return list(taps) + (list(outs) if isinstance(outs, (list, tuple)) else [outs])
 
 
-def kernel_noise(ctx, prm, sk, top, base, names, run, plain, windows):
+# multiplicative depth (products on the path) of each tap and output
+VITAL_DEPTHS = [1, 1, 2, 3, 3, 4, 4, 4, 4, 7, 7, 8, 8, 9, 10, 3, 3, 11, 11]
+GESTURE_DEPTHS = [1, 1, 2, 3, 5, 6, 7, 9, 11]
+
+
+def kernel_noise(ctx, prm, sk, top, base, depths, names, run, plain, windows):
     """Per-kernel encryption noise, the method of section 5.2 (Table 3): the
     MSE and max |error| between each decoded intermediate of the encrypted
     pipeline and the same value from plaintext execution, cumulative after
     the preceding kernels, over the given windows (encrypted at level `top`,
-    evaluated from the plan's level `base`); depth = levels consumed."""
+    evaluated from the plan's level `base`), with the multiplicative depth
+    of the stage and the level its ciphertext ends at."""
     sq = [0.0] * len(names)
     cnt = [0] * len(names)
     mx = [0.0] * len(names)
-    depth = [0] * len(names)
+    level = [0] * len(names)
     for k, z in enumerate(windows):
         v = np.zeros(ctx.n_slots, dtype=np.complex128)
         v[: z.size] = np.asarray(z).reshape(-1)
@@ -796,9 +803,9 @@ def kernel_noise(ctx, prm, sk, top, base, names, run, plain, windows):
             sq[i] += float(np.sum(err ** 2))
             cnt[i] += len(slots)
             mx[i] = max(mx[i], float(np.max(np.abs(err))))
-            depth[i] = base - c.level
+            level[i] = c.level
     return [{"stage": n, "mse": float(f"{sq[i] / cnt[i]:.3e}"),
-             "max_abs_err": float(f"{mx[i]:.3e}"), "depth": depth[i]}
+             "max_abs_err": float(f"{mx[i]:.3e}"), "depth": depths[i], "level": level[i]}
             for i, n in enumerate(names)]
 
 

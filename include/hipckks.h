@@ -329,9 +329,11 @@ int hck_lt_destroy(hck_linear_transform *lt);
  * F frames x R range bins, packed frame-major (slot t R + r) into a real
  * and an imaginary ciphertext at level l0 (the batched packing of section
  * 3.3.1).  Stages (level reached):
- *   K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p by rotations R, 2R, ...
- *   K2  w = E^2 (l0-2); num_bin = sum_r w_r bin_index_r,
- *       den_bin = sum_r w_r bin_mask_r (rotations 1 .. R/2; l0-3)
+ *   K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p by rotations R, 2R, ... on a
+ *       copy of p dropped to level 3 (the bin branch needs two more levels
+ *       and one of headroom, so its rotations run on few limbs)
+ *   K2  w = E^2 (level 2); num_bin = sum_r w_r bin_index_r,
+ *       den_bin = sum_r w_r bin_mask_r (rotations 1 .. R/2; level 1)
  *   K4  m = p^2 (l0-2); I = sum_r m Re, Q = sum_r m Im per frame (l0-3)
  *   K5  (If, Qf) per band = FIR transform (I, Q) (BSGS, hck_lt_eval; l0-4)
  *   K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
@@ -349,7 +351,7 @@ int hck_lt_destroy(hck_linear_transform *lt);
  * G); the client's scalar divisions (section 3.3.4) give the target bin and
  * the two rates in beats per minute.
  * The operands are public plaintexts and transforms owned by the caller,
- * encoded for inputs at a base level l0 (bin_index at l0-2, the others as
+ * encoded for inputs at a base level l0 (fir_* at l0-3, the others as
  * above, at scale q_level so that a product keeps the ciphertext's scale).
  * Inputs may come at any level >= l0: the pipeline drops them to l0 first
  * (the circuit consumes only its depth), so a plan encoded at l0 = depth runs
@@ -360,7 +362,7 @@ typedef struct {
   uint32_t frames, bins;         /* F; R a power of two, pow2ceil(F) R <= N/2 */
   uint32_t taylor_order;         /* 1 or 3 */
   uint32_t lanes_resp, lanes_hr; /* DFT bins per band; 2 pow2ceil(max) <= R */
-  const hck_plaintext *bin_index, *bin_mask;                    /* l0-2 */
+  const hck_plaintext *bin_index, *bin_mask;                    /* level 2 */
   const hck_linear_transform *fir_resp, *fir_hr;                /* l0-3 */
   const hck_plaintext *third;                                   /* l0-5 (order 3) */
   const hck_plaintext *dft_re_resp, *dft_im_resp, *dft_re_hr, *dft_im_hr; /* l0-7 / l0-5 */

@@ -11,8 +11,11 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
 (input level l0):
 
   K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p[t, r] by rotations R, 2R, ...
-  K2  w = E^2 (l0-2); num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2
-      (index and mask plaintexts, rotations 1 .. R/2; l0-3)
+      on a copy of p dropped to level BIN_LEVEL (the bin branch needs only
+      two more levels, plus one of headroom at its end, so its rotations run
+      on few limbs)
+  K2  w = E^2 (BIN_LEVEL-1); num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2
+      (index and mask plaintexts, rotations 1 .. R/2; BIN_LEVEL-2)
   K4  m = p^2 (l0-2); I[t] = sum_r m Re, Q[t] = sum_r m Im (l0-3), left in
       slot t R
   K5  per band b: If_b = T_b I, Qf_b = T_b Q with the zero-padded Toeplitz
@@ -46,6 +49,10 @@ import numpy as np
 from . import Ciphertext, Oracle, Plaintext
 
 OUTPUTS = ("num_bin", "den_bin", "num_rates", "den_rates")
+
+# level of the energy sums of the bin branch (K1 -> K2): its outputs end at
+# level 1
+BIN_LEVEL = 3
 
 
 def _pow2_at_least(x: int) -> int:
@@ -129,7 +136,7 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
 def levels(cfg: dict, level0: int) -> dict:
     """Level of each operand for inputs at level0."""
     phi = level0 - (7 if cfg["taylor_order"] == 3 else 5)
-    return {"bin_index": level0 - 2, "bin_mask": level0 - 2, "fir": level0 - 3,
+    return {"bin_index": BIN_LEVEL - 1, "bin_mask": BIN_LEVEL - 1, "fir": level0 - 3,
             "third": level0 - 5, "dft": phi, "freq": phi - 3, "out": phi - 4}
 
 
@@ -192,9 +199,9 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     lay = layout(cfg, o.n_slots)
     r, t2 = lay.bins, lay.t2
     out = {}
-    # K1: energy per bin
+    # K1: energy per bin, summed on few limbs
     p = _square_sum(o, re, im, rlk)
-    e = _rotsum(o, p, r, t2, gks)
+    e = _rotsum(o, o.drop_level(p, BIN_LEVEL), r, t2, gks)
     # K2: soft power attention over bins (gamma = 2)
     w = _mul(o, e, e, rlk)
     out["num_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_index"])), 1, r, gks)

@@ -19,6 +19,10 @@ namespace {
     if (_rc) return _rc;  \
   } while (0)
 
+// level of the energy sums of the bin branch (K1 -> K2): the branch needs
+// two more levels and ends at level 1, so its rotations run on few limbs
+constexpr uint32_t kBinLevel = 3;
+
 uint32_t pow2_at_least(uint32_t x) {
   uint32_t p = 1;
   while (p < x) p *= 2;
@@ -182,12 +186,15 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
                               hck_ciphertext *const *taps) {
   TRY(check_plan(ctx, p));
   const uint32_t depth = p->taylor_order == 3 ? 11 : 9;
-  // the plan's operands are encoded for inputs at level l0 (bin_index at
-  // l0 - 2); inputs above it are dropped to it, since the circuit uses only
-  // its first depth + 1 primes anyway
-  const uint32_t l0 = p->bin_index->level + 2;
+  // the plan's operands are encoded for inputs at level l0 (the FIR
+  // transforms at l0 - 3, the bin branch's plaintexts at kBinLevel - 1);
+  // inputs above l0 are dropped to it, since the circuit uses only its first
+  // depth + 1 primes anyway
+  const uint32_t l0 = p->fir_resp->level + 3;
   if (l0 < depth || l0 >= ctx->L)
     return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
+  if (p->bin_index->level != kBinLevel - 1 || p->bin_mask->level != kBinLevel - 1)
+    return set_error(HCK_ELEVEL, "bin plaintexts must be encoded at level 2");
   for (uint32_t k = 0; k < n; k++) {
     if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
     if (!wk.gks[k] || !wk.rlk[k]) return set_error(HCK_EINVAL, "null key");
@@ -236,22 +243,23 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(hck_add(ctx, t[k], u[k], t[k]));
   }
   TRY(relin_rs(ctx, t, one, wk, pw));
-  for (uint32_t k = 0; k < n; k++) TRY(hck_drop_level(ctx, pw[k], pw[k]->level, e[k]));
+  for (uint32_t k = 0; k < n; k++) TRY(hck_drop_level(ctx, pw[k], kBinLevel, e[k]));
   TRY(rotsum(ctx, e, one, r, t2, wk, sc));
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 0, pw[k]));
     TRY(tap(k, 1, e[k]));
   }
-  // K2 over bins (gamma = 2) and K4 (P_phi = 2) share their squarings' level
-  std::vector<hck_ciphertext *> w = fresh(n), m = fresh(n), ts, outs;
+  // K2 over bins (gamma = 2) on the bin branch's level, K4 (P_phi = 2)
+  std::vector<hck_ciphertext *> w = fresh(n), m = fresh(n), ts, outs, tm;
   for (uint32_t k = 0; k < n; k++) {
-    hck_ciphertext *tw = sc.get(), *tm = sc.get();
+    hck_ciphertext *tw = sc.get(), *tp = sc.get();
     TRY(hck_mul(ctx, e[k], e[k], tw));
-    TRY(hck_mul(ctx, pw[k], pw[k], tm));
-    ts.insert(ts.end(), {tw, tm});
-    outs.insert(outs.end(), {w[k], m[k]});
+    TRY(hck_mul(ctx, pw[k], pw[k], tp));
+    ts.push_back(tw);
+    tm.push_back(tp);
   }
-  TRY(relin_rs(ctx, ts, two, wk, outs));
+  TRY(relin_rs(ctx, ts, one, wk, w));
+  TRY(relin_rs(ctx, tm, one, wk, m));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 2, w[k]));
   std::vector<hck_ciphertext *> it = fresh(n), qt = fresh(n);
   ts.clear();
@@ -269,9 +277,14 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   }
   TRY(relin_rs(ctx, ts, two, wk, outs));
   {
-    std::vector<hck_ciphertext *> chain;
-    for (uint32_t k = 0; k < n; k++) chain.insert(chain.end(), {O(k, 0), O(k, 1), it[k], qt[k]});
-    TRY(rotsum(ctx, chain, four, 1, (uint32_t)r, wk, sc));
+    // the bins' sums (low level) and K4's I and Q (high level): two chains
+    std::vector<hck_ciphertext *> bins, iq;
+    for (uint32_t k = 0; k < n; k++) {
+      bins.insert(bins.end(), {O(k, 0), O(k, 1)});
+      iq.insert(iq.end(), {it[k], qt[k]});
+    }
+    TRY(rotsum(ctx, bins, two, 1, (uint32_t)r, wk, sc));
+    TRY(rotsum(ctx, iq, two, 1, (uint32_t)r, wk, sc));
   }
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 3, it[k]));

@@ -13,10 +13,15 @@ def _next_pow2(x: int) -> int:
     return 1 << max(0, (int(x) - 1).bit_length())
 
 
+# level of the bin branch's energy sums (K1 -> K2); its plaintexts sit one
+# level below and its outputs end at level 1
+BIN_LEVEL = 3
+
+
 def plan_levels(taylor_order: int, level0: int) -> dict:
     """Level at which each operand is applied, for inputs at level0."""
     dft = level0 - (7 if taylor_order == 3 else 5)
-    return dict(bins=level0 - 2, fir=level0 - 3, third=level0 - 5, dft=dft, freq=dft - 3)
+    return dict(bins=BIN_LEVEL - 1, fir=level0 - 3, third=level0 - 5, dft=dft, freq=dft - 3)
 
 
 def operand_vectors(cfg: dict, n_slots: int) -> dict:

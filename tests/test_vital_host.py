@@ -29,6 +29,7 @@ def test_operand_vectors_match_oracle(order):
     hl = HV.plan_levels(order, 23)
     assert (hl["bins"], hl["fir"], hl["third"], hl["dft"], hl["freq"]) == (
         lv["bin_index"], lv["fir"], lv["third"], lv["dft"], lv["freq"])
+    assert HV.BIN_LEVEL == OV.BIN_LEVEL
 
 
 def test_band_lane_groups():
@@ -98,7 +99,7 @@ def test_oracle_pipeline_decodes_to_plain_circuit():
     out = OV.evaluate(o, cfg, ops, re, im, gks, rlk)
     want = OV.plain_slots(cfg, z, o.n_slots)
     for k in OV.OUTPUTS:
-        assert out[k].level == (l0 - 3 if k.endswith("bin") else 0)
+        assert out[k].level == (OV.BIN_LEVEL - 2 if k.endswith("bin") else 0)
         dec = o.decode(o.decrypt(s, out[k])).real
         for slot, v in want[k].items():
             assert abs(dec[slot] - v) < 1e-6 * max(1.0, abs(v)), (k, slot)
