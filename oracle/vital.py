@@ -141,9 +141,18 @@ def levels(cfg: dict, level0: int) -> dict:
 
 
 def fir_baby_step(cfg: dict) -> int:
-    """Baby step of the FIR transforms: about sqrt(taps) frames of R slots."""
-    taps = len(cfg["taps_resp"])
-    return cfg["bins"] * max(1, int(round(np.sqrt(taps))))
+    """Baby step of the FIR transforms, n1 frames of R slots: the n1 with the
+    fewest rotations for the evaluation's 2 inputs and 4 outputs, i.e.
+    2 (n1 - 1) baby steps plus 4 per nonzero giant step over the offsets
+    -h .. h (smallest n1 on ties)."""
+    h = (len(cfg["taps_resp"]) - 1) // 2
+    best, best_n1 = None, 1
+    for n1 in range(1, 2 * h + 2):
+        giants = h // n1 - (-h // n1)          # nonzero giants among floor(k / n1)
+        cost = 2 * (n1 - 1) + 4 * giants
+        if best is None or cost < best:
+            best, best_n1 = cost, n1
+    return cfg["bins"] * best_n1
 
 
 def encode_operands(o: Oracle, cfg: dict, level0: int, vecs: dict | None = None) -> dict:

@@ -74,9 +74,15 @@ def lane_group(cfg: dict) -> int:
 
 
 def fir_baby_step(cfg: dict) -> int:
-    """Baby step of the FIR transforms (offsets are multiples of R): about
-    sqrt(taps) frames."""
-    return cfg["bins"] * max(1, int(round(np.sqrt(len(cfg["taps_resp"])))))
+    """Baby step of the FIR transforms (offsets are multiples of R), in
+    frames: the one that needs the fewest rotations for the evaluation's 2
+    inputs (baby steps, hoisted) and 4 outputs (giant steps)."""
+    half = len(cfg["taps_resp"]) // 2
+    costs = []
+    for frames in range(1, 2 * half + 2):
+        lo, hi = -half // frames, half // frames     # giant indices floor(k / frames)
+        costs.append((2 * (frames - 1) + 4 * (hi - lo), frames))
+    return cfg["bins"] * min(costs)[1]
 
 
 def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
