@@ -323,6 +323,27 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
                 uint32_t flags);
 int hck_lt_destroy(hck_linear_transform *lt);
 
+/* ---- constants and polynomials ---------------------------------------------
+ * The constant slot vector `value` at `scale` and `level`: its only nonzero
+ * coefficient is m_0 = round(value * scale), half away from zero (a constant
+ * has that single coefficient; no FFT rounding enters).  |value * scale|
+ * must stay below 2^63 (HCK_EINVAL). */
+int hck_encode_const(hck_context *ctx, double value, double scale, uint32_t level,
+                     hck_plaintext **out);
+/* out = sum_k coeffs[k] x^k slot-wise, k = 0 .. degree (1 <= degree <= 64;
+ * some coeffs[k], k >= 1, nonzero), the building block of the polynomial
+ * approximations in section 3.3's pipelines (magnitudes, activations).
+ * Powers x^(2^j) by squaring, any other x^k = x^a x^(k-a) with a the largest
+ * power of two below k (the factor on the higher level dropped to the
+ * other's), each product relinearized and rescaled; every term with
+ * c_k != 0 is dropped to level l_f + 1, multiplied by the constant c_k
+ * encoded at scale s q_(l_f+1) / scale(x^k) and rescaled, so all land on
+ * level l_f = level(x) - ceil(log2 degree) - 1 at the input's scale s; they
+ * are added in increasing k, then c_0.  out must not alias x.
+ * Errors: HCK_ELEVEL (level(x) below ceil(log2 degree) + 1), HCK_EINVAL. */
+int hck_poly_eval(hck_context *ctx, const hck_ciphertext *x, const double *coeffs,
+                  uint32_t degree, const hck_switch_key *rlk, hck_ciphertext *out);
+
 /* ---- vital-sign pipeline -------------------------------------------------
  * The paper's encrypted vital-sign pipeline (section 3.3.3, example
  * pipelines: K1 -> K2 -> K4 -> K5 -> K7 -> K3 -> K1 -> K2) on one window of

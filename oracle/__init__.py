@@ -642,6 +642,53 @@ class Oracle:
         polys = np.stack([rescale_poly(x, self.q, c.level, self.log_n) for x in c.polys])
         return Ciphertext(polys, c.level - 1, c.scale / self.q[c.level])
 
+    # --- constants and polynomials (reading A28) --------------------------------
+    def encode_const(self, value: float, scale: float, level: int) -> Plaintext:
+        """The constant slot vector `value` at `scale`: its only nonzero
+        coefficient is m_0 = round(value * scale), half away from zero (a
+        constant has that single coefficient in the inverse canonical
+        embedding)."""
+        c = [0] * self.n
+        c[0] = int(_round_half_away(np.array([value * scale]))[0])
+        return self.plaintext_from_ints(c, level, scale)
+
+    def poly_eval(self, x: Ciphertext, coeffs, rlk) -> Ciphertext:
+        """sum_k coeffs[k] x^k, slot-wise (reading A28).
+
+        Powers: x^(2^j) by repeated squaring; any other x^k as x^a x^(k-a) with
+        a the largest power of two below k, the factor on the higher level
+        dropped to the other's level; every product relinearized and rescaled,
+        so x^k sits at level l - ceil(log2 k).  Terms: each x^k with a nonzero
+        coefficient, dropped to level l_f + 1 (l_f = l - ceil(log2 d) - 1),
+        times the constant coeffs[k] encoded at scale s q_(l_f+1) / scale(x^k)
+        (s: the input's scale), rescaled to level l_f; the terms are added in
+        increasing k, then coeffs[0] at the sum's scale."""
+        d = len(coeffs) - 1
+        if d < 1 or not any(coeffs[1:]):
+            raise ValueError("need a nonzero coefficient of degree >= 1")
+        depth = (d - 1).bit_length() + 1
+        if x.level < depth:
+            raise ValueError("not enough levels for this degree")
+        pw = {1: x}
+        for k in range(2, d + 1):
+            a = 1 << ((k - 1).bit_length() - 1)     # largest power of two below k
+            u, v = pw[a], pw[k - a]
+            lv = min(u.level, v.level)
+            u, v = self.drop_level(u, lv), self.drop_level(v, lv)
+            pw[k] = self.rescale(self.relinearize(self.tensor(u, v), rlk))
+        lf = x.level - depth
+        acc = None
+        for k in range(1, d + 1):
+            if coeffs[k] == 0:
+                continue
+            t = self.drop_level(pw[k], lf + 1)
+            pt = self.encode_const(coeffs[k], x.scale * self.q[lf + 1] / t.scale, lf + 1)
+            term = self.rescale(self.mul_plain(t, pt))
+            acc = term if acc is None else self.add(acc, term)
+        if coeffs[0] != 0:
+            acc = self.add_plain(acc, self.encode_const(coeffs[0], acc.scale, lf))
+        return acc
+
     # --- baby-step/giant-step linear transform (reading A18) ---------------------
     @staticmethod
     def bsgs_split(offset: int, n1: int):

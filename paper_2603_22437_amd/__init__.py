@@ -126,6 +126,8 @@ SIGNATURES = {
     "hck_encode_coeffs": ([_U32, _P, _P, _D, _P], _I),
     "hck_decode_residues": ([_U32, _P, _P, _U32, _D, _P, _P], _I),
     "hck_switch_key_import": ([_P, _P, _SZ, _PP], _I),
+    "hck_encode_const": ([_P, _D, _D, _U32, _PP], _I),
+    "hck_poly_eval": ([_P, _P, _P, _U32, _P, _P], _I),
     "hck_autotune_keyswitch": ([_P, _P, _U32, _U32, _P, _P], _I),
     "hck_set_keyswitch_cap": ([_P, _U32, _U32], _I),
     "hck_keyswitch_batch_limit": ([_P, _U32, _PU32], _I),
@@ -481,6 +483,16 @@ class Context:
         im = np.ascontiguousarray(z.imag, dtype=np.float64) if np.iscomplexobj(z) else None
         return self._new(capi.hck_encode, _ptr(re), _ptr(im) if im is not None else None,
                          len(re), scale, level, cls=Plaintext)
+
+    def encode_const(self, value: float, scale: float, level: int) -> Plaintext:
+        return self._new(capi.hck_encode_const, float(value), float(scale), level, cls=Plaintext)
+
+    def poly_eval(self, x, coeffs, rlk, out=None):
+        """sum_k coeffs[k] x^k slot-wise (hck_poly_eval)."""
+        c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+        out = self._out(out)
+        _check(capi.hck_poly_eval(self.h, x, _ptr(c), len(c) - 1, rlk, out))
+        return out
 
     def plaintext_import(self, res, level: int, scale: float) -> Plaintext:
         r = _u64(res)
@@ -839,9 +851,10 @@ class Server:
         im = _u64(im_words)
         n_out = 1 if self._keep.get(tenant, (SERVE_VITAL,))[0] == SERVE_GESTURE else 4
         out = np.empty(n_out * 2 * self.ctx.L * self.ctx.n, dtype=np.uint64)
-        self._out[request] = out
-        _check(capi.hck_server_submit(self.h, request, tenant, _ptr(re), _ptr(im), level, scale,
-                                      _ptr(out), out.size))
+        rc = capi.hck_server_submit(self.h, request, tenant, _ptr(re), _ptr(im), level, scale,
+                                    _ptr(out), out.size)
+        _check(rc)
+        self._out[request] = out    # the server writes it when the request completes
 
     def poll(self, timeout_ms: int = 0, cap: int = 64) -> list:
         """Completed requests: dicts with the result record and 'outputs', the

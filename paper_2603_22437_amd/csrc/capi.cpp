@@ -601,6 +601,20 @@ static void coeffs_to_residues(const hck_context *ctx, const std::vector<int64_t
   }
 }
 
+int hck_encode_const(hck_context *ctx, double value, double scale, uint32_t level,
+                     hck_plaintext **out) {
+  ENTER(ctx);
+  if (!out) return set_error(HCK_EINVAL, "null argument");
+  if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  const double v = value * scale;
+  if (!(std::fabs(v) < 9.2e18)) return set_error(HCK_EINVAL, "constant times scale beyond 2^63");
+  std::vector<int64_t> c(ctx->n, 0);
+  c[0] = (int64_t)std::copysign(std::floor(std::fabs(v) + 0.5), v);  // half away from zero
+  std::vector<uint64_t> res;
+  coeffs_to_residues(ctx, c, level, res);
+  return plaintext_from_rows(ctx, res.data(), level, scale, out);
+}
+
 int hck_encode(hck_context *ctx, const double *re, const double *im, uint32_t n_slots,
                double scale, uint32_t level, hck_plaintext **out) {
   ENTER(ctx);

@@ -95,6 +95,9 @@ CONFIGS: dict[str, dict] = {
                     dnum=3, scale=2.0 ** 50),
     "mix15": dict(log_n=15, q=[(60, 1, False), (50, 11, True)], p=[(60, 4, False)],
                   dnum=3, scale=2.0 ** 50),
+    # a small ring with 8 levels (polynomial evaluation up to degree 64)
+    "deep12": dict(log_n=12, q=[(60, 1, False), (50, 7, True)], p=[(60, 3, False)],
+                   dnum=3, scale=2.0 ** 50),
     # smallest and largest supported rings (edge cases of the parity tests)
     "edge11": dict(log_n=11, q=[(60, 1, False), (50, 2, True)], p=[(60, 1, False)],
                    dnum=3, scale=2.0 ** 40),

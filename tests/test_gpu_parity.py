@@ -594,3 +594,42 @@ def test_autotune_keyswitch_keeps_results_exact():
     assert ctx.keyswitch_batch_limit(5) == rule[5]
     with pytest.raises(H.HckError):
         ctx.set_keyswitch_cap(top + 1, 4)
+
+
+@pytest.mark.parametrize("coeffs", [
+    [0.3, -0.7],
+    [0.1, 0.5, -0.25, 0.125],
+    [0.0, 1.0, 0.0, -1 / 6, 0.0, 1 / 120, 0.0, -1 / 5040],
+    list(np.random.default_rng(5).uniform(-1, 1, 16)),
+])
+def test_poly_eval_matches_oracle(coeffs):
+    """hck_poly_eval bit-exact against the oracle's polynomial evaluation on
+    one encrypted input (N = 2^12, L = 8), and decoded against numpy."""
+    p = pair("deep12")
+    o = p.o
+    x = S.uniform_slots(o.n_slots, 3)
+    ct_o = o.encrypt_sk(p.s_o, o.encode(x, p.prm["scale"], o.L - 1), 11)
+    ct = p.ctx.ciphertext_import(ct_o.polys, ct_o.level, ct_o.scale)
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    want = o.poly_eval(ct_o, coeffs, o.keygen_relin(p.s_o, 7))
+    got = p.ctx.poly_eval(ct, coeffs, rlk)
+    assert got.level == want.level and got.scale == want.scale
+    assert np.array_equal(p.export(got), want.polys)
+    dec = p.ctx.decode(p.ctx.decrypt(p.sk, got)).real
+    np.testing.assert_allclose(dec, np.polynomial.polynomial.polyval(x, coeffs), rtol=0,
+                               atol=1e-6)
+
+
+def test_encode_const_and_poly_eval_errors():
+    p = pair("deep12")
+    pt = p.ctx.encode_const(-1.25, 2.0 ** 40, 3)
+    res, lvl, sc = p.ctx.plaintext_export(pt)
+    assert np.array_equal(res, p.o.encode_const(-1.25, 2.0 ** 40, 3).res)
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    ct, _ = p.rand_ct(2, 520)
+    with pytest.raises(H.HckError):       # depth 3 above level 2
+        p.ctx.poly_eval(ct, [0, 0, 0, 0, 1.0], rlk)
+    with pytest.raises(H.HckError):       # nothing of degree >= 1
+        p.ctx.poly_eval(ct, [1.0, 0.0], rlk)
+    with pytest.raises(H.HckError):
+        p.ctx.poly_eval(ct, [0.0, 1.0], rlk, out=ct)
