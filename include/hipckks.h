@@ -388,6 +388,11 @@ typedef struct {
   const hck_plaintext *third;                                   /* l0-5 (order 3) */
   const hck_plaintext *dft_re_resp, *dft_im_resp, *dft_re_hr, *dft_im_hr; /* l0-7 / l0-5 */
   const hck_plaintext *freq, *mask;                             /* dft level - 3 */
+  /* magnitude option (0: the paper's power): the bin estimate's energy sums
+   * the polynomial magnitude sum_k mag_coeffs[k] p^k ~ |z| of degree
+   * mag_degree (1 .. 15, evaluated by hck_poly_eval on p) instead of p */
+  uint32_t mag_degree;
+  const double *mag_coeffs; /* mag_degree + 1 coefficients, caller-owned */
 } hck_vital_plan;
 /* Rotation steps the pipeline needs Galois keys for (ascending; `cap` is the
  * capacity of steps[], *n receives the count; steps may be NULL). */

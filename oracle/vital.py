@@ -13,7 +13,9 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
   K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p[t, r] by rotations R, 2R, ...
       on a copy of p dropped to level BIN_LEVEL (the bin branch needs only
       two more levels, plus one of headroom at its end, so its rotations run
-      on few limbs)
+      on few limbs).  With the magnitude option (cfg["mag_coeffs"], reading
+      A29) the bin branch sums the polynomial magnitude poly(p) ~ |z|
+      (Oracle.poly_eval) instead of p
   K2  w = E^2 (BIN_LEVEL-1); num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2
       (index and mask plaintexts, rotations 1 .. R/2; BIN_LEVEL-2)
   K4  m = p^2 (l0-2); I[t] = sum_r m Re, Q[t] = sum_r m Im (l0-3), left in
@@ -208,9 +210,11 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     lay = layout(cfg, o.n_slots)
     r, t2 = lay.bins, lay.t2
     out = {}
-    # K1: energy per bin, summed on few limbs
+    # K1: energy per bin (of the power, or of the polynomial magnitude),
+    # summed on few limbs
     p = _square_sum(o, re, im, rlk)
-    e = _rotsum(o, o.drop_level(p, BIN_LEVEL), r, t2, gks)
+    src = o.poly_eval(p, cfg["mag_coeffs"], rlk) if cfg.get("mag_coeffs") else p
+    e = _rotsum(o, o.drop_level(src, BIN_LEVEL), r, t2, gks)
     # K2: soft power attention over bins (gamma = 2)
     w = _mul(o, e, e, rlk)
     out["num_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_index"])), 1, r, gks)
@@ -265,7 +269,10 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
     f, r = cfg["frames"], cfg["bins"]
     re, im = z.real, z.imag
     p = re ** 2 + im ** 2
-    e = p.sum(axis=0)
+    if cfg.get("mag_coeffs"):
+        e = np.polynomial.polynomial.polyval(p, cfg["mag_coeffs"]).sum(axis=0)
+    else:
+        e = p.sum(axis=0)
     w = e ** 2
     out = {"num_bin": float(np.sum(np.arange(r) * w) / f ** 2),
            "den_bin": float(np.sum(w) / f ** 2)}

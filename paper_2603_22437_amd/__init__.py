@@ -305,21 +305,28 @@ class VitalPlan(ctypes.Structure):
                 ("lanes_hr", ctypes.c_uint32)] + [
         (name, ctypes.c_void_p) for name in (
             "bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
-            "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")]
+            "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")] + [
+        ("mag_degree", ctypes.c_uint32), ("mag_coeffs", ctypes.c_void_p)]
 
     OPERANDS = ("bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
                 "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")
     OUTPUTS = ("num_bin", "den_bin", "num_rates", "den_rates")
 
     @classmethod
-    def build(cls, frames, bins, taylor_order, lanes_resp, lanes_hr, operands: dict):
+    def build(cls, frames, bins, taylor_order, lanes_resp, lanes_hr, operands: dict,
+              mag_coeffs=None):
         """operands: name -> Plaintext / LinearTransform handle (kept alive by
-        the plan object)."""
+        the plan object); mag_coeffs: the magnitude option's polynomial."""
         plan = cls(frames, bins, taylor_order, lanes_resp, lanes_hr)
         plan._keep = dict(operands)
         for name in cls.OPERANDS:
             h = operands.get(name)
             setattr(plan, name, h.h if h is not None else None)
+        if mag_coeffs is not None and len(mag_coeffs) > 1:
+            c = np.ascontiguousarray(np.asarray(mag_coeffs, dtype=np.float64))
+            plan._mag = c
+            plan.mag_degree = len(c) - 1
+            plan.mag_coeffs = c.ctypes.data
         return plan
 
 

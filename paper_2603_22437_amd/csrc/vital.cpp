@@ -71,6 +71,8 @@ int check_plan(const hck_context *ctx, const hck_vital_plan *p) {
       !p->dft_im_resp || !p->dft_re_hr || !p->dft_im_hr || !p->freq || !p->mask ||
       (p->taylor_order == 3 && !p->third))
     return set_error(HCK_EINVAL, "missing plan operand");
+  if (p->mag_degree > 15 || (p->mag_degree && !p->mag_coeffs))
+    return set_error(HCK_EINVAL, "magnitude polynomial: degree 0 .. 15 with coefficients");
   return HCK_OK;
 }
 
@@ -243,7 +245,15 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(hck_add(ctx, t[k], u[k], t[k]));
   }
   TRY(relin_rs(ctx, t, one, wk, pw));
-  for (uint32_t k = 0; k < n; k++) TRY(hck_drop_level(ctx, pw[k], kBinLevel, e[k]));
+  for (uint32_t k = 0; k < n; k++) {
+    if (p->mag_degree) {  // the polynomial magnitude ~ |z| instead of the power
+      hck_ciphertext *mg = sc.get();
+      TRY(hck_poly_eval(ctx, pw[k], p->mag_coeffs, p->mag_degree, wk.rlk[k], mg));
+      TRY(hck_drop_level(ctx, mg, kBinLevel, e[k]));
+    } else {
+      TRY(hck_drop_level(ctx, pw[k], kBinLevel, e[k]));
+    }
+  }
   TRY(rotsum(ctx, e, one, r, t2, wk, sc));
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 0, pw[k]));

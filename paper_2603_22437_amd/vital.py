@@ -106,7 +106,7 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
     for name in ("freq", "mask"):
         ops[name] = pt(name, lv["freq"])
     return VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"], len(cfg["k_resp"]),
-                           len(cfg["k_hr"]), ops)
+                           len(cfg["k_hr"]), ops, cfg.get("mag_coeffs"))
 
 
 def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
@@ -122,7 +122,10 @@ def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
     t = np.arange(F)
     frame0 = t * R
     p = re ** 2 + im ** 2
-    e = p.sum(axis=0)
+    # the bin estimate sums the power, or with the magnitude option the
+    # polynomial magnitude of the power
+    mag = np.polynomial.polynomial.polyval(p, cfg["mag_coeffs"]) if cfg.get("mag_coeffs") else p
+    e = mag.sum(axis=0)
     w = e ** 2
     m = p ** 2
     i_t, q_t = (m * re).sum(axis=1), (m * im).sum(axis=1)

@@ -225,9 +225,21 @@ def fir_bandpass(taps: int, lo_hz: float, hi_hz: float, fs: float) -> np.ndarray
     return h / gain
 
 
+def sqrt_poly(degree: int) -> list:
+    """Power-basis coefficients c_0 .. c_degree of the least-squares fit of
+    sqrt(x) on [0, 1] at 4 (degree + 1) Chebyshev points, through the origin
+    (c_0 = 0: a zero sample, e.g. a frame of zero padding, has magnitude 0):
+    the polynomial magnitude |z| = sqrt(|z|^2) of a unit-normalized window."""
+    k = np.arange(4 * (degree + 1))
+    x = 0.5 - 0.5 * np.cos((2 * k + 1) * np.pi / (2 * len(k)))
+    basis = np.stack([x ** j for j in range(1, degree + 1)], axis=1)
+    c, *_ = np.linalg.lstsq(basis, np.sqrt(x), rcond=None)
+    return [0.0] + list(c)
+
+
 def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
                           taps: int = 41, taylor_order: int = 3, fir_gain: float = 5.0,
-                          dft_gain: float = 10.0) -> dict:
+                          dft_gain: float = 10.0, magnitude_degree: int = 0) -> dict:
     """The vital-sign pipeline's public parameters (section 3.3.3 example
     pipeline): respiration 0.1-0.6 Hz and heart rate 0.8-2.5 Hz bands, the
     FIR taps of each band (times fir_gain), the Hann window of the phase DFT
@@ -235,11 +247,16 @@ def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
     k fps / frames) inside each band.  The two gains are normalization
     constants folded into public weights (as section 3.3.3 folds s^gamma / F
     into W^(1)) so that the cubic Taylor term and the spectra stay near 1 on
-    unit-normalized windows."""
+    unit-normalized windows.  With magnitude_degree > 0 the configuration also
+    carries the power-basis coefficients of a polynomial magnitude (sqrt_poly),
+    which the bin estimate's energy sums instead of the power."""
     res = fps / frames
     bands = {"resp": (0.1, 0.6), "hr": (0.8, 2.5)}
     cfg = dict(frames=frames, bins=bins, fps=fps, taylor_order=taylor_order,
                window=np.hanning(frames), dft_gain=dft_gain)
+    if magnitude_degree:
+        # the bin estimate's energy sums a polynomial magnitude instead of the power
+        cfg["mag_coeffs"] = sqrt_poly(magnitude_degree)
     for name, (lo, hi) in bands.items():
         cfg[f"taps_{name}"] = fir_gain * fir_bandpass(taps, lo, hi, fps)
         cfg[f"k_{name}"] = list(range(int(np.ceil(lo / res - 1e-9)),

@@ -1,7 +1,7 @@
 """The vital-sign pipeline on the GPU (hck_vital_eval).
 
 * N = 2^15, L = 12 (the third-order circuit's 11 levels): residues of all four
-  outputs bit-exact against the oracle's pipeline, both sides fed the same
+  outputs bit-exact (also with the polynomial magnitude option) against the oracle's pipeline, both sides fed the same
   integer operands (encoded once by the oracle) and the same encrypted
   window.
 * N = 2^16, L = 24 (the benchmark ring), with the library's own encoder:
@@ -29,17 +29,18 @@ def _import_plan(ctx, o, cfg, ops):
         else:
             handles[name] = ctx.plaintext_import(v.res, v.level, v.scale)
     return H.VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"],
-                             len(cfg["k_resp"]), len(cfg["k_hr"]), handles)
+                             len(cfg["k_resp"]), len(cfg["k_hr"]), handles,
+                             cfg.get("mag_coeffs"))
 
 
-@pytest.mark.parametrize("order", [3, 1])
-def test_vital_pipeline_matches_oracle(order):
+@pytest.mark.parametrize("order,magnitude", [(3, 0), (1, 0), (3, 8)])
+def test_vital_pipeline_matches_oracle(order, magnitude):
     prm = S.params("mix15")
     o = O.Oracle(prm)
     ctx = H.Context.from_params(prm)
     s_o = o.keygen_secret(1)
     sk = ctx.keygen_secret(1)
-    cfg = S.vital_pipeline_config(taylor_order=order)
+    cfg = S.vital_pipeline_config(taylor_order=order, magnitude_degree=magnitude)
     z = S.vital_window(1001, cfg["frames"], cfg["bins"])
     l0 = o.L - 1
     ops = OV.encode_operands(o, cfg, l0)
@@ -210,3 +211,29 @@ def test_vital_inputs_above_the_plan_level_are_dropped():
     low = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], 11), 102)
     with pytest.raises(H.HckError):   # below the plan's level
         ctx.vital_eval(plan, low, low, gks, rlk)
+
+
+def test_vital_magnitude_option_decodes_at_benchmark_ring():
+    """The magnitude option (the bin estimate sums a degree-8 polynomial
+    magnitude of the power) at N = 2^16 from plan level 12: outputs decode to
+    the same circuit on plaintext numbers, and the bin estimate stays on the
+    synthetic target."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config(magnitude_degree=8)
+    plan = HV.encode_plan(ctx, cfg, 12)
+    gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    z = S.vital_window(1006, cfg["frames"], cfg["bins"])
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: z.size] = z.reshape(-1)
+    top = len(prm["q"]) - 1
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 101)
+    got = ctx.vital_eval(plan, re, im, gks, rlk)
+    want = OV.plain_slots(cfg, z, ctx.n_slots)
+    num, den = (ctx.decode(ctx.decrypt(sk, got[i])).real[0] for i in (0, 1))
+    assert abs(num - want["num_bin"][0]) < 1e-3 and abs(den - want["den_bin"][0]) < 1e-3
+    target = int(np.argmax(np.abs(z).sum(axis=0)))
+    assert abs(num / den - target) < 1.0

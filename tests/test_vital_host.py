@@ -82,13 +82,15 @@ def test_plain_circuit_is_the_dsp_it_approximates():
 
 
 @pytest.mark.slow
-def test_oracle_pipeline_decodes_to_plain_circuit():
+@pytest.mark.parametrize("magnitude", [0, 8])
+def test_oracle_pipeline_decodes_to_plain_circuit(magnitude):
     """The oracle pipeline at N = 2^15 (L = 12: the 11 levels of the third
-    order circuit) decodes to the plaintext circuit's numbers."""
+    order circuit) decodes to the plaintext circuit's numbers, also with the
+    polynomial magnitude option."""
     prm = S.params("mix15")
     o = O.Oracle(prm)
     s = o.keygen_secret(1)
-    cfg = S.vital_pipeline_config()
+    cfg = S.vital_pipeline_config(magnitude_degree=magnitude)
     z = S.vital_window(1000, cfg["frames"], cfg["bins"])
     l0 = o.L - 1
     ops = OV.encode_operands(o, cfg, l0)
@@ -118,3 +120,16 @@ def test_library_plain_stages_end_in_the_oracle_outputs():
         assert sorted(int(s) for s in slots) == sorted(want[name])
         for s, v in zip(slots, vals):
             assert abs(v - want[name][int(s)]) <= 1e-12 * max(1.0, abs(v)), name
+
+
+def test_sqrt_polynomial_is_the_magnitude():
+    """The magnitude option's polynomial approximates sqrt on [0, 1] (the
+    power of a unit-normalized window), passes through the origin (zero
+    padding adds nothing to a sum of magnitudes) and keeps its coefficients
+    small enough to encode as constants at scale 2^50."""
+    c = S.sqrt_poly(8)
+    assert c[0] == 0.0
+    x = np.linspace(0, 1, 2001)
+    err = np.abs(np.polynomial.polynomial.polyval(x, c) - np.sqrt(x))
+    assert err.max() < 0.04 and err[x >= 0.05].max() < 0.02
+    assert max(abs(v) for v in c) * 2.0 ** 50 < 2.0 ** 63
