@@ -353,8 +353,9 @@ int hck_poly_eval(hck_context *ctx, const hck_ciphertext *x, const double *coeff
  *   K1  p = Re^2 + Im^2 (l0-1); E_r = sum_t p by rotations R, 2R, ... on a
  *       copy of p dropped to level 3 (the bin branch needs two more levels
  *       and one of headroom, so its rotations run on few limbs)
- *   K2  w = E^2 (level 2); num_bin = sum_r w_r bin_index_r,
- *       den_bin = sum_r w_r bin_mask_r (rotations 1 .. R/2; level 1)
+ *   K2  w = E^gamma by squarings (level 2; gamma below); num_bin =
+ *       sum_r w_r bin_index_r, den_bin = sum_r w_r bin_mask_r (rotations
+ *       1 .. R/2; level 1)
  *   K4  m = p^2 (l0-2); I = sum_r m Re, Q = sum_r m Im per frame (l0-3)
  *   K5  (If, Qf) per band = FIR transform (I, Q) (BSGS, hck_lt_eval; l0-4)
  *   K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
@@ -364,7 +365,7 @@ int hck_poly_eval(hck_context *ctx, const hck_ciphertext *x, const double *coeff
  *       lane 0, heart rate from lane G.  Each band's dphi is copied into its
  *       lanes by rotations -1, -2, ...; the bands' weighted products are
  *       added and summed over frames at once (rotations R, 2R, ...): X
- *   K1  P = Re X^2 + Im X^2;  K2  S = P^2;  num = sum S freq, den = sum S
+ *   K1  P = Re X^2 + Im X^2;  K2  S = P^gamma;  num = sum S freq, den = sum S
  *       mask over each lane group (rotations 1 .. G/2; output level: dft
  *       level - 4).
  * Outputs: out[0] num_bin, out[1] den_bin (value in slot 0), out[2]
@@ -393,6 +394,11 @@ typedef struct {
    * mag_degree (1 .. 15, evaluated by hck_poly_eval on p) instead of p */
   uint32_t mag_degree;
   const double *mag_coeffs; /* mag_degree + 1 coefficients, caller-owned */
+  /* soft-attention exponent of both K2 stages (Eq. soft_power_weight):
+   * 2 (0 also means 2) or 4, by one or two squarings; 4 adds one level to
+   * the main chain (freq and mask at dft level - 4, outputs one level
+   * lower) and one to the bin branch (its energy sums at level 4) */
+  uint32_t gamma;
 } hck_vital_plan;
 /* Rotation steps the pipeline needs Galois keys for (ascending; `cap` is the
  * capacity of steps[], *n receives the count; steps may be NULL). */

@@ -16,8 +16,10 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
       on few limbs).  With the magnitude option (cfg["mag_coeffs"], reading
       A29) the bin branch sums the polynomial magnitude poly(p) ~ |z|
       (Oracle.poly_eval) instead of p
-  K2  w = E^2 (BIN_LEVEL-1); num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2
-      (index and mask plaintexts, rotations 1 .. R/2; BIN_LEVEL-2)
+  K2  w = E^gamma by log2(gamma) squarings (level 2; gamma = cfg["gamma"],
+      2 by default, 4 for sharper selection, Eq. soft_power_weight);
+      num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2 (index and mask
+      plaintexts, rotations 1 .. R/2; level 1)
   K4  m = p^2 (l0-2); I[t] = sum_r m Re, Q[t] = sum_r m Im (l0-3), left in
       slot t R
   K5  per band b: If_b = T_b I, Qf_b = T_b Q with the zero-padded Toeplitz
@@ -35,7 +37,7 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
       rotations R, 2R, ... (one chain for the real, one for the imaginary
       part)
   K1  P = Re X^2 + Im X^2
-  K2  S = P^2; num = sum_c f_c S_c, den = sum_c S_c over each lane group
+  K2  S = P^gamma; num = sum_c f_c S_c, den = sum_c S_c over each lane group
       (f_c the bin frequency in beats per minute; rotations 1 .. G/2)
 
 Outputs: num_bin, den_bin (value in slot 0; the target bin r^ = num / den),
@@ -52,9 +54,21 @@ from . import Ciphertext, Oracle, Plaintext
 
 OUTPUTS = ("num_bin", "den_bin", "num_rates", "den_rates")
 
-# level of the energy sums of the bin branch (K1 -> K2): its outputs end at
-# level 1
+# level of the energy sums of the bin branch (K1 -> K2) for gamma = 2: its
+# outputs end at level 1 (bin_level adds a level per further squaring)
 BIN_LEVEL = 3
+
+
+def log2_gamma(cfg: dict) -> int:
+    g = cfg.get("gamma", 2)
+    if g not in (2, 4):
+        raise ValueError("gamma must be 2 or 4")
+    return g.bit_length() - 1
+
+
+def bin_level(cfg: dict) -> int:
+    """Level of the bin branch's energy sums: w = E^gamma lands on level 2."""
+    return 2 + log2_gamma(cfg)
 
 
 def _pow2_at_least(x: int) -> int:
@@ -138,8 +152,9 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
 def levels(cfg: dict, level0: int) -> dict:
     """Level of each operand for inputs at level0."""
     phi = level0 - (7 if cfg["taylor_order"] == 3 else 5)
-    return {"bin_index": BIN_LEVEL - 1, "bin_mask": BIN_LEVEL - 1, "fir": level0 - 3,
-            "third": level0 - 5, "dft": phi, "freq": phi - 3, "out": phi - 4}
+    sharp = phi - 2 - log2_gamma(cfg)          # S = P^gamma
+    return {"bin_index": 2, "bin_mask": 2, "fir": level0 - 3,
+            "third": level0 - 5, "dft": phi, "freq": sharp, "out": sharp - 1}
 
 
 def fir_baby_step(cfg: dict) -> int:
@@ -214,9 +229,11 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     # summed on few limbs
     p = _square_sum(o, re, im, rlk)
     src = o.poly_eval(p, cfg["mag_coeffs"], rlk) if cfg.get("mag_coeffs") else p
-    e = _rotsum(o, o.drop_level(src, BIN_LEVEL), r, t2, gks)
-    # K2: soft power attention over bins (gamma = 2)
-    w = _mul(o, e, e, rlk)
+    e = _rotsum(o, o.drop_level(src, bin_level(cfg)), r, t2, gks)
+    # K2: soft power attention over bins, w = E^gamma by squarings
+    w = e
+    for _ in range(log2_gamma(cfg)):
+        w = _mul(o, w, w, rlk)
     out["num_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_index"])), 1, r, gks)
     out["den_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_mask"])), 1, r, gks)
     # K4: soft I/Q (P_phi = 2)
@@ -257,7 +274,9 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     x_im = _rotsum(o, x_im, r, t2, gks)
     # K1 on the spectrum, K2: sharpening and weighted frequency averages
     pw = _square_sum(o, x_re, x_im, rlk)
-    sh = _mul(o, pw, pw, rlk)
+    sh = pw
+    for _ in range(log2_gamma(cfg)):
+        sh = _mul(o, sh, sh, rlk)
     out["num_rates"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops["freq"])), 1, lay.group, gks)
     out["den_rates"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops["mask"])), 1, lay.group, gks)
     return out
@@ -273,7 +292,7 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
         e = np.polynomial.polynomial.polyval(p, cfg["mag_coeffs"]).sum(axis=0)
     else:
         e = p.sum(axis=0)
-    w = e ** 2
+    w = e ** cfg.get("gamma", 2)
     out = {"num_bin": float(np.sum(np.arange(r) * w) / f ** 2),
            "den_bin": float(np.sum(w) / f ** 2)}
     m = p ** 2
@@ -306,7 +325,7 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
         ws = win.sum() / cfg["dft_gain"]
         xr = np.array([np.sum(win * np.cos(2 * np.pi * k * t / f) * dphi) for k in ks]) / ws
         xi = np.array([-np.sum(win * np.sin(2 * np.pi * k * t / f) * dphi) for k in ks]) / ws
-        s = (xr ** 2 + xi ** 2) ** 2
+        s = (xr ** 2 + xi ** 2) ** cfg.get("gamma", 2)
         fk = 60.0 * ks * cfg["fps"] / f
         out[f"num_{band}"] = float(np.sum(fk * s))
         out[f"den_{band}"] = float(np.sum(s))

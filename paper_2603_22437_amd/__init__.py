@@ -306,7 +306,8 @@ class VitalPlan(ctypes.Structure):
         (name, ctypes.c_void_p) for name in (
             "bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
             "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")] + [
-        ("mag_degree", ctypes.c_uint32), ("mag_coeffs", ctypes.c_void_p)]
+        ("mag_degree", ctypes.c_uint32), ("mag_coeffs", ctypes.c_void_p),
+        ("gamma", ctypes.c_uint32)]
 
     OPERANDS = ("bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
                 "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")
@@ -314,10 +315,12 @@ class VitalPlan(ctypes.Structure):
 
     @classmethod
     def build(cls, frames, bins, taylor_order, lanes_resp, lanes_hr, operands: dict,
-              mag_coeffs=None):
+              mag_coeffs=None, gamma: int = 2):
         """operands: name -> Plaintext / LinearTransform handle (kept alive by
-        the plan object); mag_coeffs: the magnitude option's polynomial."""
+        the plan object); mag_coeffs: the magnitude option's polynomial;
+        gamma: the soft-attention exponent (2 or 4)."""
         plan = cls(frames, bins, taylor_order, lanes_resp, lanes_hr)
+        plan.gamma = gamma
         plan._keep = dict(operands)
         for name in cls.OPERANDS:
             h = operands.get(name)

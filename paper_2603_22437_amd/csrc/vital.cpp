@@ -19,9 +19,12 @@ namespace {
     if (_rc) return _rc;  \
   } while (0)
 
-// level of the energy sums of the bin branch (K1 -> K2): the branch needs
-// two more levels and ends at level 1, so its rotations run on few limbs
-constexpr uint32_t kBinLevel = 3;
+// The bin branch (K1 -> K2) needs log2(gamma) + 1 more levels and ends at
+// level 1, so its energy sums run on few limbs: at level 2 + log2(gamma), its
+// plaintexts at level 2.
+constexpr uint32_t kBinPlainLevel = 2;
+
+uint32_t log2_gamma(const hck_vital_plan *p) { return p->gamma == 4 ? 2 : 1; }
 
 uint32_t pow2_at_least(uint32_t x) {
   uint32_t p = 1;
@@ -71,6 +74,8 @@ int check_plan(const hck_context *ctx, const hck_vital_plan *p) {
       !p->dft_im_resp || !p->dft_re_hr || !p->dft_im_hr || !p->freq || !p->mask ||
       (p->taylor_order == 3 && !p->third))
     return set_error(HCK_EINVAL, "missing plan operand");
+  if (p->gamma != 0 && p->gamma != 2 && p->gamma != 4)
+    return set_error(HCK_EINVAL, "gamma must be 2 or 4");
   if (p->mag_degree > 15 || (p->mag_degree && !p->mag_coeffs))
     return set_error(HCK_EINVAL, "magnitude polynomial: degree 0 .. 15 with coefficients");
   return HCK_OK;
@@ -152,6 +157,26 @@ int relin_rs(hck_context *ctx, const std::vector<hck_ciphertext *> &ts,
   return HCK_OK;
 }
 
+// outs[i] = ins[i]^(2^times) by repeated squaring, every square relinearized
+// (key-switched together) and rescaled
+int square_rs(hck_context *ctx, const std::vector<hck_ciphertext *> &ins, uint32_t times,
+              const std::vector<uint32_t> &win, const WindowKeys &wk,
+              const std::vector<hck_ciphertext *> &outs, Scratch &sc) {
+  std::vector<hck_ciphertext *> cur = ins;
+  for (uint32_t r = 0; r < times; r++) {
+    std::vector<hck_ciphertext *> ts, dst = r + 1 == times ? outs : std::vector<hck_ciphertext *>();
+    for (size_t i = 0; i < cur.size(); i++) {
+      hck_ciphertext *t = sc.get();
+      TRY(hck_mul(ctx, cur[i], cur[i], t));
+      ts.push_back(t);
+      if (r + 1 < times) dst.push_back(sc.get());
+    }
+    TRY(relin_rs(ctx, ts, win, wk, dst));
+    cur = dst;
+  }
+  return HCK_OK;
+}
+
 // out = (a pt) rescaled
 int mulpt_rs(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
              hck_ciphertext *out) {
@@ -187,15 +212,17 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
                               uint32_t n, const WindowKeys &wk, hck_ciphertext *const *out,
                               hck_ciphertext *const *taps) {
   TRY(check_plan(ctx, p));
-  const uint32_t depth = p->taylor_order == 3 ? 11 : 9;
+  const uint32_t sq = log2_gamma(p);  // squarings of each K2 stage
+  const uint32_t depth = (p->taylor_order == 3 ? 11 : 9) + sq - 1;
+  const uint32_t bin_level = kBinPlainLevel + sq;
   // the plan's operands are encoded for inputs at level l0 (the FIR
-  // transforms at l0 - 3, the bin branch's plaintexts at kBinLevel - 1);
+  // transforms at l0 - 3, the bin branch's plaintexts at level 2);
   // inputs above l0 are dropped to it, since the circuit uses only its first
   // depth + 1 primes anyway
   const uint32_t l0 = p->fir_resp->level + 3;
   if (l0 < depth || l0 >= ctx->L)
     return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
-  if (p->bin_index->level != kBinLevel - 1 || p->bin_mask->level != kBinLevel - 1)
+  if (p->bin_index->level != kBinPlainLevel || p->bin_mask->level != kBinPlainLevel)
     return set_error(HCK_ELEVEL, "bin plaintexts must be encoded at level 2");
   for (uint32_t k = 0; k < n; k++) {
     if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
@@ -249,9 +276,9 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     if (p->mag_degree) {  // the polynomial magnitude ~ |z| instead of the power
       hck_ciphertext *mg = sc.get();
       TRY(hck_poly_eval(ctx, pw[k], p->mag_coeffs, p->mag_degree, wk.rlk[k], mg));
-      TRY(hck_drop_level(ctx, mg, kBinLevel, e[k]));
+      TRY(hck_drop_level(ctx, mg, bin_level, e[k]));
     } else {
-      TRY(hck_drop_level(ctx, pw[k], kBinLevel, e[k]));
+      TRY(hck_drop_level(ctx, pw[k], bin_level, e[k]));
     }
   }
   TRY(rotsum(ctx, e, one, r, t2, wk, sc));
@@ -259,17 +286,16 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     TRY(tap(k, 0, pw[k]));
     TRY(tap(k, 1, e[k]));
   }
-  // K2 over bins (gamma = 2) on the bin branch's level, K4 (P_phi = 2)
+  // K2 over bins, w = E^gamma by squarings on the bin branch's level, and
+  // K4 (P_phi = 2)
   std::vector<hck_ciphertext *> w = fresh(n), m = fresh(n), ts, outs, tm;
   for (uint32_t k = 0; k < n; k++) {
-    hck_ciphertext *tw = sc.get(), *tp = sc.get();
-    TRY(hck_mul(ctx, e[k], e[k], tw));
+    hck_ciphertext *tp = sc.get();
     TRY(hck_mul(ctx, pw[k], pw[k], tp));
-    ts.push_back(tw);
     tm.push_back(tp);
   }
-  TRY(relin_rs(ctx, ts, one, wk, w));
   TRY(relin_rs(ctx, tm, one, wk, m));
+  TRY(square_rs(ctx, e, sq, one, wk, w, sc));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 2, w[k]));
   std::vector<hck_ciphertext *> it = fresh(n), qt = fresh(n);
   ts.clear();
@@ -418,13 +444,7 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
   }
   TRY(relin_rs(ctx, ts, one, wk, pspec));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 13, pspec[k]));
-  ts.clear();
-  for (uint32_t k = 0; k < n; k++) {
-    hck_ciphertext *t1 = sc.get();
-    TRY(hck_mul(ctx, pspec[k], pspec[k], t1));
-    ts.push_back(t1);
-  }
-  TRY(relin_rs(ctx, ts, one, wk, sh));
+  TRY(square_rs(ctx, pspec, sq, one, wk, sh, sc));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 14, sh[k]));
   std::vector<hck_ciphertext *> chain;
   for (uint32_t k = 0; k < n; k++) {

@@ -13,15 +13,17 @@ def _next_pow2(x: int) -> int:
     return 1 << max(0, (int(x) - 1).bit_length())
 
 
-# level of the bin branch's energy sums (K1 -> K2); its plaintexts sit one
-# level below and its outputs end at level 1
+# level of the bin branch's energy sums (K1 -> K2) for gamma = 2; one more per
+# further squaring, so that its plaintexts sit at level 2 and its outputs end
+# at level 1
 BIN_LEVEL = 3
 
 
-def plan_levels(taylor_order: int, level0: int) -> dict:
+def plan_levels(taylor_order: int, level0: int, gamma: int = 2) -> dict:
     """Level at which each operand is applied, for inputs at level0."""
     dft = level0 - (7 if taylor_order == 3 else 5)
-    return dict(bins=BIN_LEVEL - 1, fir=level0 - 3, third=level0 - 5, dft=dft, freq=dft - 3)
+    squarings = {2: 1, 4: 2}[gamma]
+    return dict(bins=2, fir=level0 - 3, third=level0 - 5, dft=dft, freq=dft - 2 - squarings)
 
 
 def operand_vectors(cfg: dict, n_slots: int) -> dict:
@@ -90,7 +92,7 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
     is applied, at scale q_level (a product then keeps the ciphertext scale)."""
     from . import VitalPlan
     vec = operand_vectors(cfg, ctx.n // 2) if vectors is None else vectors
-    lv = plan_levels(cfg["taylor_order"], level0)
+    lv = plan_levels(cfg["taylor_order"], level0, cfg.get("gamma", 2))
     q = ctx.q
 
     def pt(name, level):
@@ -106,7 +108,7 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
     for name in ("freq", "mask"):
         ops[name] = pt(name, lv["freq"])
     return VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"], len(cfg["k_resp"]),
-                           len(cfg["k_hr"]), ops, cfg.get("mag_coeffs"))
+                           len(cfg["k_hr"]), ops, cfg.get("mag_coeffs"), cfg.get("gamma", 2))
 
 
 def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
@@ -126,7 +128,8 @@ def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
     # polynomial magnitude of the power
     mag = np.polynomial.polynomial.polyval(p, cfg["mag_coeffs"]) if cfg.get("mag_coeffs") else p
     e = mag.sum(axis=0)
-    w = e ** 2
+    gamma = cfg.get("gamma", 2)
+    w = e ** gamma
     m = p ** 2
     i_t, q_t = (m * re).sum(axis=1), (m * im).sum(axis=1)
     out = [(np.arange(F * R), p.reshape(-1)), (np.arange(R), e), (np.arange(R), w),
@@ -166,7 +169,7 @@ def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
     out += dphis
     lanes, xr, xi, fq = (np.asarray(v) for v in (lanes, xr, xi, fq))
     pw = xr ** 2 + xi ** 2
-    sh = pw ** 2
+    sh = pw ** gamma
     out += [(lanes, xr), (lanes, xi), (lanes, pw), (lanes, sh)]
     n_resp = len(cfg["k_resp"])
     two = np.array([0, G])

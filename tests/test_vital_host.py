@@ -25,6 +25,10 @@ def test_operand_vectors_match_oracle(order):
         else:
             np.testing.assert_allclose(a[k], b[k], rtol=0, atol=1e-15, err_msg=k)
     assert HV.fir_baby_step(cfg) == OV.fir_baby_step(cfg)
+    for g in (2, 4):
+        lg = OV.levels(dict(cfg, gamma=g), 23)
+        hg = HV.plan_levels(order, 23, g)
+        assert (hg["bins"], hg["freq"]) == (lg["bin_index"], lg["freq"])
     lv = OV.levels(cfg, 23)
     hl = HV.plan_levels(order, 23)
     assert (hl["bins"], hl["fir"], hl["third"], hl["dft"], hl["freq"]) == (
@@ -82,15 +86,15 @@ def test_plain_circuit_is_the_dsp_it_approximates():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("magnitude", [0, 8])
-def test_oracle_pipeline_decodes_to_plain_circuit(magnitude):
+@pytest.mark.parametrize("magnitude,order,gamma", [(0, 3, 2), (8, 3, 2), (0, 1, 4)])
+def test_oracle_pipeline_decodes_to_plain_circuit(magnitude, order, gamma):
     """The oracle pipeline at N = 2^15 (L = 12: the 11 levels of the third
     order circuit) decodes to the plaintext circuit's numbers, also with the
     polynomial magnitude option."""
     prm = S.params("mix15")
     o = O.Oracle(prm)
     s = o.keygen_secret(1)
-    cfg = S.vital_pipeline_config(magnitude_degree=magnitude)
+    cfg = S.vital_pipeline_config(magnitude_degree=magnitude, taylor_order=order, gamma=gamma)
     z = S.vital_window(1000, cfg["frames"], cfg["bins"])
     l0 = o.L - 1
     ops = OV.encode_operands(o, cfg, l0)
@@ -100,8 +104,9 @@ def test_oracle_pipeline_decodes_to_plain_circuit(magnitude):
     re, im = OV.encrypt_window(o, s, z, l0, prm["scale"], 100)
     out = OV.evaluate(o, cfg, ops, re, im, gks, rlk)
     want = OV.plain_slots(cfg, z, o.n_slots)
+    depth = (11 if order == 3 else 9) + (gamma.bit_length() - 2)
     for k in OV.OUTPUTS:
-        assert out[k].level == (OV.BIN_LEVEL - 2 if k.endswith("bin") else 0)
+        assert out[k].level == (1 if k.endswith("bin") else l0 - depth)
         dec = o.decode(o.decrypt(s, out[k])).real
         for slot, v in want[k].items():
             assert abs(dec[slot] - v) < 1e-6 * max(1.0, abs(v)), (k, slot)
