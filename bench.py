@@ -485,6 +485,21 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     torch.cuda.synchronize()
     batched_wps = batch * reps / (time.perf_counter() - t0)
     del outs_b, res_b, ims_b
+    # the paper's two FIR backends: Toeplitz BSGS (above) against one hoisted
+    # rotation per tap
+    rcfg = dict(cfg, fir_backend="rotation")
+    rplan = HV.encode_plan(ctx, rcfg, base)
+    rgks = ctx.keygen_rotation(sk, ctx.vital_required_steps(rplan), 5)
+    ctx.vital_eval(rplan, re, im, rgks, rlk, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fir_windows = 20
+    for _ in range(fir_windows):
+        ctx.vital_eval(rplan, re, im, rgks, rlk, outs)
+    torch.cuda.synchronize()
+    rotation_fir_ms = (time.perf_counter() - t0) * 1e3 / fir_windows
+    del rgks, rplan
+    ctx.vital_eval(plan, re, im, gks, rlk, outs)
     noise = kernel_noise(ctx, prm, sk, top, base, VITAL_DEPTHS, ctx.VITAL_TAPS + plan.OUTPUTS,
                          lambda re_, im_: _flat(ctx.vital_eval_taps(plan, re_, im_, gks, rlk)),
                          lambda zz: HV.plain_stages(cfg, zz, ctx.n_slots),
@@ -498,6 +513,7 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "p99_ms": round(float(np.percentile(ms, 99)), 3),
            "windows_per_s": round(windows / wall, 2),
            "batched_8_windows_per_s": round(batched_wps, 2),
+           "rotation_fir_backend_ms_per_window": round(rotation_fir_ms, 3),
            "taylor_order": cfg["taylor_order"], "input_level": top, "plan_level": base,
            "rotation_keys": len(gks), "target_bin_true": target,
            "target_bin_est": round(float(got[0][0] / got[1][0]), 4),

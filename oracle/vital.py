@@ -157,11 +157,18 @@ def levels(cfg: dict, level0: int) -> dict:
             "third": level0 - 5, "dft": phi, "freq": sharp, "out": sharp - 1}
 
 
-def fir_baby_step(cfg: dict) -> int:
-    """Baby step of the FIR transforms, n1 frames of R slots: the n1 with the
-    fewest rotations for the evaluation's 2 inputs and 4 outputs, i.e.
-    2 (n1 - 1) baby steps plus 4 per nonzero giant step over the offsets
-    -h .. h (smallest n1 on ties)."""
+def fir_baby_step(cfg: dict, n_slots: int | None = None) -> int:
+    """Baby step of the FIR transforms in slots.  The Toeplitz backend (the
+    default): n1 frames of R slots, the n1 with the fewest rotations for the
+    evaluation's 2 inputs and 4 outputs, i.e. 2 (n1 - 1) baby steps plus 4
+    per nonzero giant step over the offsets -h .. h (smallest n1 on ties).
+    The rotation backend (cfg["fir_backend"] == "rotation", section 3.3's
+    alternative): n1 = N/2 slots, so every tap is its own (hoisted) rotation
+    of the input and there is no giant step."""
+    if cfg.get("fir_backend", "toeplitz") == "rotation":
+        if n_slots is None:
+            raise ValueError("the rotation backend needs the slot count")
+        return n_slots
     h = (len(cfg["taps_resp"]) - 1) // 2
     best, best_n1 = None, 1
     for n1 in range(1, 2 * h + 2):
@@ -180,7 +187,7 @@ def encode_operands(o: Oracle, cfg: dict, level0: int, vecs: dict | None = None)
     ops = {"bin_index": enc("bin_index", lv["bin_index"]),
            "bin_mask": enc("bin_mask", lv["bin_mask"]),
            "third": enc("third", lv["third"])}
-    n1 = fir_baby_step(cfg)
+    n1 = fir_baby_step(cfg, o.n_slots)
     for band in ("resp", "hr"):
         ops[f"fir_{band}"] = o.lt_create(vecs[f"fir_{band}"], n1, lv["fir"])
         for part in ("dft_re", "dft_im"):

@@ -75,10 +75,16 @@ def lane_group(cfg: dict) -> int:
     return _next_pow2(max(len(cfg["k_resp"]), len(cfg["k_hr"])))
 
 
-def fir_baby_step(cfg: dict) -> int:
-    """Baby step of the FIR transforms (offsets are multiples of R), in
-    frames: the one that needs the fewest rotations for the evaluation's 2
-    inputs (baby steps, hoisted) and 4 outputs (giant steps)."""
+def fir_baby_step(cfg: dict, n_slots: int | None = None) -> int:
+    """Baby step of the FIR transforms in slots (offsets are multiples of R).
+    Toeplitz backend (default): the number of frames that needs the fewest
+    rotations for the evaluation's 2 inputs (baby steps, hoisted) and 4
+    outputs (giant steps).  Rotation backend (cfg["fir_backend"] ==
+    "rotation"): all N/2 slots, every tap a hoisted rotation of the input."""
+    if cfg.get("fir_backend", "toeplitz") == "rotation":
+        if n_slots is None:
+            raise ValueError("the rotation backend needs the slot count")
+        return n_slots
     half = len(cfg["taps_resp"]) // 2
     costs = []
     for frames in range(1, 2 * half + 2):
@@ -100,7 +106,7 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
 
     ops = {"bin_index": pt("bin_index", lv["bins"]), "bin_mask": pt("bin_mask", lv["bins"]),
            "third": pt("third", lv["third"])}
-    n1 = fir_baby_step(cfg)
+    n1 = fir_baby_step(cfg, ctx.n_slots)
     for band in ("resp", "hr"):
         ops["fir_" + band] = ctx.lt_create(vec["fir_" + band], n1, lv["fir"])
         for name in ("dft_re_", "dft_im_"):

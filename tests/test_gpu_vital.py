@@ -1,8 +1,8 @@
 """The vital-sign pipeline on the GPU (hck_vital_eval).
 
 * N = 2^15, L = 12 (the third-order circuit's 11 levels): residues of all four
-  outputs bit-exact (also with the polynomial magnitude option and with
-  gamma = 4) against the oracle's pipeline, both sides fed the same
+  outputs bit-exact (also with the polynomial magnitude option, with
+  gamma = 4 and with the rotation-based FIR backend) against the oracle's pipeline, both sides fed the same
   integer operands (encoded once by the oracle) and the same encrypted
   window.
 * N = 2^16, L = 24 (the benchmark ring), with the library's own encoder:
@@ -34,14 +34,17 @@ def _import_plan(ctx, o, cfg, ops):
                              cfg.get("mag_coeffs"), cfg.get("gamma", 2))
 
 
-@pytest.mark.parametrize("order,magnitude,gamma", [(3, 0, 2), (1, 0, 2), (3, 8, 2), (1, 0, 4)])
-def test_vital_pipeline_matches_oracle(order, magnitude, gamma):
+@pytest.mark.parametrize("order,magnitude,gamma,fir", [
+    (3, 0, 2, "toeplitz"), (1, 0, 2, "toeplitz"), (3, 8, 2, "toeplitz"), (1, 0, 4, "toeplitz"),
+    (3, 0, 2, "rotation")])
+def test_vital_pipeline_matches_oracle(order, magnitude, gamma, fir):
     prm = S.params("mix15")
     o = O.Oracle(prm)
     ctx = H.Context.from_params(prm)
     s_o = o.keygen_secret(1)
     sk = ctx.keygen_secret(1)
-    cfg = S.vital_pipeline_config(taylor_order=order, magnitude_degree=magnitude, gamma=gamma)
+    cfg = S.vital_pipeline_config(taylor_order=order, magnitude_degree=magnitude, gamma=gamma,
+                                  fir_backend=fir)
     z = S.vital_window(1001, cfg["frames"], cfg["bins"])
     l0 = o.L - 1
     ops = OV.encode_operands(o, cfg, l0)

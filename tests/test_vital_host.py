@@ -25,6 +25,8 @@ def test_operand_vectors_match_oracle(order):
         else:
             np.testing.assert_allclose(a[k], b[k], rtol=0, atol=1e-15, err_msg=k)
     assert HV.fir_baby_step(cfg) == OV.fir_baby_step(cfg)
+    rot = dict(cfg, fir_backend="rotation")
+    assert HV.fir_baby_step(rot, n_slots) == OV.fir_baby_step(rot, n_slots) == n_slots
     for g in (2, 4):
         lg = OV.levels(dict(cfg, gamma=g), 23)
         hg = HV.plan_levels(order, 23, g)
