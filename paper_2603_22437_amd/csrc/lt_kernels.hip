@@ -13,17 +13,174 @@
 // groups; then each of its 4 waves takes giant groups w, w + 4, ... (GW at a
 // time, round robin), one coefficient per lane, and streams those groups'
 // diagonals once,
-// keeping GW x O x 2 sums in 128-bit registers that are reduced by one
-// Montgomery REDC at the end (and at flushes, see below).  The terms enter as
-// a sign per (transform, input, output); a negative one multiplies by the
-// negated diagonal (q - w).
+// keeping GW x O x 2 sums in registers that are reduced by one Montgomery
+// REDC at the end (and at flushes, see below).  A limb whose prime is below
+// 2^52 keeps each sum in three carry-free 64-bit columns (four 32-bit
+// multiply-adds per product); a wider prime keeps it as one 128-bit value.
+// The terms enter as a sign per (transform, input, output); a negative one
+// multiplies by the negated diagonal (q - w).
 #include "internal.h"
 
 namespace hck {
 
 namespace {
 
-template <int GW, int O, int I>
+// One inner sum in a 128-bit register pair: any q < 2^62.  The count of
+// products between reductions stays below 2^64 / q (the REDC input bound).
+struct WideSum {
+  u128 v;
+  __device__ __forceinline__ void set(uint64_t r) {
+    v.lo = r;
+    v.hi = 0;
+  }
+  __device__ __forceinline__ void mac(uint64_t w, uint64_t x) { mac_wide(v, w, x); }
+  __device__ __forceinline__ u128 total() const { return v; }
+  static __device__ __forceinline__ uint64_t max_products(uint64_t q) { return ~0ull / q - 1; }
+};
+
+// One inner sum in three 64-bit columns, for q < 2^52.  Both factors split
+// at bit 26 into halves below 2^26, so each of the four 32 x 32-bit partial
+// products is below 2^52 and lands, without carry handling, in the column of
+// weight 1, 2^26 or 2^52: four v_mad_u64_u32 per product in place of a
+// 128-bit multiply and add.  The middle column takes two partial products
+// per product, so up to 2^11 products fit.
+struct ColSum {
+  static constexpr uint32_t kLow = (1u << 26) - 1;
+  uint64_t c0, c1, c2;
+  __device__ __forceinline__ void set(uint64_t r) {
+    c0 = r;
+    c1 = c2 = 0;
+  }
+  __device__ __forceinline__ void mac(uint64_t w, uint64_t x) {
+    const uint32_t w0 = (uint32_t)w & kLow, w1 = (uint32_t)(w >> 26);
+    const uint32_t x0 = (uint32_t)x & kLow, x1 = (uint32_t)(x >> 26);
+    c0 += (uint64_t)w0 * x0;
+    c1 += (uint64_t)w0 * x1;
+    c1 += (uint64_t)w1 * x0;
+    c2 += (uint64_t)w1 * x1;
+  }
+  // c0 + c1 2^26 + c2 2^52 as a 128-bit value
+  __device__ __forceinline__ u128 total() const {
+    const uint64_t a = c1 << 26, b = c2 << 52;
+    u128 t;
+    t.lo = c0 + a;
+    uint64_t carry = t.lo < a;
+    t.lo += b;
+    carry += t.lo < b;
+    t.hi = (c1 >> 38) + (c2 >> 12) + carry;
+    return t;
+  }
+  static __device__ __forceinline__ uint64_t max_products(uint64_t q) {
+    return min<uint64_t>(~0ull / q - 1, 2047);
+  }
+};
+
+// The giant groups of one wave over the staged baby rotations xs; Sum is the
+// accumulator kind, GW the groups a wave carries at a time.
+template <class Sum, int GW, int O, int I>
+__device__ __forceinline__ void lt_sums_wave(const LtSumArgs &a, const uint64_t *xs,
+                                             const ModConst &m, size_t base, int n, int wave,
+                                             int lane) {
+  constexpr int C = kLtCoeffs;
+  const int nb = (int)a.nb;
+  const size_t off = base + lane;
+  // each baby step adds up to max_terms products to one sum.  A flush
+  // reduces a sum to r in [0, q) and restarts it from r 2^64 mod q, which
+  // REDC maps back to r.
+  const int flush_b = (int)max<uint64_t>(1, Sum::max_products(m.q) / a.max_terms);
+  // wave w takes giant groups w, w + 4, w + 8, ... (GW at a time), so the
+  // four waves of a workgroup stay within one group of each other
+  for (int g0 = wave; g0 < (int)a.ng; g0 += 4 * GW) {
+    Sum acc[GW][O][2];
+#pragma unroll
+    for (int gi = 0; gi < GW; gi++)
+#pragma unroll
+      for (int o = 0; o < O; o++)
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+          uint64_t r = 0;
+          if (a.accumulate && g0 + 4 * gi < (int)a.ng && o < (int)a.n_out)
+            r = shoup(a.sums[((size_t)(g0 + 4 * gi) * a.n_out + o) * 2 * a.ps + p * a.ps + off],
+                      m.r64, m.r64_shoup, m.q);
+          acc[gi][o][p].set(r);
+        }
+    // an absent diagonal reads a row of zeros, so every step issues all its
+    // loads without branches before any product; addresses are wave-uniform
+    // bases (scalar) plus the lane
+    auto load_rows = [&](uint64_t(&w)[GW][kLtLts], int b) {
+#pragma unroll
+      for (int l = 0; l < kLtLts; l++)
+#pragma unroll
+        for (int gi = 0; gi < GW; gi++) {
+          const int g = g0 + 4 * gi;
+          const bool on = g < (int)a.ng && ((a.present[l][g] >> b) & 1u);
+          const uint64_t *row =
+              on ? a.grid[l] +
+                       (size_t)(a.gmap[l][g] * (int)a.grid_nb[l] + a.bmap[l][b]) * a.grid_rows[l] * n +
+                       base
+                 : a.zero + base;
+          w[gi][l] = row[lane];
+        }
+    };
+    int since = 0;
+    for (int b = 0; b < nb; b++) {
+      uint64_t w[GW][kLtLts];
+      load_rows(w, b);
+      uint64_t x[I][2];
+#pragma unroll
+      for (int in = 0; in < I; in++)
+#pragma unroll
+        for (int p = 0; p < 2; p++)
+          x[in][p] = in < (int)a.n_in ? xs[((in * nb + b) * 2 + p) * C + lane] : 0;
+      // a negative term multiplies by q - w (a transform's terms share w)
+#pragma unroll
+      for (int l = 0; l < kLtLts; l++) {
+        bool neg = false;
+#pragma unroll
+        for (int ii = 0; ii < I; ii++)
+#pragma unroll
+          for (int oo = 0; oo < O; oo++) neg = neg || a.coef[l][ii][oo] < 0;
+#pragma unroll
+        for (int gi = 0; gi < GW; gi++) {
+          const uint64_t wn = neg ? m.q - w[gi][l] : 0;
+#pragma unroll
+          for (int ii = 0; ii < I; ii++)
+#pragma unroll
+            for (int oo = 0; oo < O; oo++) {
+              const int c = a.coef[l][ii][oo];
+              if (c == 0) continue;
+              const uint64_t ws = c < 0 ? wn : w[gi][l];
+              acc[gi][oo][0].mac(ws, x[ii][0]);
+              acc[gi][oo][1].mac(ws, x[ii][1]);
+            }
+        }
+      }
+      if (++since == flush_b && b + 1 < nb) {
+        since = 0;
+#pragma unroll
+        for (int gi = 0; gi < GW; gi++)
+#pragma unroll
+          for (int o = 0; o < O; o++)
+#pragma unroll
+            for (int p = 0; p < 2; p++)
+              acc[gi][o][p].set(
+                  shoup(redc(acc[gi][o][p].total(), m.q, m.qinv), m.r64, m.r64_shoup, m.q));
+      }
+    }
+#pragma unroll
+    for (int gi = 0; gi < GW; gi++)
+#pragma unroll
+      for (int o = 0; o < O; o++)
+        if (g0 + 4 * gi < (int)a.ng && o < (int)a.n_out) {
+          uint64_t *dst = a.sums + ((size_t)(g0 + 4 * gi) * a.n_out + o) * 2 * a.ps + off;
+          dst[0] = redc(acc[gi][o][0].total(), m.q, m.qinv);
+          dst[a.ps] = redc(acc[gi][o][1].total(), m.q, m.qinv);
+        }
+  }
+}
+
+// GW / GWN: giant groups a wave carries at a time with 128-bit / column sums
+template <int GW, int GWN, int O, int I>
 __global__ __launch_bounds__(256, 4) void k_lt_sums(LtSumArgs a, const ModConst *__restrict__ mc,
                                                  int n) {
   constexpr int C = kLtCoeffs;
@@ -44,108 +201,17 @@ __global__ __launch_bounds__(256, 4) void k_lt_sums(LtSumArgs a, const ModConst 
   // compiler keep the giant tables, branches and diagonal addresses scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64), lane = threadIdx.x % 64;
   const ModConst m = mc[limb];
-  const size_t off = base + lane;
-  // products of values below q accumulate safely while their count stays
-  // below 2^64 / q (the REDC input bound); each baby step adds up to
-  // max_terms products to one sum.  A flush reduces a sum to r in [0, q) and
-  // restarts it from r 2^64 mod q, which REDC maps back to r.
-  const uint64_t per_flush = ~0ull / m.q - 1;
-  const int flush_b = (int)max<uint64_t>(1, per_flush / a.max_terms);
-  // wave w takes giant groups w, w + 4, w + 8, ... (GW at a time), so the
-  // four waves of a workgroup stay within one group of each other
-  for (int g0 = wave; g0 < (int)a.ng; g0 += 4 * GW) {
-    u128 acc[GW][O][2];
-#pragma unroll
-    for (int gi = 0; gi < GW; gi++)
-#pragma unroll
-      for (int o = 0; o < O; o++)
-#pragma unroll
-        for (int p = 0; p < 2; p++) {
-          acc[gi][o][p].lo = acc[gi][o][p].hi = 0;
-          if (a.accumulate && g0 + 4 * gi < (int)a.ng && o < (int)a.n_out)
-            acc[gi][o][p].lo =
-                shoup(a.sums[((size_t)(g0 + 4 * gi) * a.n_out + o) * 2 * a.ps + p * a.ps + off],
-                      m.r64, m.r64_shoup, m.q);
-        }
-    // an absent diagonal reads a row of zeros, so every step issues all its
-    // loads without branches before any product; addresses are wave-uniform
-    // bases (scalar) plus the lane
-    int since = 0;
-    for (int b = 0; b < nb; b++) {
-      uint64_t x[I][2];
-#pragma unroll
-      for (int in = 0; in < I; in++)
-#pragma unroll
-        for (int p = 0; p < 2; p++)
-          x[in][p] = in < (int)a.n_in ? xs[((in * nb + b) * 2 + p) * C + lane] : 0;
-      uint64_t w[GW][kLtLts];
-#pragma unroll
-      for (int l = 0; l < kLtLts; l++) {
-#pragma unroll
-        for (int gi = 0; gi < GW; gi++) {
-          const int g = g0 + 4 * gi;
-          const bool on = g < (int)a.ng && ((a.present[l][g] >> b) & 1u);
-          const uint64_t *row =
-              on ? a.grid[l] +
-                       (size_t)(a.gmap[l][g] * (int)a.grid_nb[l] + a.bmap[l][b]) * a.grid_rows[l] * n +
-                       base
-                 : a.zero + base;
-          w[gi][l] = row[lane];
-        }
-      }
-      // a negative term multiplies by q - w (a transform's terms share w)
-#pragma unroll
-      for (int l = 0; l < kLtLts; l++) {
-        bool neg = false;
-#pragma unroll
-        for (int ii = 0; ii < I; ii++)
-#pragma unroll
-          for (int oo = 0; oo < O; oo++) neg = neg || a.coef[l][ii][oo] < 0;
-#pragma unroll
-        for (int gi = 0; gi < GW; gi++) {
-          const uint64_t wn = neg ? m.q - w[gi][l] : 0;
-#pragma unroll
-          for (int ii = 0; ii < I; ii++)
-#pragma unroll
-            for (int oo = 0; oo < O; oo++) {
-              const int c = a.coef[l][ii][oo];
-              if (c == 0) continue;
-              const uint64_t ws = c < 0 ? wn : w[gi][l];
-              mac_wide(acc[gi][oo][0], ws, x[ii][0]);
-              mac_wide(acc[gi][oo][1], ws, x[ii][1]);
-            }
-        }
-      }
-      if (++since == flush_b && b + 1 < nb) {
-        since = 0;
-#pragma unroll
-        for (int gi = 0; gi < GW; gi++)
-#pragma unroll
-          for (int o = 0; o < O; o++)
-#pragma unroll
-            for (int p = 0; p < 2; p++) {
-              acc[gi][o][p].lo =
-                  shoup(redc(acc[gi][o][p], m.q, m.qinv), m.r64, m.r64_shoup, m.q);
-              acc[gi][o][p].hi = 0;
-            }
-      }
-    }
-#pragma unroll
-    for (int gi = 0; gi < GW; gi++)
-#pragma unroll
-      for (int o = 0; o < O; o++)
-        if (g0 + 4 * gi < (int)a.ng && o < (int)a.n_out) {
-          uint64_t *dst = a.sums + ((size_t)(g0 + 4 * gi) * a.n_out + o) * 2 * a.ps + off;
-          dst[0] = redc(acc[gi][o][0], m.q, m.qinv);
-          dst[a.ps] = redc(acc[gi][o][1], m.q, m.qinv);
-        }
-  }
+  // the limb's modulus is uniform across the workgroup
+  if (m.q < (1ull << 52))
+    lt_sums_wave<ColSum, GWN, O, I>(a, xs, m, base, n, wave, lane);
+  else
+    lt_sums_wave<WideSum, GW, O, I>(a, xs, m, base, n, wave, lane);
 }
 
-template <int GW, int O, int I>
+template <int GW, int GWN, int O, int I>
 void launch(hck_context *ctx, const LtSumArgs &a, uint32_t nq) {
   const size_t lds = (size_t)a.n_in * a.nb * 2 * kLtCoeffs * sizeof(uint64_t);
-  k_lt_sums<GW, O, I><<<dim3(ctx->n / kLtCoeffs, nq), 256, lds, ctx->stream>>>(a, ctx->d_mod,
+  k_lt_sums<GW, GWN, O, I><<<dim3(ctx->n / kLtCoeffs, nq), 256, lds, ctx->stream>>>(a, ctx->d_mod,
                                                                                ctx->n);
 }
 
@@ -174,11 +240,11 @@ int launch_lt_sums(hck_context *ctx, const LtSumArgs &a, uint32_t level) {
                8.0 * words * (diags + babies + 2.0 * a.ng * a.n_out * (a.accumulate ? 2 : 1)),
                words * macs);
   if (a.n_out <= 1 && a.n_in <= 2)
-    launch<8, 1, 2>(ctx, a, nq);
+    launch<8, 6, 1, 2>(ctx, a, nq);
   else if (a.n_out <= 2 && a.n_in <= 2)
-    launch<5, 2, 2>(ctx, a, nq);
+    launch<5, 3, 2, 2>(ctx, a, nq);
   else
-    launch<2, kLtOut, kLtIn>(ctx, a, nq);
+    launch<2, 1, kLtOut, kLtIn>(ctx, a, nq);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
