@@ -59,8 +59,8 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  const int li = blockIdx.y;  // limb i (modulus i)
-  const uint32_t b = blockIdx.z;
+  const int li = blockIdx.z;  // limb i (modulus i)
+  const uint32_t b = blockIdx.y;
   const uint64_t q = mc[li].q;
   const size_t roff = (size_t)li * G::N;
   const uint64_t *d = kb.d[b];
@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  const uint32_t t = blockIdx.y;
-  const uint32_t b = blockIdx.z;
+  const uint32_t t = blockIdx.z;
+  const uint32_t b = blockIdx.y;
   const uint32_t mi = t < kg.nq ? t : kg.L + (t - kg.nq);
   const ModConst m = mc[mi];
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
@@ -208,8 +208,8 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  const uint32_t p = blockIdx.y / kg.nq, li = blockIdx.y % kg.nq;
-  const uint32_t b = blockIdx.z;
+  const uint32_t p = blockIdx.z & 1, li = blockIdx.z >> 1;
+  const uint32_t b = blockIdx.y;
   const uint64_t *slot = ws + (size_t)b * kg.slot_rows * G::N;
   const uint64_t q = mc[li].q;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
@@ -297,7 +297,7 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
   uint64_t *ws = ws_ks(ctx);
   int rc;
   timing_begin(ctx, "ks_intt_gather", 16.0 * N * nq * nb, 0.5 * N * B * nq * nb);
-  k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nq, nb), kNttThreads, 0, ctx->stream>>>(
+  k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nb, nq), kNttThreads, 0, ctx->stream>>>(
       ws, kb, kg, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup);
   timing_end(ctx);
   RowScale sc;
@@ -405,7 +405,7 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
   for (uint32_t b = 0; b < nb; b++) adds += (kb.add0[b] ? nq : 0) + (kb.add1[b] ? nq : 0);
   timing_begin(ctx, "ks_moddown_tail", 8.0 * N * (3.0 * 2 * nq * nb + adds),
                N * (0.5 * B + 1) * 2 * nq * nb);
-  k_moddown_contig_tail<LOGN><<<dim3(GB::BLOCKS, 2 * nq, nb), kNttThreads, 0, ctx->stream>>>(
+  k_moddown_contig_tail<LOGN><<<dim3(GB::BLOCKS, nb, 2 * nq), kNttThreads, 0, ctx->stream>>>(
       ws, kb, pinv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
@@ -432,7 +432,7 @@ int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level) {
   timing_begin(ctx, "ks_contig_inner",
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * keys),
                N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
-  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne, nb), kNttThreads, 0, ctx->stream>>>(
+  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(
       ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
   return ks_moddown<LOGN>(ctx, kb, kg);
@@ -511,7 +511,7 @@ int ks_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *const *
   timing_begin(ctx, "ks_contig_inner",
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * nb),
                N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
-  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, ne, nb), kNttThreads, 0, ctx->stream>>>(
+  k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(
       ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
