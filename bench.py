@@ -567,12 +567,37 @@ def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
                          lambda re_, im_: _flat(ctx.gesture_eval_taps(plan, re_, im_, gks, rlk)),
                          lambda xx: HG.plain_stages(cfg, xx, ctx.n_slots),
                          [S.gesture_window(2000 + i, cfg["frames"]) for i in range(3)])
+    # per-frame packing (section 3.3.2): one ciphertext pair per frame, the
+    # same plan; a few windows, each timed with HIP events
+    frames = HG.pack_frames(x, ctx.n_slots)
+    res_f = [ctx.encrypt_sk(sk, ctx.encode(fv.real, prm["scale"], top), 400 + 2 * f)
+             for f, fv in enumerate(frames)]
+    ims_f = [ctx.encrypt_sk(sk, ctx.encode(fv.imag, prm["scale"], top), 401 + 2 * f)
+             for f, fv in enumerate(frames)]
+    out_f = ctx.ciphertext()
+    ctx.gesture_eval_frames(plan, res_f, ims_f, gks, rlk, out_f)
+    torch.cuda.synchronize()
+    pf_windows = 5
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(pf_windows + 1)]
+    evs[0].record(stream)
+    for k in range(pf_windows):
+        ctx.gesture_eval_frames(plan, res_f, ims_f, gks, rlk, out_f)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    ms_f = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(pf_windows)])
+    logits_f = ctx.decode(ctx.decrypt(sk, out_f))[:classes].real
+    per_frame = {"windows": pf_windows, "input_ciphertexts": 2 * len(frames),
+                 "p50_ms": round(float(np.percentile(ms_f, 50)), 3),
+                 "vs_batched_latency": round(float(np.percentile(ms_f, 50)
+                                                   / np.percentile(ms, 50)), 2),
+                 "decoded_max_abs_diff_vs_batched": float(np.abs(logits_f - logits).max())}
     res = {"windows": windows, "p50_ms": round(float(np.percentile(ms, 50)), 3),
            "p99_ms": round(float(np.percentile(ms, 99)), 3),
            "windows_per_s": round(windows / wall, 2), "rotation_keys": len(gks),
            "input_level": top, "plan_level": base,
            "frames": cfg["frames"], "classes": classes,
-           "predicted_class": int(np.argmax(logits)), "kernel_noise": noise}
+           "predicted_class": int(np.argmax(logits)), "per_frame_packing": per_frame,
+           "kernel_noise": noise}
     log(f"gesture pipeline: {res}")
     return res
 

@@ -480,6 +480,25 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *plan,
                           const hck_ciphertext *re, const hck_ciphertext *im,
                           const hck_galois_keys *gks, const hck_switch_key *rlk,
                           hck_ciphertext *out, hck_ciphertext *const *taps);
+/* The same pipeline on per-frame packing (section 3.3.2, the layout before
+ * batching: one ciphertext pair per frame).  re[f], im[f] (f < n_frames) hold
+ * frame f's R range bins x D chirps in slots r D + c and zeros in every other
+ * slot (the caller's packing; nonzero slots there would enter the frame sum).
+ * Each pair runs K3 -> K1 -> K6 -> K2 on its own, exactly as one frame block
+ * of hck_gesture_eval; the n_frames features are added in frame order, and
+ * rotations R D, 2 R D, ..., N/4 copy the sum into every block of R D slots
+ * before the FC network, as the batched packing leaves it.  So the logits
+ * decode to those of hck_gesture_eval on the same frames packed together,
+ * at the same level (l0-11), for 2 n_frames input ciphertexts instead of 2.
+ * plan->frames is not used beyond the layout check; any 1 <= n_frames <=
+ * HCK_GESTURE_MAX_FRAMES frames are accepted.  All frames share one level (at
+ * least l0; higher ones are dropped to l0) and one scale.
+ * Errors: HCK_EINVAL, HCK_ELEVEL, HCK_ESCALE, HCK_ENOKEY. */
+#define HCK_GESTURE_MAX_FRAMES 4096
+int hck_gesture_eval_frames(hck_context *ctx, const hck_gesture_plan *plan,
+                            const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                            uint32_t n_frames, const hck_galois_keys *gks,
+                            const hck_switch_key *rlk, hck_ciphertext *out);
 
 /* ---- device calibration ---------------------------------------------------
  * Rate of 64-bit Shoup modular products (a w mod q for a fixed w, the product
@@ -488,6 +507,8 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *plan,
  * in dependent chains, 8 per thread) on the context's stream.  A measured
  * integer ceiling for the evaluation kernels, reported beside the HBM
  * bandwidth.  Errors: HCK_EINVAL, HCK_EDEVICE. */
+int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s);
+
 /* Autotuner of the key-switch schedule (the batching of section 3.3's
  * rotations on this chip): for each of n_levels levels it times key
  * switches of `count` zero ciphertexts at that level with a zero key.  Each
@@ -503,7 +524,6 @@ int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_
  * restores the built-in rule), and reads the size in force. */
 int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap);
 int hck_keyswitch_batch_limit(const hck_context *ctx, uint32_t level, uint32_t *cap);
-int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s);
 
 /* ---- kernel timing --------------------------------------------------------
  * With timing on, every kernel launch is bracketed by HIP events on the

@@ -171,11 +171,10 @@ def _mul(o, a, b, rlk):
     return o.rescale(o.relinearize(o.tensor(a, b), rlk))
 
 
-def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gks: dict,
-             rlk) -> Ciphertext:
-    rd = cfg["bins"] * cfg["chirps"]
-    t2 = _pow2_at_least(cfg["frames"])
-    h1 = cfg["weights"][0].shape[0]
+def _front_end(o: Oracle, ops: dict, re: Ciphertext, im: Ciphertext, gks: dict,
+               rlk) -> Ciphertext:
+    """K3 -> K1 -> K6 -> K2 on one ciphertext pair: the feature P P^4 of
+    every frame block it holds."""
     terms = [(ops["dft_c"], 0, 0, 1), (ops["dft_s"], 1, 0, -1), (ops["dft_s"], 0, 1, 1),
              (ops["dft_c"], 1, 1, 1)]
     d_re, d_im = (o.rescale(c) for c in o.lt_eval([re, im], terms, gks, 2, hoist=True,
@@ -184,11 +183,24 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     p = o.rescale(o.mul_plain(p, ops["notch"]))
     p2 = _mul(o, p, p, rlk)
     p4 = _mul(o, p2, p2, rlk)
-    feat = _mul(o, o.drop_level(p, p4.level), p4, rlk)
+    return _mul(o, o.drop_level(p, p4.level), p4, rlk)
+
+
+def _spread(o: Oracle, cfg: dict, feat: Ciphertext, gks: dict) -> Ciphertext:
+    """Adds the blocks of R D slots cyclically (rotations R D, 2 R D, ...): each
+    block ends with the sum of all blocks."""
+    rd = cfg["bins"] * cfg["chirps"]
     s = rd
-    while s < rd * t2:
+    while s < o.n_slots:
         feat = o.add(feat, o.rotate(feat, s, gks))
         s *= 2
+    return feat
+
+
+def _fc_tail(o: Oracle, cfg: dict, ops: dict, feat: Ciphertext, gks: dict, rlk) -> Ciphertext:
+    """FC1 -> x^2 -> FC2 -> x^2 -> FC3 on the features present in every block."""
+    rd = cfg["bins"] * cfg["chirps"]
+    h1 = cfg["weights"][0].shape[0]
     y = o.rescale(o.lt_eval([feat], [(ops["fc1"], 0, 0, 1)], gks, 1, hoist=True,
                             hoist_giant=True)[0])
     s = h1
@@ -204,6 +216,29 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     y = o.rescale(o.lt_eval([h], [(ops["fc3"], 0, 0, 1)], gks, 1, hoist=True,
                             hoist_giant=True)[0])
     return o.add_plain(y, ops["bias3"])
+
+
+def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gks: dict,
+             rlk) -> Ciphertext:
+    """Batched packing: all frames in one ciphertext pair; the frame sum is
+    the block spreading itself (pow2(F) R D = N/2)."""
+    check_layout(cfg, o.n_slots)
+    feat = _front_end(o, ops, re, im, gks, rlk)
+    return _fc_tail(o, cfg, ops, _spread(o, cfg, feat, gks), gks, rlk)
+
+
+def evaluate_frames(o: Oracle, cfg: dict, ops: dict, res: list, ims: list, gks: dict,
+                    rlk) -> Ciphertext:
+    """Per-frame packing (section 3.3.2, one ciphertext pair per frame, frame
+    f in slots r D + c): the front end on every pair, the features added in
+    frame order, then spread to every block of R D slots for the FC network."""
+    if not res or len(res) != len(ims):
+        raise ValueError("one real and one imaginary ciphertext per frame")
+    feat = None
+    for re, im in zip(res, ims):
+        f = _front_end(o, ops, re, im, gks, rlk)
+        feat = f if feat is None else o.add(feat, f)
+    return _fc_tail(o, cfg, ops, _spread(o, cfg, feat, gks), gks, rlk)
 
 
 def plain(cfg: dict, x: np.ndarray) -> np.ndarray:
@@ -232,3 +267,16 @@ def encrypt_window(o: Oracle, s, x: np.ndarray, level: int, scale: float, seed: 
     v[: x.size] = x.reshape(-1)
     return (o.encrypt_sk(s, o.encode(v.real, scale, level), seed),
             o.encrypt_sk(s, o.encode(v.imag, scale, level), seed + 1))
+
+
+def encrypt_frames(o: Oracle, s, x: np.ndarray, level: int, scale: float, seed: int):
+    """Per-frame packing of x [frames][bins][chirps]: frame f's real and
+    imaginary parts in slots r D + c of their own ciphertexts (seeds
+    seed + 2f, seed + 2f + 1)."""
+    res, ims = [], []
+    for f in range(x.shape[0]):
+        v = np.zeros(o.n_slots, dtype=np.complex128)
+        v[: x[f].size] = x[f].reshape(-1)
+        res.append(o.encrypt_sk(s, o.encode(v.real, scale, level), seed + 2 * f))
+        ims.append(o.encrypt_sk(s, o.encode(v.imag, scale, level), seed + 2 * f + 1))
+    return res, ims

@@ -106,6 +106,7 @@ SIGNATURES = {
     "hck_gesture_eval": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "hck_vital_eval_taps": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
     "hck_gesture_eval_taps": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "hck_gesture_eval_frames": ([_P, _P, _P, _P, _U32, _P, _P, _P], _I),
     "hck_measure_mulmod_rate": ([_P, _PD], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
@@ -744,6 +745,19 @@ class Context:
         """The logits ciphertext (slots 0 .. classes-1)."""
         out = self._out(out)
         _check(capi.hck_gesture_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, out))
+        return out
+
+    def gesture_eval_frames(self, plan: GesturePlan, res, ims, gks, rlk, out=None):
+        """The logits from per-frame packing: res[f], ims[f] hold frame f in
+        slots r D + c (zeros elsewhere)."""
+        n = len(res)
+        if len(ims) != n:
+            raise ValueError("one imaginary ciphertext per frame")
+        out = self._out(out)
+        a = (ctypes.c_void_p * max(1, n))(*[c.h for c in res])
+        b = (ctypes.c_void_p * max(1, n))(*[c.h for c in ims])
+        _check(capi.hck_gesture_eval_frames(self.h, ctypes.addressof(plan), a, b, n, gks, rlk,
+                                            out))
         return out
 
     GESTURE_TAPS = ("K3 d_re", "K3 d_im", "K1 power", "K6 notch", "K2 P^4", "K2 feature",

@@ -97,6 +97,79 @@ int dense(hck_context *ctx, const hck_linear_transform *fc, const hck_plaintext 
   return hck_add_plain(ctx, out, bias, out);
 }
 
+// K3 -> K1 -> K6 -> K2 of one ciphertext pair at the plan's level: feat =
+// P P^4 in place (every frame block of the pair at once).  tap(i, c) records
+// intermediate i.
+template <class Tap>
+int front_end(hck_context *ctx, const hck_gesture_plan *p, const hck_ciphertext *re,
+              const hck_ciphertext *im, const hck_switch_key *rlk, const hck_galois_keys *gks,
+              hck_ciphertext *feat, Tap &&tap) {
+  Scratch sc(ctx);
+  // K3: Doppler DFT (complex, Eq. dft_re form)
+  hck_ciphertext *d[2] = {sc.get(), sc.get()};
+  {
+    const hck_ciphertext *ins[2] = {re, im};
+    const hck_linear_transform *lts[4] = {p->dft_c, p->dft_s, p->dft_s, p->dft_c};
+    const uint32_t tin[4] = {0, 1, 0, 1}, tout[4] = {0, 0, 1, 1};
+    const int32_t sign[4] = {1, -1, 1, 1};
+    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, sign, 4, gks, d, 2,
+                    HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
+    TRY(hck_rescale(ctx, d[0], d[0]));
+    TRY(hck_rescale(ctx, d[1], d[1]));
+  }
+  TRY(tap(0, d[0]));
+  TRY(tap(1, d[1]));
+  // K1: power, K6: notch
+  hck_ciphertext *pw = sc.get(), *t = sc.get(), *u = sc.get();
+  TRY(hck_mul(ctx, d[0], d[0], t));
+  TRY(hck_mul(ctx, d[1], d[1], u));
+  TRY(hck_add(ctx, t, u, t));
+  TRY(hck_relinearize(ctx, t, rlk, pw));
+  TRY(hck_rescale(ctx, pw, pw));
+  TRY(tap(2, pw));
+  TRY(hck_mul_plain(ctx, pw, p->notch, pw));
+  TRY(hck_rescale(ctx, pw, pw));
+  TRY(tap(3, pw));
+  // K2: gamma = 4, feature = P w
+  hck_ciphertext *p2 = sc.get(), *p4 = sc.get(), *pl = sc.get();
+  TRY(mul_rs(ctx, pw, pw, rlk, p2, sc));
+  TRY(mul_rs(ctx, p2, p2, rlk, p4, sc));
+  TRY(tap(4, p4));
+  TRY(hck_drop_level(ctx, pw, p4->level, pl));
+  return mul_rs(ctx, pl, p4, rlk, feat, sc);
+}
+
+// the FC network with square activations on the accumulated features, which
+// sit in every block of bins x chirps slots
+template <class Tap>
+int fc_tail(hck_context *ctx, const hck_gesture_plan *p, const hck_ciphertext *feat,
+            const hck_switch_key *rlk, const hck_galois_keys *gks, hck_ciphertext *out,
+            Tap &&tap) {
+  Scratch sc(ctx);
+  const uint32_t rd = p->bins * p->chirps;
+  hck_ciphertext *y = sc.get(), *h = sc.get();
+  TRY(dense(ctx, p->fc1, p->bias1, feat, gks, y, p->hidden1, rd / p->hidden1, sc));
+  TRY(tap(6, y));
+  TRY(mul_rs(ctx, y, y, rlk, h, sc));
+  TRY(dense(ctx, p->fc2, p->bias2, h, gks, y, 0, 1, sc));
+  TRY(tap(7, y));
+  TRY(mul_rs(ctx, y, y, rlk, h, sc));
+  return dense(ctx, p->fc3, p->bias3, h, gks, out, 0, 1, sc);
+}
+
+// checks shared by both packings: the plan, its keys and the inputs' level
+int check_call(hck_context *ctx, const hck_gesture_plan *p, const hck_galois_keys *gks,
+               uint32_t level) {
+  TRY(check_plan(ctx, p));
+  if (p->dft_c->level < 11) return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
+  if (level < p->dft_c->level)
+    return set_error(HCK_ELEVEL, "inputs must share a level of at least the plan's level");
+  for (int32_t s : plan_steps(p))
+    if (!gks->keys.count(galois_of_step(ctx, s)))
+      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
+  return HCK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -133,16 +206,11 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *p, const hck
     hck_ciphertext *t = taps ? taps[i] : nullptr;
     return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
   };
-  TRY(check_plan(ctx, p));
+  if (re->level != im->level) return set_error(HCK_ELEVEL, "inputs must share a level");
+  TRY(check_call(ctx, p, gks, re->level));
   // the plan's operands are encoded for inputs at the level of its Doppler
   // DFT; inputs above it are dropped to it
   const uint32_t l0 = p->dft_c->level;
-  if (l0 < 11) return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
-  if (re->level != im->level || re->level < l0)
-    return set_error(HCK_ELEVEL, "inputs must share a level of at least the plan's level");
-  for (int32_t s : plan_steps(p))
-    if (!gks->keys.count(galois_of_step(ctx, s)))
-      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
   Scratch sc(ctx);
   if (re->level > l0) {
     hck_ciphertext *a = sc.get(), *b = sc.get();
@@ -152,49 +220,49 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *p, const hck
     im = b;
   }
   const uint32_t rd = p->bins * p->chirps, t2 = pow2_at_least(p->frames);
-  // K3: Doppler DFT (complex, Eq. dft_re form)
-  hck_ciphertext *d[2] = {sc.get(), sc.get()};
-  {
-    const hck_ciphertext *ins[2] = {re, im};
-    const hck_linear_transform *lts[4] = {p->dft_c, p->dft_s, p->dft_s, p->dft_c};
-    const uint32_t tin[4] = {0, 1, 0, 1}, tout[4] = {0, 0, 1, 1};
-    const int32_t sign[4] = {1, -1, 1, 1};
-    TRY(hck_lt_eval(ctx, ins, 2, lts, tin, tout, sign, 4, gks, d, 2,
-                    HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
-    TRY(hck_rescale(ctx, d[0], d[0]));
-    TRY(hck_rescale(ctx, d[1], d[1]));
-  }
-  TRY(tap(0, d[0]));
-  TRY(tap(1, d[1]));
-  // K1: power, K6: notch
-  hck_ciphertext *pw = sc.get(), *t = sc.get(), *u = sc.get();
-  TRY(hck_mul(ctx, d[0], d[0], t));
-  TRY(hck_mul(ctx, d[1], d[1], u));
-  TRY(hck_add(ctx, t, u, t));
-  TRY(hck_relinearize(ctx, t, rlk, pw));
-  TRY(hck_rescale(ctx, pw, pw));
-  TRY(tap(2, pw));
-  TRY(hck_mul_plain(ctx, pw, p->notch, pw));
-  TRY(hck_rescale(ctx, pw, pw));
-  TRY(tap(3, pw));
-  // K2: gamma = 4, feature = P w, then the frame sum
-  hck_ciphertext *p2 = sc.get(), *p4 = sc.get(), *pl = sc.get(), *feat = sc.get();
-  TRY(mul_rs(ctx, pw, pw, rlk, p2, sc));
-  TRY(mul_rs(ctx, p2, p2, rlk, p4, sc));
-  TRY(tap(4, p4));
-  TRY(hck_drop_level(ctx, pw, p4->level, pl));
-  TRY(mul_rs(ctx, pl, p4, rlk, feat, sc));
+  hck_ciphertext *feat = sc.get();
+  TRY(front_end(ctx, p, re, im, rlk, gks, feat, tap));
+  // frame accumulation: every block of rd slots ends with the sum of all
   TRY(rotsum(ctx, feat, rd, t2, gks, sc));
   TRY(tap(5, feat));
-  // FC network with square activations
-  hck_ciphertext *y = sc.get(), *h = sc.get();
-  TRY(dense(ctx, p->fc1, p->bias1, feat, gks, y, p->hidden1, rd / p->hidden1, sc));
-  TRY(tap(6, y));
-  TRY(mul_rs(ctx, y, y, rlk, h, sc));
-  TRY(dense(ctx, p->fc2, p->bias2, h, gks, y, 0, 1, sc));
-  TRY(tap(7, y));
-  TRY(mul_rs(ctx, y, y, rlk, h, sc));
-  return dense(ctx, p->fc3, p->bias3, h, gks, out, 0, 1, sc);
+  return fc_tail(ctx, p, feat, rlk, gks, out, tap);
+}
+
+int hck_gesture_eval_frames(hck_context *ctx, const hck_gesture_plan *p,
+                            const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                            uint32_t n_frames, const hck_galois_keys *gks,
+                            const hck_switch_key *rlk, hck_ciphertext *out) {
+  if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (n_frames == 0 || n_frames > HCK_GESTURE_MAX_FRAMES)
+    return set_error(HCK_EINVAL, "frame count out of range");
+  for (uint32_t f = 0; f < n_frames; f++) {
+    if (!re[f] || !im[f]) return set_error(HCK_EINVAL, "null frame ciphertext");
+    if (re[f]->level != re[0]->level || im[f]->level != re[0]->level)
+      return set_error(HCK_ELEVEL, "frame ciphertexts must share a level");
+    if (re[f]->scale != re[0]->scale || im[f]->scale != re[0]->scale)
+      return set_error(HCK_ESCALE, "frame ciphertexts must share a scale");
+  }
+  TRY(check_call(ctx, p, gks, re[0]->level));
+  const uint32_t l0 = p->dft_c->level;
+  auto no_tap = [](int, const hck_ciphertext *) { return HCK_OK; };
+  Scratch sc(ctx);
+  hck_ciphertext *acc = sc.get(), *feat = sc.get(), *a = sc.get(), *b = sc.get();
+  for (uint32_t f = 0; f < n_frames; f++) {
+    const hck_ciphertext *x = re[f], *y = im[f];
+    if (x->level > l0) {
+      TRY(hck_drop_level(ctx, x, l0, a));
+      TRY(hck_drop_level(ctx, y, l0, b));
+      x = a;
+      y = b;
+    }
+    TRY(front_end(ctx, p, x, y, rlk, gks, f ? feat : acc, no_tap));
+    if (f) TRY(hck_add(ctx, acc, feat, acc));
+  }
+  // the frame sum sits in the first block of rd slots; the FC network reads
+  // it in every block, as the batched packing leaves it
+  const uint32_t rd = p->bins * p->chirps;
+  TRY(rotsum(ctx, acc, rd, (uint32_t)(ctx->n / 2 / rd), gks, sc));
+  return fc_tail(ctx, p, acc, rlk, gks, out, no_tap);
 }
 
 }  // extern "C"

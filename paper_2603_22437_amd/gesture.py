@@ -133,3 +133,15 @@ def plain_stages(cfg: dict, x: np.ndarray, n_slots: int) -> list:
             (slots, power.reshape(-1)), (slots, notched.reshape(-1)), (slots, p4.reshape(-1)),
             (np.arange(R * D), feat), (np.arange(len(y1)), y1), (np.arange(len(y2)), y2),
             (np.arange(len(y3)), y3)]
+
+
+def pack_frames(x: np.ndarray, n_slots: int) -> list:
+    """Per-frame packing of x [frames][bins][chirps] (complex): one slot
+    vector per frame with range bin r, chirp c in slot r D + c and zeros
+    elsewhere, the input layout of Context.gesture_eval_frames."""
+    out = []
+    for f in range(x.shape[0]):
+        v = np.zeros(n_slots, dtype=np.complex128)
+        v[: x[f].size] = x[f].reshape(-1)
+        out.append(v)
+    return out

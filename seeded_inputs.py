@@ -98,6 +98,10 @@ CONFIGS: dict[str, dict] = {
     # a small ring with 8 levels (polynomial evaluation up to degree 64)
     "deep12": dict(log_n=12, q=[(60, 1, False), (50, 7, True)], p=[(60, 3, False)],
                    dnum=3, scale=2.0 ** 50),
+    # the gesture circuit's 12 levels on a small ring whose slots hold two
+    # 32 x 32 frame blocks (per-frame packing tests; not a secure size)
+    "gest12": dict(log_n=12, q=[(60, 1, False), (50, 11, True)], p=[(60, 4, False)],
+                   dnum=3, scale=2.0 ** 50),
     # smallest and largest supported rings (edge cases of the parity tests)
     "edge11": dict(log_n=11, q=[(60, 1, False), (50, 2, True)], p=[(60, 1, False)],
                    dnum=3, scale=2.0 ** 40),

@@ -85,3 +85,49 @@ def test_library_plain_stages_end_in_the_oracle_logits():
     spec = np.fft.fftshift(np.fft.fft(np.asarray(cfg["window"]) * x[t, r]))
     idx = int(np.flatnonzero(slots == (t * cfg["bins"] + r) * cfg["chirps"] + k)[0])
     assert abs(d_re[idx] - spec[k].real / np.sum(cfg["window"])) < 1e-12
+
+
+def _gest12_setup(frames_in_plan=2):
+    prm = S.params("gest12")
+    o = O.Oracle(prm)
+    s = o.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=frames_in_plan)
+    l0 = o.L - 1
+    ops = OG.encode_operands(o, cfg, l0, prm["scale"])
+    steps = OG.required_steps(o, cfg, ops)
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5) for k in steps}
+    rlk = o.keygen_relin(s, 7)
+    return prm, o, s, cfg, l0, ops, gks, rlk
+
+
+def test_oracle_per_frame_packing_decodes_to_plain_circuit():
+    """Per-frame packing (one ciphertext pair per frame, section 3.3.2) in the
+    oracle: three frames, each through K3 -> K1 -> K6 -> K2 on its own and
+    then added and spread over the ring's two blocks of 1024 slots, decode to
+    the plaintext circuit's logits over the three frames (N = 2^12)."""
+    prm, o, s, cfg, l0, ops, gks, rlk = _gest12_setup()
+    x = S.gesture_window(2010, 3)
+    # FC1's cyclic diagonals read past the first block only for the features
+    # of range bins 0 and 1: the strongest range bin is rolled to bin 0, so a
+    # frame sum left unspread (zeros beyond the first block) changes the
+    # logits by about 1e-3
+    peak = int(np.argmax((np.abs(x) ** 2).sum(axis=(0, 2))))
+    x = np.roll(x, -peak, axis=1)
+    res, ims = OG.encrypt_frames(o, s, x, l0, prm["scale"], 300)
+    out = OG.evaluate_frames(o, cfg, ops, res, ims, gks, rlk)
+    assert out.level == l0 - OG.DEPTH
+    classes = cfg["weights"][2].shape[0]
+    got = o.decode(o.decrypt(s, out))[:classes].real
+    np.testing.assert_allclose(got, OG.plain(cfg, x), rtol=0, atol=1e-6)
+
+
+def test_oracle_per_frame_packing_of_one_frame_is_the_batched_pipeline():
+    """With one frame the two packings are the same ciphertext operations:
+    bit-identical residues."""
+    prm, o, s, cfg, l0, ops, gks, rlk = _gest12_setup()
+    x = S.gesture_window(2011, 1)
+    re, im = OG.encrypt_window(o, s, x, l0, prm["scale"], 400)
+    a = OG.evaluate(o, cfg, ops, re, im, gks, rlk)
+    b = OG.evaluate_frames(o, cfg, ops, [re], [im], gks, rlk)
+    assert a.level == b.level and a.scale == b.scale
+    assert np.array_equal(a.polys, b.polys)

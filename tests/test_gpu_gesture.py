@@ -150,3 +150,74 @@ def test_gesture_inputs_above_the_plan_level_are_dropped():
     classes = cfg["weights"][2].shape[0]
     got = ctx.decode(ctx.decrypt(sk, out))[:classes].real
     np.testing.assert_allclose(got, OG.plain(cfg, x), rtol=0, atol=1e-3)
+
+
+def test_gesture_per_frame_packing_matches_oracle():
+    """hck_gesture_eval_frames (one ciphertext pair per frame) at N = 2^12,
+    L = 12 with three frames: the logits' residues bit-exact against the
+    oracle's per-frame composition."""
+    prm = S.params("gest12")
+    o = O.Oracle(prm)
+    ctx = H.Context.from_params(prm)
+    s_o = o.keygen_secret(1)
+    sk = ctx.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=2)
+    x = S.gesture_window(2012, 3)
+    x = np.roll(x, -int(np.argmax((np.abs(x) ** 2).sum(axis=(0, 2)))), axis=1)
+    l0 = o.L - 1
+    ops = OG.encode_operands(o, cfg, l0, prm["scale"])
+    plan = _import_plan(ctx, cfg, ops)
+    steps = OG.required_steps(o, cfg, ops)
+    assert ctx.gesture_required_steps(plan) == steps
+    gko = {o.galois_element(k): o.keygen_galois(s_o, o.galois_element(k), 5) for k in steps}
+    rlk_o = o.keygen_relin(s_o, 7)
+    gks = ctx.keygen_rotation(sk, steps, 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    res_o, ims_o = OG.encrypt_frames(o, s_o, x, l0, prm["scale"], 500)
+    res = [ctx.ciphertext_import(c.polys, l0, c.scale) for c in res_o]
+    ims = [ctx.ciphertext_import(c.polys, l0, c.scale) for c in ims_o]
+    got = ctx.gesture_eval_frames(plan, res, ims, gks, rlk)
+    want = OG.evaluate_frames(o, cfg, ops, res_o, ims_o, gko, rlk_o)
+    r, lvl, sc = ctx.ciphertext_export(got)
+    assert lvl == want.level == l0 - OG.DEPTH
+    assert sc == want.scale
+    assert np.array_equal(r, want.polys)
+    with pytest.raises(H.HckError):      # no frames
+        ctx.gesture_eval_frames(plan, [], [], gks, rlk)
+    with pytest.raises(H.HckError):      # frames at different levels
+        ctx.gesture_eval_frames(plan, [res[0], ctx.drop_level(res[1], l0 - 1)], ims[:2],
+                                gks, rlk)
+
+
+def test_gesture_per_frame_packing_decodes_like_batched():
+    """At N = 2^16, L = 24 with 30 frames: 60 per-frame input ciphertexts
+    (top level, dropped to the plan's level) give the logits of the batched
+    packing's 2, and of the plaintext circuit."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.gesture_pipeline_config(frames=30)
+    x = S.gesture_window(2013, cfg["frames"])
+    top = len(prm["q"]) - 1
+    plan = HG.encode_plan(ctx, cfg, HG.DEPTH, prm["scale"])
+    gks = ctx.keygen_rotation(sk, ctx.gesture_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    frames = HG.pack_frames(x, ctx.n_slots)
+    res = [ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 600 + 2 * f)
+           for f, v in enumerate(frames)]
+    ims = [ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 601 + 2 * f)
+           for f, v in enumerate(frames)]
+    out = ctx.gesture_eval_frames(plan, res, ims, gks, rlk)
+    v = np.zeros(ctx.n_slots, dtype=np.complex128)
+    v[: x.size] = x.reshape(-1)
+    re = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), 100)
+    im = ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), 101)
+    ref = ctx.gesture_eval(plan, re, im, gks, rlk)
+    assert out.level == ref.level == 0
+    classes = cfg["weights"][2].shape[0]
+    got = ctx.decode(ctx.decrypt(sk, out))[:classes].real
+    bat = ctx.decode(ctx.decrypt(sk, ref))[:classes].real
+    want = OG.plain(cfg, x)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-3)
+    np.testing.assert_allclose(got, bat, rtol=0, atol=1e-3)
+    assert int(np.argmax(got)) == int(np.argmax(want))
