@@ -43,11 +43,17 @@ struct KsGeom {
   uint32_t off_ext, off_acc, off_conv;      // row offsets inside a slot
 };
 
+// One launch of the ModUp: entry k converts digit digit[k] (source rows from
+// src[k]) into target modulus mod[k] (output row row[k]) and, where row2[k] is
+// not kNoRow, into mod2[k] (row2[k]) from the same reads of the sources.
+constexpr uint16_t kNoRow = 0xffff;
 struct ModUpRows {
   uint32_t n;
   uint16_t row[kMaxRows];     // output row (workspace row)
+  uint16_t row2[kMaxRows];    // second output row or kNoRow
   uint16_t src[kMaxRows];     // workspace row of the digit's first source limb
   uint8_t mod[kMaxRows];
+  uint8_t mod2[kMaxRows];
   uint8_t digit[kMaxRows];
 };
 
@@ -86,28 +92,40 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
   using G = Pass<split_a(LOGN), LOGN, true>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  const int mi = rows.mod[blockIdx.y];
-  const int j = rows.digit[blockIdx.y];
+  const int k = blockIdx.y;
+  const int j = rows.digit[k];
+  const bool two = rows.row2[k] != kNoRow;
   const uint32_t na = min(kg.alpha, kg.nq - j * kg.alpha);
-  const ModConst m = mc[mi];
+  const int mi = rows.mod[k], mi2 = two ? rows.mod2[k] : mi;
+  const ModConst m = mc[mi], m2 = mc[mi2];
   const uint64_t *cv = conv + (size_t)j * kg.alpha * kg.nm + mi;
-  const uint64_t *src = ws + (size_t)rows.src[blockIdx.y] * G::N;
+  const uint64_t *cv2 = conv + (size_t)j * kg.alpha * kg.nm + mi2;
+  const uint64_t *src = ws + (size_t)rows.src[k] * G::N;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
-  uint64_t x[P];
+  uint64_t x[P], y[P];
 #pragma unroll
   for (int i = 0; i < P; i++) {
     const size_t pos = G::gaddr(g, G::ipoint(r, i));
-    u128 acc;
-    acc.lo = acc.hi = 0;
-    for (uint32_t a = 0; a < na; a++)
-      mac_wide(acc, src[(size_t)a * G::N + pos], cv[(size_t)a * kg.nm]);
+    u128 acc, acc2;
+    acc.lo = acc.hi = acc2.lo = acc2.hi = 0;
+    for (uint32_t a = 0; a < na; a++) {
+      const uint64_t v = src[(size_t)a * G::N + pos];
+      mac_wide(acc, v, cv[(size_t)a * kg.nm]);
+      mac_wide(acc2, v, cv2[(size_t)a * kg.nm]);
+    }
     x[i] = redc(acc, m.q, m.qinv);
+    y[i] = redc(acc2, m2.q, m2.qinv);
   }
   G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
-  uint64_t *out = ws + (size_t)rows.row[blockIdx.y] * G::N;
+  uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
   for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+  if (!two) return;
+  G::forward(lds, y, c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, m2.q);
+  uint64_t *out2 = ws + (size_t)rows.row2[k] * G::N;
+#pragma unroll
+  for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
 }
 
 template <int LOGN>
@@ -176,28 +194,42 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
   using G = Pass<split_a(LOGN), LOGN, true>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  const uint32_t p = blockIdx.y / kg.nq, li = blockIdx.y % kg.nq;
+  // workgroup y converts target limbs li and li + 1 (if below nq) of poly p
+  // from one read of the K special limbs
+  const uint32_t pairs = (kg.nq + 1) / 2;
+  const uint32_t p = blockIdx.y / pairs, li = 2 * (blockIdx.y % pairs);
+  const bool two = li + 1 < kg.nq;
+  const uint32_t li2 = two ? li + 1 : li;
   uint64_t *slot = ws + (size_t)blockIdx.z * kg.slot_rows * G::N;
-  const ModConst m = mc[li];
-  const uint64_t h = hneg[li];
+  const ModConst m = mc[li], m2 = mc[li2];
+  const uint64_t h = hneg[li], h2 = hneg[li2];
   const uint64_t *src = slot + ((size_t)kg.off_acc + p * kg.ne + kg.nq) * G::N;
-  const uint64_t *cv = down_conv + li;
+  const uint64_t *cv = down_conv + li, *cv2 = down_conv + li2;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
-  uint64_t x[P];
+  uint64_t x[P], y[P];
 #pragma unroll
   for (int i = 0; i < P; i++) {
     const size_t pos = G::gaddr(g, G::ipoint(r, i));
-    u128 s;
-    s.lo = s.hi = 0;
-    for (uint32_t k = 0; k < kg.K; k++)
-      mac_wide(s, src[(size_t)k * G::N + pos], cv[(size_t)k * kg.nm]);
+    u128 s, s2;
+    s.lo = s.hi = s2.lo = s2.hi = 0;
+    for (uint32_t k = 0; k < kg.K; k++) {
+      const uint64_t v = src[(size_t)k * G::N + pos];
+      mac_wide(s, v, cv[(size_t)k * kg.nm]);
+      mac_wide(s2, v, cv2[(size_t)k * kg.nm]);
+    }
     x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
+    y[i] = add_mod(redc(s2, m2.q, m2.qinv), h2, m2.q);
   }
   G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
   uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
 #pragma unroll
   for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+  if (!two) return;
+  G::forward(lds, y, c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, m2.q);
+  uint64_t *out2 = slot + ((size_t)kg.off_conv + p * kg.L + li2) * G::N;
+#pragma unroll
+  for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
 }
 
 template <int LOGN>
@@ -339,19 +371,39 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
       }
     }
   const uint64_t *up_conv = ctx->d_up_conv + (size_t)level * kg.dnum * alpha * nm;
-  for (size_t s = 0; s < ext_rows.size(); s += kMaxRows) {
+  // consecutive targets of one digit share a workgroup (one read of the
+  // digit's limbs for both)
+  std::vector<std::pair<size_t, size_t>> groups;  // (first row, second row or npos)
+  for (size_t i = 0; i < ext_rows.size();) {
+    const bool pair = i + 1 < ext_rows.size() && ext_rows[i + 1].src == ext_rows[i].src &&
+                      ext_rows[i + 1].digit == ext_rows[i].digit;
+    groups.push_back({i, pair ? i + 1 : SIZE_MAX});
+    i += pair ? 2 : 1;
+  }
+  for (size_t s = 0; s < groups.size(); s += kMaxRows) {
     ModUpRows mr;
-    mr.n = (uint32_t)std::min(ext_rows.size() - s, (size_t)kMaxRows);
-    double srcs = 0;
+    mr.n = (uint32_t)std::min(groups.size() - s, (size_t)kMaxRows);
+    double srcs = 0, outs = 0, macs = 0;
     for (uint32_t k = 0; k < mr.n; k++) {
-      const Row &rw = ext_rows[s + k];
+      const Row &rw = ext_rows[groups[s + k].first];
       mr.row[k] = rw.row;
       mr.src[k] = rw.src;
       mr.mod[k] = rw.mod;
       mr.digit[k] = rw.digit;
+      mr.row2[k] = kNoRow;
+      mr.mod2[k] = rw.mod;
       srcs += rw.na;
+      outs += 1;
+      macs += rw.na;
+      if (groups[s + k].second != SIZE_MAX) {
+        const Row &r2 = ext_rows[groups[s + k].second];
+        mr.row2[k] = r2.row;
+        mr.mod2[k] = r2.mod;
+        outs += 1;
+        macs += rw.na;
+      }
     }
-    timing_begin(ctx, "ks_modup_strided", 8.0 * N * (srcs + mr.n), N * (srcs + 0.5 * A * mr.n));
+    timing_begin(ctx, "ks_modup_strided", 8.0 * N * (srcs + outs), N * (macs + 0.5 * A * outs));
     k_modup_strided<LOGN><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
         ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
     timing_end(ctx);
@@ -390,9 +442,11 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
     if ((rc = ntt_pass(ctx, ws, mp, true, false, nullptr))) return rc;
     if ((rc = ntt_pass(ctx, ws, mp, true, true, &sp, (int)(2 * K)))) return rc;
   }
-  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K + 1) * 2 * nq * nb,
+  // K special limbs read once per pair of target limbs
+  const uint32_t pairs = (nq + 1) / 2;
+  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K * pairs + nq) * 2 * nb,
                N * (K + 0.5 * A) * 2 * nq * nb);
-  k_moddown_strided<LOGN><<<dim3(GA::BLOCKS, 2 * nq, nb), kNttThreads, 0, ctx->stream>>>(
+  k_moddown_strided<LOGN><<<dim3(GA::BLOCKS, 2 * pairs, nb), kNttThreads, 0, ctx->stream>>>(
       ws, ctx->d_down_conv, ctx->d_down_hneg, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
   RowScale pinv;
