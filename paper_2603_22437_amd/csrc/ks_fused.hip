@@ -47,6 +47,10 @@ struct KsGeom {
 // src[k]) into target modulus mod[k] (output row row[k]) and, where row2[k] is
 // not kNoRow, into mod2[k] (row2[k]) from the same reads of the sources.
 constexpr uint16_t kNoRow = 0xffff;
+// workgroups (at one target each) from which the basis conversions pair
+// targets: halved, they still fill the chip twice over at the paired kernel's
+// occupancy (about 3 workgroups of 256 threads per CU)
+constexpr size_t kPairMinBlocks = 3072;
 struct ModUpRows {
   uint32_t n;
   uint16_t row[kMaxRows];     // output row (workspace row)
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
   for (int i = 0; i < P; i++) y[roff + G::gaddr(g, G::ipoint(r, i))] = x[i];
 }
 
-template <int LOGN>
+template <int LOGN, bool PAIR>
 __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     uint64_t *__restrict__ ws, ModUpRows rows, const uint64_t *__restrict__ conv, KsGeom kg,
     const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
@@ -94,38 +98,57 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
   __shared__ uint64_t lds[G::LDS_WORDS];
   const int k = blockIdx.y;
   const int j = rows.digit[k];
-  const bool two = rows.row2[k] != kNoRow;
   const uint32_t na = min(kg.alpha, kg.nq - j * kg.alpha);
-  const int mi = rows.mod[k], mi2 = two ? rows.mod2[k] : mi;
-  const ModConst m = mc[mi], m2 = mc[mi2];
+  const int mi = rows.mod[k];
+  const ModConst m = mc[mi];
   const uint64_t *cv = conv + (size_t)j * kg.alpha * kg.nm + mi;
-  const uint64_t *cv2 = conv + (size_t)j * kg.alpha * kg.nm + mi2;
   const uint64_t *src = ws + (size_t)rows.src[k] * G::N;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
-  uint64_t x[P], y[P];
+  if constexpr (!PAIR) {
+    uint64_t x[P];
 #pragma unroll
-  for (int i = 0; i < P; i++) {
-    const size_t pos = G::gaddr(g, G::ipoint(r, i));
-    u128 acc, acc2;
-    acc.lo = acc.hi = acc2.lo = acc2.hi = 0;
-    for (uint32_t a = 0; a < na; a++) {
-      const uint64_t v = src[(size_t)a * G::N + pos];
-      mac_wide(acc, v, cv[(size_t)a * kg.nm]);
-      mac_wide(acc2, v, cv2[(size_t)a * kg.nm]);
+    for (int i = 0; i < P; i++) {
+      const size_t pos = G::gaddr(g, G::ipoint(r, i));
+      u128 acc;
+      acc.lo = acc.hi = 0;
+      for (uint32_t a = 0; a < na; a++)
+        mac_wide(acc, src[(size_t)a * G::N + pos], cv[(size_t)a * kg.nm]);
+      x[i] = redc(acc, m.q, m.qinv);
     }
-    x[i] = redc(acc, m.q, m.qinv);
-    y[i] = redc(acc2, m2.q, m2.qinv);
+    G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+    uint64_t *out = ws + (size_t)rows.row[k] * G::N;
+#pragma unroll
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+  } else {
+    const bool two = rows.row2[k] != kNoRow;
+    const int mi2 = two ? rows.mod2[k] : mi;
+    const ModConst m2 = mc[mi2];
+    const uint64_t *cv2 = conv + (size_t)j * kg.alpha * kg.nm + mi2;
+    uint64_t x[P], y[P];
+#pragma unroll
+    for (int i = 0; i < P; i++) {
+      const size_t pos = G::gaddr(g, G::ipoint(r, i));
+      u128 acc, acc2;
+      acc.lo = acc.hi = acc2.lo = acc2.hi = 0;
+      for (uint32_t a = 0; a < na; a++) {
+        const uint64_t v = src[(size_t)a * G::N + pos];
+        mac_wide(acc, v, cv[(size_t)a * kg.nm]);
+        mac_wide(acc2, v, cv2[(size_t)a * kg.nm]);
+      }
+      x[i] = redc(acc, m.q, m.qinv);
+      y[i] = redc(acc2, m2.q, m2.qinv);
+    }
+    G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+    uint64_t *out = ws + (size_t)rows.row[k] * G::N;
+#pragma unroll
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    if (!two) return;
+    G::forward(lds, y, c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, m2.q);
+    uint64_t *out2 = ws + (size_t)rows.row2[k] * G::N;
+#pragma unroll
+    for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
   }
-  G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
-  uint64_t *out = ws + (size_t)rows.row[k] * G::N;
-#pragma unroll
-  for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
-  if (!two) return;
-  G::forward(lds, y, c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, m2.q);
-  uint64_t *out2 = ws + (size_t)rows.row2[k] * G::N;
-#pragma unroll
-  for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
 }
 
 template <int LOGN>
@@ -186,7 +209,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
   }
 }
 
-template <int LOGN>
+template <int LOGN, bool PAIR>
 __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
     uint64_t *__restrict__ ws, const uint64_t *__restrict__ down_conv,
     const uint64_t *__restrict__ hneg, KsGeom kg, const ModConst *__restrict__ mc,
@@ -194,42 +217,62 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
   using G = Pass<split_a(LOGN), LOGN, true>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  // workgroup y converts target limbs li and li + 1 (if below nq) of poly p
-  // from one read of the K special limbs
-  const uint32_t pairs = (kg.nq + 1) / 2;
-  const uint32_t p = blockIdx.y / pairs, li = 2 * (blockIdx.y % pairs);
-  const bool two = li + 1 < kg.nq;
-  const uint32_t li2 = two ? li + 1 : li;
+  // with PAIR workgroup y converts target limbs li and li + 1 (if below nq)
+  // of poly p from one read of the K special limbs, else limb li alone
+  const uint32_t per = PAIR ? (kg.nq + 1) / 2 : kg.nq;
+  const uint32_t p = blockIdx.y / per, li = (PAIR ? 2 : 1) * (blockIdx.y % per);
   uint64_t *slot = ws + (size_t)blockIdx.z * kg.slot_rows * G::N;
-  const ModConst m = mc[li], m2 = mc[li2];
-  const uint64_t h = hneg[li], h2 = hneg[li2];
+  const ModConst m = mc[li];
+  const uint64_t h = hneg[li];
   const uint64_t *src = slot + ((size_t)kg.off_acc + p * kg.ne + kg.nq) * G::N;
-  const uint64_t *cv = down_conv + li, *cv2 = down_conv + li2;
+  const uint64_t *cv = down_conv + li;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
-  uint64_t x[P], y[P];
+  if constexpr (!PAIR) {
+    uint64_t x[P];
 #pragma unroll
-  for (int i = 0; i < P; i++) {
-    const size_t pos = G::gaddr(g, G::ipoint(r, i));
-    u128 s, s2;
-    s.lo = s.hi = s2.lo = s2.hi = 0;
-    for (uint32_t k = 0; k < kg.K; k++) {
-      const uint64_t v = src[(size_t)k * G::N + pos];
-      mac_wide(s, v, cv[(size_t)k * kg.nm]);
-      mac_wide(s2, v, cv2[(size_t)k * kg.nm]);
+    for (int i = 0; i < P; i++) {
+      const size_t pos = G::gaddr(g, G::ipoint(r, i));
+      u128 s;
+      s.lo = s.hi = 0;
+      for (uint32_t k = 0; k < kg.K; k++)
+        mac_wide(s, src[(size_t)k * G::N + pos], cv[(size_t)k * kg.nm]);
+      x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
     }
-    x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
-    y[i] = add_mod(redc(s2, m2.q, m2.qinv), h2, m2.q);
+    G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
+    uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
+#pragma unroll
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+  } else {
+    const bool two = li + 1 < kg.nq;
+    const uint32_t li2 = two ? li + 1 : li;
+    const ModConst m2 = mc[li2];
+    const uint64_t h2 = hneg[li2];
+    const uint64_t *cv2 = down_conv + li2;
+    uint64_t x[P], y[P];
+#pragma unroll
+    for (int i = 0; i < P; i++) {
+      const size_t pos = G::gaddr(g, G::ipoint(r, i));
+      u128 s, s2;
+      s.lo = s.hi = s2.lo = s2.hi = 0;
+      for (uint32_t k = 0; k < kg.K; k++) {
+        const uint64_t v = src[(size_t)k * G::N + pos];
+        mac_wide(s, v, cv[(size_t)k * kg.nm]);
+        mac_wide(s2, v, cv2[(size_t)k * kg.nm]);
+      }
+      x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
+      y[i] = add_mod(redc(s2, m2.q, m2.qinv), h2, m2.q);
+    }
+    G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
+    uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
+#pragma unroll
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    if (!two) return;
+    G::forward(lds, y, c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, m2.q);
+    uint64_t *out2 = slot + ((size_t)kg.off_conv + p * kg.L + li2) * G::N;
+#pragma unroll
+    for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
   }
-  G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
-  uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
-#pragma unroll
-  for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
-  if (!two) return;
-  G::forward(lds, y, c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, m2.q);
-  uint64_t *out2 = slot + ((size_t)kg.off_conv + p * kg.L + li2) * G::N;
-#pragma unroll
-  for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
 }
 
 template <int LOGN>
@@ -371,11 +414,15 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
       }
     }
   const uint64_t *up_conv = ctx->d_up_conv + (size_t)level * kg.dnum * alpha * nm;
+  // in a launch large enough to fill the chip at half the workgroups,
   // consecutive targets of one digit share a workgroup (one read of the
-  // digit's limbs for both)
-  std::vector<std::pair<size_t, size_t>> groups;  // (first row, second row or npos)
+  // digit's limbs for both); small launches keep one target per workgroup
+  // and the kernel's lower register count
+  const bool paired = ext_rows.size() * GA::BLOCKS >= kPairMinBlocks;
+  std::vector<std::pair<size_t, size_t>> groups;  // (first row, second row or SIZE_MAX)
   for (size_t i = 0; i < ext_rows.size();) {
-    const bool pair = i + 1 < ext_rows.size() && ext_rows[i + 1].src == ext_rows[i].src &&
+    const bool pair = paired && i + 1 < ext_rows.size() &&
+                      ext_rows[i + 1].src == ext_rows[i].src &&
                       ext_rows[i + 1].digit == ext_rows[i].digit;
     groups.push_back({i, pair ? i + 1 : SIZE_MAX});
     i += pair ? 2 : 1;
@@ -404,8 +451,12 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
       }
     }
     timing_begin(ctx, "ks_modup_strided", 8.0 * N * (srcs + outs), N * (macs + 0.5 * A * outs));
-    k_modup_strided<LOGN><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
-        ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+    if (paired)
+      k_modup_strided<LOGN, true><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
+          ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+    else
+      k_modup_strided<LOGN, false><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
+          ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
     timing_end(ctx);
   }
   HCK_HIP(ctx, hipGetLastError());
@@ -442,12 +493,20 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
     if ((rc = ntt_pass(ctx, ws, mp, true, false, nullptr))) return rc;
     if ((rc = ntt_pass(ctx, ws, mp, true, true, &sp, (int)(2 * K)))) return rc;
   }
-  // K special limbs read once per pair of target limbs
-  const uint32_t pairs = (nq + 1) / 2;
-  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K * pairs + nq) * 2 * nb,
+  // in a launch large enough to fill the chip at half the workgroups, the K
+  // special limbs are read once per pair of target limbs
+  const bool paired = (size_t)2 * nq * nb * GA::BLOCKS >= kPairMinBlocks;
+  const uint32_t per = paired ? (nq + 1) / 2 : nq;
+  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K * per + nq) * 2 * nb,
                N * (K + 0.5 * A) * 2 * nq * nb);
-  k_moddown_strided<LOGN><<<dim3(GA::BLOCKS, 2 * pairs, nb), kNttThreads, 0, ctx->stream>>>(
-      ws, ctx->d_down_conv, ctx->d_down_hneg, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  if (paired)
+    k_moddown_strided<LOGN, true><<<dim3(GA::BLOCKS, 2 * per, nb), kNttThreads, 0,
+                                    ctx->stream>>>(ws, ctx->d_down_conv, ctx->d_down_hneg, kg,
+                                                   ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  else
+    k_moddown_strided<LOGN, false><<<dim3(GA::BLOCKS, 2 * per, nb), kNttThreads, 0,
+                                     ctx->stream>>>(ws, ctx->d_down_conv, ctx->d_down_hneg, kg,
+                                                    ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
   RowScale pinv;
   for (uint32_t i = 0; i < nq; i++) {
