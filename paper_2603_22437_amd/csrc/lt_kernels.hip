@@ -75,22 +75,16 @@ struct ColSum {
   }
 };
 
-// The giant groups of one wave over the staged baby rotations xs; Sum is the
-// accumulator kind, GW the groups a wave carries at a time.
+// One pass of a wave over the staged baby rotations xs: giant groups g0,
+// g0 + 4, ..., g0 + 4 (GW - 1) (those below ng); Sum is the accumulator kind.
 template <class Sum, int GW, int O, int I>
-__device__ __forceinline__ void lt_sums_wave(const LtSumArgs &a, const uint64_t *xs,
-                                             const ModConst &m, size_t base, int n, int wave,
-                                             int lane) {
+__device__ __forceinline__ void lt_sums_pass(const LtSumArgs &a, const uint64_t *xs,
+                                             const ModConst &m, size_t base, int n, int lane,
+                                             int g0, int flush_b) {
   constexpr int C = kLtCoeffs;
   const int nb = (int)a.nb;
   const size_t off = base + lane;
-  // each baby step adds up to max_terms products to one sum.  A flush
-  // reduces a sum to r in [0, q) and restarts it from r 2^64 mod q, which
-  // REDC maps back to r.
-  const int flush_b = (int)max<uint64_t>(1, Sum::max_products(m.q) / a.max_terms);
-  // wave w takes giant groups w, w + 4, w + 8, ... (GW at a time), so the
-  // four waves of a workgroup stay within one group of each other
-  for (int g0 = wave; g0 < (int)a.ng; g0 += 4 * GW) {
+  {
     Sum acc[GW][O][2];
 #pragma unroll
     for (int gi = 0; gi < GW; gi++)
@@ -179,6 +173,44 @@ __device__ __forceinline__ void lt_sums_wave(const LtSumArgs &a, const uint64_t 
   }
 }
 
+// The last R or fewer groups of a wave (rem of them, 1 <= rem <= R) in one
+// pass of exactly rem slots.
+template <class Sum, int R, int O, int I>
+__device__ __forceinline__ void lt_sums_rest(const LtSumArgs &a, const uint64_t *xs,
+                                             const ModConst &m, size_t base, int n, int lane,
+                                             int g0, int rem, int flush_b) {
+  if constexpr (R > 0) {
+    if (rem == R)
+      lt_sums_pass<Sum, R, O, I>(a, xs, m, base, n, lane, g0, flush_b);
+    else
+      lt_sums_rest<Sum, R - 1, O, I>(a, xs, m, base, n, lane, g0, rem, flush_b);
+  }
+}
+
+// The giant groups of one wave: w, w + 4, w + 8, ..., GW at a time, so the
+// four waves of a workgroup stay within one group of each other.  With REST
+// the last fewer than GW take a pass of their own size (no idle slots, each
+// of which loads a row of zeros); otherwise the last pass has idle slots.
+template <class Sum, int GW, int O, int I, bool REST>
+__device__ __forceinline__ void lt_sums_wave(const LtSumArgs &a, const uint64_t *xs,
+                                             const ModConst &m, size_t base, int n, int wave,
+                                             int lane) {
+  // each baby step adds up to max_terms products to one sum.  A flush
+  // reduces a sum to r in [0, q) and restarts it from r 2^64 mod q, which
+  // REDC maps back to r.
+  const int flush_b = (int)max<uint64_t>(1, Sum::max_products(m.q) / a.max_terms);
+  const int ng = (int)a.ng;
+  int g0 = wave;
+  if constexpr (REST) {
+    for (; g0 + 4 * (GW - 1) < ng; g0 += 4 * GW)
+      lt_sums_pass<Sum, GW, O, I>(a, xs, m, base, n, lane, g0, flush_b);
+    if (g0 < ng)
+      lt_sums_rest<Sum, GW - 1, O, I>(a, xs, m, base, n, lane, g0, (ng - g0 + 3) / 4, flush_b);
+  } else {
+    for (; g0 < ng; g0 += 4 * GW) lt_sums_pass<Sum, GW, O, I>(a, xs, m, base, n, lane, g0, flush_b);
+  }
+}
+
 // GW / GWN: giant groups a wave carries at a time with 128-bit / column sums
 template <int GW, int GWN, int O, int I>
 __global__ __launch_bounds__(256, 4) void k_lt_sums(LtSumArgs a, const ModConst *__restrict__ mc,
@@ -203,9 +235,9 @@ __global__ __launch_bounds__(256, 4) void k_lt_sums(LtSumArgs a, const ModConst 
   const ModConst m = mc[limb];
   // the limb's modulus is uniform across the workgroup
   if (m.q < (1ull << 52))
-    lt_sums_wave<ColSum, GWN, O, I>(a, xs, m, base, n, wave, lane);
+    lt_sums_wave<ColSum, GWN, O, I, true>(a, xs, m, base, n, wave, lane);
   else
-    lt_sums_wave<WideSum, GW, O, I>(a, xs, m, base, n, wave, lane);
+    lt_sums_wave<WideSum, GW, O, I, false>(a, xs, m, base, n, wave, lane);
 }
 
 template <int GW, int GWN, int O, int I>
