@@ -442,9 +442,9 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     cfg = S.vital_pipeline_config()
     top = len(prm["q"]) - 1
     # the circuit needs its depth in levels, plus one of headroom for the rate
-    # numerators (fourth powers of the spectrum reach 1e6 on strong windows,
-    # beyond q0 / scale at level 0): the plan is encoded for inputs at that
-    # level and the top-level inputs are dropped to it
+    # numerators (fourth powers of the spectrum times frequencies, whose size
+    # depends on the window): the plan is encoded for inputs at that level and
+    # the top-level inputs are dropped to it
     base = (11 if cfg["taylor_order"] == 3 else 9) + 1
     plan = HV.encode_plan(ctx, cfg, base)
     gks = ctx.keygen_rotation(sk, ctx.vital_required_steps(plan), 5)

@@ -37,8 +37,9 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
       rotations R, 2R, ... (one chain for the real, one for the imaginary
       part)
   K1  P = Re X^2 + Im X^2
-  K2  S = P^gamma; num = sum_c f_c S_c, den = sum_c S_c over each lane group
-      (f_c the bin frequency in beats per minute; rotations 1 .. G/2)
+  K2  S = P^gamma; num = sum_c a f_c S_c, den = sum_c a S_c over each lane
+      group (f_c the bin frequency in beats per minute, a the public
+      rate_gain of the configuration; rotations 1 .. G/2)
 
 Outputs: num_bin, den_bin (value in slot 0; the target bin r^ = num / den),
 num_rates, den_rates (respiration in slot 0, heart rate in slot G; rate in
@@ -140,8 +141,8 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
             c = c0 + i
             re[t * r + c] = w * np.cos(2 * np.pi * k * t / f) / ws
             im[t * r + c] = -w * np.sin(2 * np.pi * k * t / f) / ws
-            fr[c] = 60.0 * k * cfg["fps"] / f
-            mk[c] = 1.0
+            fr[c] = 60.0 * k * cfg["fps"] / f * cfg.get("rate_gain", 1.0)
+            mk[c] = cfg.get("rate_gain", 1.0)
         v[f"dft_re_{band}"] = re
         v[f"dft_im_{band}"] = im
     v["freq"] = fr
@@ -334,8 +335,9 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
         xi = np.array([-np.sum(win * np.sin(2 * np.pi * k * t / f) * dphi) for k in ks]) / ws
         s = (xr ** 2 + xi ** 2) ** cfg.get("gamma", 2)
         fk = 60.0 * ks * cfg["fps"] / f
-        out[f"num_{band}"] = float(np.sum(fk * s))
-        out[f"den_{band}"] = float(np.sum(s))
+        g = cfg.get("rate_gain", 1.0)
+        out[f"num_{band}"] = float(g * np.sum(fk * s))
+        out[f"den_{band}"] = float(g * np.sum(s))
     return out
 
 

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -226,22 +227,32 @@ def decode_residues(log_n: int, res: np.ndarray, mods, scale: float) -> np.ndarr
 # ---------------------------------------------------------------------------
 
 class _Handle:
+    """A library object.  It is freed by close() or, at the latest, when it
+    is garbage-collected or the interpreter exits (weakref.finalize, which
+    also runs the handles' finalizers before the older context's).  The C
+    side makes any order safe: destroying a context releases the device
+    memory of every handle still alive, whose own destroy call then frees
+    only its host record."""
     _destroy = None
 
     def __init__(self, ctx, h):
         self.ctx = ctx          # keeps the context alive
         self.h = h
+        self._fin = weakref.finalize(self, type(self)._destroy, h) if h else None
 
     def close(self):
-        if self.h:
-            type(self)._destroy(self.h)
-            self.h = None
+        if self._fin is not None:
+            self._fin()
+            self._fin = None
+        self.h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+    def _disown(self):
+        """The library took ownership of the object (e.g. a key inserted
+        into a key set): forget it without destroying it."""
+        if self._fin is not None:
+            self._fin.detach()
+            self._fin = None
+        self.h = None
 
     @property
     def _as_parameter_(self):
@@ -351,6 +362,11 @@ class GesturePlan(ctypes.Structure):
         return plan
 
 
+def _destroy_context(h, hooks_keep):
+    capi.hck_context_destroy(h)
+    hooks_keep.clear()
+
+
 def _stream_handle(stream):
     if stream is None:
         return None
@@ -372,6 +388,11 @@ class Context:
         _check(capi.hck_context_create(ctypes.byref(prm), device, _stream_handle(stream),
                                        ctypes.byref(h)))
         self.h = h.value
+        # the finalizer holds the allocator hooks (use_torch_allocator) alive
+        # until the context is destroyed: its destroy call still frees
+        # through them
+        self._hooks_keep = []
+        self._fin = weakref.finalize(self, _destroy_context, self.h, self._hooks_keep)
         self.log_n, self.n, self.dnum = log_n, 1 << log_n, dnum
         self.q = [int(x) for x in q]
         self.p = [int(x) for x in p]
@@ -385,15 +406,14 @@ class Context:
         return cls(prm["log_n"], prm["q"], prm["p"], prm["dnum"], device, stream)
 
     def close(self):
-        if getattr(self, "h", None):
-            capi.hck_context_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        """Destroys the context.  Handles still alive lose their device
+        memory and can no longer be used (calls with them fail); closing
+        them afterwards is harmless."""
+        fin = getattr(self, "_fin", None)
+        if fin is not None:
+            fin()
+            self._fin = None
+        self.h = None
 
     @property
     def _as_parameter_(self):
@@ -426,6 +446,7 @@ class Context:
         hooks = (ALLOC_FN(alloc), FREE_FN(free))
         _check(capi.hck_set_allocator(self.h, hooks[0], hooks[1], None))
         self._alloc_hooks = hooks   # the C side calls them until close()
+        self._hooks_keep.append(hooks)
 
     def use_default_allocator(self):
         _check(capi.hck_set_allocator(self.h, ALLOC_FN(), FREE_FN(), None))
@@ -471,7 +492,7 @@ class Context:
         for g, words in keys.items():
             swk = self.switch_key_import(words)
             _check(capi.hck_galois_keys_insert(gks.h, int(g), swk.h))
-            swk.h = None    # owned by the set now
+            swk._disown()    # owned by the set now
         return gks
 
     def keygen_galois(self, sk, elements, seed: int) -> GaloisKeys:
@@ -854,6 +875,7 @@ class Server:
         h = ctypes.c_void_p()
         _check(capi.hck_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h.value
+        self._fin = weakref.finalize(self, capi.hck_server_destroy, self.h)
         self._keep = {}         # tenants' plans and key words
         self._out = {}          # request -> output buffer
 
@@ -910,12 +932,7 @@ class Server:
         return {name: getattr(st, name) for name, _ in ServerStats._fields_}
 
     def close(self):
-        if self.h:
-            capi.hck_server_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        if self._fin is not None:
+            self._fin()
+            self._fin = None
+        self.h = None

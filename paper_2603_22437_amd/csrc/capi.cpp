@@ -35,6 +35,47 @@ int enter(hck_context *ctx) {
 
 size_t poly_stride(const hck_context *ctx) { return (size_t)ctx->L * ctx->n; }
 
+// Releases of caller handles (hck::track): the device memory goes back and
+// the handle is detached from its context (ctx = null), so that its destroy
+// call later frees only the host record.
+template <class T>
+void release_data(void *p) {
+  T *x = static_cast<T *>(p);
+  if (x->ctx) dev_free(x->ctx, x->data);
+  x->data = nullptr;
+  x->ctx = nullptr;
+}
+
+void release_ct(void *p) {
+  hck_ciphertext *ct = static_cast<hck_ciphertext *>(p);
+  release_data<hck_ciphertext>(ct);
+  ct->cap_polys = ct->size = 0;
+}
+
+void release_gks(void *p) {
+  hck_galois_keys *g = static_cast<hck_galois_keys *>(p);
+  for (auto &kv : g->keys) release_data<hck_switch_key>(kv.second);
+  g->ctx = nullptr;
+}
+
+void release_lt(void *p) {
+  hck_linear_transform *lt = static_cast<hck_linear_transform *>(p);
+  if (lt->ctx)
+    for (uint64_t *q : lt->owned) dev_free(lt->ctx, q);
+  lt->owned.clear();
+  lt->groups.clear();
+  lt->grid = nullptr;
+  lt->ctx = nullptr;
+}
+
+// a handle given to a call must belong to the call's context (a handle whose
+// context was destroyed has none)
+#define OWNED(ctx, h)                                                                 \
+  do {                                                                                \
+    if ((h) && (h)->ctx != (ctx))                                                     \
+      return set_error(HCK_EINVAL, #h " belongs to another (or a destroyed) context"); \
+  } while (0)
+
 // Host buffers are often locals of the caller, so uploads complete before
 // returning (set-up paths only; evaluation never uploads).
 int upload(hck_context *ctx, uint64_t *dst, const void *src, size_t bytes) {
@@ -355,13 +396,15 @@ int hck_secret_key_import(hck_context *ctx, const int8_t *coeffs, hck_secret_key
     delete sk;
     return rc;
   }
+  track(ctx, sk, release_data<hck_secret_key>);
   *out = sk;
   return HCK_OK;
 }
 
 int hck_secret_key_destroy(hck_secret_key *sk) {
   if (sk) {
-    dev_free(sk->ctx, sk->data);
+    if (sk->ctx) untrack(sk->ctx, sk);
+    release_data<hck_secret_key>(sk);
     delete sk;
   }
   return HCK_OK;
@@ -370,6 +413,7 @@ int hck_secret_key_destroy(hck_secret_key *sk) {
 int hck_keygen_public(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
                       hck_public_key **out) {
   ENTER(ctx);
+  OWNED(ctx, sk);
   if (!sk || !out) return set_error(HCK_EINVAL, "null argument");
   TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
   const size_t n = ctx->n;
@@ -396,6 +440,7 @@ int hck_keygen_public(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
     delete pk;
     return rc;
   }
+  track(ctx, pk, release_data<hck_public_key>);
   *out = pk;
   return HCK_OK;
 }
@@ -403,6 +448,7 @@ int hck_keygen_public(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
 int hck_public_key_export(hck_context *ctx, const hck_public_key *pk, uint64_t *out,
                           size_t n_words) {
   ENTER(ctx);
+  OWNED(ctx, pk);
   if (!pk || !out) return set_error(HCK_EINVAL, "null argument");
   if (n_words != (size_t)2 * ctx->L * ctx->n) return set_error(HCK_EINVAL, "size mismatch");
   return export_rows(ctx, pk->data, 2, ctx->L, ctx->L, true, 0, out);
@@ -410,7 +456,8 @@ int hck_public_key_export(hck_context *ctx, const hck_public_key *pk, uint64_t *
 
 int hck_public_key_destroy(hck_public_key *pk) {
   if (pk) {
-    dev_free(pk->ctx, pk->data);
+    if (pk->ctx) untrack(pk->ctx, pk);
+    release_data<hck_public_key>(pk);
     delete pk;
   }
   return HCK_OK;
@@ -419,6 +466,7 @@ int hck_public_key_destroy(hck_public_key *pk) {
 int hck_keygen_relin(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
                      hck_switch_key **out) {
   ENTER(ctx);
+  OWNED(ctx, sk);
   if (!sk || !out) return set_error(HCK_EINVAL, "null argument");
   TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
   // s^2 in Montgomery form: REDC(s~ s~) = s^2 2^64
@@ -431,12 +479,14 @@ int hck_keygen_relin(hck_context *ctx, const hck_secret_key *sk, uint64_t seed,
   int rc = launch_mul_mont(ctx, s2, sk->data, sk->data, fullmap(ctx), 0);
   if (!rc) rc = make_switch_key(ctx, sk, s2, "rlk", seed, out);
   dev_free(ctx, own);
+  if (!rc) track(ctx, *out, release_data<hck_switch_key>);
   return rc;
 }
 
 int hck_switch_key_export(hck_context *ctx, const hck_switch_key *swk, uint64_t *out,
                           size_t n_words) {
   ENTER(ctx);
+  OWNED(ctx, swk);
   if (!swk || !out) return set_error(HCK_EINVAL, "null argument");
   if (n_words != (size_t)ctx->dnum * 2 * (ctx->L + ctx->K) * ctx->n)
     return set_error(HCK_EINVAL, "size mismatch");
@@ -445,7 +495,8 @@ int hck_switch_key_export(hck_context *ctx, const hck_switch_key *swk, uint64_t 
 
 int hck_switch_key_destroy(hck_switch_key *swk) {
   if (swk) {
-    dev_free(swk->ctx, swk->data);
+    if (swk->ctx) untrack(swk->ctx, swk);
+    release_data<hck_switch_key>(swk);
     delete swk;
   }
   return HCK_OK;
@@ -472,6 +523,7 @@ int hck_switch_key_import(hck_context *ctx, const uint64_t *words, size_t n_word
     hck_switch_key_destroy(key);
     return rc;
   }
+  track(ctx, key, release_data<hck_switch_key>);
   *out = key;
   return HCK_OK;
 }
@@ -480,6 +532,7 @@ int hck_galois_keys_create(hck_context *ctx, hck_galois_keys **out) {
   if (!ctx || !out) return set_error(HCK_EINVAL, "null argument");
   hck_galois_keys *gks = new hck_galois_keys();
   gks->ctx = ctx;
+  track(ctx, gks, release_gks);
   *out = gks;
   return HCK_OK;
 }
@@ -488,8 +541,10 @@ int hck_galois_keys_insert(hck_galois_keys *gks, uint32_t element, hck_switch_ke
   if (!gks || !swk) return set_error(HCK_EINVAL, "null argument");
   if ((element & 1) == 0 || element >= 2 * gks->ctx->n)
     return set_error(HCK_EINVAL, "Galois element must be odd and below 2N");
-  if (swk->ctx != gks->ctx) return set_error(HCK_EINVAL, "key of another context");
+  if (!gks->ctx || swk->ctx != gks->ctx) return set_error(HCK_EINVAL, "key of another context");
   auto it = gks->keys.find(element);
+  if (it != gks->keys.end() && it->second == swk) return HCK_OK;
+  untrack(gks->ctx, swk);   // owned by the set from now on
   if (it != gks->keys.end()) hck_switch_key_destroy(it->second);
   gks->keys[element] = swk;
   return HCK_OK;
@@ -498,6 +553,7 @@ int hck_galois_keys_insert(hck_galois_keys *gks, uint32_t element, hck_switch_ke
 int hck_keygen_galois(hck_context *ctx, const hck_secret_key *sk, const uint32_t *elements,
                       uint32_t n, uint64_t seed, hck_galois_keys **out) {
   ENTER(ctx);
+  OWNED(ctx, sk);
   if (!sk || !out || (n && !elements)) return set_error(HCK_EINVAL, "null argument");
   for (uint32_t i = 0; i < n; i++)
     if ((elements[i] & 1) == 0 || elements[i] >= 2 * ctx->n)
@@ -522,6 +578,7 @@ int hck_keygen_galois(hck_context *ctx, const hck_secret_key *sk, const uint32_t
     hck_galois_keys_destroy(gks);
     return rc;
   }
+  track(ctx, gks, release_gks);
   *out = gks;
   return HCK_OK;
 }
@@ -529,6 +586,7 @@ int hck_keygen_galois(hck_context *ctx, const hck_secret_key *sk, const uint32_t
 int hck_keygen_rotation(hck_context *ctx, const hck_secret_key *sk, const int32_t *steps,
                         uint32_t n, uint64_t seed, hck_galois_keys **out) {
   ENTER(ctx);
+  OWNED(ctx, sk);
   if (n && !steps) return set_error(HCK_EINVAL, "null steps");
   std::vector<uint32_t> el;
   for (uint32_t i = 0; i < n; i++)
@@ -539,6 +597,7 @@ int hck_keygen_rotation(hck_context *ctx, const hck_secret_key *sk, const int32_
 int hck_galois_keys_export(hck_context *ctx, const hck_galois_keys *gks, uint32_t element,
                            uint64_t *out, size_t n_words) {
   ENTER(ctx);
+  OWNED(ctx, gks);
   if (!gks) return set_error(HCK_EINVAL, "null keys");
   auto it = gks->keys.find(element);
   if (it == gks->keys.end()) return set_error(HCK_ENOKEY, "no key for this element");
@@ -553,6 +612,7 @@ int hck_galois_keys_count(const hck_galois_keys *gks, uint32_t *n) {
 
 int hck_galois_keys_destroy(hck_galois_keys *gks) {
   if (gks) {
+    if (gks->ctx) untrack(gks->ctx, gks);
     for (auto &kv : gks->keys) hck_switch_key_destroy(kv.second);
     delete gks;
   }
@@ -575,6 +635,7 @@ static int plaintext_from_rows(hck_context *ctx, const uint64_t *res, uint32_t l
     delete pt;
     return rc;
   }
+  track(ctx, pt, release_data<hck_plaintext>);
   *out = pt;
   return HCK_OK;
 }
@@ -631,6 +692,7 @@ int hck_encode(hck_context *ctx, const double *re, const double *im, uint32_t n_
 int hck_plaintext_export(hck_context *ctx, const hck_plaintext *pt, uint64_t *out,
                          size_t n_words, uint32_t *level, double *scale) {
   ENTER(ctx);
+  OWNED(ctx, pt);
   if (!pt || !out) return set_error(HCK_EINVAL, "null argument");
   if (n_words < (size_t)(pt->level + 1) * ctx->n) return set_error(HCK_EINVAL, "buffer too small");
   if (level) *level = pt->level;
@@ -641,6 +703,7 @@ int hck_plaintext_export(hck_context *ctx, const hck_plaintext *pt, uint64_t *ou
 int hck_decode(hck_context *ctx, const hck_plaintext *pt, double *re, double *im,
                uint32_t n_slots) {
   ENTER(ctx);
+  OWNED(ctx, pt);
   if (!pt) return set_error(HCK_EINVAL, "null plaintext");
   if (n_slots != ctx->n / 2) return set_error(HCK_EINVAL, "n_slots must be N/2");
   std::vector<uint64_t> res((size_t)(pt->level + 1) * ctx->n);
@@ -651,7 +714,8 @@ int hck_decode(hck_context *ctx, const hck_plaintext *pt, double *re, double *im
 
 int hck_plaintext_destroy(hck_plaintext *pt) {
   if (pt) {
-    dev_free(pt->ctx, pt->data);
+    if (pt->ctx) untrack(pt->ctx, pt);
+    release_data<hck_plaintext>(pt);
     delete pt;
   }
   return HCK_OK;
@@ -664,6 +728,7 @@ int hck_ciphertext_create(hck_context *ctx, hck_ciphertext **out) {
   if (!out) return set_error(HCK_EINVAL, "null output");
   hck_ciphertext *ct = new hck_ciphertext();
   ct->ctx = ctx;
+  track(ctx, ct, release_ct);
   *out = ct;
   return HCK_OK;
 }
@@ -685,6 +750,7 @@ int hck_ciphertext_import(hck_context *ctx, const uint64_t *res, uint32_t size, 
   ct->size = size;
   ct->level = level;
   ct->scale = scale;
+  track(ctx, ct, release_ct);
   *out = ct;
   return HCK_OK;
 }
@@ -692,6 +758,7 @@ int hck_ciphertext_import(hck_context *ctx, const uint64_t *res, uint32_t size, 
 int hck_ciphertext_export(hck_context *ctx, const hck_ciphertext *ct, uint64_t *out,
                           size_t n_words, uint32_t *size, uint32_t *level, double *scale) {
   ENTER(ctx);
+  OWNED(ctx, ct);
   if (!ct || !out) return set_error(HCK_EINVAL, "null argument");
   if (ct->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
   if (n_words < (size_t)ct->size * (ct->level + 1) * ctx->n)
@@ -713,7 +780,8 @@ int hck_ciphertext_info(const hck_ciphertext *ct, uint32_t *size, uint32_t *leve
 
 int hck_ciphertext_destroy(hck_ciphertext *ct) {
   if (ct) {
-    if (ct->ctx) dev_free(ct->ctx, ct->data);
+    if (ct->ctx) untrack(ct->ctx, ct);
+    release_ct(ct);
     delete ct;
   }
   return HCK_OK;
@@ -722,6 +790,9 @@ int hck_ciphertext_destroy(hck_ciphertext *ct) {
 int hck_encrypt_sk(hck_context *ctx, const hck_secret_key *sk, const hck_plaintext *pt,
                    uint64_t seed, hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, sk);
+  OWNED(ctx, pt);
+  OWNED(ctx, out);
   if (!sk || !pt || !out) return set_error(HCK_EINVAL, "null argument");
   TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
   TRY(ensure_ct(ctx, out, 2));
@@ -753,6 +824,9 @@ int hck_encrypt_sk(hck_context *ctx, const hck_secret_key *sk, const hck_plainte
 int hck_encrypt_pk(hck_context *ctx, const hck_public_key *pk, const hck_plaintext *pt,
                    uint64_t seed, hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, pk);
+  OWNED(ctx, pt);
+  OWNED(ctx, out);
   if (!pk || !pt || !out) return set_error(HCK_EINVAL, "null argument");
   TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
   TRY(ensure_ct(ctx, out, 2));
@@ -784,6 +858,8 @@ int hck_encrypt_pk(hck_context *ctx, const hck_public_key *pk, const hck_plainte
 int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext *ct,
                 hck_plaintext **out) {
   ENTER(ctx);
+  OWNED(ctx, sk);
+  OWNED(ctx, ct);
   if (!sk || !ct || !out) return set_error(HCK_EINVAL, "null argument");
   if (ct->size < 2) return set_error(HCK_EINVAL, "empty ciphertext");
   TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
@@ -808,6 +884,7 @@ int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext
     hck_plaintext_destroy(pt);
     return rc;
   }
+  track(ctx, pt, release_data<hck_plaintext>);
   *out = pt;
   return HCK_OK;
 }
@@ -817,6 +894,9 @@ int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext
 static int addsub_ct(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
                      hck_ciphertext *out, int op) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, b);
+  OWNED(ctx, out);
   if (!a || !b || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size == 0 || a->size != b->size) return set_error(HCK_EINVAL, "sizes differ");
   if (a->level != b->level) return set_error(HCK_ELEVEL, "levels differ");
@@ -847,6 +927,9 @@ int hck_sub(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
 int hck_add_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
                   hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, pt);
+  OWNED(ctx, out);
   if (!a || !pt || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
   if (pt->level < a->level) return set_error(HCK_ELEVEL, "plaintext level below ciphertext level");
@@ -872,6 +955,9 @@ int hck_add_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext
 int hck_mul_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext *pt,
                   hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, pt);
+  OWNED(ctx, out);
   if (!a || !pt || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
   if (pt->level < a->level) return set_error(HCK_ELEVEL, "plaintext level below ciphertext level");
@@ -891,6 +977,8 @@ int hck_mul_plain(hck_context *ctx, const hck_ciphertext *a, const hck_plaintext
 int hck_drop_level(hck_context *ctx, const hck_ciphertext *a, uint32_t level,
                    hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, out);
   if (!a || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
   if (level > a->level) return set_error(HCK_ELEVEL, "cannot raise the level");
@@ -911,6 +999,9 @@ int hck_drop_level(hck_context *ctx, const hck_ciphertext *a, uint32_t level,
 int hck_mul(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
             hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, b);
+  OWNED(ctx, out);
   if (!a || !b || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size != 2 || b->size != 2) return set_error(HCK_EINVAL, "mul needs 2-part ciphertexts");
   if (a->level != b->level) return set_error(HCK_ELEVEL, "levels differ");
@@ -927,6 +1018,9 @@ int hck_mul(hck_context *ctx, const hck_ciphertext *a, const hck_ciphertext *b,
 int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *rlk,
                     hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, rlk);
+  OWNED(ctx, out);
   if (!a || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size != 3) return set_error(HCK_EINVAL, "relinearization needs a 3-part ciphertext");
   const uint32_t level = a->level;
@@ -944,13 +1038,20 @@ int hck_relinearize(hck_context *ctx, const hck_ciphertext *a, const hck_switch_
 int hck_relinearize_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n,
                          const hck_switch_key *rlk, hck_ciphertext *const *out) {
   ENTER(ctx);
+  OWNED(ctx, rlk);
   if ((n && (!a || !out)) || !rlk) return set_error(HCK_EINVAL, "null argument");
+  for (uint32_t i = 0; i < n; i++) {
+    OWNED(ctx, a[i]);
+    OWNED(ctx, out[i]);
+  }
   std::vector<const hck_switch_key *> keys(n, rlk);
   return relinearize_keys(ctx, a, keys.data(), n, out);
 }
 
 int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, out);
   if (!a || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
   if (a->level == 0) return set_error(HCK_ELEVEL, "no level left to rescale");
@@ -980,6 +1081,9 @@ int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out) 
 int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
                const hck_galois_keys *gks, hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, gks);
+  OWNED(ctx, out);
   if (!a || !out) return set_error(HCK_EINVAL, "null argument");
   if ((int64_t)step % (ctx->n / 2) == 0) {
     if (a == out) return HCK_OK;
@@ -999,6 +1103,9 @@ int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
 int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element,
                      const hck_galois_keys *gks, hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, gks);
+  OWNED(ctx, out);
   if (!a || !gks || !out) return set_error(HCK_EINVAL, "null argument");
   return apply_galois_core(ctx, a, element, gks, out);
 }
@@ -1006,6 +1113,9 @@ int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element
 int hck_keyswitch(hck_context *ctx, const hck_ciphertext *a, const hck_switch_key *swk,
                   hck_ciphertext *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, swk);
+  OWNED(ctx, out);
   if (!a || !swk || !out) return set_error(HCK_EINVAL, "null argument");
   if (a->size == 0) return set_error(HCK_EINVAL, "empty ciphertext");
   const uint32_t level = a->level;
@@ -1063,6 +1173,7 @@ static int lt_finish_create(hck_context *ctx, const std::vector<std::vector<uint
     hck_lt_destroy(lt);
     return rc;
   }
+  track(ctx, lt, release_lt);
   *out = lt;
   return HCK_OK;
 }
@@ -1149,12 +1260,15 @@ int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s) {
 int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int32_t *steps,
                      uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
   ENTER(ctx);
+  OWNED(ctx, gks);
   if ((n && (!a || !out || !steps)) || !gks) return set_error(HCK_EINVAL, "null argument");
   std::vector<const hck_ciphertext *> src;
   std::vector<hck_ciphertext *> dst;
   std::vector<uint32_t> gal;
   for (uint32_t i = 0; i < n; i++) {
     if (!a[i] || !out[i]) return set_error(HCK_EINVAL, "null ciphertext");
+    OWNED(ctx, a[i]);
+    OWNED(ctx, out[i]);
     for (uint32_t k = 0; k < n; k++)
       if ((k < i && out[k] == out[i]) || (k != i && out[k] == a[i]))
         return set_error(HCK_EINVAL, "outputs must be distinct and alias only their own input");
@@ -1174,9 +1288,13 @@ int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int
 int hck_rotate_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n, int32_t step,
                     const hck_galois_keys *gks, hck_ciphertext *const *out) {
   ENTER(ctx);
+  OWNED(ctx, gks);
   if ((n && (!a || !out)) || !gks) return set_error(HCK_EINVAL, "null argument");
-  for (uint32_t i = 0; i < n; i++)
+  for (uint32_t i = 0; i < n; i++) {
     if (!a[i] || !out[i]) return set_error(HCK_EINVAL, "null ciphertext");
+    OWNED(ctx, a[i]);
+    OWNED(ctx, out[i]);
+  }
   if ((int64_t)step % (ctx->n / 2) == 0) {
     for (uint32_t i = 0; i < n; i++) TRY(hck_rotate(ctx, a[i], step, gks, out[i]));
     return HCK_OK;
@@ -1187,6 +1305,8 @@ int hck_rotate_many(hck_context *ctx, const hck_ciphertext *const *a, uint32_t n
 int hck_rotate_hoisted(hck_context *ctx, const hck_ciphertext *a, const int32_t *steps,
                        uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out) {
   ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, gks);
   if (!a || !gks || (n && (!steps || !out))) return set_error(HCK_EINVAL, "null argument");
   if (a->size != 2) return set_error(HCK_EINVAL, "rotation needs a 2-part ciphertext");
   std::vector<uint32_t> gal;
@@ -1196,6 +1316,7 @@ int hck_rotate_hoisted(hck_context *ctx, const hck_ciphertext *a, const int32_t 
   bool alias = false;
   for (uint32_t i = 0; i < n; i++) {
     if (!out[i]) return set_error(HCK_EINVAL, "null output");
+    OWNED(ctx, out[i]);
     for (uint32_t k = 0; k < i; k++)
       if (out[k] == out[i]) return set_error(HCK_EINVAL, "outputs must be distinct");
     alias = alias || out[i] == a;
@@ -1253,9 +1374,13 @@ int hck_lt_eval(hck_context *ctx, const hck_ciphertext *const *in, uint32_t n_in
                 const hck_galois_keys *gks, hck_ciphertext *const *out, uint32_t n_out,
                 uint32_t flags) {
   ENTER(ctx);
+  OWNED(ctx, gks);
   if (!in || !lts || !term_in || !term_out || !out || !gks || n_in == 0 || n_terms == 0 ||
       n_out == 0)
     return set_error(HCK_EINVAL, "null or empty argument");
+  for (uint32_t i = 0; i < n_in; i++) OWNED(ctx, in[i]);
+  for (uint32_t i = 0; i < n_out; i++) OWNED(ctx, out[i]);
+  for (uint32_t t = 0; t < n_terms; t++) OWNED(ctx, lts[t]);
   const uint32_t level = in[0]->level;
   uint32_t n1 = 0;
   for (uint32_t i = 0; i < n_in; i++) {
@@ -1573,7 +1698,8 @@ int hck_lt_apply(hck_context *ctx, const hck_linear_transform *lt, const hck_cip
 
 int hck_lt_destroy(hck_linear_transform *lt) {
   if (lt) {
-    for (uint64_t *p : lt->owned) dev_free(lt->ctx, p);
+    if (lt->ctx) untrack(lt->ctx, lt);
+    release_lt(lt);
     delete lt;
   }
   return HCK_OK;

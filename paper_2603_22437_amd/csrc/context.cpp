@@ -387,9 +387,27 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
   return HCK_OK;
 }
 
+void track(hck_context *ctx, void *obj, void (*release)(void *)) { ctx->handles[obj] = release; }
+
+void untrack(hck_context *ctx, void *obj) { ctx->handles.erase(obj); }
+
+void track_server(hck_context *ctx, void *srv, void (*release)(void *)) {
+  ctx->servers[srv] = release;
+}
+
+void untrack_server(hck_context *ctx, void *srv) { ctx->servers.erase(srv); }
+
 void destroy_context(hck_context *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  // servers stop their workers first; then every live handle gives back its
+  // device memory and is detached
+  auto servers = std::move(ctx->servers);
+  ctx->servers.clear();
+  for (auto &kv : servers) kv.second(kv.first);
+  auto handles = std::move(ctx->handles);
+  ctx->handles.clear();
+  for (auto &kv : handles) kv.second(kv.first);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx, ctx->ws);
   dev_free(ctx, ctx->lt_scratch);

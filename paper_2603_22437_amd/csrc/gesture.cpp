@@ -198,6 +198,9 @@ int hck_gesture_eval_taps(hck_context *ctx, const hck_gesture_plan *p, const hck
                           const hck_switch_key *rlk, hck_ciphertext *out,
                           hck_ciphertext *const *taps) {
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (foreign(ctx, re) || foreign(ctx, im) || foreign(ctx, gks) || foreign(ctx, rlk) ||
+      foreign(ctx, out))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
   if (taps)
     for (int i = 0; i < HCK_GESTURE_TAPS; i++)
       if (taps[i] && (taps[i] == re || taps[i] == im))
@@ -235,8 +238,12 @@ int hck_gesture_eval_frames(hck_context *ctx, const hck_gesture_plan *p,
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
   if (n_frames == 0 || n_frames > HCK_GESTURE_MAX_FRAMES)
     return set_error(HCK_EINVAL, "frame count out of range");
+  if (foreign(ctx, gks) || foreign(ctx, rlk) || foreign(ctx, out))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
   for (uint32_t f = 0; f < n_frames; f++) {
     if (!re[f] || !im[f]) return set_error(HCK_EINVAL, "null frame ciphertext");
+    if (foreign(ctx, re[f]) || foreign(ctx, im[f]))
+      return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
     if (re[f]->level != re[0]->level || im[f]->level != re[0]->level)
       return set_error(HCK_ELEVEL, "frame ciphertexts must share a level");
     if (re[f]->scale != re[0]->scale || im[f]->scale != re[0]->scale)

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "hipckks.h"
@@ -95,6 +96,15 @@ struct hck_context {
   uint64_t live_allocs = 0;
 
   bool broken = false;
+
+  // Caller-owned objects made on this context and not yet destroyed, each
+  // with the function that releases its device memory and detaches it
+  // (sets its ctx to null).  hck_context_destroy releases servers first
+  // (their workers use the context and the other handles), then every other
+  // handle; a handle's own destroy call afterwards frees only its host
+  // record.  So destroy calls may come in any order.
+  std::unordered_map<void *, void (*)(void *)> handles;
+  std::unordered_map<void *, void (*)(void *)> servers;
 
   // kernel timing
   bool timing = false;
@@ -197,6 +207,19 @@ int check_hip(hck_context *ctx, hipError_t e, const char *what);
     hipError_t _e = (expr);                                         \
     if (_e != hipSuccess) return ::hck::check_hip((ctx), _e, #expr); \
   } while (0)
+
+// ---- ownership of caller handles (context.cpp) ----
+void track(hck_context *ctx, void *obj, void (*release)(void *));
+void untrack(hck_context *ctx, void *obj);   // no-op for an untracked object
+void track_server(hck_context *ctx, void *srv, void (*release)(void *));
+void untrack_server(hck_context *ctx, void *srv);
+
+// true when a handle is not of this context (or was detached from a
+// destroyed one)
+template <class T>
+inline bool foreign(const hck_context *ctx, const T *h) {
+  return h && h->ctx != ctx;
+}
 
 // ---- device memory ----
 int dev_alloc(hck_context *ctx, uint64_t **p, size_t words);

@@ -57,6 +57,8 @@ extern "C" {
 int hck_poly_eval(hck_context *ctx, const hck_ciphertext *x, const double *coeffs,
                   uint32_t degree, const hck_switch_key *rlk, hck_ciphertext *out) {
   if (!ctx || !x || !coeffs || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (foreign(ctx, x) || foreign(ctx, rlk) || foreign(ctx, out))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
   if (out == x) return set_error(HCK_EINVAL, "the output must not alias the input");
   if (degree < 1 || degree > 64) return set_error(HCK_EINVAL, "degree must be 1..64");
   bool any = false;

@@ -480,6 +480,36 @@ void worker_main(hck_server *s) {
   }
 }
 
+// stops the worker and releases every resource of the server; the server
+// record stays, detached from its context (the context's destroy call runs
+// this for servers still alive, before it releases the other handles, which
+// the tenants' plans reference)
+void server_shutdown(void *p) {
+  hck_server *s = static_cast<hck_server *>(p);
+  if (!s->ctx) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  s->worker.join();
+  hck_context *ctx = s->ctx;
+  (void)hipSetDevice(ctx->device);
+  for (auto &kv : s->tenants) drop_keys(s, kv.second);
+  s->tenants.clear();
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(s->copy);
+  for (auto *q : s->slots_in) (void)hipHostFree(q);
+  for (auto *q : s->slots_out) (void)hipHostFree(q);
+  s->slots_in.clear();
+  s->slots_out.clear();
+  for (auto e : s->free_events) (void)hipEventDestroy(e);
+  s->free_events.clear();
+  (void)hipStreamDestroy(s->copy);
+  s->copy = nullptr;
+  s->ctx = nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -515,6 +545,7 @@ int hck_server_create(hck_context *ctx, const hck_server_config *cfg, hck_server
   }
   s->stats.budget = cfg->hbm_budget;
   s->worker = std::thread(worker_main, s);
+  track_server(ctx, s, server_shutdown);
   *out = s;
   return HCK_OK;
 }
@@ -524,6 +555,7 @@ int hck_server_add_tenant(hck_server *s, uint32_t tenant, uint32_t kind, const v
                           const uint64_t *rlk_words) {
   if (!s || !plan || !rlk_words || (n_steps && (!steps || !gk_words)))
     return set_error(HCK_EINVAL, "null argument");
+  if (!s->ctx) return set_error(HCK_EINVAL, "the server's context was destroyed");
   if (kind != HCK_SERVE_VITAL && kind != HCK_SERVE_GESTURE)
     return set_error(HCK_EINVAL, "unknown pipeline kind");
   hck_context *ctx = s->ctx;
@@ -563,6 +595,7 @@ int hck_server_submit(hck_server *s, uint64_t request, uint32_t tenant, const ui
                       const uint64_t *im_words, uint32_t level, double scale, uint64_t *out_words,
                       size_t out_capacity) {
   if (!s || !re_words || !im_words || !out_words) return set_error(HCK_EINVAL, "null argument");
+  if (!s->ctx) return set_error(HCK_EINVAL, "the server's context was destroyed");
   hck_context *ctx = s->ctx;
   if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
   const size_t half = (size_t)2 * (level + 1) * ctx->n;
@@ -634,21 +667,10 @@ int hck_server_stats_get(hck_server *s, hck_server_stats *out) {
 
 int hck_server_destroy(hck_server *s) {
   if (!s) return HCK_OK;
-  {
-    std::lock_guard<std::mutex> g(s->mu);
-    s->stop = true;
-    s->cv_work.notify_all();
+  if (s->ctx) {
+    untrack_server(s->ctx, s);
+    server_shutdown(s);
   }
-  s->worker.join();
-  hck_context *ctx = s->ctx;
-  (void)hipSetDevice(ctx->device);
-  for (auto &kv : s->tenants) drop_keys(s, kv.second);
-  (void)hipStreamSynchronize(ctx->stream);
-  (void)hipStreamSynchronize(s->copy);
-  for (auto *p : s->slots_in) (void)hipHostFree(p);
-  for (auto *p : s->slots_out) (void)hipHostFree(p);
-  for (auto e : s->free_events) (void)hipEventDestroy(e);
-  (void)hipStreamDestroy(s->copy);
   delete s;
   return HCK_OK;
 }

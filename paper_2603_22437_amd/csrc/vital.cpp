@@ -467,13 +467,20 @@ int vital_eval_batch(hck_context *ctx, const hck_vital_plan *p, const hck_cipher
 
 }  // namespace hck
 
-// outputs and taps must not alias an input
-static int check_aliases(const hck_ciphertext *const *re, const hck_ciphertext *const *im,
-                         uint32_t n, hck_ciphertext *const *out, uint32_t n_out) {
-  for (uint32_t i = 0; i < n_out; i++)
+// outputs and taps must not alias an input, and all belong to the context
+static int check_aliases(const hck_context *ctx, const hck_ciphertext *const *re,
+                         const hck_ciphertext *const *im, uint32_t n, hck_ciphertext *const *out,
+                         uint32_t n_out) {
+  for (uint32_t k = 0; k < n; k++)
+    if (foreign(ctx, re[k]) || foreign(ctx, im[k]))
+      return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
+  for (uint32_t i = 0; i < n_out; i++) {
+    if (foreign(ctx, out[i]))
+      return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
     for (uint32_t k = 0; k < n; k++)
       if (out[i] && (out[i] == re[k] || out[i] == im[k]))
         return set_error(HCK_EINVAL, "outputs must not alias inputs");
+  }
   return HCK_OK;
 }
 
@@ -490,8 +497,10 @@ int hck_vital_eval_taps(hck_context *ctx, const hck_vital_plan *p, const hck_cip
                         const hck_switch_key *rlk, hck_ciphertext *const *out,
                         hck_ciphertext *const *taps) {
   if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
-  TRY(check_aliases(&re, &im, 1, out, 4));
-  if (taps) TRY(check_aliases(&re, &im, 1, taps, HCK_VITAL_TAPS));
+  if (foreign(ctx, gks) || foreign(ctx, rlk))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
+  TRY(check_aliases(ctx, &re, &im, 1, out, 4));
+  if (taps) TRY(check_aliases(ctx, &re, &im, 1, taps, HCK_VITAL_TAPS));
   return vital_eval_windows(ctx, p, &re, &im, 1, WindowKeys{&gks, &rlk}, out, taps);
 }
 
@@ -502,7 +511,9 @@ int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,
   if (!ctx || !gks || !rlk || (n && (!re || !im || !out)))
     return set_error(HCK_EINVAL, "null argument");
   if (n == 0) return HCK_OK;
-  TRY(check_aliases(re, im, n, out, 4 * n));
+  if (foreign(ctx, gks) || foreign(ctx, rlk))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
+  TRY(check_aliases(ctx, re, im, n, out, 4 * n));
   std::vector<const hck_galois_keys *> g(n, gks);
   std::vector<const hck_switch_key *> rl(n, rlk);
   return vital_eval_windows(ctx, p, re, im, n, WindowKeys{g.data(), rl.data()}, out, nullptr);

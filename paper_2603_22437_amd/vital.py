@@ -63,8 +63,8 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
             ang = 2.0 * np.pi * k * frames / F
             vr[frames * R + lane] = norm * win * np.cos(ang)
             vi[frames * R + lane] = -norm * win * np.sin(ang)
-            out["freq"][lane] = 60.0 * k * cfg["fps"] / F
-            out["mask"][lane] = 1.0
+            out["freq"][lane] = 60.0 * k * cfg["fps"] / F * cfg.get("rate_gain", 1.0)
+            out["mask"][lane] = cfg.get("rate_gain", 1.0)
         out["dft_re_" + band], out["dft_im_" + band] = vr, vi
     return out
 
@@ -179,8 +179,10 @@ def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
     out += [(lanes, xr), (lanes, xi), (lanes, pw), (lanes, sh)]
     n_resp = len(cfg["k_resp"])
     two = np.array([0, G])
+    a = cfg.get("rate_gain", 1.0)
     out += [(np.array([0]), np.array([np.sum(np.arange(R) * w) / F ** 2])),
             (np.array([0]), np.array([np.sum(w) / F ** 2])),
-            (two, np.array([np.sum(fq[:n_resp] * sh[:n_resp]), np.sum(fq[n_resp:] * sh[n_resp:])])),
-            (two, np.array([np.sum(sh[:n_resp]), np.sum(sh[n_resp:])]))]
+            (two, a * np.array([np.sum(fq[:n_resp] * sh[:n_resp]),
+                                np.sum(fq[n_resp:] * sh[n_resp:])])),
+            (two, a * np.array([np.sum(sh[:n_resp]), np.sum(sh[n_resp:])]))]
     return out

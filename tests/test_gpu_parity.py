@@ -4,9 +4,11 @@ Every test feeds the same seeded inputs to the HIP library and to the CPU
 oracle and requires bit-identical residues (coefficient domain, fully
 reduced).  Inputs are either uniform residue arrays from ``seeded_inputs`` or
 objects both sides derive from the same seeds (keys, encryptions).  Ring
-sizes: N = 2^12 (L = 3, K = 1), N = 2^15 (L = 12, K = 4) and the benchmark's
-N = 2^16, L = 24, K = 8, dnum = 3; levels from the top down to 0 exercise
-ragged last digits.
+sizes: N = 2^12 (L = 3, K = 1), N = 2^15 (L = 12, K = 4), the benchmark's
+N = 2^16, L = 24, K = 8 and the gesture shape N = 2^16, L = 30, K = 10 (ten
+60-bit special primes, where the basis-conversion sums come closest to their
+2^64 bound), all with dnum = 3; levels from the top down to 0 exercise ragged
+last digits.
 """
 import numpy as np
 import pytest
@@ -58,7 +60,7 @@ def pair(name):
     return _pairs[name]
 
 
-CONFIGS = ["tiny", "mix15", "vital"]
+CONFIGS = ["tiny", "mix15", "vital", "gesture"]
 
 
 @pytest.mark.parametrize("name", CONFIGS)
@@ -184,7 +186,7 @@ def test_tensor_relin_rescale_match_oracle(name):
     assert np.array_equal(p.export(t3), o.rescale(t_o).polys)
 
 
-@pytest.mark.parametrize("name", ["tiny", "vital"])
+@pytest.mark.parametrize("name", ["tiny", "vital", "gesture"])
 def test_elementwise_match_oracle(name):
     p = pair(name)
     o = p.o
@@ -250,7 +252,8 @@ def test_rotate_steps_matches_single_rotations(name):
     in-place member and more members than one batch holds."""
     p = pair(name)
     o = p.o
-    steps = [1, 3, 0, 5, 1, -2, 3, 5, 1, 7] if name != "vital" else [1, 3, 0, 1, 3, 1, 3, 1, 3, 1]
+    steps = ([1, 3, 0, 5, 1, -2, 3, 5, 1, 7] if name in ("tiny", "mix15")
+             else [1, 3, 0, 1, 3, 1, 3, 1, 3, 1])
     gks, gko = p.galois(steps)
     level = o.L - 1 if name != "mix15" else o.L // 2
     cts = [p.rand_ct(level, 1100 + i) for i in range(len(steps))]
@@ -316,7 +319,7 @@ def test_lt_eval_complex_dft_matches_oracle(name, d, n1):
     assert np.array_equal(p.export(got2[1]), want[1].polys)
 
 
-@pytest.mark.parametrize("name", ["tiny", "mix15", "vital"])
+@pytest.mark.parametrize("name", ["tiny", "mix15", "vital", "gesture"])
 def test_hoisted_rotations_match_oracle(name):
     p = pair(name)
     o = p.o
@@ -446,7 +449,8 @@ def test_relinearize_many_matches_oracle(name):
     level = o.L - 1 if name == "tiny" else o.L // 2
     rlk = p.ctx.keygen_relin(p.sk, 7)
     rlk_o = o.keygen_relin(p.s_o, 7)
-    cts = [p.rand_ct(level, 1800 + i, size=3) for i in range(10 if name != "vital" else 9)]
+    cts = [p.rand_ct(level, 1800 + i, size=3)
+           for i in range(10 if name in ("tiny", "mix15") else 9)]
     outs = [p.ctx.ciphertext() for _ in range(len(cts) - 1)] + [cts[-1][0]]
     p.ctx.relinearize_many([c for c, _ in cts], rlk, outs)
     for (c, c_o), out in zip(cts, outs):

@@ -5,7 +5,9 @@ them from host memory into HBM when needed.  Every served result is compared
 bit for bit with the plain call (hck_vital_eval / hck_gesture_eval) on the
 same window with the tenant's original keys: the same result alone and in the
 mix, under a budget that forces evictions, and in batches that mix tenants.
-Also: imported keys act exactly like the keys they were exported from.
+A vital and a gesture window served together are also compared bit for bit
+with the oracle's pipeline compositions.  Also: imported keys act exactly
+like the keys they were exported from.
 """
 import numpy as np
 import pytest
@@ -203,3 +205,78 @@ def test_server_errors(world):
         assert len(got) == 1 and got[0]["request"] == 7 and got[0]["status"] != 0
     finally:
         srv.close()
+
+
+def _import_ops(ctx, ops):
+    """GPU handles of an oracle-encoded plan's operands (same integers)."""
+    import oracle as O
+    handles = {}
+    for name, v in ops.items():
+        if isinstance(v, O.LinearTransform):
+            res = {g * v.n1 + b: pt.res for g, items in v.groups.items() for b, pt in items}
+            handles[name] = ctx.lt_create_from_residues(res, v.n1, v.level, v.scale)
+        else:
+            handles[name] = ctx.plaintext_import(v.res, v.level, v.scale)
+    return handles
+
+
+def test_served_windows_match_the_oracle(world):
+    """One vital and one gesture window served together (two tenants, one
+    server) give the residues of the oracle's pipeline compositions on the
+    same encrypted windows: the operands are encoded once by the oracle and
+    imported, and the tenants' key words are the oracle's own keys."""
+    import oracle as O
+    from oracle import gesture as OG
+    from oracle import vital as OV
+    w = world
+    ctx, prm, l0 = w["ctx"], w["prm"], w["l0"]
+    o = O.Oracle(prm)
+    vcfg, gcfg = w["vcfg"], w["gcfg"]
+    vops = OV.encode_operands(o, vcfg, l0)
+    gops = OG.encode_operands(o, gcfg, l0, prm["scale"])
+    vh, gh = _import_ops(ctx, vops), _import_ops(ctx, gops)
+    vplan = H.VitalPlan.build(vcfg["frames"], vcfg["bins"], vcfg["taylor_order"],
+                              len(vcfg["k_resp"]), len(vcfg["k_hr"]), vh,
+                              vcfg.get("mag_coeffs"), vcfg.get("gamma", 2))
+    gplan = H.GesturePlan.build(gcfg["frames"], gcfg["bins"], gcfg["chirps"],
+                                gcfg["weights"][0].shape[0], gh)
+    cases = {}
+    for t, kind, mod, cfg, ops, plan in ((40, H.SERVE_VITAL, OV, vcfg, vops, vplan),
+                                         (41, H.SERVE_GESTURE, OG, gcfg, gops, gplan)):
+        s_o = o.keygen_secret(60 + t)
+        steps = mod.required_steps(o, cfg, ops)
+        gko = {o.galois_element(k): o.keygen_galois(s_o, o.galois_element(k), 70 + t)
+               for k in steps}
+        rlk_o = o.keygen_relin(s_o, 80 + t)
+        if kind == H.SERVE_VITAL:
+            z = S.vital_window(1600 + t, cfg["frames"], cfg["bins"])
+        else:
+            z = S.gesture_window(1600 + t, cfg["frames"])
+        re_o, im_o = mod.encrypt_window(o, s_o, z, l0, prm["scale"], 90 + 2 * t)
+        want = mod.evaluate(o, cfg, ops, re_o, im_o, gko, rlk_o)
+        want = [want[n] for n in OV.OUTPUTS] if kind == H.SERVE_VITAL else [want]
+        words = [np.ascontiguousarray(gko[o.galois_element(k)], dtype=np.uint64) for k in steps]
+        cases[t] = dict(kind=kind, plan=plan, steps=steps, words=words,
+                        rlk=np.ascontiguousarray(rlk_o, dtype=np.uint64),
+                        re=re_o.polys, im=im_o.polys, want=want)
+    srv = H.Server(ctx, 1 << 40, 8, 8)
+    try:
+        for t, c in cases.items():
+            srv.add_tenant(t, c["kind"], c["plan"], c["steps"], c["words"], c["rlk"])
+        for t, c in cases.items():
+            srv.submit(t, t, c["re"], c["im"], l0, prm["scale"])
+        done = {}
+        while len(done) < len(cases):
+            got = srv.poll(timeout_ms=20000)
+            assert got, "server made no progress for 20 s"
+            for r in got:
+                done[r["request"]] = r
+    finally:
+        srv.close()
+    for t, c in cases.items():
+        r = done[t]
+        assert r["status"] == 0, t
+        assert len(r["outputs"]) == len(c["want"])
+        for got, want, lvl, sc in zip(r["outputs"], c["want"], r["levels"], r["scales"]):
+            assert lvl == want.level and sc == want.scale, t
+            assert np.array_equal(got, want.polys), t

@@ -177,8 +177,8 @@ def test_vital_taps_follow_plaintext_execution():
 
 def test_vital_inputs_above_the_plan_level_are_dropped():
     """A plan encoded for inputs at level 12 of 24 (the depth, 11, plus one
-    level of headroom: the rate numerators, fourth powers of the spectrum,
-    reach 1e6 on strong windows, beyond what q0 holds at scale 2^50):
+    level of headroom for the rate numerators, fourth powers of the spectrum
+    times frequencies, whose magnitude depends on the window):
     top-level inputs are dropped to it, giving exactly the residues of inputs
     the caller dropped, and the decoded outputs of the plaintext circuit."""
     prm = S.params("vital")
@@ -201,14 +201,14 @@ def test_vital_inputs_above_the_plan_level_are_dropped():
     assert [c.level for c in got] == [1, 1, 1, 1]
     want = OV.plain_slots(cfg, z, ctx.n_slots)
     dec = {name: ctx.decode(ctx.decrypt(sk, g)).real for name, g in zip(OV.OUTPUTS, got)}
-    # the bin outputs within 1e-3; the rate numerators and denominators reach
-    # 1e6 on this strong window, so they are checked relatively, and the
-    # client's quantity, the rate in beats per minute, within 1e-3
+    # every output within 1e-3 absolute (the rate averages carry the public
+    # rate_gain, which keeps them far below 10^6 on this strong window), and
+    # the client's quantity, the rate in beats per minute, within 1e-3
     for name in ("num_bin", "den_bin"):
         assert abs(dec[name][0] - want[name][0]) < 1e-3, name
     for name in ("num_rates", "den_rates"):
         for slot, val in want[name].items():
-            assert abs(dec[name][slot] - val) <= 1e-6 * max(1.0, abs(val)), (name, slot)
+            assert abs(dec[name][slot] - val) < 1e-3, (name, slot, val)
     for slot in want["num_rates"]:
         bpm = dec["num_rates"][slot] / dec["den_rates"][slot]
         assert abs(bpm - want["num_rates"][slot] / want["den_rates"][slot]) < 1e-3, slot
