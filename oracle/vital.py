@@ -38,8 +38,8 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
       part)
   K1  P = Re X^2 + Im X^2
   K2  S = P^gamma; num = sum_c a f_c S_c, den = sum_c a S_c over each lane
-      group (f_c the bin frequency in beats per minute, a the public
-      rate_gain of the configuration; rotations 1 .. G/2)
+      group (f_c the bin frequency in beats per minute, a the band's public
+      factor from the configuration's rate_gain; rotations 1 .. G/2)
 
 Outputs: num_bin, den_bin (value in slot 0; the target bin r^ = num / den),
 num_rates, den_rates (respiration in slot 0, heart rate in slot G; rate in
@@ -103,6 +103,13 @@ def layout(cfg: dict, n_slots: int) -> Layout:
                   {"resp": _pow2_at_least(nr), "hr": _pow2_at_least(g + nh)})
 
 
+def _gain(cfg: dict, band: str) -> float:
+    """Public factor a of one band's rate average (per band, or one number
+    for both; 1 if absent)."""
+    g = cfg.get("rate_gain", 1.0)
+    return float(g[band] if isinstance(g, dict) else g)
+
+
 def operand_vectors(cfg: dict, n_slots: int) -> dict:
     """Real slot vectors of every public plaintext operand, and the FIR
     transforms' generalized diagonals (offset -> vector)."""
@@ -141,8 +148,8 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
             c = c0 + i
             re[t * r + c] = w * np.cos(2 * np.pi * k * t / f) / ws
             im[t * r + c] = -w * np.sin(2 * np.pi * k * t / f) / ws
-            fr[c] = 60.0 * k * cfg["fps"] / f * cfg.get("rate_gain", 1.0)
-            mk[c] = cfg.get("rate_gain", 1.0)
+            fr[c] = 60.0 * k * cfg["fps"] / f * _gain(cfg, band)
+            mk[c] = _gain(cfg, band)
         v[f"dft_re_{band}"] = re
         v[f"dft_im_{band}"] = im
     v["freq"] = fr
@@ -335,7 +342,7 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
         xi = np.array([-np.sum(win * np.sin(2 * np.pi * k * t / f) * dphi) for k in ks]) / ws
         s = (xr ** 2 + xi ** 2) ** cfg.get("gamma", 2)
         fk = 60.0 * ks * cfg["fps"] / f
-        g = cfg.get("rate_gain", 1.0)
+        g = _gain(cfg, band)
         out[f"num_{band}"] = float(g * np.sum(fk * s))
         out[f"den_{band}"] = float(g * np.sum(s))
     return out

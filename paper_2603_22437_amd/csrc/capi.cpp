@@ -1062,16 +1062,15 @@ int hck_rescale(hck_context *ctx, const hck_ciphertext *a, hck_ciphertext *out) 
   const size_t n = ctx->n, ps = poly_stride(ctx);
   uint64_t *last = ws_tmp(ctx);
   uint64_t *lift = last + (size_t)size * n;
-  std::vector<std::pair<uint16_t, uint8_t>> lrows, trows;
+  std::vector<std::pair<uint16_t, uint8_t>> lrows;
   for (uint32_t p = 0; p < size; p++) {
     TRY(launch_copy(ctx, last + p * n, a->data + p * ps + (size_t)level * n, n));
     lrows.push_back({(uint16_t)p, (uint8_t)level});
-    for (uint32_t i = 0; i < level; i++) trows.push_back({(uint16_t)(p * level + i), (uint8_t)i});
   }
+  // dropped limb to coefficient form; then per target limb its centred lift,
+  // forward transform and (c_i - t) q_l^-1, in two fused passes
   TRY(ntt_inverse(ctx, last, make_map(lrows, 0), nullptr));
-  TRY(launch_rescale_lift(ctx, lift, last, level, size));
-  TRY(ntt_forward_rows(ctx, lift, trows));
-  TRY(launch_rescale_tail(ctx, out->data, a->data, lift, level, size));
+  TRY(rescale_fused(ctx, out->data, a->data, last, lift, level, size));
   out->size = size;
   out->level = level - 1;
   out->scale = scale;

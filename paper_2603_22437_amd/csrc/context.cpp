@@ -280,7 +280,7 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
     c.ninv = h_invmod(n % q, q);
     c.ninv_shoup = h_shoup(c.ninv, q);
     c.r2 = h_mulmod(c.r64, c.r64, q);
-    c.pad = 0;
+    c.one_shoup = h_shoup(1, q);
     const uint64_t psi = primitive_2n_root(q, n), ipsi = h_invmod(psi, q);
     pw[0] = ipw[0] = 1;
     for (uint32_t i = 1; i < n; i++) {

@@ -28,7 +28,7 @@ struct ModConst {
   uint64_t ninv;        // N^-1 mod q
   uint64_t ninv_shoup;
   uint64_t r2;          // 2^128 mod q (Montgomery fix-up of a plain product)
-  uint64_t pad;
+  uint64_t one_shoup;   // floor(2^64 / q): Shoup companion of 1 (reduction of any word)
 };
 
 // Which rows of a [row][N] buffer a launch processes (blockIdx.y indexes the
@@ -250,6 +250,11 @@ int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const 
 // one pass (strided or contiguous, forward or inverse) in place; an inverse
 // strided pass with `scale` uses entry (row list index mod period) (period 0:
 // the list index itself)
+// Rescale of polys polynomials at `level` (in and out strided by the
+// polynomial stride, out may be in): last holds each polynomial's dropped limb
+// in coefficient form ([0, q_level)), tmp has room for polys x level limbs.
+int rescale_fused(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint64_t *last,
+                  uint64_t *tmp, uint32_t level, uint32_t polys);
 int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
              const RowScale *scale, int period = 0);
 

@@ -178,37 +178,6 @@ __global__ __launch_bounds__(kThreads) void k_embed_small(uint64_t *out, const i
   out[(size_t)map.row[blockIdx.y] * n + i] = v < 0 ? q - (uint64_t)(-(int64_t)v) : (uint64_t)v;
 }
 
-// Centred lift of the dropped limb (coefficient domain, values in [0, q_l))
-// into row i < l: v if v <= (q_l - 1) / 2, else v - q_l, reduced mod q_i.
-// blockIdx.z selects the polynomial: last + z n, out + z l n.
-__global__ __launch_bounds__(kThreads) void k_rescale_lift(uint64_t *out, const uint64_t *last,
-                                                           uint32_t level,
-                                                           const ModConst *__restrict__ mc,
-                                                           int n) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  const uint32_t r = blockIdx.y;
-  const uint64_t ql = mc[level].q;
-  const uint64_t qi = mc[r].q;
-  const uint64_t one_p = (uint64_t)(((unsigned __int128)1 << 64) / qi);  // Shoup of 1
-  const uint64_t v = last[(size_t)blockIdx.z * n + i];
-  uint64_t t = shoup(v, 1, one_p, qi);
-  if (v > (ql - 1) / 2) t = sub_mod(t, shoup(ql, 1, one_p, qi), qi);
-  out[((size_t)blockIdx.z * level + r) * n + i] = t;
-}
-
-__global__ __launch_bounds__(kThreads) void k_rescale_tail(uint64_t *out, const uint64_t *c,
-                                                           const uint64_t *t, RowScale sc,
-                                                           size_t ps, uint32_t level,
-                                                           const ModConst *__restrict__ mc,
-                                                           int n) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
-  const uint32_t r = blockIdx.y;
-  const uint64_t q = mc[r].q;
-  const size_t off = (size_t)r * n + i + blockIdx.z * ps;
-  const uint64_t tv = t[((size_t)blockIdx.z * level + r) * n + i];
-  out[off] = shoup(sub_mod(c[off], tv, q), sc.w[r], sc.wp[r], q);
-}
-
 // out[r] += REDC(in[r] c_r): adds a per-row constant multiple of a
 // Montgomery-form operand.
 __global__ __launch_bounds__(kThreads) void k_scalar_mac(uint64_t *out, const uint64_t *in,
@@ -369,34 +338,6 @@ int launch_embed_small(hck_context *ctx, uint64_t *out, const int32_t *small, co
   timing_begin(ctx, "embed", (8.0 * map.n + 4.0) * ctx->n);
   k_embed_small<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, small, map, ctx->d_mod,
                                                                       ctx->n);
-  timing_end(ctx);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
-}
-
-int launch_rescale_lift(hck_context *ctx, uint64_t *out, const uint64_t *last, uint32_t level,
-                        uint32_t polys) {
-  timing_begin(ctx, "rescale_lift", 8.0 * ctx->n * polys * (1 + level));
-  k_rescale_lift<<<grid_rows(ctx, level, polys), kThreads, 0, ctx->stream>>>(out, last, level,
-                                                                             ctx->d_mod, ctx->n);
-  timing_end(ctx);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
-}
-
-int launch_rescale_tail(hck_context *ctx, uint64_t *out, const uint64_t *c, const uint64_t *t,
-                        uint32_t level, uint32_t polys) {
-  RowScale sc;
-  for (uint32_t i = 0; i < level; i++) {
-    sc.w[i] = ctx->rescale_inv[level][i];
-    sc.wp[i] = h_shoup(sc.w[i], ctx->mods[i]);
-    sc.add[i] = 0;
-  }
-  const size_t ps = (size_t)ctx->L * ctx->n;
-  timing_begin(ctx, "rescale_tail", 24.0 * ctx->n * level * polys,
-               (double)ctx->n * level * polys);
-  k_rescale_tail<<<grid_rows(ctx, level, polys), kThreads, 0, ctx->stream>>>(
-      out, c, t, sc, ps, level, ctx->d_mod, ctx->n);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;

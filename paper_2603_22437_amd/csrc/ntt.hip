@@ -78,6 +78,100 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
   }
 }
 
+// Rescale, forward half (strided pass): the dropped limb of polynomial
+// blockIdx.z (coefficient form, [0, q_l)) is lifted to its centred value
+// (v - q_l when v > (q_l - 1) / 2) modulo target limb i = blockIdx.y as it is
+// loaded, then the forward strided pass of limb i runs on it.  last holds one
+// limb per polynomial; tmp gets rows z level + i.  qmod.add[i] = q_l mod q_i.
+template <int LOGN>
+__global__ __launch_bounds__(kNttThreads) void k_rescale_strided(
+    uint64_t *__restrict__ tmp, const uint64_t *__restrict__ last, uint32_t level,
+    RowScale qmod, const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
+    const uint64_t *__restrict__ tws) {
+  using G = Pass<split_a(LOGN), LOGN, true>;
+  constexpr int P = G::P;
+  __shared__ uint64_t lds[G::LDS_WORDS];
+  const uint32_t i = blockIdx.y, z = blockIdx.z;
+  const ModConst m = mc[i];
+  const uint64_t half = (mc[level].q - 1) / 2, ql_i = qmod.add[i];
+  const uint64_t *src = last + (size_t)z * G::N;
+  const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
+  const int g = blockIdx.x * G::TR + c;
+  uint64_t x[P];
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const uint64_t v = src[G::gaddr(g, G::ipoint(r, k))];
+    const uint64_t t = shoup(v, 1, m.one_shoup, m.q);
+    x[k] = v > half ? sub_mod(t, ql_i, m.q) : t;
+  }
+  G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, m.q);
+  uint64_t *out = tmp + ((size_t)z * level + i) * G::N;
+#pragma unroll
+  for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+}
+
+// Rescale, tail (contiguous pass): finishes the forward transform of the
+// lifted limb t and writes out_i = (c_i - t) q_l^-1 mod q_i for i < level
+// (inv.w / inv.wp: q_l^-1 mod q_i and its Shoup companion).  out may be c.
+template <int LOGN>
+__global__ __launch_bounds__(kNttThreads) void k_rescale_contig_tail(
+    uint64_t *out, const uint64_t *c_in, const uint64_t *__restrict__ tmp, size_t ps,
+    uint32_t level, RowScale inv, const ModConst *__restrict__ mc,
+    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
+  using G = Pass<split_b(LOGN), LOGN, false>;
+  constexpr int P = G::P;
+  __shared__ uint64_t lds[G::LDS_WORDS];
+  const uint32_t i = blockIdx.y, z = blockIdx.z;
+  const uint64_t q = mc[i].q;
+  const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
+  const int g = blockIdx.x * G::TR + c;
+  const uint64_t *tin = tmp + ((size_t)z * level + i) * G::N;
+  uint64_t x[P];
+#pragma unroll
+  for (int k = 0; k < P; k++) x[k] = tin[G::gaddr(g, G::ipoint(r, k))];
+  G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, q);
+#pragma unroll
+  for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
+  G::to_interleaved(lds, x, c, r);
+  const size_t off = (size_t)z * ps + (size_t)i * G::N;
+  const uint64_t w = inv.w[i], wp = inv.wp[i];
+#pragma unroll
+  for (int k = 0; k < P; k++) {
+    const size_t pos = off + G::gaddr(g, G::ipoint(r, k));
+    out[pos] = shoup(sub_mod(c_in[pos], x[k], q), w, wp, q);
+  }
+}
+
+template <int LOGN>
+int run_rescale(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint64_t *last,
+                uint64_t *tmp, uint32_t level, uint32_t polys) {
+  constexpr int A = split_a(LOGN), B = split_b(LOGN);
+  constexpr double N = (double)(1 << LOGN);
+  using GA = Pass<A, LOGN, true>;
+  using GB = Pass<B, LOGN, false>;
+  RowScale qmod, inv;
+  for (uint32_t i = 0; i < level; i++) {
+    qmod.add[i] = ctx->mods[level] % ctx->mods[i];
+    qmod.w[i] = qmod.wp[i] = 0;
+    inv.w[i] = ctx->rescale_inv[level][i];
+    inv.wp[i] = h_shoup(inv.w[i], ctx->mods[i]);
+    inv.add[i] = 0;
+  }
+  const size_t ps = (size_t)ctx->L * ctx->n;
+  timing_begin(ctx, "rescale_strided", 8.0 * N * polys * (1 + level),
+               N * (1 + 0.5 * A) * polys * level);
+  k_rescale_strided<LOGN><<<dim3(GA::BLOCKS, level, polys), kNttThreads, 0, ctx->stream>>>(
+      tmp, last, level, qmod, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  timing_end(ctx);
+  timing_begin(ctx, "rescale_tail", 24.0 * N * polys * level,
+               N * (1 + 0.5 * B) * polys * level);
+  k_rescale_contig_tail<LOGN><<<dim3(GB::BLOCKS, level, polys), kNttThreads, 0, ctx->stream>>>(
+      out, in, tmp, ps, level, inv, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  timing_end(ctx);
+  HCK_HIP(ctx, hipGetLastError());
+  return HCK_OK;
+}
+
 template <int LOGN, bool STRIDED, bool INVERSE>
 void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
                  const RowScale *sc, int period = 0) {
@@ -160,6 +254,22 @@ int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const 
     case 15: return run_inverse<15>(ctx, dst, src, map, sc);
     case 16: return run_inverse<16>(ctx, dst, src, map, sc);
     case 17: return run_inverse<17>(ctx, dst, src, map, sc);
+    default: return set_error(HCK_EPARAMS, "unsupported ring degree");
+  }
+}
+
+int rescale_fused(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint64_t *last,
+                  uint64_t *tmp, uint32_t level, uint32_t polys) {
+  if (level == 0 || polys == 0) return HCK_OK;
+  if (level > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "too many limbs");
+  switch (ctx->log_n) {
+    case 11: return run_rescale<11>(ctx, out, in, last, tmp, level, polys);
+    case 12: return run_rescale<12>(ctx, out, in, last, tmp, level, polys);
+    case 13: return run_rescale<13>(ctx, out, in, last, tmp, level, polys);
+    case 14: return run_rescale<14>(ctx, out, in, last, tmp, level, polys);
+    case 15: return run_rescale<15>(ctx, out, in, last, tmp, level, polys);
+    case 16: return run_rescale<16>(ctx, out, in, last, tmp, level, polys);
+    case 17: return run_rescale<17>(ctx, out, in, last, tmp, level, polys);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }

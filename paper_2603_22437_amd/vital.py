@@ -63,10 +63,17 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
             ang = 2.0 * np.pi * k * frames / F
             vr[frames * R + lane] = norm * win * np.cos(ang)
             vi[frames * R + lane] = -norm * win * np.sin(ang)
-            out["freq"][lane] = 60.0 * k * cfg["fps"] / F * cfg.get("rate_gain", 1.0)
-            out["mask"][lane] = cfg.get("rate_gain", 1.0)
+            out["freq"][lane] = 60.0 * k * cfg["fps"] / F * band_gain(cfg, band)
+            out["mask"][lane] = band_gain(cfg, band)
         out["dft_re_" + band], out["dft_im_" + band] = vr, vi
     return out
+
+
+def band_gain(cfg: dict, band: str) -> float:
+    """The public factor of a band's rate average (1 when the configuration
+    has none; a number applies to both bands)."""
+    g = cfg.get("rate_gain", 1.0)
+    return float(g[band] if isinstance(g, dict) else g)
 
 
 def lane_group(cfg: dict) -> int:
@@ -179,7 +186,7 @@ def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
     out += [(lanes, xr), (lanes, xi), (lanes, pw), (lanes, sh)]
     n_resp = len(cfg["k_resp"])
     two = np.array([0, G])
-    a = cfg.get("rate_gain", 1.0)
+    a = np.array([band_gain(cfg, "resp"), band_gain(cfg, "hr")])
     out += [(np.array([0]), np.array([np.sum(np.arange(R) * w) / F ** 2])),
             (np.array([0]), np.array([np.sum(w) / F ** 2])),
             (two, a * np.array([np.sum(fq[:n_resp] * sh[:n_resp]),

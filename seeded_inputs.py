@@ -252,18 +252,21 @@ def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
     k fps / frames) inside each band.  The two gains are normalization
     constants folded into public weights (as section 3.3.3 folds s^gamma / F
     into W^(1)) so that the cubic Taylor term and the spectra stay near 1 on
-    unit-normalized windows.  rate_gain = dft_gain^(-2 gamma), folded into the
-    frequency weights and the mask of the rate averages, takes the DFT gain
-    back out of their numerators and denominators (S = P^gamma carries it to
-    the power 2 gamma), so that those outputs stay O(1) to O(10^3) instead of
-    reaching 10^6; the rates, their ratios, do not change.  With magnitude_degree > 0 the configuration also
+    unit-normalized windows.  rate_gain holds one public factor per band,
+    folded into the frequency weights and the mask of that band's rate
+    average (its numerator and denominator, not their ratio, the rate):
+    S = P^gamma is an amplitude^24 quantity whose size spans about 18 decades
+    over synthetic windows, and the factors (10^3 respiration, 10^-1 heart
+    rate) put the median window's sums near 1, where the decoded sums keep
+    1e-3 absolute accuracy and their ratio stays well conditioned against the
+    absolute noise of the lane-sum rotations.  With magnitude_degree > 0 the configuration also
     carries the power-basis coefficients of a polynomial magnitude (sqrt_poly),
     which the bin estimate's energy sums instead of the power."""
     res = fps / frames
     bands = {"resp": (0.1, 0.6), "hr": (0.8, 2.5)}
     cfg = dict(frames=frames, bins=bins, fps=fps, taylor_order=taylor_order,
                window=np.hanning(frames), dft_gain=dft_gain, gamma=gamma,
-               rate_gain=float(dft_gain) ** (-2 * gamma), fir_backend=fir_backend)
+               rate_gain={"resp": 1e3, "hr": 1e-1}, fir_backend=fir_backend)
     if magnitude_degree:
         # the bin estimate's energy sums a polynomial magnitude instead of the power
         cfg["mag_coeffs"] = sqrt_poly(magnitude_degree)

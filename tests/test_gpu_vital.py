@@ -20,6 +20,22 @@ from paper_2603_22437_amd import vital as HV
 pytestmark = pytest.mark.gpu
 
 
+def decoded_tol(v: float) -> float:
+    """Decoded-output bound against plaintext: 1e-3 absolute, and 1e-8
+    relative for outputs above 10^5.  The rate sums are fourth powers of the
+    phase spectrum (S = P^2, P = |X|^2), spanning about 18 decades over
+    windows; CKKS noise after a product is relative to its operands' size,
+    measured at 2.5e-9 of the value at scale 2^50."""
+    return max(1e-3, 1e-8 * abs(v))
+
+
+def well_conditioned(den: float, ratio: float) -> bool:
+    """Whether the client's ratio num / den is asserted to 1e-3: the decoded
+    sums carry an absolute noise floor of about 2e-8 (the lane-sum
+    rotations), which moves the ratio by about 2e-8 (1 + |ratio|) / den."""
+    return den > 1e-4 * (1.0 + abs(ratio))
+
+
 def _import_plan(ctx, o, cfg, ops):
     """GPU plan holding the oracle's encoded operands."""
     handles = {}
@@ -87,12 +103,17 @@ def test_vital_pipeline_decodes_at_benchmark_ring():
     for name, g in zip(OV.OUTPUTS, got):
         dec[name] = ctx.decode(ctx.decrypt(sk, g)).real
         for slot, v in want[name].items():
-            assert abs(dec[name][slot] - v) < 1e-3, (name, slot, dec[name][slot], v)
+            assert abs(dec[name][slot] - v) < decoded_tol(v), (name, slot, dec[name][slot], v)
     # the client's divisions (section 3.3.4)
+    checked = 0
     for num, den in (("num_bin", "den_bin"), ("num_rates", "den_rates")):
         for slot in want[num]:
-            est = dec[num][slot] / dec[den][slot]
-            assert abs(est - want[num][slot] / want[den][slot]) < 1e-3, (num, slot)
+            ratio = want[num][slot] / want[den][slot]
+            if well_conditioned(want[den][slot], ratio):
+                est = dec[num][slot] / dec[den][slot]
+                assert abs(est - ratio) < 1e-3, (num, slot, est, ratio)
+                checked += 1
+    assert checked == 3    # both rates and the bin on this window
 
 
 def test_vital_plan_errors():
@@ -201,17 +222,19 @@ def test_vital_inputs_above_the_plan_level_are_dropped():
     assert [c.level for c in got] == [1, 1, 1, 1]
     want = OV.plain_slots(cfg, z, ctx.n_slots)
     dec = {name: ctx.decode(ctx.decrypt(sk, g)).real for name, g in zip(OV.OUTPUTS, got)}
-    # every output within 1e-3 absolute (the rate averages carry the public
-    # rate_gain, which keeps them far below 10^6 on this strong window), and
-    # the client's quantity, the rate in beats per minute, within 1e-3
+    # every output within the decoded tolerance, and the client's quantity,
+    # the rate in beats per minute, within 1e-3 (both bands are well
+    # conditioned on this strong window)
     for name in ("num_bin", "den_bin"):
         assert abs(dec[name][0] - want[name][0]) < 1e-3, name
     for name in ("num_rates", "den_rates"):
         for slot, val in want[name].items():
-            assert abs(dec[name][slot] - val) < 1e-3, (name, slot, val)
+            assert abs(dec[name][slot] - val) < decoded_tol(val), (name, slot, val)
     for slot in want["num_rates"]:
+        ratio = want["num_rates"][slot] / want["den_rates"][slot]
+        assert well_conditioned(want["den_rates"][slot], ratio), slot
         bpm = dec["num_rates"][slot] / dec["den_rates"][slot]
-        assert abs(bpm - want["num_rates"][slot] / want["den_rates"][slot]) < 1e-3, slot
+        assert abs(bpm - ratio) < 1e-3, slot
     low = ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], 11), 102)
     with pytest.raises(H.HckError):   # below the plan's level
         ctx.vital_eval(plan, low, low, gks, rlk)
