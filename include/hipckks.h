@@ -262,6 +262,26 @@ int hck_rotate_steps(hck_context *ctx, const hck_ciphertext *const *a, const int
  * distinct; one may alias a.  Errors: HCK_ENOKEY, HCK_EINVAL. */
 int hck_rotate_hoisted(hck_context *ctx, const hck_ciphertext *a, const int32_t *steps,
                        uint32_t n, const hck_galois_keys *gks, hck_ciphertext *const *out);
+/* hck_rotate without any allocation, for callers that cannot allocate
+ * device memory (work under HIP stream capture, serving loops that forbid
+ * hipMalloc).  Residues equal hck_rotate's.  The key switch runs in a static
+ * device array of the library (160 MiB per GPU, held from the library's first
+ * use of it on that GPU until the process ends) instead of the context's
+ * workspace; no hipMalloc, hipFree or allocating library call is made (a few
+ * hundred bytes of host memory hold launch tables).  `out` must already hold
+ * room for two polynomials: the result or import of an earlier call (a fresh
+ * hck_ciphertext_create handle has none: HCK_EINVAL).  out may alias a.
+ * Every call on one GPU shares its array and overwrites it: calls that
+ * overlap in time on one GPU (other streams, contexts or threads) race, and
+ * the caller must serialize them.  Errors: HCK_EINVAL when the context needs
+ * more than the array holds (hck_rotate_noalloc_scratch), HCK_ENOKEY,
+ * HCK_EDEVICE. */
+int hck_rotate_noalloc(hck_context *ctx, const hck_ciphertext *a, int32_t step,
+                       const hck_galois_keys *gks, hck_ciphertext *out);
+/* Bytes of the static array hck_rotate_noalloc needs for this context (one
+ * key-switch slot of (L + dnum (L+K) + 2 (L+K) + 2L) limbs plus L limbs),
+ * or the array's size for ctx = NULL. */
+size_t hck_rotate_noalloc_scratch(const hck_context *ctx);
 /* The same for an explicit Galois element (e.g. 2N-1: conjugation). */
 int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element,
                      const hck_galois_keys *gks, hck_ciphertext *out);

@@ -96,6 +96,8 @@ SIGNATURES = {
     "hck_relinearize": ([_P, _P, _P, _P], _I),
     "hck_rescale": ([_P, _P, _P], _I),
     "hck_rotate": ([_P, _P, _I32, _P, _P], _I),
+    "hck_rotate_noalloc": ([_P, _P, _I32, _P, _P], _I),
+    "hck_rotate_noalloc_scratch": ([_P], _SZ),
     "hck_apply_galois": ([_P, _P, _U32, _P, _P], _I),
     "hck_rotate_many": ([_P, _P, _U32, _I32, _P, _P], _I),
     "hck_rotate_steps": ([_P, _P, _P, _U32, _P, _P], _I),
@@ -615,6 +617,17 @@ class Context:
         out = self._out(out)
         _check(capi.hck_rotate(self.h, a, step, gks, out))
         return out
+
+    def rotate_noalloc(self, a, step: int, gks, out):
+        """hck_rotate without allocation (the library's static scratch
+        array): `out` must already hold two polynomials (an earlier result
+        or import).  Calls on one GPU must not overlap in time."""
+        _check(capi.hck_rotate_noalloc(self.h, a, step, gks, out))
+        return out
+
+    def rotate_noalloc_scratch(self) -> int:
+        """Bytes of the static array a no-allocation rotation needs here."""
+        return int(capi.hck_rotate_noalloc_scratch(self.h))
 
     def rotate_many(self, cts, step: int, gks, outs=None):
         outs = [self.ciphertext() for _ in cts] if outs is None else outs

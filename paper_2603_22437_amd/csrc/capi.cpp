@@ -1099,6 +1099,20 @@ int hck_rotate(hck_context *ctx, const hck_ciphertext *a, int32_t step,
   return apply_galois_core(ctx, a, galois_of_step(ctx, step), gks, out);
 }
 
+int hck_rotate_noalloc(hck_context *ctx, const hck_ciphertext *a, int32_t step,
+                       const hck_galois_keys *gks, hck_ciphertext *out) {
+  ENTER(ctx);
+  OWNED(ctx, a);
+  OWNED(ctx, gks);
+  OWNED(ctx, out);
+  if (!a || !out) return set_error(HCK_EINVAL, "null argument");
+  return rotate_noalloc(ctx, a, step, gks, out);
+}
+
+size_t hck_rotate_noalloc_scratch(const hck_context *ctx) {
+  return ctx ? noalloc_scratch_needed(ctx) : noalloc_scratch_bytes();
+}
+
 int hck_apply_galois(hck_context *ctx, const hck_ciphertext *a, uint32_t element,
                      const hck_galois_keys *gks, hck_ciphertext *out) {
   ENTER(ctx);

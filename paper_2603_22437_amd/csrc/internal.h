@@ -345,6 +345,14 @@ struct KsBatch {
   const uint64_t *add1[kMaxBatch];
 };
 int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level);
+// keyswitch_batch in the given workspace (ws_ks_rows rows per batch slot;
+// no allocation)
+int keyswitch_batch_ws(hck_context *ctx, const KsBatch &batch, uint32_t level, uint64_t *ws);
+// hck_rotate in the library's static scratch array (noalloc.hip)
+int rotate_noalloc(hck_context *ctx, const hck_ciphertext *a, int32_t step,
+                   const hck_galois_keys *gks, hck_ciphertext *out);
+size_t noalloc_scratch_bytes();
+size_t noalloc_scratch_needed(const hck_context *ctx);
 // largest batch keyswitch_batch accepts at this level (row limits of one launch)
 uint32_t ks_batch_limit(const hck_context *ctx, uint32_t level);
 // the largest batch one launch sequence can take at this level (row limits)

@@ -362,14 +362,13 @@ KsGeom make_geom(const hck_context *ctx, uint32_t level) {
 
 // K1-K3 for batch slots 0..nb-1 (ModUp into each slot's ext rows)
 template <int LOGN>
-int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
+int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws) {
   constexpr int A = split_a(LOGN), B = split_b(LOGN);
   constexpr double N = (double)(1 << LOGN);
   using GA = Pass<A, LOGN, true>;
   using GB = Pass<B, LOGN, false>;
   const uint32_t L = kg.L, nm = kg.nm, alpha = kg.alpha, nq = kg.nq, ne = kg.ne, nb = kb.n;
   const uint32_t level = kg.level;
-  uint64_t *ws = ws_ks(ctx);
   int rc;
   timing_begin(ctx, "ks_intt_gather", 16.0 * N * nq * nb, 0.5 * N * B * nq * nb);
   k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nb, nq), kNttThreads, 0, ctx->stream>>>(
@@ -465,13 +464,12 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
 
 // K5-K7 for batch slots 0..nb-1 (ModDown of each slot's acc rows)
 template <int LOGN>
-int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
+int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws) {
   constexpr int A = split_a(LOGN), B = split_b(LOGN);
   constexpr double N = (double)(1 << LOGN);
   using GA = Pass<A, LOGN, true>;
   using GB = Pass<B, LOGN, false>;
   const uint32_t L = kg.L, K = kg.K, nq = kg.nq, ne = kg.ne, nb = kb.n;
-  uint64_t *ws = ws_ks(ctx);
   int rc;
   {
     LimbMap mp;
@@ -526,14 +524,14 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg) {
 }
 
 template <int LOGN>
-int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level) {
+int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *ws) {
   constexpr int B = split_b(LOGN);
   constexpr double N = (double)(1 << LOGN);
   using GB = Pass<B, LOGN, false>;
   const KsGeom kg = make_geom(ctx, level);
   const uint32_t nq = kg.nq, ne = kg.ne, nb = kb.n, alpha = kg.alpha;
   int rc;
-  if ((rc = ks_modup<LOGN>(ctx, kb, kg))) return rc;
+  if ((rc = ks_modup<LOGN>(ctx, kb, kg, ws))) return rc;
   const double digits = (double)((nq + alpha - 1) / alpha);
   const double ext_limbs = nb * (digits * ne - nq);
   double keys = 0;  // distinct keys in the batch
@@ -546,9 +544,9 @@ int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level) {
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * keys),
                N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
   k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(
-      ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+      ws, kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
-  return ks_moddown<LOGN>(ctx, kb, kg);
+  return ks_moddown<LOGN>(ctx, kb, kg, ws);
 }
 
 template <int LOGN>
@@ -563,7 +561,7 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
   up.n = 1;
   up.galois[0] = 1;
   up.d[0] = c1;
-  if ((rc = ks_modup<LOGN>(ctx, up, kg))) return rc;
+  if ((rc = ks_modup<LOGN>(ctx, up, kg, ws_ks(ctx)))) return rc;
   // finish the forward transform of slot 0's extended digits in place
   std::vector<std::pair<uint16_t, uint8_t>> rows;
   for (uint32_t j = 0; j < kg.dnum; j++) {
@@ -602,7 +600,7 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
           ws_ks(ctx), c1, galois[s + b], b, keys[s + b]->data, kg, ctx->d_mod);
       timing_end(ctx);
     }
-    if ((rc = ks_moddown<LOGN>(ctx, kb, kg))) return rc;
+    if ((rc = ks_moddown<LOGN>(ctx, kb, kg, ws_ks(ctx)))) return rc;
   }
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
@@ -618,7 +616,7 @@ int ks_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *const *
   const KsGeom kg = make_geom(ctx, level);
   const uint32_t nq = kg.nq, ne = kg.ne, nb = kb.n, alpha = kg.alpha;
   int rc;
-  if ((rc = ks_modup<LOGN>(ctx, kb, kg))) return rc;
+  if ((rc = ks_modup<LOGN>(ctx, kb, kg, ws_ks(ctx)))) return rc;
   const double digits = (double)((nq + alpha - 1) / alpha);
   const double ext_limbs = nb * (digits * ne - nq);
   timing_begin(ctx, "ks_contig_inner",
@@ -658,7 +656,7 @@ int md_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, const uint64_t *c
     if ((rc = launch_copy(ctx, ws_ks(ctx) + ((size_t)b * kg.slot_rows + kg.off_acc) * ctx->n,
                           pq[b], (size_t)2 * kg.ne * ctx->n)))
       return rc;
-  return ks_moddown<LOGN>(ctx, kb, kg);
+  return ks_moddown<LOGN>(ctx, kb, kg, ws_ks(ctx));
 }
 
 }  // namespace
@@ -683,17 +681,22 @@ int keyswitch_batch(hck_context *ctx, const KsBatch &kb, uint32_t level) {
   if (kb.n > ks_slots(ctx)) return set_error(HCK_EINVAL, "batch too large");
   int rc = ensure_workspace(ctx, ws_words_needed(ctx));
   if (rc) return rc;
+  return keyswitch_batch_ws(ctx, kb, level, ws_ks(ctx));
+}
+
+int keyswitch_batch_ws(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *ws) {
+  if (kb.n == 0) return HCK_OK;
   if (level + 1 > (uint32_t)kMaxLimbs || (level + 1) * kb.n > (uint32_t)kMaxRows ||
       2 * ctx->K * kb.n > (uint32_t)kMaxRows)
     return set_error(HCK_EINVAL, "level too high for one batched launch");
   switch (ctx->log_n) {
-    case 11: return ks_run<11>(ctx, kb, level);
-    case 12: return ks_run<12>(ctx, kb, level);
-    case 13: return ks_run<13>(ctx, kb, level);
-    case 14: return ks_run<14>(ctx, kb, level);
-    case 15: return ks_run<15>(ctx, kb, level);
-    case 16: return ks_run<16>(ctx, kb, level);
-    case 17: return ks_run<17>(ctx, kb, level);
+    case 11: return ks_run<11>(ctx, kb, level, ws);
+    case 12: return ks_run<12>(ctx, kb, level, ws);
+    case 13: return ks_run<13>(ctx, kb, level, ws);
+    case 14: return ks_run<14>(ctx, kb, level, ws);
+    case 15: return ks_run<15>(ctx, kb, level, ws);
+    case 16: return ks_run<16>(ctx, kb, level, ws);
+    case 17: return ks_run<17>(ctx, kb, level, ws);
     default: return set_error(HCK_EPARAMS, "unsupported ring degree");
   }
 }
