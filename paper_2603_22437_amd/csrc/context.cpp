@@ -269,7 +269,12 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
   std::vector<ModConst> mc(nm);
   std::vector<uint64_t> tw((size_t)nm * n), tws((size_t)nm * n), itw((size_t)nm * n),
       itws((size_t)nm * n);
+  std::vector<uint64_t> ttw((size_t)nm * n), ttws((size_t)nm * n), ittw((size_t)nm * n),
+      ittws((size_t)nm * n);
   std::vector<uint64_t> pw(n), ipw(n);
+  // contiguous-pass twists (ntt_core.h): word w = g R2 + i of a limb gets
+  // beta_g^i with beta_g = psi^(2 brv_a(g)), a = log2 of the strided radix
+  const int log_a = (ctx->log_n + 1) / 2, log_b = ctx->log_n / 2;
   for (uint32_t m = 0; m < nm; m++) {
     const uint64_t q = ctx->mods[m];
     ModConst &c = mc[m];
@@ -293,6 +298,19 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
       tws[(size_t)m * n + k] = h_shoup(pw[b], q);
       itw[(size_t)m * n + k] = ipw[b];
       itws[(size_t)m * n + k] = h_shoup(ipw[b], q);
+    }
+    for (uint32_t g = 0; g < (1u << log_a); g++) {
+      const uint64_t bg = 2ull * bit_reverse(g, log_a);
+      for (uint32_t i = 0; i < (1u << log_b); i++) {
+        const uint64_t e = bg * i % (2ull * n);   // psi^N = -1
+        const uint64_t f = e < n ? pw[e] : (q - pw[e - n]) % q;
+        const uint64_t fi = e < n ? ipw[e] : (q - ipw[e - n]) % q;
+        const size_t w = (size_t)m * n + ((size_t)g << log_b) + i;
+        ttw[w] = f;
+        ttws[w] = h_shoup(f, q);
+        ittw[w] = fi;
+        ittws[w] = h_shoup(fi, q);
+      }
     }
   }
 
@@ -377,6 +395,9 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
   if ((rc = up((uint64_t **)&ctx->d_mod, mc.data(), nm * sizeof(ModConst))) ||
       (rc = up(&ctx->d_tw, tw.data(), tb)) || (rc = up(&ctx->d_tw_shoup, tws.data(), tb)) ||
       (rc = up(&ctx->d_itw, itw.data(), tb)) || (rc = up(&ctx->d_itw_shoup, itws.data(), tb)) ||
+      (rc = up(&ctx->d_ttw, ttw.data(), tb)) || (rc = up(&ctx->d_ttw_shoup, ttws.data(), tb)) ||
+      (rc = up(&ctx->d_ittw, ittw.data(), tb)) ||
+      (rc = up(&ctx->d_ittw_shoup, ittws.data(), tb)) ||
       (rc = up(&ctx->d_up_conv, up_conv.data(), up_conv.size() * 8)) ||
       (rc = up(&ctx->d_down_conv, down_conv.data(), down_conv.size() * 8)) ||
       (rc = up(&ctx->d_down_hneg, ctx->down_hneg.data(), ctx->down_hneg.size() * 8))) {
@@ -420,7 +441,9 @@ void destroy_context(hck_context *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   else (void)hipDeviceSynchronize();
   for (void *p : {(void *)ctx->d_mod, (void *)ctx->d_tw, (void *)ctx->d_tw_shoup,
-                  (void *)ctx->d_itw, (void *)ctx->d_itw_shoup, (void *)ctx->d_up_conv,
+                  (void *)ctx->d_itw, (void *)ctx->d_itw_shoup, (void *)ctx->d_ttw,
+                  (void *)ctx->d_ttw_shoup, (void *)ctx->d_ittw, (void *)ctx->d_ittw_shoup,
+                  (void *)ctx->d_up_conv,
                   (void *)ctx->d_down_conv, (void *)ctx->d_down_hneg})
     if (p) (void)hipFree(p);
   for (auto &t : ctx->pending) {

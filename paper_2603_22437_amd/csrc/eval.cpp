@@ -100,10 +100,11 @@ int apply_galois_keys(hck_context *ctx, const hck_ciphertext *const *a, const ui
       // input gets a copy of c0 to read instead
       if ((rc = ensure_ct(ctx, y, 2))) return rc;
       const uint64_t *c0 = x->data, *c1 = x->data + ps;
+      kb.add0_src[b] = nullptr;
       if (y == x) {
-        uint64_t *copy = ws_rot(ctx) + (size_t)b * ps;
-        if ((rc = launch_copy(ctx, copy, x->data, (size_t)(level + 1) * ctx->n))) return rc;
-        c0 = copy;
+        // the first launch copies c0 into the workspace for the last one
+        kb.add0_src[b] = x->data;
+        c0 = ws_rot(ctx) + (size_t)b * ps;
       }
       kb.key[b] = keys[s + b]->data;
       kb.galois[b] = g[s + b];

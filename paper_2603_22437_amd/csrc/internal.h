@@ -62,6 +62,10 @@ struct hck_context {
   uint64_t *d_tw_shoup = nullptr;
   uint64_t *d_itw = nullptr;         // [L+K][N] psi^-brv(k)
   uint64_t *d_itw_shoup = nullptr;
+  uint64_t *d_ttw = nullptr;         // [L+K][N] contiguous-pass twist beta_g^i (ntt_core.h)
+  uint64_t *d_ttw_shoup = nullptr;
+  uint64_t *d_ittw = nullptr;        // [L+K][N] inverse twist beta_g^-i
+  uint64_t *d_ittw_shoup = nullptr;
   // basis conversion matrices (Montgomery form, per (level, digit) or ModDown)
   uint64_t *d_up_conv = nullptr;     // [L][dnum][alpha][L+K]
   uint64_t *d_down_conv = nullptr;   // [K][L+K] (columns < L used)
@@ -333,7 +337,10 @@ uint64_t *ws_pq(hck_context *ctx);    // [kLtOut][2][L+K][N]: extended-basis sum
 // (out0[b], out1[b]) = KeySwitch(phi_g(d[b])) + (phi_g(add0[b]), phi_g(add1[b])).
 // d and the addends are [level+1][N] in evaluation form; g = 1 for no
 // automorphism; null addends are skipped.  out rows must not overlap d; with
-// g != 1 they must not overlap the addends.
+// g != 1 they must not overlap the addends.  An output that aliases its
+// input's c0 sets add0_src[b] = c0 and add0[b] = a workspace copy of
+// [level+1][N] words: the first launch copies c0 there before the last
+// launch overwrites it (null: add0 is read in place).
 struct KsBatch {
   uint32_t n;
   const uint64_t *key[kMaxBatch];
@@ -343,6 +350,7 @@ struct KsBatch {
   uint64_t *out1[kMaxBatch];
   const uint64_t *add0[kMaxBatch];
   const uint64_t *add1[kMaxBatch];
+  const uint64_t *add0_src[kMaxBatch] = {};
 };
 int keyswitch_batch(hck_context *ctx, const KsBatch &batch, uint32_t level);
 // keyswitch_batch in the given workspace (ws_ks_rows rows per batch slot;
@@ -364,9 +372,11 @@ inline uint32_t even_batch(size_t left, uint32_t limit) {
   return (uint32_t)((left + batches - 1) / batches);
 }
 // K1-K4 of keyswitch_batch without ModDown: slot b's key products
-// (acc0, acc1) in Q_level u P are added into pq[b] ([2][level+1+K][N],
-// evaluation form), or stored there when first[b]; slots may share a pq
-// buffer.  out/add fields of the batch are unused.
+// (acc0, acc1) in Q_level u P are added into pq[b] ([2][level+1+K][N];
+// Q limbs in evaluation form, P limbs after ModDown's inverse contiguous
+// pass, a linear map, so sums stay consistent), or stored there when
+// first[b]; slots may share a pq buffer.  out/add fields of the batch are
+// unused.  Only moddown_pq reads pq.
 int keyswitch_pq(hck_context *ctx, const KsBatch &batch, uint32_t level, uint64_t *const *pq,
                  const bool *first);
 // ModDown of n extended-basis pairs pq[b] ([2][level+1+K][N]) to Q_level:

@@ -5,7 +5,8 @@
 // KeySwitch(d) at level l with a switching key swk(s' -> s); d is read through
 // the NTT-domain automorphism X -> X^g (g = 1: no automorphism), so a
 // rotation never materializes phi_g(c):
-//   K1  inverse contiguous pass of phi_g(d) over Q_l -> y          (gather)
+//   K1  inverse contiguous pass of phi_g(d) over Q_l -> y          (gather;
+//       also the copy of c0 for an output that aliases its input)
 //   K2  inverse strided pass, times N^-1 (Q_j / q_i)^-1 per limb    (digit scale)
 //   K3  ModUp: per digit j and target limb t not in D_j, the fast basis
 //       conversion of y's digit limbs computed at load time, then the
@@ -13,7 +14,8 @@
 //   K4  per extended limb t: forward contiguous pass of every digit's ext
 //       (or phi_g(d) itself on the digit's own limbs), then
 //       acc_{0,1}[t] = sum_j d~_j[t] swk_j[t] (keys in Montgomery form); slots
-//       that share a key re-read its tiles from cache
+//       that share a key re-read its tiles from cache; on the P limbs the
+//       inverse contiguous pass of K5 follows in the same kernel
 //   K5  inverse passes of acc's P limbs, times N^-1 (P/p_k)^-1, plus
 //       ((P-1)/2) (P/p_k)^-1 (the rounding term of ModDown)
 //   K6  ModDown conversion P -> q_i (minus (P-1)/2) at load time, then the
@@ -65,7 +67,8 @@ template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
     uint64_t *__restrict__ ws, KsBatch kb, KsGeom kg,
     const ModConst *__restrict__ mc, const uint64_t *__restrict__ itw,
-    const uint64_t *__restrict__ itws) {
+    const uint64_t *__restrict__ itws, const uint64_t *__restrict__ itt,
+    const uint64_t *__restrict__ itts) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
@@ -78,14 +81,65 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
   uint64_t *y = ws + (size_t)b * kg.slot_rows * G::N;
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
+  if (const uint64_t *c0 = kb.add0_src[b]) {
+    // an output aliasing its input: copy this tile of c0 for the last launch
+    uint64_t *cp = const_cast<uint64_t *>(kb.add0[b]);
+#pragma unroll
+    for (int i = 0; i < P; i++) {
+      const size_t a = roff + G::gaddr(g, G::ipoint(r, i));
+      cp[a] = c0[a];
+    }
+  }
   uint64_t x[P];
 #pragma unroll
   for (int i = 0; i < P; i++)
     x[i] = d[roff + galois_src((uint32_t)G::gaddr(g, G::ipoint(r, i)), galois, LOGN)];
   G::to_blocked(lds, x, c, r);
   G::inverse(lds, x, c, r, g, itw + roff, itws + roff, q);
+  G::twist(x, g, r, itt + roff, itts + roff, q);
 #pragma unroll
   for (int i = 0; i < P; i++) y[roff + G::gaddr(g, G::ipoint(r, i))] = x[i];
+}
+
+// Fast basis conversion of a thread's P points (interleaved layout of the
+// strided pass) at load time, into NT target moduli at once:
+//   x[t][i] = REDC(sum_{a < na} src[a N + pos_i] cv[t][a cstride]) in [0, q_t)
+// (constants in Montgomery form; the sum stays below q_t 2^64).  Points are
+// taken CH at a time, with the CH loads of one source limb issued together
+// so that their latencies overlap (one load, then a wait, per product
+// leaves the conversion latency-bound); each loaded word serves every
+// target.
+template <class G, int NT>
+__device__ __forceinline__ void bconv_points(uint64_t (&x)[NT][G::P],
+                                             const uint64_t *__restrict__ src,
+                                             const uint64_t *const (&cv)[NT], uint32_t cstride,
+                                             uint32_t na, int g, int r,
+                                             const ModConst (&m)[NT]) {
+  constexpr int P = G::P;
+  constexpr int CH = NT == 1 ? P : P / 2;
+#pragma unroll
+  for (int c0 = 0; c0 < P; c0 += CH) {
+    u128 acc[NT][CH];
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+      for (int k = 0; k < CH; k++) acc[t][k].lo = acc[t][k].hi = 0;
+    for (uint32_t a = 0; a < na; a++) {
+      uint64_t v[CH];
+#pragma unroll
+      for (int k = 0; k < CH; k++) v[k] = src[(size_t)a * G::N + G::gaddr(g, G::ipoint(r, c0 + k))];
+#pragma unroll
+      for (int t = 0; t < NT; t++) {
+        const uint64_t c = cv[t][(size_t)a * cstride];
+#pragma unroll
+        for (int k = 0; k < CH; k++) mac_wide(acc[t][k], v[k], c);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+      for (int k = 0; k < CH; k++) x[t][c0 + k] = redc(acc[t][k], m[t].q, m[t].qinv);
+  }
 }
 
 template <int LOGN, bool PAIR>
@@ -106,59 +160,48 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   if constexpr (!PAIR) {
-    uint64_t x[P];
-#pragma unroll
-    for (int i = 0; i < P; i++) {
-      const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      u128 acc;
-      acc.lo = acc.hi = 0;
-      for (uint32_t a = 0; a < na; a++)
-        mac_wide(acc, src[(size_t)a * G::N + pos], cv[(size_t)a * kg.nm]);
-      x[i] = redc(acc, m.q, m.qinv);
-    }
-    G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+    uint64_t x[1][P];
+    const uint64_t *const cvs[1] = {cv};
+    const ModConst ms[1] = {m};
+    bconv_points<G, 1>(x, src, cvs, kg.nm, na, g, r, ms);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
-    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
   } else {
     const bool two = rows.row2[k] != kNoRow;
     const int mi2 = two ? rows.mod2[k] : mi;
     const ModConst m2 = mc[mi2];
     const uint64_t *cv2 = conv + (size_t)j * kg.alpha * kg.nm + mi2;
-    uint64_t x[P], y[P];
-#pragma unroll
-    for (int i = 0; i < P; i++) {
-      const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      u128 acc, acc2;
-      acc.lo = acc.hi = acc2.lo = acc2.hi = 0;
-      for (uint32_t a = 0; a < na; a++) {
-        const uint64_t v = src[(size_t)a * G::N + pos];
-        mac_wide(acc, v, cv[(size_t)a * kg.nm]);
-        mac_wide(acc2, v, cv2[(size_t)a * kg.nm]);
-      }
-      x[i] = redc(acc, m.q, m.qinv);
-      y[i] = redc(acc2, m2.q, m2.qinv);
-    }
-    G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+    uint64_t x[2][P];
+    const uint64_t *const cvs[2] = {cv, cv2};
+    const ModConst ms[2] = {m, m2};
+    bconv_points<G, 2>(x, src, cvs, kg.nm, na, g, r, ms);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
-    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
     if (!two) return;
-    G::forward(lds, y, c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, m2.q);
+    G::forward(lds, x[1], c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, m2.q);
     uint64_t *out2 = ws + (size_t)rows.row2[k] * G::N;
 #pragma unroll
-    for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
+    for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = x[1][v];
   }
 }
 
 template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
     uint64_t *__restrict__ ws, KsBatch kb, KsGeom kg, const ModConst *__restrict__ mc,
-    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
+    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws,
+    const uint64_t *__restrict__ tt, const uint64_t *__restrict__ tts,
+    const uint64_t *__restrict__ itw, const uint64_t *__restrict__ itws,
+    const uint64_t *__restrict__ itt, const uint64_t *__restrict__ itts) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
-  const uint32_t t = blockIdx.z;
+  // the special limbs, which also run an inverse pass, are dispatched first
+  // so that the shorter workgroups fill in behind them
+  const uint32_t t = blockIdx.z < kg.K ? kg.nq + blockIdx.z : blockIdx.z - kg.K;
   const uint32_t b = blockIdx.y;
   const uint32_t mi = t < kg.nq ? t : kg.L + (t - kg.nq);
   const ModConst m = mc[mi];
@@ -185,6 +228,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
       const uint64_t *e = slot + ((size_t)kg.off_ext + j * kg.ne + t) * G::N;
 #pragma unroll
       for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
+      G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, m.q);
       G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
 #pragma unroll
       for (int v = 0; v < P; v++) x[v] = reduce4(x[v], m.q);
@@ -198,6 +242,17 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
       a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kbp[pos]), m.q, m.qinv), m.q);
       a1[i] = add_mod(a1[i], redc(mul_wide(x[i], kap[pos]), m.q, m.qinv), m.q);
     }
+  }
+  if (t >= kg.nq) {
+    // special limb: ModDown's inverse contiguous pass, while the limb's
+    // blocks are at hand
+    const size_t toff = (size_t)mi * G::N;
+    G::to_blocked(lds, a0, c, r);
+    G::inverse(lds, a0, c, r, g, itw + toff, itws + toff, m.q);
+    G::twist(a0, g, r, itt + toff, itts + toff, m.q);
+    G::to_blocked(lds, a1, c, r);
+    G::inverse(lds, a1, c, r, g, itw + toff, itws + toff, m.q);
+    G::twist(a1, g, r, itt + toff, itts + toff, m.q);
   }
   uint64_t *o0 = slot + ((size_t)kg.off_acc + t) * G::N;
   uint64_t *o1 = slot + ((size_t)kg.off_acc + kg.ne + t) * G::N;
@@ -229,49 +284,40 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   if constexpr (!PAIR) {
-    uint64_t x[P];
+    uint64_t x[1][P];
+    const uint64_t *const cvs[1] = {cv};
+    const ModConst ms[1] = {m};
+    bconv_points<G, 1>(x, src, cvs, kg.nm, kg.K, g, r, ms);
 #pragma unroll
-    for (int i = 0; i < P; i++) {
-      const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      u128 s;
-      s.lo = s.hi = 0;
-      for (uint32_t k = 0; k < kg.K; k++)
-        mac_wide(s, src[(size_t)k * G::N + pos], cv[(size_t)k * kg.nm]);
-      x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
-    }
-    G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
+    for (int i = 0; i < P; i++) x[0][i] = add_mod(x[0][i], h, m.q);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
     uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
 #pragma unroll
-    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
   } else {
     const bool two = li + 1 < kg.nq;
     const uint32_t li2 = two ? li + 1 : li;
     const ModConst m2 = mc[li2];
     const uint64_t h2 = hneg[li2];
     const uint64_t *cv2 = down_conv + li2;
-    uint64_t x[P], y[P];
+    uint64_t x[2][P];
+    const uint64_t *const cvs[2] = {cv, cv2};
+    const ModConst ms[2] = {m, m2};
+    bconv_points<G, 2>(x, src, cvs, kg.nm, kg.K, g, r, ms);
 #pragma unroll
     for (int i = 0; i < P; i++) {
-      const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      u128 s, s2;
-      s.lo = s.hi = s2.lo = s2.hi = 0;
-      for (uint32_t k = 0; k < kg.K; k++) {
-        const uint64_t v = src[(size_t)k * G::N + pos];
-        mac_wide(s, v, cv[(size_t)k * kg.nm]);
-        mac_wide(s2, v, cv2[(size_t)k * kg.nm]);
-      }
-      x[i] = add_mod(redc(s, m.q, m.qinv), h, m.q);
-      y[i] = add_mod(redc(s2, m2.q, m2.qinv), h2, m2.q);
+      x[0][i] = add_mod(x[0][i], h, m.q);
+      x[1][i] = add_mod(x[1][i], h2, m2.q);
     }
-    G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
     uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
 #pragma unroll
-    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
+    for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
     if (!two) return;
-    G::forward(lds, y, c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, m2.q);
+    G::forward(lds, x[1], c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, m2.q);
     uint64_t *out2 = slot + ((size_t)kg.off_conv + p * kg.L + li2) * G::N;
 #pragma unroll
-    for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = y[v];
+    for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = x[1][v];
   }
 }
 
@@ -279,7 +325,8 @@ template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
     uint64_t *__restrict__ ws, KsBatch kb, RowScale pinv, KsGeom kg,
     const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
-    const uint64_t *__restrict__ tws) {
+    const uint64_t *__restrict__ tws, const uint64_t *__restrict__ tt,
+    const uint64_t *__restrict__ tts) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
@@ -293,6 +340,7 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
   uint64_t x[P];
 #pragma unroll
   for (int i = 0; i < P; i++) x[i] = cin[G::gaddr(g, G::ipoint(r, i))];
+  G::twist(x, g, r, tt + (size_t)li * G::N, tts + (size_t)li * G::N, q);
   G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, q);
 #pragma unroll
   for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
@@ -370,9 +418,11 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws
   const uint32_t L = kg.L, nm = kg.nm, alpha = kg.alpha, nq = kg.nq, ne = kg.ne, nb = kb.n;
   const uint32_t level = kg.level;
   int rc;
-  timing_begin(ctx, "ks_intt_gather", 16.0 * N * nq * nb, 0.5 * N * B * nq * nb);
+  double copies = 0;   // c0 tiles copied for outputs that alias their input
+  for (uint32_t b = 0; b < nb; b++) copies += kb.add0_src[b] ? nq : 0;
+  timing_begin(ctx, "ks_intt_gather", 16.0 * N * (nq * nb + copies), 0.5 * N * B * nq * nb);
   k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nb, nq), kNttThreads, 0, ctx->stream>>>(
-      ws, kb, kg, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup);
+      ws, kb, kg, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup, ctx->d_ittw, ctx->d_ittw_shoup);
   timing_end(ctx);
   RowScale sc;
   for (uint32_t i = 0; i < nq; i++) {
@@ -464,7 +514,8 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws
 
 // K5-K7 for batch slots 0..nb-1 (ModDown of each slot's acc rows)
 template <int LOGN>
-int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws) {
+int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws,
+               bool special_contig_done) {
   constexpr int A = split_a(LOGN), B = split_b(LOGN);
   constexpr double N = (double)(1 << LOGN);
   using GA = Pass<A, LOGN, true>;
@@ -488,7 +539,9 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *
         sp.wp[p * K + k] = h_shoup(ctx->down_scale[k], ctx->mods[L + k]);
         sp.add[p * K + k] = ctx->down_add[k];
       }
-    if ((rc = ntt_pass(ctx, ws, mp, true, false, nullptr))) return rc;
+    // the inverse contiguous pass of the special limbs is fused into the
+    // inner-product kernel's epilogue, except on the hoisted path
+    if (!special_contig_done && (rc = ntt_pass(ctx, ws, mp, true, false, nullptr))) return rc;
     if ((rc = ntt_pass(ctx, ws, mp, true, true, &sp, (int)(2 * K)))) return rc;
   }
   // in a launch large enough to fill the chip at half the workgroups, the K
@@ -517,7 +570,7 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *
   timing_begin(ctx, "ks_moddown_tail", 8.0 * N * (3.0 * 2 * nq * nb + adds),
                N * (0.5 * B + 1) * 2 * nq * nb);
   k_moddown_contig_tail<LOGN><<<dim3(GB::BLOCKS, nb, 2 * nq), kNttThreads, 0, ctx->stream>>>(
-      ws, kb, pinv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+      ws, kb, pinv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup, ctx->d_ttw, ctx->d_ttw_shoup);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
@@ -542,11 +595,12 @@ int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *ws) {
   }
   timing_begin(ctx, "ks_contig_inner",
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * keys),
-               N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
+               N * (0.5 * B * (ext_limbs + 2.0 * kg.K * nb) + 2 * digits * ne * nb));
   k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(
-      ws, kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+      ws, kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup, ctx->d_ttw, ctx->d_ttw_shoup,
+      ctx->d_itw, ctx->d_itw_shoup, ctx->d_ittw, ctx->d_ittw_shoup);
   timing_end(ctx);
-  return ks_moddown<LOGN>(ctx, kb, kg, ws);
+  return ks_moddown<LOGN>(ctx, kb, kg, ws, true);
 }
 
 template <int LOGN>
@@ -600,7 +654,7 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
           ws_ks(ctx), c1, galois[s + b], b, keys[s + b]->data, kg, ctx->d_mod);
       timing_end(ctx);
     }
-    if ((rc = ks_moddown<LOGN>(ctx, kb, kg, ws_ks(ctx)))) return rc;
+    if ((rc = ks_moddown<LOGN>(ctx, kb, kg, ws_ks(ctx), false))) return rc;
   }
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
@@ -621,9 +675,10 @@ int ks_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *const *
   const double ext_limbs = nb * (digits * ne - nq);
   timing_begin(ctx, "ks_contig_inner",
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * nb),
-               N * (0.5 * B * ext_limbs + 2 * digits * ne * nb));
+               N * (0.5 * B * (ext_limbs + 2.0 * kg.K * nb) + 2 * digits * ne * nb));
   k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(
-      ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+      ws_ks(ctx), kb, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup, ctx->d_ttw,
+      ctx->d_ttw_shoup, ctx->d_itw, ctx->d_itw_shoup, ctx->d_ittw, ctx->d_ittw_shoup);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   LimbMap rows;
@@ -656,7 +711,7 @@ int md_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, const uint64_t *c
     if ((rc = launch_copy(ctx, ws_ks(ctx) + ((size_t)b * kg.slot_rows + kg.off_acc) * ctx->n,
                           pq[b], (size_t)2 * kg.ne * ctx->n)))
       return rc;
-  return ks_moddown<LOGN>(ctx, kb, kg, ws_ks(ctx));
+  return ks_moddown<LOGN>(ctx, kb, kg, ws_ks(ctx), true);
 }
 
 }  // namespace

@@ -89,13 +89,12 @@ int rotate_noalloc(hck_context *ctx, const hck_ciphertext *a, int32_t step,
     // (phi_g(c0), 0) + KeySwitch(phi_g(c1)); the final launch gathers c0
     // while it writes the output, so an output aliasing the input reads a
     // copy of c0 placed after the key-switch slot
+    KsBatch kb;
     const uint64_t *c0 = a->data;
     if (out == a) {
-      uint64_t *copy = ws + ws_ks_rows(ctx) * n;
-      if ((rc = launch_copy(ctx, copy, a->data, (level + 1) * n))) return rc;
-      c0 = copy;
+      kb.add0_src[0] = a->data;    // copied by the first launch
+      c0 = ws + ws_ks_rows(ctx) * n;
     }
-    KsBatch kb;
     kb.n = 1;
     kb.key[0] = it->second->data;
     kb.galois[0] = g;

@@ -18,6 +18,8 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
                                                           const ModConst *__restrict__ mc,
                                                           const uint64_t *__restrict__ tw,
                                                           const uint64_t *__restrict__ tws,
+                                                          const uint64_t *__restrict__ tt,
+                                                          const uint64_t *__restrict__ tts,
                                                           RowScale sc, int scale_period) {
   using G = Pass<LOGR, LOGN, STRIDED>;
   constexpr int P = G::P;
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
   if (!INVERSE) {
 #pragma unroll
     for (int i = 0; i < P; i++) x[i] = in[G::gaddr(g, G::ipoint(r, i))];
+    if constexpr (!STRIDED) G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, q);
     G::forward(lds, x, c, r, g, w, wp, q);
     if (STRIDED) {
 #pragma unroll
@@ -56,7 +59,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
       G::to_blocked(lds, x, c, r);
     }
     G::inverse(lds, x, c, r, g, w, wp, q);
-    if (STRIDED) {
+    if constexpr (STRIDED) {
       uint64_t sw, swp, sa;
       if (scale_period) {
         const int k = blockIdx.y % scale_period;
@@ -72,6 +75,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
       for (int i = 0; i < P; i++)
         out[G::gaddr(g, G::ipoint(r, i))] = add_mod(shoup(x[i], sw, swp, q), sa, q);
     } else {
+      G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, q);
 #pragma unroll
       for (int i = 0; i < P; i++) out[G::gaddr(g, G::ipoint(r, i))] = x[i];
     }
@@ -117,7 +121,8 @@ template <int LOGN>
 __global__ __launch_bounds__(kNttThreads) void k_rescale_contig_tail(
     uint64_t *out, const uint64_t *c_in, const uint64_t *__restrict__ tmp, size_t ps,
     uint32_t level, RowScale inv, const ModConst *__restrict__ mc,
-    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws) {
+    const uint64_t *__restrict__ tw, const uint64_t *__restrict__ tws,
+    const uint64_t *__restrict__ tt, const uint64_t *__restrict__ tts) {
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
@@ -129,6 +134,7 @@ __global__ __launch_bounds__(kNttThreads) void k_rescale_contig_tail(
   uint64_t x[P];
 #pragma unroll
   for (int k = 0; k < P; k++) x[k] = tin[G::gaddr(g, G::ipoint(r, k))];
+  G::twist(x, g, r, tt + (size_t)i * G::N, tts + (size_t)i * G::N, q);
   G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, q);
 #pragma unroll
   for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
@@ -166,7 +172,8 @@ int run_rescale(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint6
   timing_begin(ctx, "rescale_tail", 24.0 * N * polys * level,
                N * (1 + 0.5 * B) * polys * level);
   k_rescale_contig_tail<LOGN><<<dim3(GB::BLOCKS, level, polys), kNttThreads, 0, ctx->stream>>>(
-      out, in, tmp, ps, level, inv, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+      out, in, tmp, ps, level, inv, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup, ctx->d_ttw,
+      ctx->d_ttw_shoup);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
@@ -185,7 +192,8 @@ void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const Lim
   timing_begin(ctx, names[INVERSE][STRIDED], 16.0 * N * map.n, mm);
   k_ntt_pass<LOGR, LOGN, STRIDED, INVERSE><<<dim3(G::BLOCKS, map.n), kNttThreads, 0, ctx->stream>>>(
       dst, src, map, ctx->d_mod, INVERSE ? ctx->d_itw : ctx->d_tw,
-      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, sc ? *sc : dummy,
+      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, INVERSE ? ctx->d_ittw : ctx->d_ttw,
+      INVERSE ? ctx->d_ittw_shoup : ctx->d_ttw_shoup, sc ? *sc : dummy,
       sc ? (period ? period : (int)map.n) : 0);
   timing_end(ctx);
 }

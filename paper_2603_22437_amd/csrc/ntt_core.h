@@ -19,7 +19,21 @@
 //     log2(P) stages pair registers i and i + h;
 //   blocked layout: thread r holds points r P + v (v < P); the remaining
 //     stages (half-width < T <= P) pair registers v and v + t.
-// One LDS exchange switches layouts.  Global accesses are coalesced in the
+// One LDS exchange switches layouts.
+//
+// The contiguous pass's sub-transform g (words g R2 .. g R2 + R2 - 1) would
+// need its own twiddles: the twiddle of its stage s and group grp is
+// psi^brv(2^(a+s) + g 2^s + grp) (a = log2 R1), which factors as sub-transform
+// 0's twiddle times beta_g^(R2 / 2^(s+1)), beta_g = psi^(2 brv_a(g)).  So
+// every sub-transform runs sub-transform 0's network on its input twisted
+// by x_i <- x_i beta_g^i: by induction over the stages the values entering
+// stage s are the untwisted ones times beta_g^(i mod R2/2^s), and after the
+// last stage the factor is 1, so the outputs are the same residues.  The
+// inverse network is untwisted at its end (x_i beta_g^-i).  A twist is one
+// coalesced table read and one Shoup product per point; the butterflies'
+// twiddles then depend on the stage and group only (uniform across the
+// wavefront in the interleaved stages, a handful of cached words in the
+// blocked ones) instead of one scattered load per butterfly.  Global accesses are coalesced in the
 // interleaved layout for the contiguous pass and in either layout for the
 // strided pass (adjacent threads own adjacent columns).  Butterflies are
 // Harvey's lazy ones (values in [0, 4q) forward, [0, 2q) inverse, q < 2^61)
@@ -74,26 +88,64 @@ struct Pass {
   __device__ static int ipoint(int r, int i) { return r + T * i; }
   __device__ static int bpoint(int r, int v) { return r * P + v; }
   // global twiddle index of pass stage s for the butterfly with top point p
+  // (the contiguous pass uses sub-transform 0's twiddles for every g, on
+  // twisted inputs)
   __device__ static int tw(int s, int g, int p) {
     const int grp = p >> (LOGR - s);
-    return STRIDED ? (1 << s) + grp : (1 << s) * (OTHER + g) + grp;
+    return STRIDED ? (1 << s) + grp : (1 << s) * OTHER + grp;
   }
 
+  // the same for the interleaved stages (s < LOGP), where a thread's point
+  // r + T i with r < T gives grp = i >> (LOGP - s): a compile-time index,
+  // the same for every lane, so the twiddle comes through the scalar cache
+  __device__ static constexpr int tw_interleaved(int s, int i) {
+    return (STRIDED ? (1 << s) : (1 << s) * OTHER) + (i >> (LOGP - s));
+  }
+
+  // contiguous pass, interleaved layout: x_i <- x_i t[i] (t: the limb's twist
+  // or inverse-twist table, indexed like the data), for any x_i < 2^64;
+  // results in [0, 2q)
+  __device__ static void twist(uint64_t (&x)[P], int g, int r, const uint64_t *t,
+                               const uint64_t *ts, uint64_t q) {
+    static_assert(!STRIDED, "twists belong to the contiguous pass");
+#pragma unroll
+    for (int i = 0; i < P; i++) {
+      const size_t a = gaddr(g, ipoint(r, i));
+      x[i] = shoup_lazy(x[i], t[a], ts[a], q);
+    }
+  }
+
+  // A layout switch exchanges values among the T threads of one
+  // sub-transform through its own LDS rows.  In the contiguous pass those
+  // threads are consecutive and T divides 64, so they share one wavefront:
+  // a wavefront-scope fence keeps the compiler from moving the LDS reads
+  // above the writes (or the next writes above the reads), and a wavefront's
+  // LDS operations complete in issue order, so no workgroup barrier is
+  // needed.  The strided pass spreads a sub-transform over the workgroup.
+  static_assert(STRIDED || (T <= 64 && 64 % T == 0), "sub-transform must fit one wavefront");
+  __device__ static void exchange_sync() {
+    if constexpr (STRIDED) {
+      __syncthreads();
+    } else {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
   __device__ static void to_blocked(uint64_t *lds, uint64_t (&x)[P], int c, int r) {
 #pragma unroll
     for (int i = 0; i < P; i++) lds[lidx(c, ipoint(r, i))] = x[i];
-    __syncthreads();
+    exchange_sync();
 #pragma unroll
     for (int v = 0; v < P; v++) x[v] = lds[lidx(c, bpoint(r, v))];
-    __syncthreads();
+    exchange_sync();
   }
   __device__ static void to_interleaved(uint64_t *lds, uint64_t (&x)[P], int c, int r) {
 #pragma unroll
     for (int v = 0; v < P; v++) lds[lidx(c, bpoint(r, v))] = x[v];
-    __syncthreads();
+    exchange_sync();
 #pragma unroll
     for (int i = 0; i < P; i++) x[i] = lds[lidx(c, ipoint(r, i))];
-    __syncthreads();
+    exchange_sync();
   }
 
   // forward stages: interleaved in, blocked out
@@ -105,7 +157,7 @@ struct Pass {
 #pragma unroll
       for (int i = 0; i < P; i++) {
         if (i & h) continue;
-        const int k = tw(s, g, ipoint(r, i));
+        const int k = tw_interleaved(s, i);
         ct_bfly(x[i], x[i + h], w[k], wp[k], q);
       }
     }
@@ -142,7 +194,7 @@ struct Pass {
 #pragma unroll
       for (int i = 0; i < P; i++) {
         if (i & h) continue;
-        const int k = tw(s, g, ipoint(r, i));
+        const int k = tw_interleaved(s, i);
         gs_bfly(x[i], x[i + h], w[k], wp[k], q);
       }
     }
