@@ -102,6 +102,11 @@ CONFIGS: dict[str, dict] = {
     # 32 x 32 frame blocks (per-frame packing tests; not a secure size)
     "gest12": dict(log_n=12, q=[(60, 1, False), (50, 11, True)], p=[(60, 4, False)],
                    dnum=3, scale=2.0 ** 50),
+    # the gesture CNN's 19 levels (+1 of headroom) on a small ring whose slots
+    # hold 16 blocks of an 8 x 8 feature map (oracle pins, GPU parity; not a
+    # secure size)
+    "cnn11": dict(log_n=11, q=[(60, 1, False), (50, 20, True)], p=[(60, 7, False)],
+                  dnum=3, scale=2.0 ** 50),
     # smallest and largest supported rings (edge cases of the parity tests)
     "edge11": dict(log_n=11, q=[(60, 1, False), (50, 2, True)], p=[(60, 1, False)],
                    dnum=3, scale=2.0 ** 40),
@@ -328,3 +333,38 @@ def gesture_pipeline_config(frames: int = 30, bins: int = 32, chirps: int = 32,
         bs.append(rng.uniform(-0.1, 0.1, dims[i + 1]))
     return dict(frames=frames, bins=bins, chirps=chirps, window=np.hanning(chirps),
                 notch=[chirps // 2], weights=ws, biases=bs)
+
+
+def cnn_activation(degree: int = 3, bound: float = 6.0) -> list:
+    """Power-basis coefficients of the CNN's degree-3 activation: the
+    least-squares fit of the logistic sigmoid on [-bound, bound] (the
+    HE-friendly sigmoid of polynomial networks)."""
+    x = np.linspace(-bound, bound, 2001)
+    y = 1.0 / (1.0 + np.exp(-x))
+    c = np.polynomial.polynomial.polyfit(x, y, degree)
+    return [float(v) if abs(v) > 1e-12 else 0.0 for v in c]
+
+
+def gesture_cnn_config(frames: int = 30, bins: int = 32, chirps: int = 32, c1: int = 8,
+                       c2: int = 16, hidden: int = 64, classes: int = 10, seed: int = 78,
+                       feature_gain: float = 4.0) -> dict:
+    """The gesture CNN's public parameters: the front end of the gesture
+    pipeline (Doppler DFT window, notch), then two 3 x 3 convolutions with
+    stride 2 and zero padding (1 -> c1 -> c2 channels on the bins x chirps
+    feature map), 2 x 2 average pooling, dense c2 (bins/8) (chirps/8) ->
+    hidden -> classes, with the degree-3 activation after both convolutions
+    and the first dense layer.  Weights are random and public (trained ones
+    are not available); feature_gain is folded into the first convolution."""
+    if bins % 8 or chirps % 8:
+        raise ValueError("bins and chirps must be multiples of 8")
+    rng = np.random.default_rng(seed)
+    conv1 = rng.standard_normal((c1, 3, 3)) / 3.0 * feature_gain
+    conv2 = rng.standard_normal((c2, c1, 3, 3)) / np.sqrt(9.0 * c1)
+    flat = c2 * (bins // 8) * (chirps // 8)
+    dense1 = rng.standard_normal((hidden, flat)) / np.sqrt(flat)
+    dense2 = rng.standard_normal((classes, hidden)) / np.sqrt(hidden)
+    return dict(frames=frames, bins=bins, chirps=chirps, window=np.hanning(chirps),
+                notch=[chirps // 2], conv1=conv1, conv2=conv2, dense1=dense1,
+                dense2=dense2, bias1=rng.uniform(-0.1, 0.1, hidden),
+                bias2=rng.uniform(-0.1, 0.1, classes), act=cnn_activation())
+
