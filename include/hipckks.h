@@ -520,6 +520,54 @@ int hck_gesture_eval_frames(hck_context *ctx, const hck_gesture_plan *plan,
                             uint32_t n_frames, const hck_galois_keys *gks,
                             const hck_switch_key *rlk, hck_ciphertext *out);
 
+/* ---- gesture CNN variant ----------------------------------------------------
+ * The gesture classifier's CNN variant: the front end of hck_gesture_eval
+ * (K3 Doppler DFT -> K1 power -> K6 notch -> K2 P^4, feature P P^4, frame
+ * accumulation; section 3.3.3), then on the R x D feature map (slot r D + c
+ * of every block of R D slots):
+ *   conv1  3 x 3, stride 2, zero padding, 1 -> c1 channels: block b computes
+ *          channel b mod c1 at the even positions (r, c); one BSGS transform
+ *          over the diagonals of offsets dy D + dx
+ *   act    sum_k act_coeffs[k] x^k (hck_poly_eval)
+ *   conv2  3 x 3, stride 2, c1 -> c2: block b computes channel b mod c2 at
+ *          the positions that are multiples of 4, from channel (b + delta)
+ *          mod c1 of block b + delta (offsets delta R D + 2 (dy D + dx))
+ *   act
+ *   dense1 2 x 2 average pooling folded into the hybrid diagonals of the
+ *          hidden x (c2 (R/8) (D/8)) weights over the period c2 R D of the
+ *          replicated channels (offsets 0 .. hidden-1), then rotations hidden,
+ *          2 hidden, ..., c2 R D / 2 sum the sub-blocks; + bias1; act
+ *   dense2 classes x hidden by its rectangular diagonals; + bias2: the logits
+ *          in slots 0 .. classes-1.
+ * Every transform is applied with hoisted baby steps and a shared ModDown
+ * per giant step and followed by one rescale.  Levels, for the input level
+ * l0 of dft_c and a = ceil(log2 act_degree) + 1: conv1 at l0-6, conv2 at
+ * l0-7-a, dense1 at l0-8-2a, bias1 l0-9-2a, dense2 l0-9-3a, bias2 and the
+ * logits l0-10-3a.  Requirements: pow2(frames) R D = N/2, R and D multiples
+ * of 8, (N/2)/(R D) a multiple of c1 and of c2, c2 R D / hidden a power of
+ * two.  Inputs above l0 are dropped to it. */
+typedef struct {
+  uint32_t frames, bins, chirps;      /* F x R x D, batched packing */
+  uint32_t c1, c2, hidden, classes;
+  const hck_linear_transform *dft_c, *dft_s;            /* level l0 */
+  const hck_plaintext *notch;                           /* l0 - 2 */
+  const hck_linear_transform *conv1, *conv2, *dense1, *dense2;
+  const hck_plaintext *bias1, *bias2;
+  uint32_t act_degree;                /* 1 .. 15 */
+  const double *act_coeffs;           /* act_degree + 1, caller-owned */
+} hck_gesture_cnn_plan;
+int hck_gesture_cnn_required_steps(const hck_context *ctx, const hck_gesture_cnn_plan *plan,
+                                   int32_t *steps, uint32_t cap, uint32_t *n);
+/* The logits of one window.  taps (nullable; null entries skipped) receive
+ * the intermediates: 0 the accumulated feature map, 1 conv1 + act, 2 conv2
+ * + act, 3 dense1 + bias1 + act.  Errors: HCK_EINVAL, HCK_ELEVEL,
+ * HCK_ENOKEY. */
+#define HCK_GESTURE_CNN_TAPS 4
+int hck_gesture_cnn_eval(hck_context *ctx, const hck_gesture_cnn_plan *plan,
+                         const hck_ciphertext *re, const hck_ciphertext *im,
+                         const hck_galois_keys *gks, const hck_switch_key *rlk,
+                         hck_ciphertext *out, hck_ciphertext *const *taps);
+
 /* ---- device calibration ---------------------------------------------------
  * Rate of 64-bit Shoup modular products (a w mod q for a fixed w, the product
  * of every NTT butterfly) that this device sustains on its vector ALUs, in

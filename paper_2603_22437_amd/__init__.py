@@ -110,6 +110,8 @@ SIGNATURES = {
     "hck_vital_eval_taps": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
     "hck_gesture_eval_taps": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
     "hck_gesture_eval_frames": ([_P, _P, _P, _P, _U32, _P, _P, _P], _I),
+    "hck_gesture_cnn_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
+    "hck_gesture_cnn_eval": ([_P, _P, _P, _P, _P, _P, _P, _P], _I),
     "hck_measure_mulmod_rate": ([_P, _PD], _I),
     "hck_lt_eval": ([_P, _P, _U32, _P, _P, _P, _P, _U32, _P, _P, _U32, _U32], _I),
     "hck_rotate_hoisted": ([_P, _P, _P, _U32, _P, _P], _I),
@@ -361,6 +363,31 @@ class GesturePlan(ctypes.Structure):
         for name in cls.OPERANDS:
             h = operands.get(name)
             setattr(plan, name, h.h if h is not None else None)
+        return plan
+
+
+class GestureCnnPlan(ctypes.Structure):
+    """hck_gesture_cnn_plan: layout of one gesture window, the CNN's shape and
+    its public operands."""
+    OPERANDS = ("dft_c", "dft_s", "notch", "conv1", "conv2", "dense1", "dense2", "bias1",
+                "bias2")
+    _fields_ = [(name, ctypes.c_uint32) for name in
+                ("frames", "bins", "chirps", "c1", "c2", "hidden", "classes")] + [
+        (name, ctypes.c_void_p) for name in OPERANDS] + [
+        ("act_degree", ctypes.c_uint32), ("act_coeffs", ctypes.POINTER(ctypes.c_double))]
+
+    @classmethod
+    def build(cls, shape: dict, operands: dict, act_coeffs):
+        plan = cls(*[int(shape[k]) for k in
+                     ("frames", "bins", "chirps", "c1", "c2", "hidden", "classes")])
+        plan._keep = dict(operands)
+        for name in cls.OPERANDS:
+            h = operands.get(name)
+            setattr(plan, name, h.h if h is not None else None)
+        coeffs = np.ascontiguousarray(act_coeffs, dtype=np.float64)
+        plan._coeffs = coeffs
+        plan.act_degree = len(coeffs) - 1
+        plan.act_coeffs = coeffs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         return plan
 
 
@@ -792,6 +819,31 @@ class Context:
         b = (ctypes.c_void_p * max(1, n))(*[c.h for c in ims])
         _check(capi.hck_gesture_eval_frames(self.h, ctypes.addressof(plan), a, b, n, gks, rlk,
                                             out))
+        return out
+
+    def gesture_cnn_required_steps(self, plan: GestureCnnPlan) -> list[int]:
+        n = ctypes.c_uint32()
+        _check(capi.hck_gesture_cnn_required_steps(self.h, ctypes.addressof(plan), None, 0,
+                                                   ctypes.byref(n)))
+        buf = (ctypes.c_int32 * max(1, n.value))()
+        _check(capi.hck_gesture_cnn_required_steps(self.h, ctypes.addressof(plan), buf, n.value,
+                                                   ctypes.byref(n)))
+        return list(buf[: n.value])
+
+    GESTURE_CNN_TAPS = ("feature", "conv1 + act", "conv2 + act", "dense1 + act")
+
+    def gesture_cnn_eval(self, plan: GestureCnnPlan, re, im, gks, rlk, out=None, taps=False):
+        """The CNN variant's logits (slots 0 .. classes-1); with taps=True,
+        (logits, [feature, conv1 + act, conv2 + act, dense1 + act])."""
+        out = self._out(out)
+        if taps:
+            ts = [self.ciphertext() for _ in self.GESTURE_CNN_TAPS]
+            arr = (ctypes.c_void_p * len(ts))(*[t.h for t in ts])
+            _check(capi.hck_gesture_cnn_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk,
+                                             out, arr))
+            return out, ts
+        _check(capi.hck_gesture_cnn_eval(self.h, ctypes.addressof(plan), re, im, gks, rlk, out,
+                                         None))
         return out
 
     GESTURE_TAPS = ("K3 d_re", "K3 d_im", "K1 power", "K6 notch", "K2 P^4", "K2 feature",

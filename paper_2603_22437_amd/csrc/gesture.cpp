@@ -170,6 +170,66 @@ int check_call(hck_context *ctx, const hck_gesture_plan *p, const hck_galois_key
   return HCK_OK;
 }
 
+// ---- the CNN variant ----------------------------------------------------
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+int act_depth(uint32_t degree) {
+  int bits = 0;
+  while ((1u << bits) < degree) bits++;   // ceil(log2 degree)
+  return bits + 1;
+}
+
+int check_cnn_plan(const hck_context *ctx, const hck_gesture_cnn_plan *p) {
+  if (!p) return set_error(HCK_EINVAL, "null plan");
+  if (!p->dft_c || !p->dft_s || !p->notch || !p->conv1 || !p->conv2 || !p->dense1 ||
+      !p->dense2 || !p->bias1 || !p->bias2)
+    return set_error(HCK_EINVAL, "missing plan operand");
+  if (p->act_degree < 1 || p->act_degree > 15 || !p->act_coeffs)
+    return set_error(HCK_EINVAL, "activation degree must be 1 .. 15 with its coefficients");
+  if (!p->frames || !p->bins || !p->chirps || !p->c1 || !p->c2 || !p->hidden || !p->classes)
+    return set_error(HCK_EINVAL, "empty layout");
+  const uint64_t rd = (uint64_t)p->bins * p->chirps;
+  if (pow2_at_least(p->frames) * rd != ctx->n / 2)
+    return set_error(HCK_EINVAL, "pow2(frames) x bins x chirps must equal N/2");
+  if (p->bins % 8 || p->chirps % 8)
+    return set_error(HCK_EINVAL, "bins and chirps must be multiples of 8");
+  const uint64_t blocks = ctx->n / 2 / rd;
+  if (blocks % p->c1 || blocks % p->c2)
+    return set_error(HCK_EINVAL, "the block count must be a multiple of both channel counts");
+  const uint64_t period = p->c2 * rd;
+  if (period % p->hidden || !is_pow2(period / p->hidden))
+    return set_error(HCK_EINVAL, "c2 bins chirps / hidden must be a power of two");
+  return HCK_OK;
+}
+
+std::vector<int32_t> cnn_plan_steps(const hck_gesture_cnn_plan *p) {
+  std::vector<int32_t> s;
+  const uint32_t rd = p->bins * p->chirps, t2 = pow2_at_least(p->frames);
+  const uint32_t period = p->c2 * rd;
+  for (uint32_t k = rd; k < rd * t2; k *= 2) s.push_back((int32_t)k);
+  for (uint32_t k = p->hidden; k < period; k *= 2) s.push_back((int32_t)k);
+  for (const hck_linear_transform *lt :
+       {p->dft_c, p->dft_s, p->conv1, p->conv2, p->dense1, p->dense2})
+    for (auto &kv : lt->groups) {
+      if (kv.first != 0) s.push_back(kv.first * (int32_t)lt->n1);
+      for (auto &bp : kv.second)
+        if (bp.first != 0) s.push_back(bp.first);
+    }
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  return s;
+}
+
+// out = rescale(lt(x)), hoisted baby steps and one ModDown per giant step
+int apply_lt(hck_context *ctx, const hck_linear_transform *lt, const hck_ciphertext *x,
+             const hck_galois_keys *gks, hck_ciphertext *out) {
+  const uint32_t zero = 0;
+  TRY(hck_lt_eval(ctx, &x, 1, &lt, &zero, &zero, nullptr, 1, gks, &out, 1,
+                  HCK_LT_HOIST_BABY | HCK_LT_HOIST_GIANT));
+  return hck_rescale(ctx, out, out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -270,6 +330,83 @@ int hck_gesture_eval_frames(hck_context *ctx, const hck_gesture_plan *p,
   const uint32_t rd = p->bins * p->chirps;
   TRY(rotsum(ctx, acc, rd, (uint32_t)(ctx->n / 2 / rd), gks, sc));
   return fc_tail(ctx, p, acc, rlk, gks, out, no_tap);
+}
+
+int hck_gesture_cnn_required_steps(const hck_context *ctx, const hck_gesture_cnn_plan *plan,
+                                   int32_t *steps, uint32_t cap, uint32_t *n) {
+  if (!ctx || !n) return set_error(HCK_EINVAL, "null argument");
+  TRY(check_cnn_plan(ctx, plan));
+  const std::vector<int32_t> s = cnn_plan_steps(plan);
+  *n = (uint32_t)s.size();
+  if (steps) {
+    if (cap < s.size()) return set_error(HCK_EINVAL, "steps buffer too small");
+    std::copy(s.begin(), s.end(), steps);
+  }
+  return HCK_OK;
+}
+
+int hck_gesture_cnn_eval(hck_context *ctx, const hck_gesture_cnn_plan *p,
+                         const hck_ciphertext *re, const hck_ciphertext *im,
+                         const hck_galois_keys *gks, const hck_switch_key *rlk,
+                         hck_ciphertext *out, hck_ciphertext *const *taps) {
+  if (!ctx || !re || !im || !gks || !rlk || !out) return set_error(HCK_EINVAL, "null argument");
+  if (foreign(ctx, re) || foreign(ctx, im) || foreign(ctx, gks) || foreign(ctx, rlk) ||
+      foreign(ctx, out))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
+  TRY(check_cnn_plan(ctx, p));
+  if (taps)
+    for (int i = 0; i < HCK_GESTURE_CNN_TAPS; i++)
+      if (taps[i] && (taps[i] == re || taps[i] == im || foreign(ctx, taps[i])))
+        return set_error(HCK_EINVAL, "taps must be this context's and not alias inputs");
+  if (re->level != im->level) return set_error(HCK_ELEVEL, "inputs must share a level");
+  const uint32_t l0 = p->dft_c->level;
+  const uint32_t a = (uint32_t)act_depth(p->act_degree);
+  if (l0 < 10 + 3 * a) return set_error(HCK_ELEVEL, "plan encoded below the network's depth");
+  if (re->level < l0)
+    return set_error(HCK_ELEVEL, "inputs must share a level of at least the plan's level");
+  if (p->conv1->level != l0 - 6 || p->conv2->level != l0 - 7 - a ||
+      p->dense1->level != l0 - 8 - 2 * a || p->dense2->level != l0 - 9 - 3 * a)
+    return set_error(HCK_ELEVEL, "plan transforms at levels other than the network's");
+  for (int32_t s : cnn_plan_steps(p))
+    if (!gks->keys.count(galois_of_step(ctx, s)))
+      return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
+  auto tap = [&](int i, const hck_ciphertext *c) {
+    hck_ciphertext *t = taps ? taps[i] : nullptr;
+    return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
+  };
+  Scratch sc(ctx);
+  if (re->level > l0) {
+    hck_ciphertext *x = sc.get(), *y = sc.get();
+    TRY(hck_drop_level(ctx, re, l0, x));
+    TRY(hck_drop_level(ctx, im, l0, y));
+    re = x;
+    im = y;
+  }
+  // front end of the gesture pipeline (its plan fields read there)
+  hck_gesture_plan fe{};
+  fe.dft_c = p->dft_c;
+  fe.dft_s = p->dft_s;
+  fe.notch = p->notch;
+  auto no_tap = [](int, const hck_ciphertext *) { return HCK_OK; };
+  const uint32_t rd = p->bins * p->chirps, t2 = pow2_at_least(p->frames);
+  hck_ciphertext *feat = sc.get(), *u = sc.get(), *v = sc.get();
+  TRY(front_end(ctx, &fe, re, im, rlk, gks, feat, no_tap));
+  TRY(rotsum(ctx, feat, rd, t2, gks, sc));
+  TRY(tap(0, feat));
+  const uint32_t deg = p->act_degree;
+  TRY(apply_lt(ctx, p->conv1, feat, gks, u));
+  TRY(hck_poly_eval(ctx, u, p->act_coeffs, deg, rlk, v));
+  TRY(tap(1, v));
+  TRY(apply_lt(ctx, p->conv2, v, gks, u));
+  TRY(hck_poly_eval(ctx, u, p->act_coeffs, deg, rlk, v));
+  TRY(tap(2, v));
+  TRY(apply_lt(ctx, p->dense1, v, gks, u));
+  TRY(rotsum(ctx, u, p->hidden, p->c2 * rd / p->hidden, gks, sc));
+  TRY(hck_add_plain(ctx, u, p->bias1, u));
+  TRY(hck_poly_eval(ctx, u, p->act_coeffs, deg, rlk, v));
+  TRY(tap(3, v));
+  TRY(apply_lt(ctx, p->dense2, v, gks, out));
+  return hck_add_plain(ctx, out, p->bias2, out);
 }
 
 }  // extern "C"

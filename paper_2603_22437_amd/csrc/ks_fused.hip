@@ -479,16 +479,22 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws
   for (size_t s = 0; s < groups.size(); s += kMaxRows) {
     ModUpRows mr;
     mr.n = (uint32_t)std::min(groups.size() - s, (size_t)kMaxRows);
+    // algorithmic bytes: every digit limb a launch converts is read once
+    // (the targets sharing it re-read it from cache), every output written
     double srcs = 0, outs = 0, macs = 0;
+    std::vector<uint16_t> seen;
     for (uint32_t k = 0; k < mr.n; k++) {
       const Row &rw = ext_rows[groups[s + k].first];
+      if (std::find(seen.begin(), seen.end(), rw.src) == seen.end()) {
+        seen.push_back(rw.src);
+        srcs += rw.na;
+      }
       mr.row[k] = rw.row;
       mr.src[k] = rw.src;
       mr.mod[k] = rw.mod;
       mr.digit[k] = rw.digit;
       mr.row2[k] = kNoRow;
       mr.mod2[k] = rw.mod;
-      srcs += rw.na;
       outs += 1;
       macs += rw.na;
       if (groups[s + k].second != SIZE_MAX) {
@@ -548,7 +554,9 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *
   // special limbs are read once per pair of target limbs
   const bool paired = (size_t)2 * nq * nb * GA::BLOCKS >= kPairMinBlocks;
   const uint32_t per = paired ? (nq + 1) / 2 : nq;
-  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K * per + nq) * 2 * nb,
+  // algorithmic bytes: each output's K special limbs read once, its target
+  // limbs written
+  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K + nq) * 2 * nb,
                N * (K + 0.5 * A) * 2 * nq * nb);
   if (paired)
     k_moddown_strided<LOGN, true><<<dim3(GA::BLOCKS, 2 * per, nb), kNttThreads, 0,
