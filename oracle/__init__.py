@@ -43,7 +43,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libockks.so")
+# OCKKS_LIB names another build of ockks.c (the sanitizer test loads one built
+# with AddressSanitizer and UndefinedBehaviorSanitizer)
+_LIB_PATH = os.environ.get("OCKKS_LIB") or os.path.join(_HERE, "libockks.so")
 _lib = None
 
 u64p = ctypes.POINTER(ctypes.c_uint64)

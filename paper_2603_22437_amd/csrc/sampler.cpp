@@ -100,7 +100,7 @@ class Shake256 {
     }
     uint8_t last[kRate];
     std::memset(last, 0, kRate);
-    std::memcpy(last, msg.data() + off, msg.size() - off);
+    if (msg.size() > off) std::memcpy(last, msg.data() + off, msg.size() - off);
     last[msg.size() - off] ^= 0x1F;  // SHAKE domain bits 1111 then pad10*1's first 1
     last[kRate - 1] ^= 0x80;         // pad10*1's final 1
     absorb_block(last);
