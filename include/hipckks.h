@@ -606,6 +606,63 @@ int hck_timing_read(hck_context *ctx, const char *name, double *total_ms, uint64
                     double *bytes, double *mulmods);
 int hck_timing_names(hck_context *ctx, char *buf, size_t cap);
 
+/* ---- graph capture -------------------------------------------------------
+ * Batching of section 3.3's windows on this chip: the evaluation calls a
+ * caller makes on one or more contexts (one per ring or parameter set) are
+ * recorded once into one HIP graph and replayed as a whole, with each
+ * context's calls on a branch of their own, so that the windows of different
+ * rings run side by side and no launch waits for the host.
+ *
+ * hck_graph_begin starts recording every call on the n contexts (distinct,
+ * same GPU, each on a created stream of its own, none timing).  Until
+ * hck_graph_end, calls on them issue nothing to the device; they record.
+ * Recorded calls must not allocate device memory (run the same calls once
+ * before capturing: every workspace, scratch ciphertext and output then
+ * exists), transfer host memory (encode, encrypt, import, export, decrypt) or
+ * wait (hck_synchronize); such calls fail with HCK_EINVAL, and the capture
+ * then fails at hck_graph_end.  One capture per host thread at a time.
+ *
+ * hck_graph_end (same contexts, same order) stops recording and instantiates
+ * the graph.  hck_graph_launch replays it: after all work issued earlier on
+ * the contexts' streams, and before any work issued later on them; the
+ * outputs of the recorded calls are rewritten from the current contents of
+ * their inputs (the ciphertext levels and scales stay those of the capture).
+ * A replay is refused (HCK_EINVAL) once a device buffer of the contexts that
+ * existed when the capture ended has been given back (the graph may read
+ * it): destroy no handle the recorded calls used, and capture again after a
+ * workspace has grown.  Destroying
+ * any of the contexts releases the graph (later launches: HCK_EINVAL); its
+ * destroy call then frees the host record.  hck_graph_info gives the number
+ * of contexts and of graph nodes.
+ * Errors: HCK_EINVAL, HCK_EDEVICE. */
+typedef struct hck_graph hck_graph;
+int hck_graph_begin(hck_context *const *ctxs, uint32_t n);
+int hck_graph_end(hck_context *const *ctxs, uint32_t n, hck_graph **out);
+int hck_graph_launch(hck_graph *graph);
+int hck_graph_info(const hck_graph *graph, uint32_t *contexts, size_t *nodes);
+int hck_graph_destroy(hck_graph *graph);
+
+/* ---- launch trace ----------------------------------------------------------
+ * The execution trace of Theorem 2 (data obliviousness; proof in Appendix D):
+ * what the cloud side does, in order, as the host issues it.  With the trace
+ * on, the context appends one record per kernel launch (its name as the
+ * timing names above, its grid in workgroups, its algorithmic bytes and
+ * modular multiplications) and one per device allocation ("alloc", bytes) or
+ * release ("free"), in issue order.  Nothing is timed and nothing waits on the
+ * device.  Two runs of a pipeline on inputs of the same public configuration
+ * must give identical records.  Turning the trace on clears the log; records
+ * are kept until the next hck_trace_enable(ctx, 1). */
+typedef struct hck_trace_record {
+  char name[32];
+  uint32_t grid[3];
+  double bytes;
+  double mulmods;
+} hck_trace_record;
+int hck_trace_enable(hck_context *ctx, int on);
+/* Copies up to cap records into out (out may be NULL when cap is 0) and
+ * stores the number of records held in *count.  Errors: HCK_EINVAL. */
+int hck_trace_read(hck_context *ctx, hck_trace_record *out, size_t cap, size_t *count);
+
 /* ---- client-side host utilities (no context, no device) -------------------
  * The paper's client encodes, encrypts and decodes (section 3.2 "Encoding and
  * Batching"; section 3.3.4 result recovery).  These run on the host only. */

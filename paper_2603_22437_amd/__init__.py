@@ -51,6 +51,12 @@ class _Params(ctypes.Structure):
                 ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64))]
 
 
+class TraceRecord(ctypes.Structure):
+    """hck_trace_record: one kernel launch, allocation or release."""
+    _fields_ = [("name", ctypes.c_char * 32), ("grid", _U32 * 3), ("bytes", _D),
+                ("mulmods", _D)]
+
+
 # C signature table: name -> (argtypes, restype).  Every symbol of hipckks.h.
 SIGNATURES = {
     "hck_context_create": ([ctypes.POINTER(_Params), _I, _P, _PP], _I),
@@ -125,6 +131,13 @@ SIGNATURES = {
     "hck_timing_reset": ([_P], _I),
     "hck_timing_read": ([_P, ctypes.c_char_p, _PD, ctypes.POINTER(ctypes.c_uint64), _PD, _PD], _I),
     "hck_timing_names": ([_P, ctypes.c_char_p, _SZ], _I),
+    "hck_graph_begin": ([_P, _U32], _I),
+    "hck_graph_end": ([_P, _U32, _PP], _I),
+    "hck_graph_launch": ([_P], _I),
+    "hck_graph_info": ([_P, _PU32, ctypes.POINTER(_SZ)], _I),
+    "hck_graph_destroy": ([_P], _I),
+    "hck_trace_enable": ([_P, _I], _I),
+    "hck_trace_read": ([_P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
     "hck_shake256": ([_P, _SZ, _P, _SZ], _I),
     "hck_sample_uniform": ([ctypes.c_char_p, _U64, _U32, _U64, _P, _SZ], _I),
     "hck_sample_ternary": ([ctypes.c_char_p, _U64, _P, _SZ], _I),
@@ -402,6 +415,65 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream   # torch.cuda.Stream
+
+
+class Graph:
+    """Evaluation calls on one or more contexts recorded into one HIP graph
+    (hck_graph_*).  Use ``capture``::
+
+        with H.Graph.capture([ctx16, ctx15]) as g:
+            ctx16.vital_eval(...)      # recorded, not run
+            ctx15.gesture_eval(...)
+        g.launch()                     # replays every recorded call
+
+    Every context needs a stream of its own (``Context.set_stream``), and the
+    recorded calls must have run once before (no allocation while
+    recording)."""
+
+    def __init__(self, ctxs):
+        self.ctxs = list(ctxs)        # keeps the contexts alive
+        self.h = None
+        self._fin = None
+
+    @classmethod
+    def capture(cls, ctxs):
+        return _GraphCapture(cls(ctxs))
+
+    def launch(self):
+        _check(capi.hck_graph_launch(self.h))
+
+    def info(self) -> dict:
+        c, n = ctypes.c_uint32(), ctypes.c_size_t()
+        _check(capi.hck_graph_info(self.h, ctypes.byref(c), ctypes.byref(n)))
+        return dict(contexts=c.value, nodes=n.value)
+
+    def close(self):
+        if self._fin is not None:
+            self._fin()
+            self._fin = None
+        self.h = None
+
+
+class _GraphCapture:
+    def __init__(self, g: Graph):
+        self.g = g
+        self.arr = (ctypes.c_void_p * len(g.ctxs))(*[c.h for c in g.ctxs])
+
+    def __enter__(self) -> Graph:
+        _check(capi.hck_graph_begin(self.arr, len(self.g.ctxs)))
+        return self.g
+
+    def __exit__(self, exc_type, exc, tb):
+        h = ctypes.c_void_p()
+        rc = capi.hck_graph_end(self.arr, len(self.g.ctxs), ctypes.byref(h))
+        if exc_type is not None:
+            if rc == 0:
+                capi.hck_graph_destroy(h.value)
+            return False
+        _check(rc)
+        self.g.h = h.value
+        self.g._fin = weakref.finalize(self.g, capi.hck_graph_destroy, h.value)
+        return False
 
 
 class Context:
@@ -904,6 +976,19 @@ class Context:
         buf = ctypes.create_string_buffer(4096)
         _check(capi.hck_timing_names(self.h, buf, 4096))
         return [x for x in buf.value.decode().split(",") if x]
+
+    # --- launch trace (data obliviousness) ---
+    def trace(self, on: bool):
+        """Starts (clearing the log) or stops the launch trace."""
+        _check(capi.hck_trace_enable(self.h, 1 if on else 0))
+
+    def trace_read(self) -> list[tuple]:
+        """The trace records in issue order: (name, (gx, gy, gz), bytes, mulmods)."""
+        n = ctypes.c_size_t()
+        _check(capi.hck_trace_read(self.h, None, 0, ctypes.byref(n)))
+        recs = (TraceRecord * max(1, n.value))()
+        _check(capi.hck_trace_read(self.h, recs, n.value, ctypes.byref(n)))
+        return [(r.name.decode(), tuple(r.grid), r.bytes, r.mulmods) for r in recs[:n.value]]
 
 
 # --- serving runtime -----------------------------------------------------

@@ -79,12 +79,14 @@ void release_lt(void *p) {
 // Host buffers are often locals of the caller, so uploads complete before
 // returning (set-up paths only; evaluation never uploads).
 int upload(hck_context *ctx, uint64_t *dst, const void *src, size_t bytes) {
+  if (ctx->capturing) return set_error(HCK_EINVAL, "host transfer during graph capture");
   HCK_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
   HCK_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return HCK_OK;
 }
 
 int download(hck_context *ctx, void *dst, const uint64_t *src, size_t bytes) {
+  if (ctx->capturing) return set_error(HCK_EINVAL, "host transfer during graph capture");
   HCK_HIP(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream));
   HCK_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return HCK_OK;
@@ -287,6 +289,7 @@ int key_rows_to_internal(hck_context *ctx, uint64_t *buf) {
 int ct_from_host_async(hck_context *ctx, hck_ciphertext *ct, const uint64_t *host,
                        uint32_t polys, uint32_t level, double scale) {
   if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
+  if (ctx->capturing) return set_error(HCK_EINVAL, "host transfer during graph capture");
   TRY(ensure_ct(ctx, ct, polys));
   const size_t n = ctx->n, rows = level + 1;
   for (uint32_t p = 0; p < polys; p++)

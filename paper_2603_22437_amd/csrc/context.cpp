@@ -66,10 +66,27 @@ int check_hip(hck_context *ctx, hipError_t e, const char *what) {
   return set_error(HCK_EDEVICE, std::string("HIP error in ") + what + ": " + hipGetErrorString(e));
 }
 
+// one record of the launch trace (hck_trace_enable)
+static void trace_note(hck_context *ctx, const char *name, dim3 grid, double bytes,
+                       double mulmods) {
+  hck_trace_record r{};
+  std::strncpy(r.name, name, sizeof(r.name) - 1);
+  r.grid[0] = grid.x;
+  r.grid[1] = grid.y;
+  r.grid[2] = grid.z;
+  r.bytes = bytes;
+  r.mulmods = mulmods;
+  ctx->trace_log.push_back(r);
+}
+
 int dev_alloc(hck_context *ctx, uint64_t **p, size_t words) {
   *p = nullptr;
   if (words == 0) return HCK_OK;
   const size_t bytes = words * sizeof(uint64_t);
+  if (ctx->capturing)
+    return set_error(HCK_EINVAL, "device allocation of " + std::to_string(bytes) +
+                                     " bytes during graph capture (run the calls once "
+                                     "before capturing them)");
   if (ctx->alloc_fn) {
     *p = (uint64_t *)ctx->alloc_fn(bytes, (void *)ctx->stream, ctx->alloc_user);
     if (!*p)
@@ -84,18 +101,27 @@ int dev_alloc(hck_context *ctx, uint64_t **p, size_t words) {
     }
   }
   ctx->live_allocs++;
+  ctx->alloc_seq[*p] = ++ctx->alloc_counter;
+  if (ctx->trace) trace_note(ctx, "alloc", dim3(0, 0, 0), (double)bytes, 0);
   return HCK_OK;
 }
 
 void dev_free(hck_context *ctx, void *p) {
   if (!p) return;
+  if (ctx->trace) trace_note(ctx, "free", dim3(0, 0, 0), 0, 0);
   if (ctx->free_fn) ctx->free_fn(p, (void *)ctx->stream, ctx->alloc_user);
   else (void)hipFreeAsync(p, ctx->stream);
   ctx->live_allocs--;
+  auto it = ctx->alloc_seq.find(p);
+  if (it != ctx->alloc_seq.end()) {
+    if (it->second < ctx->graph_mark) ctx->freed_old.push_back(it->second);
+    ctx->alloc_seq.erase(it);
+  }
 }
 
 int ensure_ct(hck_context *ctx, hck_ciphertext *ct, uint32_t polys) {
   if (ct->cap_polys >= polys && ct->data) return HCK_OK;
+  if (ct->pooled) polys = std::max(polys, 3u);
   uint64_t *p = nullptr;
   int rc = dev_alloc(ctx, &p, (size_t)polys * ctx->L * ctx->n);
   if (rc) return rc;
@@ -168,7 +194,8 @@ uint32_t galois_of_step(const hck_context *ctx, int32_t step) {
 
 // ---- timing ----------------------------------------------------------------
 
-void timing_begin(hck_context *ctx, const char *name, double bytes, double mulmods) {
+void timing_begin(hck_context *ctx, const char *name, dim3 grid, double bytes, double mulmods) {
+  if (ctx->trace) trace_note(ctx, name, grid, bytes, mulmods);
   if (!ctx->timing) return;
   hck_context::Timed t;
   t.name = name;
@@ -421,6 +448,7 @@ void untrack_server(hck_context *ctx, void *srv) { ctx->servers.erase(srv); }
 void destroy_context(hck_context *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  abort_capture(ctx);
   // servers stop their workers first; then every live handle gives back its
   // device memory and is detached
   auto servers = std::move(ctx->servers);
@@ -488,12 +516,14 @@ int hck_set_allocator(hck_context *ctx, void *(*alloc)(size_t, void *, void *),
 
 int hck_context_set_stream(hck_context *ctx, void *hip_stream) {
   if (!ctx) return hck::set_error(HCK_EINVAL, "null context");
+  if (ctx->capturing) return hck::set_error(HCK_EINVAL, "stream change during graph capture");
   ctx->stream = (hipStream_t)hip_stream;
   return HCK_OK;
 }
 
 int hck_synchronize(hck_context *ctx) {
   if (!ctx) return hck::set_error(HCK_EINVAL, "null context");
+  if (ctx->capturing) return hck::set_error(HCK_EINVAL, "wait during graph capture");
   HCK_HIP(ctx, hipStreamSynchronize(ctx->stream));
   return HCK_OK;
 }
@@ -504,6 +534,7 @@ uint32_t hck_galois_element(const hck_context *ctx, int32_t step) {
 
 int hck_timing_enable(hck_context *ctx, int on) {
   if (!ctx) return hck::set_error(HCK_EINVAL, "null context");
+  if (ctx->capturing) return hck::set_error(HCK_EINVAL, "timing during graph capture");
   int rc = hck::timing_collect(ctx);
   ctx->timing = on != 0;
   return rc;
@@ -528,6 +559,21 @@ int hck_timing_read(hck_context *ctx, const char *name, double *total_ms, uint64
   if (launches) *launches = t.launches;
   if (bytes) *bytes = t.bytes;
   if (mulmods) *mulmods = t.mulmods;
+  return HCK_OK;
+}
+
+int hck_trace_enable(hck_context *ctx, int on) {
+  if (!ctx) return hck::set_error(HCK_EINVAL, "null context");
+  if (on) ctx->trace_log.clear();
+  ctx->trace = on != 0;
+  return HCK_OK;
+}
+
+int hck_trace_read(hck_context *ctx, hck_trace_record *out, size_t cap, size_t *count) {
+  if (!ctx || !count || (cap && !out)) return hck::set_error(HCK_EINVAL, "null argument");
+  *count = ctx->trace_log.size();
+  const size_t n = std::min(cap, ctx->trace_log.size());
+  if (n) std::memcpy(out, ctx->trace_log.data(), n * sizeof(hck_trace_record));
   return HCK_OK;
 }
 

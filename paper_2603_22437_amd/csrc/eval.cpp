@@ -145,6 +145,7 @@ hck_ciphertext *pool_get(hck_context *ctx) {
   }
   hck_ciphertext *ct = new hck_ciphertext();
   ct->ctx = ctx;
+  ct->pooled = true;
   return ct;
 }
 

@@ -98,6 +98,18 @@ struct hck_context {
   void (*free_fn)(void *, void *, void *) = nullptr;
   void *alloc_user = nullptr;
   uint64_t live_allocs = 0;
+  // Allocation sequence numbers, for the validity of captured graphs: a
+  // graph may read any buffer allocated before its capture ended (sequence
+  // below its mark) and none allocated later.  graph_mark is the highest mark
+  // of the graphs captured so far; a buffer below it that is given back is
+  // logged in freed_old, which hck_graph_launch checks.
+  uint64_t alloc_counter = 0;
+  std::unordered_map<void *, uint64_t> alloc_seq;
+  uint64_t graph_mark = 0;
+  std::vector<uint64_t> freed_old;
+  // the context's stream is being captured into a HIP graph (hck_graph_begin):
+  // allocation, host transfers and waits are refused until hck_graph_end
+  bool capturing = false;
 
   bool broken = false;
 
@@ -124,6 +136,11 @@ struct hck_context {
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, TimingTotal> timing_total;
+
+  // launch trace (hck_trace_*): every kernel launch and device allocation in
+  // issue order, while `trace` is on
+  bool trace = false;
+  std::vector<hck_trace_record> trace_log;
 };
 
 namespace hck {
@@ -155,6 +172,10 @@ struct hck_ciphertext {
   hck_context *ctx = nullptr;
   uint64_t *data = nullptr;  // [cap_polys][L][N], evaluation (NTT) domain, plain form
   uint32_t cap_polys = 0;
+  // a scratch ciphertext of the context's pool: always allocated for 3
+  // polynomials, so that a pool entry never grows in a later call whatever
+  // role it takes (calls in graph capture cannot allocate)
+  bool pooled = false;
   uint32_t size = 0;  // polynomials in use (0: empty)
   uint32_t level = 0;
   double scale = 1.0;
@@ -212,6 +233,9 @@ int check_hip(hck_context *ctx, hipError_t e, const char *what);
     if (_e != hipSuccess) return ::hck::check_hip((ctx), _e, #expr); \
   } while (0)
 
+// ---- graph capture (graph.cpp) ----
+void abort_capture(hck_context *ctx);
+
 // ---- ownership of caller handles (context.cpp) ----
 void track(hck_context *ctx, void *obj, void (*release)(void *));
 void untrack(hck_context *ctx, void *obj);   // no-op for an untracked object
@@ -234,9 +258,12 @@ int ensure_lt_scratch(hck_context *ctx, size_t words);
 int ensure_zero_rows(hck_context *ctx);
 
 // ---- kernel timing ----
-// `bytes` and `mulmods`: the launch's algorithmic HBM traffic and 64-bit
-// modular multiplications (the method's own counts, not the implementation's)
-void timing_begin(hck_context *ctx, const char *name, double bytes = 0, double mulmods = 0);
+// Called before every kernel launch with the launch's grid, its algorithmic
+// HBM traffic `bytes` and 64-bit modular multiplications `mulmods` (the
+// method's own counts, not the implementation's).  With timing on it records
+// events around the launch; with the launch trace on it appends a record.
+void timing_begin(hck_context *ctx, const char *name, dim3 grid, double bytes = 0,
+                  double mulmods = 0);
 void timing_end(hck_context *ctx);
 int timing_collect(hck_context *ctx);
 

@@ -197,8 +197,8 @@ dim3 grid_rows(const hck_context *ctx, uint32_t rows, uint32_t z = 1) {
 
 int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t words) {
   if (words == 0 || dst == src) return HCK_OK;
-  timing_begin(ctx, "copy", 16.0 * words);
   unsigned blocks = (unsigned)std::min<size_t>((words + kThreads - 1) / kThreads, 8192);
+  timing_begin(ctx, "copy", dim3(blocks), 16.0 * words);
   k_copy<<<blocks, kThreads, 0, ctx->stream>>>(dst, src, words);
   timing_end(ctx);
   HCK_HIP(ctx, hipGetLastError());
@@ -208,7 +208,7 @@ int launch_copy(hck_context *ctx, uint64_t *dst, const uint64_t *src, size_t wor
 int launch_addsub(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
                   const LimbMap &map, int op) {
   if (map.n == 0) return HCK_OK;
-  timing_begin(ctx, "addsub", 24.0 * ctx->n * map.n);
+  timing_begin(ctx, "addsub", grid_rows(ctx, map.n), 24.0 * ctx->n * map.n);
   k_addsub<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, b, map, ctx->d_mod,
                                                                  ctx->n, op);
   timing_end(ctx);
@@ -226,7 +226,7 @@ int launch_sum_many(hck_context *ctx, uint64_t *out, const uint64_t *const *in, 
     sa.n = 0;
     if (s > 0) sa.in[sa.n++] = out;
     while (s < n_in && sa.n < (uint32_t)kSumInputs) sa.in[sa.n++] = in[s++];
-    timing_begin(ctx, "sum_many", 8.0 * ctx->n * map.n * (sa.n + 1));
+    timing_begin(ctx, "sum_many", grid_rows(ctx, map.n), 8.0 * ctx->n * map.n * (sa.n + 1));
     k_sum_many<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, sa, map, ctx->d_mod,
                                                                       ctx->n);
     timing_end(ctx);
@@ -252,7 +252,7 @@ int launch_gather_sum(hck_context *ctx, uint64_t *out, const uint64_t *const *in
       ga.in[ga.n] = in[s];
       ga.galois[ga.n++] = galois[s++];
     }
-    timing_begin(ctx, "gather_sum", 8.0 * ctx->n * map.n * (ga.n + 1));
+    timing_begin(ctx, "gather_sum", grid_rows(ctx, map.n), 8.0 * ctx->n * map.n * (ga.n + 1));
     k_gather_sum<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, ga, map, ctx->d_mod,
                                                                         (int)ctx->log_n);
     timing_end(ctx);
@@ -295,8 +295,8 @@ int measure_mulmod_rate(hck_context *ctx, double *tera_per_s) {
 int launch_mul_mont(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *bm,
                     const LimbMap &map, int mode) {
   if (map.n == 0) return HCK_OK;
-  timing_begin(ctx, "mul_plain", ((mode == 1 || mode == 2) ? 32.0 : 24.0) * ctx->n * map.n,
-               (double)ctx->n * map.n);
+  timing_begin(ctx, "mul_plain", grid_rows(ctx, map.n),
+               ((mode == 1 || mode == 2) ? 32.0 : 24.0) * ctx->n * map.n, (double)ctx->n * map.n);
   k_mul_mont<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, bm, map, ctx->d_mod,
                                                                    ctx->n, mode);
   timing_end(ctx);
@@ -306,7 +306,7 @@ int launch_mul_mont(hck_context *ctx, uint64_t *out, const uint64_t *a, const ui
 
 int launch_to_mont(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool to) {
   if (map.n == 0) return HCK_OK;
-  timing_begin(ctx, "mont", 16.0 * ctx->n * map.n, (double)ctx->n * map.n);
+  timing_begin(ctx, "mont", grid_rows(ctx, map.n), 16.0 * ctx->n * map.n, (double)ctx->n * map.n);
   k_to_mont<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(buf, map, ctx->d_mod, ctx->n,
                                                                   to ? 1 : 0);
   timing_end(ctx);
@@ -316,7 +316,7 @@ int launch_to_mont(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool to)
 
 int launch_tensor(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint64_t *b,
                   size_t poly_stride, const LimbMap &map) {
-  timing_begin(ctx, "tensor", 56.0 * ctx->n * map.n, 4.0 * ctx->n * map.n);
+  timing_begin(ctx, "tensor", grid_rows(ctx, map.n), 56.0 * ctx->n * map.n, 4.0 * ctx->n * map.n);
   k_tensor<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, a, b, poly_stride, map,
                                                                  ctx->d_mod, ctx->n);
   timing_end(ctx);
@@ -326,7 +326,7 @@ int launch_tensor(hck_context *ctx, uint64_t *out, const uint64_t *a, const uint
 
 int launch_automorphism(hck_context *ctx, uint64_t *out, const uint64_t *in, size_t poly_stride,
                         uint32_t polys, const LimbMap &map, uint32_t galois) {
-  timing_begin(ctx, "automorphism", 16.0 * ctx->n * map.n * polys);
+  timing_begin(ctx, "automorphism", grid_rows(ctx, map.n, polys), 16.0 * ctx->n * map.n * polys);
   k_automorphism<<<grid_rows(ctx, map.n, polys), kThreads, 0, ctx->stream>>>(
       out, in, poly_stride, map, (int)ctx->log_n, galois);
   timing_end(ctx);
@@ -335,7 +335,7 @@ int launch_automorphism(hck_context *ctx, uint64_t *out, const uint64_t *in, siz
 }
 
 int launch_embed_small(hck_context *ctx, uint64_t *out, const int32_t *small, const LimbMap &map) {
-  timing_begin(ctx, "embed", (8.0 * map.n + 4.0) * ctx->n);
+  timing_begin(ctx, "embed", grid_rows(ctx, map.n), (8.0 * map.n + 4.0) * ctx->n);
   k_embed_small<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, small, map, ctx->d_mod,
                                                                       ctx->n);
   timing_end(ctx);
@@ -347,7 +347,8 @@ int launch_scalar_mac(hck_context *ctx, uint64_t *out, const uint64_t *in, const
                       const RowScale &sc) {
   if (map.n == 0) return HCK_OK;
   if (map.n > (uint32_t)kMaxLimbs) return set_error(HCK_EINVAL, "too many rows");
-  timing_begin(ctx, "scalar_mac", 24.0 * ctx->n * map.n, (double)ctx->n * map.n);
+  timing_begin(ctx, "scalar_mac", grid_rows(ctx, map.n), 24.0 * ctx->n * map.n,
+               (double)ctx->n * map.n);
   k_scalar_mac<<<grid_rows(ctx, map.n), kThreads, 0, ctx->stream>>>(out, in, map, sc, ctx->d_mod,
                                                                      ctx->n);
   timing_end(ctx);

@@ -420,7 +420,8 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws
   int rc;
   double copies = 0;   // c0 tiles copied for outputs that alias their input
   for (uint32_t b = 0; b < nb; b++) copies += kb.add0_src[b] ? nq : 0;
-  timing_begin(ctx, "ks_intt_gather", 16.0 * N * (nq * nb + copies), 0.5 * N * B * nq * nb);
+  timing_begin(ctx, "ks_intt_gather", dim3(GB::BLOCKS, nb, nq), 16.0 * N * (nq * nb + copies),
+               0.5 * N * B * nq * nb);
   k_ks_intt_gather<LOGN><<<dim3(GB::BLOCKS, nb, nq), kNttThreads, 0, ctx->stream>>>(
       ws, kb, kg, ctx->d_mod, ctx->d_itw, ctx->d_itw_shoup, ctx->d_ittw, ctx->d_ittw_shoup);
   timing_end(ctx);
@@ -505,7 +506,8 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws
         macs += rw.na;
       }
     }
-    timing_begin(ctx, "ks_modup_strided", 8.0 * N * (srcs + outs), N * (macs + 0.5 * A * outs));
+    timing_begin(ctx, "ks_modup_strided", dim3(GA::BLOCKS, mr.n), 8.0 * N * (srcs + outs),
+                 N * (macs + 0.5 * A * outs));
     if (paired)
       k_modup_strided<LOGN, true><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
           ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
@@ -556,8 +558,8 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *
   const uint32_t per = paired ? (nq + 1) / 2 : nq;
   // algorithmic bytes: each output's K special limbs read once, its target
   // limbs written
-  timing_begin(ctx, "ks_moddown_strided", 8.0 * N * (K + nq) * 2 * nb,
-               N * (K + 0.5 * A) * 2 * nq * nb);
+  timing_begin(ctx, "ks_moddown_strided", dim3(GA::BLOCKS, 2 * per, nb),
+               8.0 * N * (K + nq) * 2 * nb, N * (K + 0.5 * A) * 2 * nq * nb);
   if (paired)
     k_moddown_strided<LOGN, true><<<dim3(GA::BLOCKS, 2 * per, nb), kNttThreads, 0,
                                     ctx->stream>>>(ws, ctx->d_down_conv, ctx->d_down_hneg, kg,
@@ -575,8 +577,8 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *
   }
   double adds = 0;
   for (uint32_t b = 0; b < nb; b++) adds += (kb.add0[b] ? nq : 0) + (kb.add1[b] ? nq : 0);
-  timing_begin(ctx, "ks_moddown_tail", 8.0 * N * (3.0 * 2 * nq * nb + adds),
-               N * (0.5 * B + 1) * 2 * nq * nb);
+  timing_begin(ctx, "ks_moddown_tail", dim3(GB::BLOCKS, nb, 2 * nq),
+               8.0 * N * (3.0 * 2 * nq * nb + adds), N * (0.5 * B + 1) * 2 * nq * nb);
   k_moddown_contig_tail<LOGN><<<dim3(GB::BLOCKS, nb, 2 * nq), kNttThreads, 0, ctx->stream>>>(
       ws, kb, pinv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup, ctx->d_ttw, ctx->d_ttw_shoup);
   timing_end(ctx);
@@ -601,7 +603,7 @@ int ks_run(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *ws) {
     for (uint32_t k = 0; k < b; k++) seen = seen || kb.key[k] == kb.key[b];
     keys += seen ? 0 : 1;
   }
-  timing_begin(ctx, "ks_contig_inner",
+  timing_begin(ctx, "ks_contig_inner", dim3(GB::BLOCKS, nb, ne),
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * keys),
                N * (0.5 * B * (ext_limbs + 2.0 * kg.K * nb) + 2 * digits * ne * nb));
   k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(
@@ -657,7 +659,8 @@ int ks_hoisted(hck_context *ctx, const uint64_t *c0, const uint64_t *c1, uint32_
       kb.out1[b] = out1[s + b];
       kb.add0[b] = c0;
       kb.add1[b] = nullptr;
-      timing_begin(ctx, "ks_inner_gather", 8.0 * N * ne * (3 * digits + 2), 2 * digits * N * ne);
+      timing_begin(ctx, "ks_inner_gather", dim3((1 << LOGN) / 256, ne),
+                   8.0 * N * ne * (3 * digits + 2), 2 * digits * N * ne);
       k_ks_inner_gather<LOGN><<<dim3((1 << LOGN) / 256, ne), 256, 0, ctx->stream>>>(
           ws_ks(ctx), c1, galois[s + b], b, keys[s + b]->data, kg, ctx->d_mod);
       timing_end(ctx);
@@ -681,7 +684,7 @@ int ks_pq(hck_context *ctx, const KsBatch &kb, uint32_t level, uint64_t *const *
   if ((rc = ks_modup<LOGN>(ctx, kb, kg, ws_ks(ctx)))) return rc;
   const double digits = (double)((nq + alpha - 1) / alpha);
   const double ext_limbs = nb * (digits * ne - nq);
-  timing_begin(ctx, "ks_contig_inner",
+  timing_begin(ctx, "ks_contig_inner", dim3(GB::BLOCKS, nb, ne),
                8.0 * N * (ext_limbs + nb * (nq + 2.0 * ne) + 2 * digits * ne * nb),
                N * (0.5 * B * (ext_limbs + 2.0 * kg.K * nb) + 2 * digits * ne * nb));
   k_ks_contig_inner<LOGN><<<dim3(GB::BLOCKS, nb, ne), kNttThreads, 0, ctx->stream>>>(

@@ -268,7 +268,7 @@ int launch_lt_sums(hck_context *ctx, const LtSumArgs &a, uint32_t level) {
   for (uint32_t in = 0; in < a.n_in; in++)
     for (uint32_t b = 0; b < a.nb; b++) babies += a.baby[in][b] ? 2 : 0;
   const double words = (double)ctx->n * nq;
-  timing_begin(ctx, "lt_inner",
+  timing_begin(ctx, "lt_inner", dim3(ctx->n / kLtCoeffs, nq),
                8.0 * words * (diags + babies + 2.0 * a.ng * a.n_out * (a.accumulate ? 2 : 1)),
                words * macs);
   if (a.n_out <= 1 && a.n_in <= 2)

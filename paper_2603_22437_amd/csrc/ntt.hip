@@ -164,12 +164,12 @@ int run_rescale(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint6
     inv.add[i] = 0;
   }
   const size_t ps = (size_t)ctx->L * ctx->n;
-  timing_begin(ctx, "rescale_strided", 8.0 * N * polys * (1 + level),
-               N * (1 + 0.5 * A) * polys * level);
+  timing_begin(ctx, "rescale_strided", dim3(GA::BLOCKS, level, polys),
+               8.0 * N * polys * (1 + level), N * (1 + 0.5 * A) * polys * level);
   k_rescale_strided<LOGN><<<dim3(GA::BLOCKS, level, polys), kNttThreads, 0, ctx->stream>>>(
       tmp, last, level, qmod, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
   timing_end(ctx);
-  timing_begin(ctx, "rescale_tail", 24.0 * N * polys * level,
+  timing_begin(ctx, "rescale_tail", dim3(GB::BLOCKS, level, polys), 24.0 * N * polys * level,
                N * (1 + 0.5 * B) * polys * level);
   k_rescale_contig_tail<LOGN><<<dim3(GB::BLOCKS, level, polys), kNttThreads, 0, ctx->stream>>>(
       out, in, tmp, ps, level, inv, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup, ctx->d_ttw,
@@ -189,7 +189,7 @@ void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const Lim
                                     {"ntt_inv_contig", "ntt_inv_strided"}};
   const double mm = (0.5 * LOGR + (INVERSE && STRIDED ? 1 : 0)) * N * map.n;
   RowScale dummy;
-  timing_begin(ctx, names[INVERSE][STRIDED], 16.0 * N * map.n, mm);
+  timing_begin(ctx, names[INVERSE][STRIDED], dim3(G::BLOCKS, map.n), 16.0 * N * map.n, mm);
   k_ntt_pass<LOGR, LOGN, STRIDED, INVERSE><<<dim3(G::BLOCKS, map.n), kNttThreads, 0, ctx->stream>>>(
       dst, src, map, ctx->d_mod, INVERSE ? ctx->d_itw : ctx->d_tw,
       INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, INVERSE ? ctx->d_ittw : ctx->d_ttw,
