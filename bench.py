@@ -82,6 +82,10 @@ def main():
                     help="timed windows of the vital-sign pipeline")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in key-switch batch rule (no autotuning)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the mixed batch (64 windows, rings 2^15 and 2^16)")
+    ap.add_argument("--batch-groups", type=int, default=4,
+                    help="contexts (streams) per parameter set in the mixed batch")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving measurement (256 tenants, Poisson arrivals)")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
@@ -283,6 +287,10 @@ def main():
         gesture_cnn = gesture_cnn_latency(gctx, gprm, gsk, grlk, args.pipeline_windows, log)
         gctx.close()
 
+    batched = None
+    if not args.no_batched and not args.quick:
+        batched = batched_mixed_benchmark(args.batch_groups, log)
+
     serving = None
     if not args.no_serving and not args.quick:
         serving = serving_benchmark(args.serving_seconds, log)
@@ -325,6 +333,7 @@ def main():
         "tiny_end_to_end": tiny,
         "vital_pipeline": vital,
         "gesture_pipeline": gesture,
+        "batched_mixed": batched,
         "serving": serving,
         "roofline": roof,
         # key switching (the hot path's dominant cost) as a whole: full
@@ -683,6 +692,179 @@ PAPER_CONTEXT = {"hardware": "NVIDIA RTX 3090 Ti (FIDESlib GPU + OpenFHE), CKKS 
                  "vital_window_batched_s": 1.21, "vital_window_per_frame_s": 99.48,
                  "gesture_window_batched_s": 5.76, "gesture_window_per_frame_s": 36.56,
                  "gesture_fc_layers_batched_s": 4.5}
+
+
+# the mixed batch: windows per parameter set (vital windows, gesture windows),
+# 40 vital and 24 gesture in all, on rings 2^15 and 2^16 with inputs of 12, 24
+# and 30 limbs
+MIXED_BATCH = (("mix15", 20, 12), ("vital", 20, 0), ("gesture", 0, 12))
+
+
+def batched_mixed_benchmark(groups, log, reps=3):
+    """64 encrypted windows of mixed shapes (40 vital-sign, 24 gesture; rings
+    2^15 and 2^16; inputs of 12, 24 and 30 limbs) evaluated one plain call
+    after another on one stream, against the same windows split into
+    `groups` groups per parameter set, each group on a context and stream of
+    its own (vital windows of a group evaluated together by
+    hck_vital_eval_many, so that they share key-switch launches), issued
+    eagerly and as one recorded graph set (hck_graph_*).  Every batched
+    result equals the sequential one bit for bit."""
+    import torch
+    import paper_2603_22437_amd as H
+    import seeded_inputs as S
+    from paper_2603_22437_amd import gesture as HG
+    from paper_2603_22437_amd import vital as HV
+    t_setup = time.time()
+    vcfg = S.vital_pipeline_config()
+    vbase = (11 if vcfg["taylor_order"] == 3 else 9) + 1
+
+    class Member:
+        """One context evaluating a group of windows of one parameter set."""
+
+        def __init__(self, name, nv, ng, key_words, stream, vseed, gseed):
+            prm = S.params(name)
+            self.prm = prm
+            self.ctx = ctx = H.Context.from_params(prm)
+            ctx.set_stream(stream)
+            self.stream = stream
+            top = len(prm["q"]) - 1
+            self.gcfg = S.gesture_pipeline_config(frames=30 if prm["log_n"] == 16 else 14)
+            self.vplan = HV.encode_plan(ctx, vcfg, min(vbase, top)) if nv else None
+            self.gplan = HG.encode_plan(ctx, self.gcfg, 11, prm["scale"]) if ng else None
+            sk = ctx.keygen_secret(1)
+            if key_words is None:       # the parameter set's first context makes the keys
+                steps = set()
+                if nv:
+                    steps |= set(ctx.vital_required_steps(self.vplan))
+                if ng:
+                    steps |= set(ctx.gesture_required_steps(self.gplan))
+                gk = ctx.keygen_rotation(sk, sorted(steps), 5)
+                rl = ctx.keygen_relin(sk, 7)
+                key_words = ({ctx.galois_element(s): ctx.galois_keys_export(gk, ctx.galois_element(s))
+                              for s in steps}, ctx.switch_key_export(rl))
+            self.key_words = key_words
+            self.gks = ctx.galois_keys_from_words(key_words[0])
+            self.rlk = ctx.switch_key_import(key_words[1])
+
+            def enc(x, seed):
+                v = np.zeros(ctx.n_slots, dtype=np.complex128)
+                v[: x.size] = x.reshape(-1)
+                return (ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], top), seed),
+                        ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], top), seed + 1))
+            # window k: scene seed vseed + k (gesture: gseed + k), encryption
+            # seeds derived from it, so every context holding that window
+            # holds the same ciphertexts
+            self.vin = [enc(S.vital_window(vseed + k, vcfg["frames"], vcfg["bins"]),
+                            2 * (vseed + k)) for k in range(nv)]
+            self.gin = [enc(S.gesture_window(gseed + k, self.gcfg["frames"]),
+                            2 * (gseed + k)) for k in range(ng)]
+            self.vout = [[ctx.ciphertext() for _ in range(4)] for _ in range(nv)]
+            self.gout = [ctx.ciphertext() for _ in range(ng)]
+
+        def plain(self):
+            for (re, im), o in zip(self.vin, self.vout):
+                self.ctx.vital_eval(self.vplan, re, im, self.gks, self.rlk, o)
+            for (re, im), o in zip(self.gin, self.gout):
+                self.ctx.gesture_eval(self.gplan, re, im, self.gks, self.rlk, o)
+
+        def batched(self):
+            if self.vin:
+                self.ctx.vital_eval_many(self.vplan, [a for a, _ in self.vin],
+                                         [b for _, b in self.vin], self.gks, self.rlk, self.vout)
+            for (re, im), o in zip(self.gin, self.gout):
+                self.ctx.gesture_eval(self.gplan, re, im, self.gks, self.rlk, o)
+
+        def results(self):
+            return ([[self.ctx.ciphertext_export(c)[0] for c in w] for w in self.vout] +
+                    [[self.ctx.ciphertext_export(c)[0]] for c in self.gout])
+
+        def close(self):
+            self.ctx.synchronize()
+            self.ctx.close()
+
+    def split(total, k):
+        return total // groups + (1 if k < total % groups else 0)
+
+    # sequential plain path: one context per parameter set, one stream
+    s0 = torch.cuda.Stream()
+    seq, words = [], {}
+    for name, nv, ng in MIXED_BATCH:
+        m = Member(name, nv, ng, None, s0, 10000, 20000)
+        words[name] = m.key_words
+        seq.append(m)
+    # the same windows in groups, each group a context on its own stream
+    bat = []
+    for name, nv, ng in MIXED_BATCH:
+        first_v = first_g = 0
+        for k in range(groups):
+            gv, gg = split(nv, k), split(ng, k)
+            if gv + gg == 0:
+                continue
+            # this group's windows are the sequential member's windows
+            # first_v .. first_v + gv and first_g .. first_g + gg
+            m = Member(name, gv, gg, words[name], torch.cuda.Stream(), 10000 + first_v,
+                       20000 + first_g)
+            bat.append((m, name, first_v, gv, first_g, gg))
+            first_v += gv
+            first_g += gg
+    setup_s = time.time() - t_setup
+    windows = sum(nv + ng for _, nv, ng in MIXED_BATCH)
+    log(f"mixed batch: {windows} windows, {len(bat)} batched contexts, setup {setup_s:.1f}s")
+
+    def run_seq():
+        for m in seq:
+            m.plain()
+
+    def run_bat():
+        for m, *_ in bat:
+            m.batched()
+
+    def timed(fn, streams):
+        fn()
+        for s in streams:
+            s.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            for s in streams:
+                s.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best
+
+    t_seq = timed(run_seq, [s0])
+    streams = [m.stream for m, *_ in bat]
+    t_eager = timed(run_bat, streams)
+    with H.Graph.capture([m.ctx for m, *_ in bat]) as g:
+        run_bat()
+    t_graph = timed(g.launch, streams)
+    # every batched result equals the sequential one
+    exact = True
+    for m, name, fv, gv, fg, gg in bat:
+        s = next(x for x, (nm, _, _) in zip(seq, MIXED_BATCH) if nm == name)
+        got = m.results()
+        want_v = [[s.ctx.ciphertext_export(c)[0] for c in w] for w in s.vout[fv: fv + gv]]
+        want_g = [[s.ctx.ciphertext_export(c)[0]] for c in s.gout[fg: fg + gg]]
+        for a, b in zip(got, want_v + want_g):
+            exact = exact and all(np.array_equal(x, y) for x, y in zip(a, b))
+    info = g.info()
+    g.close()
+    for m, *_ in bat:
+        m.close()
+    for m in seq:
+        m.close()
+    res = {"windows": windows,
+           "mix": [{"params": name, "vital": nv, "gesture": ng} for name, nv, ng in MIXED_BATCH],
+           "groups_per_param_set": groups, "batched_contexts": len(streams),
+           "sequential_plain_windows_per_s": round(windows / t_seq, 1),
+           "batched_eager_windows_per_s": round(windows / t_eager, 1),
+           "batched_graph_windows_per_s": round(windows / t_graph, 1),
+           "speedup_graph_vs_sequential": round(t_seq / t_graph, 3),
+           "speedup_eager_vs_sequential": round(t_seq / t_eager, 3),
+           "graph_nodes": info["nodes"], "bit_exact_vs_sequential": bool(exact),
+           "setup_s": round(setup_s, 1)}
+    log(f"mixed batch: {res}")
+    return res
 
 
 def _pinned_u64(a):

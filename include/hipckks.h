@@ -608,10 +608,11 @@ int hck_timing_names(hck_context *ctx, char *buf, size_t cap);
 
 /* ---- graph capture -------------------------------------------------------
  * Batching of section 3.3's windows on this chip: the evaluation calls a
- * caller makes on one or more contexts (one per ring or parameter set) are
- * recorded once into one HIP graph and replayed as a whole, with each
- * context's calls on a branch of their own, so that the windows of different
- * rings run side by side and no launch waits for the host.
+ * caller makes on one or more contexts (one per ring or parameter set, or
+ * several per ring, each evaluating its own group of windows) are recorded
+ * once, each context's calls into a HIP graph on its own stream, and replayed
+ * together, so that the windows of the contexts run side by side on the
+ * device and no launch waits for the host.
  *
  * hck_graph_begin starts recording every call on the n contexts (distinct,
  * same GPU, each on a created stream of its own, none timing).  Until
@@ -623,10 +624,12 @@ int hck_timing_names(hck_context *ctx, char *buf, size_t cap);
  * then fails at hck_graph_end.  One capture per host thread at a time.
  *
  * hck_graph_end (same contexts, same order) stops recording and instantiates
- * the graph.  hck_graph_launch replays it: after all work issued earlier on
- * the contexts' streams, and before any work issued later on them; the
- * outputs of the recorded calls are rewritten from the current contents of
- * their inputs (the ciphertext levels and scales stay those of the capture).
+ * the graphs.  hck_graph_launch replays every context's graph on that
+ * context's stream: after all work issued earlier on the stream, and before
+ * any work issued later on it (the contexts' replays are not ordered with
+ * respect to each other).  The outputs of the recorded calls are rewritten
+ * from the current contents of their inputs (the ciphertext levels and
+ * scales stay those of the capture).
  * A replay is refused (HCK_EINVAL) once a device buffer of the contexts that
  * existed when the capture ended has been given back (the graph may read
  * it): destroy no handle the recorded calls used, and capture again after a

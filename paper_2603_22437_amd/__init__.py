@@ -418,8 +418,9 @@ def _stream_handle(stream):
 
 
 class Graph:
-    """Evaluation calls on one or more contexts recorded into one HIP graph
-    (hck_graph_*).  Use ``capture``::
+    """Evaluation calls on one or more contexts recorded into HIP graphs, one
+    per context on its stream, replayed together (hck_graph_*).  Use
+    ``capture``::
 
         with H.Graph.capture([ctx16, ctx15]) as g:
             ctx16.vital_eval(...)      # recorded, not run

@@ -4,9 +4,9 @@
   written into the same input ciphertexts; every replay's outputs equal, bit
   for bit, the eager call's on the same inputs, with eager work and waits
   between the replays.
-* Two contexts on two streams (rings 2^15 and 2^12, one graph): a vital
-  window on one ring and a gesture window on the other, replayed side by
-  side, each equal to its eager result.
+* Two contexts on two streams (rings 2^15 and 2^12, one graph handle): a
+  vital window on one ring and a gesture window on the other, replayed side
+  by side, each equal to its eager result.
 * Refusals: a recorded call that would allocate, a replay after a buffer
   was given back, a replay after a context was destroyed.
 """
