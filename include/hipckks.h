@@ -205,6 +205,50 @@ int hck_encrypt_pk(hck_context *ctx, const hck_public_key *pk, const hck_plainte
 int hck_decrypt(hck_context *ctx, const hck_secret_key *sk, const hck_ciphertext *ct,
                 hck_plaintext **out);
 
+/* ---- interchange form ------------------------------------------------------
+ * The paper's client uploads its evaluation keys once, at enrollment, and
+ * the cloud keeps them; windows travel as ciphertexts (section 5.4,
+ * communication and resource overhead).  A blob is a 64-byte header, little
+ * endian, then the residues in the export layout (ciphertexts
+ * [size][level+1][N], switching keys [dnum][2][L+K][N], coefficient domain).
+ * The header names the parameter set: prime_hash is FNV-1a (64-bit) over the
+ * L q primes then the K special primes, each as 8 little-endian bytes. */
+#define HCK_BLOB_CIPHERTEXT 1u
+#define HCK_BLOB_SWITCH_KEY 2u
+typedef struct hck_blob_header {
+  char magic[8];        /* "HCKCKKS1" */
+  uint32_t kind;        /* HCK_BLOB_CIPHERTEXT or HCK_BLOB_SWITCH_KEY */
+  uint32_t log_n;
+  uint32_t num_q;       /* L */
+  uint32_t num_p;       /* K */
+  uint32_t dnum;
+  uint32_t level;       /* ciphertext level; L - 1 for keys */
+  uint32_t polys;       /* ciphertext size (2, 3); 2 dnum for keys */
+  uint32_t rows;        /* limbs per polynomial: level + 1; L + K for keys */
+  double scale;         /* ciphertext scale; 0 for keys */
+  uint64_t prime_hash;
+  uint64_t words;       /* residue words after the header: polys rows N */
+} hck_blob_header;
+/* The parameter set's prime hash (host only, no context). */
+int hck_params_hash(const hck_params *params, uint64_t *hash);
+/* Checks a blob's header against itself (magic, kind, ranges, shape, total
+ * size == 64 + 8 words) and copies it out (host only).  Errors: HCK_EINVAL. */
+int hck_blob_parse(const void *buf, size_t size, hck_blob_header *out);
+/* Writes the blob of a ciphertext or switching key into buf (cap bytes);
+ * *size receives its size.  buf NULL: only the size.  Waits for the stream.
+ * Errors: HCK_EINVAL (buffer too small). */
+int hck_ciphertext_serialize(hck_context *ctx, const hck_ciphertext *ct, void *buf, size_t cap,
+                             size_t *size);
+int hck_switch_key_serialize(hck_context *ctx, const hck_switch_key *swk, void *buf, size_t cap,
+                             size_t *size);
+/* Reads a blob into a new object owned by the caller.  Errors: HCK_EINVAL
+ * (malformed blob, another kind, a residue not below its prime), HCK_EPARAMS
+ * (made under another parameter set). */
+int hck_ciphertext_deserialize(hck_context *ctx, const void *buf, size_t size,
+                               hck_ciphertext **out);
+int hck_switch_key_deserialize(hck_context *ctx, const void *buf, size_t size,
+                               hck_switch_key **out);
+
 /* ---- evaluation (section 3.2 "Three Primitive Operations") ----------------
  * All asynchronous on the context stream. */
 
@@ -588,6 +632,20 @@ int hck_measure_mulmod_rate(hck_context *ctx, double *tera_per_s);
  * on the schedule (tested bit for bit).  Errors: HCK_ELEVEL, HCK_EINVAL. */
 int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_levels,
                            uint32_t count, uint32_t *caps, double *us_per_switch);
+/* Autotuner of the digit count of hybrid key switching (dnum; section 3.2's
+ * relinearization and Galois keys are the switching keys): more digits make
+ * smaller keys' special-prime basis but more key-inner-product work and
+ * larger keys.  candidates[0..n) share the ring and the q chain, each with its
+ * own dnum and special primes.  For each, a context is built on `device` /
+ * `hip_stream`, `count` key switches of zero ciphertexts at `level` are timed
+ * with a zero key (median of 3 after a warm-up), and the context is
+ * destroyed.  us_per_switch[i] and key_bytes[i] (a switching key's device
+ * size) receive each candidate's figures, *best the fastest's index (any
+ * output may be NULL).  Errors: HCK_EINVAL, HCK_ELEVEL, HCK_EPARAMS,
+ * HCK_EDEVICE, HCK_ENOMEM. */
+int hck_autotune_dnum(const hck_params *candidates, uint32_t n, int device, void *hip_stream,
+                      uint32_t level, uint32_t count, double *us_per_switch, double *key_bytes,
+                      uint32_t *best);
 /* Sets the key switches per launch sequence at `level` (a saved tuning; 0
  * restores the built-in rule), and reads the size in force. */
 int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap);

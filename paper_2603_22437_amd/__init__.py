@@ -51,6 +51,31 @@ class _Params(ctypes.Structure):
                 ("q", ctypes.POINTER(ctypes.c_uint64)), ("p", ctypes.POINTER(ctypes.c_uint64))]
 
 
+class BlobHeader(ctypes.Structure):
+    """hck_blob_header: the 64-byte header of the interchange form."""
+    _fields_ = [("magic", ctypes.c_char * 8), ("kind", _U32), ("log_n", _U32), ("num_q", _U32),
+                ("num_p", _U32), ("dnum", _U32), ("level", _U32), ("polys", _U32),
+                ("rows", _U32), ("scale", _D), ("prime_hash", _U64), ("words", _U64)]
+
+
+def params_hash(prm: dict) -> int:
+    """FNV-1a prime hash of a parameter set (hck_params_hash; host only)."""
+    q, p = _u64(prm["q"]), _u64(prm["p"])
+    par = _Params(prm["log_n"], len(q), len(p), prm["dnum"],
+                  q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                  p.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    h = ctypes.c_uint64()
+    _check(capi.hck_params_hash(ctypes.byref(par), ctypes.byref(h)))
+    return h.value
+
+
+def blob_parse(blob: bytes) -> dict:
+    """The checked header of a blob (hck_blob_parse; host only)."""
+    h = BlobHeader()
+    _check(capi.hck_blob_parse(blob, len(blob), ctypes.byref(h)))
+    return {f: getattr(h, f) for f, _ in BlobHeader._fields_}
+
+
 class TraceRecord(ctypes.Structure):
     """hck_trace_record: one kernel launch, allocation or release."""
     _fields_ = [("name", ctypes.c_char * 32), ("grid", _U32 * 3), ("bytes", _D),
@@ -136,6 +161,13 @@ SIGNATURES = {
     "hck_graph_launch": ([_P], _I),
     "hck_graph_info": ([_P, _PU32, ctypes.POINTER(_SZ)], _I),
     "hck_graph_destroy": ([_P], _I),
+    "hck_autotune_dnum": ([_P, _U32, _I, _P, _U32, _U32, _P, _P, _PU32], _I),
+    "hck_params_hash": ([ctypes.POINTER(_Params), ctypes.POINTER(_U64)], _I),
+    "hck_blob_parse": ([_P, _SZ, _P], _I),
+    "hck_ciphertext_serialize": ([_P, _P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
+    "hck_switch_key_serialize": ([_P, _P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
+    "hck_ciphertext_deserialize": ([_P, _P, _SZ, _PP], _I),
+    "hck_switch_key_deserialize": ([_P, _P, _SZ, _PP], _I),
     "hck_trace_enable": ([_P, _I], _I),
     "hck_trace_read": ([_P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
     "hck_shake256": ([_P, _SZ, _P, _SZ], _I),
@@ -417,6 +449,26 @@ def _stream_handle(stream):
     return stream.cuda_stream   # torch.cuda.Stream
 
 
+def autotune_dnum(candidates: list, level: int, count: int = 16, device: int = 0,
+                  stream=None) -> dict:
+    """Times key switching for parameter sets that differ only in dnum and
+    their special primes (hck_autotune_dnum).  candidates: parameter dicts
+    (``seeded_inputs.params`` form).  Returns {"best": index, "us_per_switch":
+    [...], "key_bytes": [...]}."""
+    n = len(candidates)
+    keep = [(_u64(c["q"]), _u64(c["p"])) for c in candidates]
+    arr = (_Params * n)(*[_Params(c["log_n"], len(q), len(p), c["dnum"],
+                                  q.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  p.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+                          for c, (q, p) in zip(candidates, keep)])
+    us = np.zeros(n, dtype=np.float64)
+    kb = np.zeros(n, dtype=np.float64)
+    best = ctypes.c_uint32()
+    _check(capi.hck_autotune_dnum(arr, n, device, _stream_handle(stream), level, count, _ptr(us),
+                                  _ptr(kb), ctypes.byref(best)))
+    return {"best": best.value, "us_per_switch": us.tolist(), "key_bytes": kb.tolist()}
+
+
 class Graph:
     """Evaluation calls on one or more contexts recorded into HIP graphs, one
     per context on its stream, replayed together (hck_graph_*).  Use
@@ -653,6 +705,22 @@ class Context:
         r = _u64(res)
         return self._new(capi.hck_ciphertext_import, _ptr(r), r.shape[0], level, scale,
                          cls=Ciphertext)
+
+    def serialize(self, obj) -> bytes:
+        """The interchange blob of a Ciphertext or SwitchKey."""
+        fn = (capi.hck_ciphertext_serialize if isinstance(obj, Ciphertext)
+              else capi.hck_switch_key_serialize)
+        n = ctypes.c_size_t()
+        _check(fn(self.h, obj, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(fn(self.h, obj, buf, n.value, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def ciphertext_deserialize(self, blob: bytes) -> Ciphertext:
+        return self._new(capi.hck_ciphertext_deserialize, blob, len(blob), cls=Ciphertext)
+
+    def switch_key_deserialize(self, blob: bytes) -> SwitchKey:
+        return self._new(capi.hck_switch_key_deserialize, blob, len(blob), cls=SwitchKey)
 
     def ciphertext_export(self, ct):
         size, lvl, sc = ct.info()

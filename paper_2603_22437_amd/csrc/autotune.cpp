@@ -45,6 +45,48 @@ int time_batch(hck_context *ctx, const std::vector<hck_ciphertext *> &in,
   return HCK_OK;
 }
 
+// zero switching key and `count` zero ciphertexts on a context (the work of a
+// key switch does not depend on the values)
+struct ZeroSetup {
+  hck_context *ctx;
+  hck_switch_key key;
+  std::vector<hck_ciphertext *> in, out;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  explicit ZeroSetup(hck_context *c) : ctx(c) { key.ctx = c; }
+  int init(uint32_t count) {
+    TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
+    const size_t kwords = (size_t)ctx->dnum * 2 * (ctx->L + ctx->K) * ctx->n;
+    TRY(dev_alloc(ctx, &key.data, kwords));
+    for (uint32_t i = 0; i < count; i++) {
+      in.push_back(pool_get(ctx));
+      out.push_back(pool_get(ctx));
+      TRY(ensure_ct(ctx, in.back(), 2));
+      TRY(ensure_ct(ctx, out.back(), 2));
+      if (hipMemsetAsync(in.back()->data, 0, (size_t)2 * ctx->L * ctx->n * 8, ctx->stream) !=
+          hipSuccess)
+        return check_hip(ctx, hipGetLastError(), "autotune set-up");
+      in.back()->size = 2;
+      in.back()->scale = 1.0;
+    }
+    if (hipMemsetAsync(key.data, 0, kwords * 8, ctx->stream) != hipSuccess)
+      return check_hip(ctx, hipGetLastError(), "autotune set-up");
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return check_hip(ctx, hipGetLastError(), "autotune events");
+    return HCK_OK;
+  }
+  void level(uint32_t l) {
+    for (hck_ciphertext *c : in) c->level = l;
+  }
+  int time(double *us) { return time_batch(ctx, in, out, &key, 3, e0, e1, us); }
+  ~ZeroSetup() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (hck_ciphertext *c : in) pool_put(ctx, c);
+    for (hck_ciphertext *c : out) pool_put(ctx, c);
+    dev_free(ctx, key.data);
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -56,47 +98,25 @@ int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_
   for (uint32_t i = 0; i < n_levels; i++)
     if (levels[i] >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");
   HCK_HIP(ctx, hipSetDevice(ctx->device));
-  TRY(ensure_workspace(ctx, ws_words_needed(ctx)));
-  // a zero switching key and zero ciphertexts
-  const size_t kwords = (size_t)ctx->dnum * 2 * (ctx->L + ctx->K) * ctx->n;
-  hck_switch_key key;
-  key.ctx = ctx;
-  TRY(dev_alloc(ctx, &key.data, kwords));
-  std::vector<hck_ciphertext *> in, out;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = HCK_OK;
-  for (uint32_t i = 0; i < count && !rc; i++) {
-    in.push_back(pool_get(ctx));
-    out.push_back(pool_get(ctx));
-    rc = ensure_ct(ctx, in.back(), 2);
-    if (!rc) rc = ensure_ct(ctx, out.back(), 2);
-    if (!rc && hipMemsetAsync(in.back()->data, 0, (size_t)2 * ctx->L * ctx->n * 8, ctx->stream) !=
-                   hipSuccess)
-      rc = check_hip(ctx, hipGetLastError(), "autotune set-up");
-    in.back()->size = 2;
-    in.back()->scale = 1.0;
-  }
-  if (!rc && hipMemsetAsync(key.data, 0, kwords * 8, ctx->stream) != hipSuccess)
-    rc = check_hip(ctx, hipGetLastError(), "autotune set-up");
-  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-    rc = check_hip(ctx, hipGetLastError(), "autotune events");
+  ZeroSetup z(ctx);
+  int rc = z.init(count);
   static const uint32_t kCand[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
   for (uint32_t li = 0; li < n_levels && !rc; li++) {
     const uint32_t level = levels[li];
-    for (hck_ciphertext *c : in) c->level = level;
+    z.level(level);
     const uint32_t fit = ks_batch_fit(ctx, level);
     const uint8_t saved = ctx->ks_cap[level];
     // the built-in rule first: a candidate must beat it by 2 % to replace it
     ctx->ks_cap[level] = 0;
     const uint32_t rule = ks_batch_limit(ctx, level);
     double best_us = 0;
-    rc = time_batch(ctx, in, out, &key, 3, e0, e1, &best_us);
+    rc = z.time(&best_us);
     uint32_t best = rule;
     for (uint32_t c : kCand) {
       if (rc || c > fit || c == rule) continue;
       ctx->ks_cap[level] = (uint8_t)c;
       double us = 0;
-      rc = time_batch(ctx, in, out, &key, 3, e0, e1, &us);
+      rc = z.time(&us);
       if (!rc && us < 0.98 * best_us) {
         best_us = us;
         best = c;
@@ -106,12 +126,50 @@ int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_
     if (caps) caps[li] = best;
     if (us_per_switch) us_per_switch[li] = best_us;
   }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  for (hck_ciphertext *c : in) pool_put(ctx, c);
-  for (hck_ciphertext *c : out) pool_put(ctx, c);
-  dev_free(ctx, key.data);
   return rc;
+}
+
+int hck_autotune_dnum(const hck_params *candidates, uint32_t n, int device, void *hip_stream,
+                      uint32_t level, uint32_t count, double *us_per_switch, double *key_bytes,
+                      uint32_t *best) {
+  if (!candidates || n == 0) return set_error(HCK_EINVAL, "no candidate parameter sets");
+  if (count == 0 || count > 256) return set_error(HCK_EINVAL, "count must be 1..256");
+  for (uint32_t i = 0; i < n; i++) {
+    const hck_params &p = candidates[i];
+    const hck_params &p0 = candidates[0];
+    if (p.log_n != p0.log_n || p.num_q != p0.num_q || !p.q || !p0.q ||
+        !std::equal(p.q, p.q + p.num_q, p0.q))
+      return set_error(HCK_EINVAL, "candidates must share the ring and the q chain");
+    if (level >= p.num_q) return set_error(HCK_ELEVEL, "level beyond the chain");
+  }
+  double best_us = 0;
+  uint32_t best_i = 0;
+  for (uint32_t i = 0; i < n; i++) {
+    hck_context *ctx = nullptr;
+    TRY(build_context(&candidates[i], device, hip_stream, &ctx));
+    double us = 0;
+    int rc = HCK_OK;
+    {
+      ZeroSetup z(ctx);
+      rc = z.init(count);
+      if (!rc) {
+        z.level(level);
+        rc = z.time(&us);
+      }
+    }
+    destroy_context(ctx);
+    if (rc) return rc;
+    if (us_per_switch) us_per_switch[i] = us;
+    if (key_bytes)
+      key_bytes[i] = 8.0 * candidates[i].dnum * 2 * (candidates[i].num_q + candidates[i].num_p) *
+                     (double)(1u << candidates[i].log_n);
+    if (i == 0 || us < best_us) {
+      best_us = us;
+      best_i = i;
+    }
+  }
+  if (best) *best = best_i;
+  return HCK_OK;
 }
 
 int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap) {

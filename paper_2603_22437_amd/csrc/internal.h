@@ -233,6 +233,10 @@ int check_hip(hck_context *ctx, hipError_t e, const char *what);
     if (_e != hipSuccess) return ::hck::check_hip((ctx), _e, #expr); \
   } while (0)
 
+// ---- contexts (context.cpp) ----
+int build_context(const hck_params *prm, int device, void *stream, hck_context **out);
+void destroy_context(hck_context *ctx);
+
 // ---- graph capture (graph.cpp) ----
 void abort_capture(hck_context *ctx);
 

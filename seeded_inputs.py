@@ -139,6 +139,19 @@ def params(name: str) -> dict:
     return dict(out)
 
 
+def params_with_dnum(name: str, dnum: int) -> dict:
+    """The parameter set `name` with another digit count: the same ring and q
+    chain, dnum digits and K = ceil(L / dnum) special primes of 60 bits
+    (distinct from the chain; the first K of a fixed list of such primes, so
+    sets with different dnum share their special primes as far as they go)."""
+    base = params(name)
+    L = len(base["q"])
+    k = -(-L // dnum)
+    two_n = 2 * base["n"]
+    specials = _primes_near(60, two_n, k, set(base["q"]), False)
+    return dict(base, name=f"{name}/dnum{dnum}", dnum=dnum, p=specials)
+
+
 def uniform_slots(n_slots: int, seed: int, lo: float = -1.0, hi: float = 1.0,
                   complex_: bool = False) -> np.ndarray:
     """Slot vector drawn uniformly from [lo, hi) (real, or real+imag parts)."""

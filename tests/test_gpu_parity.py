@@ -24,8 +24,8 @@ H = pytest.importorskip("paper_2603_22437_amd")
 class Pair:
     """A GPU context and an oracle over one parameter set, with one secret."""
 
-    def __init__(self, name):
-        self.prm = S.params(name)
+    def __init__(self, name, prm=None):
+        self.prm = S.params(name) if prm is None else prm
         self.ctx = H.Context.from_params(self.prm)
         self.o = O.Oracle(self.prm)
         self.s_o = self.o.keygen_secret(1)
@@ -637,3 +637,37 @@ def test_encode_const_and_poly_eval_errors():
         p.ctx.poly_eval(ct, [1.0, 0.0], rlk)
     with pytest.raises(H.HckError):
         p.ctx.poly_eval(ct, [0.0, 1.0], rlk, out=ct)
+
+
+@pytest.mark.parametrize("dnum", [2, 4, 6])
+def test_other_digit_counts_match_oracle(dnum):
+    """The parameter sets the dnum autotuner chooses among (N = 2^15, L = 12
+    with 2, 4 or 6 digits and K = 6, 3, 2 special primes): key switching at
+    every level class and a rotation, bit-exact."""
+    p = Pair(f"mix15/dnum{dnum}", S.params_with_dnum("mix15", dnum))
+    o = p.o
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    rlk_o = o.keygen_relin(p.s_o, 7)
+    for level in _levels(o):
+        ct, ct_o = p.rand_ct(level, 700 + level)
+        got = p.export(p.ctx.keyswitch(ct, rlk))
+        u0, u1 = o.keyswitch(ct_o.polys[0], level, rlk_o)
+        assert np.array_equal(got[0], u0) and np.array_equal(got[1], u1), level
+    gks, gko = p.galois([5])
+    ct, ct_o = p.rand_ct(o.L - 1, 710)
+    assert np.array_equal(p.export(p.ctx.rotate(ct, 5, gks)), o.rotate(ct_o, 5, gko).polys)
+
+
+def test_autotune_dnum():
+    """The dnum autotuner times each candidate's key switch and reports its
+    key size; the best is the fastest."""
+    dnums = (2, 3, 4, 6)
+    cands = [S.params_with_dnum("mix15", d) for d in dnums]
+    r = H.autotune_dnum(cands, level=11, count=8)
+    assert len(r["us_per_switch"]) == len(dnums) and min(r["us_per_switch"]) > 0
+    for d, c, kb in zip(dnums, cands, r["key_bytes"]):
+        assert kb == 8 * d * 2 * (len(c["q"]) + len(c["p"])) * c["n"]
+    assert r["best"] == int(np.argmin(r["us_per_switch"]))
+    bad = dict(cands[1], q=list(reversed(cands[1]["q"])))
+    with pytest.raises(H.HckError):
+        H.autotune_dnum([cands[0], bad], level=11)
