@@ -420,7 +420,8 @@ int hck_poly_eval(hck_context *ctx, const hck_ciphertext *x, const double *coeff
  *   K2  w = E^gamma by squarings (level 2; gamma below); num_bin =
  *       sum_r w_r bin_index_r, den_bin = sum_r w_r bin_mask_r (rotations
  *       1 .. R/2; level 1)
- *   K4  m = p^2 (l0-2); I = sum_r m Re, Q = sum_r m Im per frame (l0-3)
+ *   K4  m = p^P_phi (phase_power below; p^2 at l0-2); I = sum_r m Re,
+ *       Q = sum_r m Im per frame (l0-3 for P_phi = 2)
  *   K5  (If, Qf) per band = FIR transform (I, Q) (BSGS, hck_lt_eval; l0-4)
  *   K7  y = Qf[t] If[t-1] - If[t] Qf[t-1], x = If[t] If[t-1] + Qf[t] Qf[t-1]
  *       (l0-5); taylor_order 3: dphi = y x^2 - y^3 third (l0-7); 1: dphi = y
@@ -463,6 +464,11 @@ typedef struct {
    * the main chain (freq and mask at dft level - 4, outputs one level
    * lower) and one to the bin branch (its energy sums at level 4) */
   uint32_t gamma;
+  /* K4's mask exponent P_phi (Eq. phase_mask): 2 (0 also means 2) to 5, by
+   * p^2, p^3 = p^2 p, p^4 = (p^2)^2, p^5 = (p^2)^2 p.  3 and 4 take one level
+   * more before K5 and 5 two more: every operand from fir_* on sits that
+   * many levels lower (fir_* at l0 - 3 - e, e = 0, 1, 1, 2) */
+  uint32_t phase_power;
 } hck_vital_plan;
 /* Rotation steps the pipeline needs Galois keys for (ascending; `cap` is the
  * capacity of steps[], *n receives the count; steps may be NULL). */
@@ -489,6 +495,25 @@ int hck_vital_eval_taps(hck_context *ctx, const hck_vital_plan *plan, const hck_
                         const hck_ciphertext *im, const hck_galois_keys *gks,
                         const hck_switch_key *rlk, hck_ciphertext *const *out,
                         hck_ciphertext *const *taps);
+/* The pipeline on per-frame packing (section 3.3.2): frame t of the window
+ * in its own ciphertext pair re[t], im[t] (t < frames, frames = the plan's
+ * F), its R range bins in slots 0 .. R-1, zeros elsewhere, every pair at one
+ * level >= the plan's l0.  K1 and K4 run on each pair: p_t, and I_t, Q_t
+ * summed into slot 0 by rotations 1 .. R/2; the bin branch sums the frames'
+ * powers by additions (no rotation).  The frames' I_t and Q_t then go to slot
+ * t R of one ciphertext each by a tree of rotations (step j: every other
+ * entry rotated by -2^j R and added to its left neighbour), the batched
+ * packing's layout, and K5 -> K2 run as in hck_vital_eval.  The four outputs
+ * decode to the batched pipeline's values (their residues differ: other
+ * operations reach them).  Galois keys: hck_vital_frames_required_steps
+ * (the plan's steps and -R, -2R, ..., -(T2/2) R).  Errors as
+ * hck_vital_eval; HCK_EINVAL if frames differs from the plan's F. */
+int hck_vital_frames_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
+                                    int32_t *steps, uint32_t cap, uint32_t *n);
+int hck_vital_eval_frames(hck_context *ctx, const hck_vital_plan *plan,
+                          const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                          uint32_t frames, const hck_galois_keys *gks, const hck_switch_key *rlk,
+                          hck_ciphertext *const *out);
 /* n windows with one plan, evaluated together: every stage advances all
  * windows, so their rotate-and-sum chains and relinearizations share batched
  * key switches (a throughput mode; each window's residues equal

@@ -20,8 +20,11 @@ power of two >= F with T2 R <= N/2.  The stages and the level each ends at
       2 by default, 4 for sharper selection, Eq. soft_power_weight);
       num_r = sum_r r w_r / F^2, den_r = sum_r w_r / F^2 (index and mask
       plaintexts, rotations 1 .. R/2; level 1)
-  K4  m = p^2 (l0-2); I[t] = sum_r m Re, Q[t] = sum_r m Im (l0-3), left in
-      slot t R
+  K4  m = p^P_phi (Eq. phase_mask; P_phi = cfg["phase_power"], 2 .. 5):
+      p^2 (l0-2), p^3 = p^2 p and p^4 = p^2 p^2 (l0-3), p^5 = p^4 p (l0-4);
+      I[t] = sum_r m Re, Q[t] = sum_r m Im, left in slot t R (one level
+      below m: l0-3 for P_phi = 2, and every later stage as many levels
+      lower as m is)
   K5  per band b: If_b = T_b I, Qf_b = T_b Q with the zero-padded Toeplitz
       matrix of the band's taps, T_b[t][t+k] = h_b[k] (BSGS over offsets
       k R with hoisted baby steps and one ModDown per output; l0-4)
@@ -65,6 +68,14 @@ def log2_gamma(cfg: dict) -> int:
     if g not in (2, 4):
         raise ValueError("gamma must be 2 or 4")
     return g.bit_length() - 1
+
+
+def phase_extra(cfg: dict) -> int:
+    """Levels the mask p^P_phi takes beyond p^2."""
+    e = cfg.get("phase_power", 2)
+    if e not in (2, 3, 4, 5):
+        raise ValueError("P_phi must be 2 .. 5")
+    return {2: 0, 3: 1, 4: 1, 5: 2}[e]
 
 
 def bin_level(cfg: dict) -> int:
@@ -159,10 +170,11 @@ def operand_vectors(cfg: dict, n_slots: int) -> dict:
 
 def levels(cfg: dict, level0: int) -> dict:
     """Level of each operand for inputs at level0."""
-    phi = level0 - (7 if cfg["taylor_order"] == 3 else 5)
+    e = phase_extra(cfg)
+    phi = level0 - (7 if cfg["taylor_order"] == 3 else 5) - e
     sharp = phi - 2 - log2_gamma(cfg)          # S = P^gamma
-    return {"bin_index": 2, "bin_mask": 2, "fir": level0 - 3,
-            "third": level0 - 5, "dft": phi, "freq": sharp, "out": sharp - 1}
+    return {"bin_index": 2, "bin_mask": 2, "fir": level0 - 3 - e,
+            "third": level0 - 5 - e, "dft": phi, "freq": sharp, "out": sharp - 1}
 
 
 def fir_baby_step(cfg: dict, n_slots: int | None = None) -> int:
@@ -246,16 +258,104 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
     src = o.poly_eval(p, cfg["mag_coeffs"], rlk) if cfg.get("mag_coeffs") else p
     e = _rotsum(o, o.drop_level(src, bin_level(cfg)), r, t2, gks)
     # K2: soft power attention over bins, w = E^gamma by squarings
+    _bin_outputs(o, cfg, ops, e, rlk, gks, out)
+    # K4: soft I/Q with the mask p^P_phi
+    i_t, q_t = _soft_iq(o, cfg, p, re, im, rlk, gks)
+    _tail(o, cfg, ops, lay, i_t, q_t, gks, rlk, out)
+    return out
+
+
+def _mask(o: Oracle, cfg: dict, p: Ciphertext, rlk) -> Ciphertext:
+    """K4's mask p^P_phi: p^2, then p^3 = p^2 p, p^4 = p^2 p^2, p^5 = p^4 p."""
+    e = cfg.get("phase_power", 2)
+    m = _mul(o, p, p, rlk)
+    if e >= 4:
+        m = _mul(o, m, m, rlk)
+    if e in (3, 5):
+        m = _mul(o, m, o.drop_level(p, m.level), rlk)
+    return m
+
+
+def _soft_iq(o: Oracle, cfg: dict, p, re, im, rlk, gks):
+    """K4: I = sum_r m Re, Q = sum_r m Im, by rotations 1 .. R/2."""
+    r = cfg["bins"]
+    m = _mask(o, cfg, p, rlk)
+    re2, im2 = o.drop_level(re, m.level), o.drop_level(im, m.level)
+    return (_rotsum(o, _mul(o, m, re2, rlk), 1, r, gks),
+            _rotsum(o, _mul(o, m, im2, rlk), 1, r, gks))
+
+
+def _bin_outputs(o: Oracle, cfg: dict, ops: dict, e: Ciphertext, rlk, gks, out: dict):
+    """K2 over bins on the energy sums: w = E^gamma, num_bin, den_bin."""
     w = e
     for _ in range(log2_gamma(cfg)):
         w = _mul(o, w, w, rlk)
+    r = cfg["bins"]
     out["num_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_index"])), 1, r, gks)
     out["den_bin"] = _rotsum(o, o.rescale(o.mul_plain(w, ops["bin_mask"])), 1, r, gks)
-    # K4: soft I/Q (P_phi = 2)
-    m = _mul(o, p, p, rlk)
-    re2, im2 = o.drop_level(re, m.level), o.drop_level(im, m.level)
-    i_t = _rotsum(o, _mul(o, m, re2, rlk), 1, r, gks)
-    q_t = _rotsum(o, _mul(o, m, im2, rlk), 1, r, gks)
+
+
+def evaluate_frames(o: Oracle, cfg: dict, ops: dict, res: list, ims: list, gks: dict,
+                    rlk) -> dict:
+    """The pipeline on per-frame packing (section 3.3.2): res[t], ims[t] hold
+    frame t's R range bins in slots 0 .. R-1.  K1 per frame; E = the sum of
+    the frames' copies at the bin branch's level (additions in frame order);
+    K4 per frame (I_t, Q_t in slot 0); then the frames' I_t and Q_t go to slot
+    t R of one ciphertext each by a tree: at step j (shift 2^j R) every other
+    entry, rotated by -shift, is added to its left neighbour; K5 -> K2 as in
+    evaluate()."""
+    lay = layout(cfg, o.n_slots)
+    if len(res) != lay.frames or len(ims) != lay.frames:
+        raise ValueError("one ciphertext pair per frame")
+    out = {}
+    ps = [_square_sum(o, a, b, rlk) for a, b in zip(res, ims)]
+    srcs = [o.poly_eval(p, cfg["mag_coeffs"], rlk) if cfg.get("mag_coeffs") else p for p in ps]
+    e = o.drop_level(srcs[0], bin_level(cfg))
+    for src in srcs[1:]:
+        e = o.add(e, o.drop_level(src, bin_level(cfg)))
+    _bin_outputs(o, cfg, ops, e, rlk, gks, out)
+    cur = [_soft_iq(o, cfg, p, a, b, rlk, gks) for p, a, b in zip(ps, res, ims)]
+    shift = lay.bins
+    while len(cur) > 1:
+        nxt = []
+        for i in range(0, len(cur), 2):
+            if i + 1 < len(cur):
+                (a_i, a_q), (b_i, b_q) = cur[i], cur[i + 1]
+                nxt.append((o.add(a_i, o.rotate(b_i, -shift, gks)),
+                            o.add(a_q, o.rotate(b_q, -shift, gks))))
+            else:
+                nxt.append(cur[i])
+        cur = nxt
+        shift *= 2
+    i_t, q_t = cur[0]
+    _tail(o, cfg, ops, lay, i_t, q_t, gks, rlk, out)
+    return out
+
+
+def frames_required_steps(o: Oracle, cfg: dict, ops: dict) -> list:
+    """Galois steps of the per-frame packing: the batched pipeline's and
+    -R, -2R, ..., -(T2/2) R."""
+    lay = layout(cfg, o.n_slots)
+    extra = {-(lay.bins << j) for j in range(lay.t2.bit_length() - 1)}
+    return sorted(set(required_steps(o, cfg, ops)) | extra)
+
+
+def encrypt_frames(o: Oracle, s, z: np.ndarray, level: int, scale: float, seed: int):
+    """Per-frame packing: frame t's bins in slots 0 .. R-1 of its own pair
+    (encryption seeds seed + 2t, seed + 2t + 1)."""
+    pairs = []
+    for t, row in enumerate(np.asarray(z)):
+        v = np.zeros(o.n_slots, dtype=np.complex128)
+        v[: row.size] = row
+        pairs.append((o.encrypt_sk(s, o.encode(v.real, scale, level), seed + 2 * t),
+                      o.encrypt_sk(s, o.encode(v.imag, scale, level), seed + 2 * t + 1)))
+    return [a for a, _ in pairs], [b for _, b in pairs]
+
+
+def _tail(o: Oracle, cfg: dict, ops: dict, lay: Layout, i_t: Ciphertext, q_t: Ciphertext,
+          gks: dict, rlk, out: dict):
+    """K5 -> K7 -> K3 -> K1 -> K2 on the phase series I, Q (slot t R)."""
+    r, t2 = lay.bins, lay.t2
     # K5: FIR into the two bands
     terms = [(ops["fir_resp"], 0, 0, 1), (ops["fir_resp"], 1, 1, 1),
              (ops["fir_hr"], 0, 2, 1), (ops["fir_hr"], 1, 3, 1)]
@@ -294,7 +394,6 @@ def evaluate(o: Oracle, cfg: dict, ops: dict, re: Ciphertext, im: Ciphertext, gk
         sh = _mul(o, sh, sh, rlk)
     out["num_rates"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops["freq"])), 1, lay.group, gks)
     out["den_rates"] = _rotsum(o, o.rescale(o.mul_plain(sh, ops["mask"])), 1, lay.group, gks)
-    return out
 
 
 def plain(cfg: dict, z: np.ndarray) -> dict:
@@ -310,7 +409,7 @@ def plain(cfg: dict, z: np.ndarray) -> dict:
     w = e ** cfg.get("gamma", 2)
     out = {"num_bin": float(np.sum(np.arange(r) * w) / f ** 2),
            "den_bin": float(np.sum(w) / f ** 2)}
-    m = p ** 2
+    m = p ** cfg.get("phase_power", 2)
     i_t = (m * re).sum(axis=1)
     q_t = (m * im).sum(axis=1)
     win = np.asarray(cfg["window"])

@@ -168,6 +168,8 @@ SIGNATURES = {
     "hck_switch_key_serialize": ([_P, _P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
     "hck_ciphertext_deserialize": ([_P, _P, _SZ, _PP], _I),
     "hck_switch_key_deserialize": ([_P, _P, _SZ, _PP], _I),
+    "hck_vital_frames_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
+    "hck_vital_eval_frames": ([_P, _P, _P, _P, _U32, _P, _P, _P], _I),
     "hck_trace_enable": ([_P, _I], _I),
     "hck_trace_read": ([_P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
     "hck_shake256": ([_P, _SZ, _P, _SZ], _I),
@@ -368,7 +370,7 @@ class VitalPlan(ctypes.Structure):
             "bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
             "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")] + [
         ("mag_degree", ctypes.c_uint32), ("mag_coeffs", ctypes.c_void_p),
-        ("gamma", ctypes.c_uint32)]
+        ("gamma", ctypes.c_uint32), ("phase_power", ctypes.c_uint32)]
 
     OPERANDS = ("bin_index", "bin_mask", "fir_resp", "fir_hr", "third", "dft_re_resp",
                 "dft_im_resp", "dft_re_hr", "dft_im_hr", "freq", "mask")
@@ -376,12 +378,14 @@ class VitalPlan(ctypes.Structure):
 
     @classmethod
     def build(cls, frames, bins, taylor_order, lanes_resp, lanes_hr, operands: dict,
-              mag_coeffs=None, gamma: int = 2):
+              mag_coeffs=None, gamma: int = 2, phase_power: int = 2):
         """operands: name -> Plaintext / LinearTransform handle (kept alive by
         the plan object); mag_coeffs: the magnitude option's polynomial;
-        gamma: the soft-attention exponent (2 or 4)."""
+        gamma: the soft-attention exponent (2 or 4); phase_power: K4's mask
+        exponent P_phi (2 .. 5)."""
         plan = cls(frames, bins, taylor_order, lanes_resp, lanes_hr)
         plan.gamma = gamma
+        plan.phase_power = phase_power
         plan._keep = dict(operands)
         for name in cls.OPERANDS:
             h = operands.get(name)
@@ -919,6 +923,28 @@ class Context:
         _check(capi.hck_vital_eval_taps(self.h, ctypes.addressof(plan), re, im, gks, rlk, outs,
                                         tp))
         return outputs, taps
+
+    def vital_frames_required_steps(self, plan: VitalPlan) -> list[int]:
+        n = ctypes.c_uint32()
+        _check(capi.hck_vital_frames_required_steps(self.h, ctypes.addressof(plan), None, 0,
+                                                    ctypes.byref(n)))
+        buf = (ctypes.c_int32 * max(1, n.value))()
+        _check(capi.hck_vital_frames_required_steps(self.h, ctypes.addressof(plan), buf, n.value,
+                                                    ctypes.byref(n)))
+        return list(buf[: n.value])
+
+    def vital_eval_frames(self, plan: VitalPlan, res, ims, gks, rlk, outputs=None):
+        """The pipeline on per-frame packing: res[t], ims[t] hold frame t's
+        range bins in slots 0 .. R-1; the four outputs as vital_eval."""
+        f = len(res)
+        if len(ims) != f:
+            raise ValueError("one imaginary ciphertext per frame")
+        outputs = [self.ciphertext() for _ in range(4)] if outputs is None else outputs
+        a = (ctypes.c_void_p * f)(*[c.h for c in res])
+        b = (ctypes.c_void_p * f)(*[c.h for c in ims])
+        o = (ctypes.c_void_p * 4)(*[c.h for c in outputs])
+        _check(capi.hck_vital_eval_frames(self.h, ctypes.addressof(plan), a, b, f, gks, rlk, o))
+        return outputs
 
     def vital_eval_many(self, plan: VitalPlan, res, ims, gks, rlk, outputs=None):
         """Several windows together; returns one list of 4 outputs per window."""

@@ -26,6 +26,14 @@ constexpr uint32_t kBinPlainLevel = 2;
 
 uint32_t log2_gamma(const hck_vital_plan *p) { return p->gamma == 4 ? 2 : 1; }
 
+// K4's mask exponent P_phi (0 means 2) and the levels its powers of p take
+// beyond P_phi = 2: p^3 and p^4 one more, p^5 two more
+uint32_t phase_power(const hck_vital_plan *p) { return p->phase_power ? p->phase_power : 2; }
+uint32_t phase_extra(const hck_vital_plan *p) {
+  const uint32_t e = phase_power(p);
+  return e == 2 ? 0 : e == 5 ? 2 : 1;
+}
+
 uint32_t pow2_at_least(uint32_t x) {
   uint32_t p = 1;
   while (p < x) p *= 2;
@@ -76,6 +84,8 @@ int check_plan(const hck_context *ctx, const hck_vital_plan *p) {
     return set_error(HCK_EINVAL, "missing plan operand");
   if (p->gamma != 0 && p->gamma != 2 && p->gamma != 4)
     return set_error(HCK_EINVAL, "gamma must be 2 or 4");
+  if (p->phase_power != 0 && (p->phase_power < 2 || p->phase_power > 5))
+    return set_error(HCK_EINVAL, "phase mask exponent must be 2 .. 5");
   if (p->mag_degree > 15 || (p->mag_degree && !p->mag_coeffs))
     return set_error(HCK_EINVAL, "magnitude polynomial: degree 0 .. 15 with coefficients");
   return HCK_OK;
@@ -94,6 +104,17 @@ std::vector<int32_t> plan_steps(const hck_vital_plan *p) {
       for (auto &bp : kv.second)
         if (bp.first != 0) s.push_back(bp.first);
     }
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
+  return s;
+}
+
+// the per-frame packing's steps: the plan's and -R, -2R, ..., -(T2/2) R,
+// which move every frame's I and Q to slot t R
+std::vector<int32_t> frame_steps(const hck_vital_plan *p) {
+  std::vector<int32_t> s = plan_steps(p);
+  for (uint32_t k = p->bins; k < (uint64_t)p->bins * pow2_at_least(p->frames); k *= 2)
+    s.push_back(-(int32_t)k);
   std::sort(s.begin(), s.end());
   s.erase(std::unique(s.begin(), s.end()), s.end());
   return s;
@@ -207,32 +228,40 @@ int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
 // their rotate-and-sum chains and relinearizations share key-switch batches.
 // taps (optional, HCK_VITAL_TAPS per window, entries may be null) receive
 // copies of the kernels' intermediate results.
+// frames > 0: per-frame packing (section 3.3.2) of one window (n = 1):
+// re[t], im[t] (t < frames) hold frame t's R range bins in slots 0 .. R-1.
 static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
                               const hck_ciphertext *const *re, const hck_ciphertext *const *im,
                               uint32_t n, const WindowKeys &wk, hck_ciphertext *const *out,
-                              hck_ciphertext *const *taps) {
+                              hck_ciphertext *const *taps, uint32_t frames = 0) {
   TRY(check_plan(ctx, p));
   const uint32_t sq = log2_gamma(p);  // squarings of each K2 stage
-  const uint32_t depth = (p->taylor_order == 3 ? 11 : 9) + sq - 1;
+  const uint32_t extra = phase_extra(p);  // levels of p^P_phi beyond p^2
+  const uint32_t depth = (p->taylor_order == 3 ? 11 : 9) + sq - 1 + extra;
   const uint32_t bin_level = kBinPlainLevel + sq;
   // the plan's operands are encoded for inputs at level l0 (the FIR
-  // transforms at l0 - 3, the bin branch's plaintexts at level 2);
+  // transforms at l0 - 3 - extra, the bin branch's plaintexts at level 2);
   // inputs above l0 are dropped to it, since the circuit uses only its first
   // depth + 1 primes anyway
-  const uint32_t l0 = p->fir_resp->level + 3;
+  const uint32_t l0 = p->fir_resp->level + 3 + extra;
   if (l0 < depth || l0 >= ctx->L)
     return set_error(HCK_ELEVEL, "plan encoded below the pipeline depth");
   if (p->bin_index->level != kBinPlainLevel || p->bin_mask->level != kBinPlainLevel)
     return set_error(HCK_ELEVEL, "bin plaintexts must be encoded at level 2");
-  for (uint32_t k = 0; k < n; k++) {
+  if (frames && (n != 1 || frames != p->frames))
+    return set_error(HCK_EINVAL, "per-frame packing: one window of the plan's frame count");
+  const uint32_t n_in = frames ? frames : n;
+  for (uint32_t k = 0; k < n_in; k++) {
     if (!re[k] || !im[k]) return set_error(HCK_EINVAL, "null input");
-    if (!wk.gks[k] || !wk.rlk[k]) return set_error(HCK_EINVAL, "null key");
     if (re[k]->level != re[0]->level || im[k]->level != re[0]->level || re[0]->level < l0)
       return set_error(HCK_ELEVEL, "inputs must share a level of at least the plan's level");
+  }
+  for (uint32_t k = 0; k < n; k++) {
+    if (!wk.gks[k] || !wk.rlk[k]) return set_error(HCK_EINVAL, "null key");
     for (int i = 0; i < 4; i++)
       if (!out[4 * k + i]) return set_error(HCK_EINVAL, "null output");
   }
-  for (int32_t s : plan_steps(p))
+  for (int32_t s : frames ? frame_steps(p) : plan_steps(p))
     for (uint32_t k = 0; k < n; k++)
       if (!wk.gks[k]->keys.count(galois_of_step(ctx, s)))
         return set_error(HCK_ENOKEY, "missing Galois key for step " + std::to_string(s));
@@ -247,9 +276,9 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     for (auto &c : v) c = sc.get();
     return v;
   };
-  std::vector<const hck_ciphertext *> in_re(re, re + n), in_im(im, im + n);
+  std::vector<const hck_ciphertext *> in_re(re, re + n_in), in_im(im, im + n_in);
   if (re[0]->level > l0)
-    for (uint32_t k = 0; k < n; k++) {
+    for (uint32_t k = 0; k < n_in; k++) {
       hck_ciphertext *a = sc.get(), *b = sc.get();
       TRY(hck_drop_level(ctx, re[k], l0, a));
       TRY(hck_drop_level(ctx, im[k], l0, b));
@@ -264,63 +293,119 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
   };
 
-  // K1: p = Re^2 + Im^2 (one batched relinearization), E = sum over frames
-  std::vector<hck_ciphertext *> pw = fresh(n), e = fresh(n), t = fresh(n), u = fresh(n);
-  for (uint32_t k = 0; k < n; k++) {
-    TRY(hck_mul(ctx, re[k], re[k], t[k]));
-    TRY(hck_mul(ctx, im[k], im[k], u[k]));
-    TRY(hck_add(ctx, t[k], u[k], t[k]));
+  // K1 -> K4 run on "units": the windows (batched packing: every frame of a
+  // window in one ciphertext pair) or the frames of the one window
+  // (per-frame packing).  uw[u] is the window a unit belongs to.
+  const uint32_t U = frames ? frames : n;
+  std::vector<uint32_t> uw(U), uw2(2 * U);
+  for (uint32_t u = 0; u < U; u++) uw[u] = uw2[2 * u] = uw2[2 * u + 1] = frames ? 0 : u;
+
+  // K1: p = Re^2 + Im^2 (one batched relinearization); E = the sum over
+  // frames, on a copy at the bin branch's level: by rotations R, 2R, ...
+  // (batched) or by additions of the frames' copies (per frame)
+  std::vector<hck_ciphertext *> pw = fresh(U), e = fresh(n), ts, outs;
+  for (uint32_t u = 0; u < U; u++) {
+    hck_ciphertext *t = sc.get(), *v = sc.get();
+    TRY(hck_mul(ctx, re[u], re[u], t));
+    TRY(hck_mul(ctx, im[u], im[u], v));
+    TRY(hck_add(ctx, t, v, t));
+    ts.push_back(t);
   }
-  TRY(relin_rs(ctx, t, one, wk, pw));
-  for (uint32_t k = 0; k < n; k++) {
+  TRY(relin_rs(ctx, ts, uw, wk, pw));
+  for (uint32_t u = 0; u < U; u++) {
+    hck_ciphertext *dst = frames && u ? sc.get() : e[uw[u]];
     if (p->mag_degree) {  // the polynomial magnitude ~ |z| instead of the power
       hck_ciphertext *mg = sc.get();
-      TRY(hck_poly_eval(ctx, pw[k], p->mag_coeffs, p->mag_degree, wk.rlk[k], mg));
-      TRY(hck_drop_level(ctx, mg, bin_level, e[k]));
+      TRY(hck_poly_eval(ctx, pw[u], p->mag_coeffs, p->mag_degree, wk.rlk[uw[u]], mg));
+      TRY(hck_drop_level(ctx, mg, bin_level, dst));
     } else {
-      TRY(hck_drop_level(ctx, pw[k], bin_level, e[k]));
+      TRY(hck_drop_level(ctx, pw[u], bin_level, dst));
     }
+    if (dst != e[uw[u]]) TRY(hck_add(ctx, e[uw[u]], dst, e[uw[u]]));
   }
-  TRY(rotsum(ctx, e, one, r, t2, wk, sc));
+  if (!frames) TRY(rotsum(ctx, e, one, r, t2, wk, sc));
   for (uint32_t k = 0; k < n; k++) {
-    TRY(tap(k, 0, pw[k]));
+    if (!frames) TRY(tap(k, 0, pw[k]));
     TRY(tap(k, 1, e[k]));
   }
   // K2 over bins, w = E^gamma by squarings on the bin branch's level, and
-  // K4 (P_phi = 2)
-  std::vector<hck_ciphertext *> w = fresh(n), m = fresh(n), ts, outs, tm;
-  for (uint32_t k = 0; k < n; k++) {
-    hck_ciphertext *tp = sc.get();
-    TRY(hck_mul(ctx, pw[k], pw[k], tp));
-    tm.push_back(tp);
+  // K4's mask m = p^P_phi: p^2, then p^3 = p^2 p, p^4 = (p^2)^2 or
+  // p^5 = (p^2)^2 p, every product relinearized and rescaled
+  std::vector<hck_ciphertext *> w = fresh(n), m;
+  {
+    const uint32_t pe = phase_power(p);
+    std::vector<hck_ciphertext *> p2 = fresh(U);
+    TRY(square_rs(ctx, pw, 1, uw, wk, p2, sc));
+    m = p2;
+    if (pe >= 4) {
+      std::vector<hck_ciphertext *> p4 = fresh(U);
+      TRY(square_rs(ctx, p2, 1, uw, wk, p4, sc));
+      m = p4;
+    }
+    if (pe == 3 || pe == 5) {  // times p (dropped to the power's level)
+      std::vector<hck_ciphertext *> tm, mo = fresh(U);
+      for (uint32_t u = 0; u < U; u++) {
+        hck_ciphertext *pl = sc.get(), *tp = sc.get();
+        TRY(hck_drop_level(ctx, pw[u], m[u]->level, pl));
+        TRY(hck_mul(ctx, m[u], pl, tp));
+        tm.push_back(tp);
+      }
+      TRY(relin_rs(ctx, tm, uw, wk, mo));
+      m = mo;
+    }
   }
-  TRY(relin_rs(ctx, tm, one, wk, m));
   TRY(square_rs(ctx, e, sq, one, wk, w, sc));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 2, w[k]));
-  std::vector<hck_ciphertext *> it = fresh(n), qt = fresh(n);
+  std::vector<hck_ciphertext *> iq = fresh(2 * U);
   ts.clear();
-  outs.clear();
+  for (uint32_t u = 0; u < U; u++) {
+    hck_ciphertext *re2 = sc.get(), *im2 = sc.get(), *ti = sc.get(), *tq = sc.get();
+    TRY(hck_drop_level(ctx, re[u], m[u]->level, re2));
+    TRY(hck_drop_level(ctx, im[u], m[u]->level, im2));
+    TRY(hck_mul(ctx, m[u], re2, ti));
+    TRY(hck_mul(ctx, m[u], im2, tq));
+    ts.insert(ts.end(), {ti, tq});
+  }
   for (uint32_t k = 0; k < n; k++) {
     TRY(mulpt_rs(ctx, w[k], p->bin_index, O(k, 0)));
     TRY(mulpt_rs(ctx, w[k], p->bin_mask, O(k, 1)));
-    hck_ciphertext *re2 = sc.get(), *im2 = sc.get(), *ti = sc.get(), *tq = sc.get();
-    TRY(hck_drop_level(ctx, re[k], m[k]->level, re2));
-    TRY(hck_drop_level(ctx, im[k], m[k]->level, im2));
-    TRY(hck_mul(ctx, m[k], re2, ti));
-    TRY(hck_mul(ctx, m[k], im2, tq));
-    ts.insert(ts.end(), {ti, tq});
-    outs.insert(outs.end(), {it[k], qt[k]});
   }
-  TRY(relin_rs(ctx, ts, two, wk, outs));
+  TRY(relin_rs(ctx, ts, uw2, wk, iq));
   {
     // the bins' sums (low level) and K4's I and Q (high level): two chains
-    std::vector<hck_ciphertext *> bins, iq;
-    for (uint32_t k = 0; k < n; k++) {
-      bins.insert(bins.end(), {O(k, 0), O(k, 1)});
-      iq.insert(iq.end(), {it[k], qt[k]});
-    }
+    std::vector<hck_ciphertext *> bins;
+    for (uint32_t k = 0; k < n; k++) bins.insert(bins.end(), {O(k, 0), O(k, 1)});
     TRY(rotsum(ctx, bins, two, 1, (uint32_t)r, wk, sc));
-    TRY(rotsum(ctx, iq, two, 1, (uint32_t)r, wk, sc));
+    TRY(rotsum(ctx, iq, uw2, 1, (uint32_t)r, wk, sc));
+  }
+  std::vector<hck_ciphertext *> it(n), qt(n);
+  if (!frames) {
+    for (uint32_t k = 0; k < n; k++) {
+      it[k] = iq[2 * k];
+      qt[k] = iq[2 * k + 1];
+    }
+  } else {
+    // frame t's I and Q (slot 0 of its pair) to slot t R of one ciphertext
+    // each, as the batched packing holds them: at step j every other entry
+    // is rotated by -2^j R and added to its left neighbour (keys for -R,
+    // -2R, ..., -(T2/2) R)
+    std::vector<hck_ciphertext *> cur = iq;  // I_0, Q_0, I_1, Q_1, ...
+    for (int32_t shift = r; cur.size() > 2; shift *= 2) {
+      std::vector<hck_ciphertext *> src, nxt;
+      for (size_t i = 2; i + 1 < cur.size(); i += 4) src.insert(src.end(), {cur[i], cur[i + 1]});
+      std::vector<hck_ciphertext *> rot = fresh((uint32_t)src.size());
+      TRY(rotate_members(ctx, src, std::vector<uint32_t>(src.size(), 0), -shift, wk, rot));
+      for (size_t i = 0; i < cur.size(); i += 4) {
+        if (i + 2 < cur.size()) {
+          TRY(hck_add(ctx, cur[i], rot[i / 2], cur[i]));
+          TRY(hck_add(ctx, cur[i + 1], rot[i / 2 + 1], cur[i + 1]));
+        }
+        nxt.insert(nxt.end(), {cur[i], cur[i + 1]});
+      }
+      cur = nxt;
+    }
+    it[0] = cur[0];
+    qt[0] = cur[1];
   }
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 3, it[k]));
@@ -502,6 +587,31 @@ int hck_vital_eval_taps(hck_context *ctx, const hck_vital_plan *p, const hck_cip
   TRY(check_aliases(ctx, &re, &im, 1, out, 4));
   if (taps) TRY(check_aliases(ctx, &re, &im, 1, taps, HCK_VITAL_TAPS));
   return vital_eval_windows(ctx, p, &re, &im, 1, WindowKeys{&gks, &rlk}, out, taps);
+}
+
+int hck_vital_frames_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
+                                    int32_t *steps, uint32_t cap, uint32_t *n) {
+  if (!ctx || !n) return set_error(HCK_EINVAL, "null argument");
+  TRY(check_plan(ctx, plan));
+  const std::vector<int32_t> s = frame_steps(plan);
+  *n = (uint32_t)s.size();
+  if (steps) {
+    if (cap < s.size()) return set_error(HCK_EINVAL, "steps buffer too small");
+    std::copy(s.begin(), s.end(), steps);
+  }
+  return HCK_OK;
+}
+
+int hck_vital_eval_frames(hck_context *ctx, const hck_vital_plan *p,
+                          const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                          uint32_t frames, const hck_galois_keys *gks, const hck_switch_key *rlk,
+                          hck_ciphertext *const *out) {
+  if (!ctx || !re || !im || !gks || !rlk || !out || frames == 0)
+    return set_error(HCK_EINVAL, "null argument");
+  if (foreign(ctx, gks) || foreign(ctx, rlk))
+    return set_error(HCK_EINVAL, "handle of another (or a destroyed) context");
+  TRY(check_aliases(ctx, re, im, frames, out, 4));
+  return vital_eval_windows(ctx, p, re, im, 1, WindowKeys{&gks, &rlk}, out, nullptr, frames);
 }
 
 int hck_vital_eval_many(hck_context *ctx, const hck_vital_plan *p,

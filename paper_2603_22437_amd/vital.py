@@ -19,11 +19,19 @@ def _next_pow2(x: int) -> int:
 BIN_LEVEL = 3
 
 
-def plan_levels(taylor_order: int, level0: int, gamma: int = 2) -> dict:
+def phase_extra(phase_power: int = 2) -> int:
+    """Levels K4's mask p^P_phi takes beyond p^2 (p^3 = p^2 p, p^4 = (p^2)^2,
+    p^5 = (p^2)^2 p)."""
+    return {2: 0, 3: 1, 4: 1, 5: 2}[phase_power]
+
+
+def plan_levels(taylor_order: int, level0: int, gamma: int = 2, phase_power: int = 2) -> dict:
     """Level at which each operand is applied, for inputs at level0."""
-    dft = level0 - (7 if taylor_order == 3 else 5)
+    e = phase_extra(phase_power)
+    dft = level0 - (7 if taylor_order == 3 else 5) - e
     squarings = {2: 1, 4: 2}[gamma]
-    return dict(bins=2, fir=level0 - 3, third=level0 - 5, dft=dft, freq=dft - 2 - squarings)
+    return dict(bins=2, fir=level0 - 3 - e, third=level0 - 5 - e, dft=dft,
+                freq=dft - 2 - squarings)
 
 
 def operand_vectors(cfg: dict, n_slots: int) -> dict:
@@ -105,7 +113,8 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
     is applied, at scale q_level (a product then keeps the ciphertext scale)."""
     from . import VitalPlan
     vec = operand_vectors(cfg, ctx.n // 2) if vectors is None else vectors
-    lv = plan_levels(cfg["taylor_order"], level0, cfg.get("gamma", 2))
+    lv = plan_levels(cfg["taylor_order"], level0, cfg.get("gamma", 2),
+                     cfg.get("phase_power", 2))
     q = ctx.q
 
     def pt(name, level):
@@ -121,7 +130,8 @@ def encode_plan(ctx, cfg: dict, level0: int, vectors: dict | None = None):
     for name in ("freq", "mask"):
         ops[name] = pt(name, lv["freq"])
     return VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"], len(cfg["k_resp"]),
-                           len(cfg["k_hr"]), ops, cfg.get("mag_coeffs"), cfg.get("gamma", 2))
+                           len(cfg["k_hr"]), ops, cfg.get("mag_coeffs"), cfg.get("gamma", 2),
+                           cfg.get("phase_power", 2))
 
 
 def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
@@ -143,7 +153,7 @@ def plain_stages(cfg: dict, z: np.ndarray, n_slots: int) -> list:
     e = mag.sum(axis=0)
     gamma = cfg.get("gamma", 2)
     w = e ** gamma
-    m = p ** 2
+    m = p ** cfg.get("phase_power", 2)
     i_t, q_t = (m * re).sum(axis=1), (m * im).sum(axis=1)
     out = [(np.arange(F * R), p.reshape(-1)), (np.arange(R), e), (np.arange(R), w),
            (frame0, i_t), (frame0, q_t)]

@@ -262,7 +262,8 @@ def sqrt_poly(degree: int) -> list:
 def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
                           taps: int = 41, taylor_order: int = 3, fir_gain: float = 5.0,
                           dft_gain: float = 10.0, magnitude_degree: int = 0,
-                          gamma: int = 2, fir_backend: str = "toeplitz") -> dict:
+                          gamma: int = 2, fir_backend: str = "toeplitz",
+                          phase_power: int = 2) -> dict:
     """The vital-sign pipeline's public parameters (section 3.3.3 example
     pipeline): respiration 0.1-0.6 Hz and heart rate 0.8-2.5 Hz bands, the
     FIR taps of each band (times fir_gain), the Hann window of the phase DFT
@@ -279,12 +280,14 @@ def vital_pipeline_config(frames: int = 200, bins: int = 64, fps: float = 20.0,
     1e-3 absolute accuracy and their ratio stays well conditioned against the
     absolute noise of the lane-sum rotations.  With magnitude_degree > 0 the configuration also
     carries the power-basis coefficients of a polynomial magnitude (sqrt_poly),
-    which the bin estimate's energy sums instead of the power."""
+    which the bin estimate's energy sums instead of the power.  phase_power is
+    K4's mask exponent P_phi (2 .. 5)."""
     res = fps / frames
     bands = {"resp": (0.1, 0.6), "hr": (0.8, 2.5)}
     cfg = dict(frames=frames, bins=bins, fps=fps, taylor_order=taylor_order,
                window=np.hanning(frames), dft_gain=dft_gain, gamma=gamma,
-               rate_gain={"resp": 1e3, "hr": 1e-1}, fir_backend=fir_backend)
+               rate_gain={"resp": 1e3, "hr": 1e-1}, fir_backend=fir_backend,
+               phase_power=phase_power)
     if magnitude_degree:
         # the bin estimate's energy sums a polynomial magnitude instead of the power
         cfg["mag_coeffs"] = sqrt_poly(magnitude_degree)

@@ -2,9 +2,11 @@
 
 * N = 2^15, L = 12 (the third-order circuit's 11 levels): residues of all four
   outputs bit-exact (also with the polynomial magnitude option, with
-  gamma = 4 and with the rotation-based FIR backend) against the oracle's pipeline, both sides fed the same
+  gamma = 4, with the rotation-based FIR backend and with K4 exponents
+  P_phi = 3, 4, 5) against the oracle's pipeline, both sides fed the same
   integer operands (encoded once by the oracle) and the same encrypted
-  window.
+  window; per-frame packing bit-exact against the oracle's per-frame
+  composition at N = 2^12.
 * N = 2^16, L = 24 (the benchmark ring), with the library's own encoder:
   decoded outputs against the circuit on plaintext numbers.
 """
@@ -47,20 +49,22 @@ def _import_plan(ctx, o, cfg, ops):
             handles[name] = ctx.plaintext_import(v.res, v.level, v.scale)
     return H.VitalPlan.build(cfg["frames"], cfg["bins"], cfg["taylor_order"],
                              len(cfg["k_resp"]), len(cfg["k_hr"]), handles,
-                             cfg.get("mag_coeffs"), cfg.get("gamma", 2))
+                             cfg.get("mag_coeffs"), cfg.get("gamma", 2),
+                             cfg.get("phase_power", 2))
 
 
-@pytest.mark.parametrize("order,magnitude,gamma,fir", [
-    (3, 0, 2, "toeplitz"), (1, 0, 2, "toeplitz"), (3, 8, 2, "toeplitz"), (1, 0, 4, "toeplitz"),
-    (3, 0, 2, "rotation")])
-def test_vital_pipeline_matches_oracle(order, magnitude, gamma, fir):
+@pytest.mark.parametrize("order,magnitude,gamma,fir,phase", [
+    (3, 0, 2, "toeplitz", 2), (1, 0, 2, "toeplitz", 2), (3, 8, 2, "toeplitz", 2),
+    (1, 0, 4, "toeplitz", 2), (3, 0, 2, "rotation", 2), (1, 0, 2, "toeplitz", 3),
+    (1, 0, 2, "toeplitz", 4), (1, 0, 2, "toeplitz", 5)])
+def test_vital_pipeline_matches_oracle(order, magnitude, gamma, fir, phase):
     prm = S.params("mix15")
     o = O.Oracle(prm)
     ctx = H.Context.from_params(prm)
     s_o = o.keygen_secret(1)
     sk = ctx.keygen_secret(1)
     cfg = S.vital_pipeline_config(taylor_order=order, magnitude_degree=magnitude, gamma=gamma,
-                                  fir_backend=fir)
+                                  fir_backend=fir, phase_power=phase)
     z = S.vital_window(1001, cfg["frames"], cfg["bins"])
     l0 = o.L - 1
     ops = OV.encode_operands(o, cfg, l0)
@@ -134,6 +138,10 @@ def test_vital_plan_errors():
                                         len(prm["q"]) - 1), 4)
     with pytest.raises(H.HckError):   # keys missing
         ctx.vital_eval(plan, top, top, gks, rlk)
+    for e in (1, 6):                  # P_phi outside 2 .. 5
+        odd = H.VitalPlan.build(cfg["frames"], cfg["bins"], 3, 6, 18, plan._keep, phase_power=e)
+        with pytest.raises(H.HckError):
+            ctx.vital_required_steps(odd)
 
 
 def test_vital_windows_together_match_single_windows():
@@ -264,3 +272,62 @@ def test_vital_magnitude_option_decodes_at_benchmark_ring():
     assert abs(num - want["num_bin"][0]) < 1e-3 and abs(den - want["den_bin"][0]) < 1e-3
     target = int(np.argmax(np.abs(z).sum(axis=0)))
     assert abs(num / den - target) < 1.0
+
+
+def test_vital_per_frame_packing_matches_oracle():
+    """Per-frame packing (section 3.3.2) at N = 2^12, L = 12, 32 frames of 32
+    bins: the four outputs bit-exact against the oracle's per-frame
+    composition, both sides fed the same integer operands and frame pairs."""
+    prm = S.params("gest12")
+    o = O.Oracle(prm)
+    ctx = H.Context.from_params(prm)
+    s_o = o.keygen_secret(1)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config(frames=32, bins=32, fps=4.0)
+    z = S.vital_window(1003, cfg["frames"], cfg["bins"], fps=cfg["fps"])
+    l0 = o.L - 1
+    ops = OV.encode_operands(o, cfg, l0)
+    plan = _import_plan(ctx, o, cfg, ops)
+    steps = OV.frames_required_steps(o, cfg, ops)
+    assert ctx.vital_frames_required_steps(plan) == steps
+    gko = {o.galois_element(k): o.keygen_galois(s_o, o.galois_element(k), 5) for k in steps}
+    rlk_o = o.keygen_relin(s_o, 7)
+    gks = ctx.keygen_rotation(sk, steps, 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    res_o, ims_o = OV.encrypt_frames(o, s_o, z, l0, prm["scale"], 300)
+    res = [ctx.ciphertext_import(c.polys, l0, c.scale) for c in res_o]
+    ims = [ctx.ciphertext_import(c.polys, l0, c.scale) for c in ims_o]
+    got = ctx.vital_eval_frames(plan, res, ims, gks, rlk)
+    want = OV.evaluate_frames(o, cfg, ops, res_o, ims_o, gko, rlk_o)
+    for name, g in zip(OV.OUTPUTS, got):
+        r, lvl, sc = ctx.ciphertext_export(g)
+        assert lvl == want[name].level and sc == want[name].scale, name
+        assert np.array_equal(r, want[name].polys), name
+    with pytest.raises(H.HckError):     # one frame short of the plan's
+        ctx.vital_eval_frames(plan, res[:-1], ims[:-1], gks, rlk)
+
+
+def test_vital_per_frame_packing_decodes_at_benchmark_ring():
+    """200 frame pairs of 64 bins at N = 2^16, L = 24 (encrypted at the plan's
+    level 12): the outputs decode to the plaintext circuit's numbers."""
+    prm = S.params("vital")
+    ctx = H.Context.from_params(prm)
+    sk = ctx.keygen_secret(1)
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1002, cfg["frames"], cfg["bins"])
+    l0 = 12
+    plan = HV.encode_plan(ctx, cfg, l0)
+    gks = ctx.keygen_rotation(sk, ctx.vital_frames_required_steps(plan), 5)
+    rlk = ctx.keygen_relin(sk, 7)
+    res, ims = [], []
+    for t in range(cfg["frames"]):
+        v = np.zeros(ctx.n_slots, dtype=np.complex128)
+        v[: cfg["bins"]] = z[t]
+        res.append(ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], l0), 2 * t))
+        ims.append(ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], l0), 2 * t + 1))
+    got = ctx.vital_eval_frames(plan, res, ims, gks, rlk)
+    want = OV.plain_slots(cfg, z, ctx.n_slots)
+    for name, g in zip(OV.OUTPUTS, got):
+        dec = ctx.decode(ctx.decrypt(sk, g)).real
+        for slot, v in want[name].items():
+            assert abs(dec[slot] - v) < decoded_tol(v), (name, slot, dec[slot], v)

@@ -31,10 +31,12 @@ def test_operand_vectors_match_oracle(order):
         lg = OV.levels(dict(cfg, gamma=g), 23)
         hg = HV.plan_levels(order, 23, g)
         assert (hg["bins"], hg["freq"]) == (lg["bin_index"], lg["freq"])
-    lv = OV.levels(cfg, 23)
-    hl = HV.plan_levels(order, 23)
-    assert (hl["bins"], hl["fir"], hl["third"], hl["dft"], hl["freq"]) == (
-        lv["bin_index"], lv["fir"], lv["third"], lv["dft"], lv["freq"])
+    for e in (2, 3, 4, 5):
+        lv = OV.levels(dict(cfg, phase_power=e), 23)
+        hl = HV.plan_levels(order, 23, 2, e)
+        assert (hl["bins"], hl["fir"], hl["third"], hl["dft"], hl["freq"]) == (
+            lv["bin_index"], lv["fir"], lv["third"], lv["dft"], lv["freq"])
+        assert hl["fir"] == 20 - {2: 0, 3: 1, 4: 1, 5: 2}[e]
     assert HV.BIN_LEVEL == OV.BIN_LEVEL
 
 
@@ -87,16 +89,34 @@ def test_plain_circuit_is_the_dsp_it_approximates():
     assert abs((y * x ** 2 - y ** 3 / 3) - np.arctan2(y, x) * x ** 3) < 1e-9
 
 
+def test_phase_mask_concentrates_with_its_exponent():
+    """K4 (Eq. phase_mask): the larger P_phi, the larger the share of every
+    frame's mask on the highest-energy range bin, so that (I, Q) approach
+    that bin's samples."""
+    cfg = S.vital_pipeline_config()
+    z = S.vital_window(1000, cfg["frames"], cfg["bins"])
+    p = np.abs(z) ** 2
+    top = np.argmax(p, axis=1)
+    shares = []
+    for e in (2, 3, 4, 5):
+        m = p ** e
+        shares.append(np.mean(m[np.arange(len(top)), top] / m.sum(axis=1)))
+    assert all(a < b for a, b in zip(shares, shares[1:]))
+    assert shares[-1] > 0.9
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("magnitude,order,gamma", [(0, 3, 2), (8, 3, 2), (0, 1, 4)])
-def test_oracle_pipeline_decodes_to_plain_circuit(magnitude, order, gamma):
+@pytest.mark.parametrize("magnitude,order,gamma,phase", [
+    (0, 3, 2, 2), (8, 3, 2, 2), (0, 1, 4, 2), (0, 1, 2, 3), (0, 1, 2, 5)])
+def test_oracle_pipeline_decodes_to_plain_circuit(magnitude, order, gamma, phase):
     """The oracle pipeline at N = 2^15 (L = 12: the 11 levels of the third
     order circuit) decodes to the plaintext circuit's numbers, also with the
-    polynomial magnitude option."""
+    polynomial magnitude option, gamma = 4 and the K4 exponents 3 and 5."""
     prm = S.params("mix15")
     o = O.Oracle(prm)
     s = o.keygen_secret(1)
-    cfg = S.vital_pipeline_config(magnitude_degree=magnitude, taylor_order=order, gamma=gamma)
+    cfg = S.vital_pipeline_config(magnitude_degree=magnitude, taylor_order=order, gamma=gamma,
+                                  phase_power=phase)
     z = S.vital_window(1000, cfg["frames"], cfg["bins"])
     l0 = o.L - 1
     ops = OV.encode_operands(o, cfg, l0)
@@ -106,7 +126,7 @@ def test_oracle_pipeline_decodes_to_plain_circuit(magnitude, order, gamma):
     re, im = OV.encrypt_window(o, s, z, l0, prm["scale"], 100)
     out = OV.evaluate(o, cfg, ops, re, im, gks, rlk)
     want = OV.plain_slots(cfg, z, o.n_slots)
-    depth = (11 if order == 3 else 9) + (gamma.bit_length() - 2)
+    depth = (11 if order == 3 else 9) + (gamma.bit_length() - 2) + OV.phase_extra(cfg)
     for k in OV.OUTPUTS:
         assert out[k].level == (1 if k.endswith("bin") else l0 - depth)
         dec = o.decode(o.decrypt(s, out[k])).real
@@ -140,3 +160,41 @@ def test_sqrt_polynomial_is_the_magnitude():
     err = np.abs(np.polynomial.polynomial.polyval(x, c) - np.sqrt(x))
     assert err.max() < 0.04 and err[x >= 0.05].max() < 0.02
     assert max(abs(v) for v in c) * 2.0 ** 50 < 2.0 ** 63
+
+
+def _small_frames_config():
+    """A window the per-frame composition can run on a small ring: 32 frames
+    at 4 frames/s (0.125 Hz bins: 4 respiration and 14 heart-rate bins) of
+    32 range bins."""
+    return S.vital_pipeline_config(frames=32, bins=32, fps=4.0)
+
+
+@pytest.mark.slow
+def test_oracle_per_frame_pipeline_decodes_to_plain_circuit():
+    """The oracle's per-frame composition (section 3.3.2) at N = 2^12, L = 12:
+    32 frame pairs decode to the plaintext circuit's numbers and to the
+    batched composition's decoded outputs."""
+    prm = S.params("gest12")
+    o = O.Oracle(prm)
+    s = o.keygen_secret(1)
+    cfg = _small_frames_config()
+    z = S.vital_window(1003, cfg["frames"], cfg["bins"], fps=cfg["fps"])
+    l0 = o.L - 1
+    ops = OV.encode_operands(o, cfg, l0)
+    steps = OV.frames_required_steps(o, cfg, ops)
+    assert set(OV.required_steps(o, cfg, ops)) < set(steps)
+    assert {-32, -64, -128, -256, -512} <= set(steps)
+    gks = {o.galois_element(k): o.keygen_galois(s, o.galois_element(k), 5) for k in steps}
+    rlk = o.keygen_relin(s, 7)
+    res, ims = OV.encrypt_frames(o, s, z, l0, prm["scale"], 300)
+    got = OV.evaluate_frames(o, cfg, ops, res, ims, gks, rlk)
+    re, im = OV.encrypt_window(o, s, z, l0, prm["scale"], 100)
+    bat = OV.evaluate(o, cfg, ops, re, im, gks, rlk)
+    want = OV.plain_slots(cfg, z, o.n_slots)
+    for k in OV.OUTPUTS:
+        assert got[k].level == bat[k].level
+        dg = o.decode(o.decrypt(s, got[k])).real
+        db = o.decode(o.decrypt(s, bat[k])).real
+        for slot, v in want[k].items():
+            tol = 1e-6 * max(1.0, abs(v))
+            assert abs(dg[slot] - v) < tol and abs(dg[slot] - db[slot]) < tol, (k, slot)
