@@ -125,6 +125,10 @@ def main():
         log(f"key-switch schedule tuned in {tuning['seconds']} s: "
             f"{tuning['keyswitches_per_launch']}")
 
+    dnum_tuning = None
+    if not args.no_autotune and not args.quick:
+        dnum_tuning = dnum_autotune(prm, top, log)
+
     # window -> bin-major slots (slot r*200 + t), real and imaginary ciphertexts
     z = S.vital_window(1000, FRAMES, BINS)
     v = np.zeros(n_slots, dtype=np.complex128)
@@ -324,6 +328,7 @@ def main():
             "keyswitch_schedule": "autotuned" if tuning else "built-in rule",
         },
         "autotune": tuning,
+        "dnum_tuning": dnum_tuning,
         "decoded_max_abs_err": max_err,
         "window_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                               "p99": round(float(np.percentile(step_ms, 99)), 3),
@@ -533,6 +538,8 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
     torch.cuda.synchronize()
     rotation_fir_ms = (time.perf_counter() - t0) * 1e3 / fir_windows
     del rgks, rplan
+    graph = vital_graph_replay(ctx, plan, re, im, gks, rlk, outs, log)
+    per_frame = vital_per_frame(ctx, prm, cfg, plan, sk, rlk, z, base, outs, log)
     ctx.vital_eval(plan, re, im, gks, rlk, outs)
     noise = kernel_noise(ctx, prm, sk, top, base, VITAL_DEPTHS, ctx.VITAL_TAPS + plan.OUTPUTS,
                          lambda re_, im_: _flat(ctx.vital_eval_taps(plan, re_, im_, gks, rlk)),
@@ -548,6 +555,7 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "windows_per_s": round(windows / wall, 2),
            "batched_8_windows_per_s": round(batched_wps, 2),
            "rotation_fir_backend_ms_per_window": round(rotation_fir_ms, 3),
+           "graph_replay": graph, "per_frame_packing": per_frame,
            "taylor_order": cfg["taylor_order"], "input_level": top, "plan_level": base,
            "rotation_keys": len(gks), "target_bin_true": target,
            "target_bin_est": round(float(got[0][0] / got[1][0]), 4),
@@ -561,6 +569,98 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "kernel_noise": noise}
     log(f"vital pipeline: {res}")
     return res
+
+
+def dnum_autotune(prm, level, log, dnums=(2, 3, 4, 6, 8)):
+    """The digit-count autotuner (hck_autotune_dnum) over the benchmark ring
+    and chain: microseconds per top-level key switch and the switching-key
+    size for each dnum (K = ceil(L / dnum) special primes of 60 bits)."""
+    import paper_2603_22437_amd as H
+    import seeded_inputs as S
+    t0 = time.time()
+    cands = [S.params_with_dnum(prm["name"], d) for d in dnums]
+    r = H.autotune_dnum(cands, level=level, count=8)
+    res = {"level": level,
+           "candidates": [{"dnum": c["dnum"], "K": len(c["p"]),
+                           "us_per_keyswitch": round(u, 1), "key_MiB": round(kb / 2 ** 20, 1)}
+                          for c, u, kb in zip(cands, r["us_per_switch"], r["key_bytes"])],
+           "fastest_dnum": cands[r["best"]]["dnum"], "benchmark_dnum": prm["dnum"],
+           "seconds": round(time.time() - t0, 1)}
+    log(f"dnum tuning: {res}")
+    return res
+
+
+def vital_graph_replay(ctx, plan, re, im, gks, rlk, outs, log, windows=20):
+    """One vital window issued call by call against the same window recorded
+    once into a HIP graph (hck_graph_*) and replayed, both on a stream of the
+    context's own: per-window HIP-event latencies (p50)."""
+    import torch
+    import paper_2603_22437_amd as H
+    old = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    ctx.set_stream(st)
+    ctx.vital_eval(plan, re, im, gks, rlk, outs)
+
+    def per_window(fn):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(windows + 1)]
+        fn()
+        evs[0].record(st)
+        for k in range(windows):
+            fn()
+            evs[k + 1].record(st)
+        st.synchronize()
+        return float(np.median([evs[k].elapsed_time(evs[k + 1]) for k in range(windows)]))
+
+    eager = per_window(lambda: ctx.vital_eval(plan, re, im, gks, rlk, outs))
+    time.sleep(0.05)    # an idle gap that marks the phases apart in a kernel trace
+    with H.Graph.capture([ctx]) as g:
+        ctx.vital_eval(plan, re, im, gks, rlk, outs)
+    replay = per_window(g.launch)
+    nodes = g.info()["nodes"]
+    g.close()
+    st.synchronize()
+    ctx.set_stream(old)
+    res = {"eager_p50_ms": round(eager, 3), "graph_p50_ms": round(replay, 3),
+           "graph_nodes": nodes, "windows": windows}
+    log(f"vital graph replay: {res}")
+    return res
+
+
+def vital_per_frame(ctx, prm, cfg, plan, sk, rlk, z, base, outs, log, windows=3):
+    """The vital pipeline on per-frame packing (section 3.3.2: one ciphertext
+    pair per frame, 200 pairs encrypted at the plan's level) against the
+    batched packing's 2 ciphertexts: latency and the largest difference of
+    the decoded outputs."""
+    import torch
+    from paper_2603_22437_amd import vital as HV
+    gks = ctx.keygen_rotation(sk, ctx.vital_frames_required_steps(plan), 5)
+    res, ims = [], []
+    for t in range(cfg["frames"]):
+        v = np.zeros(ctx.n_slots, dtype=np.complex128)
+        v[: cfg["bins"]] = z[t]
+        res.append(ctx.encrypt_sk(sk, ctx.encode(v.real, prm["scale"], base), 3000 + 2 * t))
+        ims.append(ctx.encrypt_sk(sk, ctx.encode(v.imag, prm["scale"], base), 3001 + 2 * t))
+    got = ctx.vital_eval_frames(plan, res, ims, gks, rlk)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(windows):
+        t0 = time.perf_counter()
+        ctx.vital_eval_frames(plan, res, ims, gks, rlk, got)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    a = [ctx.decode(ctx.decrypt(sk, c)).real for c in got]
+    b = [ctx.decode(ctx.decrypt(sk, c)).real for c in outs]
+    g = HV.lane_group(cfg)
+    # relative to each output's size (the rate sums reach 10^6 on strong
+    # windows, where CKKS noise is relative to the value)
+    diff = max(abs(a[i][s] - b[i][s]) / max(1.0, abs(b[i][s]))
+               for i in range(4) for s in ((0,) if i < 2 else (0, g)))
+    out = {"windows": windows, "input_ciphertexts": 2 * cfg["frames"],
+           "p50_ms": round(float(np.median(ms)), 2), "rotation_keys": len(gks),
+           "decoded_max_diff_vs_batched_rel": float(f"{diff:.3e}")}
+    log(f"vital per-frame packing: {out}")
+    return out
 
 
 def gesture_pipeline_latency(ctx, prm, sk, rlk, windows, log):
