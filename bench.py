@@ -90,6 +90,9 @@ def main():
                     help="skip the serving measurement (256 tenants, Poisson arrivals)")
     ap.add_argument("--serving-seconds", type=float, default=20.0,
                     help="duration of the synthetic serving traffic")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only the device's sustained Shoup-product rate and plain "
+                         "device-to-device copy rates (the measured ALU and copy ceilings)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a plain copy of known "
                          "size, to scale hardware byte counters)")
@@ -105,6 +108,10 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.microbench:
+        print(json.dumps(microbench(log)), flush=True)
+        return
 
     prm = S.params("vital")
     torch.cuda.init()
@@ -568,6 +575,40 @@ def vital_pipeline_latency(ctx, prm, sk, rlk, windows, log):
            "resp_band_den": float(f"{plain_out[-1][1][0]:.3e}"),
            "kernel_noise": noise}
     log(f"vital pipeline: {res}")
+    return res
+
+
+def microbench(log, reps=10):
+    """The measured ceilings quoted beside the published peaks: the sustained
+    rate of 61-bit Shoup modular products (hck_measure_mulmod_rate: 8
+    independent chains per thread, each product fully reduced) and the rate
+    of plain device-to-device copies (torch, bytes read + written) of
+    several sizes, per HIP-event timing."""
+    import torch
+    import paper_2603_22437_amd as H
+    import seeded_inputs as S
+    ctx = H.Context.from_params(S.params("tiny"))
+    mulmod = [round(ctx.measure_mulmod_rate(), 4) for _ in range(3)]
+    ctx.close()
+    copies = {}
+    for mib in (256, 1024, 4096):
+        src = torch.zeros(mib << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        copies[f"{mib}_MiB_GBps"] = round(2 * (mib << 20) / sec / 1e9, 1)
+        del src, dst
+    res = {"metric": "microbench", "shoup_mulmod_T_per_s": mulmod,
+           "valu_lane_ops_peak_T_per_s": round(VALU_LANE_RATE / 1e12, 2),
+           "copy_read_plus_write": copies, "hbm_peak_GBps": HBM_PEAK_GBS}
+    log(f"microbench: {res}")
     return res
 
 
