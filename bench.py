@@ -282,6 +282,14 @@ def main():
                      "Tmulmod/s": round(v["mulmods"] / (v["ms"] * 1e-3) / 1e12, 3)
                      if v["ms"] else None}
                  for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms"])}
+    # HBM rate from the counters' bytes per launch (the committed FETCH_SIZE /
+    # WRITE_SIZE summary) over this run's mean launch time, where the
+    # kernel's source is unchanged since: what reaches HBM, without the L2
+    # re-reads that algorithmic bytes may count
+    for k, v in kernels.items():
+        t = measured_traffic(k)
+        if t and v["ms"]:
+            breakdown[k]["counter_GB/s"] = round(t * v["launches"] / (v["ms"] * 1e-3) / 1e9, 1)
 
     vital = gesture = gesture_cnn = None
     if not args.no_pipeline:

@@ -479,6 +479,15 @@ void destroy_context(hck_context *ctx) {
     (void)hipEventDestroy(t.stop);
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  // the stream-ordered allocator keeps the freed buffers cached in the
+  // device's pool; hand them back, so that a destroyed context's workspace
+  // and keys (several GB at N = 2^16) do not crowd later allocations
+  if (!ctx->alloc_fn) {
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess && pool)
+      (void)hipMemPoolTrimTo(pool, 0);
+    (void)hipGetLastError();
+  }
   delete ctx;
 }
 

@@ -228,6 +228,109 @@ int hck_vital_required_steps(const hck_context *ctx, const hck_vital_plan *plan,
 // their rotate-and-sum chains and relinearizations share key-switch batches.
 // taps (optional, HCK_VITAL_TAPS per window, entries may be null) receive
 // copies of the kernels' intermediate results.
+// frames of the per-frame packing whose K1 and K4 run together (a power of
+// two, so that the frame tree's levels inside a block are its first levels)
+constexpr uint32_t kFrameBlock = 16;
+
+// K1 and K4 on units (windows, or frames of one window) u < uw.size(), unit
+// u belonging to window uw[u]: pw[u] = Re^2 + Im^2; en[u] = its copy for the
+// bin branch (the power, or the polynomial magnitude) at bin_level; iq[2u],
+// iq[2u + 1] = I and Q (mask p^P_phi times Re, Im, summed over the R bins
+// into each frame's first slot).  Intermediates come from sc.
+static int front_units(hck_context *ctx, const hck_vital_plan *p,
+                       const hck_ciphertext *const *re, const hck_ciphertext *const *im,
+                       const std::vector<uint32_t> &uw, const WindowKeys &wk, uint32_t bin_level,
+                       Scratch &sc, std::vector<hck_ciphertext *> &pw,
+                       std::vector<hck_ciphertext *> &en, std::vector<hck_ciphertext *> &iq) {
+  const uint32_t U = (uint32_t)uw.size();
+  auto fresh = [&](uint32_t count) {
+    std::vector<hck_ciphertext *> v(count);
+    for (auto &c : v) c = sc.get();
+    return v;
+  };
+  std::vector<uint32_t> uw2(2 * U);
+  for (uint32_t u = 0; u < U; u++) uw2[2 * u] = uw2[2 * u + 1] = uw[u];
+  // K1: p = Re^2 + Im^2 (one batched relinearization)
+  pw = fresh(U);
+  en = fresh(U);
+  std::vector<hck_ciphertext *> ts;
+  for (uint32_t u = 0; u < U; u++) {
+    hck_ciphertext *t = sc.get(), *v = sc.get();
+    TRY(hck_mul(ctx, re[u], re[u], t));
+    TRY(hck_mul(ctx, im[u], im[u], v));
+    TRY(hck_add(ctx, t, v, t));
+    ts.push_back(t);
+  }
+  TRY(relin_rs(ctx, ts, uw, wk, pw));
+  for (uint32_t u = 0; u < U; u++) {
+    if (p->mag_degree) {  // the polynomial magnitude ~ |z| instead of the power
+      hck_ciphertext *mg = sc.get();
+      TRY(hck_poly_eval(ctx, pw[u], p->mag_coeffs, p->mag_degree, wk.rlk[uw[u]], mg));
+      TRY(hck_drop_level(ctx, mg, bin_level, en[u]));
+    } else {
+      TRY(hck_drop_level(ctx, pw[u], bin_level, en[u]));
+    }
+  }
+  // K4's mask m = p^P_phi: p^2, then p^3 = p^2 p, p^4 = (p^2)^2 or
+  // p^5 = (p^2)^2 p, every product relinearized and rescaled
+  const uint32_t pe = phase_power(p);
+  std::vector<hck_ciphertext *> m = fresh(U);
+  TRY(square_rs(ctx, pw, 1, uw, wk, m, sc));
+  if (pe >= 4) {
+    std::vector<hck_ciphertext *> p4 = fresh(U);
+    TRY(square_rs(ctx, m, 1, uw, wk, p4, sc));
+    m = p4;
+  }
+  if (pe == 3 || pe == 5) {  // times p (dropped to the power's level)
+    std::vector<hck_ciphertext *> tm, mo = fresh(U);
+    for (uint32_t u = 0; u < U; u++) {
+      hck_ciphertext *pl = sc.get(), *tp = sc.get();
+      TRY(hck_drop_level(ctx, pw[u], m[u]->level, pl));
+      TRY(hck_mul(ctx, m[u], pl, tp));
+      tm.push_back(tp);
+    }
+    TRY(relin_rs(ctx, tm, uw, wk, mo));
+    m = mo;
+  }
+  // I and Q: the mask times Re and Im (one batched relinearization), summed
+  // over the range bins by rotations 1 .. R/2
+  iq = fresh(2 * U);
+  ts.clear();
+  for (uint32_t u = 0; u < U; u++) {
+    hck_ciphertext *re2 = sc.get(), *im2 = sc.get(), *ti = sc.get(), *tq = sc.get();
+    TRY(hck_drop_level(ctx, re[u], m[u]->level, re2));
+    TRY(hck_drop_level(ctx, im[u], m[u]->level, im2));
+    TRY(hck_mul(ctx, m[u], re2, ti));
+    TRY(hck_mul(ctx, m[u], im2, tq));
+    ts.insert(ts.end(), {ti, tq});
+  }
+  TRY(relin_rs(ctx, ts, uw2, wk, iq));
+  return rotsum(ctx, iq, uw2, 1, p->bins, wk, sc);
+}
+
+// Levels of the frame tree over the list cur = (I_0, Q_0, I_1, Q_1, ...) of
+// one window: at each level every other entry, rotated by -shift, is added
+// to its left neighbour, and shift doubles; cur ends as (I, Q).
+static int frame_tree(hck_context *ctx, std::vector<hck_ciphertext *> &cur, int32_t shift,
+                      const WindowKeys &wk, Scratch &sc) {
+  for (; cur.size() > 2; shift *= 2) {
+    std::vector<hck_ciphertext *> src, nxt;
+    for (size_t i = 2; i + 1 < cur.size(); i += 4) src.insert(src.end(), {cur[i], cur[i + 1]});
+    std::vector<hck_ciphertext *> rot(src.size());
+    for (auto &c : rot) c = sc.get();
+    TRY(rotate_members(ctx, src, std::vector<uint32_t>(src.size(), 0), -shift, wk, rot));
+    for (size_t i = 0; i < cur.size(); i += 4) {
+      if (i + 2 < cur.size()) {
+        TRY(hck_add(ctx, cur[i], rot[i / 2], cur[i]));
+        TRY(hck_add(ctx, cur[i + 1], rot[i / 2 + 1], cur[i + 1]));
+      }
+      nxt.insert(nxt.end(), {cur[i], cur[i + 1]});
+    }
+    cur = nxt;
+  }
+  return HCK_OK;
+}
+
 // frames > 0: per-frame packing (section 3.3.2) of one window (n = 1):
 // re[t], im[t] (t < frames) hold frame t's R range bins in slots 0 .. R-1.
 static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
@@ -293,119 +396,60 @@ static int vital_eval_windows(hck_context *ctx, const hck_vital_plan *p,
     return t ? hck_drop_level(ctx, c, c->level, t) : HCK_OK;
   };
 
-  // K1 -> K4 run on "units": the windows (batched packing: every frame of a
-  // window in one ciphertext pair) or the frames of the one window
-  // (per-frame packing).  uw[u] is the window a unit belongs to.
-  const uint32_t U = frames ? frames : n;
-  std::vector<uint32_t> uw(U), uw2(2 * U);
-  for (uint32_t u = 0; u < U; u++) uw[u] = uw2[2 * u] = uw2[2 * u + 1] = frames ? 0 : u;
-
-  // K1: p = Re^2 + Im^2 (one batched relinearization); E = the sum over
-  // frames, on a copy at the bin branch's level: by rotations R, 2R, ...
-  // (batched) or by additions of the frames' copies (per frame)
-  std::vector<hck_ciphertext *> pw = fresh(U), e = fresh(n), ts, outs;
-  for (uint32_t u = 0; u < U; u++) {
-    hck_ciphertext *t = sc.get(), *v = sc.get();
-    TRY(hck_mul(ctx, re[u], re[u], t));
-    TRY(hck_mul(ctx, im[u], im[u], v));
-    TRY(hck_add(ctx, t, v, t));
-    ts.push_back(t);
-  }
-  TRY(relin_rs(ctx, ts, uw, wk, pw));
-  for (uint32_t u = 0; u < U; u++) {
-    hck_ciphertext *dst = frames && u ? sc.get() : e[uw[u]];
-    if (p->mag_degree) {  // the polynomial magnitude ~ |z| instead of the power
-      hck_ciphertext *mg = sc.get();
-      TRY(hck_poly_eval(ctx, pw[u], p->mag_coeffs, p->mag_degree, wk.rlk[uw[u]], mg));
-      TRY(hck_drop_level(ctx, mg, bin_level, dst));
-    } else {
-      TRY(hck_drop_level(ctx, pw[u], bin_level, dst));
+  // K1 and K4, then K2 over bins, on the windows (batched packing: every
+  // frame of a window in one ciphertext pair) or on the frames of the one
+  // window (per-frame packing), which run in aligned blocks of kFrameBlock
+  // frames so that only one block's intermediates are held at a time
+  std::vector<hck_ciphertext *> pw, e = fresh(n), it(n), qt(n);
+  if (!frames) {
+    std::vector<hck_ciphertext *> en, iq;
+    TRY(front_units(ctx, p, re, im, one, wk, bin_level, sc, pw, en, iq));
+    for (uint32_t k = 0; k < n; k++) {
+      TRY(hck_drop_level(ctx, en[k], en[k]->level, e[k]));
+      it[k] = iq[2 * k];
+      qt[k] = iq[2 * k + 1];
     }
-    if (dst != e[uw[u]]) TRY(hck_add(ctx, e[uw[u]], dst, e[uw[u]]));
+    TRY(rotsum(ctx, e, one, r, t2, wk, sc));
+  } else {
+    // entries of the frame tree that holds every frame's I and Q at slot t R
+    std::vector<hck_ciphertext *> tree;
+    for (uint32_t b0 = 0; b0 < frames; b0 += kFrameBlock) {
+      const uint32_t nb = std::min(kFrameBlock, frames - b0);
+      Scratch blk(ctx);
+      std::vector<hck_ciphertext *> bpw, en, iq;
+      TRY(front_units(ctx, p, re + b0, im + b0, std::vector<uint32_t>(nb, 0), wk, bin_level, blk,
+                      bpw, en, iq));
+      // E: the frames' energy copies added in frame order
+      for (uint32_t t = 0; t < nb; t++)
+        TRY(b0 + t == 0 ? hck_drop_level(ctx, en[t], en[t]->level, e[0])
+                        : hck_add(ctx, e[0], en[t], e[0]));
+      // the tree's levels inside the block; its one entry survives the block
+      TRY(frame_tree(ctx, iq, (int32_t)r, wk, blk));
+      hck_ciphertext *bi = sc.get(), *bq = sc.get();
+      TRY(hck_drop_level(ctx, iq[0], iq[0]->level, bi));
+      TRY(hck_drop_level(ctx, iq[1], iq[1]->level, bq));
+      tree.insert(tree.end(), {bi, bq});
+    }
+    TRY(frame_tree(ctx, tree, (int32_t)(r * kFrameBlock), wk, sc));
+    it[0] = tree[0];
+    qt[0] = tree[1];
   }
-  if (!frames) TRY(rotsum(ctx, e, one, r, t2, wk, sc));
   for (uint32_t k = 0; k < n; k++) {
     if (!frames) TRY(tap(k, 0, pw[k]));
     TRY(tap(k, 1, e[k]));
   }
-  // K2 over bins, w = E^gamma by squarings on the bin branch's level, and
-  // K4's mask m = p^P_phi: p^2, then p^3 = p^2 p, p^4 = (p^2)^2 or
-  // p^5 = (p^2)^2 p, every product relinearized and rescaled
-  std::vector<hck_ciphertext *> w = fresh(n), m;
-  {
-    const uint32_t pe = phase_power(p);
-    std::vector<hck_ciphertext *> p2 = fresh(U);
-    TRY(square_rs(ctx, pw, 1, uw, wk, p2, sc));
-    m = p2;
-    if (pe >= 4) {
-      std::vector<hck_ciphertext *> p4 = fresh(U);
-      TRY(square_rs(ctx, p2, 1, uw, wk, p4, sc));
-      m = p4;
-    }
-    if (pe == 3 || pe == 5) {  // times p (dropped to the power's level)
-      std::vector<hck_ciphertext *> tm, mo = fresh(U);
-      for (uint32_t u = 0; u < U; u++) {
-        hck_ciphertext *pl = sc.get(), *tp = sc.get();
-        TRY(hck_drop_level(ctx, pw[u], m[u]->level, pl));
-        TRY(hck_mul(ctx, m[u], pl, tp));
-        tm.push_back(tp);
-      }
-      TRY(relin_rs(ctx, tm, uw, wk, mo));
-      m = mo;
-    }
-  }
+  // K2 over bins: w = E^gamma by squarings on the bin branch's level
+  std::vector<hck_ciphertext *> w = fresh(n), ts, outs;
   TRY(square_rs(ctx, e, sq, one, wk, w, sc));
   for (uint32_t k = 0; k < n; k++) TRY(tap(k, 2, w[k]));
-  std::vector<hck_ciphertext *> iq = fresh(2 * U);
-  ts.clear();
-  for (uint32_t u = 0; u < U; u++) {
-    hck_ciphertext *re2 = sc.get(), *im2 = sc.get(), *ti = sc.get(), *tq = sc.get();
-    TRY(hck_drop_level(ctx, re[u], m[u]->level, re2));
-    TRY(hck_drop_level(ctx, im[u], m[u]->level, im2));
-    TRY(hck_mul(ctx, m[u], re2, ti));
-    TRY(hck_mul(ctx, m[u], im2, tq));
-    ts.insert(ts.end(), {ti, tq});
-  }
-  for (uint32_t k = 0; k < n; k++) {
-    TRY(mulpt_rs(ctx, w[k], p->bin_index, O(k, 0)));
-    TRY(mulpt_rs(ctx, w[k], p->bin_mask, O(k, 1)));
-  }
-  TRY(relin_rs(ctx, ts, uw2, wk, iq));
   {
-    // the bins' sums (low level) and K4's I and Q (high level): two chains
     std::vector<hck_ciphertext *> bins;
-    for (uint32_t k = 0; k < n; k++) bins.insert(bins.end(), {O(k, 0), O(k, 1)});
-    TRY(rotsum(ctx, bins, two, 1, (uint32_t)r, wk, sc));
-    TRY(rotsum(ctx, iq, uw2, 1, (uint32_t)r, wk, sc));
-  }
-  std::vector<hck_ciphertext *> it(n), qt(n);
-  if (!frames) {
     for (uint32_t k = 0; k < n; k++) {
-      it[k] = iq[2 * k];
-      qt[k] = iq[2 * k + 1];
+      TRY(mulpt_rs(ctx, w[k], p->bin_index, O(k, 0)));
+      TRY(mulpt_rs(ctx, w[k], p->bin_mask, O(k, 1)));
+      bins.insert(bins.end(), {O(k, 0), O(k, 1)});
     }
-  } else {
-    // frame t's I and Q (slot 0 of its pair) to slot t R of one ciphertext
-    // each, as the batched packing holds them: at step j every other entry
-    // is rotated by -2^j R and added to its left neighbour (keys for -R,
-    // -2R, ..., -(T2/2) R)
-    std::vector<hck_ciphertext *> cur = iq;  // I_0, Q_0, I_1, Q_1, ...
-    for (int32_t shift = r; cur.size() > 2; shift *= 2) {
-      std::vector<hck_ciphertext *> src, nxt;
-      for (size_t i = 2; i + 1 < cur.size(); i += 4) src.insert(src.end(), {cur[i], cur[i + 1]});
-      std::vector<hck_ciphertext *> rot = fresh((uint32_t)src.size());
-      TRY(rotate_members(ctx, src, std::vector<uint32_t>(src.size(), 0), -shift, wk, rot));
-      for (size_t i = 0; i < cur.size(); i += 4) {
-        if (i + 2 < cur.size()) {
-          TRY(hck_add(ctx, cur[i], rot[i / 2], cur[i]));
-          TRY(hck_add(ctx, cur[i + 1], rot[i / 2 + 1], cur[i + 1]));
-        }
-        nxt.insert(nxt.end(), {cur[i], cur[i + 1]});
-      }
-      cur = nxt;
-    }
-    it[0] = cur[0];
-    qt[0] = cur[1];
+    TRY(rotsum(ctx, bins, two, 1, (uint32_t)r, wk, sc));
   }
   for (uint32_t k = 0; k < n; k++) {
     TRY(tap(k, 3, it[k]));
