@@ -132,9 +132,16 @@ def main():
         log(f"key-switch schedule tuned in {tuning['seconds']} s: "
             f"{tuning['keyswitches_per_launch']}")
 
-    dnum_tuning = None
+    dnum_tuning = ntt_tuning = None
     if not args.no_autotune and not args.quick:
         dnum_tuning = dnum_autotune(prm, top, log)
+        t0 = time.time()
+        nt = ctx.autotune_ntt(rows=64)
+        ntt_tuning = {"us_per_row_forward_plus_inverse": {f"R1=2^{a}": round(u, 2)
+                                                          for a, u in nt["splits"].items()},
+                      "chosen_log2_R1": nt["chosen"], "default_log2_R1": (prm["log_n"] + 1) // 2,
+                      "seconds": round(time.time() - t0, 1)}
+        log(f"NTT split tuning: {ntt_tuning}")
 
     # window -> bin-major slots (slot r*200 + t), real and imaginary ciphertexts
     z = S.vital_window(1000, FRAMES, BINS)
@@ -344,6 +351,7 @@ def main():
         },
         "autotune": tuning,
         "dnum_tuning": dnum_tuning,
+        "ntt_tuning": ntt_tuning,
         "decoded_max_abs_err": max_err,
         "window_latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                               "p99": round(float(np.percentile(step_ms, 99)), 3),
@@ -1166,8 +1174,11 @@ def serving_benchmark(seconds, log, tenants=256, key_sets=4, budget_gb=200.0, ma
                 lag = max(lag, time.perf_counter() - base - arrivals[nxt])
                 nxt += 1
             wait = 0 if nxt >= len(arrivals) else max(0.0, arrivals[nxt] - now)
-            results += srv.poll(timeout_ms=int(min(wait, 0.05) * 1000) if nxt < len(arrivals)
-                                else 1000)
+            got = srv.poll(timeout_ms=int(min(wait, 0.05) * 1000) if nxt < len(arrivals)
+                           else 1000)
+            for r in got:       # keep the timing records only (a long run would
+                r.pop("outputs")  # otherwise hold every window's outputs)
+            results += got
             if time.perf_counter() > next_log:
                 log(f"serving: {nxt} submitted, {len(results)} done")
                 next_log += 5.0

@@ -671,6 +671,25 @@ int hck_autotune_keyswitch(hck_context *ctx, const uint32_t *levels, uint32_t n_
 int hck_autotune_dnum(const hck_params *candidates, uint32_t n, int device, void *hip_stream,
                       uint32_t level, uint32_t count, double *us_per_switch, double *key_bytes,
                       uint32_t *best);
+/* Autotuner of the NTT split (the radices of the two passes a full
+ * negacyclic NTT takes on this chip, N = R1 x R2; section 3.2's encoding,
+ * encryption and key material go through full transforms).  Candidates: the
+ * default R1 = 2^ceil(log N / 2) and one step either side where both passes
+ * fit a workgroup (at most 80 KiB of LDS each, a contiguous sub-transform in
+ * one wavefront).  Each is timed on `rows` (1 .. 256) rows of zeros, forward
+ * then inverse (median of 5 after a warm-up); splits[i] (log2 R1) and
+ * us_per_row[i] receive each candidate (cap entries at least, NULL to skip),
+ * *n their count, *chosen the split kept: the default unless another is 2 %
+ * faster.  The choice applies to the context's full transforms (encoding,
+ * encryption, imports, keys, rescale's dropped limb); the fused key-switch
+ * passes keep the default split.  Results never change (tested bit for
+ * bit).  Errors: HCK_EINVAL, HCK_ENOMEM, HCK_EDEVICE. */
+int hck_autotune_ntt(hck_context *ctx, uint32_t rows, int32_t *splits, double *us_per_row,
+                     uint32_t cap, uint32_t *n, int32_t *chosen);
+/* Selects the split of the full transforms by log2 R1 (0: the default) and
+ * reads the one in force.  Errors: HCK_EINVAL (not a candidate). */
+int hck_set_ntt_split(hck_context *ctx, int32_t log_r1);
+int hck_ntt_split(const hck_context *ctx, int32_t *log_r1);
 /* Sets the key switches per launch sequence at `level` (a saved tuning; 0
  * restores the built-in rule), and reads the size in force. */
 int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap);

@@ -170,6 +170,9 @@ SIGNATURES = {
     "hck_switch_key_deserialize": ([_P, _P, _SZ, _PP], _I),
     "hck_vital_frames_required_steps": ([_P, _P, _P, _U32, _PU32], _I),
     "hck_vital_eval_frames": ([_P, _P, _P, _P, _U32, _P, _P, _P], _I),
+    "hck_autotune_ntt": ([_P, _U32, _P, _P, _U32, _PU32, _P], _I),
+    "hck_set_ntt_split": ([_P, _I32], _I),
+    "hck_ntt_split": ([_P, _P], _I),
     "hck_trace_enable": ([_P, _I], _I),
     "hck_trace_read": ([_P, _P, _SZ, ctypes.POINTER(_SZ)], _I),
     "hck_shake256": ([_P, _SZ, _P, _SZ], _I),
@@ -1037,6 +1040,26 @@ class Context:
         _check(capi.hck_autotune_keyswitch(self.h, _ptr(lv), len(lv), count, _ptr(caps),
                                            _ptr(us)))
         return {int(l): (int(c), float(u)) for l, c, u in zip(lv, caps, us)}
+
+    def autotune_ntt(self, rows: int = 64) -> dict:
+        """Times the candidate NTT splits of the full transforms and keeps the
+        fastest; returns {"splits": {log2 R1: us per row}, "chosen": log2 R1}."""
+        sp = np.zeros(3, dtype=np.int32)
+        us = np.zeros(3, dtype=np.float64)
+        n = ctypes.c_uint32()
+        ch = ctypes.c_int32()
+        _check(capi.hck_autotune_ntt(self.h, rows, _ptr(sp), _ptr(us), 3, ctypes.byref(n),
+                                     ctypes.byref(ch)))
+        return {"splits": {int(a): float(u) for a, u in zip(sp[:n.value], us[:n.value])},
+                "chosen": ch.value}
+
+    def set_ntt_split(self, log_r1: int):
+        _check(capi.hck_set_ntt_split(self.h, log_r1))
+
+    def ntt_split(self) -> int:
+        v = ctypes.c_int32()
+        _check(capi.hck_ntt_split(self.h, ctypes.byref(v)))
+        return v.value
 
     def set_keyswitch_cap(self, level: int, cap: int):
         _check(capi.hck_set_keyswitch_cap(self.h, level, cap))

@@ -172,6 +172,83 @@ int hck_autotune_dnum(const hck_params *candidates, uint32_t n, int device, void
   return HCK_OK;
 }
 
+int hck_autotune_ntt(hck_context *ctx, uint32_t rows, int32_t *splits, double *us_per_row,
+                     uint32_t cap, uint32_t *n, int32_t *chosen) {
+  if (!ctx) return set_error(HCK_EINVAL, "null context");
+  if (rows == 0 || rows > (uint32_t)kMaxRows) return set_error(HCK_EINVAL, "rows must be 1..256");
+  if (ctx->capturing) return set_error(HCK_EINVAL, "tuning during graph capture");
+  HCK_HIP(ctx, hipSetDevice(ctx->device));
+  const int a0 = (ctx->log_n + 1) / 2;
+  std::vector<int> cand;
+  for (int a : {a0, a0 - 1, a0 + 1})
+    if (ntt_split_available(ctx->log_n, a)) cand.push_back(a);
+  if (n) *n = (uint32_t)cand.size();
+  if ((splits || us_per_row) && cap < cand.size())
+    return set_error(HCK_EINVAL, "output arrays too small");
+  uint64_t *buf = nullptr;
+  TRY(dev_alloc(ctx, &buf, (size_t)rows * ctx->n));
+  LimbMap map;
+  map.n = rows;
+  for (uint32_t r = 0; r < rows; r++) {
+    map.row[r] = (uint16_t)r;
+    map.mod[r] = (uint8_t)(r % (ctx->L + ctx->K));
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = HCK_OK;
+  if (hipMemsetAsync(buf, 0, (size_t)rows * ctx->n * 8, ctx->stream) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = check_hip(ctx, hipGetLastError(), "NTT tuning set-up");
+  const uint8_t saved = ctx->ntt_a;
+  double best_us = 0;
+  int best = a0;
+  for (size_t i = 0; i < cand.size() && !rc; i++) {
+    rc = set_ntt_split(ctx, cand[i]);
+    std::vector<double> t;
+    for (int r = 0; r <= 5 && !rc; r++) {
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = check_hip(ctx, hipGetLastError(), "event");
+      if (!rc) rc = ntt_forward(ctx, buf, map);
+      if (!rc) rc = ntt_inverse(ctx, buf, map, nullptr);
+      float ms = 0;
+      if (!rc && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                  hipEventSynchronize(e1) != hipSuccess ||
+                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = check_hip(ctx, hipGetLastError(), "NTT tuning timing");
+      if (!rc && r) t.push_back(1e3 * ms / rows);
+    }
+    if (rc) break;
+    std::sort(t.begin(), t.end());
+    const double us = t[t.size() / 2];
+    if (splits) splits[i] = cand[i];
+    if (us_per_row) us_per_row[i] = us;
+    // the default split first: another must beat it by 2 % to replace it
+    if (i == 0 || us < 0.98 * best_us) {
+      best_us = us;
+      best = cand[i];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  dev_free(ctx, buf);
+  if (rc) {
+    ctx->ntt_a = saved;
+    return rc;
+  }
+  if (chosen) *chosen = best;
+  return set_ntt_split(ctx, best);
+}
+
+int hck_set_ntt_split(hck_context *ctx, int32_t log_r1) {
+  if (!ctx) return set_error(HCK_EINVAL, "null context");
+  HCK_HIP(ctx, hipSetDevice(ctx->device));
+  return set_ntt_split(ctx, log_r1);
+}
+
+int hck_ntt_split(const hck_context *ctx, int32_t *log_r1) {
+  if (!ctx || !log_r1) return set_error(HCK_EINVAL, "null argument");
+  *log_r1 = ctx->ntt_a ? ctx->ntt_a : (int32_t)((ctx->log_n + 1) / 2);
+  return HCK_OK;
+}
+
 int hck_set_keyswitch_cap(hck_context *ctx, uint32_t level, uint32_t cap) {
   if (!ctx) return set_error(HCK_EINVAL, "null context");
   if (level >= ctx->L) return set_error(HCK_ELEVEL, "level beyond the chain");

@@ -47,6 +47,30 @@ bool is_prime_u64(uint64_t n) {
 
 // A primitive 2N-th root of unity: psi = x^((q-1)/2N) for the first x >= 3
 // with psi^N = -1 (q prime, q = 1 mod 2N).
+// contiguous-pass twists (ntt_core.h) of one limb for the split 2^log_a x
+// 2^(log_n - log_a): word g R2 + i gets beta_g^i (and beta_g^-i), beta_g =
+// psi^(2 brv_a(g)); pw, ipw hold psi^k, psi^-k for k < N
+void twist_rows(const std::vector<uint64_t> &pw, const std::vector<uint64_t> &ipw, uint64_t q,
+                uint32_t log_n, int log_a, size_t base, std::vector<uint64_t> &ttw,
+                std::vector<uint64_t> &ttws, std::vector<uint64_t> &ittw,
+                std::vector<uint64_t> &ittws) {
+  const uint64_t n = 1ull << log_n;
+  const int log_b = (int)log_n - log_a;
+  for (uint32_t g = 0; g < (1u << log_a); g++) {
+    const uint64_t bg = 2ull * bit_reverse(g, log_a);
+    for (uint32_t i = 0; i < (1u << log_b); i++) {
+      const uint64_t e = bg * i % (2ull * n);   // psi^N = -1
+      const uint64_t f = e < n ? pw[e] : (q - pw[e - n]) % q;
+      const uint64_t fi = e < n ? ipw[e] : (q - ipw[e - n]) % q;
+      const size_t w = base + ((size_t)g << log_b) + i;
+      ttw[w] = f;
+      ttws[w] = h_shoup(f, q);
+      ittw[w] = fi;
+      ittws[w] = h_shoup(fi, q);
+    }
+  }
+}
+
 uint64_t primitive_2n_root(uint64_t q, uint64_t n) {
   for (uint64_t x = 3;; x++) {
     uint64_t psi = h_powmod(x, (q - 1) / (2 * n), q);
@@ -301,7 +325,7 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
   std::vector<uint64_t> pw(n), ipw(n);
   // contiguous-pass twists (ntt_core.h): word w = g R2 + i of a limb gets
   // beta_g^i with beta_g = psi^(2 brv_a(g)), a = log2 of the strided radix
-  const int log_a = (ctx->log_n + 1) / 2, log_b = ctx->log_n / 2;
+  const int log_a = (ctx->log_n + 1) / 2;
   for (uint32_t m = 0; m < nm; m++) {
     const uint64_t q = ctx->mods[m];
     ModConst &c = mc[m];
@@ -326,19 +350,7 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
       itw[(size_t)m * n + k] = ipw[b];
       itws[(size_t)m * n + k] = h_shoup(ipw[b], q);
     }
-    for (uint32_t g = 0; g < (1u << log_a); g++) {
-      const uint64_t bg = 2ull * bit_reverse(g, log_a);
-      for (uint32_t i = 0; i < (1u << log_b); i++) {
-        const uint64_t e = bg * i % (2ull * n);   // psi^N = -1
-        const uint64_t f = e < n ? pw[e] : (q - pw[e - n]) % q;
-        const uint64_t fi = e < n ? ipw[e] : (q - ipw[e - n]) % q;
-        const size_t w = (size_t)m * n + ((size_t)g << log_b) + i;
-        ttw[w] = f;
-        ttws[w] = h_shoup(f, q);
-        ittw[w] = fi;
-        ittws[w] = h_shoup(fi, q);
-      }
-    }
+    twist_rows(pw, ipw, q, ctx->log_n, log_a, (size_t)m * n, ttw, ttws, ittw, ittws);
   }
 
   // ModUp tables: for each level l and digit j with limbs D = [lo, hi),
@@ -431,7 +443,62 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
     hck_context_destroy(ctx);
     return rc;
   }
+  ctx->def_twist[0] = ctx->d_ttw;
+  ctx->def_twist[1] = ctx->d_ttw_shoup;
+  ctx->def_twist[2] = ctx->d_ittw;
+  ctx->def_twist[3] = ctx->d_ittw_shoup;
   *out = ctx;
+  return HCK_OK;
+}
+
+const uint64_t *const *split_twists(const hck_context *ctx, int a) {
+  const int a0 = (ctx->log_n + 1) / 2;
+  if (a == a0) return ctx->def_twist;
+  if (a != a0 - 1 && a != a0 + 1) return nullptr;
+  const auto &t = ctx->alt_twist[a == a0 + 1];
+  return t[0] ? t : nullptr;
+}
+
+int set_ntt_split(hck_context *ctx, int a) {
+  const int a0 = (ctx->log_n + 1) / 2;
+  if (a == 0 || a == a0) {
+    ctx->ntt_a = 0;
+    return HCK_OK;
+  }
+  if (!ntt_split_available(ctx->log_n, a))
+    return set_error(HCK_EINVAL, "NTT split " + std::to_string(a) + " not available at log N " +
+                                     std::to_string(ctx->log_n));
+  if (ctx->capturing) return set_error(HCK_EINVAL, "NTT split change during graph capture");
+  auto &t = ctx->alt_twist[a == a0 + 1];
+  if (!t[0]) {
+    const uint32_t nm = ctx->L + ctx->K;
+    const size_t n = ctx->n;
+    std::vector<uint64_t> ttw(nm * n), ttws(nm * n), ittw(nm * n), ittws(nm * n), pw(n), ipw(n);
+    for (uint32_t m = 0; m < nm; m++) {
+      const uint64_t q = ctx->mods[m];
+      const uint64_t psi = primitive_2n_root(q, n), ipsi = h_invmod(psi, q);
+      pw[0] = ipw[0] = 1;
+      for (size_t i = 1; i < n; i++) {
+        pw[i] = h_mulmod(pw[i - 1], psi, q);
+        ipw[i] = h_mulmod(ipw[i - 1], ipsi, q);
+      }
+      twist_rows(pw, ipw, q, ctx->log_n, a, (size_t)m * n, ttw, ttws, ittw, ittws);
+    }
+    const std::vector<uint64_t> *src[4] = {&ttw, &ttws, &ittw, &ittws};
+    uint64_t *dev[4] = {};
+    for (int k = 0; k < 4; k++) {
+      hipError_t e = hipMalloc((void **)&dev[k], nm * n * 8);
+      if (e == hipSuccess) e = hipMemcpy(dev[k], src[k]->data(), nm * n * 8, hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        for (uint64_t *p : dev)
+          if (p) (void)hipFree(p);
+        (void)hipGetLastError();
+        return set_error(HCK_ENOMEM, "NTT split tables: allocation or upload failed");
+      }
+    }
+    for (int k = 0; k < 4; k++) t[k] = dev[k];
+  }
+  ctx->ntt_a = (uint8_t)a;
   return HCK_OK;
 }
 
@@ -474,6 +541,9 @@ void destroy_context(hck_context *ctx) {
                   (void *)ctx->d_up_conv,
                   (void *)ctx->d_down_conv, (void *)ctx->d_down_hneg})
     if (p) (void)hipFree(p);
+  for (auto &t : ctx->alt_twist)
+    for (uint64_t *p : t)
+      if (p) (void)hipFree(p);
   for (auto &t : ctx->pending) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);

@@ -91,6 +91,15 @@ struct hck_context {
   // device allocator: the caller's hook (hck_set_allocator) or, when unset,
   // stream-ordered hipMallocAsync / hipFreeAsync; live_allocs counts the
   // buffers dev_alloc handed out and dev_free has not yet returned
+  // split of the plain full NTTs (log2 of the strided radix R1; 0: the
+  // default (log N + 1) / 2), chosen by hck_autotune_ntt; alt_twist[0] and
+  // [1] are the contiguous pass's twist tables (forward, its Shoup
+  // companions, inverse, its companions) of the splits one below and one
+  // above the default, built when first chosen and kept until the context is
+  // destroyed (recorded graphs may read them)
+  uint8_t ntt_a = 0;
+  uint64_t *alt_twist[2][4] = {};
+  uint64_t *def_twist[4] = {};
   // key switches per launch sequence at each level, chosen by the autotuner
   // (hck_autotune_keyswitch) or set by the caller; 0: the built-in rule
   uint8_t ks_cap[HCK_MAX_LIMBS] = {};
@@ -290,6 +299,13 @@ int ntt_inverse_oop(hck_context *ctx, uint64_t *dst, const uint64_t *src, const 
 // in coefficient form ([0, q_level)), tmp has room for polys x level limbs.
 int rescale_fused(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint64_t *last,
                   uint64_t *tmp, uint32_t level, uint32_t polys);
+// whether the plain transforms of a ring can run on split a (the default or
+// one step either side), and the twist tables of split a (null: not built)
+bool ntt_split_available(uint32_t log_n, int a);
+const uint64_t *const *split_twists(const hck_context *ctx, int a);
+// selects the split of the plain full transforms (0: the default), building
+// its twist tables on first use
+int set_ntt_split(hck_context *ctx, int a);
 int ntt_pass(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, bool strided,
              const RowScale *scale, int period = 0);
 

@@ -179,10 +179,13 @@ int run_rescale(hck_context *ctx, uint64_t *out, const uint64_t *in, const uint6
   return HCK_OK;
 }
 
-template <int LOGN, bool STRIDED, bool INVERSE>
-void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
-                 const RowScale *sc, int period = 0) {
-  constexpr int LOGR = STRIDED ? split_a(LOGN) : split_b(LOGN);
+// One pass of the split N = 2^A x 2^(LOGN - A): the strided pass runs the
+// first A stages (R1 = 2^A points per sub-transform), the contiguous pass the
+// rest; tt/tts are the contiguous pass's twist tables for that split.
+template <int LOGN, int A, bool STRIDED, bool INVERSE>
+void launch_split(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                  const RowScale *sc, int period, const uint64_t *tt, const uint64_t *tts) {
+  constexpr int LOGR = STRIDED ? A : LOGN - A;
   constexpr int N = 1 << LOGN;
   using G = Pass<LOGR, LOGN, STRIDED>;
   static const char *names[2][2] = {{"ntt_fwd_contig", "ntt_fwd_strided"},
@@ -192,27 +195,79 @@ void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const Lim
   timing_begin(ctx, names[INVERSE][STRIDED], dim3(G::BLOCKS, map.n), 16.0 * N * map.n, mm);
   k_ntt_pass<LOGR, LOGN, STRIDED, INVERSE><<<dim3(G::BLOCKS, map.n), kNttThreads, 0, ctx->stream>>>(
       dst, src, map, ctx->d_mod, INVERSE ? ctx->d_itw : ctx->d_tw,
-      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, INVERSE ? ctx->d_ittw : ctx->d_ttw,
-      INVERSE ? ctx->d_ittw_shoup : ctx->d_ttw_shoup, sc ? *sc : dummy,
+      INVERSE ? ctx->d_itw_shoup : ctx->d_tw_shoup, tt, tts, sc ? *sc : dummy,
       sc ? (period ? period : (int)map.n) : 0);
   timing_end(ctx);
 }
 
+template <int LOGN, bool STRIDED, bool INVERSE>
+void launch_pass(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                 const RowScale *sc, int period = 0) {
+  launch_split<LOGN, split_a(LOGN), STRIDED, INVERSE>(
+      ctx, dst, src, map, sc, period, INVERSE ? ctx->d_ittw : ctx->d_ttw,
+      INVERSE ? ctx->d_ittw_shoup : ctx->d_ttw_shoup);
+}
+
+// whether the split 2^A x 2^(LOGN - A) has both passes: at least one
+// workgroup per limb, a contiguous sub-transform inside one wavefront, and
+// each pass's LDS within a workgroup's share of gfx950's 160 KiB
+template <int LOGN, int A>
+constexpr bool split_ok() {
+  if (A < 2 || LOGN - A < 2) return false;
+  using S = Pass<A, LOGN, true>;
+  using C = Pass<LOGN - A, LOGN, false>;
+  return S::BLOCKS >= 1 && C::BLOCKS >= 1 && C::T <= 64 && 64 % C::T == 0 &&
+         S::LDS_WORDS * 8 <= 80 * 1024 && C::LDS_WORDS * 8 <= 80 * 1024;
+}
+
+// full transforms on the split the context's NTT tuner chose (ctx->ntt_a;
+// the default split_a(LOGN) when 0), one step either side of the default
+template <int LOGN, int A>
+int forward_split(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map) {
+  if constexpr (split_ok<LOGN, A>()) {
+    const uint64_t *const *tt = split_twists(ctx, A);
+    if (!tt) return set_error(HCK_EINVAL, "NTT split tables not built");
+    launch_split<LOGN, A, true, false>(ctx, dst, src, map, nullptr, 0, nullptr, nullptr);
+    launch_split<LOGN, A, false, false>(ctx, dst, nullptr, map, nullptr, 0, tt[0], tt[1]);
+    HCK_HIP(ctx, hipGetLastError());
+    return HCK_OK;
+  } else {
+    return set_error(HCK_EINVAL, "NTT split not available for this ring");
+  }
+}
+
+template <int LOGN, int A>
+int inverse_split(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
+                  const RowScale *sc) {
+  if constexpr (split_ok<LOGN, A>()) {
+    const uint64_t *const *tt = split_twists(ctx, A);
+    if (!tt) return set_error(HCK_EINVAL, "NTT split tables not built");
+    launch_split<LOGN, A, false, true>(ctx, dst, src, map, nullptr, 0, tt[2], tt[3]);
+    launch_split<LOGN, A, true, true>(ctx, dst, nullptr, map, sc, 0, nullptr, nullptr);
+    HCK_HIP(ctx, hipGetLastError());
+    return HCK_OK;
+  } else {
+    return set_error(HCK_EINVAL, "NTT split not available for this ring");
+  }
+}
+
 template <int LOGN>
 int run_forward(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map) {
-  launch_pass<LOGN, true, false>(ctx, dst, src, map, nullptr);
-  launch_pass<LOGN, false, false>(ctx, dst, nullptr, map, nullptr);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
+  constexpr int A = split_a(LOGN);
+  const int a = ctx->ntt_a ? ctx->ntt_a : A;
+  if (a == A - 1) return forward_split<LOGN, A - 1>(ctx, dst, src, map);
+  if (a == A + 1) return forward_split<LOGN, A + 1>(ctx, dst, src, map);
+  return forward_split<LOGN, A>(ctx, dst, src, map);
 }
 
 template <int LOGN>
 int run_inverse(hck_context *ctx, uint64_t *dst, const uint64_t *src, const LimbMap &map,
                 const RowScale *sc) {
-  launch_pass<LOGN, false, true>(ctx, dst, src, map, nullptr);
-  launch_pass<LOGN, true, true>(ctx, dst, nullptr, map, sc);
-  HCK_HIP(ctx, hipGetLastError());
-  return HCK_OK;
+  constexpr int A = split_a(LOGN);
+  const int a = ctx->ntt_a ? ctx->ntt_a : A;
+  if (a == A - 1) return inverse_split<LOGN, A - 1>(ctx, dst, src, map, sc);
+  if (a == A + 1) return inverse_split<LOGN, A + 1>(ctx, dst, src, map, sc);
+  return inverse_split<LOGN, A>(ctx, dst, src, map, sc);
 }
 
 template <int LOGN>
@@ -227,6 +282,25 @@ int run_one(hck_context *ctx, uint64_t *buf, const LimbMap &map, bool inverse, b
 }
 
 }  // namespace
+
+bool ntt_split_available(uint32_t log_n, int a) {
+  switch (log_n) {
+#define HCK_SPLITS(L)                                                                   \
+  case L:                                                                                \
+    return (a == split_a(L) - 1 && split_ok<L, split_a(L) - 1>()) || a == split_a(L) || \
+           (a == split_a(L) + 1 && split_ok<L, split_a(L) + 1>());
+    HCK_SPLITS(11)
+    HCK_SPLITS(12)
+    HCK_SPLITS(13)
+    HCK_SPLITS(14)
+    HCK_SPLITS(15)
+    HCK_SPLITS(16)
+    HCK_SPLITS(17)
+#undef HCK_SPLITS
+    default:
+      return false;
+  }
+}
 
 int ntt_forward(hck_context *ctx, uint64_t *buf, const LimbMap &map) {
   return ntt_forward_oop(ctx, buf, nullptr, map);

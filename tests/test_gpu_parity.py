@@ -671,3 +671,41 @@ def test_autotune_dnum():
     bad = dict(cands[1], q=list(reversed(cands[1]["q"])))
     with pytest.raises(H.HckError):
         H.autotune_dnum([cands[0], bad], level=11)
+
+
+@pytest.mark.parametrize("name", ["tiny", "mix15", "vital"])
+def test_ntt_splits_match_oracle(name):
+    """The full transforms on every split the NTT tuner can choose (the
+    default 2^ceil(log N / 2) x 2^floor(log N / 2) and one step either side):
+    imports (forward NTT), exports (inverse NTT), products and encryption
+    bit-exact against the oracle; the tuner keeps one of the candidates."""
+    p = pair(name)
+    o = p.o
+    a0 = (p.prm["log_n"] + 1) // 2
+    tried = []
+    try:
+        for a in (a0 - 1, a0 + 1, a0):
+            try:
+                p.ctx.set_ntt_split(a)
+            except H.HckError:
+                continue
+            tried.append(a)
+            assert p.ctx.ntt_split() == a
+            level = o.L - 1
+            ct, ct_o = p.rand_ct(level, 130 + a)
+            assert np.array_equal(p.export(ct), ct_o.polys), a
+            ptres = S.uniform_residues(o.qmods(level), o.n, 140 + a)[0]
+            pt = p.ctx.plaintext_import(ptres, level, 3.0)
+            got = p.export(p.ctx.mul_plain(ct, pt))
+            assert np.array_equal(got, o.mul_plain(ct_o, O.Plaintext(ptres, level, 3.0)).polys), a
+            enc = p.export(p.ctx.encrypt_sk(p.sk, pt, 12))
+            assert np.array_equal(enc, o.encrypt_sk(p.s_o, O.Plaintext(ptres, level, 3.0),
+                                                    12).polys), a
+        assert len(tried) == 3
+        tuned = p.ctx.autotune_ntt(rows=32)
+        assert set(tuned["splits"]) == set(tried) and min(tuned["splits"].values()) > 0
+        assert p.ctx.ntt_split() == tuned["chosen"] in tried
+        with pytest.raises(H.HckError):
+            p.ctx.set_ntt_split(a0 + 2)
+    finally:
+        p.ctx.set_ntt_split(0)
