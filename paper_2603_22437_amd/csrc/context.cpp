@@ -337,6 +337,7 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
     c.ninv_shoup = h_shoup(c.ninv, q);
     c.r2 = h_mulmod(c.r64, c.r64, q);
     c.one_shoup = h_shoup(1, q);
+    c.nq = 0 - q;
     const uint64_t psi = primitive_2n_root(q, n), ipsi = h_invmod(psi, q);
     pw[0] = ipw[0] = 1;
     for (uint32_t i = 1; i < n; i++) {

@@ -29,6 +29,7 @@ struct ModConst {
   uint64_t ninv_shoup;
   uint64_t r2;          // 2^128 mod q (Montgomery fix-up of a plain product)
   uint64_t one_shoup;   // floor(2^64 / q): Shoup companion of 1 (reduction of any word)
+  uint64_t nq;          // 2^64 - q
 };
 
 // Which rows of a [row][N] buffer a launch processes (blockIdx.y indexes the

@@ -75,6 +75,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
   const int li = blockIdx.z;  // limb i (modulus i)
   const uint32_t b = blockIdx.y;
   const uint64_t q = mc[li].q;
+  const Qn qm = qn(mc[li]);
   const size_t roff = (size_t)li * G::N;
   const uint64_t *d = kb.d[b];
   const uint32_t galois = kb.galois[b];
@@ -95,8 +96,8 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_intt_gather(
   for (int i = 0; i < P; i++)
     x[i] = d[roff + galois_src((uint32_t)G::gaddr(g, G::ipoint(r, i)), galois, LOGN)];
   G::to_blocked(lds, x, c, r);
-  G::inverse(lds, x, c, r, g, itw + roff, itws + roff, q);
-  G::twist(x, g, r, itt + roff, itts + roff, q);
+  G::inverse(lds, x, c, r, g, itw + roff, itws + roff, qm);
+  G::twist(x, g, r, itt + roff, itts + roff, qm);
 #pragma unroll
   for (int i = 0; i < P; i++) y[roff + G::gaddr(g, G::ipoint(r, i))] = x[i];
 }
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     const uint64_t *const cvs[1] = {cv};
     const ModConst ms[1] = {m};
     bconv_points<G, 1>(x, src, cvs, kg.nm, na, g, r, ms);
-    G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
     for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
@@ -177,12 +178,12 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     const uint64_t *const cvs[2] = {cv, cv2};
     const ModConst ms[2] = {m, m2};
     bconv_points<G, 2>(x, src, cvs, kg.nm, na, g, r, ms);
-    G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
     for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
     if (!two) return;
-    G::forward(lds, x[1], c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, m2.q);
+    G::forward(lds, x[1], c, r, g, tw + (size_t)mi2 * G::N, tws + (size_t)mi2 * G::N, qn(m2));
     uint64_t *out2 = ws + (size_t)rows.row2[k] * G::N;
 #pragma unroll
     for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = x[1][v];
@@ -228,10 +229,10 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
       const uint64_t *e = slot + ((size_t)kg.off_ext + j * kg.ne + t) * G::N;
 #pragma unroll
       for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
-      G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, m.q);
-      G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, m.q);
+      G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, qn(m));
+      G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
 #pragma unroll
-      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], m.q);
+      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], qn(m));
       G::to_interleaved(lds, x, c, r);
     }
     const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * G::N;
@@ -248,11 +249,11 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
     // blocks are at hand
     const size_t toff = (size_t)mi * G::N;
     G::to_blocked(lds, a0, c, r);
-    G::inverse(lds, a0, c, r, g, itw + toff, itws + toff, m.q);
-    G::twist(a0, g, r, itt + toff, itts + toff, m.q);
+    G::inverse(lds, a0, c, r, g, itw + toff, itws + toff, qn(m));
+    G::twist(a0, g, r, itt + toff, itts + toff, qn(m));
     G::to_blocked(lds, a1, c, r);
-    G::inverse(lds, a1, c, r, g, itw + toff, itws + toff, m.q);
-    G::twist(a1, g, r, itt + toff, itts + toff, m.q);
+    G::inverse(lds, a1, c, r, g, itw + toff, itws + toff, qn(m));
+    G::twist(a1, g, r, itt + toff, itts + toff, qn(m));
   }
   uint64_t *o0 = slot + ((size_t)kg.off_acc + t) * G::N;
   uint64_t *o1 = slot + ((size_t)kg.off_acc + kg.ne + t) * G::N;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
     bconv_points<G, 1>(x, src, cvs, kg.nm, kg.K, g, r, ms);
 #pragma unroll
     for (int i = 0; i < P; i++) x[0][i] = add_mod(x[0][i], h, m.q);
-    G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, qn(m));
     uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
 #pragma unroll
     for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
@@ -309,12 +310,12 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
       x[0][i] = add_mod(x[0][i], h, m.q);
       x[1][i] = add_mod(x[1][i], h2, m2.q);
     }
-    G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, m.q);
+    G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, qn(m));
     uint64_t *out = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
 #pragma unroll
     for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[0][v];
     if (!two) return;
-    G::forward(lds, x[1], c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, m2.q);
+    G::forward(lds, x[1], c, r, g, tw + (size_t)li2 * G::N, tws + (size_t)li2 * G::N, qn(m2));
     uint64_t *out2 = slot + ((size_t)kg.off_conv + p * kg.L + li2) * G::N;
 #pragma unroll
     for (int v = 0; v < P; v++) out2[G::gaddr(g, G::bpoint(r, v))] = x[1][v];
@@ -334,16 +335,17 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_contig_tail(
   const uint32_t b = blockIdx.y;
   const uint64_t *slot = ws + (size_t)b * kg.slot_rows * G::N;
   const uint64_t q = mc[li].q;
+  const Qn qm = qn(mc[li]);
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   const uint64_t *cin = slot + ((size_t)kg.off_conv + p * kg.L + li) * G::N;
   uint64_t x[P];
 #pragma unroll
   for (int i = 0; i < P; i++) x[i] = cin[G::gaddr(g, G::ipoint(r, i))];
-  G::twist(x, g, r, tt + (size_t)li * G::N, tts + (size_t)li * G::N, q);
-  G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, q);
+  G::twist(x, g, r, tt + (size_t)li * G::N, tts + (size_t)li * G::N, qm);
+  G::forward(lds, x, c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, qm);
 #pragma unroll
-  for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
+  for (int v = 0; v < P; v++) x[v] = reduce4(x[v], qm);
   G::to_interleaved(lds, x, c, r);
   const uint64_t *u = slot + ((size_t)kg.off_acc + p * kg.ne + li) * G::N;
   const uint64_t *add = p == 0 ? kb.add0[b] : kb.add1[b];

@@ -63,6 +63,26 @@ __host__ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, 
   return mul_lo(a, w) - mul_lo(mul_hi(a, wp), q);
 }
 
+// A modulus with its negation nq = 2^64 - q.  nq comes from memory, so the
+// compiler cannot see that it is -q and keeps "+ k nq" a multiply-add
+// (v_mad_u64_u32 takes the addend) and "+ nq" one 64-bit add, where "- k q"
+// would be a subtract-with-borrow pair that waits on its carry.
+struct Qn {
+  uint64_t q, nq;
+};
+
+// a w mod q in [0, 2q), the same word as shoup_lazy: a w + qh (2^64 - q)
+// = a w - qh q mod 2^64.
+__host__ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t a, uint64_t w, uint64_t wp,
+                                                        Qn m) {
+  return mul_lo(a, w) + mul_lo(mul_hi(a, wp), m.nq);
+}
+
+// x - b if x >= b, else x (nb = 2^64 - b).
+__host__ __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t b, uint64_t nb) {
+  return x + (x >= b ? nb : 0);
+}
+
 __host__ __device__ __forceinline__ uint64_t reduce2(uint64_t a, uint64_t q) {
   return a >= q ? a - q : a;
 }

@@ -26,6 +26,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
   __shared__ uint64_t lds[G::LDS_WORDS];
   const int mi = map.mod[blockIdx.y];
   const uint64_t q = mc[mi].q;
+  const Qn qm = qn(mc[mi]);
   const size_t roff = (size_t)map.row[blockIdx.y] * G::N;
   uint64_t *out = dst + roff;
   const uint64_t *in = (src ? src : dst) + roff;
@@ -37,14 +38,14 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
   if (!INVERSE) {
 #pragma unroll
     for (int i = 0; i < P; i++) x[i] = in[G::gaddr(g, G::ipoint(r, i))];
-    if constexpr (!STRIDED) G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, q);
-    G::forward(lds, x, c, r, g, w, wp, q);
+    if constexpr (!STRIDED) G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, qm);
+    G::forward(lds, x, c, r, g, w, wp, qm);
     if (STRIDED) {
 #pragma unroll
       for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
     } else {
 #pragma unroll
-      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
+      for (int v = 0; v < P; v++) x[v] = reduce4(x[v], qm);
       G::to_interleaved(lds, x, c, r);
 #pragma unroll
       for (int i = 0; i < P; i++) out[G::gaddr(g, G::ipoint(r, i))] = x[i];
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
       for (int i = 0; i < P; i++) x[i] = in[G::gaddr(g, G::ipoint(r, i))];
       G::to_blocked(lds, x, c, r);
     }
-    G::inverse(lds, x, c, r, g, w, wp, q);
+    G::inverse(lds, x, c, r, g, w, wp, qm);
     if constexpr (STRIDED) {
       uint64_t sw, swp, sa;
       if (scale_period) {
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_pass(uint64_t *__restrict__
       for (int i = 0; i < P; i++)
         out[G::gaddr(g, G::ipoint(r, i))] = add_mod(shoup(x[i], sw, swp, q), sa, q);
     } else {
-      G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, q);
+      G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, qm);
 #pragma unroll
       for (int i = 0; i < P; i++) out[G::gaddr(g, G::ipoint(r, i))] = x[i];
     }
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(kNttThreads) void k_rescale_strided(
     const uint64_t t = shoup(v, 1, m.one_shoup, m.q);
     x[k] = v > half ? sub_mod(t, ql_i, m.q) : t;
   }
-  G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, m.q);
+  G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, qn(m));
   uint64_t *out = tmp + ((size_t)z * level + i) * G::N;
 #pragma unroll
   for (int v = 0; v < P; v++) out[G::gaddr(g, G::bpoint(r, v))] = x[v];
@@ -128,16 +129,17 @@ __global__ __launch_bounds__(kNttThreads) void k_rescale_contig_tail(
   __shared__ uint64_t lds[G::LDS_WORDS];
   const uint32_t i = blockIdx.y, z = blockIdx.z;
   const uint64_t q = mc[i].q;
+  const Qn qm = qn(mc[i]);
   const int c = G::sub(threadIdx.x), r = G::lane(threadIdx.x);
   const int g = blockIdx.x * G::TR + c;
   const uint64_t *tin = tmp + ((size_t)z * level + i) * G::N;
   uint64_t x[P];
 #pragma unroll
   for (int k = 0; k < P; k++) x[k] = tin[G::gaddr(g, G::ipoint(r, k))];
-  G::twist(x, g, r, tt + (size_t)i * G::N, tts + (size_t)i * G::N, q);
-  G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, q);
+  G::twist(x, g, r, tt + (size_t)i * G::N, tts + (size_t)i * G::N, qm);
+  G::forward(lds, x, c, r, g, tw + (size_t)i * G::N, tws + (size_t)i * G::N, qm);
 #pragma unroll
-  for (int v = 0; v < P; v++) x[v] = reduce4(x[v], q);
+  for (int v = 0; v < P; v++) x[v] = reduce4(x[v], qm);
   G::to_interleaved(lds, x, c, r);
   const size_t off = (size_t)z * ps + (size_t)i * G::N;
   const uint64_t w = inv.w[i], wp = inv.wp[i];

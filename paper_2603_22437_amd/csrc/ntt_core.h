@@ -45,21 +45,22 @@ namespace hck {
 
 constexpr int kNttThreads = 256;
 
+__device__ __forceinline__ Qn qn(const ModConst &m) { return Qn{m.q, m.nq}; }
+
 __device__ __forceinline__ void ct_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp,
-                                        uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  uint64_t a = x >= q2 ? x - q2 : x;       // [0, 2q)
-  uint64_t t = shoup_lazy(y, w, wp, q);    // [0, 2q)
+                                        Qn m) {
+  const uint64_t q2 = 2 * m.q;
+  uint64_t a = csub(x, q2, 2 * m.nq);      // [0, 2q)
+  uint64_t t = shoup_lazy(y, w, wp, m);    // [0, 2q)
   x = a + t;                               // [0, 4q)
   y = a - t + q2;                          // (0, 4q)
 }
 
 __device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, uint64_t wp,
-                                        uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  uint64_t s = x + y;
-  s = s >= q2 ? s - q2 : s;                // [0, 2q)
-  y = shoup_lazy(x - y + q2, w, wp, q);    // [0, 2q)
+                                        Qn m) {
+  const uint64_t q2 = 2 * m.q;
+  const uint64_t s = csub(x + y, q2, 2 * m.nq);  // [0, 2q)
+  y = shoup_lazy(x - y + q2, w, wp, m);          // [0, 2q)
   x = s;
 }
 
@@ -106,7 +107,7 @@ struct Pass {
   // or inverse-twist table, indexed like the data), for any x_i < 2^64;
   // results in [0, 2q)
   __device__ static void twist(uint64_t (&x)[P], int g, int r, const uint64_t *t,
-                               const uint64_t *ts, uint64_t q) {
+                               const uint64_t *ts, Qn q) {
     static_assert(!STRIDED, "twists belong to the contiguous pass");
 #pragma unroll
     for (int i = 0; i < P; i++) {
@@ -150,7 +151,7 @@ struct Pass {
 
   // forward stages: interleaved in, blocked out
   __device__ static void forward(uint64_t *lds, uint64_t (&x)[P], int c, int r, int g,
-                                 const uint64_t *w, const uint64_t *wp, uint64_t q) {
+                                 const uint64_t *w, const uint64_t *wp, Qn q) {
 #pragma unroll
     for (int s = 0; s < LOGP; s++) {
       const int h = P >> (s + 1);
@@ -176,7 +177,7 @@ struct Pass {
 
   // inverse stages: blocked in, interleaved out
   __device__ static void inverse(uint64_t *lds, uint64_t (&x)[P], int c, int r, int g,
-                                 const uint64_t *w, const uint64_t *wp, uint64_t q) {
+                                 const uint64_t *w, const uint64_t *wp, Qn q) {
 #pragma unroll
     for (int s = LOGR - 1; s >= LOGP; s--) {
       const int t = R >> (s + 1);
@@ -202,10 +203,8 @@ struct Pass {
 };
 
 // [0, 4q) -> [0, q)
-__device__ __forceinline__ uint64_t reduce4(uint64_t v, uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  v = v >= q2 ? v - q2 : v;
-  return v >= q ? v - q : v;
+__device__ __forceinline__ uint64_t reduce4(uint64_t v, Qn m) {
+  return csub(csub(v, 2 * m.q, 2 * m.nq), m.q, m.nq);
 }
 
 // Slot of the input that lands in slot j under X -> X^g (bit-reversed
