@@ -64,9 +64,10 @@ __device__ __forceinline__ void gs_bfly(uint64_t &x, uint64_t &y, uint64_t w, ui
   x = s;
 }
 
-// Geometry of one pass: R-point sub-transforms of an N-point limb.
+// Geometry of one pass: R-point sub-transforms of an N-point limb, two
+// layouts (interleaved, blocked) of P = 2^ceil(log2(R)/2) points a thread.
 template <int LOGR, int LOGN, bool STRIDED>
-struct Pass {
+struct Pass2 {
   static constexpr int R = 1 << LOGR;
   static constexpr int LOGP = (LOGR + 1) / 2;
   static constexpr int P = 1 << LOGP;
@@ -201,6 +202,172 @@ struct Pass {
     }
   }
 };
+
+// Contiguous pass of R = 2^LOGR points, LOGR = 7..9, with P = 8 points a
+// thread (T = R / 8 threads a sub-transform, inside one wavefront) in three
+// layouts of the point index p (bits LOGR-1 .. 0), LM = LOGR - 6:
+//   I (interleaved): thread r holds p = r + T k, so register k is the top 3
+//     bits; stages 0..2 pair registers k, k + 4 / 2 / 1 with twiddles that
+//     depend on k only (uniform across the wavefront);
+//   M (middle): register k is bits LOGR-4 .. LOGR-6 and the thread the rest,
+//     p = (r >> LM) R/8 + k 2^LM + (r mod 2^LM); stages 3 .. LOGR-4;
+//   B (blocked): thread r holds p = 8 r + k, register k the low 3 bits;
+//     stages LOGR-3 .. LOGR-1.
+// The butterflies, their twiddles and their order per point are those of
+// the two-layout pass, so the results are the same words; the pass takes two
+// LDS exchanges each way instead of one, and in return a thread holds half
+// the points (the fused key-switching passes keep three such arrays live)
+// and a workgroup half the LDS.
+template <int LOGR, int LOGN>
+struct Pass3 {
+  static_assert(LOGR >= 7 && LOGR <= 9, "three-layout pass covers 128..512 points");
+  static constexpr int R = 1 << LOGR;
+  static constexpr int P = 8;
+  static constexpr int T = R / P;                 // threads per sub-transform
+  static constexpr int TR = kNttThreads / T;      // sub-transforms per workgroup
+  static constexpr int N = 1 << LOGN;
+  static constexpr int OTHER = N / R;             // sub-transforms per limb
+  static constexpr int LM = LOGR - 6;
+  static constexpr int S = R + R / 8 + 1;         // LDS words per sub-transform
+  static constexpr int LDS_WORDS = TR * S;
+  static constexpr int BLOCKS = OTHER / TR;       // workgroups per limb
+  static_assert(T <= 64 && 64 % T == 0, "sub-transform must fit one wavefront");
+
+  __device__ static int lidx(int c, int p) { return c * S + p + (p >> 3); }
+  __device__ static size_t gaddr(int g, int p) { return (size_t)g * R + p; }
+  __device__ static int sub(int tid) { return tid / T; }
+  __device__ static int lane(int tid) { return tid % T; }
+  __device__ static int ipoint(int r, int k) { return r + T * k; }
+  __device__ static int mpoint(int r, int k) {
+    return (r >> LM) * (R / 8) + (k << LM) + (r & ((1 << LM) - 1));
+  }
+  __device__ static int bpoint(int r, int k) { return r * P + k; }
+  template <int LAYOUT>
+  __device__ static int point(int r, int k) {
+    return LAYOUT == 0 ? ipoint(r, k) : LAYOUT == 1 ? mpoint(r, k) : bpoint(r, k);
+  }
+  // twiddle of stage s for the butterfly with top point p (sub-transform
+  // 0's network, which every sub-transform runs on twisted inputs)
+  __device__ static int tw(int s, int p) { return (1 << s) * OTHER + (p >> (LOGR - s)); }
+
+  __device__ static void twist(uint64_t (&x)[P], int g, int r, const uint64_t *t,
+                               const uint64_t *ts, Qn q) {
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+      const size_t a = gaddr(g, ipoint(r, k));
+      x[k] = shoup_lazy(x[k], t[a], ts[a], q);
+    }
+  }
+
+  // a wavefront's LDS operations complete in issue order; the fence keeps
+  // the compiler from moving them across each other
+  __device__ static void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  template <int FROM, int TO>
+  __device__ static void exchange(uint64_t *lds, uint64_t (&x)[P], int c, int r) {
+#pragma unroll
+    for (int k = 0; k < P; k++) lds[lidx(c, point<FROM>(r, k))] = x[k];
+    sync();
+#pragma unroll
+    for (int k = 0; k < P; k++) x[k] = lds[lidx(c, point<TO>(r, k))];
+    sync();
+  }
+  __device__ static void to_blocked(uint64_t *lds, uint64_t (&x)[P], int c, int r) {
+    exchange<0, 2>(lds, x, c, r);
+  }
+  __device__ static void to_interleaved(uint64_t *lds, uint64_t (&x)[P], int c, int r) {
+    exchange<2, 0>(lds, x, c, r);
+  }
+
+  // forward stages: interleaved in, blocked out
+  __device__ static void forward(uint64_t *lds, uint64_t (&x)[P], int c, int r, int g,
+                                 const uint64_t *w, const uint64_t *wp, Qn q) {
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+      const int h = 4 >> s;
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k & h) continue;
+        const int t = (1 << s) * OTHER + (k >> (3 - s));
+        ct_bfly(x[k], x[k + h], w[t], wp[t], q);
+      }
+    }
+    exchange<0, 1>(lds, x, c, r);
+#pragma unroll
+    for (int s = 3; s <= LOGR - 4; s++) {
+      const int h = 1 << (LOGR - 1 - s - LM);
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k & h) continue;
+        const int t = tw(s, mpoint(r, k));
+        ct_bfly(x[k], x[k + h], w[t], wp[t], q);
+      }
+    }
+    exchange<1, 2>(lds, x, c, r);
+#pragma unroll
+    for (int s = LOGR - 3; s < LOGR; s++) {
+      const int h = 1 << (LOGR - 1 - s);
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k & h) continue;
+        const int t = tw(s, bpoint(r, k));
+        ct_bfly(x[k], x[k + h], w[t], wp[t], q);
+      }
+    }
+  }
+
+  // inverse stages: blocked in, interleaved out
+  __device__ static void inverse(uint64_t *lds, uint64_t (&x)[P], int c, int r, int g,
+                                 const uint64_t *w, const uint64_t *wp, Qn q) {
+#pragma unroll
+    for (int s = LOGR - 1; s >= LOGR - 3; s--) {
+      const int h = 1 << (LOGR - 1 - s);
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k & h) continue;
+        const int t = tw(s, bpoint(r, k));
+        gs_bfly(x[k], x[k + h], w[t], wp[t], q);
+      }
+    }
+    exchange<2, 1>(lds, x, c, r);
+#pragma unroll
+    for (int s = LOGR - 4; s >= 3; s--) {
+      const int h = 1 << (LOGR - 1 - s - LM);
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k & h) continue;
+        const int t = tw(s, mpoint(r, k));
+        gs_bfly(x[k], x[k + h], w[t], wp[t], q);
+      }
+    }
+    exchange<1, 0>(lds, x, c, r);
+#pragma unroll
+    for (int s = 2; s >= 0; s--) {
+      const int h = 4 >> s;
+#pragma unroll
+      for (int k = 0; k < P; k++) {
+        if (k & h) continue;
+        const int t = (1 << s) * OTHER + (k >> (3 - s));
+        gs_bfly(x[k], x[k + h], w[t], wp[t], q);
+      }
+    }
+  }
+};
+
+// The pass geometry of a split: three layouts for contiguous passes of 128
+// points or more, two otherwise.
+template <bool THREE, int LOGR, int LOGN, bool STRIDED>
+struct PassPick {
+  using type = Pass2<LOGR, LOGN, STRIDED>;
+};
+template <int LOGR, int LOGN>
+struct PassPick<true, LOGR, LOGN, false> {
+  using type = Pass3<LOGR, LOGN>;
+};
+template <int LOGR, int LOGN, bool STRIDED>
+using Pass = typename PassPick<!STRIDED && LOGR >= 7, LOGR, LOGN, STRIDED>::type;
 
 // [0, 4q) -> [0, q)
 __device__ __forceinline__ uint64_t reduce4(uint64_t v, Qn m) {
