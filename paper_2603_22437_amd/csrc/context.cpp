@@ -314,6 +314,8 @@ int build_context(const hck_params *prm, int device, void *stream, hck_context *
   ctx->alpha = (ctx->L + ctx->dnum - 1) / ctx->dnum;
   ctx->mods.assign(prm->q, prm->q + prm->num_q);
   ctx->mods.insert(ctx->mods.end(), prm->p, prm->p + prm->num_p);
+  ctx->bconv30 = std::all_of(ctx->mods.begin(), ctx->mods.end(),
+                             [](uint64_t m) { return m < (1ull << 60); });
   const uint32_t nm = ctx->L + ctx->K, n = ctx->n, L = ctx->L, K = ctx->K;
 
   // per-modulus constants and twiddles

@@ -99,6 +99,9 @@ struct hck_context {
   // above the default, built when first chosen and kept until the context is
   // destroyed (recorded graphs may read them)
   uint8_t ntt_a = 0;
+  // every modulus below 2^60: the basis conversions sum products of 30-bit
+  // halves in carry-free 64-bit columns
+  bool bconv30 = false;
   uint64_t *alt_twist[2][4] = {};
   uint64_t *def_twist[4] = {};
   // key switches per launch sequence at each level, chosen by the autotuner

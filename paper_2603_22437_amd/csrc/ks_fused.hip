@@ -143,7 +143,85 @@ __device__ __forceinline__ void bconv_points(uint64_t (&x)[NT][G::P],
   }
 }
 
-template <int LOGN, bool PAIR>
+// The same sums for moduli below 2^60 (sources v and constants c below
+// 2^60), with both factors split into 30-bit halves, v = v1 2^30 + v0 and
+// c = c1 2^30 + c0:
+//   sum_a v c = L + 2^30 (M1 + M2) + 2^60 H,
+//   L = sum v0 c0, M1 = sum v0 c1, M2 = sum v1 c0, H = sum v1 c1.
+// Each column is below na (2^30 - 1)^2 < 2^64 for na <= 16 sources (a
+// digit or the special basis holds at most 16 primes), so every partial
+// product is one 32 x 32 + 64-bit multiply-add into its column, with no
+// carries between columns; the columns are combined into the 128-bit sum
+// (the same integer as above, so the same REDC result) once per point.
+// Four 64-bit columns take twice the registers of one 128-bit sum, so the
+// points are taken in chunks of half the size.
+template <class G, int NT>
+__device__ __forceinline__ void bconv_points30(uint64_t (&x)[NT][G::P],
+                                               const uint64_t *__restrict__ src,
+                                               const uint64_t *const (&cv)[NT], uint32_t cstride,
+                                               uint32_t na, int g, int r,
+                                               const ModConst (&m)[NT]) {
+  constexpr int P = G::P;
+  constexpr int CH = NT == 1 ? P / 2 : P / 4;
+  constexpr uint32_t kLow30 = (1u << 30) - 1;
+#pragma unroll
+  for (int c0 = 0; c0 < P; c0 += CH) {
+    uint64_t lo[NT][CH], m1[NT][CH], m2[NT][CH], hi[NT][CH];
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+      for (int k = 0; k < CH; k++) lo[t][k] = m1[t][k] = m2[t][k] = hi[t][k] = 0;
+#pragma unroll 2
+    for (uint32_t a = 0; a < na; a++) {
+      uint32_t v0[CH], v1[CH];
+#pragma unroll
+      for (int k = 0; k < CH; k++) {
+        const uint64_t v = src[(size_t)a * G::N + G::gaddr(g, G::ipoint(r, c0 + k))];
+        v0[k] = (uint32_t)v & kLow30;
+        v1[k] = (uint32_t)(v >> 30);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; t++) {
+        const uint64_t c = cv[t][(size_t)a * cstride];
+        const uint32_t cl = (uint32_t)c & kLow30, ch = (uint32_t)(c >> 30);
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+          lo[t][k] += (uint64_t)v0[k] * cl;
+          m1[t][k] += (uint64_t)v0[k] * ch;
+          m2[t][k] += (uint64_t)v1[k] * cl;
+          hi[t][k] += (uint64_t)v1[k] * ch;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+      for (int k = 0; k < CH; k++) {
+        const wide_t mid = (wide_t)m1[t][k] + m2[t][k];
+        const wide_t y = (wide_t)lo[t][k] + (mid << 30) + ((wide_t)hi[t][k] << 60);
+        u128 s;
+        s.lo = (uint64_t)y;
+        s.hi = (uint64_t)(y >> 64);
+        x[t][c0 + k] = redc(s, m[t].q, m[t].qinv);
+        // reduce this chunk before the next chunk's loads (the empty asm
+        // takes the result and orders memory accesses, and emits nothing), so
+        // that one chunk's columns are live at a time, not every chunk's
+        asm volatile("" ::"v"(x[t][c0 + k]) : "memory");
+      }
+  }
+}
+
+template <class G, int NT, bool S30>
+__device__ __forceinline__ void bconv(uint64_t (&x)[NT][G::P], const uint64_t *__restrict__ src,
+                                      const uint64_t *const (&cv)[NT], uint32_t cstride,
+                                      uint32_t na, int g, int r, const ModConst (&m)[NT]) {
+  if constexpr (S30)
+    bconv_points30<G, NT>(x, src, cv, cstride, na, g, r, m);
+  else
+    bconv_points<G, NT>(x, src, cv, cstride, na, g, r, m);
+}
+
+template <int LOGN, bool PAIR, bool S30>
 __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     uint64_t *__restrict__ ws, ModUpRows rows, const uint64_t *__restrict__ conv, KsGeom kg,
     const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
@@ -164,7 +242,7 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     uint64_t x[1][P];
     const uint64_t *const cvs[1] = {cv};
     const ModConst ms[1] = {m};
-    bconv_points<G, 1>(x, src, cvs, kg.nm, na, g, r, ms);
+    bconv<G, 1, S30>(x, src, cvs, kg.nm, na, g, r, ms);
     G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
@@ -177,7 +255,7 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     uint64_t x[2][P];
     const uint64_t *const cvs[2] = {cv, cv2};
     const ModConst ms[2] = {m, m2};
-    bconv_points<G, 2>(x, src, cvs, kg.nm, na, g, r, ms);
+    bconv<G, 2, S30>(x, src, cvs, kg.nm, na, g, r, ms);
     G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
@@ -265,7 +343,7 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
   }
 }
 
-template <int LOGN, bool PAIR>
+template <int LOGN, bool PAIR, bool S30>
 __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
     uint64_t *__restrict__ ws, const uint64_t *__restrict__ down_conv,
     const uint64_t *__restrict__ hneg, KsGeom kg, const ModConst *__restrict__ mc,
@@ -288,7 +366,7 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
     uint64_t x[1][P];
     const uint64_t *const cvs[1] = {cv};
     const ModConst ms[1] = {m};
-    bconv_points<G, 1>(x, src, cvs, kg.nm, kg.K, g, r, ms);
+    bconv<G, 1, S30>(x, src, cvs, kg.nm, kg.K, g, r, ms);
 #pragma unroll
     for (int i = 0; i < P; i++) x[0][i] = add_mod(x[0][i], h, m.q);
     G::forward(lds, x[0], c, r, g, tw + (size_t)li * G::N, tws + (size_t)li * G::N, qn(m));
@@ -304,7 +382,7 @@ __global__ __launch_bounds__(kNttThreads) void k_moddown_strided(
     uint64_t x[2][P];
     const uint64_t *const cvs[2] = {cv, cv2};
     const ModConst ms[2] = {m, m2};
-    bconv_points<G, 2>(x, src, cvs, kg.nm, kg.K, g, r, ms);
+    bconv<G, 2, S30>(x, src, cvs, kg.nm, kg.K, g, r, ms);
 #pragma unroll
     for (int i = 0; i < P; i++) {
       x[0][i] = add_mod(x[0][i], h, m.q);
@@ -510,16 +588,38 @@ int ks_modup(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *ws
     }
     timing_begin(ctx, "ks_modup_strided", dim3(GA::BLOCKS, mr.n), 8.0 * N * (srcs + outs),
                  N * (macs + 0.5 * A * outs));
-    if (paired)
-      k_modup_strided<LOGN, true><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
+    const dim3 grid(GA::BLOCKS, mr.n);
+    if (paired && ctx->bconv30)
+      k_modup_strided<LOGN, true, true><<<grid, kNttThreads, 0, ctx->stream>>>(
+          ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+    else if (paired)
+      k_modup_strided<LOGN, true, false><<<grid, kNttThreads, 0, ctx->stream>>>(
+          ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+    else if (ctx->bconv30)
+      k_modup_strided<LOGN, false, true><<<grid, kNttThreads, 0, ctx->stream>>>(
           ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
     else
-      k_modup_strided<LOGN, false><<<dim3(GA::BLOCKS, mr.n), kNttThreads, 0, ctx->stream>>>(
+      k_modup_strided<LOGN, false, false><<<grid, kNttThreads, 0, ctx->stream>>>(
           ws, mr, up_conv, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
     timing_end(ctx);
   }
   HCK_HIP(ctx, hipGetLastError());
   return HCK_OK;
+}
+
+// K6 launch: the basis conversion on 30-bit halves where every modulus is
+// below 2^60, on whole words otherwise
+template <int LOGN, bool PAIR>
+void launch_moddown_strided(hck_context *ctx, uint64_t *ws, const KsGeom &kg, uint32_t per,
+                            uint32_t nb) {
+  using GA = Pass<split_a(LOGN), LOGN, true>;
+  const dim3 grid(GA::BLOCKS, 2 * per, nb);
+  if (ctx->bconv30)
+    k_moddown_strided<LOGN, PAIR, true><<<grid, kNttThreads, 0, ctx->stream>>>(
+        ws, ctx->d_down_conv, ctx->d_down_hneg, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+  else
+    k_moddown_strided<LOGN, PAIR, false><<<grid, kNttThreads, 0, ctx->stream>>>(
+        ws, ctx->d_down_conv, ctx->d_down_hneg, kg, ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
 }
 
 // K5-K7 for batch slots 0..nb-1 (ModDown of each slot's acc rows)
@@ -563,13 +663,9 @@ int ks_moddown(hck_context *ctx, const KsBatch &kb, const KsGeom &kg, uint64_t *
   timing_begin(ctx, "ks_moddown_strided", dim3(GA::BLOCKS, 2 * per, nb),
                8.0 * N * (K + nq) * 2 * nb, N * (K + 0.5 * A) * 2 * nq * nb);
   if (paired)
-    k_moddown_strided<LOGN, true><<<dim3(GA::BLOCKS, 2 * per, nb), kNttThreads, 0,
-                                    ctx->stream>>>(ws, ctx->d_down_conv, ctx->d_down_hneg, kg,
-                                                   ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+    launch_moddown_strided<LOGN, true>(ctx, ws, kg, per, nb);
   else
-    k_moddown_strided<LOGN, false><<<dim3(GA::BLOCKS, 2 * per, nb), kNttThreads, 0,
-                                     ctx->stream>>>(ws, ctx->d_down_conv, ctx->d_down_hneg, kg,
-                                                    ctx->d_mod, ctx->d_tw, ctx->d_tw_shoup);
+    launch_moddown_strided<LOGN, false>(ctx, ws, kg, per, nb);
   timing_end(ctx);
   RowScale pinv;
   for (uint32_t i = 0; i < nq; i++) {
