@@ -152,6 +152,17 @@ def params_with_dnum(name: str, dnum: int) -> dict:
     return dict(base, name=f"{name}/dnum{dnum}", dnum=dnum, p=specials)
 
 
+def params_wide_special(name: str) -> dict:
+    """The parameter set `name` with its K special primes moved just below
+    2^61 (still = 1 mod 2N and distinct from the chain): moduli at the top of
+    the range the library accepts, above the 2^60 bound of its 30-bit
+    basis-conversion path."""
+    base = params(name)
+    two_n = 2 * base["n"]
+    specials = _primes_near(61, two_n, len(base["p"]), set(base["q"]), False)
+    return dict(base, name=f"{name}/p61", p=specials)
+
+
 def uniform_slots(n_slots: int, seed: int, lo: float = -1.0, hi: float = 1.0,
                   complex_: bool = False) -> np.ndarray:
     """Slot vector drawn uniformly from [lo, hi) (real, or real+imag parts)."""

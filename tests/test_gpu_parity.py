@@ -658,6 +658,33 @@ def test_other_digit_counts_match_oracle(dnum):
     assert np.array_equal(p.export(p.ctx.rotate(ct, 5, gks)), o.rotate(ct_o, 5, gko).polys)
 
 
+@pytest.mark.parametrize("name", ["tiny", "mix15"])
+def test_wide_special_primes_match_oracle(name):
+    """Special primes just below 2^61, where the basis conversions take their
+    whole-word path (the 30-bit one needs every modulus below 2^60): key
+    switching at every level class, a batch of rotations large enough for
+    paired conversion launches, and a rescale, bit-exact."""
+    p = Pair(f"{name}/p61", S.params_wide_special(name))
+    o = p.o
+    assert min(o.p) >= 1 << 60 and max(o.p) < 1 << 61
+    rlk = p.ctx.keygen_relin(p.sk, 7)
+    rlk_o = o.keygen_relin(p.s_o, 7)
+    for level in _levels(o):
+        ct, ct_o = p.rand_ct(level, 760 + level)
+        got = p.export(p.ctx.keyswitch(ct, rlk))
+        u0, u1 = o.keyswitch(ct_o.polys[0], level, rlk_o)
+        assert np.array_equal(got[0], u0) and np.array_equal(got[1], u1), level
+    steps = [1, 3, 5, 7, -1, -3, 2, 4, 6, 9, 11, 13, 1, 3, 5, 7]
+    gks, gko = p.galois(steps)
+    cts = [p.rand_ct(o.L - 1, 780 + i) for i in range(len(steps))]
+    outs = [p.ctx.ciphertext() for _ in steps]
+    p.ctx.rotate_steps([c for c, _ in cts], steps, gks, outs)
+    for (c, c_o), k, out in zip(cts, steps, outs):
+        assert np.array_equal(p.export(out), o.rotate(c_o, k, gko).polys), k
+    ct, ct_o = p.rand_ct(o.L - 1, 799)
+    assert np.array_equal(p.export(p.ctx.rescale(ct)), o.rescale(ct_o).polys)
+
+
 def test_autotune_dnum():
     """The dnum autotuner times each candidate's key switch and reports its
     key size; the best is the fastest."""
