@@ -278,6 +278,16 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
   using G = Pass<split_b(LOGN), LOGN, false>;
   constexpr int P = G::P;
   __shared__ uint64_t lds[G::LDS_WORDS];
+  // With 8 points a thread (three-layout passes) a workgroup covers TILE
+  // consecutive words of a row, a wavefront 512 of them.  Each digit's two
+  // key rows over those words are copied into LDS by direct global-to-LDS
+  // loads issued before the digit's forward pass, so the copy runs under the
+  // transform without holding registers; each wavefront reads only the words
+  // it copied (no workgroup barrier).  The two rows take 32 KiB, which still
+  // leaves room for as many workgroups per CU as the registers allow.
+  constexpr bool KEY_LDS = G::P == 8 && G::T * G::TR == kNttThreads && split_b(LOGN) >= 7;
+  constexpr int TILE = kNttThreads * P;
+  __shared__ uint64_t ktile[KEY_LDS ? 2 * TILE : 1];
   // the special limbs, which also run an inverse pass, are dispatched first
   // so that the shorter workgroups fill in behind them
   const uint32_t t = blockIdx.z < kg.K ? kg.nq + blockIdx.z : blockIdx.z - kg.K;
@@ -294,11 +304,34 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
   uint64_t a0[P], a1[P], x[P];
 #pragma unroll
   for (int i = 0; i < P; i++) a0[i] = a1[i] = 0;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const size_t tile0 = (size_t)blockIdx.x * TILE;  // first word of the tile in a row
   for (uint32_t j = 0; j < kg.dnum; j++) {
     const uint32_t lo = j * kg.alpha;
     if (lo >= kg.nq) break;
     const uint32_t hi = min(lo + kg.alpha, kg.nq);
+    const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * G::N;
+    const uint64_t *kap = kbp + krow;
+    // this wavefront's 512 words of each key row: 4 loads of 16 bytes a lane
+    // (1 KiB a load), lane l's bytes landing at 16 l.  Loads complete in
+    // issue order, so the copy is issued after the digit's own loads (a wait
+    // for those does not wait for it) and before the transform it hides under.
+    auto copy_keys = [&]() {
+      if constexpr (KEY_LDS) {
+#pragma unroll
+        for (int rr = 0; rr < 2; rr++) {
+          const uint64_t *src = (rr ? kap : kbp) + tile0 + wave * 512 + 2 * (threadIdx.x % 64);
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(src + 128 * i),
+                (__attribute__((address_space(3))) void *)&ktile[rr * TILE + wave * 512 + 128 * i],
+                16, 0, 0);
+        }
+      }
+    };
     if (t >= lo && t < hi) {
+      copy_keys();
 #pragma unroll
       for (int i = 0; i < P; i++)
         x[i] = d[(size_t)t * G::N +
@@ -308,18 +341,25 @@ __global__ __launch_bounds__(kNttThreads) void k_ks_contig_inner(
 #pragma unroll
       for (int i = 0; i < P; i++) x[i] = e[G::gaddr(g, G::ipoint(r, i))];
       G::twist(x, g, r, tt + (size_t)mi * G::N, tts + (size_t)mi * G::N, qn(m));
+      copy_keys();
       G::forward(lds, x, c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
 #pragma unroll
       for (int v = 0; v < P; v++) x[v] = reduce4(x[v], qn(m));
       G::to_interleaved(lds, x, c, r);
     }
-    const uint64_t *kbp = key + 2 * j * krow + (size_t)mi * G::N;
-    const uint64_t *kap = kbp + krow;
 #pragma unroll
     for (int i = 0; i < P; i++) {
       const size_t pos = G::gaddr(g, G::ipoint(r, i));
-      a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kbp[pos]), m.q, m.qinv), m.q);
-      a1[i] = add_mod(a1[i], redc(mul_wide(x[i], kap[pos]), m.q, m.qinv), m.q);
+      uint64_t kv0, kv1;
+      if constexpr (KEY_LDS) {
+        kv0 = ktile[pos - tile0];
+        kv1 = ktile[TILE + pos - tile0];
+      } else {
+        kv0 = kbp[pos];
+        kv1 = kap[pos];
+      }
+      a0[i] = add_mod(a0[i], redc(mul_wide(x[i], kv0), m.q, m.qinv), m.q);
+      a1[i] = add_mod(a1[i], redc(mul_wide(x[i], kv1), m.q, m.qinv), m.q);
     }
   }
   if (t >= kg.nq) {
