@@ -13,21 +13,13 @@
 //     columns (stride R2) are independent R1-point transforms;
 //   * contiguous pass: stages m >= R1 stay inside the R1 blocks of R2
 //     contiguous words, independent R2-point transforms.
-// Two geometries spread a sub-transform over threads (`Pass` picks one):
-//   * two layouts (Pass2): a thread owns P = 2^ceil(log2(R)/2) points of one
-//     R-point sub-transform and T = R/P threads share it;
-//     interleaved layout: thread r holds points r + T i (i < P); the first
-//       log2(P) stages pair registers i and i + h;
-//     blocked layout: thread r holds points r P + v (v < P); the remaining
-//       stages (half-width < T <= P) pair registers v and v + t;
-//     one LDS exchange switches layouts.  Strided passes, and contiguous
-//     passes below 128 points.
-//   * three layouts (Pass3, below): 8 points a thread, the register index
-//     being the top, middle or low 3 bits of the point index, two LDS
-//     exchanges each way.  Contiguous passes of 128 to 512 points, where the
-//     fused key-switching passes keep several point arrays live at once.
-// Both compute the same butterflies with the same twiddles in the same
-// stage order, so they give the same words.
+// In a pass a thread owns P = 2^ceil(log2(R)/2) points of one R-point
+// sub-transform and T = R/P threads share it:
+//   interleaved layout: thread r holds points r + T i (i < P); the first
+//     log2(P) stages pair registers i and i + h;
+//   blocked layout: thread r holds points r P + v (v < P); the remaining
+//     stages (half-width < T <= P) pair registers v and v + t.
+// One LDS exchange switches layouts.
 //
 // The contiguous pass's sub-transform g (words g R2 .. g R2 + R2 - 1) would
 // need its own twiddles: the twiddle of its stage s and group grp is
