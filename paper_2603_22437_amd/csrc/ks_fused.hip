@@ -155,7 +155,7 @@ __device__ __forceinline__ void bconv_points(uint64_t (&x)[NT][G::P],
 // (the same integer as above, so the same REDC result) once per point.
 // Four 64-bit columns take twice the registers of one 128-bit sum, so the
 // points are taken in chunks of half the size.
-template <class G, int NT>
+template <class G, int NT, bool UNROLL2>
 __device__ __forceinline__ void bconv_points30(uint64_t (&x)[NT][G::P],
                                                const uint64_t *__restrict__ src,
                                                const uint64_t *const (&cv)[NT], uint32_t cstride,
@@ -171,8 +171,8 @@ __device__ __forceinline__ void bconv_points30(uint64_t (&x)[NT][G::P],
     for (int t = 0; t < NT; t++)
 #pragma unroll
       for (int k = 0; k < CH; k++) lo[t][k] = m1[t][k] = m2[t][k] = hi[t][k] = 0;
-#pragma unroll 2
-    for (uint32_t a = 0; a < na; a++) {
+    // one source limb: its CH words, split, into every target's columns
+    auto source = [&](uint32_t a) {
       uint32_t v0[CH], v1[CH];
 #pragma unroll
       for (int k = 0; k < CH; k++) {
@@ -192,6 +192,15 @@ __device__ __forceinline__ void bconv_points30(uint64_t (&x)[NT][G::P],
           hi[t][k] += (uint64_t)v1[k] * ch;
         }
       }
+    };
+    // two source limbs per iteration put twice the loads in flight; the
+    // paired ModUp, held to 128 registers for a fourth wave per SIMD, takes
+    // one (the unrolled loop would spill more there)
+    if constexpr (UNROLL2) {
+#pragma unroll 2
+      for (uint32_t a = 0; a < na; a++) source(a);
+    } else {
+      for (uint32_t a = 0; a < na; a++) source(a);
     }
 #pragma unroll
     for (int t = 0; t < NT; t++)
@@ -211,18 +220,21 @@ __device__ __forceinline__ void bconv_points30(uint64_t (&x)[NT][G::P],
   }
 }
 
-template <class G, int NT, bool S30>
+template <class G, int NT, bool S30, bool UNROLL2 = true>
 __device__ __forceinline__ void bconv(uint64_t (&x)[NT][G::P], const uint64_t *__restrict__ src,
                                       const uint64_t *const (&cv)[NT], uint32_t cstride,
                                       uint32_t na, int g, int r, const ModConst (&m)[NT]) {
   if constexpr (S30)
-    bconv_points30<G, NT>(x, src, cv, cstride, na, g, r, m);
+    bconv_points30<G, NT, UNROLL2>(x, src, cv, cstride, na, g, r, m);
   else
     bconv_points<G, NT>(x, src, cv, cstride, na, g, r, m);
 }
 
+// the paired 30-bit ModUp is held to 128 VGPRs (4 waves per SIMD instead of
+// 3, at 8 bytes of spill a lane): measured 6 % faster
 template <int LOGN, bool PAIR, bool S30>
-__global__ __launch_bounds__(kNttThreads) void k_modup_strided(
+__global__ __launch_bounds__(kNttThreads)
+__attribute__((amdgpu_waves_per_eu(PAIR && S30 ? 4 : 1))) void k_modup_strided(
     uint64_t *__restrict__ ws, ModUpRows rows, const uint64_t *__restrict__ conv, KsGeom kg,
     const ModConst *__restrict__ mc, const uint64_t *__restrict__ tw,
     const uint64_t *__restrict__ tws) {
@@ -255,7 +267,7 @@ __global__ __launch_bounds__(kNttThreads) void k_modup_strided(
     uint64_t x[2][P];
     const uint64_t *const cvs[2] = {cv, cv2};
     const ModConst ms[2] = {m, m2};
-    bconv<G, 2, S30>(x, src, cvs, kg.nm, na, g, r, ms);
+    bconv<G, 2, S30, false>(x, src, cvs, kg.nm, na, g, r, ms);
     G::forward(lds, x[0], c, r, g, tw + (size_t)mi * G::N, tws + (size_t)mi * G::N, qn(m));
     uint64_t *out = ws + (size_t)rows.row[k] * G::N;
 #pragma unroll
