@@ -68,6 +68,37 @@ def test_keyswitch_noise_bound(tiny, level):
     assert max(abs(x) for x in e) < ks_error_bound(o, level)
 
 
+def test_wide_special_primes_parameter_set():
+    """The sets of the whole-word basis-conversion parity test: the chain of
+    the named set with special primes in [2^60, 2^61), = 1 mod 2N, prime,
+    distinct from the chain and summing below 2^64 (the library's bound on
+    the conversion sums)."""
+    for name in ("tiny", "mix15"):
+        prm, base = S.params_wide_special(name), S.params(name)
+        assert prm["q"] == base["q"] and len(prm["p"]) == len(base["p"])
+        for p in prm["p"]:
+            assert (1 << 60) <= p < (1 << 61) and p % (2 * prm["n"]) == 1 and S.is_prime(p)
+        assert not set(prm["p"]) & set(prm["q"]) and sum(prm["p"]) < 1 << 64
+
+
+@pytest.mark.parametrize("level", [2, 0])
+def test_keyswitch_noise_bound_wide_special_primes(level):
+    """Hybrid key switching with a 61-bit special prime stays within the same
+    exact noise bound (key noise over P, plus the ModDown rounding)."""
+    o = O.Oracle(S.params_wide_special("tiny"))
+    s = o.keygen_secret(1)
+    mods = o.qmods(level)
+    g = o.galois_element(3)
+    gk = o.keygen_galois(s, g, 5)
+    d = S.uniform_residues(mods, o.n, seed=23)[0]
+    u0, u1 = o.keyswitch(d, level, gk)
+    s_r = O.embed_small(s, o.log_n, mods)
+    s_g = O.automorphism(s_r, g, o.log_n, mods)
+    err = O.poly_sub(O.poly_add(u0, O.poly_mul(u1, s_r, o.log_n, mods), o.log_n, mods),
+                     O.poly_mul(d, s_g, o.log_n, mods), o.log_n, mods)
+    assert max(abs(x) for x in centred(err, mods)) < ks_error_bound(o, level)
+
+
 def test_keyswitch_wrong_key_is_not_small(tiny):
     """The bound above is meaningful: a key for another element fails it."""
     o, s = tiny
